@@ -1,0 +1,389 @@
+"""Pins of the FP64 oracle against what the paper and the mathematics fix.
+
+No GPU.  Each test names the oracle function it pins and the passage (or the
+mathematical fact) that fixes the expected value.  Expected values never come
+from the oracle's own formulas: they come from brute force on an operator
+built independently (torch's circular conv2d), closed forms, invariants, the
+FFT identity, finite differences, or fixtures under tests/golden/.
+"""
+
+import os
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import workloads
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _load(name):
+    return np.loadtxt(os.path.join(GOLDEN, name), comments="#")
+
+
+def torch_circular_operator(W, n, m):
+    """The periodic convolution unrolled by running torch's conv2d on every
+    basis vector of a circularly padded input: an implementation of
+    (A*f)(x) = sum_y M_y f(x+y) that shares nothing with the oracle.
+    Indexing matches the oracle: (x1*m + x2)*c + channel."""
+    W = torch.as_tensor(np.asarray(W, dtype=np.float64))
+    c_out, c_in, kh, kw = W.shape
+    N = n * m * c_in
+    eye = torch.eye(N, dtype=torch.float64).reshape(N, n, m, c_in).permute(0, 3, 1, 2)
+    pad = ((kw - 1) // 2, kw // 2, (kh - 1) // 2, kh // 2)
+    # circular padding wraps at most once: fine while the kernel fits the grid
+    x = torch.nn.functional.pad(eye, pad, mode="circular")
+    y = torch.nn.functional.conv2d(x, W)                       # (N, c_out, n, m)
+    cols = y.permute(0, 2, 3, 1).reshape(N, n * m * c_out)     # column per basis vector
+    return cols.T.numpy()
+
+
+def torch_zero_padded_operator(W, n, m):
+    W = torch.as_tensor(np.asarray(W, dtype=np.float64))
+    c_out, c_in, kh, kw = W.shape
+    N = n * m * c_in
+    eye = torch.eye(N, dtype=torch.float64).reshape(N, n, m, c_in).permute(0, 3, 1, 2)
+    pad = ((kw - 1) // 2, kw // 2, (kh - 1) // 2, kh // 2)
+    x = torch.nn.functional.pad(eye, pad, mode="constant", value=0.0)
+    y = torch.nn.functional.conv2d(x, W)
+    return y.permute(0, 2, 3, 1).reshape(N, n * m * c_out).T.numpy()
+
+
+BRUTE_CASES = [
+    # c_out, c_in, kh, kw, n, m
+    (4, 4, 3, 3, 8, 8),
+    (3, 2, 3, 3, 6, 5),
+    (2, 4, 3, 3, 4, 7),
+    (4, 4, 1, 1, 5, 5),
+    (2, 3, 5, 5, 6, 6),
+    (3, 3, 3, 5, 5, 7),
+    (2, 2, 2, 2, 4, 4),       # even kernel: centred at (k-1)//2
+    (1, 1, 3, 3, 8, 8),
+]
+
+
+# --- P1: brute force --------------------------------------------------------
+
+@pytest.mark.parametrize("case", BRUTE_CASES)
+def test_unrolled_operator_matches_torch_conv2d(case):
+    """oracle.unrolled_operator == torch circular conv2d, entry by entry
+    (definition of the operator, Sec. III "Convolutional Mappings")."""
+    c_out, c_in, kh, kw, n, m = case
+    _, W = workloads.random_layer(c_out, c_in, kh, kw, n, m, seed=11, dtype=np.float64)
+    np.testing.assert_array_equal(oracle.unrolled_operator(W, n, m), torch_circular_operator(W, n, m))
+
+
+@pytest.mark.parametrize("case", BRUTE_CASES)
+def test_brute_force_singular_values(case):
+    """Union over frequencies of the symbol singular values == singular values
+    of the dense unrolled operator (Sec. III "Convolution Theorem": the Fourier
+    modes make the operator block diagonal).  Dense SVD by LAPACK dgesdd of
+    the torch-built matrix."""
+    c_out, c_in, kh, kw, n, m = case
+    _, W = workloads.random_layer(c_out, c_in, kh, kw, n, m, seed=7, dtype=np.float64)
+    dense = torch_circular_operator(W, n, m)
+    s_dense = np.sort(np.linalg.svd(dense, compute_uv=False))[::-1]
+    s_lfa = np.sort(oracle.lfa_svd(W, n, m).ravel())[::-1]
+    # the dense operator has n*m*max(c) - n*m*min(c) extra zero singular values
+    # only when it is not square: compare the nonzero part and count
+    r = min(c_out, c_in)
+    assert s_lfa.size == n * m * r
+    np.testing.assert_allclose(s_lfa, s_dense[: s_lfa.size], rtol=0, atol=1e-13 * s_dense[0])
+    assert np.all(s_dense[s_lfa.size:] <= 1e-13 * s_dense[0])
+
+
+def test_brute_force_config_n8_c4():
+    """The 4->4 channel, 8x8 grid brute-force workload: dense 256x256."""
+    L, W = workloads.brute_force_small()
+    dense = torch_circular_operator(W, L.n, L.m)
+    assert dense.shape == (256, 256)
+    s_dense = np.sort(np.linalg.svd(dense, compute_uv=False))[::-1]
+    s_lfa = np.sort(oracle.lfa_svd(W, L.n, L.m).ravel())[::-1]
+    np.testing.assert_allclose(s_lfa, s_dense, rtol=0, atol=1e-13 * s_dense[0])
+
+
+def test_dirichlet_operator_matches_torch_zero_padding():
+    """oracle.dirichlet_operator == torch conv2d with zero padding (Sec. III
+    "Boundary Conditions")."""
+    _, W = workloads.random_layer(3, 2, 3, 3, 5, 6, seed=5, dtype=np.float64)
+    np.testing.assert_array_equal(oracle.dirichlet_operator(W, 5, 6), torch_zero_padded_operator(W, 5, 6))
+
+
+# --- Convolution theorem / symbol sign -------------------------------------
+
+def test_fourier_mode_is_invariant_subspace():
+    """(A*f_k)(x) = A_k f_k(x) for f_k = e^{2 pi i <k,x>} v (Sec. III
+    "Convolution Theorem"): apply the torch-built operator to a Fourier mode
+    and read off the symbol.  Pins the +2 pi i sign and the tap centring."""
+    c_out, c_in, kh, kw, n, m = 3, 2, 3, 3, 6, 5
+    _, W = workloads.random_layer(c_out, c_in, kh, kw, n, m, seed=3, dtype=np.float64)
+    dense = torch_circular_operator(W, n, m)
+    A = oracle.symbols(W, n, m)
+    x1, x2 = np.meshgrid(np.arange(n), np.arange(m), indexing="ij")
+    rng = np.random.default_rng(0)
+    for p, q in [(0, 0), (1, 2), (5, 4), (3, 1)]:
+        v = rng.standard_normal(c_in) + 1j * rng.standard_normal(c_in)
+        wave = np.exp(2j * np.pi * (p * x1 / n + q * x2 / m)).ravel()
+        f = np.kron(wave, v)
+        g = dense @ f
+        expect = np.kron(wave, A[p, q] @ v)
+        np.testing.assert_allclose(g, expect, atol=1e-13)
+
+
+def test_shift_symbol_golden():
+    """Single tap at offset (1,0): symbol i^p on a 4x4 grid (golden fixture)."""
+    W = np.zeros((1, 1, 3, 3))
+    W[0, 0, 2, 1] = 1.0
+    A = oracle.symbols(W, 4, 4)[:, :, 0, 0]
+    for p, q, re, im in _load("shift_symbol_4x4.txt"):
+        assert abs(A[int(p), int(q)] - (re + 1j * im)) < 1e-15
+
+
+def test_laplacian_golden_and_closed_form():
+    """P4: single channel, 5-point Laplacian stencil: sigma = |4 - 2cos t1 - 2cos t2|."""
+    lap = np.array([[0, -1, 0], [-1, 4, -1], [0, -1, 0]], dtype=np.float64)[None, None]
+    s = oracle.lfa_svd(lap, 4, 4)[:, :, 0]
+    np.testing.assert_allclose(s, _load("laplacian_symbol_4x4.txt"), atol=1e-14)
+    n, m = 16, 12
+    s = oracle.lfa_svd(lap, n, m)[:, :, 0]
+    t1 = 2 * np.pi * np.arange(n)[:, None] / n
+    t2 = 2 * np.pi * np.arange(m)[None, :] / m
+    np.testing.assert_allclose(s, np.abs(4 - 2 * np.cos(t1) - 2 * np.cos(t2)), atol=1e-14)
+
+
+# --- P5: FFT identity -------------------------------------------------------
+
+@pytest.mark.parametrize("case", [(3, 2, 3, 3, 8, 6), (5, 5, 7, 7, 9, 9), (2, 3, 1, 1, 4, 4)])
+def test_fft_identity(case):
+    """A_k(p,q) = n*m * ifft2(kernel scattered to (y mod n, y mod m))[p,q]: the
+    mathematics behind the FFT method the paper compares with (Sec. I, Sec. II)."""
+    c_out, c_in, kh, kw, n, m = case
+    _, W = workloads.random_layer(c_out, c_in, kh, kw, n, m, seed=9, dtype=np.float64)
+    K = np.zeros((c_out, c_in, n, m))
+    for a in range(kh):
+        for b in range(kw):
+            K[:, :, (a - (kh - 1) // 2) % n, (b - (kw - 1) // 2) % m] += W[:, :, a, b]
+    A_fft = n * m * np.fft.ifft2(K, axes=(2, 3))          # (c_out, c_in, n, m)
+    A = oracle.symbols(W, n, m)
+    np.testing.assert_allclose(A, np.transpose(A_fft, (2, 3, 0, 1)), atol=1e-14)
+
+
+def test_sampled_frequencies_match_full_grid():
+    """symbols(freqs=...) picks the same entries as the full grid."""
+    _, W = workloads.random_layer(3, 4, 3, 3, 7, 9, seed=2, dtype=np.float64)
+    A = oracle.symbols(W, 7, 9)
+    fr = np.array([[0, 0], [6, 8], [3, 2], [1, 7]])
+    np.testing.assert_array_equal(oracle.symbols(W, 7, 9, fr), A[fr[:, 0], fr[:, 1]])
+
+
+# --- P2: Parseval ----------------------------------------------------------
+
+@pytest.mark.parametrize("case", [(16, 16, 3, 3, 32, 32), (8, 5, 3, 3, 6, 10), (4, 9, 5, 5, 7, 7)])
+def test_parseval(case):
+    """sum sigma^2 = n*m*||W||_F^2 (no tap aliasing): trace of A^H A summed over
+    the Fourier basis equals the Frobenius norm of the unrolled operator."""
+    c_out, c_in, kh, kw, n, m = case
+    _, W = workloads.random_layer(c_out, c_in, kh, kw, n, m, seed=4, dtype=np.float64)
+    s = oracle.lfa_svd(W, n, m)
+    np.testing.assert_allclose(np.sum(s**2), n * m * np.sum(W**2), rtol=1e-13)
+
+
+# --- P3: identity / orthogonal tap ------------------------------------------
+
+def test_identity_kernel_all_ones():
+    c = 5
+    W = np.zeros((c, c, 3, 3))
+    W[:, :, 1, 1] = np.eye(c)
+    np.testing.assert_allclose(oracle.lfa_svd(W, 6, 6), 1.0, atol=1e-15)
+
+
+def test_orthogonal_offcentre_tap_all_ones():
+    """Single off-centre tap holding an orthogonal Q: the operator is a shift
+    (a permutation) tensor Q, so every singular value is 1."""
+    c = 6
+    Q, _ = np.linalg.qr(np.random.default_rng(1).standard_normal((c, c)))
+    W = np.zeros((c, c, 3, 3))
+    W[:, :, 0, 2] = Q
+    np.testing.assert_allclose(oracle.lfa_svd(W, 5, 7), 1.0, atol=1e-14)
+
+
+# --- P6, P7: symmetries and invariances --------------------------------------
+
+def test_conjugate_symmetry():
+    """Real W: A_{-k} = conj(A_k), so sigma(k) = sigma(-k)."""
+    n, m = 8, 6
+    _, W = workloads.random_layer(4, 3, 3, 3, n, m, seed=6, dtype=np.float64)
+    A = oracle.symbols(W, n, m)
+    neg = A[(-np.arange(n)) % n][:, (-np.arange(m)) % m]
+    np.testing.assert_allclose(neg, np.conj(A), atol=1e-15)
+
+
+def test_invariances():
+    n = 6
+    _, W = workloads.random_layer(5, 4, 3, 3, n, n, seed=8, dtype=np.float64)
+    s = np.sort(oracle.lfa_svd(W, n).ravel())
+    # scaling
+    np.testing.assert_allclose(np.sort(oracle.lfa_svd(-2.5 * W, n).ravel()), 2.5 * s, rtol=1e-13)
+    # common orthogonal transforms of all taps
+    rng = np.random.default_rng(2)
+    Qo, _ = np.linalg.qr(rng.standard_normal((5, 5)))
+    Qi, _ = np.linalg.qr(rng.standard_normal((4, 4)))
+    W2 = np.einsum("po,oiab,iq->pqab", Qo, W, Qi)
+    np.testing.assert_allclose(np.sort(oracle.lfa_svd(W2, n).ravel()), s, atol=1e-13 * s.max())
+    # channel permutation
+    W3 = W[rng.permutation(5)][:, rng.permutation(4)]
+    np.testing.assert_allclose(np.sort(oracle.lfa_svd(W3, n).ravel()), s, atol=1e-13 * s.max())
+
+
+# --- P8: rank -----------------------------------------------------------------
+
+def test_rank_one_taps():
+    """Rank-one taps: rank A_k <= number of taps, so min(c) - 9 zero sigma."""
+    L, W = workloads.rank_one_taps(c_out=24, c_in=16, n=4)
+    s = oracle.lfa_svd(W.astype(np.float64), L.n)
+    assert s.shape == (4, 4, 16)
+    assert np.all(s[:, :, 9:] <= 1e-13 * s[:, :, :1])
+    assert np.all(s[:, :, 8] > 1e-6 * s[:, :, 0])
+
+
+def test_common_vector_closed_form():
+    """W_y = c_y a b^T  =>  sigma_1(k) = ||a|| ||b|| |sum_y c_y e^{2 pi i <k,y>}|,
+    other singular values zero.  The scalar sum is evaluated with numpy's FFT
+    (the FFT identity), not with the oracle."""
+    rng = np.random.default_rng(12)
+    a, b, cy = rng.standard_normal(6), rng.standard_normal(4), rng.standard_normal((3, 3))
+    W = np.einsum("o,i,xy->oixy", a, b, cy)
+    n, m = 7, 5
+    s = oracle.lfa_svd(W, n, m)
+    K = np.zeros((n, m))
+    for x in range(3):
+        for y in range(3):
+            K[(x - 1) % n, (y - 1) % m] += cy[x, y]
+    sym = n * m * np.fft.ifft2(K)
+    np.testing.assert_allclose(s[:, :, 0], np.linalg.norm(a) * np.linalg.norm(b) * np.abs(sym), rtol=1e-13)
+    assert np.all(s[:, :, 1:] <= 1e-13 * s[:, :, :1].max())
+
+
+# --- P9: count ----------------------------------------------------------------
+
+def test_counts_match_table2():
+    """#sigma = n*m*min(c_in, c_out), against the counts printed in Table II."""
+    for n, count in _load("table2_sigma_counts.txt"):
+        assert workloads.Layer(16, 16, 3, 3, int(n), int(n)).num_sigma == int(count)
+    s = oracle.lfa_svd(np.random.default_rng(0).standard_normal((16, 16, 3, 3)), 8, 4)
+    assert s.size == 8 * 4 * 16
+
+
+# --- P10: vectors and lift ------------------------------------------------------
+
+def test_vectors_orthonormal_and_residual():
+    _, W = workloads.random_layer(7, 5, 3, 3, 6, 6, seed=13, dtype=np.float64)
+    s, U, V = oracle.lfa_svd(W, 6, compute_uv=True)
+    A = oracle.symbols(W, 6)
+    eye = np.eye(5)
+    UhU = np.conj(np.swapaxes(U, -1, -2)) @ U
+    VhV = np.conj(np.swapaxes(V, -1, -2)) @ V
+    np.testing.assert_allclose(UhU, np.broadcast_to(eye, UhU.shape), atol=1e-13)
+    np.testing.assert_allclose(VhV, np.broadcast_to(eye, VhV.shape), atol=1e-13)
+    np.testing.assert_allclose(A @ V, U * s[..., None, :], atol=1e-13)
+    assert np.all(np.diff(s, axis=-1) <= 0)
+
+
+def test_lift_gives_global_singular_vectors():
+    """U_hat = F^out U, V_hat = F^in V are orthonormal and satisfy
+    A V_hat = U_hat S for the torch-built unrolled operator (Sec. III)."""
+    n, m = 4, 3
+    _, W = workloads.random_layer(3, 2, 3, 3, n, m, seed=21, dtype=np.float64)
+    dense = torch_circular_operator(W, n, m)
+    s, U, V = oracle.lfa_svd(W, n, m, compute_uv=True)
+    Uh_all, Vh_all, s_all = [], [], []
+    for p in range(n):
+        for q in range(m):
+            Uh, Vh = oracle.lift(U[p, q], V[p, q], n, m, p, q)
+            np.testing.assert_allclose(dense @ Vh, Uh * s[p, q][None, :], atol=1e-13)
+            Uh_all.append(Uh)
+            Vh_all.append(Vh)
+            s_all.append(s[p, q])
+    Vh_all = np.concatenate(Vh_all, axis=1)
+    Uh_all = np.concatenate(Uh_all, axis=1)
+    np.testing.assert_allclose(np.conj(Vh_all.T) @ Vh_all, np.eye(Vh_all.shape[1]), atol=1e-13)
+    np.testing.assert_allclose(np.conj(Uh_all.T) @ Uh_all, np.eye(Uh_all.shape[1]), atol=1e-13)
+    assert Vh_all.shape == (n * m * 2, n * m * 2)     # full SVD of the square-in part
+
+
+# --- P11: gradient --------------------------------------------------------------
+
+def test_sigma_grad_matches_finite_differences():
+    n, m = 5, 4
+    _, W = workloads.random_layer(4, 3, 3, 3, n, m, seed=17, dtype=np.float64)
+    picks = np.array([[1, 2, 0], [3, 1, 2], [0, 0, 1]])
+    g = np.array([1.0, -0.5, 2.0])
+    dW = oracle.sigma_grad(W, n, m, picks, g)
+
+    def loss(Wx):
+        s = oracle.lfa_svd(Wx, n, m)
+        return sum(gi * s[p, q, j] for gi, (p, q, j) in zip(g, picks))
+
+    rng = np.random.default_rng(3)
+    for _ in range(4):
+        D = rng.standard_normal(W.shape)
+        h = 1e-6 * np.linalg.norm(W)
+        fd = (loss(W + h * D) - loss(W - h * D)) / (2 * h)
+        an = np.sum(dW * D)
+        assert abs(fd - an) <= 1e-7 * max(1.0, abs(an))
+
+
+def test_sigma_grad_entrywise_fd():
+    """Every entry of the gradient of the largest sigma at one frequency."""
+    n = 4
+    _, W = workloads.random_layer(2, 2, 3, 3, n, n, seed=5, dtype=np.float64)
+    picks = np.array([[1, 3, 0]])
+    dW = oracle.sigma_grad(W, n, n, picks)
+    h = 1e-6
+    for idx in np.ndindex(W.shape):
+        Wp, Wm = W.copy(), W.copy()
+        Wp[idx] += h
+        Wm[idx] -= h
+        fd = (oracle.lfa_svd(Wp, n)[1, 3, 0] - oracle.lfa_svd(Wm, n)[1, 3, 0]) / (2 * h)
+        assert abs(fd - dW[idx]) < 1e-8
+
+
+# --- top-k -------------------------------------------------------------------------
+
+def test_topk_order_and_ties():
+    s = np.zeros((2, 3, 2))
+    s[0, 1, 0] = 5.0
+    s[1, 2, 1] = 5.0      # tie: (0,1,0) comes first
+    s[1, 0, 0] = 7.0
+    s[0, 0, 1] = 3.0
+    vals, idx = oracle.topk(s, 4)
+    np.testing.assert_array_equal(vals, [7.0, 5.0, 5.0, 3.0])
+    np.testing.assert_array_equal(idx, [[1, 0, 0], [0, 1, 0], [1, 2, 1], [0, 0, 1]])
+    # brute force on random data
+    r = np.random.default_rng(4).random((5, 4, 3))
+    vals, idx = oracle.topk(r, 8)
+    np.testing.assert_array_equal(vals, np.sort(r.ravel())[::-1][:8])
+    np.testing.assert_array_equal(r[idx[:, 0], idx[:, 1], idx[:, 2]], vals)
+
+
+def test_sigma_error_metric():
+    ref = np.array([[4.0, 2.0, 0.0], [1.0, 0.5, 0.25]])
+    test = ref + np.array([[0.0, 0.04, 0.0], [0.0, 0.0, 0.001]])
+    assert oracle.sigma_error(test, ref) == pytest.approx(0.01)
+
+
+# --- Dirichlet vs periodic (qualitative claim of Sec. IV) -----------------------
+
+def test_dirichlet_spectrum_approaches_periodic():
+    """The boundary's influence on the spectrum shrinks as the grid grows
+    (Sec. IV, boundary-condition study): the distance between the sorted
+    Dirichlet and periodic spectra, relative to sigma_max, decreases with n."""
+    _, W = workloads.random_layer(3, 3, 3, 3, 4, 4, seed=1, dtype=np.float64)
+    gaps = []
+    for n in (4, 8, 12):
+        sp = np.sort(oracle.lfa_svd(W, n).ravel())
+        sd = np.sort(np.linalg.svd(oracle.dirichlet_operator(W, n), compute_uv=False))
+        gaps.append(np.mean(np.abs(sp - sd)) / sp[-1])
+    assert gaps[0] > gaps[1] > gaps[2]
