@@ -1,0 +1,249 @@
+/*
+ * lfa.h -- C ABI of liblfa: the singular value decomposition of periodic,
+ * stride-1, multi-channel 2-D convolutions by local Fourier analysis (LFA),
+ * on AMD Instinct MI355X (gfx950).
+ *
+ * The method (Sec. III of the paper, "Convolution Theorem" and Algorithm 1):
+ * a convolution (A*f)(x) = sum_y M_y f(x+y) on a periodic n x m grid with
+ * c_in input and c_out output channels is block diagonal in the Fourier
+ * basis.  At each frequency k = (p/n, q/m) of the dual torus its block is the
+ * c_out x c_in complex "symbol"
+ *
+ *     A_k = sum_{y in N} M_y * exp(+2 pi i <k, y>),
+ *
+ * and the SVD of the whole operator is the union over k of the SVDs
+ * A_k = U_k S_k V_k^*.  This library computes the symbols (step a1) and
+ * their SVD (steps a2/a3) on the GPU, plus top-k selection and the adjoint
+ * that maps d(sum of selected sigma) back to the weights.
+ *
+ * Conventions (all entry points)
+ * ------------------------------
+ *  - Weights W: real, PyTorch channel-first [c_out][c_in][kh][kw], contiguous.
+ *    Tap (a, b) sits at offset y = (a - (kh-1)/2, b - (kw-1)/2) (integer
+ *    division): the kernel neighbourhood is centred at x (stencil figure of
+ *    Sec. III).  The first grid axis has length n, the second m.
+ *  - Frequencies are enumerated row-major: theta index t = p*m + q.
+ *  - Symbols A: [n][m][c_out][c_in] complex, interleaved (re, im) -- the
+ *    layout of torch.complex64 / complex128 and of the paper's row-major
+ *    transformed tensor (Sec. IV, "Memory Layout Effects").
+ *  - r = min(c_out, c_in).  sigma: [n][m][r] real, descending per frequency.
+ *    U: [n][m][c_out][r] complex; V: [n][m][c_in][r] complex (thin SVD,
+ *    A_k = U_k diag(sigma_k) V_k^H).  Where sigma_j(k) == 0 the column u_j is
+ *    an arbitrary unit vector orthogonal to the other columns.
+ *  - dtype LFA_F32: W and sigma are float, A/U/V complex float.
+ *    dtype LFA_F64: double / complex double throughout.
+ *  - Every array argument that is "per layer" is a host array of num_layers
+ *    device pointers.  All device buffers are allocated and owned by the
+ *    caller; the library never allocates device memory inside a compute call.
+ *    lfa_plan_create allocates small constant tables (twiddles, work lists)
+ *    that lfa_plan_destroy frees.
+ *  - `stream` is a hipStream_t passed as void* (NULL = default stream).  All
+ *    compute calls are asynchronous on that stream; the return value covers
+ *    only the checks made at enqueue time.
+ *  - Return value: LFA_OK (0) on success, a negative LFA_ERR_* on error.
+ *    After an LFA_ERR_HIP, lfa_last_hip_error() returns the hipError_t of the
+ *    failing HIP call (per thread).
+ *  - A plan is immutable after lfa_plan_create/lfa_autotune and may be used
+ *    from several threads at once, as long as concurrent calls use distinct
+ *    workspaces and outputs.
+ */
+#ifndef LFA_H
+#define LFA_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define LFA_VERSION 1
+
+typedef struct lfa_plan lfa_plan;
+typedef struct lfa_graph lfa_graph;
+
+/* One stride-1, periodic convolution layer. */
+typedef struct lfa_layer {
+    int32_t c_out, c_in; /* channels: the symbol is c_out x c_in           */
+    int32_t kh, kw;      /* kernel extent; 1 <= kh <= n, 1 <= kw <= m        */
+    int32_t n, m;        /* periodic grid; n*m symbols                      */
+} lfa_layer;
+
+enum lfa_dtype { LFA_F32 = 0, LFA_F64 = 1 };
+
+enum lfa_flags {
+    LFA_WANT_U = 1u,      /* lfa_svd writes U                                   */
+    LFA_WANT_V = 2u,      /* lfa_svd writes V                                   */
+    LFA_ASM_MFMA = 4u,    /* lfa_svd assembles symbols with the MFMA kernel into
+                             the workspace first (FP32 matrix cores) instead of
+                             fusing the assembly into the SVD kernel           */
+    LFA_ASM_BF16X2 = 8u,  /* as LFA_ASM_MFMA, split-BF16 with 3 products
+                             (hi*hi + hi*lo + lo*hi), FP32 accumulation          */
+    LFA_ASM_BF16X3 = 16u  /* as LFA_ASM_MFMA, split-BF16 with 6 products
+                             (three-term split), FP32 accumulation               */
+};
+
+enum lfa_status {
+    LFA_OK = 0,
+    LFA_ERR_INVALID_ARG = -1, /* null required pointer, bad sizes, kh > n ...  */
+    LFA_ERR_UNSUPPORTED = -2, /* dtype/flag combination or size not supported  */
+    LFA_ERR_WORKSPACE = -3,   /* workspace missing or smaller than required    */
+    LFA_ERR_HIP = -4,         /* a HIP runtime call or kernel launch failed    */
+    LFA_ERR_NO_DEVICE = -5    /* no usable gfx950 device                       */
+};
+
+/* Per-layer convergence record written by the SVD entry points into the
+ * caller's device buffer `info` (int32, LFA_INFO_WORDS per layer).  The
+ * library clears it on the stream before use. */
+enum lfa_info_word {
+    LFA_INFO_NONCONVERGED = 0, /* symbols that hit the sweep cap               */
+    LFA_INFO_MAX_SWEEPS = 1,   /* largest number of sweeps used by a symbol    */
+    LFA_INFO_SUM_SWEEPS = 2,   /* total sweeps over the layer's symbols        */
+    LFA_INFO_NONFINITE = 3,    /* symbols with a non-finite entry              */
+    LFA_INFO_WORDS = 4
+};
+
+/* ---- plans -------------------------------------------------------------- */
+
+/* Validate the layers and build a plan: size class and launch shape of each
+ * layer, the work list of the persistent batched launch, and device twiddle
+ * tables exp(2 pi i j / n) computed on the host in double precision (the grid
+ * of Algorithm 1's Init step).  Device tables are uploaded to the current
+ * device on first use, so this call itself needs no GPU.
+ *   out        : receives the plan (set to NULL on error)
+ *   layers     : host array of num_layers descriptors (copied)
+ *   num_layers : >= 1
+ *   dtype      : LFA_F32 or LFA_F64
+ *   flags      : OR of lfa_flags.  BF16/MFMA assembly requires LFA_F32.
+ * Errors: INVALID_ARG for null pointers, non-positive sizes, kh > n, kw > m
+ * (taps would alias); UNSUPPORTED for r > 1024, kh*kw > 128, or a flag that
+ * does not fit the dtype. */
+int lfa_plan_create(lfa_plan** out, const lfa_layer* layers, int32_t num_layers,
+                    int32_t dtype, uint32_t flags);
+
+/* Free the plan and its device tables.  NULL is accepted. */
+int lfa_plan_destroy(lfa_plan* plan);
+
+/* Bytes of device workspace every compute call on this plan needs (the
+ * maximum over entry points).  Writes 0 if none. */
+int lfa_plan_workspace_bytes(const lfa_plan* plan, size_t* bytes);
+
+/* Number of layers, and a copy of layer i's descriptor. */
+int lfa_plan_num_layers(const lfa_plan* plan, int32_t* num_layers);
+int lfa_plan_layer(const lfa_plan* plan, int32_t i, lfa_layer* layer);
+
+/* ---- step a1: symbol assembly ----------------------------------------- */
+
+/* A[layer][p][q][:, :] = sum_y W[layer][:, :, y] exp(+2 pi i <k, y>)
+ * (Sec. III "Convolution Theorem"; Algorithm 1 symbol step), for every
+ * frequency.  W: per-layer device pointers to weights; A: per-layer device
+ * pointers to [n][m][c_out][c_in] complex outputs.  The assembly kernel is
+ * chosen by the plan's flags: LFA_ASM_BF16X2 / X3 use split-BF16 matrix
+ * cores, LFA_ASM_MFMA FP32 matrix cores, otherwise a vector kernel
+ * (FP32 or FP64 per dtype).  No workspace is used. */
+int lfa_symbols(const lfa_plan* plan, const void* const* W, void* const* A, void* stream);
+
+/* ---- steps a1-a3: SVD of every symbol ------------------------------- */
+
+/* For every layer and frequency, the SVD of the symbol (Sec. III
+ * "Convolution Theorem"; Algorithm 1 SVD step) by one-sided Jacobi,
+ * singular values sorted descending.
+ *   W     : per-layer weights (device)
+ *   sigma : per-layer [n][m][r] outputs (device), required
+ *   U, V  : per-layer outputs, required iff the plan has LFA_WANT_U /
+ *           LFA_WANT_V, ignored (may be NULL) otherwise
+ *   info  : device int32 [num_layers][LFA_INFO_WORDS] or NULL
+ *   ws    : device workspace of ws_bytes >= lfa_plan_workspace_bytes
+ * The plain path: one launch per layer (plus one assembly launch per layer
+ * when the plan asks for MFMA/BF16 assembly). */
+int lfa_svd(const lfa_plan* plan, const void* const* W, void* const* sigma, void* const* U,
+            void* const* V, int32_t* info, void* ws, size_t ws_bytes, void* stream);
+
+/* Same results as lfa_svd for all layers of the plan in ONE persistent
+ * launch: work-groups take (layer, frequency) items from a device work list,
+ * largest symbols first.  Fused FP32/FP64 assembly only (no MFMA/BF16 flag). */
+int lfa_svd_persistent(const lfa_plan* plan, const void* const* W, void* const* sigma,
+                       void* const* U, void* const* V, int32_t* info, void* ws,
+                       size_t ws_bytes, void* stream);
+
+/* SVD of symbols the caller already holds (e.g. from lfa_symbols), same
+ * outputs as lfa_svd.  A: per-layer [n][m][c_out][c_in] complex (device). */
+int lfa_svd_symbols(const lfa_plan* plan, const void* const* A, void* const* sigma,
+                    void* const* U, void* const* V, int32_t* info, void* ws,
+                    size_t ws_bytes, void* stream);
+
+/* ---- step a4: top-k per layer --------------------------------------- */
+
+/* The k largest singular values of each layer over all (p, q, j), ordered by
+ * value descending, ties by flat index (p, q, j) ascending.
+ *   sigma : per-layer [n][m][r] (device, dtype of the plan)
+ *   k     : 1 <= k <= 64 and k <= n*m*r of every layer
+ *   vals  : device [num_layers][k] (dtype of the plan)
+ *   idx   : device int32 [num_layers][k][3] = (p, q, j)
+ * One launch for all layers. */
+int lfa_topk(const lfa_plan* plan, const void* const* sigma, int32_t k, void* vals,
+             int32_t* idx, void* stream);
+
+/* ---- step a5: adjoint -------------------------------------------------- */
+
+/* dW[layer][o][i][a][b] = sum_s g[layer][s] *
+ *     Re( exp(-2 pi i <k_s, y_ab>) * U_s[o] * conj(V_s[i]) )
+ * the gradient of sum_s g_s sigma_{j_s}(k_s) for simple singular values
+ * (first-order perturbation d sigma = Re(u^H dA v)).  dW is overwritten.
+ *   U, V  : per-layer full SVD outputs as written by lfa_svd
+ *   idx   : device int32 [num_layers][k][3] (p, q, j), e.g. from lfa_topk
+ *   grad  : device [num_layers][k] weights g (dtype of the plan)
+ *   dW    : per-layer device outputs shaped like W
+ * One launch for all layers. */
+int lfa_adjoint(const lfa_plan* plan, const void* const* U, const void* const* V,
+                const int32_t* idx, const void* grad, int32_t k, void* const* dW,
+                void* stream);
+
+/* As lfa_adjoint, but recomputes the singular vectors of only the selected
+ * symbols (at most k per layer) from W into the workspace, so the forward
+ * pass can be sigma-only.  Two launches (SVD of the selected symbols, then
+ * the adjoint). */
+int lfa_sigma_grad(const lfa_plan* plan, const void* const* W, const int32_t* idx,
+                   const void* grad, int32_t k, void* const* dW, void* ws, size_t ws_bytes,
+                   void* stream);
+
+/* ---- batched forward + backward as one HIP graph ---------------------- */
+
+/* Capture [lfa_svd_persistent (sigma only) -> lfa_topk -> lfa_sigma_grad]
+ * for fixed buffers into a HIP graph.  Replaying it with new contents in W
+ * recomputes sigma, the top-k and dW.  `grad` holds g for every selected
+ * value (e.g. all ones for L = sum of the top-k).  Buffers must stay alive
+ * and at the same addresses while the graph exists. */
+int lfa_graph_create(lfa_plan* plan, const void* const* W, void* const* sigma, int32_t k,
+                     void* vals, int32_t* idx, const void* grad, void* const* dW,
+                     int32_t* info, void* ws, size_t ws_bytes, void* stream, lfa_graph** out);
+int lfa_graph_launch(lfa_graph* graph, void* stream);
+int lfa_graph_destroy(lfa_graph* graph);
+
+/* ---- tuning and diagnostics ------------------------------------------- */
+
+/* Time the candidate launch shapes of every layer on `stream` (running the
+ * SVD on W into sigma/U/V, which are overwritten) and store the fastest in
+ * the plan.  Optional: plans carry a default shape chosen by a cost model. */
+int lfa_autotune(lfa_plan* plan, const void* const* W, void* const* sigma, void* const* U,
+                 void* const* V, void* ws, size_t ws_bytes, void* stream);
+
+/* Launch shape chosen for a layer: lanes per column pair, threads per
+ * work-group, symbols per work-group and storage (0 = LDS, 1 = global). */
+int lfa_plan_launch_shape(const lfa_plan* plan, int32_t layer, int32_t* lanes_per_pair,
+                          int32_t* threads, int32_t* symbols_per_group, int32_t* storage);
+
+/* Static text for a status code; never NULL. */
+const char* lfa_status_string(int status);
+
+/* hipError_t of the last failing HIP call on this thread (0 if none). */
+int lfa_last_hip_error(void);
+
+/* LFA_VERSION of the built library. */
+int lfa_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LFA_H */

@@ -1,0 +1,835 @@
+// Host side of liblfa: plans, launch shapes, workspace layout, and the
+// extern "C" entry points declared in include/lfa.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "lfa.h"
+#include "lfa_internal.hpp"
+
+using namespace lfa;
+
+namespace {
+
+thread_local int g_last_hip = 0;
+
+int hip_fail(hipError_t e) {
+    g_last_hip = static_cast<int>(e);
+    return LFA_ERR_HIP;
+}
+
+#define HIP_TRY(expr)                              \
+    do {                                           \
+        hipError_t _e = (expr);                    \
+        if (_e != hipSuccess) return hip_fail(_e); \
+    } while (0)
+
+#define LFA_TRY(expr)                \
+    do {                             \
+        int _s = (expr);             \
+        if (_s != LFA_OK) return _s; \
+    } while (0)
+
+constexpr size_t kAlign = 256;
+constexpr size_t kLdsCap = 160 * 1024 - 1024;  // gfx950: 160 KiB of LDS per work-group
+constexpr size_t kLdsSafe = 64 * 1024;         // always available without opt-in
+constexpr int kGlobalGrid = 1024;              // blocks of a launch using global slots
+constexpr int kPersistentGrid = 1024;          // upper bound of the persistent grid
+constexpr int kPersistentThreads = 256;
+constexpr size_t kPersistentLdsCap = 72 * 1024;
+constexpr int kMaxTopk = 64;
+constexpr int kMaxSweeps = 40;
+
+size_t align_up(size_t x, size_t a = kAlign) { return (x + a - 1) / a * a; }
+int pow2ceil(int x) {
+    int p = 1;
+    while (p < x) p <<= 1;
+    return p;
+}
+
+int elem_bytes(int dtype) { return dtype == LFA_F64 ? 8 : 4; }
+
+}  // namespace
+
+struct lfa_plan {
+    int dtype = LFA_F32;
+    uint32_t flags = 0;
+    std::vector<lfa_layer> layers;
+    std::vector<int> tw_n, tw_m;          // twiddle offsets per layer
+    std::vector<LayerDesc> desc;          // plain lfa_svd launch shape
+    std::vector<LayerDesc> desc_pers;     // persistent launch shape
+    std::vector<LayerDesc> desc_sel;      // SVD with vectors of selected symbols
+    std::vector<double> tw_host;          // (re, im) pairs
+    std::vector<WorkItem> items;          // persistent work list, LPT order per chunk
+    std::vector<int> chunk_first;         // first item of each chunk of layers (+ end)
+    double tol = 0;
+    std::mutex mu;
+    int device = -1;
+    double* tw_dev = nullptr;
+    WorkItem* items_dev = nullptr;
+};
+
+struct lfa_graph {
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+namespace {
+
+bool accumulates(const LayerDesc& d, bool want_u, bool want_v) {
+    return d.transposed ? want_u : want_v;
+}
+
+// Cost-model launch shape: enough lanes per pair that a lane holds at most
+// kRowsPerLane rows, one lane group per column pair of a step (capped at
+// 1024 threads), LDS storage when the working matrices fit under `lds_cap`.
+LayerDesc make_desc(const lfa_layer& l, int tw_n, int tw_m, bool acc, int eb, size_t lds_cap,
+                    int threads_override = 0, int L_override = 0) {
+    LayerDesc d{};
+    d.c_out = l.c_out;
+    d.c_in = l.c_in;
+    d.kh = l.kh;
+    d.kw = l.kw;
+    d.n = l.n;
+    d.m = l.m;
+    d.M = std::max(l.c_out, l.c_in);
+    d.N = std::min(l.c_out, l.c_in);
+    d.transposed = l.c_out < l.c_in ? 1 : 0;
+    d.tw_n = tw_n;
+    d.tw_m = tw_m;
+    d.num_symbols = l.n * l.m;
+    int L = pow2ceil((d.M + kRowsPerLane - 1) / kRowsPerLane);
+    L = std::max(1, std::min(64, L));
+    if (L_override) L = L_override;
+    d.L = L;
+    const int npairs = (d.N + 1) / 2;
+    int threads = pow2ceil(std::max(1, npairs * L));
+    threads = std::max(64, std::min(1024, threads));
+    if (threads_override) threads = threads_override;
+    d.threads = threads;
+    d.ldg = d.M | 1;
+    d.ldv = d.N | 1;
+    d.storage = kLds;
+    if (lds_bytes_for(d, acc, eb) > lds_cap) d.storage = kGlobal;
+    d.sym_offset = 0;
+    return d;
+}
+
+size_t slot_bytes(const LayerDesc& d, bool acc, int eb) {
+    if (d.storage != kGlobal) return 0;
+    const size_t cb = 2 * (size_t)eb;
+    return align_up(cb * d.ldg * d.N + (acc ? cb * d.ldv * d.N : 0));
+}
+
+int svd_grid(const LayerDesc& d, int count) {
+    return d.storage == kGlobal ? std::min(count, kGlobalGrid) : count;
+}
+
+size_t symbols_bytes(const lfa_layer& l, int eb) {
+    return align_up((size_t)l.n * l.m * l.c_out * l.c_in * 2 * eb);
+}
+
+bool asm_materialized(uint32_t flags) {
+    return (flags & (LFA_ASM_MFMA | LFA_ASM_BF16X2 | LFA_ASM_BF16X3)) != 0;
+}
+
+int asm_mode(uint32_t flags) {
+    if (flags & LFA_ASM_BF16X3) return 3;
+    if (flags & LFA_ASM_BF16X2) return 2;
+    return 0;
+}
+
+size_t sel_bytes(const lfa_layer& l, int eb) {
+    const size_t r = std::min(l.c_out, l.c_in);
+    return align_up((size_t)kMaxTopk * (r * eb + (size_t)(l.c_out + l.c_in) * r * 2 * eb));
+}
+
+// Workspace layout (offsets from ws):
+//   [0, 256)                   persistent dequeue counter
+//   [256, 256 + big)           per-entry-point region (regions of different
+//                              entry points may overlap: calls are stream-ordered)
+size_t workspace_bytes(const lfa_plan& p) {
+    const int eb = elem_bytes(p.dtype);
+    const bool wu = p.flags & LFA_WANT_U, wv = p.flags & LFA_WANT_V;
+    size_t need = 0;
+    for (size_t i = 0; i < p.layers.size(); ++i) {
+        const LayerDesc& d = p.desc[i];
+        const bool acc = accumulates(d, wu, wv);
+        // lfa_svd / lfa_svd_symbols: symbols (materialised assembly) + slots.
+        // A layer whose LDS need exceeds the always-available 64 KiB may fall
+        // back to global slots on a device with less LDS: reserve for that too.
+        LayerDesc dg = d;
+        dg.storage = (lds_bytes_for(d, acc, eb) > kLdsSafe) ? kGlobal : d.storage;
+        size_t s = (size_t)svd_grid(dg, d.num_symbols) * slot_bytes(dg, acc, eb);
+        if (asm_materialized(p.flags)) s += symbols_bytes(p.layers[i], eb);
+        need = std::max(need, s);
+        // lfa_sigma_grad: compact outputs of <= kMaxTopk symbols + slots
+        const LayerDesc& ds = p.desc_sel[i];
+        LayerDesc dsg = ds;
+        dsg.storage = (lds_bytes_for(ds, true, eb) > kLdsSafe) ? kGlobal : ds.storage;
+        need = std::max(need, sel_bytes(p.layers[i], eb) +
+                                  (size_t)kMaxTopk * slot_bytes(dsg, true, eb));
+    }
+    // persistent: slots for the global-storage layers
+    size_t pslot = 0;
+    for (size_t i = 0; i < p.layers.size(); ++i) {
+        LayerDesc d = p.desc_pers[i];
+        const bool acc = accumulates(d, wu, wv);
+        if (lds_bytes_for(d, acc, eb) > kLdsSafe) d.storage = kGlobal;
+        pslot = std::max(pslot, slot_bytes(d, acc, eb));
+    }
+    need = std::max(need, (size_t)kPersistentGrid * pslot);
+    return kAlign + align_up(need);
+}
+
+int validate_layer(const lfa_layer& l) {
+    if (l.c_out <= 0 || l.c_in <= 0 || l.kh <= 0 || l.kw <= 0 || l.n <= 0 || l.m <= 0)
+        return LFA_ERR_INVALID_ARG;
+    if (l.kh > l.n || l.kw > l.m) return LFA_ERR_INVALID_ARG;
+    if (std::max(l.c_out, l.c_in) > 64 * kRowsPerLane) return LFA_ERR_UNSUPPORTED;
+    if (std::min(l.c_out, l.c_in) > kMaxR) return LFA_ERR_UNSUPPORTED;
+    if (l.kh * l.kw > kMaxTaps) return LFA_ERR_UNSUPPORTED;
+    const long long hw = (long long)l.n * l.m;
+    if (hw > (1LL << 30) || (long long)l.c_out * l.c_in > (1LL << 24)) return LFA_ERR_UNSUPPORTED;
+    return LFA_OK;
+}
+
+// Upload device tables on first use from the current device.
+int ensure_device(lfa_plan* p) {
+    std::lock_guard<std::mutex> lock(p->mu);
+    int dev = -1;
+    int count = 0;
+    hipError_t e = hipGetDeviceCount(&count);
+    if (e != hipSuccess || count <= 0) {
+        g_last_hip = (int)e;
+        return LFA_ERR_NO_DEVICE;
+    }
+    HIP_TRY(hipGetDevice(&dev));
+    if (p->device >= 0) return p->device == dev ? LFA_OK : LFA_ERR_INVALID_ARG;
+    hipDeviceProp_t prop;
+    HIP_TRY(hipGetDeviceProperties(&prop, dev));
+    if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0) return LFA_ERR_NO_DEVICE;
+    HIP_TRY(hipMalloc(&p->tw_dev, p->tw_host.size() * sizeof(double)));
+    HIP_TRY(hipMemcpy(p->tw_dev, p->tw_host.data(), p->tw_host.size() * sizeof(double),
+                      hipMemcpyHostToDevice));
+    HIP_TRY(hipMalloc(&p->items_dev, std::max<size_t>(1, p->items.size()) * sizeof(WorkItem)));
+    if (!p->items.empty())
+        HIP_TRY(hipMemcpy(p->items_dev, p->items.data(), p->items.size() * sizeof(WorkItem),
+                          hipMemcpyHostToDevice));
+    // Devices reporting less LDS than the plan assumed: move layers to global slots.
+    const size_t lds_dev = prop.sharedMemPerBlock;
+    const int eb = elem_bytes(p->dtype);
+    const bool wu = p->flags & LFA_WANT_U, wv = p->flags & LFA_WANT_V;
+    for (size_t i = 0; i < p->layers.size(); ++i) {
+        if (lds_bytes_for(p->desc[i], accumulates(p->desc[i], wu, wv), eb) > lds_dev)
+            p->desc[i].storage = kGlobal;
+        if (lds_bytes_for(p->desc_sel[i], true, eb) > lds_dev) p->desc_sel[i].storage = kGlobal;
+        if (lds_bytes_for(p->desc_pers[i], accumulates(p->desc_pers[i], wu, wv), eb) > lds_dev)
+            p->desc_pers[i].storage = kGlobal;
+    }
+    p->device = dev;
+    return LFA_OK;
+}
+
+template <typename R>
+int run_svd_layer(const lfa_plan* p, const LayerDesc& d, const void* W, const void* A,
+                  void* sigma, void* U, void* V, int32_t* info, char* region,
+                  const int32_t* theta_list, int theta_stride, int theta_count,
+                  hipStream_t st) {
+    SvdArgs<R> a{};
+    a.d = d;
+    a.W = static_cast<const R*>(W);
+    a.A = static_cast<const cplx<R>*>(A);
+    a.sigma = static_cast<R*>(sigma);
+    a.U = static_cast<cplx<R>*>(U);
+    a.V = static_cast<cplx<R>*>(V);
+    a.info = info;
+    a.tw = p->tw_dev;
+    a.theta_list = theta_list;
+    a.theta_stride = theta_stride;
+    a.theta_count = theta_count;
+    a.max_sweeps = kMaxSweeps;
+    a.tol = p->tol * d.M;
+    const bool acc = (d.transposed ? U : V) != nullptr;
+    const int count = theta_list ? theta_count : d.num_symbols;
+    if (count <= 0) return LFA_OK;
+    const int grid = svd_grid(d, count);
+    a.slot_bytes = (long long)slot_bytes(d, acc, sizeof(R));
+    a.gws = d.storage == kGlobal ? region : nullptr;
+    const size_t lds = lds_bytes_for(d, acc, sizeof(R));
+    hipError_t e;
+    if constexpr (sizeof(R) == 4) e = launch_svd_f32(a, grid, lds, st);
+    else e = launch_svd_f64(a, grid, lds, st);
+    HIP_TRY(e);
+    return LFA_OK;
+}
+
+int check_ws(const lfa_plan* p, void* ws, size_t ws_bytes) {
+    const size_t need = workspace_bytes(*p);
+    if (need > kAlign && (ws == nullptr || ws_bytes < need)) return LFA_ERR_WORKSPACE;
+    return LFA_OK;
+}
+
+template <typename R>
+int svd_impl(const lfa_plan* p, const void* const* W, const void* const* A, void* const* sigma,
+             void* const* U, void* const* V, int32_t* info, void* ws, size_t ws_bytes,
+             hipStream_t st) {
+    const bool wu = p->flags & LFA_WANT_U, wv = p->flags & LFA_WANT_V;
+    char* region = static_cast<char*>(ws) + kAlign;
+    if (info) HIP_TRY(launch_fill_i32(info, 0, (long long)p->layers.size() * LFA_INFO_WORDS, st));
+    for (size_t i = 0; i < p->layers.size(); ++i) {
+        const LayerDesc& d = p->desc[i];
+        const void* Wi = nullptr;
+        const void* Ai = A ? A[i] : nullptr;
+        char* slots = region;
+        if (!A) {
+            if (asm_materialized(p->flags)) {
+                cplx<float>* sym = reinterpret_cast<cplx<float>*>(region);
+                HIP_TRY(launch_symbols_mfma(d, static_cast<const float*>(W[i]), sym, p->tw_dev,
+                                            asm_mode(p->flags), st));
+                Ai = sym;
+                slots = region + symbols_bytes(p->layers[i], sizeof(R));
+            } else {
+                Wi = W[i];
+            }
+        }
+        LFA_TRY(run_svd_layer<R>(p, d, Wi, Ai, sigma[i], wu ? U[i] : nullptr,
+                                 wv ? V[i] : nullptr,
+                                 info ? info + i * LFA_INFO_WORDS : nullptr, slots, nullptr, 0, 0,
+                                 st));
+    }
+    return LFA_OK;
+}
+
+int check_ptrs(const lfa_plan* p, const void* const* arr, bool required) {
+    if (!required) return LFA_OK;
+    if (!arr) return LFA_ERR_INVALID_ARG;
+    for (size_t i = 0; i < p->layers.size(); ++i)
+        if (!arr[i]) return LFA_ERR_INVALID_ARG;
+    return LFA_OK;
+}
+
+template <typename R>
+int persistent_impl(const lfa_plan* p, const void* const* W, void* const* sigma, void* const* U,
+                    void* const* V, int32_t* info, void* ws, hipStream_t st) {
+    const bool wu = p->flags & LFA_WANT_U, wv = p->flags & LFA_WANT_V;
+    int32_t* counter = static_cast<int32_t*>(ws);
+    char* region = static_cast<char*>(ws) + kAlign;
+    if (info) HIP_TRY(launch_fill_i32(info, 0, (long long)p->layers.size() * LFA_INFO_WORDS, st));
+    const int nl = (int)p->layers.size();
+    // one launch per chunk of kMaxLaunchLayers layers (kernel-argument limit)
+    for (int l0 = 0; l0 < nl; l0 += kMaxLaunchLayers) {
+        const int l1 = std::min(nl, l0 + kMaxLaunchLayers);
+        PersistentArgs<R> pa{};
+        pa.num_layers = l1 - l0;
+        pa.threads = kPersistentThreads;
+        size_t lds = 0, slot = 0;
+        for (int i = l0; i < l1; ++i) {
+            const LayerDesc& d = p->desc_pers[i];
+            const bool acc = accumulates(d, wu, wv);
+            SvdArgs<R>& a = pa.layer[i - l0];
+            a.d = d;
+            a.W = static_cast<const R*>(W[i]);
+            a.sigma = static_cast<R*>(sigma[i]);
+            a.U = wu ? static_cast<cplx<R>*>(U[i]) : nullptr;
+            a.V = wv ? static_cast<cplx<R>*>(V[i]) : nullptr;
+            a.info = info ? info + i * LFA_INFO_WORDS : nullptr;
+            a.tw = p->tw_dev;
+            a.max_sweeps = kMaxSweeps;
+            a.tol = p->tol * d.M;
+            a.slot_bytes = (long long)slot_bytes(d, acc, sizeof(R));
+            a.gws = d.storage == kGlobal ? region : nullptr;
+            lds = std::max(lds, lds_bytes_for(d, acc, sizeof(R)));
+            slot = std::max(slot, (size_t)a.slot_bytes);
+        }
+        const int chunk = l0 / kMaxLaunchLayers;
+        const int first = p->chunk_first[chunk];
+        const int count = p->chunk_first[chunk + 1] - first;
+        if (count == 0) continue;
+        pa.items = p->items_dev + first;
+        pa.num_items = count;
+        pa.counter = counter;
+        HIP_TRY(launch_fill_i32(counter, 0, 1, st));
+        const int grid = std::min(kPersistentGrid, count);
+        hipError_t e;
+        if constexpr (sizeof(R) == 4) e = launch_persistent_f32(pa, grid, lds, st);
+        else e = launch_persistent_f64(pa, grid, lds, st);
+        HIP_TRY(e);
+    }
+    return LFA_OK;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// Selected-symbol SVD + adjoint (sigma gradient)
+// ---------------------------------------------------------------------------
+namespace {
+
+template <typename R>
+int adjoint_launch(const lfa_plan* p, int l0, int l1, const void* const* U, const void* const* V,
+                   const int32_t* idx, const void* grad, int k, void* const* dW, int compact,
+                   hipStream_t st) {
+    AdjointArgs<R> a{};
+    a.num_layers = l1 - l0;
+    a.k = k;
+    a.compact = compact;
+    a.idx = idx + (size_t)l0 * k * 3;
+    a.grad = static_cast<const R*>(grad) + (size_t)l0 * k;
+    a.tw = p->tw_dev;
+    int blocks = 0;
+    for (int i = l0; i < l1; ++i) {
+        const lfa_layer& l = p->layers[i];
+        const int j = i - l0;
+        a.c_out[j] = l.c_out;
+        a.c_in[j] = l.c_in;
+        a.kh[j] = l.kh;
+        a.kw[j] = l.kw;
+        a.n[j] = l.n;
+        a.m[j] = l.m;
+        a.tw_n[j] = p->tw_n[i];
+        a.tw_m[j] = p->tw_m[i];
+        a.U[j] = static_cast<const cplx<R>*>(U[compact ? j : i]);
+        a.V[j] = static_cast<const cplx<R>*>(V[compact ? j : i]);
+        a.dW[j] = static_cast<R*>(dW[i]);
+        a.blocks_before[j] = blocks;
+        blocks += (l.c_out * l.c_in + 255) / 256;
+    }
+    a.blocks_before[l1 - l0] = blocks;
+    hipError_t e;
+    if constexpr (sizeof(R) == 4) e = launch_adjoint_f32(a, st);
+    else e = launch_adjoint_f64(a, st);
+    HIP_TRY(e);
+    return LFA_OK;
+}
+
+template <typename R>
+int sigma_grad_impl(const lfa_plan* p, const void* const* W, const int32_t* idx, const void* grad,
+                    int k, void* const* dW, void* ws, hipStream_t st) {
+    char* region = static_cast<char*>(ws) + kAlign;
+    const int eb = sizeof(R);
+    // Layers one after the other, reusing one compact buffer: SVD with
+    // vectors of the k selected symbols, then the adjoint of the layer.
+    for (size_t i = 0; i < p->layers.size(); ++i) {
+        const lfa_layer& l = p->layers[i];
+        const LayerDesc& d = p->desc_sel[i];
+        const size_t r = std::min(l.c_out, l.c_in);
+        char* sig = region;
+        char* Uc = sig + align_up((size_t)k * r * eb);
+        char* Vc = Uc + align_up((size_t)k * l.c_out * r * 2 * eb);
+        char* slots = region + sel_bytes(l, eb);
+        LFA_TRY(run_svd_layer<R>(p, d, W[i], nullptr, sig, Uc, Vc, nullptr, slots,
+                                 idx + (size_t)i * k * 3, 3, k, st));
+        const void* Ua[1] = {Uc};
+        const void* Va[1] = {Vc};
+        LFA_TRY(adjoint_launch<R>(p, (int)i, (int)i + 1, Ua, Va, idx, grad, k, dW, 1, st));
+    }
+    return LFA_OK;
+}
+
+template <typename R>
+int topk_impl(const lfa_plan* p, const void* const* sigma, int k, void* vals, int32_t* idx,
+              hipStream_t st) {
+    const int nl = (int)p->layers.size();
+    for (int l0 = 0; l0 < nl; l0 += kMaxLaunchLayers) {
+        const int l1 = std::min(nl, l0 + kMaxLaunchLayers);
+        TopkArgs<R> a{};
+        a.num_layers = l1 - l0;
+        a.k = k;
+        a.vals = static_cast<R*>(vals) + (size_t)l0 * k;
+        a.idx = idx + (size_t)l0 * k * 3;
+        for (int i = l0; i < l1; ++i) {
+            a.sigma[i - l0] = static_cast<const R*>(sigma[i]);
+            a.n[i - l0] = p->layers[i].n;
+            a.m[i - l0] = p->layers[i].m;
+            a.r[i - l0] = std::min(p->layers[i].c_out, p->layers[i].c_in);
+        }
+        hipError_t e;
+        if constexpr (sizeof(R) == 4) e = launch_topk_f32(a, st);
+        else e = launch_topk_f64(a, st);
+        HIP_TRY(e);
+    }
+    return LFA_OK;
+}
+
+int check_k(const lfa_plan* p, int k) {
+    if (k < 1 || k > kMaxTopk) return LFA_ERR_INVALID_ARG;
+    for (const lfa_layer& l : p->layers) {
+        if ((long long)l.n * l.m * std::min(l.c_out, l.c_in) < k) return LFA_ERR_INVALID_ARG;
+        if (k * l.kh * l.kw > 4096) return LFA_ERR_UNSUPPORTED;
+    }
+    return LFA_OK;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// extern "C"
+// ---------------------------------------------------------------------------
+extern "C" {
+
+int lfa_version(void) { return LFA_VERSION; }
+
+int lfa_last_hip_error(void) { return g_last_hip; }
+
+const char* lfa_status_string(int status) {
+    switch (status) {
+        case LFA_OK: return "success";
+        case LFA_ERR_INVALID_ARG: return "invalid argument";
+        case LFA_ERR_UNSUPPORTED: return "unsupported size, dtype or flag combination";
+        case LFA_ERR_WORKSPACE: return "workspace missing or too small";
+        case LFA_ERR_HIP: return "HIP runtime error (see lfa_last_hip_error)";
+        case LFA_ERR_NO_DEVICE: return "no usable gfx950 device";
+        default: return "unknown status";
+    }
+}
+
+int lfa_plan_create(lfa_plan** out, const lfa_layer* layers, int32_t num_layers, int32_t dtype,
+                    uint32_t flags) {
+    if (!out) return LFA_ERR_INVALID_ARG;
+    *out = nullptr;
+    if (!layers || num_layers < 1 || num_layers > kMaxLayers) return LFA_ERR_INVALID_ARG;
+    if (dtype != LFA_F32 && dtype != LFA_F64) return LFA_ERR_INVALID_ARG;
+    const uint32_t known = LFA_WANT_U | LFA_WANT_V | LFA_ASM_MFMA | LFA_ASM_BF16X2 | LFA_ASM_BF16X3;
+    if (flags & ~known) return LFA_ERR_INVALID_ARG;
+    const uint32_t asm_flags = flags & (LFA_ASM_MFMA | LFA_ASM_BF16X2 | LFA_ASM_BF16X3);
+    if (asm_flags & (asm_flags - 1)) return LFA_ERR_INVALID_ARG;   // more than one
+    if (asm_flags && dtype != LFA_F32) return LFA_ERR_UNSUPPORTED;
+    for (int i = 0; i < num_layers; ++i) LFA_TRY(validate_layer(layers[i]));
+
+    lfa_plan* p = new (std::nothrow) lfa_plan();
+    if (!p) return LFA_ERR_INVALID_ARG;
+    p->dtype = dtype;
+    p->flags = flags;
+    p->layers.assign(layers, layers + num_layers);
+    const int eb = elem_bytes(dtype);
+    // unit roundoff of the working precision; the convergence threshold of a
+    // layer is tol * M
+    p->tol = dtype == LFA_F64 ? std::ldexp(1.0, -53) : std::ldexp(1.0, -24);
+
+    // twiddles exp(2 pi i j / L) for every distinct grid length L
+    std::map<int, int> off;
+    for (const lfa_layer& l : p->layers) {
+        for (int len : {l.n, l.m}) {
+            if (off.count(len)) continue;
+            off[len] = (int)(p->tw_host.size() / 2);
+            for (int j = 0; j < len; ++j) {
+                // reduce j/len to [-1/2, 1/2) turns before the library cos/sin
+                const double turns = (2 * j < len) ? double(j) / len : double(j - len) / len;
+                const double ang = 2.0 * M_PI * turns;
+                p->tw_host.push_back(std::cos(ang));
+                p->tw_host.push_back(std::sin(ang));
+            }
+        }
+    }
+    const bool wu = flags & LFA_WANT_U, wv = flags & LFA_WANT_V;
+    for (const lfa_layer& l : p->layers) {
+        p->tw_n.push_back(off[l.n]);
+        p->tw_m.push_back(off[l.m]);
+        LayerDesc d = make_desc(l, off[l.n], off[l.m], false, eb, kLdsCap);
+        d = make_desc(l, off[l.n], off[l.m], accumulates(d, wu, wv), eb, kLdsCap);
+        p->desc.push_back(d);
+        p->desc_sel.push_back(make_desc(l, off[l.n], off[l.m], true, eb, kLdsCap));
+        LayerDesc dp = make_desc(l, off[l.n], off[l.m], accumulates(d, wu, wv), eb,
+                                 kPersistentLdsCap, kPersistentThreads);
+        p->desc_pers.push_back(dp);
+    }
+    // persistent work list: per chunk of layers, items by estimated cost
+    // (N^2 M per sweep), largest first (longest-processing-time order)
+    const int nl = num_layers;
+    for (int l0 = 0; l0 < nl; l0 += kMaxLaunchLayers) {
+        const int l1 = std::min(nl, l0 + kMaxLaunchLayers);
+        p->chunk_first.push_back((int)p->items.size());
+        std::vector<std::pair<double, WorkItem>> v;
+        for (int i = l0; i < l1; ++i) {
+            const LayerDesc& d = p->desc_pers[i];
+            const double cost = double(d.N) * d.N * d.M;
+            for (int t = 0; t < d.num_symbols; ++t) v.push_back({cost, WorkItem{i - l0, t}});
+        }
+        std::stable_sort(v.begin(), v.end(),
+                         [](const std::pair<double, WorkItem>& a, const std::pair<double, WorkItem>& b) {
+                             return a.first > b.first;
+                         });
+        for (auto& x : v) p->items.push_back(x.second);
+    }
+    p->chunk_first.push_back((int)p->items.size());
+    *out = p;
+    return LFA_OK;
+}
+
+int lfa_plan_destroy(lfa_plan* plan) {
+    if (!plan) return LFA_OK;
+    if (plan->tw_dev) (void)hipFree(plan->tw_dev);
+    if (plan->items_dev) (void)hipFree(plan->items_dev);
+    delete plan;
+    return LFA_OK;
+}
+
+int lfa_plan_workspace_bytes(const lfa_plan* plan, size_t* bytes) {
+    if (!plan || !bytes) return LFA_ERR_INVALID_ARG;
+    *bytes = workspace_bytes(*plan);
+    return LFA_OK;
+}
+
+int lfa_plan_num_layers(const lfa_plan* plan, int32_t* num_layers) {
+    if (!plan || !num_layers) return LFA_ERR_INVALID_ARG;
+    *num_layers = (int32_t)plan->layers.size();
+    return LFA_OK;
+}
+
+int lfa_plan_layer(const lfa_plan* plan, int32_t i, lfa_layer* layer) {
+    if (!plan || !layer || i < 0 || i >= (int32_t)plan->layers.size()) return LFA_ERR_INVALID_ARG;
+    *layer = plan->layers[i];
+    return LFA_OK;
+}
+
+int lfa_plan_launch_shape(const lfa_plan* plan, int32_t layer, int32_t* lanes_per_pair,
+                          int32_t* threads, int32_t* symbols_per_group, int32_t* storage) {
+    if (!plan || layer < 0 || layer >= (int32_t)plan->layers.size()) return LFA_ERR_INVALID_ARG;
+    const LayerDesc& d = plan->desc[layer];
+    if (lanes_per_pair) *lanes_per_pair = d.L;
+    if (threads) *threads = d.threads;
+    if (symbols_per_group) *symbols_per_group = 1;
+    if (storage) *storage = d.storage;
+    return LFA_OK;
+}
+
+int lfa_symbols(const lfa_plan* plan, const void* const* W, void* const* A, void* stream) {
+    if (!plan) return LFA_ERR_INVALID_ARG;
+    LFA_TRY(check_ptrs(plan, W, true));
+    LFA_TRY(check_ptrs(plan, A, true));
+    lfa_plan* p = const_cast<lfa_plan*>(plan);
+    LFA_TRY(ensure_device(p));
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    for (size_t i = 0; i < p->layers.size(); ++i) {
+        const LayerDesc& d = p->desc[i];
+        hipError_t e;
+        if (p->dtype == LFA_F64)
+            e = launch_symbols_valu_f64(d, static_cast<const double*>(W[i]),
+                                        static_cast<cplx<double>*>(A[i]), p->tw_dev, st);
+        else if (asm_materialized(p->flags))
+            e = launch_symbols_mfma(d, static_cast<const float*>(W[i]),
+                                    static_cast<cplx<float>*>(A[i]), p->tw_dev,
+                                    asm_mode(p->flags), st);
+        else
+            e = launch_symbols_valu_f32(d, static_cast<const float*>(W[i]),
+                                        static_cast<cplx<float>*>(A[i]), p->tw_dev, st);
+        HIP_TRY(e);
+    }
+    return LFA_OK;
+}
+
+static int svd_common(const lfa_plan* plan, const void* const* W, const void* const* A,
+                      void* const* sigma, void* const* U, void* const* V, int32_t* info, void* ws,
+                      size_t ws_bytes, void* stream, bool persistent) {
+    if (!plan) return LFA_ERR_INVALID_ARG;
+    LFA_TRY(check_ptrs(plan, W ? W : A, true));
+    LFA_TRY(check_ptrs(plan, sigma, true));
+    LFA_TRY(check_ptrs(plan, U, (plan->flags & LFA_WANT_U) != 0));
+    LFA_TRY(check_ptrs(plan, V, (plan->flags & LFA_WANT_V) != 0));
+    if (persistent && asm_materialized(plan->flags)) return LFA_ERR_UNSUPPORTED;
+    LFA_TRY(check_ws(plan, ws, ws_bytes));
+    lfa_plan* p = const_cast<lfa_plan*>(plan);
+    LFA_TRY(ensure_device(p));
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    if (persistent) {
+        if (p->dtype == LFA_F64) return persistent_impl<double>(p, W, sigma, U, V, info, ws, st);
+        return persistent_impl<float>(p, W, sigma, U, V, info, ws, st);
+    }
+    if (p->dtype == LFA_F64) return svd_impl<double>(p, W, A, sigma, U, V, info, ws, ws_bytes, st);
+    return svd_impl<float>(p, W, A, sigma, U, V, info, ws, ws_bytes, st);
+}
+
+int lfa_svd(const lfa_plan* plan, const void* const* W, void* const* sigma, void* const* U,
+            void* const* V, int32_t* info, void* ws, size_t ws_bytes, void* stream) {
+    if (!W) return LFA_ERR_INVALID_ARG;
+    return svd_common(plan, W, nullptr, sigma, U, V, info, ws, ws_bytes, stream, false);
+}
+
+int lfa_svd_persistent(const lfa_plan* plan, const void* const* W, void* const* sigma,
+                       void* const* U, void* const* V, int32_t* info, void* ws, size_t ws_bytes,
+                       void* stream) {
+    if (!W) return LFA_ERR_INVALID_ARG;
+    return svd_common(plan, W, nullptr, sigma, U, V, info, ws, ws_bytes, stream, true);
+}
+
+int lfa_svd_symbols(const lfa_plan* plan, const void* const* A, void* const* sigma,
+                    void* const* U, void* const* V, int32_t* info, void* ws, size_t ws_bytes,
+                    void* stream) {
+    if (!A) return LFA_ERR_INVALID_ARG;
+    return svd_common(plan, nullptr, A, sigma, U, V, info, ws, ws_bytes, stream, false);
+}
+
+int lfa_topk(const lfa_plan* plan, const void* const* sigma, int32_t k, void* vals, int32_t* idx,
+             void* stream) {
+    if (!plan || !vals || !idx) return LFA_ERR_INVALID_ARG;
+    LFA_TRY(check_ptrs(plan, sigma, true));
+    LFA_TRY(check_k(plan, k));
+    lfa_plan* p = const_cast<lfa_plan*>(plan);
+    LFA_TRY(ensure_device(p));
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    if (p->dtype == LFA_F64) return topk_impl<double>(p, sigma, k, vals, idx, st);
+    return topk_impl<float>(p, sigma, k, vals, idx, st);
+}
+
+int lfa_adjoint(const lfa_plan* plan, const void* const* U, const void* const* V,
+                const int32_t* idx, const void* grad, int32_t k, void* const* dW, void* stream) {
+    if (!plan || !idx || !grad) return LFA_ERR_INVALID_ARG;
+    LFA_TRY(check_ptrs(plan, U, true));
+    LFA_TRY(check_ptrs(plan, V, true));
+    LFA_TRY(check_ptrs(plan, dW, true));
+    LFA_TRY(check_k(plan, k));
+    lfa_plan* p = const_cast<lfa_plan*>(plan);
+    LFA_TRY(ensure_device(p));
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const int nl = (int)p->layers.size();
+    for (int l0 = 0; l0 < nl; l0 += kMaxLaunchLayers) {
+        const int l1 = std::min(nl, l0 + kMaxLaunchLayers);
+        if (p->dtype == LFA_F64) LFA_TRY(adjoint_launch<double>(p, l0, l1, U, V, idx, grad, k, dW, 0, st));
+        else LFA_TRY(adjoint_launch<float>(p, l0, l1, U, V, idx, grad, k, dW, 0, st));
+    }
+    return LFA_OK;
+}
+
+int lfa_sigma_grad(const lfa_plan* plan, const void* const* W, const int32_t* idx, const void* grad,
+                   int32_t k, void* const* dW, void* ws, size_t ws_bytes, void* stream) {
+    if (!plan || !idx || !grad) return LFA_ERR_INVALID_ARG;
+    LFA_TRY(check_ptrs(plan, W, true));
+    LFA_TRY(check_ptrs(plan, dW, true));
+    LFA_TRY(check_k(plan, k));
+    LFA_TRY(check_ws(plan, ws, ws_bytes));
+    lfa_plan* p = const_cast<lfa_plan*>(plan);
+    LFA_TRY(ensure_device(p));
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    if (p->dtype == LFA_F64) return sigma_grad_impl<double>(p, W, idx, grad, k, dW, ws, st);
+    return sigma_grad_impl<float>(p, W, idx, grad, k, dW, ws, st);
+}
+
+int lfa_graph_create(lfa_plan* plan, const void* const* W, void* const* sigma, int32_t k,
+                     void* vals, int32_t* idx, const void* grad, void* const* dW, int32_t* info,
+                     void* ws, size_t ws_bytes, void* stream, lfa_graph** out) {
+    if (!out) return LFA_ERR_INVALID_ARG;
+    *out = nullptr;
+    if (!plan || !vals || !idx || !grad) return LFA_ERR_INVALID_ARG;
+    if (plan->flags & (LFA_WANT_U | LFA_WANT_V)) return LFA_ERR_UNSUPPORTED;
+    LFA_TRY(check_ptrs(plan, W, true));
+    LFA_TRY(check_ptrs(plan, sigma, true));
+    LFA_TRY(check_ptrs(plan, dW, true));
+    LFA_TRY(check_k(plan, k));
+    LFA_TRY(check_ws(plan, ws, ws_bytes));
+    LFA_TRY(ensure_device(plan));
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    if (st == nullptr) return LFA_ERR_INVALID_ARG;   // cannot capture the legacy default stream
+    lfa_graph* g = new (std::nothrow) lfa_graph();
+    if (!g) return LFA_ERR_INVALID_ARG;
+    hipError_t e = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) {
+        delete g;
+        return hip_fail(e);
+    }
+    int s = lfa_svd_persistent(plan, W, sigma, nullptr, nullptr, info, ws, ws_bytes, stream);
+    if (s == LFA_OK) s = lfa_topk(plan, sigma, k, vals, idx, stream);
+    if (s == LFA_OK) s = lfa_sigma_grad(plan, W, idx, grad, k, dW, ws, ws_bytes, stream);
+    e = hipStreamEndCapture(st, &g->graph);
+    if (s != LFA_OK || e != hipSuccess) {
+        if (g->graph) (void)hipGraphDestroy(g->graph);
+        delete g;
+        return s != LFA_OK ? s : hip_fail(e);
+    }
+    e = hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        (void)hipGraphDestroy(g->graph);
+        delete g;
+        return hip_fail(e);
+    }
+    *out = g;
+    return LFA_OK;
+}
+
+int lfa_graph_launch(lfa_graph* graph, void* stream) {
+    if (!graph) return LFA_ERR_INVALID_ARG;
+    HIP_TRY(hipGraphLaunch(graph->exec, static_cast<hipStream_t>(stream)));
+    return LFA_OK;
+}
+
+int lfa_graph_destroy(lfa_graph* graph) {
+    if (!graph) return LFA_OK;
+    if (graph->exec) (void)hipGraphExecDestroy(graph->exec);
+    if (graph->graph) (void)hipGraphDestroy(graph->graph);
+    delete graph;
+    return LFA_OK;
+}
+
+int lfa_autotune(lfa_plan* plan, const void* const* W, void* const* sigma, void* const* U,
+                 void* const* V, void* ws, size_t ws_bytes, void* stream) {
+    if (!plan) return LFA_ERR_INVALID_ARG;
+    LFA_TRY(check_ptrs(plan, W, true));
+    LFA_TRY(check_ptrs(plan, sigma, true));
+    LFA_TRY(check_ptrs(plan, U, (plan->flags & LFA_WANT_U) != 0));
+    LFA_TRY(check_ptrs(plan, V, (plan->flags & LFA_WANT_V) != 0));
+    LFA_TRY(check_ws(plan, ws, ws_bytes));
+    LFA_TRY(ensure_device(plan));
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const bool wu = plan->flags & LFA_WANT_U, wv = plan->flags & LFA_WANT_V;
+    const int eb = elem_bytes(plan->dtype);
+    hipEvent_t e0, e1;
+    HIP_TRY(hipEventCreate(&e0));
+    HIP_TRY(hipEventCreate(&e1));
+    int status = LFA_OK;
+    for (size_t i = 0; i < plan->layers.size() && status == LFA_OK; ++i) {
+        const LayerDesc base = plan->desc[i];
+        const bool acc = accumulates(base, wu, wv);
+        std::vector<LayerDesc> cands;
+        for (int L = 1; L <= 64; L <<= 1) {
+            if (L * kRowsPerLane < base.M) continue;
+            if (L > 4 * base.L) continue;
+            for (int th = 64; th <= 1024; th <<= 1) {
+                if (th < L) continue;
+                if (th > 2 * pow2ceil(((base.N + 1) / 2) * L) && th > 64) continue;
+                cands.push_back(make_desc(plan->layers[i], base.tw_n, base.tw_m, acc, eb,
+                                          base.storage == kGlobal ? 0 : kLdsCap, th, L));
+            }
+        }
+        float best = 1e30f;
+        LayerDesc best_d = base;
+        char* region = static_cast<char*>(ws) + kAlign;
+        for (const LayerDesc& d : cands) {
+            float ms = 0;
+            for (int rep = 0; rep < 2 && status == LFA_OK; ++rep) {
+                if (hipEventRecord(e0, st) != hipSuccess) { status = LFA_ERR_HIP; break; }
+                if (plan->dtype == LFA_F64)
+                    status = run_svd_layer<double>(plan, d, W[i], nullptr, sigma[i],
+                                                   wu ? U[i] : nullptr, wv ? V[i] : nullptr,
+                                                   nullptr, region, nullptr, 0, 0, st);
+                else
+                    status = run_svd_layer<float>(plan, d, W[i], nullptr, sigma[i],
+                                                  wu ? U[i] : nullptr, wv ? V[i] : nullptr,
+                                                  nullptr, region, nullptr, 0, 0, st);
+                if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
+                    status = LFA_ERR_HIP;
+                    break;
+                }
+                (void)hipEventElapsedTime(&ms, e0, e1);
+            }
+            if (status != LFA_OK) break;
+            if (ms < best) {
+                best = ms;
+                best_d = d;
+            }
+        }
+        plan->desc[i] = best_d;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return status;
+}
+
+}  // extern "C"

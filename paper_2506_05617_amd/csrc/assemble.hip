@@ -1,0 +1,235 @@
+// Symbol assembly on gfx950:
+//     A[theta][o][i] = sum_t W[o][i][t] * exp(+2 pi i <k_theta, y_t>)
+// (Sec. III "Convolution Theorem"; Algorithm 1 symbol step).
+//
+// Read as a matrix product, with Phi[theta][t] the complex phase matrix and
+// W reshaped to [t][e] (e = o*c_in + i):  A = Phi * W, i.e. two real GEMMs of
+// shape [n*m x T] x [T x c_out*c_in] sharing the right operand.
+//
+//  * symbols_valu: one thread per output element e, a tile of frequencies per
+//    block; phases of the tile staged in LDS.  FP32 or FP64.
+//  * symbols_mfma: 16x16 output tiles on the matrix cores, K = taps.  Modes:
+//      0  FP32 MFMA (v_mfma_f32_16x16x4f32), K padded to 4;
+//      2  split-BF16, 3 products  Phi1*W1 + Phi1*W2 + Phi2*W1, FP32 accumulate;
+//      3  split-BF16, 6 products of a three-term split, FP32 accumulate;
+//    the split terms are laid end to end along K so one accumulator chain
+//    sums all products (v_mfma_f32_16x16x16bf16_1k).
+// The phase of (theta, t) is the product of two double-precision twiddles
+// exp(2 pi i j/n) at the integer-reduced indices (p*y1 mod n, q*y2 mod m),
+// rounded once to the working precision.
+
+#include <hip/hip_runtime.h>
+
+#include "lfa_internal.hpp"
+
+namespace lfa {
+namespace {
+
+__device__ __forceinline__ void phase_d(const double* tw, const LayerDesc& d, int theta, int t,
+                                        double& re, double& im) {
+    const int p = theta / d.m, q = theta - (theta / d.m) * d.m;
+    const int a = t / d.kw, b = t - (t / d.kw) * d.kw;
+    const int y1 = a - (d.kh - 1) / 2, y2 = b - (d.kw - 1) / 2;
+    int i1 = (p * y1) % d.n;
+    if (i1 < 0) i1 += d.n;
+    int i2 = (q * y2) % d.m;
+    if (i2 < 0) i2 += d.m;
+    const double ar = tw[2 * (d.tw_n + i1)], ai = tw[2 * (d.tw_n + i1) + 1];
+    const double br = tw[2 * (d.tw_m + i2)], bi = tw[2 * (d.tw_m + i2) + 1];
+    re = ar * br - ai * bi;
+    im = ar * bi + ai * br;
+}
+
+constexpr int kValuThetaTile = 16;
+
+template <typename R>
+__global__ void __launch_bounds__(256) symbols_valu(LayerDesc d, const R* __restrict__ W,
+                                                   cplx<R>* __restrict__ A,
+                                                   const double* __restrict__ tw) {
+    __shared__ cplx<R> ph[kValuThetaTile * kMaxTaps];
+    const int T = d.kh * d.kw;
+    const int E = d.c_out * d.c_in;
+    const int HW = d.num_symbols;
+    const int theta0 = blockIdx.y * kValuThetaTile;
+    const int nth = min(kValuThetaTile, HW - theta0);
+    for (int x = threadIdx.x; x < nth * T; x += blockDim.x) {
+        const int th = x / T, t = x - (x / T) * T;
+        double re, im;
+        phase_d(tw, d, theta0 + th, t, re, im);
+        ph[th * kMaxTaps + t] = {R(re), R(im)};
+    }
+    __syncthreads();
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= E) return;
+    const R* w = W + (size_t)e * T;
+    R re[kValuThetaTile], im[kValuThetaTile];
+#pragma unroll
+    for (int th = 0; th < kValuThetaTile; ++th) re[th] = im[th] = R(0);
+    for (int t = 0; t < T; ++t) {
+        const R wt = w[t];
+#pragma unroll
+        for (int th = 0; th < kValuThetaTile; ++th) {
+            const cplx<R> p = ph[th * kMaxTaps + t];
+            re[th] = fma(wt, p.x, re[th]);
+            im[th] = fma(wt, p.y, im[th]);
+        }
+    }
+#pragma unroll
+    for (int th = 0; th < kValuThetaTile; ++th)
+        if (th < nth) A[(size_t)(theta0 + th) * E + e] = {re[th], im[th]};
+}
+
+// ---------------------------------------------------------------- MFMA ----
+
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+typedef short bf16x4 __attribute__((ext_vector_type(4)));
+
+// Round-to-nearest-even float -> bfloat16 bits (finite inputs).
+__device__ __forceinline__ unsigned short f2bf(float x) {
+    unsigned u = __float_as_uint(x);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return (unsigned short)(u >> 16);
+}
+__device__ __forceinline__ float bf2f(unsigned short h) { return __uint_as_float((unsigned)h << 16); }
+
+// Split x into `terms` bfloat16 values whose sum approximates x.
+__device__ __forceinline__ void split_bf16(float x, int terms, unsigned short* out) {
+    float rest = x;
+    for (int s = 0; s < terms; ++s) {
+        const unsigned short h = f2bf(rest);
+        out[s] = h;
+        rest -= bf2f(h);
+    }
+}
+
+// Segment tables: product s multiplies split term ta[s] of Phi with term tb[s] of W.
+__constant__ int kSegA[2][6] = {{0, 0, 1, 0, 0, 0}, {0, 0, 1, 0, 1, 2}};
+__constant__ int kSegB[2][6] = {{0, 1, 0, 0, 0, 0}, {0, 1, 0, 2, 1, 0}};
+
+constexpr int kMfmaETile = 64;   // e columns per block (4 sub-tiles of 16)
+
+// Block: 4 waves; wave w owns frequencies theta0 + 16w .. +16 and all 64
+// e-columns of the block (4 output tiles of 16x16, re and im).
+__global__ void __launch_bounds__(256) symbols_mfma(LayerDesc d, const float* __restrict__ W,
+                                                    cplx<float>* __restrict__ A,
+                                                    const double* __restrict__ tw, int mode) {
+    const int T = d.kh * d.kw;
+    const int E = d.c_out * d.c_in;
+    const int HW = d.num_symbols;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int theta0 = blockIdx.y * 64 + wave * 16;
+    const int e0 = blockIdx.x * kMfmaETile;
+    const int li = lane & 15, lk = lane >> 4;
+
+    floatx4 acc_re[4], acc_im[4];
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+        acc_re[s] = floatx4{0.f, 0.f, 0.f, 0.f};
+        acc_im[s] = floatx4{0.f, 0.f, 0.f, 0.f};
+    }
+    const int theta_a = theta0 + li;   // row of the A operand this lane feeds
+    if (mode == 0) {
+        // FP32: K-step 4; lane feeds A[i = li][k = lk], B[k = lk][j = li].
+        for (int k0 = 0; k0 < T; k0 += 4) {
+            const int t = k0 + lk;
+            float pr = 0.f, pi = 0.f;
+            if (t < T && theta_a < HW) {
+                double re, im;
+                phase_d(tw, d, theta_a, t, re, im);
+                pr = float(re);
+                pi = float(im);
+            }
+#pragma unroll
+            for (int s = 0; s < 4; ++s) {
+                const int e = e0 + s * 16 + li;
+                const float b = (t < T && e < E) ? W[(size_t)e * T + t] : 0.f;
+                acc_re[s] = __builtin_amdgcn_mfma_f32_16x16x4f32(pr, b, acc_re[s], 0, 0, 0);
+                acc_im[s] = __builtin_amdgcn_mfma_f32_16x16x4f32(pi, b, acc_im[s], 0, 0, 0);
+            }
+        }
+    } else {
+        // split-BF16: K' = nseg*T, K-step 16; lane feeds k = 4*lk + v.
+        const int ms = (mode == 3) ? 1 : 0;
+        const int nseg = (mode == 3) ? 6 : 3;
+        const int terms = (mode == 3) ? 3 : 2;
+        const int Kp = nseg * T;
+        for (int k0 = 0; k0 < Kp; k0 += 16) {
+            bf16x4 ar, ai;
+            bf16x4 bv[4];
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int kk = k0 + 4 * lk + v;
+                unsigned short hr = 0, hi = 0;
+                unsigned short wb[4] = {0, 0, 0, 0};
+                if (kk < Kp) {
+                    const int seg = kk / T, t = kk - (kk / T) * T;
+                    if (theta_a < HW) {
+                        double re, im;
+                        phase_d(tw, d, theta_a, t, re, im);
+                        unsigned short sr[3], si[3];
+                        split_bf16(float(re), terms, sr);
+                        split_bf16(float(im), terms, si);
+                        hr = sr[kSegA[ms][seg]];
+                        hi = si[kSegA[ms][seg]];
+                    }
+#pragma unroll
+                    for (int s = 0; s < 4; ++s) {
+                        const int e = e0 + s * 16 + li;
+                        if (e < E) {
+                            unsigned short sw[3];
+                            split_bf16(W[(size_t)e * T + t], terms, sw);
+                            wb[s] = sw[kSegB[ms][seg]];
+                        }
+                    }
+                }
+                ar[v] = (short)hr;
+                ai[v] = (short)hi;
+#pragma unroll
+                for (int s = 0; s < 4; ++s) bv[s][v] = (short)wb[s];
+            }
+#pragma unroll
+            for (int s = 0; s < 4; ++s) {
+                acc_re[s] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ar, bv[s], acc_re[s], 0, 0, 0);
+                acc_im[s] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ai, bv[s], acc_im[s], 0, 0, 0);
+            }
+        }
+    }
+    // D[i][j]: j = lane & 15, i = 4*(lane >> 4) + v
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+        const int e = e0 + s * 16 + li;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int th = theta0 + 4 * lk + v;
+            if (th < HW && e < E) A[(size_t)th * E + e] = {acc_re[s][v], acc_im[s][v]};
+        }
+    }
+}
+
+}  // namespace
+
+hipError_t launch_symbols_valu_f32(const LayerDesc& d, const float* W, cplx<float>* A,
+                                   const double* tw, hipStream_t s) {
+    const int E = d.c_out * d.c_in;
+    const dim3 grid((E + 255) / 256, (d.num_symbols + kValuThetaTile - 1) / kValuThetaTile);
+    hipLaunchKernelGGL(symbols_valu<float>, grid, dim3(256), 0, s, d, W, A, tw);
+    return hipGetLastError();
+}
+
+hipError_t launch_symbols_valu_f64(const LayerDesc& d, const double* W, cplx<double>* A,
+                                   const double* tw, hipStream_t s) {
+    const int E = d.c_out * d.c_in;
+    const dim3 grid((E + 255) / 256, (d.num_symbols + kValuThetaTile - 1) / kValuThetaTile);
+    hipLaunchKernelGGL(symbols_valu<double>, grid, dim3(256), 0, s, d, W, A, tw);
+    return hipGetLastError();
+}
+
+hipError_t launch_symbols_mfma(const LayerDesc& d, const float* W, cplx<float>* A,
+                               const double* tw, int mode, hipStream_t s) {
+    const int E = d.c_out * d.c_in;
+    const dim3 grid((E + kMfmaETile - 1) / kMfmaETile, (d.num_symbols + 63) / 64);
+    hipLaunchKernelGGL(symbols_mfma, grid, dim3(256), 0, s, d, W, A, tw, mode);
+    return hipGetLastError();
+}
+
+}  // namespace lfa

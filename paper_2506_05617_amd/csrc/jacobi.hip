@@ -1,0 +1,580 @@
+// Batched one-sided Jacobi SVD of convolution symbols on gfx950.
+//
+// One work-group owns one symbol at a time.  It assembles the c_out x c_in
+// symbol A_k = sum_y M_y exp(+2 pi i <k,y>) (Sec. III "Convolution Theorem",
+// Algorithm 1 symbol step) straight into its working matrix G (LDS, or a
+// global slot for symbols larger than LDS), runs complex one-sided (Hestenes)
+// Jacobi sweeps on the columns of G with a parallel round-robin pair order,
+// and writes sigma (sorted), U and V (Algorithm 1 SVD step).
+//
+// G is M x N, column-major with leading dimension ldg, M = max(c_out, c_in),
+// N = min(c_out, c_in).  For c_out >= c_in, G = A and the accumulated
+// rotations form V; for c_out < c_in, G = A^H and the roles of U and V swap.
+//
+// A column pair (j, k) is handled by a group of L lanes of one wavefront;
+// lane l owns rows l, l+L, ... of both columns in registers.  The three inner
+// products alpha = |g_j|^2, beta = |g_k|^2, gamma = g_j^H g_k are reduced with
+// xor shuffles inside the lane group, the rotation is computed in double
+// precision by every lane of the group (no broadcast), and applied to the
+// registers, then written back.  The N/2 pairs of one round-robin step are
+// disjoint, so groups never touch the same column within a step; a
+// work-group barrier separates steps.
+
+#include <hip/hip_runtime.h>
+#include <math.h>
+
+#include "lfa_internal.hpp"
+
+namespace lfa {
+namespace {
+
+template <typename R>
+__device__ __forceinline__ cplx<R> cmul(cplx<R> a, cplx<R> b) {
+    return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
+}
+
+template <typename R>
+__device__ __forceinline__ R shfl_xor(R v, int mask) {
+    return __shfl_xor(v, mask, 64);
+}
+
+// Sum over the L lanes of a lane group (L a power of two <= 64).
+template <typename R, int L>
+__device__ __forceinline__ R group_sum(R v) {
+#pragma unroll
+    for (int off = L / 2; off >= 1; off >>= 1) v += shfl_xor(v, off);
+    return v;
+}
+
+// Round-robin ("circle") ordering on Np (even) positions: position 0 is
+// fixed, positions 1..Np-1 rotate by one each step.  Over Np-1 steps every
+// unordered pair meets exactly once.
+__device__ __forceinline__ void rr_pair(int pr, int step, int Np, int& j, int& k) {
+    const int c = Np - 1;
+    auto pos = [&](int i) { return i == 0 ? 0 : ((i - 1 + step) % c) + 1; };
+    j = pos(pr);
+    k = pos(Np - 1 - pr);
+}
+
+// exp(2 pi i ((p*y1 mod n)/n + (q*y2 mod m)/m)) from the double twiddle tables.
+__device__ __forceinline__ void phase(const double* tw, const LayerDesc& d, int p, int q, int t,
+                                      double& re, double& im) {
+    const int a = t / d.kw, b = t - (t / d.kw) * d.kw;
+    const int y1 = a - (d.kh - 1) / 2, y2 = b - (d.kw - 1) / 2;
+    int i1 = (p * y1) % d.n;
+    if (i1 < 0) i1 += d.n;
+    int i2 = (q * y2) % d.m;
+    if (i2 < 0) i2 += d.m;
+    const double ar = tw[2 * (d.tw_n + i1)], ai = tw[2 * (d.tw_n + i1) + 1];
+    const double br = tw[2 * (d.tw_m + i2)], bi = tw[2 * (d.tw_m + i2) + 1];
+    re = ar * br - ai * bi;
+    im = ar * bi + ai * br;
+}
+
+template <typename R>
+struct Shared {
+    cplx<R>* ph;     // [kMaxTaps] phases of the current frequency
+    R* sig;          // [N] column norms
+    int* perm;       // [N] sorted position -> column
+    int* inv;        // [N] column -> sorted position
+    cplx<R>* coef;   // [N] Gram-Schmidt coefficients (completion of zero columns)
+    cplx<R>* xtmp;   // [M] Gram-Schmidt work vector
+    int* flags;      // [4] rotation flags (3 rotating) + scratch
+    R* red;          // [64] scratch for block reductions
+    cplx<R>* G;      // working matrix (LDS or global)
+    cplx<R>* Q;      // rotation accumulator (LDS or global), or null
+};
+
+template <typename R>
+__device__ __forceinline__ Shared<R> carve(char* lds, const LayerDesc& d, bool acc, char* gslot) {
+    Shared<R> s;
+    char* p = lds;
+    s.ph = reinterpret_cast<cplx<R>*>(p);
+    p += sizeof(cplx<R>) * kMaxTaps;
+    s.red = reinterpret_cast<R*>(p);
+    p += sizeof(R) * 64;
+    s.sig = reinterpret_cast<R*>(p);
+    p += sizeof(R) * ((d.N + 3) & ~3);
+    s.perm = reinterpret_cast<int*>(p);
+    p += sizeof(int) * ((d.N + 3) & ~3);
+    s.inv = reinterpret_cast<int*>(p);
+    p += sizeof(int) * ((d.N + 3) & ~3);
+    p = reinterpret_cast<char*>((reinterpret_cast<uintptr_t>(p) + 15) & ~uintptr_t(15));
+    s.coef = reinterpret_cast<cplx<R>*>(p);
+    p += sizeof(cplx<R>) * d.N;
+    s.xtmp = reinterpret_cast<cplx<R>*>(p);
+    p += sizeof(cplx<R>) * d.M;
+    s.flags = reinterpret_cast<int*>(p);
+    p += sizeof(int) * 4;
+    p = reinterpret_cast<char*>((reinterpret_cast<uintptr_t>(p) + 15) & ~uintptr_t(15));
+    char* base = (d.storage == kLds) ? p : gslot;
+    s.G = reinterpret_cast<cplx<R>*>(base);
+    base += sizeof(cplx<R>) * (size_t)d.ldg * d.N;
+    s.Q = acc ? reinterpret_cast<cplx<R>*>(base) : nullptr;
+    return s;
+}
+
+template <typename R>
+__device__ __forceinline__ R sort_key(R v) {
+    return v == v ? v : R(-1);
+}
+
+// Block-wide sum (all threads receive it).
+template <typename R>
+__device__ R block_sum(R v, R* red) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
+    v = group_sum<R, 64>(v);
+    __syncthreads();
+    if (lane == 0) red[wave] = v;
+    __syncthreads();
+    R t = 0;
+    for (int w = 0; w < nw; ++w) t += red[w];
+    return t;
+}
+
+// ---------------------------------------------------------------------------
+// Load the symbol of frequency theta into G (and Q = I).
+// ---------------------------------------------------------------------------
+template <typename R>
+__device__ void load_symbol(const SvdArgs<R>& a, const Shared<R>& s, int theta) {
+    const LayerDesc& d = a.d;
+    const int tid = threadIdx.x, nt = blockDim.x;
+    const int T = d.kh * d.kw;
+    const int p = theta / d.m, q = theta - (theta / d.m) * d.m;
+    const int E = d.c_out * d.c_in;
+    if (a.A == nullptr) {
+        for (int t = tid; t < T; t += nt) {
+            double re, im;
+            phase(a.tw, d, p, q, t, re, im);
+            s.ph[t] = {R(re), R(im)};
+        }
+        __syncthreads();
+        for (int e = tid; e < E; e += nt) {
+            const R* w = a.W + (size_t)e * T;
+            R re = 0, im = 0;
+            for (int t = 0; t < T; ++t) {
+                const R wt = w[t];
+                const cplx<R> ph = s.ph[t];
+                re = fma(wt, ph.x, re);
+                im = fma(wt, ph.y, im);
+            }
+            const int o = e / d.c_in, i = e - (e / d.c_in) * d.c_in;
+            if (!d.transposed) s.G[(size_t)i * d.ldg + o] = {re, im};
+            else               s.G[(size_t)o * d.ldg + i] = {re, -im};
+        }
+    } else {
+        const cplx<R>* A = a.A + (size_t)theta * E;
+        for (int e = tid; e < E; e += nt) {
+            const cplx<R> v = A[e];
+            const int o = e / d.c_in, i = e - (e / d.c_in) * d.c_in;
+            if (!d.transposed) s.G[(size_t)i * d.ldg + o] = v;
+            else               s.G[(size_t)o * d.ldg + i] = {v.x, -v.y};
+        }
+    }
+    if (s.Q) {
+        const int N = d.N;
+        for (int e = tid; e < N * N; e += nt) {
+            const int j = e / N, i = e - (e / N) * N;
+            s.Q[(size_t)j * d.ldv + i] = {R(i == j ? 1 : 0), R(0)};
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// One-sided Jacobi sweeps.  Returns the number of sweeps used; `converged`
+// tells whether the last sweep made no rotation.
+// ---------------------------------------------------------------------------
+template <typename R, int L>
+__device__ int jacobi(const LayerDesc& d, const Shared<R>& s, int max_sweeps, double tol,
+                      bool& converged) {
+    constexpr int RM = kRowsPerLane;
+    const int tid = threadIdx.x;
+    const int lane = tid & (L - 1), group = tid / L, ngroups = blockDim.x / L;
+    const int M = d.M, N = d.N, ldg = d.ldg, ldv = d.ldv;
+    const int Np = N + (N & 1);
+    const int npairs = Np / 2, nsteps = Np - 1;
+    cplx<R>* __restrict__ G = s.G;
+    cplx<R>* __restrict__ Q = s.Q;
+
+    if (tid == 0) s.flags[0] = s.flags[1] = s.flags[2] = 0;
+    __syncthreads();
+    converged = (N < 2);
+    int sweep = 0;
+    while (!converged && sweep < max_sweeps) {
+        if (tid == 0) s.flags[(sweep + 1) % 3] = 0;
+        for (int step = 0; step < nsteps; ++step) {
+            for (int pb = 0; pb < npairs; pb += ngroups) {
+                const int pr = pb + group;
+                if (pr >= npairs) continue;
+                int j, k;
+                rr_pair(pr, step, Np, j, k);
+                if (j >= N || k >= N) continue;
+                cplx<R> x[RM], y[RM];
+                R al = 0, be = 0, gr = 0, gi = 0;
+#pragma unroll
+                for (int t = 0; t < RM; ++t) {
+                    const int i = lane + t * L;
+                    if (i < M) {
+                        x[t] = G[(size_t)j * ldg + i];
+                        y[t] = G[(size_t)k * ldg + i];
+                        al = fma(x[t].x, x[t].x, fma(x[t].y, x[t].y, al));
+                        be = fma(y[t].x, y[t].x, fma(y[t].y, y[t].y, be));
+                        gr = fma(x[t].x, y[t].x, fma(x[t].y, y[t].y, gr));
+                        gi = fma(x[t].x, y[t].y, fma(-x[t].y, y[t].x, gi));
+                    }
+                }
+                al = group_sum<R, L>(al);
+                be = group_sum<R, L>(be);
+                gr = group_sum<R, L>(gr);
+                gi = group_sum<R, L>(gi);
+                const double g = sqrt(double(gr) * double(gr) + double(gi) * double(gi));
+                if (!(g > tol * sqrt(double(al) * double(be)))) continue;
+                // Real 2x2 symmetric Schur step on [[al, g], [g, be]] after the
+                // phase of gamma is moved into column k.
+                const double zeta = (double(be) - double(al)) / (2.0 * g);
+                const double tt = copysign(1.0, zeta) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+                const double cs = 1.0 / sqrt(1.0 + tt * tt);
+                const double sn = cs * tt;
+                // x' = c x - s e^{-i phi} y ;  y' = c y + s e^{+i phi} x
+                const R c = R(cs);
+                const R sr = R(sn * double(gr) / g), si = R(-sn * double(gi) / g);
+#pragma unroll
+                for (int t = 0; t < RM; ++t) {
+                    const int i = lane + t * L;
+                    if (i < M) {
+                        const cplx<R> xv = x[t], yv = y[t];
+                        cplx<R> xn, yn;
+                        xn.x = fma(c, xv.x, -fma(sr, yv.x, -si * yv.y));
+                        xn.y = fma(c, xv.y, -fma(sr, yv.y, si * yv.x));
+                        yn.x = fma(c, yv.x, fma(sr, xv.x, si * xv.y));
+                        yn.y = fma(c, yv.y, fma(sr, xv.y, -si * xv.x));
+                        G[(size_t)j * ldg + i] = xn;
+                        G[(size_t)k * ldg + i] = yn;
+                    }
+                }
+                if (Q) {
+#pragma unroll
+                    for (int t = 0; t < RM; ++t) {
+                        const int i = lane + t * L;
+                        if (i < N) {
+                            const cplx<R> xv = Q[(size_t)j * ldv + i], yv = Q[(size_t)k * ldv + i];
+                            cplx<R> xn, yn;
+                            xn.x = fma(c, xv.x, -fma(sr, yv.x, -si * yv.y));
+                            xn.y = fma(c, xv.y, -fma(sr, yv.y, si * yv.x));
+                            yn.x = fma(c, yv.x, fma(sr, xv.x, si * xv.y));
+                            yn.y = fma(c, yv.y, fma(sr, xv.y, -si * xv.x));
+                            Q[(size_t)j * ldv + i] = xn;
+                            Q[(size_t)k * ldv + i] = yn;
+                        }
+                    }
+                }
+                if (lane == 0) s.flags[sweep % 3] = 1;
+            }
+            __syncthreads();
+        }
+        converged = (s.flags[sweep % 3] == 0);
+        ++sweep;
+    }
+    __syncthreads();
+    return sweep;
+}
+
+// ---------------------------------------------------------------------------
+// Norms, sort, normalisation, completion of zero columns, outputs.
+// ---------------------------------------------------------------------------
+template <typename R, int L>
+__device__ void finish(const SvdArgs<R>& a, const Shared<R>& s, int out_idx, int sweeps,
+                       bool converged) {
+    const LayerDesc& d = a.d;
+    const int tid = threadIdx.x, nt = blockDim.x;
+    const int lane = tid & (L - 1), group = tid / L, ngroups = nt / L;
+    const int M = d.M, N = d.N, ldg = d.ldg, ldv = d.ldv;
+    cplx<R>* G = s.G;
+    cplx<R>* Q = s.Q;
+
+    // column norms
+    for (int j = group; j < N; j += ngroups) {
+        R acc = 0;
+        for (int i = lane; i < M; i += L) {
+            const cplx<R> v = G[(size_t)j * ldg + i];
+            acc = fma(v.x, v.x, fma(v.y, v.y, acc));
+        }
+        acc = group_sum<R, L>(acc);
+        if (lane == 0) s.sig[j] = sqrt(acc);
+    }
+    __syncthreads();
+    // rank sort: descending, ties by column index; NaN sorts as -1 so the
+    // ranks always form a permutation
+    for (int j = tid; j < N; j += nt) {
+        const R sj = sort_key(s.sig[j]);
+        int rank = 0;
+        for (int k = 0; k < N; ++k) {
+            const R sk = sort_key(s.sig[k]);
+            rank += (sk > sj) || (sk == sj && k < j);
+        }
+        s.perm[rank] = j;
+        s.inv[j] = rank;
+    }
+    __syncthreads();
+
+    const int r = N;
+    R* sig_out = a.sigma + (size_t)out_idx * r;
+    bool bad = false;
+    for (int c = tid; c < r; c += nt) {
+        const R v = s.sig[s.perm[c]];
+        sig_out[c] = v;
+        bad |= !isfinite(v);
+    }
+    const bool want_left = d.transposed ? (a.V != nullptr) : (a.U != nullptr);
+    const bool want_right = d.transposed ? (a.U != nullptr) : (a.V != nullptr);
+
+    if (want_left) {
+        // normalise columns in place: u_j = g_j / sigma_j (zero columns stay 0)
+        for (int e = tid; e < N * M; e += nt) {
+            const int j = e / M, i = e - (e / M) * M;
+            const R sj = s.sig[j];
+            const cplx<R> v = G[(size_t)j * ldg + i];
+            const R inv = sj > R(0) ? R(1) / sj : R(0);
+            G[(size_t)j * ldg + i] = {v.x * inv, v.y * inv};
+        }
+        __syncthreads();
+        // Columns with sigma == 0 (they sort last) get an orthonormal
+        // completion: unit vectors e_0, e_1, ... orthogonalised by two passes
+        // of classical Gram-Schmidt against every accepted column, kept when
+        // the residual norm exceeds a threshold (1/2, lowered if no unit
+        // vector qualifies; some residual has norm >= 1/sqrt(M)).
+        int nz = 0;
+        while (nz < N && s.sig[s.perm[N - 1 - nz]] == R(0)) ++nz;
+        int cand = 0;
+        R thresh = R(0.5);
+        for (int zc = N - nz; zc < N; ++zc) {
+            const int jz = s.perm[zc];
+            bool done = false;
+            for (int tries = 0; !done && tries < 4 * M; ++tries) {
+                if (cand == M) {
+                    cand = 0;
+                    thresh *= R(0.2);
+                }
+                for (int i = tid; i < M; i += nt) G[(size_t)jz * ldg + i] = {R(i == cand), R(0)};
+                __syncthreads();
+                for (int pass = 0; pass < 2; ++pass) {
+                    for (int col = group; col < N; col += ngroups) {
+                        // accepted: nonzero columns and zero columns completed earlier
+                        const bool use = col != jz && (s.sig[col] > R(0) || s.inv[col] < zc);
+                        cplx<R> acc = {0, 0};
+                        if (use) {
+                            for (int i = lane; i < M; i += L) {
+                                const cplx<R> u = G[(size_t)col * ldg + i];
+                                const cplx<R> x = G[(size_t)jz * ldg + i];
+                                acc.x = fma(u.x, x.x, fma(u.y, x.y, acc.x));
+                                acc.y = fma(u.x, x.y, fma(-u.y, x.x, acc.y));
+                            }
+                        }
+                        acc.x = group_sum<R, L>(acc.x);
+                        acc.y = group_sum<R, L>(acc.y);
+                        if (lane == 0) s.coef[col] = acc;
+                    }
+                    __syncthreads();
+                    for (int i = tid; i < M; i += nt) {
+                        cplx<R> x = G[(size_t)jz * ldg + i];
+                        for (int col = 0; col < N; ++col) {
+                            const cplx<R> cf = s.coef[col];
+                            const cplx<R> u = G[(size_t)col * ldg + i];
+                            x.x -= cf.x * u.x - cf.y * u.y;
+                            x.y -= cf.x * u.y + cf.y * u.x;
+                        }
+                        s.xtmp[i] = x;
+                    }
+                    __syncthreads();
+                    for (int i = tid; i < M; i += nt) G[(size_t)jz * ldg + i] = s.xtmp[i];
+                    __syncthreads();
+                }
+                R nrm = 0;
+                for (int i = tid; i < M; i += nt) {
+                    const cplx<R> x = G[(size_t)jz * ldg + i];
+                    nrm = fma(x.x, x.x, fma(x.y, x.y, nrm));
+                }
+                nrm = sqrt(block_sum<R>(nrm, s.red));
+                if (nrm > thresh) {
+                    const R inv = R(1) / nrm;
+                    for (int i = tid; i < M; i += nt) {
+                        const cplx<R> x = G[(size_t)jz * ldg + i];
+                        G[(size_t)jz * ldg + i] = {x.x * inv, x.y * inv};
+                    }
+                    done = true;
+                }
+                ++cand;
+                __syncthreads();
+            }
+        }
+        // write: out[theta][i][c] = G[perm[c]][i]
+        cplx<R>* out = (d.transposed ? a.V : a.U) + (size_t)out_idx * M * r;
+        for (int e = tid; e < M * r; e += nt) {
+            const int i = e / r, c = e - (e / r) * r;
+            out[e] = G[(size_t)s.perm[c] * ldg + i];
+        }
+    }
+    if (want_right) {
+        cplx<R>* out = (d.transposed ? a.U : a.V) + (size_t)out_idx * N * r;
+        for (int e = tid; e < N * r; e += nt) {
+            const int i = e / r, c = e - (e / r) * r;
+            out[e] = Q[(size_t)s.perm[c] * ldv + i];
+        }
+    }
+    if (a.info) {
+        if (tid == 0) {
+            atomicAdd(&a.info[LFA_INFO_SUM_SWEEPS], sweeps);
+            atomicMax(&a.info[LFA_INFO_MAX_SWEEPS], sweeps);
+            if (!converged) atomicAdd(&a.info[LFA_INFO_NONCONVERGED], 1);
+        }
+        if (bad) atomicOr(&a.info[LFA_INFO_NONFINITE], 1);
+    }
+    __syncthreads();
+}
+
+// Symbol `theta`; outputs at position `out_idx` of sigma/U/V.
+template <typename R, int L>
+__device__ void svd_one(const SvdArgs<R>& a, char* lds, int theta, int out_idx, char* gslot) {
+    const bool acc = (a.d.transposed ? a.U : a.V) != nullptr;
+    const Shared<R> s = carve<R>(lds, a.d, acc, gslot);
+    load_symbol<R>(a, s, theta);
+    __syncthreads();
+    bool converged;
+    const int sweeps = jacobi<R, L>(a.d, s, a.max_sweeps, a.tol, converged);
+    finish<R, L>(a, s, out_idx, sweeps, converged);
+}
+
+template <typename R, int L>
+__global__ void __launch_bounds__(1024) svd_kernel(SvdArgs<R> a) {
+    extern __shared__ __align__(16) char lds[];
+    char* gslot = a.gws ? a.gws + (size_t)blockIdx.x * a.slot_bytes : nullptr;
+    const int count = a.theta_list ? a.theta_count : a.d.num_symbols;
+    for (int item = blockIdx.x; item < count; item += gridDim.x) {
+        // with a symbol list, outputs are compact: entry `item` of the list
+        int theta = item;
+        if (a.theta_list) {
+            const int32_t* e = a.theta_list + (size_t)item * a.theta_stride;
+            theta = a.theta_stride >= 2 ? e[0] * a.d.m + e[1] : e[0];
+        }
+        svd_one<R, L>(a, lds, theta, item, gslot);
+    }
+}
+
+// Dynamic LDS above 64 KiB needs an explicit per-kernel opt-in.
+template <typename K>
+hipError_t allow_lds(K kernel, size_t lds) {
+    if (lds <= 65536) return hipSuccess;
+    return hipFuncSetAttribute(reinterpret_cast<const void*>(kernel),
+                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+}
+
+template <typename R, int L>
+hipError_t launch_svd_L(const SvdArgs<R>& a, int grid, size_t lds, hipStream_t st) {
+    hipError_t e = allow_lds(svd_kernel<R, L>, lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((svd_kernel<R, L>), dim3(grid), dim3(a.d.threads), lds, st, a);
+    return hipGetLastError();
+}
+
+template <typename R>
+hipError_t launch_svd(const SvdArgs<R>& a, int grid, size_t lds, hipStream_t st) {
+    switch (a.d.L) {
+        case 1: return launch_svd_L<R, 1>(a, grid, lds, st);
+        case 2: return launch_svd_L<R, 2>(a, grid, lds, st);
+        case 4: return launch_svd_L<R, 4>(a, grid, lds, st);
+        case 8: return launch_svd_L<R, 8>(a, grid, lds, st);
+        case 16: return launch_svd_L<R, 16>(a, grid, lds, st);
+        case 32: return launch_svd_L<R, 32>(a, grid, lds, st);
+        case 64: return launch_svd_L<R, 64>(a, grid, lds, st);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Persistent launch: work-groups dequeue (layer, theta) items.
+// ---------------------------------------------------------------------------
+template <typename R>
+__global__ void __launch_bounds__(256) persistent_kernel(PersistentArgs<R> pa_arg) {
+    extern __shared__ __align__(16) char lds[];
+    __shared__ int item_sh;
+    // Index the per-layer table where it lives (the kernel-argument segment)
+    // instead of letting a dynamic index copy the whole argument to scratch.
+#if defined(__HIP_DEVICE_COMPILE__)
+    const PersistentArgs<R>& pa = *(const PersistentArgs<R>*)__builtin_amdgcn_kernarg_segment_ptr();
+    (void)pa_arg;
+#else
+    const PersistentArgs<R>& pa = pa_arg;
+#endif
+    for (;;) {
+        if (threadIdx.x == 0) item_sh = atomicAdd(pa.counter, 1);
+        __syncthreads();
+        const int item = item_sh;
+        __syncthreads();
+        if (item >= pa.num_items) break;
+        const WorkItem w = pa.items[item];
+        const SvdArgs<R>& a = pa.layer[w.layer];
+        char* gslot = a.gws ? a.gws + (size_t)blockIdx.x * a.slot_bytes : nullptr;
+        switch (a.d.L) {
+            case 1: svd_one<R, 1>(a, lds, w.theta, w.theta, gslot); break;
+            case 2: svd_one<R, 2>(a, lds, w.theta, w.theta, gslot); break;
+            case 4: svd_one<R, 4>(a, lds, w.theta, w.theta, gslot); break;
+            case 8: svd_one<R, 8>(a, lds, w.theta, w.theta, gslot); break;
+            case 16: svd_one<R, 16>(a, lds, w.theta, w.theta, gslot); break;
+            case 32: svd_one<R, 32>(a, lds, w.theta, w.theta, gslot); break;
+            default: svd_one<R, 64>(a, lds, w.theta, w.theta, gslot); break;
+        }
+    }
+}
+
+__global__ void fill_i32_kernel(int32_t* p, int32_t v, long long n) {
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+         i += (long long)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+}  // namespace
+
+size_t lds_bytes_for(const LayerDesc& d, bool accumulate, int elem_bytes) {
+    const int cb = 2 * elem_bytes;
+    size_t b = (size_t)cb * kMaxTaps + (size_t)elem_bytes * 64 +
+               (size_t)elem_bytes * ((d.N + 3) & ~3) + 2 * sizeof(int) * ((d.N + 3) & ~3);
+    b = (b + 15) & ~size_t(15);
+    b += (size_t)cb * (d.N + d.M) + sizeof(int) * 4;
+    b = (b + 15) & ~size_t(15);
+    if (d.storage == kLds) {
+        b += (size_t)cb * d.ldg * d.N;
+        if (accumulate) b += (size_t)cb * d.ldv * d.N;
+    }
+    return b;
+}
+
+hipError_t launch_svd_f32(const SvdArgs<float>& a, int grid, size_t lds, hipStream_t s) {
+    return launch_svd<float>(a, grid, lds, s);
+}
+hipError_t launch_svd_f64(const SvdArgs<double>& a, int grid, size_t lds, hipStream_t s) {
+    return launch_svd<double>(a, grid, lds, s);
+}
+
+hipError_t launch_persistent_f32(const PersistentArgs<float>& a, int grid, size_t lds,
+                                 hipStream_t s) {
+    hipError_t e = allow_lds(persistent_kernel<float>, lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(persistent_kernel<float>, dim3(grid), dim3(a.threads), lds, s, a);
+    return hipGetLastError();
+}
+hipError_t launch_persistent_f64(const PersistentArgs<double>& a, int grid, size_t lds,
+                                 hipStream_t s) {
+    hipError_t e = allow_lds(persistent_kernel<double>, lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(persistent_kernel<double>, dim3(grid), dim3(a.threads), lds, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_i32(int32_t* p, int32_t value, long long count, hipStream_t s) {
+    if (count <= 0) return hipSuccess;
+    const int grid = (int)((count + 255) / 256 < 1024 ? (count + 255) / 256 : 1024);
+    hipLaunchKernelGGL(fill_i32_kernel, dim3(grid), dim3(256), 0, s, p, value, count);
+    return hipGetLastError();
+}
+
+}  // namespace lfa

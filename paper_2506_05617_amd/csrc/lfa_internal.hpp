@@ -1,0 +1,132 @@
+// Internal declarations shared by the host API (api.cpp) and the HIP kernel
+// sources.  Not part of the public ABI (that is include/lfa.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "lfa.h"
+
+namespace lfa {
+
+// Complex number in interleaved (re, im) layout, identical to
+// torch.complex64 / complex128 element storage.
+template <typename R>
+struct alignas(2 * sizeof(R)) cplx {
+    R x, y;
+};
+
+// Storage of the working matrix G (and the rotation accumulator) of a symbol
+// during the Jacobi sweeps.
+enum Storage : int { kLds = 0, kGlobal = 1 };
+
+// Per-layer launch description, device-visible (passed by value).
+struct LayerDesc {
+    int c_out, c_in, kh, kw, n, m;
+    int M, N;          // working matrix G is M x N with M = max(c), N = min(c)
+    int transposed;    // 1 when c_out < c_in: G = A^H
+    int tw_n, tw_m;    // offsets (in entries) of the n- and m-twiddle tables
+    int L;             // lanes cooperating on one column pair (power of two)
+    int threads;       // work-group size
+    int storage;       // Storage
+    int ldg, ldv;      // leading dimensions (elements) of G and of the accumulator
+    int num_symbols;   // n*m
+    long long sym_offset;   // first symbol of this layer in the plan's work list
+};
+
+// One item of the persistent work list: a (layer, first symbol) pair.
+struct WorkItem {
+    int layer;
+    int theta;
+};
+
+constexpr int kMaxLayers = 64;        // layers per plan
+constexpr int kMaxLaunchLayers = 12;  // layers per multi-layer launch (kernarg <= 4 KB)
+constexpr int kMaxTaps = 128;
+constexpr int kMaxR = 1024;
+constexpr int kRowsPerLane = 8;   // max rows of a column pair held per lane
+
+// Arguments of one SVD launch over one layer (plain path) or over a work
+// list (persistent path).
+template <typename R>
+struct SvdArgs {
+    LayerDesc d;
+    const R* W;                  // [c_out][c_in][kh*kw] weights, or null
+    const cplx<R>* A;            // [n*m][c_out][c_in] symbols, or null
+    R* sigma;                    // [n*m][r]
+    cplx<R>* U;                  // [n*m][c_out][r] or null
+    cplx<R>* V;                  // [n*m][c_in][r] or null
+    int32_t* info;               // [LFA_INFO_WORDS] of this layer, or null
+    const double* tw;            // twiddle table, (re, im) pairs
+    char* gws;                   // global working storage, one slot per block
+    long long slot_bytes;        // bytes per slot
+    const int32_t* theta_list;   // optional: symbol indices to process
+    int theta_stride;            // element stride in theta_list (3 for (p,q,j) triples)
+    int theta_count;             // number of symbols to process
+    int max_sweeps;
+    double tol;
+};
+
+size_t lds_bytes_for(const LayerDesc& d, bool accumulate, int elem_bytes);
+
+// Launchers (each returns a hipError_t).
+hipError_t launch_svd_f32(const SvdArgs<float>& a, int grid, size_t lds, hipStream_t s);
+hipError_t launch_svd_f64(const SvdArgs<double>& a, int grid, size_t lds, hipStream_t s);
+
+hipError_t launch_symbols_valu_f32(const LayerDesc& d, const float* W, cplx<float>* A,
+                                   const double* tw, hipStream_t s);
+hipError_t launch_symbols_valu_f64(const LayerDesc& d, const double* W, cplx<double>* A,
+                                   const double* tw, hipStream_t s);
+// mode: 0 = FP32 MFMA, 2 = split-BF16 x2 (3 products), 3 = split-BF16 x3 (6 products)
+hipError_t launch_symbols_mfma(const LayerDesc& d, const float* W, cplx<float>* A,
+                               const double* tw, int mode, hipStream_t s);
+
+hipError_t launch_fill_i32(int32_t* p, int32_t value, long long count, hipStream_t s);
+
+template <typename R>
+struct TopkArgs {
+    const R* sigma[kMaxLaunchLayers];
+    int n[kMaxLaunchLayers], m[kMaxLaunchLayers], r[kMaxLaunchLayers];
+    int num_layers;
+    int k;
+    R* vals;
+    int32_t* idx;
+};
+hipError_t launch_topk_f32(const TopkArgs<float>& a, hipStream_t s);
+hipError_t launch_topk_f64(const TopkArgs<double>& a, hipStream_t s);
+
+template <typename R>
+struct AdjointArgs {
+    int c_out[kMaxLaunchLayers], c_in[kMaxLaunchLayers], kh[kMaxLaunchLayers],
+        kw[kMaxLaunchLayers], n[kMaxLaunchLayers], m[kMaxLaunchLayers];
+    int tw_n[kMaxLaunchLayers], tw_m[kMaxLaunchLayers];
+    const cplx<R>* U[kMaxLaunchLayers];   // full [n*m][c_out][r] or compact [k][c_out][r]
+    const cplx<R>* V[kMaxLaunchLayers];
+    R* dW[kMaxLaunchLayers];
+    int blocks_before[kMaxLaunchLayers + 1];
+    int num_layers;
+    int k;
+    int compact;                    // 1: U/V hold only the k selected symbols
+    const int32_t* idx;             // [num_layers][k][3]
+    const R* grad;                  // [num_layers][k]
+    const double* tw;
+};
+hipError_t launch_adjoint_f32(const AdjointArgs<float>& a, hipStream_t s);
+hipError_t launch_adjoint_f64(const AdjointArgs<double>& a, hipStream_t s);
+
+// Persistent launch over a work list covering several layers.
+template <typename R>
+struct PersistentArgs {
+    SvdArgs<R> layer[kMaxLaunchLayers];   // per-layer arguments (d, pointers)
+    int num_layers;
+    const WorkItem* items;          // device work list, largest work first
+    int num_items;
+    int32_t* counter;               // device dequeue counter (cleared before launch)
+    int threads;                    // common work-group size
+};
+hipError_t launch_persistent_f32(const PersistentArgs<float>& a, int grid, size_t lds,
+                                 hipStream_t s);
+hipError_t launch_persistent_f64(const PersistentArgs<double>& a, int grid, size_t lds,
+                                 hipStream_t s);
+
+}  // namespace lfa

@@ -1,0 +1,323 @@
+"""PyTorch binding of liblfa: argument marshalling only.
+
+Every step of the computation runs in the HIP kernels of liblfa.so; this
+module checks shapes and dtypes, allocates outputs and workspace with torch
+(device memory is owned by PyTorch's allocator) and passes raw pointers and
+the current HIP stream through the C ABI.
+
+Layouts (see include/lfa.h): W is [c_out, c_in, kh, kw]; symbols are
+[n, m, c_out, c_in] complex; sigma is [n, m, r] (descending); U is
+[n, m, c_out, r], V is [n, m, c_in, r] with A = U diag(sigma) V^H.
+"""
+
+from __future__ import annotations
+
+import ctypes
+from dataclasses import dataclass
+from typing import Sequence
+
+import torch
+
+from . import _lib
+from ._lib import check, ptr_array
+
+
+def _stream_ptr():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _dtype_code(dtype):
+    if dtype == torch.float32:
+        return _lib.LFA_F32
+    if dtype == torch.float64:
+        return _lib.LFA_F64
+    raise TypeError(f"weights must be float32 or float64, got {dtype}")
+
+
+def _complex_of(dtype):
+    return torch.complex64 if dtype == torch.float32 else torch.complex128
+
+
+def _asm_flag(asm):
+    return {None: 0, "valu": 0, "mfma": _lib.LFA_ASM_MFMA,
+            "bf16x2": _lib.LFA_ASM_BF16X2, "bf16x3": _lib.LFA_ASM_BF16X3}[asm]
+
+
+@dataclass(frozen=True)
+class LayerSpec:
+    c_out: int
+    c_in: int
+    kh: int
+    kw: int
+    n: int
+    m: int
+
+    @property
+    def r(self):
+        return min(self.c_out, self.c_in)
+
+
+class Plan:
+    """An lfa_plan: layer shapes, dtype and flags fixed at creation.
+
+    Workspace is allocated lazily on the device of the first call and reused.
+    """
+
+    def __init__(self, layers: Sequence[LayerSpec], dtype=torch.float32, want_u=False,
+                 want_v=False, asm=None):
+        self.lib = _lib.load()
+        self.layers = [LayerSpec(*l) if not isinstance(l, LayerSpec) else l for l in layers]
+        self.dtype = dtype
+        self.want_u, self.want_v, self.asm = want_u, want_v, asm
+        flags = (_lib.LFA_WANT_U if want_u else 0) | (_lib.LFA_WANT_V if want_v else 0) | _asm_flag(asm)
+        arr = (_lib.LfaLayer * len(self.layers))(
+            *[_lib.LfaLayer(l.c_out, l.c_in, l.kh, l.kw, l.n, l.m) for l in self.layers])
+        h = ctypes.c_void_p()
+        check(self.lib.lfa_plan_create(ctypes.byref(h), arr, len(self.layers),
+                                       _dtype_code(dtype), flags), "lfa_plan_create")
+        self.handle = h
+        nb = ctypes.c_size_t()
+        check(self.lib.lfa_plan_workspace_bytes(h, ctypes.byref(nb)), "lfa_plan_workspace_bytes")
+        self.ws_bytes = nb.value
+        self._ws = None
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h is not None and h.value:
+            self.lib.lfa_plan_destroy(h)
+            self.handle = None
+
+    def workspace(self, device):
+        if self._ws is None or self._ws.device != device:
+            self._ws = torch.empty(max(self.ws_bytes, 256), dtype=torch.uint8, device=device)
+        return self._ws
+
+    def launch_shape(self, layer):
+        vals = [ctypes.c_int32() for _ in range(4)]
+        check(self.lib.lfa_plan_launch_shape(self.handle, layer, *[ctypes.byref(v) for v in vals]),
+              "lfa_plan_launch_shape")
+        return tuple(v.value for v in vals)
+
+    # -- checks --------------------------------------------------------------
+    def _check_weights(self, Ws):
+        if len(Ws) != len(self.layers):
+            raise ValueError("one weight tensor per layer")
+        dev = Ws[0].device
+        for W, l in zip(Ws, self.layers):
+            if W.device.type != "cuda":
+                raise ValueError("weights must be on the GPU")
+            if W.device != dev:
+                raise ValueError("all weights on one device")
+            if W.dtype != self.dtype:
+                raise TypeError(f"weights must be {self.dtype}")
+            if tuple(W.shape) != (l.c_out, l.c_in, l.kh, l.kw) or not W.is_contiguous():
+                raise ValueError(f"weight of shape {tuple(W.shape)} does not match {l}")
+        return dev
+
+    def _alloc_outputs(self, dev, want_u, want_v, count=None):
+        cdt = _complex_of(self.dtype)
+        S, U, V = [], [], []
+        for l in self.layers:
+            lead = (l.n, l.m) if count is None else (count,)
+            S.append(torch.empty(*lead, l.r, dtype=self.dtype, device=dev))
+            U.append(torch.empty(*lead, l.c_out, l.r, dtype=cdt, device=dev) if want_u else None)
+            V.append(torch.empty(*lead, l.c_in, l.r, dtype=cdt, device=dev) if want_v else None)
+        return S, U, V
+
+    # -- entry points -------------------------------------------------------
+    def symbols(self, Ws):
+        dev = self._check_weights(Ws)
+        cdt = _complex_of(self.dtype)
+        A = [torch.empty(l.n, l.m, l.c_out, l.c_in, dtype=cdt, device=dev) for l in self.layers]
+        w, _k1 = ptr_array([W.data_ptr() for W in Ws])
+        a, _k2 = ptr_array([x.data_ptr() for x in A])
+        check(self.lib.lfa_symbols(self.handle, w, a, _stream_ptr()), "lfa_symbols")
+        return A
+
+    def _svd_call(self, fn, name, inputs, dev, info=None, out=None):
+        S, U, V = out if out is not None else self._alloc_outputs(dev, self.want_u, self.want_v)
+        if info is None:
+            info = torch.zeros(len(self.layers), _lib.LFA_INFO_WORDS, dtype=torch.int32, device=dev)
+        ws = self.workspace(dev)
+        i_arr, _k0 = ptr_array([x.data_ptr() for x in inputs])
+        s_arr, _k1 = ptr_array([x.data_ptr() for x in S])
+        u_arr, _k2 = ptr_array([x.data_ptr() if x is not None else 0 for x in U])
+        v_arr, _k3 = ptr_array([x.data_ptr() if x is not None else 0 for x in V])
+        check(fn(self.handle, i_arr, s_arr, u_arr if self.want_u else None,
+                 v_arr if self.want_v else None, ctypes.c_void_p(info.data_ptr()),
+                 ctypes.c_void_p(ws.data_ptr()), ctypes.c_size_t(ws.numel()), _stream_ptr()), name)
+        return S, U, V, info
+
+    def svd(self, Ws, persistent=False, info=None, out=None):
+        """SVD of every symbol of every layer.  Returns lists (S, U, V, info)."""
+        dev = self._check_weights(Ws)
+        fn = self.lib.lfa_svd_persistent if persistent else self.lib.lfa_svd
+        return self._svd_call(fn, "lfa_svd_persistent" if persistent else "lfa_svd", Ws, dev, info, out)
+
+    def svd_symbols(self, As, info=None):
+        cdt = _complex_of(self.dtype)
+        for A, l in zip(As, self.layers):
+            if A.dtype != cdt or tuple(A.shape) != (l.n, l.m, l.c_out, l.c_in) or not A.is_contiguous():
+                raise ValueError("symbols must be contiguous [n, m, c_out, c_in] complex")
+        return self._svd_call(self.lib.lfa_svd_symbols, "lfa_svd_symbols", As, As[0].device, info)
+
+    def topk(self, S, k):
+        dev = S[0].device
+        vals = torch.empty(len(self.layers), k, dtype=self.dtype, device=dev)
+        idx = torch.empty(len(self.layers), k, 3, dtype=torch.int32, device=dev)
+        s_arr, _k = ptr_array([x.data_ptr() for x in S])
+        check(self.lib.lfa_topk(self.handle, s_arr, k, ctypes.c_void_p(vals.data_ptr()),
+                                ctypes.c_void_p(idx.data_ptr()), _stream_ptr()), "lfa_topk")
+        return vals, idx
+
+    def adjoint(self, U, V, idx, grad):
+        dev = idx.device
+        k = idx.shape[1]
+        dW = [torch.empty(l.c_out, l.c_in, l.kh, l.kw, dtype=self.dtype, device=dev) for l in self.layers]
+        u_arr, _k1 = ptr_array([x.data_ptr() for x in U])
+        v_arr, _k2 = ptr_array([x.data_ptr() for x in V])
+        d_arr, _k3 = ptr_array([x.data_ptr() for x in dW])
+        idx = idx.contiguous()
+        grad = grad.to(self.dtype).contiguous()
+        check(self.lib.lfa_adjoint(self.handle, u_arr, v_arr, ctypes.c_void_p(idx.data_ptr()),
+                                   ctypes.c_void_p(grad.data_ptr()), k, d_arr, _stream_ptr()),
+              "lfa_adjoint")
+        return dW
+
+    def sigma_grad(self, Ws, idx, grad, out=None):
+        dev = self._check_weights(Ws)
+        k = idx.shape[1]
+        dW = out if out is not None else [
+            torch.empty(l.c_out, l.c_in, l.kh, l.kw, dtype=self.dtype, device=dev) for l in self.layers]
+        ws = self.workspace(dev)
+        w_arr, _k1 = ptr_array([x.data_ptr() for x in Ws])
+        d_arr, _k2 = ptr_array([x.data_ptr() for x in dW])
+        idx = idx.contiguous()
+        grad = grad.to(self.dtype).contiguous()
+        check(self.lib.lfa_sigma_grad(self.handle, w_arr, ctypes.c_void_p(idx.data_ptr()),
+                                      ctypes.c_void_p(grad.data_ptr()), k, d_arr,
+                                      ctypes.c_void_p(ws.data_ptr()), ctypes.c_size_t(ws.numel()),
+                                      _stream_ptr()), "lfa_sigma_grad")
+        return dW
+
+    def autotune(self, Ws):
+        dev = self._check_weights(Ws)
+        S, U, V = self._alloc_outputs(dev, self.want_u, self.want_v)
+        ws = self.workspace(dev)
+        w_arr, _k0 = ptr_array([x.data_ptr() for x in Ws])
+        s_arr, _k1 = ptr_array([x.data_ptr() for x in S])
+        u_arr, _k2 = ptr_array([x.data_ptr() if x is not None else 0 for x in U])
+        v_arr, _k3 = ptr_array([x.data_ptr() if x is not None else 0 for x in V])
+        check(self.lib.lfa_autotune(self.handle, w_arr, s_arr, u_arr, v_arr,
+                                    ctypes.c_void_p(ws.data_ptr()), ctypes.c_size_t(ws.numel()),
+                                    _stream_ptr()), "lfa_autotune")
+
+
+class GraphStep:
+    """HIP graph of [persistent sigma-only SVD -> top-k -> sigma gradient] for
+    fixed buffers.  Copy new weights into ``self.W`` and call ``replay()``."""
+
+    def __init__(self, plan: Plan, Ws, k, grad=None, stream=None):
+        if plan.want_u or plan.want_v:
+            raise ValueError("graph step needs a sigma-only plan")
+        self.plan = plan
+        dev = plan._check_weights(Ws)
+        self.W = Ws
+        self.k = k
+        self.stream = stream if stream is not None else torch.cuda.Stream(device=dev)
+        self.S, _, _ = plan._alloc_outputs(dev, False, False)
+        L = len(plan.layers)
+        self.vals = torch.empty(L, k, dtype=plan.dtype, device=dev)
+        self.idx = torch.empty(L, k, 3, dtype=torch.int32, device=dev)
+        self.grad = (torch.ones(L, k, dtype=plan.dtype, device=dev) if grad is None
+                     else grad.to(plan.dtype).contiguous())
+        self.dW = [torch.empty_like(W) for W in Ws]
+        self.info = torch.zeros(L, _lib.LFA_INFO_WORDS, dtype=torch.int32, device=dev)
+        ws = plan.workspace(dev)
+        self._keep = []
+        w_arr, k0 = ptr_array([x.data_ptr() for x in Ws])
+        s_arr, k1 = ptr_array([x.data_ptr() for x in self.S])
+        d_arr, k2 = ptr_array([x.data_ptr() for x in self.dW])
+        self._keep += [k0, k1, k2, ws]
+        h = ctypes.c_void_p()
+        torch.cuda.synchronize(dev)
+        check(plan.lib.lfa_graph_create(
+            plan.handle, w_arr, s_arr, k, ctypes.c_void_p(self.vals.data_ptr()),
+            ctypes.c_void_p(self.idx.data_ptr()), ctypes.c_void_p(self.grad.data_ptr()), d_arr,
+            ctypes.c_void_p(self.info.data_ptr()), ctypes.c_void_p(ws.data_ptr()),
+            ctypes.c_size_t(ws.numel()), ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h)),
+            "lfa_graph_create")
+        self.handle = h
+
+    def replay(self):
+        torch.cuda.current_stream().synchronize()
+        check(self.plan.lib.lfa_graph_launch(self.handle, ctypes.c_void_p(self.stream.cuda_stream)),
+              "lfa_graph_launch")
+        return self.stream
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h is not None and h.value:
+            self.plan.lib.lfa_graph_destroy(h)
+            self.handle = None
+
+
+# ---------------------------------------------------------------------------
+# Convenience functions
+# ---------------------------------------------------------------------------
+
+_PLANS = {}
+
+
+def _plan_for(specs, dtype, want_u, want_v, asm=None):
+    key = (tuple(specs), dtype, want_u, want_v, asm)
+    p = _PLANS.get(key)
+    if p is None:
+        p = Plan(specs, dtype, want_u, want_v, asm)
+        _PLANS[key] = p
+    return p
+
+
+def _spec(W, n, m):
+    c_out, c_in, kh, kw = W.shape
+    return LayerSpec(c_out, c_in, kh, kw, n, n if m is None else m)
+
+
+def symbols(W, n, m=None, asm=None):
+    """Symbols [n, m, c_out, c_in] of one layer (lfa_symbols)."""
+    return _plan_for([_spec(W, n, m)], W.dtype, False, False, asm).symbols([W])[0]
+
+
+def svd(W, n, m=None, compute_uv=False, asm=None, return_info=False):
+    """Singular values [n, m, r] (and U, V if compute_uv) of one layer."""
+    p = _plan_for([_spec(W, n, m)], W.dtype, compute_uv, compute_uv, asm)
+    S, U, V, info = p.svd([W])
+    out = (S[0], U[0], V[0]) if compute_uv else S[0]
+    return (out, info[0]) if return_info else out
+
+
+class SigmaTopK(torch.autograd.Function):
+    """Per-layer top-k singular values of a stack of periodic convolutions,
+    differentiable in the weights: forward = one persistent sigma-only SVD
+    launch + top-k; backward = SVD with vectors of the selected symbols +
+    adjoint kernel (lfa_sigma_grad)."""
+
+    @staticmethod
+    def forward(ctx, plan: Plan, k: int, *Ws):
+        S, _, _, info = plan.svd(list(Ws), persistent=True)
+        vals, idx = plan.topk(S, k)
+        ctx.plan = plan
+        ctx.save_for_backward(idx, *Ws)
+        ctx.mark_non_differentiable(idx)
+        return vals, idx
+
+    @staticmethod
+    def backward(ctx, grad_vals, _grad_idx):
+        idx, *Ws = ctx.saved_tensors
+        dW = ctx.plan.sigma_grad(list(Ws), idx, grad_vals.contiguous())
+        return (None, None, *dW)
+
+
+def sigma_topk(plan: Plan, Ws, k: int):
+    """Differentiable per-layer top-k singular values: returns (vals [L, k], idx [L, k, 3])."""
+    return SigmaTopK.apply(plan, k, *Ws)

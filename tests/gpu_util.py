@@ -1,0 +1,87 @@
+"""Helpers shared by the GPU parity tests (comparison metrics, case banners).
+No method arithmetic: expected values always come from ``oracle``."""
+
+import sys
+
+import numpy as np
+import torch
+
+EPS32 = 2.0 ** -24
+EPS64 = 2.0 ** -53
+
+
+def banner(msg):
+    print(f"\n[gpu-case] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+def to_np(t):
+    return t.detach().cpu().numpy()
+
+
+def sigma_gate(dtype):
+    """sigma error gates: normwise per symbol, 1e-5 in FP32, 1e-12 in FP64."""
+    return 1e-5 if dtype == torch.float32 else 1e-12
+
+
+def ortho_gate(M, dtype):
+    """Loss of orthogonality allowed for U and V columns: the Jacobi stopping
+    threshold (M times the unit roundoff, relative) twice, plus slack for the
+    rounding of the accumulated rotations."""
+    eps = EPS32 if dtype == torch.float32 else EPS64
+    return 2 * M * eps + (1e-6 if dtype == torch.float32 else 1e-14)
+
+
+def resid_gate(M, dtype):
+    eps = EPS32 if dtype == torch.float32 else EPS64
+    return 4 * M * eps + (1e-6 if dtype == torch.float32 else 1e-14)
+
+
+def check_vectors(A, S, U, V, dtype, tag=""):
+    """A [..., c_out, c_in] (oracle, complex128); S, U, V from the GPU (numpy).
+    Checks residual ||A V - U S||_F / ||A||_F, orthonormality of U and V."""
+    c_out, c_in = A.shape[-2:]
+    M = max(c_out, c_in)
+    Sd = S.astype(np.float64)
+    Ud = U.astype(np.complex128)
+    Vd = V.astype(np.complex128)
+    res = A @ Vd - Ud * Sd[..., None, :]
+    nA = np.sqrt(np.sum(np.abs(A) ** 2, axis=(-2, -1)))
+    nA = np.where(nA > 0, nA, 1.0)
+    rel = np.sqrt(np.sum(np.abs(res) ** 2, axis=(-2, -1))) / nA
+    r = S.shape[-1]
+    eye = np.eye(r)
+    ou = np.max(np.abs(np.conj(np.swapaxes(Ud, -1, -2)) @ Ud - eye))
+    ov = np.max(np.abs(np.conj(np.swapaxes(Vd, -1, -2)) @ Vd - eye))
+    assert rel.max() <= resid_gate(M, dtype), f"{tag} residual {rel.max():.3e}"
+    assert ou <= ortho_gate(M, dtype), f"{tag} U orthonormality {ou:.3e}"
+    assert ov <= ortho_gate(M, dtype), f"{tag} V orthonormality {ov:.3e}"
+    return rel.max(), ou, ov
+
+
+def check_projectors(S_ref, U_ref, V_ref, U, V, dtype, tag=""):
+    """Gauge-invariant comparison with the oracle: for singular values with a
+    relative gap to their neighbours, u_j v_j^H must match."""
+    eps = 1e-6 if dtype == torch.float32 else 1e-13
+    r = S_ref.shape[-1]
+    smax = S_ref[..., :1]
+    gap = np.full(S_ref.shape, np.inf)
+    if r > 1:
+        d = np.abs(np.diff(S_ref, axis=-1))
+        gap[..., :-1] = np.minimum(gap[..., :-1], d)
+        gap[..., 1:] = np.minimum(gap[..., 1:], d)
+    rel_gap = gap / np.where(smax > 0, smax, 1.0)
+    Ud, Vd = U.astype(np.complex128), V.astype(np.complex128)
+    worst = 0.0
+    flat_ok = rel_gap > 1e-3
+    idx = np.argwhere(flat_ok)
+    for ind in idx[:: max(1, len(idx) // 400)]:
+        *lead, j = ind
+        lead = tuple(lead)
+        P_ref = np.outer(U_ref[lead][:, j], np.conj(V_ref[lead][:, j]))
+        P = np.outer(Ud[lead][:, j], np.conj(Vd[lead][:, j]))
+        err = np.max(np.abs(P - P_ref))
+        bound = eps * (10 + 1.0 / rel_gap[lead + (j,)])
+        worst = max(worst, err / bound)
+        assert err <= bound, f"{tag} projector {lead}, j={j}: {err:.3e} > {bound:.3e}"
+    return worst

@@ -1,0 +1,119 @@
+"""C-ABI checks that need no GPU: the library loads, exports every function
+declared in include/lfa.h, and rejects bad plans at enqueue time."""
+
+import ctypes
+import os
+import re
+
+import pytest
+
+import paper_2506_05617_amd as lfa
+from paper_2506_05617_amd import _lib
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "lfa.h")
+
+needs_lib = pytest.mark.skipif(not os.path.exists(_lib.LIB_PATH),
+                               reason="liblfa.so not built (run __graft_entry__.build())")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(lfa_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_header_declares_the_documented_entry_points():
+    names = declared_functions()
+    for must in ["lfa_plan_create", "lfa_symbols", "lfa_svd", "lfa_svd_persistent", "lfa_topk",
+                 "lfa_adjoint", "lfa_sigma_grad", "lfa_graph_create", "lfa_autotune",
+                 "lfa_status_string"]:
+        assert must in names
+    assert set(names) == set(_lib.SIGNATURES), "binding and header disagree"
+
+
+@needs_lib
+def test_library_exports_every_declared_symbol():
+    lib = ctypes.CDLL(_lib.LIB_PATH)
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+
+
+@needs_lib
+def test_status_strings_and_version():
+    lib = lfa.load()
+    assert lib.lfa_version() == 1
+    for code in (0, -1, -2, -3, -4, -5, 12345):
+        assert lib.lfa_status_string(code)
+    assert lib.lfa_last_hip_error() == 0
+
+
+def _create(layers, dtype=0, flags=0):
+    lib = lfa.load()
+    arr = (_lib.LfaLayer * len(layers))(*[_lib.LfaLayer(*l) for l in layers])
+    h = ctypes.c_void_p()
+    st = lib.lfa_plan_create(ctypes.byref(h), arr, len(layers), dtype, flags)
+    if st == 0:
+        lib.lfa_plan_destroy(h)
+    else:
+        assert not h.value
+    return st
+
+
+@needs_lib
+@pytest.mark.parametrize("layer,dtype,flags,expect", [
+    ((16, 16, 3, 3, 32, 32), 0, 0, 0),
+    ((16, 16, 3, 3, 32, 32), 1, 3, 0),
+    ((0, 16, 3, 3, 32, 32), 0, 0, -1),            # empty channel
+    ((16, 16, 3, 3, 0, 32), 0, 0, -1),            # empty grid
+    ((16, 16, 5, 5, 4, 4), 0, 0, -1),             # kernel wider than the grid
+    ((16, 16, 3, 3, 32, 32), 2, 0, -1),           # unknown dtype
+    ((16, 16, 3, 3, 32, 32), 0, 1 << 10, -1),     # unknown flag
+    ((16, 16, 3, 3, 32, 32), 0, 8 | 16, -1),      # two assembly modes
+    ((16, 16, 3, 3, 32, 32), 1, 8, -2),           # BF16 assembly needs FP32
+    ((1024, 16, 3, 3, 8, 8), 0, 0, -2),           # more rows than one work-group holds
+    ((16, 16, 13, 13, 16, 16), 0, 0, -2),         # more than 128 taps
+])
+def test_plan_validation(layer, dtype, flags, expect):
+    assert _create([layer], dtype, flags) == expect
+
+
+@needs_lib
+def test_null_and_count_arguments():
+    lib = lfa.load()
+    h = ctypes.c_void_p()
+    arr = (_lib.LfaLayer * 1)(_lib.LfaLayer(4, 4, 3, 3, 8, 8))
+    assert lib.lfa_plan_create(None, arr, 1, 0, 0) == -1
+    assert lib.lfa_plan_create(ctypes.byref(h), None, 1, 0, 0) == -1
+    assert lib.lfa_plan_create(ctypes.byref(h), arr, 0, 0, 0) == -1
+    assert lib.lfa_plan_destroy(None) == 0
+    assert lib.lfa_svd(None, None, None, None, None, None, None, 0, None) == -1
+    assert lib.lfa_topk(None, None, 8, None, None, None) == -1
+
+
+@needs_lib
+def test_compute_calls_reject_bad_arguments_before_touching_the_gpu():
+    plan = lfa.Plan([lfa.LayerSpec(8, 8, 3, 3, 8, 8)])
+    lib = plan.lib
+    pp, keep = _lib.ptr_array([0])
+    # null weight pointer in the per-layer array
+    assert lib.lfa_svd(plan.handle, pp, pp, None, None, None, None, 0, None) == -1
+    one, keep1 = _lib.ptr_array([1 << 20])
+    # workspace missing
+    assert lib.lfa_svd(plan.handle, one, one, None, None, None, None, 0, None) == -3
+    # k out of range
+    assert lib.lfa_topk(plan.handle, one, 0, ctypes.c_void_p(1), ctypes.c_void_p(1), None) == -1
+    assert lib.lfa_topk(plan.handle, one, 65, ctypes.c_void_p(1), ctypes.c_void_p(1), None) == -1
+
+
+@needs_lib
+def test_workspace_and_launch_shapes():
+    small = lfa.Plan([lfa.LayerSpec(16, 16, 3, 3, 32, 32)])
+    L, threads, spg, storage = small.launch_shape(0)
+    assert (L, storage) == (2, 0) and threads >= 64
+    big = lfa.Plan([lfa.LayerSpec(512, 256, 3, 3, 32, 32)], want_u=True, want_v=True)
+    L, threads, spg, storage = big.launch_shape(0)
+    assert (L, threads, storage) == (64, 1024, 1)
+    assert big.ws_bytes > 512 * 256 * 8
+    wide = lfa.Plan([lfa.LayerSpec(3, 64, 3, 3, 8, 8)])     # c_out < c_in: works on A^H
+    assert wide.launch_shape(0)[0] == 8
