@@ -57,6 +57,15 @@ int pow2ceil(int x) {
 
 int elem_bytes(int dtype) { return dtype == LFA_F64 ? 8 : 4; }
 
+// Rotation threshold of a column pair: |g_j^H g_k| > tol * |g_j| |g_k| with
+// tol = 2 sqrt(M) u.  The computed inner product of two orthogonal columns
+// carries at most (rows per lane + log2 lanes) u |g_j| |g_k| <= 14 u of
+// rounding error, below this threshold for every M >= 16, so sweeps cannot
+// stall on rounding noise; the final loss of orthogonality is about tol.
+double jacobi_tol(double unit_roundoff, int M) {
+    return 2.0 * std::sqrt((double)std::max(M, 16)) * unit_roundoff;
+}
+
 }  // namespace
 
 struct lfa_plan {
@@ -70,11 +79,14 @@ struct lfa_plan {
     std::vector<double> tw_host;          // (re, im) pairs
     std::vector<WorkItem> items;          // persistent work list, LPT order per chunk
     std::vector<int> chunk_first;         // first item of each chunk of layers (+ end)
+    std::vector<int32_t> canon_host;      // canonical frequencies of every layer, concatenated
+    std::vector<int> canon_off;           // offset of each layer in canon_host
     double tol = 0;
     std::mutex mu;
     int device = -1;
     double* tw_dev = nullptr;
     WorkItem* items_dev = nullptr;
+    int32_t* canon_dev = nullptr;
 };
 
 struct lfa_graph {
@@ -92,7 +104,7 @@ bool accumulates(const LayerDesc& d, bool want_u, bool want_v) {
 // kRowsPerLane rows, one lane group per column pair of a step (capped at
 // 1024 threads), LDS storage when the working matrices fit under `lds_cap`.
 LayerDesc make_desc(const lfa_layer& l, int tw_n, int tw_m, bool acc, int eb, size_t lds_cap,
-                    int threads_override = 0, int L_override = 0) {
+                    int threads_override = 0, int L_override = 0, bool allow_wave = true) {
     LayerDesc d{};
     d.c_out = l.c_out;
     d.c_in = l.c_in;
@@ -118,10 +130,20 @@ LayerDesc make_desc(const lfa_layer& l, int tw_n, int tw_m, bool acc, int eb, si
     d.ldg = d.M | 1;
     d.ldv = d.N | 1;
     d.storage = kLds;
+    d.kind = 0;
+    if (allow_wave && d.M <= 64 && !threads_override && !L_override) {
+        // register-resident kernel: rows in lanes, one wave (+ one for Q)
+        d.kind = 1;
+        d.wave_ml = std::max(16, pow2ceil(d.M));
+        d.wave_nc = std::max(4, pow2ceil(d.N));
+        d.threads = acc ? 128 : 64;
+    }
     if (lds_bytes_for(d, acc, eb) > lds_cap) d.storage = kGlobal;
     d.sym_offset = 0;
     return d;
 }
+
+int wave_symbols_per_group(const LayerDesc& d) { return d.kind == 1 ? 64 / d.wave_ml : 1; }
 
 size_t slot_bytes(const LayerDesc& d, bool acc, int eb) {
     if (d.storage != kGlobal) return 0;
@@ -224,6 +246,9 @@ int ensure_device(lfa_plan* p) {
     if (!p->items.empty())
         HIP_TRY(hipMemcpy(p->items_dev, p->items.data(), p->items.size() * sizeof(WorkItem),
                           hipMemcpyHostToDevice));
+    HIP_TRY(hipMalloc(&p->canon_dev, std::max<size_t>(1, p->canon_host.size()) * sizeof(int32_t)));
+    HIP_TRY(hipMemcpy(p->canon_dev, p->canon_host.data(), p->canon_host.size() * sizeof(int32_t),
+                      hipMemcpyHostToDevice));
     // Devices reporting less LDS than the plan assumed: move layers to global slots.
     const size_t lds_dev = prop.sharedMemPerBlock;
     const int eb = elem_bytes(p->dtype);
@@ -243,9 +268,10 @@ template <typename R>
 int run_svd_layer(const lfa_plan* p, const LayerDesc& d, const void* W, const void* A,
                   void* sigma, void* U, void* V, int32_t* info, char* region,
                   const int32_t* theta_list, int theta_stride, int theta_count,
-                  hipStream_t st) {
+                  hipStream_t st, const int32_t* canon = nullptr) {
     SvdArgs<R> a{};
     a.d = d;
+    a.canon = theta_list ? nullptr : canon;
     a.W = static_cast<const R*>(W);
     a.A = static_cast<const cplx<R>*>(A);
     a.sigma = static_cast<R*>(sigma);
@@ -257,15 +283,24 @@ int run_svd_layer(const lfa_plan* p, const LayerDesc& d, const void* W, const vo
     a.theta_stride = theta_stride;
     a.theta_count = theta_count;
     a.max_sweeps = kMaxSweeps;
-    a.tol = p->tol * d.M;
+    a.tol = jacobi_tol(p->tol, d.M);
     const bool acc = (d.transposed ? U : V) != nullptr;
-    const int count = theta_list ? theta_count : d.num_symbols;
+    const int count = item_count(a);
     if (count <= 0) return LFA_OK;
+    hipError_t e;
+    if (d.kind == 1) {
+        if (acc != (d.threads > 64)) return LFA_ERR_INVALID_ARG;   // shape made for other outputs
+        const int spg = wave_symbols_per_group(d);
+        const int grid = (count + spg - 1) / spg;
+        if constexpr (sizeof(R) == 4) e = launch_wave_svd_f32(a, grid, st);
+        else e = launch_wave_svd_f64(a, grid, st);
+        HIP_TRY(e);
+        return LFA_OK;
+    }
     const int grid = svd_grid(d, count);
     a.slot_bytes = (long long)slot_bytes(d, acc, sizeof(R));
     a.gws = d.storage == kGlobal ? region : nullptr;
     const size_t lds = lds_bytes_for(d, acc, sizeof(R));
-    hipError_t e;
     if constexpr (sizeof(R) == 4) e = launch_svd_f32(a, grid, lds, st);
     else e = launch_svd_f64(a, grid, lds, st);
     HIP_TRY(e);
@@ -301,10 +336,13 @@ int svd_impl(const lfa_plan* p, const void* const* W, const void* const* A, void
                 Wi = W[i];
             }
         }
+        // weights are real: decompose one symbol per conjugate pair.  Symbols
+        // handed in by the caller carry no such guarantee.
+        const int32_t* canon = A ? nullptr : p->canon_dev + p->canon_off[i];
         LFA_TRY(run_svd_layer<R>(p, d, Wi, Ai, sigma[i], wu ? U[i] : nullptr,
                                  wv ? V[i] : nullptr,
                                  info ? info + i * LFA_INFO_WORDS : nullptr, slots, nullptr, 0, 0,
-                                 st));
+                                 st, canon));
     }
     return LFA_OK;
 }
@@ -331,10 +369,17 @@ int persistent_impl(const lfa_plan* p, const void* const* W, void* const* sigma,
         PersistentArgs<R> pa{};
         pa.num_layers = l1 - l0;
         pa.threads = kPersistentThreads;
+        // One slot stride for every layer of the launch: a block owns the
+        // same slot whatever layer its current item belongs to.
         size_t lds = 0, slot = 0;
         for (int i = l0; i < l1; ++i) {
             const LayerDesc& d = p->desc_pers[i];
             const bool acc = accumulates(d, wu, wv);
+            lds = std::max(lds, lds_bytes_for(d, acc, sizeof(R)));
+            slot = std::max(slot, slot_bytes(d, acc, sizeof(R)));
+        }
+        for (int i = l0; i < l1; ++i) {
+            const LayerDesc& d = p->desc_pers[i];
             SvdArgs<R>& a = pa.layer[i - l0];
             a.d = d;
             a.W = static_cast<const R*>(W[i]);
@@ -344,11 +389,10 @@ int persistent_impl(const lfa_plan* p, const void* const* W, void* const* sigma,
             a.info = info ? info + i * LFA_INFO_WORDS : nullptr;
             a.tw = p->tw_dev;
             a.max_sweeps = kMaxSweeps;
-            a.tol = p->tol * d.M;
-            a.slot_bytes = (long long)slot_bytes(d, acc, sizeof(R));
+            a.tol = jacobi_tol(p->tol, d.M);
+            a.slot_bytes = (long long)slot;
             a.gws = d.storage == kGlobal ? region : nullptr;
-            lds = std::max(lds, lds_bytes_for(d, acc, sizeof(R)));
-            slot = std::max(slot, (size_t)a.slot_bytes);
+            a.canon = p->canon_dev + p->canon_off[i];
         }
         const int chunk = l0 / kMaxLaunchLayers;
         const int first = p->chunk_first[chunk];
@@ -511,8 +555,7 @@ int lfa_plan_create(lfa_plan** out, const lfa_layer* layers, int32_t num_layers,
     p->flags = flags;
     p->layers.assign(layers, layers + num_layers);
     const int eb = elem_bytes(dtype);
-    // unit roundoff of the working precision; the convergence threshold of a
-    // layer is tol * M
+    // unit roundoff of the working precision (see jacobi_tol)
     p->tol = dtype == LFA_F64 ? std::ldexp(1.0, -53) : std::ldexp(1.0, -24);
 
     // twiddles exp(2 pi i j / L) for every distinct grid length L
@@ -530,8 +573,22 @@ int lfa_plan_create(lfa_plan** out, const lfa_layer* layers, int32_t num_layers,
             }
         }
     }
-    const bool wu = flags & LFA_WANT_U, wv = flags & LFA_WANT_V;
+    // canonical frequencies: index t with t <= index of its mirror -k
     for (const lfa_layer& l : p->layers) {
+        p->canon_off.push_back((int)p->canon_host.size());
+        for (int t = 0; t < l.n * l.m; ++t) {
+            const int pp = t / l.m, qq = t % l.m;
+            const int mi = ((l.n - pp) % l.n) * l.m + (l.m - qq) % l.m;
+            if (t <= mi) p->canon_host.push_back(t);
+        }
+    }
+    const bool wu = flags & LFA_WANT_U, wv = flags & LFA_WANT_V;
+    int li = 0;
+    for (const lfa_layer& l : p->layers) {
+        const int ncanon = (li + 1 < (int)p->canon_off.size() ? p->canon_off[li + 1]
+                                                               : (int)p->canon_host.size()) -
+                           p->canon_off[li];
+        ++li;
         p->tw_n.push_back(off[l.n]);
         p->tw_m.push_back(off[l.m]);
         LayerDesc d = make_desc(l, off[l.n], off[l.m], false, eb, kLdsCap);
@@ -539,7 +596,10 @@ int lfa_plan_create(lfa_plan** out, const lfa_layer* layers, int32_t num_layers,
         p->desc.push_back(d);
         p->desc_sel.push_back(make_desc(l, off[l.n], off[l.m], true, eb, kLdsCap));
         LayerDesc dp = make_desc(l, off[l.n], off[l.m], accumulates(d, wu, wv), eb,
-                                 kPersistentLdsCap, kPersistentThreads);
+                                 kPersistentLdsCap, kPersistentThreads, 0, false);
+        p->desc.back().num_canon = ncanon;
+        p->desc_sel.back().num_canon = ncanon;
+        dp.num_canon = ncanon;
         p->desc_pers.push_back(dp);
     }
     // persistent work list: per chunk of layers, items by estimated cost
@@ -552,7 +612,7 @@ int lfa_plan_create(lfa_plan** out, const lfa_layer* layers, int32_t num_layers,
         for (int i = l0; i < l1; ++i) {
             const LayerDesc& d = p->desc_pers[i];
             const double cost = double(d.N) * d.N * d.M;
-            for (int t = 0; t < d.num_symbols; ++t) v.push_back({cost, WorkItem{i - l0, t}});
+            for (int t = 0; t < d.num_canon; ++t) v.push_back({cost, WorkItem{i - l0, t}});
         }
         std::stable_sort(v.begin(), v.end(),
                          [](const std::pair<double, WorkItem>& a, const std::pair<double, WorkItem>& b) {
@@ -569,6 +629,7 @@ int lfa_plan_destroy(lfa_plan* plan) {
     if (!plan) return LFA_OK;
     if (plan->tw_dev) (void)hipFree(plan->tw_dev);
     if (plan->items_dev) (void)hipFree(plan->items_dev);
+    if (plan->canon_dev) (void)hipFree(plan->canon_dev);
     delete plan;
     return LFA_OK;
 }
@@ -597,7 +658,7 @@ int lfa_plan_launch_shape(const lfa_plan* plan, int32_t layer, int32_t* lanes_pe
     const LayerDesc& d = plan->desc[layer];
     if (lanes_per_pair) *lanes_per_pair = d.L;
     if (threads) *threads = d.threads;
-    if (symbols_per_group) *symbols_per_group = 1;
+    if (symbols_per_group) *symbols_per_group = wave_symbols_per_group(d);
     if (storage) *storage = d.storage;
     return LFA_OK;
 }
@@ -788,6 +849,7 @@ int lfa_autotune(lfa_plan* plan, const void* const* W, void* const* sigma, void*
         const LayerDesc base = plan->desc[i];
         const bool acc = accumulates(base, wu, wv);
         std::vector<LayerDesc> cands;
+        if (base.M <= 64) cands.push_back(make_desc(plan->layers[i], base.tw_n, base.tw_m, acc, eb, kLdsCap));
         for (int L = 1; L <= 64; L <<= 1) {
             if (L * kRowsPerLane < base.M) continue;
             if (L > 4 * base.L) continue;
@@ -795,24 +857,27 @@ int lfa_autotune(lfa_plan* plan, const void* const* W, void* const* sigma, void*
                 if (th < L) continue;
                 if (th > 2 * pow2ceil(((base.N + 1) / 2) * L) && th > 64) continue;
                 cands.push_back(make_desc(plan->layers[i], base.tw_n, base.tw_m, acc, eb,
-                                          base.storage == kGlobal ? 0 : kLdsCap, th, L));
+                                          base.storage == kGlobal ? 0 : kLdsCap, th, L, false));
             }
         }
         float best = 1e30f;
         LayerDesc best_d = base;
         char* region = static_cast<char*>(ws) + kAlign;
-        for (const LayerDesc& d : cands) {
+        for (LayerDesc d : cands) {
+            d.num_canon = base.num_canon;
             float ms = 0;
             for (int rep = 0; rep < 2 && status == LFA_OK; ++rep) {
                 if (hipEventRecord(e0, st) != hipSuccess) { status = LFA_ERR_HIP; break; }
                 if (plan->dtype == LFA_F64)
                     status = run_svd_layer<double>(plan, d, W[i], nullptr, sigma[i],
                                                    wu ? U[i] : nullptr, wv ? V[i] : nullptr,
-                                                   nullptr, region, nullptr, 0, 0, st);
+                                                   nullptr, region, nullptr, 0, 0, st,
+                                                   plan->canon_dev + plan->canon_off[i]);
                 else
                     status = run_svd_layer<float>(plan, d, W[i], nullptr, sigma[i],
                                                   wu ? U[i] : nullptr, wv ? V[i] : nullptr,
-                                                  nullptr, region, nullptr, 0, 0, st);
+                                                  nullptr, region, nullptr, 0, 0, st,
+                                                  plan->canon_dev + plan->canon_off[i]);
                 if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
                     status = LFA_ERR_HIP;
                     break;
@@ -825,6 +890,7 @@ int lfa_autotune(lfa_plan* plan, const void* const* W, void* const* sigma, void*
                 best_d = d;
             }
         }
+        best_d.num_canon = base.num_canon;
         plan->desc[i] = best_d;
     }
     (void)hipEventDestroy(e0);

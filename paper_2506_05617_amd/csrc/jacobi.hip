@@ -283,8 +283,8 @@ __device__ int jacobi(const LayerDesc& d, const Shared<R>& s, int max_sweeps, do
 // Norms, sort, normalisation, completion of zero columns, outputs.
 // ---------------------------------------------------------------------------
 template <typename R, int L>
-__device__ void finish(const SvdArgs<R>& a, const Shared<R>& s, int out_idx, int sweeps,
-                       bool converged) {
+__device__ void finish(const SvdArgs<R>& a, const Shared<R>& s, int out_idx, int mirror,
+                       int sweeps, bool converged) {
     const LayerDesc& d = a.d;
     const int tid = threadIdx.x, nt = blockDim.x;
     const int lane = tid & (L - 1), group = tid / L, ngroups = nt / L;
@@ -319,10 +319,12 @@ __device__ void finish(const SvdArgs<R>& a, const Shared<R>& s, int out_idx, int
 
     const int r = N;
     R* sig_out = a.sigma + (size_t)out_idx * r;
+    R* sig_mir = mirror >= 0 ? a.sigma + (size_t)mirror * r : nullptr;
     bool bad = false;
     for (int c = tid; c < r; c += nt) {
         const R v = s.sig[s.perm[c]];
         sig_out[c] = v;
+        if (sig_mir) sig_mir[c] = v;
         bad |= !isfinite(v);
     }
     const bool want_left = d.transposed ? (a.V != nullptr) : (a.U != nullptr);
@@ -409,16 +411,22 @@ __device__ void finish(const SvdArgs<R>& a, const Shared<R>& s, int out_idx, int
         }
         // write: out[theta][i][c] = G[perm[c]][i]
         cplx<R>* out = (d.transposed ? a.V : a.U) + (size_t)out_idx * M * r;
+        cplx<R>* mir = mirror >= 0 ? (d.transposed ? a.V : a.U) + (size_t)mirror * M * r : nullptr;
         for (int e = tid; e < M * r; e += nt) {
             const int i = e / r, c = e - (e / r) * r;
-            out[e] = G[(size_t)s.perm[c] * ldg + i];
+            const cplx<R> v = G[(size_t)s.perm[c] * ldg + i];
+            out[e] = v;
+            if (mir) mir[e] = {v.x, -v.y};
         }
     }
     if (want_right) {
         cplx<R>* out = (d.transposed ? a.U : a.V) + (size_t)out_idx * N * r;
+        cplx<R>* mir = mirror >= 0 ? (d.transposed ? a.U : a.V) + (size_t)mirror * N * r : nullptr;
         for (int e = tid; e < N * r; e += nt) {
             const int i = e / r, c = e - (e / r) * r;
-            out[e] = Q[(size_t)s.perm[c] * ldv + i];
+            const cplx<R> v = Q[(size_t)s.perm[c] * ldv + i];
+            out[e] = v;
+            if (mir) mir[e] = {v.x, -v.y};
         }
     }
     if (a.info) {
@@ -432,32 +440,27 @@ __device__ void finish(const SvdArgs<R>& a, const Shared<R>& s, int out_idx, int
     __syncthreads();
 }
 
-// Symbol `theta`; outputs at position `out_idx` of sigma/U/V.
+// Work item `item` (see target_of).
 template <typename R, int L>
-__device__ void svd_one(const SvdArgs<R>& a, char* lds, int theta, int out_idx, char* gslot) {
+__device__ void svd_one(const SvdArgs<R>& a, char* lds, int item, char* gslot) {
+    const Target tg = target_of(a, item);
+    const int theta = tg.theta;
     const bool acc = (a.d.transposed ? a.U : a.V) != nullptr;
     const Shared<R> s = carve<R>(lds, a.d, acc, gslot);
     load_symbol<R>(a, s, theta);
     __syncthreads();
     bool converged;
     const int sweeps = jacobi<R, L>(a.d, s, a.max_sweeps, a.tol, converged);
-    finish<R, L>(a, s, out_idx, sweeps, converged);
+    finish<R, L>(a, s, tg.out, tg.mirror, sweeps, converged);
 }
 
 template <typename R, int L>
 __global__ void __launch_bounds__(1024) svd_kernel(SvdArgs<R> a) {
     extern __shared__ __align__(16) char lds[];
     char* gslot = a.gws ? a.gws + (size_t)blockIdx.x * a.slot_bytes : nullptr;
-    const int count = a.theta_list ? a.theta_count : a.d.num_symbols;
-    for (int item = blockIdx.x; item < count; item += gridDim.x) {
-        // with a symbol list, outputs are compact: entry `item` of the list
-        int theta = item;
-        if (a.theta_list) {
-            const int32_t* e = a.theta_list + (size_t)item * a.theta_stride;
-            theta = a.theta_stride >= 2 ? e[0] * a.d.m + e[1] : e[0];
-        }
-        svd_one<R, L>(a, lds, theta, item, gslot);
-    }
+    // with a symbol list, outputs are compact (entry `item` of the list)
+    const int count = item_count(a);
+    for (int item = blockIdx.x; item < count; item += gridDim.x) svd_one<R, L>(a, lds, item, gslot);
 }
 
 // Dynamic LDS above 64 KiB needs an explicit per-kernel opt-in.
@@ -515,13 +518,13 @@ __global__ void __launch_bounds__(256) persistent_kernel(PersistentArgs<R> pa_ar
         const SvdArgs<R>& a = pa.layer[w.layer];
         char* gslot = a.gws ? a.gws + (size_t)blockIdx.x * a.slot_bytes : nullptr;
         switch (a.d.L) {
-            case 1: svd_one<R, 1>(a, lds, w.theta, w.theta, gslot); break;
-            case 2: svd_one<R, 2>(a, lds, w.theta, w.theta, gslot); break;
-            case 4: svd_one<R, 4>(a, lds, w.theta, w.theta, gslot); break;
-            case 8: svd_one<R, 8>(a, lds, w.theta, w.theta, gslot); break;
-            case 16: svd_one<R, 16>(a, lds, w.theta, w.theta, gslot); break;
-            case 32: svd_one<R, 32>(a, lds, w.theta, w.theta, gslot); break;
-            default: svd_one<R, 64>(a, lds, w.theta, w.theta, gslot); break;
+            case 1: svd_one<R, 1>(a, lds, w.theta, gslot); break;
+            case 2: svd_one<R, 2>(a, lds, w.theta, gslot); break;
+            case 4: svd_one<R, 4>(a, lds, w.theta, gslot); break;
+            case 8: svd_one<R, 8>(a, lds, w.theta, gslot); break;
+            case 16: svd_one<R, 16>(a, lds, w.theta, gslot); break;
+            case 32: svd_one<R, 32>(a, lds, w.theta, gslot); break;
+            default: svd_one<R, 64>(a, lds, w.theta, gslot); break;
         }
     }
 }
@@ -535,6 +538,7 @@ __global__ void fill_i32_kernel(int32_t* p, int32_t v, long long n) {
 }  // namespace
 
 size_t lds_bytes_for(const LayerDesc& d, bool accumulate, int elem_bytes) {
+    if (d.kind == 1) return wave_lds_bytes_for(d.wave_nc, d.wave_ml, elem_bytes);
     const int cb = 2 * elem_bytes;
     size_t b = (size_t)cb * kMaxTaps + (size_t)elem_bytes * 64 +
                (size_t)elem_bytes * ((d.N + 3) & ~3) + 2 * sizeof(int) * ((d.N + 3) & ~3);

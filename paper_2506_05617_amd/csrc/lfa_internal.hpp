@@ -31,8 +31,46 @@ struct LayerDesc {
     int storage;       // Storage
     int ldg, ldv;      // leading dimensions (elements) of G and of the accumulator
     int num_symbols;   // n*m
+    int num_canon;     // frequencies with index <= that of their mirror (-k)
+    int kind;          // 0: lane-group kernel (LDS/global), 1: register (wave) kernel
+    int wave_nc;       // wave kernel: padded column count (power of two)
+    int wave_ml;       // wave kernel: lanes per symbol (16, 32 or 64)
     long long sym_offset;   // first symbol of this layer in the plan's work list
 };
+
+// Work item -> (frequency decomposed, output position, mirror output or -1).
+// Real weights give A_{-k} = conj(A_k): sigma(-k) = sigma(k), U_{-k} =
+// conj(U_k), V_{-k} = conj(V_k), so one symbol per conjugate pair is enough.
+struct Target {
+    int theta, out, mirror;
+};
+
+template <typename A>
+__host__ __device__ inline int item_count(const A& a) {
+    return a.theta_list ? a.theta_count : (a.canon ? a.d.num_canon : a.d.num_symbols);
+}
+
+template <typename A>
+__device__ inline Target target_of(const A& a, int item) {
+    Target t;
+    if (a.theta_list) {
+        const int32_t* e = a.theta_list + (size_t)item * a.theta_stride;
+        t.theta = a.theta_stride >= 2 ? e[0] * a.d.m + e[1] : e[0];
+        t.out = item;
+        t.mirror = -1;
+    } else if (a.canon) {
+        t.theta = a.canon[item];
+        t.out = t.theta;
+        const int p = t.theta / a.d.m, q = t.theta - (t.theta / a.d.m) * a.d.m;
+        const int mi = ((a.d.n - p) % a.d.n) * a.d.m + (a.d.m - q) % a.d.m;
+        t.mirror = mi != t.theta ? mi : -1;
+    } else {
+        t.theta = item;
+        t.out = item;
+        t.mirror = -1;
+    }
+    return t;
+}
 
 // One item of the persistent work list: a (layer, first symbol) pair.
 struct WorkItem {
@@ -60,6 +98,8 @@ struct SvdArgs {
     const double* tw;            // twiddle table, (re, im) pairs
     char* gws;                   // global working storage, one slot per block
     long long slot_bytes;        // bytes per slot
+    const int32_t* canon;        // optional: canonical frequencies (one per conjugate pair);
+                                 // outputs are also written for the mirror frequency
     const int32_t* theta_list;   // optional: symbol indices to process
     int theta_stride;            // element stride in theta_list (3 for (p,q,j) triples)
     int theta_count;             // number of symbols to process
@@ -69,7 +109,11 @@ struct SvdArgs {
 
 size_t lds_bytes_for(const LayerDesc& d, bool accumulate, int elem_bytes);
 
+size_t wave_lds_bytes_for(int nc, int ml, int elem_bytes);
+
 // Launchers (each returns a hipError_t).
+hipError_t launch_wave_svd_f32(const SvdArgs<float>& a, int grid, hipStream_t s);
+hipError_t launch_wave_svd_f64(const SvdArgs<double>& a, int grid, hipStream_t s);
 hipError_t launch_svd_f32(const SvdArgs<float>& a, int grid, size_t lds, hipStream_t s);
 hipError_t launch_svd_f64(const SvdArgs<double>& a, int grid, size_t lds, hipStream_t s);
 

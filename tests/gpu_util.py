@@ -25,16 +25,18 @@ def sigma_gate(dtype):
 
 
 def ortho_gate(M, dtype):
-    """Loss of orthogonality allowed for U and V columns: the Jacobi stopping
-    threshold (M times the unit roundoff, relative) twice, plus slack for the
-    rounding of the accumulated rotations."""
+    """Loss of orthogonality allowed for U and V columns: twice the Jacobi
+    stopping threshold (2 sqrt(M) u, relative), plus the rounding of the
+    accumulated rotations (a few hundred rotations per column, u each)."""
     eps = EPS32 if dtype == torch.float32 else EPS64
-    return 2 * M * eps + (1e-6 if dtype == torch.float32 else 1e-14)
+    return 4 * np.sqrt(max(M, 16)) * eps + 64 * eps * np.sqrt(M)
 
 
 def resid_gate(M, dtype):
+    """||A V - U S||_F / ||A||_F: rounding of the rotations applied to G and V
+    (about u per rotation, a few hundred per column)."""
     eps = EPS32 if dtype == torch.float32 else EPS64
-    return 4 * M * eps + (1e-6 if dtype == torch.float32 else 1e-14)
+    return 64 * eps * np.sqrt(M) + 4 * np.sqrt(max(M, 16)) * eps
 
 
 def check_vectors(A, S, U, V, dtype, tag=""):
