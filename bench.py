@@ -2,19 +2,27 @@
 
 Headline (``value``): singular values per second, with left and right
 singular vectors, for the 64 -> 64 channel, 3x3, 64x64-grid layer
-(4096 symbols of 64x64): one step = assembly + Jacobi SVD + sort/normalise
-(one lfa_svd call; weights resident in HBM, outputs preallocated).
+(4096 symbols of 64x64): one step = symbol assembly + Jacobi SVD + sort /
+normalise / write of sigma, U, V (one lfa_svd call; weights resident in HBM,
+outputs preallocated).
 
-Also reported:
-  * the sigma-gradient throughput (layers/s) of the 12-layer ResNet-18-shaped
-    stack, batched (persistent launch + HIP graph) vs plain (one launch per
-    layer and stage, no graph), loss = sum of the top-8 sigma per layer;
-  * roofline of the dominant kernel (the Jacobi SVD kernel): algorithmic
-    FLOP per launch (measured sweeps x pairs x per-pair work) / launch time;
-  * the FP64 oracle (NumPy/LAPACK) timed on the host cores on the same
-    layer, and the sigma error of the GPU result against it.
+Also reported (``workloads``):
+  * 16 -> 16 channels on a 32x32 grid in FP64 mode (sigma, U, V);
+  * 256 -> 512 channels on a 32x32 grid (1024 symbols of 512x256), sigma-only
+    and with U, V, plus the instance with rank-one taps;
+  * the 12-layer ResNet-18-shaped stack: sigma-gradient throughput in layers/s
+    (forward sigma of every layer, top-8 per layer, dL/dW), batched (one
+    persistent launch + HIP graph) and plain (one launch per layer and stage);
+  * 64 -> 64 channels, 7x7 kernel, 224x224 grid (50176 symbols), sigma-only,
+    with FP32 fused assembly and with split-BF16 matrix-core assembly
+    (3 and 6 products), and the assembly kernel alone against HBM bandwidth.
+The roofline of the headline's dominant kernel (the fused SVD kernel) is
+algorithmic FLOP per launch (sweeps measured by the kernel x pairs x
+per-pair work) over the launch time measured with HIP events.  The FP64
+oracle (NumPy/LAPACK) is timed on the host cores on the headline layer; the
+same leg reports every workload's sigma error against the oracle.
 
-Usage: python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu] [--no-stack]
+Usage: python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu] [--quick]
 """
 
 from __future__ import annotations
@@ -35,21 +43,23 @@ import paper_2506_05617_amd as lfa  # noqa: E402
 import workloads  # noqa: E402
 
 METRIC = "singular values/s (with vectors) and σ-grad layers/s vs plain at σ rel err ≤1e-5"
-PEAK_FP32_VECTOR_TFLOPS = 157.3
-HBM_PEAK_GBS = 8000.0
+PEAK_FP32_VECTOR_TFLOPS = 157.3     # MI355X, packed FP32 (this build issues unpacked FP32: half)
+PEAK_HBM_GBS = 8000.0
 
 
-def jacobi_flops(layer: workloads.Layer, sum_sweeps: int, vectors: bool) -> float:
-    """Algorithmic FLOP of the one-sided Jacobi sweeps of one layer: per
-    column pair and sweep, three inner products over the M rows (16 M) and
-    the complex rotation of two columns of G (20 M) and, with vectors, of the
-    accumulator (20 N); N(N-1)/2 pairs per sweep."""
+def jacobi_flops(layer, sum_sweeps: int, vectors: bool) -> float:
+    """Algorithmic FLOP of the one-sided Jacobi sweeps: per column pair and
+    sweep, three inner products over the M rows (16 M) and the complex
+    rotation of two columns of G (20 M) and, with vectors, of the
+    accumulator (20 N); N(N-1)/2 pairs per sweep.  sum_sweeps counts the
+    sweeps of the symbols actually decomposed."""
     M, N = max(layer.c_out, layer.c_in), min(layer.c_out, layer.c_in)
     per_pair = 36.0 * M + (20.0 * N if vectors else 0.0)
     return sum_sweeps * N * (N - 1) / 2.0 * per_pair
 
 
-def time_steps(fn, steps, warmup, stream=None):
+def event_times(fn, steps, warmup):
+    """Per-call times from HIP events on the current stream, and wall time."""
     for _ in range(warmup):
         fn()
     torch.cuda.synchronize()
@@ -62,33 +72,28 @@ def time_steps(fn, steps, warmup, stream=None):
         ends[i].record()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    ev = [s.elapsed_time(e) for s, e in zip(starts, ends)]
-    return wall, ev
+    return wall, [s.elapsed_time(e) for s, e in zip(starts, ends)]
 
 
-def bench_single_layer(args, dev):
-    L, W = workloads.single_layer_64()
+def run_layer(L, W, dev, vectors, steps, warmup, asm=None, dtype=torch.float32):
     Wt = torch.from_numpy(W).to(dev)
     spec = lfa.LayerSpec(L.c_out, L.c_in, L.kh, L.kw, L.n, L.m)
-    plan = lfa.Plan([spec], torch.float32, want_u=True, want_v=True)
-    S, U, V = plan._alloc_outputs(dev, True, True)
+    plan = lfa.Plan([spec], dtype, want_u=vectors, want_v=vectors, asm=asm)
+    S, U, V = plan._alloc_outputs(dev, vectors, vectors)
     info = torch.zeros(1, 4, dtype=torch.int32, device=dev)
-    out = (S, U, V)
 
     def step():
-        plan.svd([Wt], info=info, out=out)
+        plan.svd([Wt], info=info, out=(S, U, V))
 
-    wall, ev = time_steps(step, args.steps, args.warmup)
-    torch.cuda.synchronize()
+    wall, ev = event_times(step, steps, warmup)
     inf = info.cpu().numpy()[0]
-    ms = wall * 1e3 / args.steps
-    kernel_ms = float(np.mean(ev))
-    flops = jacobi_flops(L, int(inf[2]), True)
-    return dict(layer=L, W=W, S=S[0], U=U[0], V=V[0], ms=ms, kernel_ms=kernel_ms, info=inf,
-                flops=flops, plan=plan)
+    ms = wall * 1e3 / steps
+    return dict(layer=L, W=W, S=S[0], U=U[0], V=V[0], ms=ms, kernel_ms=float(np.mean(ev)),
+                info=[int(x) for x in inf], sigma_per_s=L.num_sigma / (ms * 1e-3),
+                flops=jacobi_flops(L, int(inf[2]), vectors), plan=plan)
 
 
-def bench_stack(args, dev, steps):
+def bench_stack(dev, steps):
     layers, Ws = workloads.resnet18_stack()
     specs = [lfa.LayerSpec(l.c_out, l.c_in, l.kh, l.kw, l.n, l.m) for l in layers]
     plan = lfa.Plan(specs, torch.float32)
@@ -97,11 +102,13 @@ def bench_stack(args, dev, steps):
     ones = torch.ones(len(specs), k, device=dev)
     S, _, _ = plan._alloc_outputs(dev, False, False)
     info = torch.zeros(len(specs), 4, dtype=torch.int32, device=dev)
+    none = [None] * len(S)
+    res = {}
 
     def plain():
-        plan.svd(Wt, persistent=False, info=info, out=(S, [None] * len(S), [None] * len(S)))
+        plan.svd(Wt, persistent=False, info=info, out=(S, none, none))
         vals, idx = plan.topk(S, k)
-        plan.sigma_grad(Wt, idx, ones)
+        res["plain"] = (vals, idx, plan.sigma_grad(Wt, idx, ones))
 
     graph = lfa.GraphStep(plan, Wt, k)
 
@@ -109,24 +116,53 @@ def bench_stack(args, dev, steps):
         graph.replay()
         torch.cuda.current_stream().wait_stream(graph.stream)
 
-    wall_p, _ = time_steps(plain, steps, 1)
-    wall_b, _ = time_steps(batched, steps, 1)
+    wall_p, _ = event_times(plain, steps, 1)
+    wall_b, _ = event_times(batched, steps, 1)
     nl = len(specs)
-    return dict(plain_layers_per_s=nl * steps / wall_p, batched_layers_per_s=nl * steps / wall_b,
+    return dict(layers=layers, Ws=Ws, graph=graph, plain_out=res["plain"],
+                plain_layers_per_s=nl * steps / wall_p, batched_layers_per_s=nl * steps / wall_b,
                 plain_ms=wall_p * 1e3 / steps, batched_ms=wall_b * 1e3 / steps)
 
 
-def cpu_baseline(res):
-    """The FP64 oracle on the host cores over all 4096 symbols of the layer
-    (assembly + SVD with vectors), thread pool over frequency chunks with one
-    BLAS thread each; also the sigma error of the GPU result against it."""
+def bench_assembly(dev, steps, asm):
+    """The assembly kernel alone on the 224x224, 7x7 layer: 1.64 GB of
+    symbols written; HBM-bound."""
+    L, W, _ = workloads.large_grid_7x7()
+    Wt = torch.from_numpy(W).to(dev)
+    plan = lfa.Plan([lfa.LayerSpec(L.c_out, L.c_in, L.kh, L.kw, L.n, L.m)], asm=asm)
+    out = {}
+
+    def step():
+        out["A"] = plan.symbols([Wt])[0]
+
+    step()
+    torch.cuda.synchronize()
+    A = out["A"]
+    # reuse the output buffer: time the kernel through the C ABI directly
+    w_arr, k0 = lfa._lib.ptr_array([Wt.data_ptr()])
+    a_arr, k1 = lfa._lib.ptr_array([A.data_ptr()])
+    lib = plan.lib
+
+    def launch():
+        lfa._lib.check(lib.lfa_symbols(plan.handle, w_arr, a_arr, lfa.lfa._stream_ptr()), "lfa_symbols")
+
+    _, ev = event_times(launch, steps, 2)
+    ms = float(np.mean(ev))
+    bytes_moved = A.numel() * A.element_size() + W.nbytes
+    return dict(ms=ms, gbs=bytes_moved / (ms * 1e-3) / 1e9, bytes=bytes_moved, A=A, L=L, W=W)
+
+
+def cpu_leg(head, extra):
+    """FP64 oracle on the host: timed on the headline layer (all 4096 symbols,
+    sigma+U+V, thread pool over frequency chunks, one BLAS thread each), and
+    used to report the sigma error of every GPU result."""
     from concurrent.futures import ThreadPoolExecutor
 
     from threadpoolctl import threadpool_limits
 
     import oracle
 
-    L, W = res["layer"], res["W"]
+    L, W = head["layer"], head["W"]
     cores = min(os.cpu_count() or 1, 16)
     pp, qq = np.meshgrid(np.arange(L.n), np.arange(L.m), indexing="ij")
     freqs = np.stack([pp.ravel(), qq.ravel()], axis=1)
@@ -136,19 +172,61 @@ def cpu_baseline(res):
     def work(fr):
         return fr, oracle.lfa_svd(W64, L.n, L.m, compute_uv=True, freqs=fr)
 
+    reps = 3
     with threadpool_limits(limits=1):
         t0 = time.perf_counter()
-        with ThreadPoolExecutor(max_workers=cores) as ex:
-            parts = list(ex.map(work, chunks))
-        secs = time.perf_counter() - t0
+        for _ in range(reps):
+            with ThreadPoolExecutor(max_workers=cores) as ex:
+                parts = list(ex.map(work, chunks))
+        secs = (time.perf_counter() - t0) / reps
     S_ref = np.zeros((L.n, L.m, L.r))
     for fr, (s, _, _) in parts:
         S_ref[fr[:, 0], fr[:, 1]] = s
-    err = oracle.sigma_error(res["S"].cpu().numpy(), S_ref)
+    errors = {"single_layer_64": oracle.sigma_error(head["S"].cpu().numpy(), S_ref)}
+
+    rng = np.random.default_rng(0)
+
+    def sampled(name, res, nsamp=64):
+        Lx, Wx = res["layer"], res["W"]
+        fr = np.stack([rng.integers(0, Lx.n, nsamp), rng.integers(0, Lx.m, nsamp)], axis=1)
+        ref = oracle.lfa_svd(Wx.astype(np.float64), Lx.n, Lx.m, freqs=fr)
+        got = res["S"].cpu().numpy()[fr[:, 0], fr[:, 1]]
+        errors[name] = oracle.sigma_error(got, ref)
+        return got, ref
+
+    with threadpool_limits(limits=cores):
+        for name, res in extra.items():
+            if name == "stack":
+                st = res
+                vals, idx, dW = st["plain_out"]
+                idx_np = idx.cpu().numpy()
+                gerr = 0.0
+                for li, l in enumerate(st["layers"]):
+                    ref = oracle.sigma_grad(st["Ws"][li].astype(np.float64), l.n, l.m, idx_np[li])
+                    gerr = max(gerr, float(np.linalg.norm(dW[li].cpu().numpy() - ref) / np.linalg.norm(ref)))
+                    sref = oracle.lfa_svd(st["Ws"][li].astype(np.float64), l.n, l.m)
+                    ov, _ = oracle.topk(sref, 8)
+                    errors[f"stack_top8_layer{li}"] = float(np.max(np.abs(vals[li].cpu().numpy() - ov)) / ov[0])
+                errors["stack_grad_rel_frobenius"] = gerr
+            elif name.startswith("rank_one"):
+                got, ref = sampled(name, res)
+                errors[name + "_zero_sigma_max_rel"] = float(np.max(got[..., 9:] / got[..., :1]))
+                W64 = res["W"].astype(np.float64)
+                Sall = res["S"].cpu().numpy().astype(np.float64)
+                Lx = res["layer"]
+                errors[name + "_parseval_rel"] = float(abs(np.sum(Sall ** 2) / (Lx.n * Lx.m * np.sum(W64 ** 2)) - 1))
+            elif name.startswith("assembly"):
+                fr = np.stack([rng.integers(0, res["L"].n, 32), rng.integers(0, res["L"].m, 32)], axis=1)
+                ref = oracle.symbols(res["W"].astype(np.float64), res["L"].n, res["L"].m, fr)
+                got = res["A"].cpu().numpy()[fr[:, 0], fr[:, 1]]
+                scale = np.max(np.sum(np.abs(res["W"].astype(np.float64)), axis=(2, 3)))
+                errors[name + "_symbol_rel"] = float(np.max(np.abs(got - ref)) / scale)
+            else:
+                sampled(name, res)
     nsig = L.n * L.m * L.r
     return dict(value=nsig / secs, unit="singular values/s", cores=cores, kind="oracle",
                 sample=f"all {L.n * L.m} symbols of the 64x64 layer, sigma+U+V, complex128 "
-                       f"NumPy/LAPACK, {cores} threads ({secs:.2f} s)"), err
+                       f"NumPy/LAPACK, {cores} threads, mean of {reps} passes ({secs:.3f} s each)"), errors
 
 
 def main():
@@ -157,8 +235,7 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--no-stack", action="store_true")
-    ap.add_argument("--stack-steps", type=int, default=3)
+    ap.add_argument("--quick", action="store_true", help="headline workload only")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the LFA SVD shards over frequencies, but this build "
@@ -168,19 +245,17 @@ def main():
     torch.cuda.set_device(dev)
     lfa.load()
 
-    res = bench_single_layer(args, dev)
-    L = res["layer"]
-    nsig = L.n * L.m * L.r
-    value = nsig / (res["ms"] * 1e-3)
-    achieved = res["flops"] / (res["kernel_ms"] * 1e-3) / 1e12
+    L, W = workloads.single_layer_64()
+    head = run_layer(L, W, dev, True, args.steps, args.warmup)
+    achieved = head["flops"] / (head["kernel_ms"] * 1e-3) / 1e12
     line = {
         "metric": METRIC,
-        "value": value,
+        "value": head["sigma_per_s"],
         "unit": "singular values/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": res["ms"],
+        "ms_per_step": head["ms"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -189,22 +264,55 @@ def main():
         "config": {"workload": "single conv layer 64->64, 3x3, 64x64 periodic grid, "
                                "4096 symbols 64x64, sigma+U+V",
                    "c_in": 64, "c_out": 64, "kernel": 3, "n": 64, "symbols": 4096},
-        "sweeps": {"sum": int(res["info"][2]), "max": int(res["info"][1]),
-                   "nonconverged": int(res["info"][0])},
-        "roofline": {"bound": "alu", "kernel": "svd_kernel (fused assembly + Jacobi + post)",
+        "sweeps": {"sum": head["info"][2], "max": head["info"][1], "nonconverged": head["info"][0]},
+        "roofline": {"bound": "alu", "kernel": "wave_svd_kernel<float,64,64> (fused assembly + Jacobi + sort/write)",
                      "achieved": achieved, "peak": PEAK_FP32_VECTOR_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP32_VECTOR_TFLOPS, "traffic": None,
-                     "kernel_ms": res["kernel_ms"]},
+                     "kernel_ms": head["kernel_ms"]},
     }
-    if not args.no_stack:
-        st = bench_stack(args, dev, args.stack_steps)
-        line["sigma_grad_stack"] = {
-            "workload": "12 ResNet-18-shaped 3x3 layers, loss = sum of top-8 sigma per layer",
-            **st, "speedup_batched_vs_plain": st["batched_layers_per_s"] / st["plain_layers_per_s"]}
+    extra = {}
+    if not args.quick:
+        reps = 3
+        wl = {}
+        L1, W1 = workloads.single_layer_16()
+        r = run_layer(L1, W1, dev, True, reps * 3, 1, dtype=torch.float64)
+        extra["single_layer_16_fp64"] = r
+        wl["single_layer_16_fp64"] = dict(ms=r["ms"], sigma_per_s=r["sigma_per_s"], sweeps=r["info"][1:3],
+                                          vectors=True, dtype="f64")
+        L3, W3 = workloads.rectangular_256_512()
+        for vec in (False, True):
+            r = run_layer(L3, W3, dev, vec, reps, 1)
+            key = "rectangular_512x256" + ("_uv" if vec else "")
+            extra[key] = r
+            wl[key] = dict(ms=r["ms"], sigma_per_s=r["sigma_per_s"], sweeps=r["info"][1:3], vectors=vec,
+                           tflops=r["flops"] / (r["kernel_ms"] * 1e-3) / 1e12)
+        L3r, W3r = workloads.rank_one_taps()
+        r = run_layer(L3r, W3r, dev, True, reps, 1)
+        extra["rank_one_512x256"] = r
+        wl["rank_one_512x256_uv"] = dict(ms=r["ms"], sigma_per_s=r["sigma_per_s"], sweeps=r["info"][1:3])
+        st = bench_stack(dev, reps)
+        extra["stack"] = st
+        wl["resnet18_stack_sigma_grad"] = {
+            "layers": 12, "loss": "sum of top-8 sigma per layer",
+            "plain_layers_per_s": st["plain_layers_per_s"], "batched_layers_per_s": st["batched_layers_per_s"],
+            "plain_ms": st["plain_ms"], "batched_ms": st["batched_ms"],
+            "speedup_batched_vs_plain": st["batched_layers_per_s"] / st["plain_layers_per_s"]}
+        L5, W5, _ = workloads.large_grid_7x7()
+        for asm in (None, "bf16x2", "bf16x3"):
+            r = run_layer(L5, W5, dev, False, reps, 1, asm=asm)
+            key = "large_grid_7x7_" + (asm or "fp32")
+            extra[key] = r
+            wl[key] = dict(ms=r["ms"], sigma_per_s=r["sigma_per_s"], sweeps=r["info"][1:3], vectors=False)
+        for asm in ("valu", "mfma", "bf16x3"):
+            a = bench_assembly(dev, 5, asm)
+            extra["assembly_" + asm] = a
+            wl["assembly_224x224_7x7_" + asm] = dict(ms=a["ms"], hbm_gbs=a["gbs"],
+                                                     frac_of_hbm_peak=a["gbs"] / PEAK_HBM_GBS)
+        line["workloads"] = wl
     if not args.no_cpu:
-        cb, err = cpu_baseline(res)
+        cb, errors = cpu_leg(head, extra)
         line["cpu_baseline"] = cb
-        line["sigma_error_vs_oracle"] = err
+        line["sigma_error_vs_oracle"] = errors
     print(json.dumps(line), flush=True)
 
 

@@ -46,6 +46,8 @@ constexpr int kPersistentGrid = 1024;          // upper bound of the persistent 
 constexpr int kPersistentThreads = 256;
 constexpr size_t kPersistentLdsCap = 72 * 1024;
 constexpr int kMaxTopk = 64;
+constexpr int kBlockCols = 8;                     // column block of the blocked kernel
+constexpr size_t kCounterBytes = 256 * ((4 * (4 * 1024 + 4) + 255) / 256);   // team counters
 constexpr int kMaxSweeps = 40;
 
 size_t align_up(size_t x, size_t a = kAlign) { return (x + a - 1) / a * a; }
@@ -87,6 +89,7 @@ struct lfa_plan {
     double* tw_dev = nullptr;
     WorkItem* items_dev = nullptr;
     int32_t* canon_dev = nullptr;
+    int num_cus = 0;
 };
 
 struct lfa_graph {
@@ -137,6 +140,13 @@ LayerDesc make_desc(const lfa_layer& l, int tw_n, int tw_m, bool acc, int eb, si
         d.wave_ml = std::max(16, pow2ceil(d.M));
         d.wave_nc = std::max(4, pow2ceil(d.N));
         d.threads = acc ? 128 : 64;
+    } else if (allow_wave && !threads_override && !L_override) {
+        // blocked kernel: one thread per row, column blocks in registers,
+        // working matrices in a global slot
+        d.kind = 2;
+        d.threads = (d.M + 63) / 64 * 64;
+        d.storage = kGlobal;
+        return d;
     }
     if (lds_bytes_for(d, acc, eb) > lds_cap) d.storage = kGlobal;
     d.sym_offset = 0;
@@ -209,7 +219,8 @@ size_t workspace_bytes(const lfa_plan& p) {
         pslot = std::max(pslot, slot_bytes(d, acc, eb));
     }
     need = std::max(need, (size_t)kPersistentGrid * pslot);
-    return kAlign + align_up(need);
+    // team counters of the blocked kernel precede its slots
+    return kAlign + kCounterBytes + align_up(need);
 }
 
 int validate_layer(const lfa_layer& l) {
@@ -239,6 +250,7 @@ int ensure_device(lfa_plan* p) {
     hipDeviceProp_t prop;
     HIP_TRY(hipGetDeviceProperties(&prop, dev));
     if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0) return LFA_ERR_NO_DEVICE;
+    p->num_cus = prop.multiProcessorCount;
     HIP_TRY(hipMalloc(&p->tw_dev, p->tw_host.size() * sizeof(double)));
     HIP_TRY(hipMemcpy(p->tw_dev, p->tw_host.data(), p->tw_host.size() * sizeof(double),
                       hipMemcpyHostToDevice));
@@ -300,6 +312,28 @@ int run_svd_layer(const lfa_plan* p, const LayerDesc& d, const void* W, const vo
     const int grid = svd_grid(d, count);
     a.slot_bytes = (long long)slot_bytes(d, acc, sizeof(R));
     a.gws = d.storage == kGlobal ? region : nullptr;
+    if (d.kind == 2) {
+        // Teams of W work-groups share one symbol's block pairs when there
+        // are too few symbols to fill the device; W > 1 requires every
+        // work-group of the grid to be resident at once.
+        // Each team barrier writes back the L2 of the arriving work-group, so
+        // teams pay off only while they give work-groups CUs of their own:
+        // W is about (CUs / symbols), never more than the grid can hold.
+        const int resident = block_resident(d, acc, sizeof(R));
+        const int NB = (d.N + kBlockCols - 1) / kBlockCols, NBP = NB + (NB & 1);
+        int W = 1, teams = std::min(count, kGlobalGrid);
+        const int cap = std::min(resident, p->num_cus);
+        if (cap >= 2 && 2 * count <= cap) {
+            W = std::max(1, std::min(NBP / 2, cap / count));
+            teams = W > 1 ? std::min(count, cap / W) : teams;
+        }
+        int32_t* counters = reinterpret_cast<int32_t*>(region);
+        a.gws = region + kCounterBytes;
+        if constexpr (sizeof(R) == 4) e = launch_block_svd_f32(a, teams, W, counters, st);
+        else e = launch_block_svd_f64(a, teams, W, counters, st);
+        HIP_TRY(e);
+        return LFA_OK;
+    }
     const size_t lds = lds_bytes_for(d, acc, sizeof(R));
     if constexpr (sizeof(R) == 4) e = launch_svd_f32(a, grid, lds, st);
     else e = launch_svd_f64(a, grid, lds, st);
@@ -849,7 +883,7 @@ int lfa_autotune(lfa_plan* plan, const void* const* W, void* const* sigma, void*
         const LayerDesc base = plan->desc[i];
         const bool acc = accumulates(base, wu, wv);
         std::vector<LayerDesc> cands;
-        if (base.M <= 64) cands.push_back(make_desc(plan->layers[i], base.tw_n, base.tw_m, acc, eb, kLdsCap));
+        cands.push_back(make_desc(plan->layers[i], base.tw_n, base.tw_m, acc, eb, kLdsCap));
         for (int L = 1; L <= 64; L <<= 1) {
             if (L * kRowsPerLane < base.M) continue;
             if (L > 4 * base.L) continue;

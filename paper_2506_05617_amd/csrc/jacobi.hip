@@ -83,6 +83,7 @@ struct Shared {
     R* red;          // [64] scratch for block reductions
     cplx<R>* G;      // working matrix (LDS or global)
     cplx<R>* Q;      // rotation accumulator (LDS or global), or null
+    size_t small_end;   // LDS bytes used by the arrays above (G/Q excluded)
 };
 
 template <typename R>
@@ -107,6 +108,7 @@ __device__ __forceinline__ Shared<R> carve(char* lds, const LayerDesc& d, bool a
     s.flags = reinterpret_cast<int*>(p);
     p += sizeof(int) * 4;
     p = reinterpret_cast<char*>((reinterpret_cast<uintptr_t>(p) + 15) & ~uintptr_t(15));
+    s.small_end = (size_t)(p - lds);
     char* base = (d.storage == kLds) ? p : gslot;
     s.G = reinterpret_cast<cplx<R>*>(base);
     base += sizeof(cplx<R>) * (size_t)d.ldg * d.N;
@@ -454,6 +456,318 @@ __device__ void svd_one(const SvdArgs<R>& a, char* lds, int item, char* gslot) {
     finish<R, L>(a, s, tg.out, tg.mirror, sweeps, converged);
 }
 
+// ---------------------------------------------------------------------------
+// Blocked one-sided Jacobi for symbols with more than 64 rows.
+//
+// Thread t of the work-group owns row t of G (M x N, column-major in a global
+// slot) and row t of the accumulator Q (N x N): it is the only thread that
+// ever reads or writes those rows, so the global traffic of the sweeps needs
+// no synchronisation.  Columns are taken B at a time: a block pair (2B columns
+// of the thread's row, and of its Q row) sits in registers while its column
+// pairs are rotated, then goes back to the slot.
+//
+// One sweep visits every column pair exactly once:
+//  * intra pass: blocks (2i, 2i+1) are loaded together and the pairs inside
+//    each block are rotated by a round-robin of B-1 steps;
+//  * cross passes: a round-robin over the blocks (NB-1 outer steps); in a
+//    block pair (a, b), step t rotates (a_p, b_{(p+t) mod B}) for all p.
+// Inner products are reduced over rows by a per-wave LDS transpose and a sum
+// over the waves; one thread per pair computes the rotation.
+// ---------------------------------------------------------------------------
+constexpr int kBlk = 8;   // columns per block
+
+template <typename R>
+struct BlockLds {
+    R* wpart;        // [waves][64][4B+4]
+    R* wsum;         // [waves][4B]
+    quad<R>* prm;    // [B]
+    int* rflag;      // rotation made in this sweep
+};
+
+template <typename R>
+__device__ __forceinline__ BlockLds<R> carve_block(char* lds, size_t off) {
+    constexpr int B = kBlk, PST = 4 * B + 4;
+    const int nw = blockDim.x >> 6;
+    BlockLds<R> b;
+    R* p = reinterpret_cast<R*>(lds + ((off + 63) & ~size_t(63)));
+    b.wpart = p;
+    p += nw * 64 * PST;
+    b.wsum = p;
+    p += nw * 4 * B;
+    b.prm = reinterpret_cast<quad<R>*>(p);
+    b.rflag = reinterpret_cast<int*>(b.prm + B);
+    return b;
+}
+
+// Sum the per-row contributions q[p] (p < B pairs) over all rows and compute
+// the B rotations into bl.prm.  Contains two work-group barriers.
+template <typename R>
+__device__ __forceinline__ void block_reduce_rotate(const BlockLds<R>& bl, quad<R> (&q)[kBlk],
+                                                    double tol) {
+    constexpr int B = kBlk, PST = 4 * B + 4, Q = 4 * B, H = 64 / Q;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nw = blockDim.x >> 6;
+    R* wp = bl.wpart + wave * 64 * PST;
+#pragma unroll
+    for (int p = 0; p < B; ++p) *reinterpret_cast<quad<R>*>(wp + lane * PST + 4 * p) = q[p];
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    const int qi = lane % Q, h = lane / Q;
+    R sum = 0;
+#pragma unroll 8
+    for (int r = h * (64 / H); r < (h + 1) * (64 / H); ++r) sum += wp[r * PST + qi];
+#pragma unroll
+    for (int off = Q; off < 64; off <<= 1) sum += __shfl_xor(sum, off, 64);
+    if (lane < Q) bl.wsum[wave * Q + qi] = sum;
+    __syncthreads();
+    if (tid < B) {
+        R s0 = 0, s1 = 0, s2 = 0, s3 = 0;
+        for (int w = 0; w < nw; ++w) {
+            const R* ws = bl.wsum + w * Q + 4 * tid;
+            s0 += ws[0];
+            s1 += ws[1];
+            s2 += ws[2];
+            s3 += ws[3];
+        }
+        const quad<R> r = rotation<R>(s0, s1, s2, s3, tol);
+        bl.prm[tid] = r;
+        if (r.d != R(0)) *bl.rflag = 1;
+    }
+    __syncthreads();
+}
+
+template <typename R>
+__device__ __forceinline__ quad<R> pair_partials(cplx<R> x, cplx<R> y) {
+    quad<R> q;
+    q.a = fma(x.x, x.x, x.y * x.y);
+    q.b = fma(y.x, y.x, y.y * y.y);
+    q.c = fma(x.x, y.x, x.y * y.y);
+    q.d = fma(x.x, y.y, -x.y * y.x);
+    return q;
+}
+
+// Load / store block `blk` (columns blk*B ..) of this thread's row.
+template <typename R>
+__device__ __forceinline__ void load_block(const cplx<R>* base, int ld, int blk, int ncols, int row,
+                                           bool row_ok, cplx<R> (&x)[kBlk]) {
+#pragma unroll
+    for (int k = 0; k < kBlk; ++k) {
+        const int c = blk * kBlk + k;
+        x[k] = (row_ok && c < ncols) ? base[(size_t)c * ld + row] : cplx<R>{R(0), R(0)};
+    }
+}
+template <typename R>
+__device__ __forceinline__ void store_block(cplx<R>* base, int ld, int blk, int ncols, int row,
+                                            bool row_ok, const cplx<R> (&x)[kBlk]) {
+#pragma unroll
+    for (int k = 0; k < kBlk; ++k) {
+        const int c = blk * kBlk + k;
+        if (row_ok && c < ncols) base[(size_t)c * ld + row] = x[k];
+    }
+}
+
+// Team of W work-groups working on one symbol.  Counters live in device
+// memory, cleared before the launch; `target` counts the barriers passed.
+struct Team {
+    int member, W;
+    int32_t* bar;        // arrivals (monotonic)
+    int32_t* rot;        // work-groups that rotated, summed over the sweeps (monotonic)
+    int32_t* err;        // bit 1 set when a barrier timed out
+    int target;
+};
+
+// All W work-groups of the team arrive before any leaves; global writes
+// before the barrier are visible to every member after it (release/acquire
+// at agent scope).  The wait is bounded: on timeout the error bit is set and
+// this and every later barrier return at once, so no wave ever hangs.
+__device__ void team_barrier(Team& t) {
+    t.target += t.W;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __threadfence();
+        __hip_atomic_fetch_add(t.bar, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        int spins = 0;
+        while (__hip_atomic_load(t.bar, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < t.target) {
+            if (__hip_atomic_load(t.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & 2) break;
+            __builtin_amdgcn_s_sleep(4);
+            if (++spins > (1 << 24)) {
+                __hip_atomic_fetch_or(t.err, 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                break;
+            }
+        }
+        __threadfence();
+    }
+    __syncthreads();
+}
+
+template <typename R>
+__device__ void block_sweeps(const LayerDesc& d, const Shared<R>& s, const BlockLds<R>& bl,
+                             int max_sweeps, double tol, Team& team, int& sweeps_out,
+                             bool& conv_out) {
+    constexpr int B = kBlk;
+    const int tid = threadIdx.x;
+    const int member = team.member, W = team.W;
+    const int M = d.M, N = d.N;
+    const int NB = (N + B - 1) / B, NBP = NB + (NB & 1);
+    const bool grow = tid < M, qrow = s.Q != nullptr && tid < N;
+    cplx<R> ga[B], gb[B], va[B], vb[B];
+    quad<R> q[B];
+    int sweeps = 0;
+    bool converged = (N < 2);
+    while (!converged && sweeps < max_sweeps) {
+        if (tid == 0) *bl.rflag = 0;
+        __syncthreads();
+        // team: rotations counted before this sweep (all earlier increments
+        // happened before the barrier that ended the previous sweep)
+        const int rot_before =
+            W > 1 ? __hip_atomic_load(team.rot, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) : 0;
+        // ---- intra pass: pairs inside blocks 2i and 2i+1
+        for (int i = member; 2 * i < NB; i += W) {
+            const int ba = 2 * i, bb = 2 * i + 1;
+            load_block(s.G, d.ldg, ba, N, tid, grow, ga);
+            load_block(s.G, d.ldg, bb, N, tid, grow, gb);
+            if (s.Q) {
+                load_block(s.Q, d.ldv, ba, N, tid, qrow, va);
+                load_block(s.Q, d.ldv, bb, N, tid, qrow, vb);
+            }
+            for (int step = 0; step < B - 1; ++step) {
+#pragma unroll
+                for (int p = 0; p < B / 2; ++p) {
+                    q[p] = pair_partials(ga[p], ga[B - 1 - p]);
+                    q[B / 2 + p] = pair_partials(gb[p], gb[B - 1 - p]);
+                }
+                block_reduce_rotate<R>(bl, q, tol);
+#pragma unroll
+                for (int p = 0; p < B / 2; ++p) {
+                    const quad<R> ra = bl.prm[p], rb = bl.prm[B / 2 + p];
+                    rot_apply(ga[p], ga[B - 1 - p], ra.a, ra.b, ra.c);
+                    rot_apply(gb[p], gb[B - 1 - p], rb.a, rb.b, rb.c);
+                    if (s.Q) {
+                        rot_apply(va[p], va[B - 1 - p], ra.a, ra.b, ra.c);
+                        rot_apply(vb[p], vb[B - 1 - p], rb.a, rb.b, rb.c);
+                    }
+                }
+                // round-robin: positions 1..B-1 move by one
+                const cplx<R> la = ga[B - 1], lb = gb[B - 1], lva = va[B - 1], lvb = vb[B - 1];
+#pragma unroll
+                for (int k = B - 1; k >= 2; --k) {
+                    ga[k] = ga[k - 1];
+                    gb[k] = gb[k - 1];
+                    va[k] = va[k - 1];
+                    vb[k] = vb[k - 1];
+                }
+                ga[1] = la;
+                gb[1] = lb;
+                va[1] = lva;
+                vb[1] = lvb;
+            }
+            // B-1 steps bring every position back: store in place
+            store_block(s.G, d.ldg, ba, N, tid, grow, ga);
+            store_block(s.G, d.ldg, bb, N, tid, grow, gb);
+            if (s.Q) {
+                store_block(s.Q, d.ldv, ba, N, tid, qrow, va);
+                store_block(s.Q, d.ldv, bb, N, tid, qrow, vb);
+            }
+        }
+        if (W > 1) team_barrier(team);
+        // ---- cross passes: round-robin over block pairs
+        for (int os = 0; os < NBP - 1; ++os) {
+            for (int bp = member; bp < NBP / 2; bp += W) {
+                int ba, bb;
+                rr_pair(bp, os, NBP, ba, bb);
+                if (ba >= NB || bb >= NB) continue;
+                load_block(s.G, d.ldg, ba, N, tid, grow, ga);
+                load_block(s.G, d.ldg, bb, N, tid, grow, gb);
+                if (s.Q) {
+                    load_block(s.Q, d.ldv, ba, N, tid, qrow, va);
+                    load_block(s.Q, d.ldv, bb, N, tid, qrow, vb);
+                }
+                for (int t = 0; t < B; ++t) {
+#pragma unroll
+                    for (int p = 0; p < B; ++p) q[p] = pair_partials(ga[p], gb[p]);
+                    block_reduce_rotate<R>(bl, q, tol);
+#pragma unroll
+                    for (int p = 0; p < B; ++p) {
+                        const quad<R> r = bl.prm[p];
+                        rot_apply(ga[p], gb[p], r.a, r.b, r.c);
+                        if (s.Q) rot_apply(va[p], vb[p], r.a, r.b, r.c);
+                    }
+                    // block b shifts by one against block a
+                    const cplx<R> fb = gb[0], fv = vb[0];
+#pragma unroll
+                    for (int k = 0; k < B - 1; ++k) {
+                        gb[k] = gb[k + 1];
+                        vb[k] = vb[k + 1];
+                    }
+                    gb[B - 1] = fb;
+                    vb[B - 1] = fv;
+                }
+                // B shifts bring block b back to its order
+                store_block(s.G, d.ldg, ba, N, tid, grow, ga);
+                store_block(s.G, d.ldg, bb, N, tid, grow, gb);
+                if (s.Q) {
+                    store_block(s.Q, d.ldv, ba, N, tid, qrow, va);
+                    store_block(s.Q, d.ldv, bb, N, tid, qrow, vb);
+                }
+            }
+            if (W > 1 && os < NBP - 2) team_barrier(team);
+        }
+        __syncthreads();
+        if (W > 1) {
+            if (tid == 0 && *bl.rflag)
+                __hip_atomic_fetch_add(team.rot, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            team_barrier(team);
+            converged = __hip_atomic_load(team.rot, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) ==
+                        rot_before;
+        } else {
+            converged = (*bl.rflag == 0);
+        }
+        ++sweeps;
+        __syncthreads();
+    }
+    sweeps_out = sweeps;
+    conv_out = converged;
+}
+
+template <typename R>
+__device__ void block_one(const SvdArgs<R>& a, char* lds, int item, char* gslot, Team& team) {
+    const Target tg = target_of(a, item);
+    const bool acc = (a.d.transposed ? a.U : a.V) != nullptr;
+    const Shared<R> s = carve<R>(lds, a.d, acc, gslot);
+    const BlockLds<R> bl = carve_block<R>(lds, s.small_end);
+    if (team.member == 0) load_symbol<R>(a, s, tg.theta);
+    if (team.W > 1) team_barrier(team);
+    else __syncthreads();
+    int sweeps;
+    bool converged;
+    block_sweeps<R>(a.d, s, bl, a.max_sweeps, a.tol, team, sweeps, converged);
+    if (team.member == 0) finish<R, 64>(a, s, tg.out, tg.mirror, sweeps, converged);
+    // the slot is reused for the team's next symbol: members wait for the finish
+    if (team.W > 1) team_barrier(team);
+    if (a.info && threadIdx.x == 0 && team.member == 0 &&
+        (__hip_atomic_load(team.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & 2))
+        atomicOr(&a.info[LFA_INFO_NONFINITE], 2);
+}
+
+// Grid = teams x W work-groups, all resident at once (the host sizes the
+// grid from the occupancy of this kernel).  Team t owns slot t and works on
+// items t, t + teams, ...
+template <typename R>
+__global__ void __launch_bounds__(512) block_kernel(SvdArgs<R> a, int W, int32_t* counters) {
+    extern __shared__ __align__(16) char lds[];
+    const int teams = gridDim.x / W;
+    const int tix = blockIdx.x / W;
+    Team team;
+    team.member = blockIdx.x - tix * W;
+    team.W = W;
+    team.bar = counters + 4 * tix;
+    team.rot = counters + 4 * tix + 1;
+    team.err = counters + 4 * teams;
+    team.target = 0;
+    char* gslot = a.gws + (size_t)tix * a.slot_bytes;
+    const int count = item_count(a);
+    for (int item = tix; item < count; item += teams) block_one<R>(a, lds, item, gslot, team);
+}
+
 template <typename R, int L>
 __global__ void __launch_bounds__(1024) svd_kernel(SvdArgs<R> a) {
     extern __shared__ __align__(16) char lds[];
@@ -539,6 +853,7 @@ __global__ void fill_i32_kernel(int32_t* p, int32_t v, long long n) {
 
 size_t lds_bytes_for(const LayerDesc& d, bool accumulate, int elem_bytes) {
     if (d.kind == 1) return wave_lds_bytes_for(d.wave_nc, d.wave_ml, elem_bytes);
+    if (d.kind == 2) return block_lds_bytes(d, accumulate, elem_bytes);
     const int cb = 2 * elem_bytes;
     size_t b = (size_t)cb * kMaxTaps + (size_t)elem_bytes * 64 +
                (size_t)elem_bytes * ((d.N + 3) & ~3) + 2 * sizeof(int) * ((d.N + 3) & ~3);
@@ -550,6 +865,53 @@ size_t lds_bytes_for(const LayerDesc& d, bool accumulate, int elem_bytes) {
         if (accumulate) b += (size_t)cb * d.ldv * d.N;
     }
     return b;
+}
+
+size_t block_lds_bytes(const LayerDesc& d, bool accumulate, int elem_bytes) {
+    LayerDesc dg = d;
+    dg.kind = 0;
+    dg.storage = kGlobal;
+    const int nw = d.threads / 64;
+    return lds_bytes_for(dg, accumulate, elem_bytes) +
+           (size_t)elem_bytes * (nw * 64 * (4 * kBlk + 4) + nw * 4 * kBlk + 4 * kBlk) + 16 + 64;
+}
+
+template <typename R>
+hipError_t launch_block(const SvdArgs<R>& a, int teams, int W, int32_t* counters, hipStream_t st) {
+    const bool acc = (a.d.transposed ? a.U : a.V) != nullptr;
+    const size_t lds = block_lds_bytes(a.d, acc, sizeof(R));
+    hipError_t e = allow_lds(block_kernel<R>, lds);
+    if (e != hipSuccess) return e;
+    e = launch_fill_i32(counters, 0, 4LL * teams + 4, st);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(block_kernel<R>, dim3(teams * W), dim3(a.d.threads), lds, st, a, W, counters);
+    return hipGetLastError();
+}
+
+template <typename R>
+int block_resident_t(const LayerDesc& d, bool acc) {
+    const size_t lds = block_lds_bytes(d, acc, sizeof(R));
+    if (allow_lds(block_kernel<R>, lds) != hipSuccess) return 0;
+    int per_cu = 0, dev = 0, cus = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, block_kernel<R>, d.threads, lds) !=
+        hipSuccess)
+        return 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+        return 0;
+    return per_cu * cus;
+}
+
+hipError_t launch_block_svd_f32(const SvdArgs<float>& a, int teams, int W, int32_t* counters,
+                                hipStream_t s) {
+    return launch_block<float>(a, teams, W, counters, s);
+}
+hipError_t launch_block_svd_f64(const SvdArgs<double>& a, int teams, int W, int32_t* counters,
+                                hipStream_t s) {
+    return launch_block<double>(a, teams, W, counters, s);
+}
+int block_resident(const LayerDesc& d, bool acc, int elem_bytes) {
+    return elem_bytes == 8 ? block_resident_t<double>(d, acc) : block_resident_t<float>(d, acc);
 }
 
 hipError_t launch_svd_f32(const SvdArgs<float>& a, int grid, size_t lds, hipStream_t s) {

@@ -37,58 +37,12 @@
 namespace lfa {
 namespace {
 
-template <typename R>
-struct alignas(4 * sizeof(R)) quad {
-    R a, b, c, d;
-};
 
 template <typename R>
 __device__ __forceinline__ R skey(R v) {
     return v == v ? v : R(-1);
 }
 
-template <typename R>
-__device__ __forceinline__ void rot_apply(cplx<R>& x, cplx<R>& y, R c, R sr, R si) {
-    // x' = c x - sn y ;  y' = c y + conj(sn) x,  sn = sr + i si
-    const cplx<R> xv = x, yv = y;
-    x.x = fma(c, xv.x, -fma(sr, yv.x, -si * yv.y));
-    x.y = fma(c, xv.y, -fma(sr, yv.y, si * yv.x));
-    y.x = fma(c, yv.x, fma(sr, xv.x, si * xv.y));
-    y.y = fma(c, yv.y, fma(sr, xv.y, -si * xv.x));
-}
-
-// Rotation of one column pair from alpha = |g_j|^2, beta = |g_k|^2 and
-// gamma = g_j^H g_k: (c, Re(sn), Im(sn), flag) with sn = s conj(gamma)/|gamma|,
-// or the identity (1, 0, 0, 0) when |gamma| <= tol sqrt(alpha beta).  The
-// threshold test and the angle are evaluated in double precision; the
-// difference beta - alpha of two working-precision sums is exact there.  In
-// the FP32 path the reciprocals and square roots use the hardware
-// approximations (about 2^-23 relative, the rounding c and s receive anyway
-// when they are stored in FP32); the FP64 path keeps correctly rounded ones.
-template <typename R>
-__device__ __forceinline__ quad<R> rotation(R al, R be, R gr, R gi, double tol) {
-    const double g2 = double(gr) * double(gr) + double(gi) * double(gi);
-    quad<R> q = {R(1), R(0), R(0), R(0)};
-    if (!(g2 > tol * tol * (double(al) * double(be)))) return q;
-    if constexpr (sizeof(R) == 4) {
-        const double rg = __builtin_amdgcn_rsq(g2);                  // 1/|gamma|
-        const double z = 0.5 * (double(be) - double(al)) * rg;       // zeta
-        const double az = fabs(z);
-        const double w = fma(az, az, 1.0);
-        const double t = copysign(__builtin_amdgcn_rcp(az + w * __builtin_amdgcn_rsq(w)), z);
-        const double c = __builtin_amdgcn_rsq(fma(t, t, 1.0));
-        const double sn = c * t * rg;
-        q = {R(c), R(sn * double(gr)), R(-sn * double(gi)), R(1)};
-    } else {
-        const double gg = sqrt(g2);
-        const double z = (double(be) - double(al)) / (2.0 * gg);
-        const double t = copysign(1.0, z) / (fabs(z) + sqrt(1.0 + z * z));
-        const double c = 1.0 / sqrt(1.0 + t * t);
-        const double sn = c * t / gg;
-        q = {R(c), R(sn * double(gr)), R(-sn * double(gi)), R(1)};
-    }
-    return q;
-}
 
 template <int NC, typename T>
 __device__ __forceinline__ void rotate_positions(T (&g)[NC]) {

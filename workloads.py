@@ -87,7 +87,7 @@ def rank_one_taps(c_out: int = 512, c_in: int = 256, k: int = 3, n: int = 32, se
     a = _round_significand(rng.standard_normal((k, k, c_out)) / np.sqrt(k * k * c_in), 8)
     b = _round_significand(rng.standard_normal((k, k, c_in)), 8)
     W = np.einsum("abo,abi->oiab", a, b)
-    W32 = W.astype(np.float32)
+    W32 = np.ascontiguousarray(W, dtype=np.float32)
     assert np.array_equal(W32.astype(np.float64), W)
     return L, W32
 
