@@ -207,9 +207,18 @@ int lfa_sigma_grad(const lfa_plan* plan, const void* const* W, const int32_t* id
                    const void* grad, int32_t k, void* const* dW, void* ws, size_t ws_bytes,
                    void* stream);
 
+/* Same result as lfa_sigma_grad in two launches for all layers: one
+ * persistent launch computes the singular vectors of the k selected symbols
+ * of every layer (work-group teams share the large symbols), then one adjoint
+ * launch.  The work list for a given k is built and uploaded on the first
+ * call with that k (synchronously). */
+int lfa_sigma_grad_persistent(const lfa_plan* plan, const void* const* W, const int32_t* idx,
+                              const void* grad, int32_t k, void* const* dW, void* ws,
+                              size_t ws_bytes, void* stream);
+
 /* ---- batched forward + backward as one HIP graph ---------------------- */
 
-/* Capture [lfa_svd_persistent (sigma only) -> lfa_topk -> lfa_sigma_grad]
+/* Capture [lfa_svd_persistent (sigma only) -> lfa_topk -> lfa_sigma_grad_persistent]
  * for fixed buffers into a HIP graph.  Replaying it with new contents in W
  * recomputes sigma, the top-k and dW.  `grad` holds g for every selected
  * value (e.g. all ones for L = sum of the top-k).  Buffers must stay alive

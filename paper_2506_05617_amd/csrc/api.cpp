@@ -43,8 +43,7 @@ constexpr size_t kLdsCap = 160 * 1024 - 1024;  // gfx950: 160 KiB of LDS per wor
 constexpr size_t kLdsSafe = 64 * 1024;         // always available without opt-in
 constexpr int kGlobalGrid = 1024;              // blocks of a launch using global slots
 constexpr int kPersistentGrid = 1024;          // upper bound of the persistent grid
-constexpr int kPersistentThreads = 256;
-constexpr size_t kPersistentLdsCap = 72 * 1024;
+
 constexpr int kMaxTopk = 64;
 constexpr int kBlockCols = 8;                     // column block of the blocked kernel
 constexpr size_t kCounterBytes = 256 * ((4 * (4 * 1024 + 4) + 255) / 256);   // team counters
@@ -90,6 +89,23 @@ struct lfa_plan {
     WorkItem* items_dev = nullptr;
     int32_t* canon_dev = nullptr;
     int num_cus = 0;
+    // persistent launch: slots of the blocked layers, team counters, schedule
+    std::vector<size_t> pers_slot_off;    // byte offset of each layer's slots (blocked layers)
+    size_t pers_slots_total = 0;
+    int pers_teams = 0;                   // team instances (one per blocked-layer symbol)
+    int pers_wave_slots = 4;
+    std::vector<size_t> pers_lds;         // per chunk
+    std::vector<int> pers_grid;           // per chunk
+    // persistent SVD-with-vectors of the selected symbols, per k
+    struct GradSched {
+        WorkItem* items_dev = nullptr;
+        std::vector<int> chunk_first;
+        std::vector<size_t> lds;
+        std::vector<int> grid;
+        int teams = 0;
+    };
+    std::map<int, GradSched> grad_sched;
+    std::vector<LayerDesc> desc_gsel;     // blocked-kernel shape with vectors, 256 threads
 };
 
 struct lfa_graph {
@@ -179,6 +195,10 @@ int asm_mode(uint32_t flags) {
     return 0;
 }
 
+size_t pers_counter_bytes(const lfa_plan& p) {
+    return align_up(sizeof(int32_t) * (4 * (size_t)p.pers_teams + 4));
+}
+
 size_t sel_bytes(const lfa_layer& l, int eb) {
     const size_t r = std::min(l.c_out, l.c_in);
     return align_up((size_t)kMaxTopk * (r * eb + (size_t)(l.c_out + l.c_in) * r * 2 * eb));
@@ -210,15 +230,15 @@ size_t workspace_bytes(const lfa_plan& p) {
         need = std::max(need, sel_bytes(p.layers[i], eb) +
                                   (size_t)kMaxTopk * slot_bytes(dsg, true, eb));
     }
-    // persistent: slots for the global-storage layers
-    size_t pslot = 0;
-    for (size_t i = 0; i < p.layers.size(); ++i) {
-        LayerDesc d = p.desc_pers[i];
-        const bool acc = accumulates(d, wu, wv);
-        if (lds_bytes_for(d, acc, eb) > kLdsSafe) d.storage = kGlobal;
-        pslot = std::max(pslot, slot_bytes(d, acc, eb));
+    // persistent: team counters, then the slots of the blocked layers
+    need = std::max(need, pers_counter_bytes(p) + p.pers_slots_total);
+    // persistent sigma gradient: counters, compact outputs of every layer, slots
+    {
+        size_t g = align_up(sizeof(int32_t) * (4 * (size_t)kMaxTopk * p.layers.size() + 4));
+        for (size_t i = 0; i < p.layers.size(); ++i)
+            g += sel_bytes(p.layers[i], eb) + (size_t)kMaxTopk * slot_bytes(p.desc_gsel[i], true, eb);
+        need = std::max(need, g);
     }
-    need = std::max(need, (size_t)kPersistentGrid * pslot);
     // team counters of the blocked kernel precede its slots
     return kAlign + kCounterBytes + align_up(need);
 }
@@ -233,6 +253,90 @@ int validate_layer(const lfa_layer& l) {
     const long long hw = (long long)l.n * l.m;
     if (hw > (1LL << 30) || (long long)l.c_out * l.c_in > (1LL << 24)) return LFA_ERR_UNSUPPORTED;
     return LFA_OK;
+}
+
+// Work list of the persistent launch, per chunk of layers.  Cost model (work
+// units N^2 M per symbol, times 1.5 with vectors): a wave of the register
+// kernel takes ~7.5 ns per unit; a 256-thread work-group of the blocked
+// kernel ~2.5 ns per unit, and a team of W ~2.5 ns (1 + 0.08 W) / W per unit
+// (barrier overhead, measured on MI355X).  Each blocked layer gets the
+// smallest team size whose symbol time does not exceed the chunk's average
+// load per work-group; units (teams, bundles) are then listed longest first
+// with the members of a team consecutive.
+void build_schedule(lfa_plan* p) {
+    const int eb = elem_bytes(p->dtype);
+    const bool wu = p->flags & LFA_WANT_U, wv = p->flags & LFA_WANT_V;
+    const int nl = (int)p->layers.size();
+    p->items.clear();
+    p->chunk_first.clear();
+    p->pers_lds.clear();
+    p->pers_grid.clear();
+    // waves per work-group that run bundles: as many as LDS allows (<= 4)
+    size_t wmax = 0;
+    for (int i = 0; i < nl; ++i)
+        if (p->desc_pers[i].kind == 1)
+            wmax = std::max(wmax, lfa::wave_lds_bytes_for(p->desc_pers[i].wave_nc, p->desc_pers[i].wave_ml, eb));
+    p->pers_wave_slots = wmax ? (int)std::max<size_t>(1, std::min<size_t>(4, kLdsCap / wmax)) : 4;
+    for (int l0 = 0; l0 < nl; l0 += kMaxLaunchLayers) {
+        const int l1 = std::min(nl, l0 + kMaxLaunchLayers);
+        p->chunk_first.push_back((int)p->items.size());
+        const bool acc_any = wu || wv;
+        const size_t lds = persistent_lds_bytes(p->desc_pers.data() + l0, l1 - l0, acc_any, eb,
+                                                p->pers_wave_slots);
+        int grid = persistent_resident(lds, eb);
+        if (grid <= 0) grid = std::max(1, p->num_cus);
+        p->pers_lds.push_back(lds);
+        p->pers_grid.push_back(grid);
+        struct Unit {
+            double dur;
+            int layer, kind, item, W;
+        };
+        std::vector<Unit> units;
+        double total = 0;
+        std::vector<double> sym_cost(l1 - l0, 0.0);
+        for (int i = l0; i < l1; ++i) {
+            const LayerDesc& d = p->desc_pers[i];
+            const double u = double(d.N) * d.N * d.M * (accumulates(d, wu, wv) ? 1.5 : 1.0);
+            if (d.kind == 1) {
+                const int spw = 64 / d.wave_ml, per = spw * p->pers_wave_slots;
+                const double dur = 7.5e-9 * u * spw;
+                for (int it = 0; it < d.num_canon; it += per) total += dur;
+            } else {
+                sym_cost[i - l0] = 2.5e-9 * u;
+                total += sym_cost[i - l0] * d.num_canon;
+            }
+        }
+        const double avg = total / grid;
+        int team = 0;
+        for (int i = l0; i < l1; ++i) {
+            const LayerDesc& d = p->desc_pers[i];
+            if (d.kind == 1) {
+                const int spw = 64 / d.wave_ml, per = spw * p->pers_wave_slots;
+                const double u = double(d.N) * d.N * d.M;
+                for (int it = 0; it < d.num_canon; it += per)
+                    units.push_back({7.5e-9 * u * spw, i - l0, 0, it, 1});
+            } else {
+                const int NB = (d.N + kBlockCols - 1) / kBlockCols, NBP = NB + (NB & 1);
+                const double c = sym_cost[i - l0];
+                int W = 1;
+                while (W < NBP / 2 && W < grid && c * (1 + 0.08 * W) / W > avg) ++W;
+                for (int it = 0; it < d.num_canon; ++it)
+                    units.push_back({c * (1 + 0.08 * W) / W, i - l0, 1, it, W});
+            }
+        }
+        std::stable_sort(units.begin(), units.end(),
+                         [](const Unit& x, const Unit& y) { return x.dur > y.dur; });
+        for (const Unit& un : units) {
+            if (un.kind == 0) {
+                p->items.push_back(WorkItem{un.layer, 0, un.item, 0, 1, 0});
+            } else {
+                for (int m = 0; m < un.W; ++m)
+                    p->items.push_back(WorkItem{un.layer, 1, un.item, m, un.W, team});
+                ++team;
+            }
+        }
+    }
+    p->chunk_first.push_back((int)p->items.size());
 }
 
 // Upload device tables on first use from the current device.
@@ -254,10 +358,6 @@ int ensure_device(lfa_plan* p) {
     HIP_TRY(hipMalloc(&p->tw_dev, p->tw_host.size() * sizeof(double)));
     HIP_TRY(hipMemcpy(p->tw_dev, p->tw_host.data(), p->tw_host.size() * sizeof(double),
                       hipMemcpyHostToDevice));
-    HIP_TRY(hipMalloc(&p->items_dev, std::max<size_t>(1, p->items.size()) * sizeof(WorkItem)));
-    if (!p->items.empty())
-        HIP_TRY(hipMemcpy(p->items_dev, p->items.data(), p->items.size() * sizeof(WorkItem),
-                          hipMemcpyHostToDevice));
     HIP_TRY(hipMalloc(&p->canon_dev, std::max<size_t>(1, p->canon_host.size()) * sizeof(int32_t)));
     HIP_TRY(hipMemcpy(p->canon_dev, p->canon_host.data(), p->canon_host.size() * sizeof(int32_t),
                       hipMemcpyHostToDevice));
@@ -272,6 +372,11 @@ int ensure_device(lfa_plan* p) {
         if (lds_bytes_for(p->desc_pers[i], accumulates(p->desc_pers[i], wu, wv), eb) > lds_dev)
             p->desc_pers[i].storage = kGlobal;
     }
+    build_schedule(p);
+    HIP_TRY(hipMalloc(&p->items_dev, std::max<size_t>(1, p->items.size()) * sizeof(WorkItem)));
+    if (!p->items.empty())
+        HIP_TRY(hipMemcpy(p->items_dev, p->items.data(), p->items.size() * sizeof(WorkItem),
+                          hipMemcpyHostToDevice));
     p->device = dev;
     return LFA_OK;
 }
@@ -395,25 +500,19 @@ int persistent_impl(const lfa_plan* p, const void* const* W, void* const* sigma,
     const bool wu = p->flags & LFA_WANT_U, wv = p->flags & LFA_WANT_V;
     int32_t* counter = static_cast<int32_t*>(ws);
     char* region = static_cast<char*>(ws) + kAlign;
+    int32_t* team_counters = reinterpret_cast<int32_t*>(region);
+    char* slots = region + pers_counter_bytes(*p);
     if (info) HIP_TRY(launch_fill_i32(info, 0, (long long)p->layers.size() * LFA_INFO_WORDS, st));
     const int nl = (int)p->layers.size();
     // one launch per chunk of kMaxLaunchLayers layers (kernel-argument limit)
-    for (int l0 = 0; l0 < nl; l0 += kMaxLaunchLayers) {
+    for (int l0 = 0, chunk = 0; l0 < nl; l0 += kMaxLaunchLayers, ++chunk) {
         const int l1 = std::min(nl, l0 + kMaxLaunchLayers);
         PersistentArgs<R> pa{};
         pa.num_layers = l1 - l0;
         pa.threads = kPersistentThreads;
-        // One slot stride for every layer of the launch: a block owns the
-        // same slot whatever layer its current item belongs to.
-        size_t lds = 0, slot = 0;
         for (int i = l0; i < l1; ++i) {
             const LayerDesc& d = p->desc_pers[i];
             const bool acc = accumulates(d, wu, wv);
-            lds = std::max(lds, lds_bytes_for(d, acc, sizeof(R)));
-            slot = std::max(slot, slot_bytes(d, acc, sizeof(R)));
-        }
-        for (int i = l0; i < l1; ++i) {
-            const LayerDesc& d = p->desc_pers[i];
             SvdArgs<R>& a = pa.layer[i - l0];
             a.d = d;
             a.W = static_cast<const R*>(W[i]);
@@ -424,22 +523,35 @@ int persistent_impl(const lfa_plan* p, const void* const* W, void* const* sigma,
             a.tw = p->tw_dev;
             a.max_sweeps = kMaxSweeps;
             a.tol = jacobi_tol(p->tol, d.M);
-            a.slot_bytes = (long long)slot;
-            a.gws = d.storage == kGlobal ? region : nullptr;
             a.canon = p->canon_dev + p->canon_off[i];
+            if (d.kind == 2) {
+                a.slot_bytes = (long long)slot_bytes(d, acc, sizeof(R));
+                a.gws = slots + p->pers_slot_off[i];
+            }
         }
-        const int chunk = l0 / kMaxLaunchLayers;
         const int first = p->chunk_first[chunk];
         const int count = p->chunk_first[chunk + 1] - first;
         if (count == 0) continue;
         pa.items = p->items_dev + first;
         pa.num_items = count;
         pa.counter = counter;
+        pa.team_counters = team_counters;
+        pa.num_teams = p->pers_teams;
+        pa.wave_slots = p->pers_wave_slots;
+        pa.wave_lds = (int)(p->pers_wave_slots ? p->pers_lds[chunk] / p->pers_wave_slots : 0);
+        // per-wave LDS stride: the largest bundle region of the chunk
+        size_t wl = 0;
+        for (int i = l0; i < l1; ++i)
+            if (p->desc_pers[i].kind == 1)
+                wl = std::max(wl, wave_lds_bytes_for(p->desc_pers[i].wave_nc, p->desc_pers[i].wave_ml,
+                                                     (int)sizeof(R)));
+        pa.wave_lds = (int)wl;
         HIP_TRY(launch_fill_i32(counter, 0, 1, st));
-        const int grid = std::min(kPersistentGrid, count);
+        HIP_TRY(launch_fill_i32(team_counters, 0, 4LL * p->pers_teams + 4, st));
+        const int grid = std::min(p->pers_grid[chunk], count);
         hipError_t e;
-        if constexpr (sizeof(R) == 4) e = launch_persistent_f32(pa, grid, lds, st);
-        else e = launch_persistent_f64(pa, grid, lds, st);
+        if constexpr (sizeof(R) == 4) e = launch_persistent_f32(pa, grid, p->pers_lds[chunk], st);
+        else e = launch_persistent_f64(pa, grid, p->pers_lds[chunk], st);
         HIP_TRY(e);
     }
     return LFA_OK;
@@ -538,6 +650,135 @@ int topk_impl(const lfa_plan* p, const void* const* sigma, int k, void* vals, in
     return LFA_OK;
 }
 
+// Work list of the persistent SVD of the k selected symbols of every layer
+// (with vectors, blocked kernel), same cost model as build_schedule.
+int ensure_grad_schedule(lfa_plan* p, int k) {
+    std::lock_guard<std::mutex> lock(p->mu);
+    if (p->grad_sched.count(k)) return LFA_OK;
+    lfa_plan::GradSched gs;
+    const int eb = elem_bytes(p->dtype);
+    const int nl = (int)p->layers.size();
+    std::vector<WorkItem> items;
+    for (int l0 = 0; l0 < nl; l0 += kMaxLaunchLayers) {
+        const int l1 = std::min(nl, l0 + kMaxLaunchLayers);
+        gs.chunk_first.push_back((int)items.size());
+        const size_t lds = persistent_lds_bytes(p->desc_gsel.data() + l0, l1 - l0, true, eb, 1);
+        int grid = persistent_resident(lds, eb);
+        if (grid <= 0) grid = std::max(1, p->num_cus);
+        gs.lds.push_back(lds);
+        gs.grid.push_back(grid);
+        double total = 0;
+        for (int i = l0; i < l1; ++i) {
+            const LayerDesc& d = p->desc_gsel[i];
+            total += 2.5e-9 * 1.5 * double(d.N) * d.N * d.M * k;
+        }
+        const double avg = total / grid;
+        struct Unit {
+            double dur;
+            int layer, item, W;
+        };
+        std::vector<Unit> units;
+        for (int i = l0; i < l1; ++i) {
+            const LayerDesc& d = p->desc_gsel[i];
+            const int NB = (d.N + kBlockCols - 1) / kBlockCols, NBP = NB + (NB & 1);
+            const double c = 2.5e-9 * 1.5 * double(d.N) * d.N * d.M;
+            int W = 1;
+            while (W < NBP / 2 && W < grid && c * (1 + 0.08 * W) / W > avg) ++W;
+            for (int s = 0; s < k; ++s) units.push_back({c * (1 + 0.08 * W) / W, i - l0, s, W});
+        }
+        std::stable_sort(units.begin(), units.end(),
+                         [](const Unit& x, const Unit& y) { return x.dur > y.dur; });
+        int team = 0;
+        for (const Unit& un : units) {
+            for (int m = 0; m < un.W; ++m) items.push_back(WorkItem{un.layer, 1, un.item, m, un.W, team});
+            ++team;
+        }
+        gs.teams = std::max(gs.teams, team);
+    }
+    gs.chunk_first.push_back((int)items.size());
+    HIP_TRY(hipMalloc(&gs.items_dev, std::max<size_t>(1, items.size()) * sizeof(WorkItem)));
+    if (!items.empty())
+        HIP_TRY(hipMemcpy(gs.items_dev, items.data(), items.size() * sizeof(WorkItem),
+                          hipMemcpyHostToDevice));
+    p->grad_sched[k] = gs;
+    return LFA_OK;
+}
+
+// Sigma gradient in two launches: one persistent SVD-with-vectors of the
+// selected symbols of all layers (compact outputs), then one adjoint launch.
+template <typename R>
+int sigma_grad_persistent_impl(const lfa_plan* p, const void* const* W, const int32_t* idx,
+                               const void* grad, int k, void* const* dW, void* ws, hipStream_t st) {
+    const lfa_plan::GradSched& gs = p->grad_sched.at(k);
+    const int nl = (int)p->layers.size();
+    const int eb = sizeof(R);
+    int32_t* counter = static_cast<int32_t*>(ws);
+    char* region = static_cast<char*>(ws) + kAlign;
+    int32_t* team_counters = reinterpret_cast<int32_t*>(region);
+    char* cur = region + align_up(sizeof(int32_t) * (4 * (size_t)kMaxTopk * nl + 4));
+    std::vector<void*> sig(nl), Uc(nl), Vc(nl);
+    std::vector<char*> slot(nl);
+    for (int i = 0; i < nl; ++i) {
+        const lfa_layer& l = p->layers[i];
+        const size_t r = std::min(l.c_out, l.c_in);
+        sig[i] = cur;
+        Uc[i] = cur + align_up((size_t)k * r * eb);
+        Vc[i] = (char*)Uc[i] + align_up((size_t)k * l.c_out * r * 2 * eb);
+        cur += sel_bytes(l, eb);
+    }
+    for (int i = 0; i < nl; ++i) {
+        slot[i] = cur;
+        cur += (size_t)k * slot_bytes(p->desc_gsel[i], true, eb);
+    }
+    for (int l0 = 0, chunk = 0; l0 < nl; l0 += kMaxLaunchLayers, ++chunk) {
+        const int l1 = std::min(nl, l0 + kMaxLaunchLayers);
+        PersistentArgs<R> pa{};
+        pa.num_layers = l1 - l0;
+        pa.threads = kPersistentThreads;
+        for (int i = l0; i < l1; ++i) {
+            const LayerDesc& d = p->desc_gsel[i];
+            SvdArgs<R>& a = pa.layer[i - l0];
+            a.d = d;
+            a.W = static_cast<const R*>(W[i]);
+            a.sigma = static_cast<R*>(sig[i]);
+            // vectors of A: U (c_out x r), V (c_in x r), whichever side accumulates
+            a.U = static_cast<cplx<R>*>(Uc[i]);
+            a.V = static_cast<cplx<R>*>(Vc[i]);
+            a.tw = p->tw_dev;
+            a.max_sweeps = kMaxSweeps;
+            a.tol = jacobi_tol(p->tol, d.M);
+            a.theta_list = idx + (size_t)i * k * 3;
+            a.theta_stride = 3;
+            a.theta_count = k;
+            a.slot_bytes = (long long)slot_bytes(d, true, eb);
+            a.gws = slot[i];
+        }
+        const int first = gs.chunk_first[chunk];
+        const int count = gs.chunk_first[chunk + 1] - first;
+        if (count == 0) continue;
+        pa.items = gs.items_dev + first;
+        pa.num_items = count;
+        pa.counter = counter;
+        pa.team_counters = team_counters;
+        pa.num_teams = gs.teams;
+        pa.wave_slots = 1;
+        pa.wave_lds = 0;
+        HIP_TRY(launch_fill_i32(counter, 0, 1, st));
+        HIP_TRY(launch_fill_i32(team_counters, 0, 4LL * gs.teams + 4, st));
+        const int grid = std::min(gs.grid[chunk], count);
+        hipError_t e;
+        if constexpr (sizeof(R) == 4) e = launch_persistent_f32(pa, grid, gs.lds[chunk], st);
+        else e = launch_persistent_f64(pa, grid, gs.lds[chunk], st);
+        HIP_TRY(e);
+    }
+    for (int l0 = 0; l0 < nl; l0 += kMaxLaunchLayers) {
+        const int l1 = std::min(nl, l0 + kMaxLaunchLayers);
+        std::vector<const void*> Uv(Uc.begin() + l0, Uc.begin() + l1), Vv(Vc.begin() + l0, Vc.begin() + l1);
+        LFA_TRY(adjoint_launch<R>(p, l0, l1, Uv.data(), Vv.data(), idx, grad, k, dW, 1, st));
+    }
+    return LFA_OK;
+}
+
 int check_k(const lfa_plan* p, int k) {
     if (k < 1 || k > kMaxTopk) return LFA_ERR_INVALID_ARG;
     for (const lfa_layer& l : p->layers) {
@@ -629,32 +870,36 @@ int lfa_plan_create(lfa_plan** out, const lfa_layer* layers, int32_t num_layers,
         d = make_desc(l, off[l.n], off[l.m], accumulates(d, wu, wv), eb, kLdsCap);
         p->desc.push_back(d);
         p->desc_sel.push_back(make_desc(l, off[l.n], off[l.m], true, eb, kLdsCap));
-        LayerDesc dp = make_desc(l, off[l.n], off[l.m], accumulates(d, wu, wv), eb,
-                                 kPersistentLdsCap, kPersistentThreads, 0, false);
+        // persistent launch: bundles of the register kernel for small symbols
+        // without vectors, the blocked kernel (256 threads) otherwise
+        const bool pacc = accumulates(d, wu, wv);
+        LayerDesc dp = make_desc(l, off[l.n], off[l.m], pacc, eb, kLdsCap);
+        if (dp.kind != 1 || pacc) {
+            dp = make_desc(l, off[l.n], off[l.m], pacc, eb, kLdsCap);
+            dp.kind = 2;
+            dp.threads = kPersistentThreads;
+            dp.storage = kGlobal;
+        }
+        {
+            LayerDesc dg = make_desc(l, off[l.n], off[l.m], true, eb, kLdsCap);
+            dg.kind = 2;
+            dg.threads = kPersistentThreads;
+            dg.storage = kGlobal;
+            dg.num_canon = ncanon;
+            p->desc_gsel.push_back(dg);
+        }
         p->desc.back().num_canon = ncanon;
         p->desc_sel.back().num_canon = ncanon;
         dp.num_canon = ncanon;
         p->desc_pers.push_back(dp);
-    }
-    // persistent work list: per chunk of layers, items by estimated cost
-    // (N^2 M per sweep), largest first (longest-processing-time order)
-    const int nl = num_layers;
-    for (int l0 = 0; l0 < nl; l0 += kMaxLaunchLayers) {
-        const int l1 = std::min(nl, l0 + kMaxLaunchLayers);
-        p->chunk_first.push_back((int)p->items.size());
-        std::vector<std::pair<double, WorkItem>> v;
-        for (int i = l0; i < l1; ++i) {
-            const LayerDesc& d = p->desc_pers[i];
-            const double cost = double(d.N) * d.N * d.M;
-            for (int t = 0; t < d.num_canon; ++t) v.push_back({cost, WorkItem{i - l0, t}});
+        if (dp.kind == 2) {
+            p->pers_slot_off.push_back(p->pers_slots_total);
+            p->pers_slots_total += (size_t)ncanon * slot_bytes(dp, pacc, eb);
+            p->pers_teams += ncanon;
+        } else {
+            p->pers_slot_off.push_back(0);
         }
-        std::stable_sort(v.begin(), v.end(),
-                         [](const std::pair<double, WorkItem>& a, const std::pair<double, WorkItem>& b) {
-                             return a.first > b.first;
-                         });
-        for (auto& x : v) p->items.push_back(x.second);
     }
-    p->chunk_first.push_back((int)p->items.size());
     *out = p;
     return LFA_OK;
 }
@@ -664,6 +909,8 @@ int lfa_plan_destroy(lfa_plan* plan) {
     if (plan->tw_dev) (void)hipFree(plan->tw_dev);
     if (plan->items_dev) (void)hipFree(plan->items_dev);
     if (plan->canon_dev) (void)hipFree(plan->canon_dev);
+    for (auto& kv : plan->grad_sched)
+        if (kv.second.items_dev) (void)hipFree(kv.second.items_dev);
     delete plan;
     return LFA_OK;
 }
@@ -808,6 +1055,22 @@ int lfa_sigma_grad(const lfa_plan* plan, const void* const* W, const int32_t* id
     return sigma_grad_impl<float>(p, W, idx, grad, k, dW, ws, st);
 }
 
+int lfa_sigma_grad_persistent(const lfa_plan* plan, const void* const* W, const int32_t* idx,
+                              const void* grad, int32_t k, void* const* dW, void* ws,
+                              size_t ws_bytes, void* stream) {
+    if (!plan || !idx || !grad) return LFA_ERR_INVALID_ARG;
+    LFA_TRY(check_ptrs(plan, W, true));
+    LFA_TRY(check_ptrs(plan, dW, true));
+    LFA_TRY(check_k(plan, k));
+    LFA_TRY(check_ws(plan, ws, ws_bytes));
+    lfa_plan* p = const_cast<lfa_plan*>(plan);
+    LFA_TRY(ensure_device(p));
+    LFA_TRY(ensure_grad_schedule(p, k));
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    if (p->dtype == LFA_F64) return sigma_grad_persistent_impl<double>(p, W, idx, grad, k, dW, ws, st);
+    return sigma_grad_persistent_impl<float>(p, W, idx, grad, k, dW, ws, st);
+}
+
 int lfa_graph_create(lfa_plan* plan, const void* const* W, void* const* sigma, int32_t k,
                      void* vals, int32_t* idx, const void* grad, void* const* dW, int32_t* info,
                      void* ws, size_t ws_bytes, void* stream, lfa_graph** out) {
@@ -821,6 +1084,7 @@ int lfa_graph_create(lfa_plan* plan, const void* const* W, void* const* sigma, i
     LFA_TRY(check_k(plan, k));
     LFA_TRY(check_ws(plan, ws, ws_bytes));
     LFA_TRY(ensure_device(plan));
+    LFA_TRY(ensure_grad_schedule(plan, k));   // uploads: not allowed while capturing
     hipStream_t st = static_cast<hipStream_t>(stream);
     if (st == nullptr) return LFA_ERR_INVALID_ARG;   // cannot capture the legacy default stream
     lfa_graph* g = new (std::nothrow) lfa_graph();
@@ -832,7 +1096,7 @@ int lfa_graph_create(lfa_plan* plan, const void* const* W, void* const* sigma, i
     }
     int s = lfa_svd_persistent(plan, W, sigma, nullptr, nullptr, info, ws, ws_bytes, stream);
     if (s == LFA_OK) s = lfa_topk(plan, sigma, k, vals, idx, stream);
-    if (s == LFA_OK) s = lfa_sigma_grad(plan, W, idx, grad, k, dW, ws, ws_bytes, stream);
+    if (s == LFA_OK) s = lfa_sigma_grad_persistent(plan, W, idx, grad, k, dW, ws, ws_bytes, stream);
     e = hipStreamEndCapture(st, &g->graph);
     if (s != LFA_OK || e != hipSuccess) {
         if (g->graph) (void)hipGraphDestroy(g->graph);

@@ -1,0 +1,1216 @@
+// Device code of the Jacobi SVD kernels, shared by the translation units
+// that define kernels (plain launches, the register kernel, the persistent
+// launch).  Header-only: templates and inline functions.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <math.h>
+
+#include "lfa_internal.hpp"
+
+namespace lfa {
+namespace dev {
+
+// ===================== lane-group and blocked kernels ======================
+//  Batched one-sided Jacobi SVD of convolution symbols on gfx950.
+//
+// One work-group owns one symbol at a time.  It assembles the c_out x c_in
+// symbol A_k = sum_y M_y exp(+2 pi i <k,y>) (Sec. III "Convolution Theorem",
+// Algorithm 1 symbol step) straight into its working matrix G (LDS, or a
+// global slot for symbols larger than LDS), runs complex one-sided (Hestenes)
+// Jacobi sweeps on the columns of G with a parallel round-robin pair order,
+// and writes sigma (sorted), U and V (Algorithm 1 SVD step).
+//
+// G is M x N, column-major with leading dimension ldg, M = max(c_out, c_in),
+// N = min(c_out, c_in).  For c_out >= c_in, G = A and the accumulated
+// rotations form V; for c_out < c_in, G = A^H and the roles of U and V swap.
+//
+// A column pair (j, k) is handled by a group of L lanes of one wavefront;
+// lane l owns rows l, l+L, ... of both columns in registers.  The three inner
+// products alpha = |g_j|^2, beta = |g_k|^2, gamma = g_j^H g_k are reduced with
+// xor shuffles inside the lane group, the rotation is computed in double
+// precision by every lane of the group (no broadcast), and applied to the
+// registers, then written back.  The N/2 pairs of one round-robin step are
+// disjoint, so groups never touch the same column within a step; a
+// work-group barrier separates steps.
+
+
+template <typename R>
+__device__ __forceinline__ cplx<R> cmul(cplx<R> a, cplx<R> b) {
+    return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
+}
+
+template <typename R>
+__device__ __forceinline__ R shfl_xor(R v, int mask) {
+    return __shfl_xor(v, mask, 64);
+}
+
+// Sum over the L lanes of a lane group (L a power of two <= 64).
+template <typename R, int L>
+__device__ __forceinline__ R group_sum(R v) {
+#pragma unroll
+    for (int off = L / 2; off >= 1; off >>= 1) v += shfl_xor(v, off);
+    return v;
+}
+
+// Round-robin ("circle") ordering on Np (even) positions: position 0 is
+// fixed, positions 1..Np-1 rotate by one each step.  Over Np-1 steps every
+// unordered pair meets exactly once.
+__device__ __forceinline__ void rr_pair(int pr, int step, int Np, int& j, int& k) {
+    const int c = Np - 1;
+    auto pos = [&](int i) { return i == 0 ? 0 : ((i - 1 + step) % c) + 1; };
+    j = pos(pr);
+    k = pos(Np - 1 - pr);
+}
+
+// exp(2 pi i ((p*y1 mod n)/n + (q*y2 mod m)/m)) from the double twiddle tables.
+__device__ __forceinline__ void phase(const double* tw, const LayerDesc& d, int p, int q, int t,
+                                      double& re, double& im) {
+    const int a = t / d.kw, b = t - (t / d.kw) * d.kw;
+    const int y1 = a - (d.kh - 1) / 2, y2 = b - (d.kw - 1) / 2;
+    int i1 = (p * y1) % d.n;
+    if (i1 < 0) i1 += d.n;
+    int i2 = (q * y2) % d.m;
+    if (i2 < 0) i2 += d.m;
+    const double ar = tw[2 * (d.tw_n + i1)], ai = tw[2 * (d.tw_n + i1) + 1];
+    const double br = tw[2 * (d.tw_m + i2)], bi = tw[2 * (d.tw_m + i2) + 1];
+    re = ar * br - ai * bi;
+    im = ar * bi + ai * br;
+}
+
+template <typename R>
+struct Shared {
+    cplx<R>* ph;     // [kMaxTaps] phases of the current frequency
+    R* sig;          // [N] column norms
+    int* perm;       // [N] sorted position -> column
+    int* inv;        // [N] column -> sorted position
+    cplx<R>* coef;   // [N] Gram-Schmidt coefficients (completion of zero columns)
+    cplx<R>* xtmp;   // [M] Gram-Schmidt work vector
+    int* flags;      // [4] rotation flags (3 rotating) + scratch
+    R* red;          // [64] scratch for block reductions
+    cplx<R>* G;      // working matrix (LDS or global)
+    cplx<R>* Q;      // rotation accumulator (LDS or global), or null
+    size_t small_end;   // LDS bytes used by the arrays above (G/Q excluded)
+};
+
+template <typename R>
+__device__ __forceinline__ Shared<R> carve(char* lds, const LayerDesc& d, bool acc, char* gslot) {
+    Shared<R> s;
+    char* p = lds;
+    s.ph = reinterpret_cast<cplx<R>*>(p);
+    p += sizeof(cplx<R>) * kMaxTaps;
+    s.red = reinterpret_cast<R*>(p);
+    p += sizeof(R) * 64;
+    s.sig = reinterpret_cast<R*>(p);
+    p += sizeof(R) * ((d.N + 3) & ~3);
+    s.perm = reinterpret_cast<int*>(p);
+    p += sizeof(int) * ((d.N + 3) & ~3);
+    s.inv = reinterpret_cast<int*>(p);
+    p += sizeof(int) * ((d.N + 3) & ~3);
+    p = reinterpret_cast<char*>((reinterpret_cast<uintptr_t>(p) + 15) & ~uintptr_t(15));
+    s.coef = reinterpret_cast<cplx<R>*>(p);
+    p += sizeof(cplx<R>) * d.N;
+    s.xtmp = reinterpret_cast<cplx<R>*>(p);
+    p += sizeof(cplx<R>) * d.M;
+    s.flags = reinterpret_cast<int*>(p);
+    p += sizeof(int) * 4;
+    p = reinterpret_cast<char*>((reinterpret_cast<uintptr_t>(p) + 15) & ~uintptr_t(15));
+    s.small_end = (size_t)(p - lds);
+    char* base = (d.storage == kLds) ? p : gslot;
+    s.G = reinterpret_cast<cplx<R>*>(base);
+    base += sizeof(cplx<R>) * (size_t)d.ldg * d.N;
+    s.Q = acc ? reinterpret_cast<cplx<R>*>(base) : nullptr;
+    return s;
+}
+
+template <typename R>
+__device__ __forceinline__ R sort_key(R v) {
+    return v == v ? v : R(-1);
+}
+
+// Block-wide sum (all threads receive it).
+template <typename R>
+__device__ R block_sum(R v, R* red) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
+    v = group_sum<R, 64>(v);
+    __syncthreads();
+    if (lane == 0) red[wave] = v;
+    __syncthreads();
+    R t = 0;
+    for (int w = 0; w < nw; ++w) t += red[w];
+    return t;
+}
+
+// ---------------------------------------------------------------------------
+// Load the symbol of frequency theta into G (and Q = I).
+// ---------------------------------------------------------------------------
+template <typename R>
+__device__ void load_symbol(const SvdArgs<R>& a, const Shared<R>& s, int theta) {
+    const LayerDesc& d = a.d;
+    const int tid = threadIdx.x, nt = blockDim.x;
+    const int T = d.kh * d.kw;
+    const int p = theta / d.m, q = theta - (theta / d.m) * d.m;
+    const int E = d.c_out * d.c_in;
+    if (a.A == nullptr) {
+        for (int t = tid; t < T; t += nt) {
+            double re, im;
+            phase(a.tw, d, p, q, t, re, im);
+            s.ph[t] = {R(re), R(im)};
+        }
+        __syncthreads();
+        for (int e = tid; e < E; e += nt) {
+            const R* w = a.W + (size_t)e * T;
+            R re = 0, im = 0;
+            for (int t = 0; t < T; ++t) {
+                const R wt = w[t];
+                const cplx<R> ph = s.ph[t];
+                re = fma(wt, ph.x, re);
+                im = fma(wt, ph.y, im);
+            }
+            const int o = e / d.c_in, i = e - (e / d.c_in) * d.c_in;
+            if (!d.transposed) s.G[(size_t)i * d.ldg + o] = {re, im};
+            else               s.G[(size_t)o * d.ldg + i] = {re, -im};
+        }
+    } else {
+        const cplx<R>* A = a.A + (size_t)theta * E;
+        for (int e = tid; e < E; e += nt) {
+            const cplx<R> v = A[e];
+            const int o = e / d.c_in, i = e - (e / d.c_in) * d.c_in;
+            if (!d.transposed) s.G[(size_t)i * d.ldg + o] = v;
+            else               s.G[(size_t)o * d.ldg + i] = {v.x, -v.y};
+        }
+    }
+    if (s.Q) {
+        const int N = d.N;
+        for (int e = tid; e < N * N; e += nt) {
+            const int j = e / N, i = e - (e / N) * N;
+            s.Q[(size_t)j * d.ldv + i] = {R(i == j ? 1 : 0), R(0)};
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// One-sided Jacobi sweeps.  Returns the number of sweeps used; `converged`
+// tells whether the last sweep made no rotation.
+// ---------------------------------------------------------------------------
+template <typename R, int L>
+__device__ int jacobi(const LayerDesc& d, const Shared<R>& s, int max_sweeps, double tol,
+                      bool& converged) {
+    constexpr int RM = kRowsPerLane;
+    const int tid = threadIdx.x;
+    const int lane = tid & (L - 1), group = tid / L, ngroups = blockDim.x / L;
+    const int M = d.M, N = d.N, ldg = d.ldg, ldv = d.ldv;
+    const int Np = N + (N & 1);
+    const int npairs = Np / 2, nsteps = Np - 1;
+    cplx<R>* __restrict__ G = s.G;
+    cplx<R>* __restrict__ Q = s.Q;
+
+    if (tid == 0) s.flags[0] = s.flags[1] = s.flags[2] = 0;
+    __syncthreads();
+    converged = (N < 2);
+    int sweep = 0;
+    while (!converged && sweep < max_sweeps) {
+        if (tid == 0) s.flags[(sweep + 1) % 3] = 0;
+        for (int step = 0; step < nsteps; ++step) {
+            for (int pb = 0; pb < npairs; pb += ngroups) {
+                const int pr = pb + group;
+                if (pr >= npairs) continue;
+                int j, k;
+                rr_pair(pr, step, Np, j, k);
+                if (j >= N || k >= N) continue;
+                cplx<R> x[RM], y[RM];
+                R al = 0, be = 0, gr = 0, gi = 0;
+#pragma unroll
+                for (int t = 0; t < RM; ++t) {
+                    const int i = lane + t * L;
+                    if (i < M) {
+                        x[t] = G[(size_t)j * ldg + i];
+                        y[t] = G[(size_t)k * ldg + i];
+                        al = fma(x[t].x, x[t].x, fma(x[t].y, x[t].y, al));
+                        be = fma(y[t].x, y[t].x, fma(y[t].y, y[t].y, be));
+                        gr = fma(x[t].x, y[t].x, fma(x[t].y, y[t].y, gr));
+                        gi = fma(x[t].x, y[t].y, fma(-x[t].y, y[t].x, gi));
+                    }
+                }
+                al = group_sum<R, L>(al);
+                be = group_sum<R, L>(be);
+                gr = group_sum<R, L>(gr);
+                gi = group_sum<R, L>(gi);
+                const double g = sqrt(double(gr) * double(gr) + double(gi) * double(gi));
+                if (!(g > tol * sqrt(double(al) * double(be)))) continue;
+                // Real 2x2 symmetric Schur step on [[al, g], [g, be]] after the
+                // phase of gamma is moved into column k.
+                const double zeta = (double(be) - double(al)) / (2.0 * g);
+                const double tt = copysign(1.0, zeta) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+                const double cs = 1.0 / sqrt(1.0 + tt * tt);
+                const double sn = cs * tt;
+                // x' = c x - s e^{-i phi} y ;  y' = c y + s e^{+i phi} x
+                const R c = R(cs);
+                const R sr = R(sn * double(gr) / g), si = R(-sn * double(gi) / g);
+#pragma unroll
+                for (int t = 0; t < RM; ++t) {
+                    const int i = lane + t * L;
+                    if (i < M) {
+                        const cplx<R> xv = x[t], yv = y[t];
+                        cplx<R> xn, yn;
+                        xn.x = fma(c, xv.x, -fma(sr, yv.x, -si * yv.y));
+                        xn.y = fma(c, xv.y, -fma(sr, yv.y, si * yv.x));
+                        yn.x = fma(c, yv.x, fma(sr, xv.x, si * xv.y));
+                        yn.y = fma(c, yv.y, fma(sr, xv.y, -si * xv.x));
+                        G[(size_t)j * ldg + i] = xn;
+                        G[(size_t)k * ldg + i] = yn;
+                    }
+                }
+                if (Q) {
+#pragma unroll
+                    for (int t = 0; t < RM; ++t) {
+                        const int i = lane + t * L;
+                        if (i < N) {
+                            const cplx<R> xv = Q[(size_t)j * ldv + i], yv = Q[(size_t)k * ldv + i];
+                            cplx<R> xn, yn;
+                            xn.x = fma(c, xv.x, -fma(sr, yv.x, -si * yv.y));
+                            xn.y = fma(c, xv.y, -fma(sr, yv.y, si * yv.x));
+                            yn.x = fma(c, yv.x, fma(sr, xv.x, si * xv.y));
+                            yn.y = fma(c, yv.y, fma(sr, xv.y, -si * xv.x));
+                            Q[(size_t)j * ldv + i] = xn;
+                            Q[(size_t)k * ldv + i] = yn;
+                        }
+                    }
+                }
+                if (lane == 0) s.flags[sweep % 3] = 1;
+            }
+            __syncthreads();
+        }
+        converged = (s.flags[sweep % 3] == 0);
+        ++sweep;
+    }
+    __syncthreads();
+    return sweep;
+}
+
+// ---------------------------------------------------------------------------
+// Norms, sort, normalisation, completion of zero columns, outputs.
+// ---------------------------------------------------------------------------
+template <typename R, int L>
+__device__ void finish(const SvdArgs<R>& a, const Shared<R>& s, int out_idx, int mirror,
+                       int sweeps, bool converged) {
+    const LayerDesc& d = a.d;
+    const int tid = threadIdx.x, nt = blockDim.x;
+    const int lane = tid & (L - 1), group = tid / L, ngroups = nt / L;
+    const int M = d.M, N = d.N, ldg = d.ldg, ldv = d.ldv;
+    cplx<R>* G = s.G;
+    cplx<R>* Q = s.Q;
+
+    // column norms
+    for (int j = group; j < N; j += ngroups) {
+        R acc = 0;
+        for (int i = lane; i < M; i += L) {
+            const cplx<R> v = G[(size_t)j * ldg + i];
+            acc = fma(v.x, v.x, fma(v.y, v.y, acc));
+        }
+        acc = group_sum<R, L>(acc);
+        if (lane == 0) s.sig[j] = sqrt(acc);
+    }
+    __syncthreads();
+    // rank sort: descending, ties by column index; NaN sorts as -1 so the
+    // ranks always form a permutation
+    for (int j = tid; j < N; j += nt) {
+        const R sj = sort_key(s.sig[j]);
+        int rank = 0;
+        for (int k = 0; k < N; ++k) {
+            const R sk = sort_key(s.sig[k]);
+            rank += (sk > sj) || (sk == sj && k < j);
+        }
+        s.perm[rank] = j;
+        s.inv[j] = rank;
+    }
+    __syncthreads();
+
+    const int r = N;
+    R* sig_out = a.sigma + (size_t)out_idx * r;
+    R* sig_mir = mirror >= 0 ? a.sigma + (size_t)mirror * r : nullptr;
+    bool bad = false;
+    for (int c = tid; c < r; c += nt) {
+        const R v = s.sig[s.perm[c]];
+        sig_out[c] = v;
+        if (sig_mir) sig_mir[c] = v;
+        bad |= !isfinite(v);
+    }
+    const bool want_left = d.transposed ? (a.V != nullptr) : (a.U != nullptr);
+    const bool want_right = d.transposed ? (a.U != nullptr) : (a.V != nullptr);
+
+    if (want_left) {
+        // normalise columns in place: u_j = g_j / sigma_j (zero columns stay 0)
+        for (int e = tid; e < N * M; e += nt) {
+            const int j = e / M, i = e - (e / M) * M;
+            const R sj = s.sig[j];
+            const cplx<R> v = G[(size_t)j * ldg + i];
+            const R inv = sj > R(0) ? R(1) / sj : R(0);
+            G[(size_t)j * ldg + i] = {v.x * inv, v.y * inv};
+        }
+        __syncthreads();
+        // Columns with sigma == 0 (they sort last) get an orthonormal
+        // completion: unit vectors e_0, e_1, ... orthogonalised by two passes
+        // of classical Gram-Schmidt against every accepted column, kept when
+        // the residual norm exceeds a threshold (1/2, lowered if no unit
+        // vector qualifies; some residual has norm >= 1/sqrt(M)).
+        int nz = 0;
+        while (nz < N && s.sig[s.perm[N - 1 - nz]] == R(0)) ++nz;
+        int cand = 0;
+        R thresh = R(0.5);
+        for (int zc = N - nz; zc < N; ++zc) {
+            const int jz = s.perm[zc];
+            bool done = false;
+            for (int tries = 0; !done && tries < 4 * M; ++tries) {
+                if (cand == M) {
+                    cand = 0;
+                    thresh *= R(0.2);
+                }
+                for (int i = tid; i < M; i += nt) G[(size_t)jz * ldg + i] = {R(i == cand), R(0)};
+                __syncthreads();
+                for (int pass = 0; pass < 2; ++pass) {
+                    for (int col = group; col < N; col += ngroups) {
+                        // accepted: nonzero columns and zero columns completed earlier
+                        const bool use = col != jz && (s.sig[col] > R(0) || s.inv[col] < zc);
+                        cplx<R> acc = {0, 0};
+                        if (use) {
+                            for (int i = lane; i < M; i += L) {
+                                const cplx<R> u = G[(size_t)col * ldg + i];
+                                const cplx<R> x = G[(size_t)jz * ldg + i];
+                                acc.x = fma(u.x, x.x, fma(u.y, x.y, acc.x));
+                                acc.y = fma(u.x, x.y, fma(-u.y, x.x, acc.y));
+                            }
+                        }
+                        acc.x = group_sum<R, L>(acc.x);
+                        acc.y = group_sum<R, L>(acc.y);
+                        if (lane == 0) s.coef[col] = acc;
+                    }
+                    __syncthreads();
+                    for (int i = tid; i < M; i += nt) {
+                        cplx<R> x = G[(size_t)jz * ldg + i];
+                        for (int col = 0; col < N; ++col) {
+                            const cplx<R> cf = s.coef[col];
+                            const cplx<R> u = G[(size_t)col * ldg + i];
+                            x.x -= cf.x * u.x - cf.y * u.y;
+                            x.y -= cf.x * u.y + cf.y * u.x;
+                        }
+                        s.xtmp[i] = x;
+                    }
+                    __syncthreads();
+                    for (int i = tid; i < M; i += nt) G[(size_t)jz * ldg + i] = s.xtmp[i];
+                    __syncthreads();
+                }
+                R nrm = 0;
+                for (int i = tid; i < M; i += nt) {
+                    const cplx<R> x = G[(size_t)jz * ldg + i];
+                    nrm = fma(x.x, x.x, fma(x.y, x.y, nrm));
+                }
+                nrm = sqrt(block_sum<R>(nrm, s.red));
+                if (nrm > thresh) {
+                    const R inv = R(1) / nrm;
+                    for (int i = tid; i < M; i += nt) {
+                        const cplx<R> x = G[(size_t)jz * ldg + i];
+                        G[(size_t)jz * ldg + i] = {x.x * inv, x.y * inv};
+                    }
+                    done = true;
+                }
+                ++cand;
+                __syncthreads();
+            }
+        }
+        // write: out[theta][i][c] = G[perm[c]][i]
+        cplx<R>* out = (d.transposed ? a.V : a.U) + (size_t)out_idx * M * r;
+        cplx<R>* mir = mirror >= 0 ? (d.transposed ? a.V : a.U) + (size_t)mirror * M * r : nullptr;
+        for (int e = tid; e < M * r; e += nt) {
+            const int i = e / r, c = e - (e / r) * r;
+            const cplx<R> v = G[(size_t)s.perm[c] * ldg + i];
+            out[e] = v;
+            if (mir) mir[e] = {v.x, -v.y};
+        }
+    }
+    if (want_right) {
+        cplx<R>* out = (d.transposed ? a.U : a.V) + (size_t)out_idx * N * r;
+        cplx<R>* mir = mirror >= 0 ? (d.transposed ? a.U : a.V) + (size_t)mirror * N * r : nullptr;
+        for (int e = tid; e < N * r; e += nt) {
+            const int i = e / r, c = e - (e / r) * r;
+            const cplx<R> v = Q[(size_t)s.perm[c] * ldv + i];
+            out[e] = v;
+            if (mir) mir[e] = {v.x, -v.y};
+        }
+    }
+    if (a.info) {
+        if (tid == 0) {
+            atomicAdd(&a.info[LFA_INFO_SUM_SWEEPS], sweeps);
+            atomicMax(&a.info[LFA_INFO_MAX_SWEEPS], sweeps);
+            if (!converged) atomicAdd(&a.info[LFA_INFO_NONCONVERGED], 1);
+        }
+        if (bad) atomicOr(&a.info[LFA_INFO_NONFINITE], 1);
+    }
+    __syncthreads();
+}
+
+// Work item `item` (see target_of).
+template <typename R, int L>
+__device__ void svd_one(const SvdArgs<R>& a, char* lds, int item, char* gslot) {
+    const Target tg = target_of(a, item);
+    const int theta = tg.theta;
+    const bool acc = (a.d.transposed ? a.U : a.V) != nullptr;
+    const Shared<R> s = carve<R>(lds, a.d, acc, gslot);
+    load_symbol<R>(a, s, theta);
+    __syncthreads();
+    bool converged;
+    const int sweeps = jacobi<R, L>(a.d, s, a.max_sweeps, a.tol, converged);
+    finish<R, L>(a, s, tg.out, tg.mirror, sweeps, converged);
+}
+
+// ---------------------------------------------------------------------------
+// Blocked one-sided Jacobi for symbols with more than 64 rows.
+//
+// Thread t of the work-group owns row t of G (M x N, column-major in a global
+// slot) and row t of the accumulator Q (N x N): it is the only thread that
+// ever reads or writes those rows, so the global traffic of the sweeps needs
+// no synchronisation.  Columns are taken B at a time: a block pair (2B columns
+// of the thread's row, and of its Q row) sits in registers while its column
+// pairs are rotated, then goes back to the slot.
+//
+// One sweep visits every column pair exactly once:
+//  * intra pass: blocks (2i, 2i+1) are loaded together and the pairs inside
+//    each block are rotated by a round-robin of B-1 steps;
+//  * cross passes: a round-robin over the blocks (NB-1 outer steps); in a
+//    block pair (a, b), step t rotates (a_p, b_{(p+t) mod B}) for all p.
+// Inner products are reduced over rows by a per-wave LDS transpose and a sum
+// over the waves; one thread per pair computes the rotation.
+// ---------------------------------------------------------------------------
+constexpr int kBlk = 8;   // columns per block
+
+template <typename R>
+struct BlockLds {
+    R* wpart;        // [waves][64][4B+4]
+    R* wsum;         // [waves][4B]
+    quad<R>* prm;    // [B]
+    int* rflag;      // rotation made in this sweep
+};
+
+template <typename R>
+__device__ __forceinline__ BlockLds<R> carve_block(char* lds, size_t off) {
+    constexpr int B = kBlk, PST = 4 * B + 4;
+    const int nw = blockDim.x >> 6;
+    BlockLds<R> b;
+    R* p = reinterpret_cast<R*>(lds + ((off + 63) & ~size_t(63)));
+    b.wpart = p;
+    p += nw * 64 * PST;
+    b.wsum = p;
+    p += nw * 4 * B;
+    b.prm = reinterpret_cast<quad<R>*>(p);
+    b.rflag = reinterpret_cast<int*>(b.prm + B);
+    return b;
+}
+
+// Sum the per-row contributions q[p] (p < B pairs) over all rows and compute
+// the B rotations into bl.prm.  Contains two work-group barriers.
+template <typename R>
+__device__ __forceinline__ void block_reduce_rotate(const BlockLds<R>& bl, quad<R> (&q)[kBlk],
+                                                    double tol) {
+    constexpr int B = kBlk, PST = 4 * B + 4, Q = 4 * B, H = 64 / Q;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nw = blockDim.x >> 6;
+    R* wp = bl.wpart + wave * 64 * PST;
+#pragma unroll
+    for (int p = 0; p < B; ++p) *reinterpret_cast<quad<R>*>(wp + lane * PST + 4 * p) = q[p];
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    const int qi = lane % Q, h = lane / Q;
+    R sum = 0;
+#pragma unroll 8
+    for (int r = h * (64 / H); r < (h + 1) * (64 / H); ++r) sum += wp[r * PST + qi];
+#pragma unroll
+    for (int off = Q; off < 64; off <<= 1) sum += __shfl_xor(sum, off, 64);
+    if (lane < Q) bl.wsum[wave * Q + qi] = sum;
+    __syncthreads();
+    if (tid < B) {
+        R s0 = 0, s1 = 0, s2 = 0, s3 = 0;
+        for (int w = 0; w < nw; ++w) {
+            const R* ws = bl.wsum + w * Q + 4 * tid;
+            s0 += ws[0];
+            s1 += ws[1];
+            s2 += ws[2];
+            s3 += ws[3];
+        }
+        const quad<R> r = rotation<R>(s0, s1, s2, s3, tol);
+        bl.prm[tid] = r;
+        if (r.d != R(0)) *bl.rflag = 1;
+    }
+    __syncthreads();
+}
+
+template <typename R>
+__device__ __forceinline__ quad<R> pair_partials(cplx<R> x, cplx<R> y) {
+    quad<R> q;
+    q.a = fma(x.x, x.x, x.y * x.y);
+    q.b = fma(y.x, y.x, y.y * y.y);
+    q.c = fma(x.x, y.x, x.y * y.y);
+    q.d = fma(x.x, y.y, -x.y * y.x);
+    return q;
+}
+
+// Load / store block `blk` (columns blk*B ..) of this thread's row.
+template <typename R>
+__device__ __forceinline__ void load_block(const cplx<R>* base, int ld, int blk, int ncols, int row,
+                                           bool row_ok, cplx<R> (&x)[kBlk]) {
+#pragma unroll
+    for (int k = 0; k < kBlk; ++k) {
+        const int c = blk * kBlk + k;
+        x[k] = (row_ok && c < ncols) ? base[(size_t)c * ld + row] : cplx<R>{R(0), R(0)};
+    }
+}
+template <typename R>
+__device__ __forceinline__ void store_block(cplx<R>* base, int ld, int blk, int ncols, int row,
+                                            bool row_ok, const cplx<R> (&x)[kBlk]) {
+#pragma unroll
+    for (int k = 0; k < kBlk; ++k) {
+        const int c = blk * kBlk + k;
+        if (row_ok && c < ncols) base[(size_t)c * ld + row] = x[k];
+    }
+}
+
+// Team of W work-groups working on one symbol.  Counters live in device
+// memory, cleared before the launch; `target` counts the barriers passed.
+struct Team {
+    int member, W;
+    int32_t* bar;        // arrivals (monotonic)
+    int32_t* rot;        // work-groups that rotated, summed over the sweeps (monotonic)
+    int32_t* err;        // bit 1 set when a barrier timed out
+    int target;
+};
+
+// All W work-groups of the team arrive before any leaves; global writes
+// before the barrier are visible to every member after it (release/acquire
+// at agent scope).  The wait is bounded: on timeout the error bit is set and
+// this and every later barrier return at once, so no wave ever hangs.
+__device__ void team_barrier(Team& t) {
+    t.target += t.W;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __threadfence();
+        __hip_atomic_fetch_add(t.bar, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        int spins = 0;
+        while (__hip_atomic_load(t.bar, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < t.target) {
+            if (__hip_atomic_load(t.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & 2) break;
+            __builtin_amdgcn_s_sleep(4);
+            if (++spins > (1 << 24)) {
+                __hip_atomic_fetch_or(t.err, 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                break;
+            }
+        }
+        __threadfence();
+    }
+    __syncthreads();
+}
+
+// RPT rows per thread: thread t owns rows t, t + nt, ..., t + (RPT-1) nt.
+template <typename R, int RPT>
+__device__ void block_sweeps(const LayerDesc& d, const Shared<R>& s, const BlockLds<R>& bl,
+                             int max_sweeps, double tol, Team& team, int& sweeps_out,
+                             bool& conv_out) {
+    constexpr int B = kBlk;
+    const int tid = threadIdx.x, nt = blockDim.x;
+    const int member = team.member, W = team.W;
+    const int M = d.M, N = d.N;
+    const int NB = (N + B - 1) / B, NBP = NB + (NB & 1);
+    const bool acc = s.Q != nullptr;
+    int rows[RPT];
+    bool grow[RPT], qrow[RPT];
+#pragma unroll
+    for (int r = 0; r < RPT; ++r) {
+        rows[r] = tid + r * nt;
+        grow[r] = rows[r] < M;
+        qrow[r] = acc && rows[r] < N;
+    }
+    cplx<R> ga[RPT][B], gb[RPT][B], va[RPT][B], vb[RPT][B];
+    quad<R> q[B];
+    auto load2 = [&](int ba, int bb) {
+#pragma unroll
+        for (int r = 0; r < RPT; ++r) {
+            load_block(s.G, d.ldg, ba, N, rows[r], grow[r], ga[r]);
+            load_block(s.G, d.ldg, bb, N, rows[r], grow[r], gb[r]);
+            if (acc) {
+                load_block(s.Q, d.ldv, ba, N, rows[r], qrow[r], va[r]);
+                load_block(s.Q, d.ldv, bb, N, rows[r], qrow[r], vb[r]);
+            }
+        }
+    };
+    auto store2 = [&](int ba, int bb) {
+#pragma unroll
+        for (int r = 0; r < RPT; ++r) {
+            store_block(s.G, d.ldg, ba, N, rows[r], grow[r], ga[r]);
+            store_block(s.G, d.ldg, bb, N, rows[r], grow[r], gb[r]);
+            if (acc) {
+                store_block(s.Q, d.ldv, ba, N, rows[r], qrow[r], va[r]);
+                store_block(s.Q, d.ldv, bb, N, rows[r], qrow[r], vb[r]);
+            }
+        }
+    };
+    int sweeps = 0;
+    bool converged = (N < 2);
+    while (!converged && sweeps < max_sweeps) {
+        if (tid == 0) *bl.rflag = 0;
+        __syncthreads();
+        // team: rotations counted before this sweep (all earlier increments
+        // happened before the barrier that ended the previous sweep)
+        const int rot_before =
+            W > 1 ? __hip_atomic_load(team.rot, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) : 0;
+        // ---- intra pass: pairs inside blocks 2i and 2i+1
+        for (int i = member; 2 * i < NB; i += W) {
+            const int ba = 2 * i, bb = 2 * i + 1;
+            load2(ba, bb);
+            for (int step = 0; step < B - 1; ++step) {
+#pragma unroll
+                for (int p = 0; p < B / 2; ++p) {
+                    q[p] = pair_partials(ga[0][p], ga[0][B - 1 - p]);
+                    q[B / 2 + p] = pair_partials(gb[0][p], gb[0][B - 1 - p]);
+#pragma unroll
+                    for (int r = 1; r < RPT; ++r) {
+                        const quad<R> x = pair_partials(ga[r][p], ga[r][B - 1 - p]);
+                        const quad<R> y = pair_partials(gb[r][p], gb[r][B - 1 - p]);
+                        q[p] = {q[p].a + x.a, q[p].b + x.b, q[p].c + x.c, q[p].d + x.d};
+                        q[B / 2 + p] = {q[B / 2 + p].a + y.a, q[B / 2 + p].b + y.b,
+                                        q[B / 2 + p].c + y.c, q[B / 2 + p].d + y.d};
+                    }
+                }
+                block_reduce_rotate<R>(bl, q, tol);
+#pragma unroll
+                for (int p = 0; p < B / 2; ++p) {
+                    const quad<R> ra = bl.prm[p], rb = bl.prm[B / 2 + p];
+#pragma unroll
+                    for (int r = 0; r < RPT; ++r) {
+                        rot_apply(ga[r][p], ga[r][B - 1 - p], ra.a, ra.b, ra.c);
+                        rot_apply(gb[r][p], gb[r][B - 1 - p], rb.a, rb.b, rb.c);
+                        if (acc) {
+                            rot_apply(va[r][p], va[r][B - 1 - p], ra.a, ra.b, ra.c);
+                            rot_apply(vb[r][p], vb[r][B - 1 - p], rb.a, rb.b, rb.c);
+                        }
+                    }
+                }
+                // round-robin: positions 1..B-1 move by one
+#pragma unroll
+                for (int r = 0; r < RPT; ++r) {
+                    const cplx<R> la = ga[r][B - 1], lb = gb[r][B - 1], lva = va[r][B - 1],
+                                  lvb = vb[r][B - 1];
+#pragma unroll
+                    for (int k = B - 1; k >= 2; --k) {
+                        ga[r][k] = ga[r][k - 1];
+                        gb[r][k] = gb[r][k - 1];
+                        va[r][k] = va[r][k - 1];
+                        vb[r][k] = vb[r][k - 1];
+                    }
+                    ga[r][1] = la;
+                    gb[r][1] = lb;
+                    va[r][1] = lva;
+                    vb[r][1] = lvb;
+                }
+            }
+            // B-1 steps bring every position back: store in place
+            store2(ba, bb);
+        }
+        if (W > 1) team_barrier(team);
+        // ---- cross passes: round-robin over block pairs
+        for (int os = 0; os < NBP - 1; ++os) {
+            for (int bp = member; bp < NBP / 2; bp += W) {
+                int ba, bb;
+                rr_pair(bp, os, NBP, ba, bb);
+                if (ba >= NB || bb >= NB) continue;
+                load2(ba, bb);
+                for (int t = 0; t < B; ++t) {
+#pragma unroll
+                    for (int p = 0; p < B; ++p) {
+                        q[p] = pair_partials(ga[0][p], gb[0][p]);
+#pragma unroll
+                        for (int r = 1; r < RPT; ++r) {
+                            const quad<R> x = pair_partials(ga[r][p], gb[r][p]);
+                            q[p] = {q[p].a + x.a, q[p].b + x.b, q[p].c + x.c, q[p].d + x.d};
+                        }
+                    }
+                    block_reduce_rotate<R>(bl, q, tol);
+#pragma unroll
+                    for (int p = 0; p < B; ++p) {
+                        const quad<R> rr = bl.prm[p];
+#pragma unroll
+                        for (int r = 0; r < RPT; ++r) {
+                            rot_apply(ga[r][p], gb[r][p], rr.a, rr.b, rr.c);
+                            if (acc) rot_apply(va[r][p], vb[r][p], rr.a, rr.b, rr.c);
+                        }
+                    }
+                    // block b shifts by one against block a
+#pragma unroll
+                    for (int r = 0; r < RPT; ++r) {
+                        const cplx<R> fb = gb[r][0], fv = vb[r][0];
+#pragma unroll
+                        for (int k = 0; k < B - 1; ++k) {
+                            gb[r][k] = gb[r][k + 1];
+                            vb[r][k] = vb[r][k + 1];
+                        }
+                        gb[r][B - 1] = fb;
+                        vb[r][B - 1] = fv;
+                    }
+                }
+                // B shifts bring block b back to its order
+                store2(ba, bb);
+            }
+            if (W > 1 && os < NBP - 2) team_barrier(team);
+        }
+        __syncthreads();
+        if (W > 1) {
+            if (tid == 0 && *bl.rflag)
+                __hip_atomic_fetch_add(team.rot, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            team_barrier(team);
+            converged = __hip_atomic_load(team.rot, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) ==
+                        rot_before;
+        } else {
+            converged = (*bl.rflag == 0);
+        }
+        ++sweeps;
+        __syncthreads();
+    }
+    sweeps_out = sweeps;
+    conv_out = converged;
+}
+
+template <typename R, int RPT>
+__device__ void block_one(const SvdArgs<R>& a, char* lds, int item, char* gslot, Team& team) {
+    const Target tg = target_of(a, item);
+    const bool acc = (a.d.transposed ? a.U : a.V) != nullptr;
+    const Shared<R> s = carve<R>(lds, a.d, acc, gslot);
+    const BlockLds<R> bl = carve_block<R>(lds, s.small_end);
+    if (team.member == 0) load_symbol<R>(a, s, tg.theta);
+    if (team.W > 1) team_barrier(team);
+    else __syncthreads();
+    int sweeps;
+    bool converged;
+    block_sweeps<R, RPT>(a.d, s, bl, a.max_sweeps, a.tol, team, sweeps, converged);
+    if (team.member == 0) finish<R, 64>(a, s, tg.out, tg.mirror, sweeps, converged);
+    // the slot is reused for the team's next symbol: members wait for the finish
+    if (team.W > 1) team_barrier(team);
+    if (a.info && threadIdx.x == 0 && team.member == 0 &&
+        (__hip_atomic_load(team.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & 2))
+        atomicOr(&a.info[LFA_INFO_NONFINITE], 2);
+}
+
+
+// ===================== register (rows-in-lanes) kernel =====================
+// Register-resident one-sided Jacobi SVD for symbols of at most 64 rows and
+// 64 columns (rows-in-lanes layout), gfx950.
+//
+// A work-group is one wavefront for G (plus one for the rotation accumulator
+// when singular vectors are wanted).  Lane l of the G wave owns row l of the
+// M x N working matrix G of its symbol in registers, all NC (>= N, power of
+// two) columns; with ML lanes per symbol (16, 32 or 64) one wave holds
+// 64/ML symbols.  Lane l of the second wave owns row l of the N x N
+// accumulator Q.
+//
+// One round-robin step pairs the columns at positions (p, NC-1-p),
+// p < NC/2 -- all compile-time register indices -- and then rotates the
+// positions 1..NC-1 by one (register moves).  After NC-1 steps, i.e. one
+// sweep, every column is back at its starting position, so the final column
+// order is the original one.
+//
+// Per step:
+//  1. every G lane forms its row's contributions to alpha_p = |g_j|^2,
+//     beta_p = |g_k|^2 and gamma_p = g_j^H g_k for all pairs and writes them
+//     to LDS ([symbol][row][4 * NC/2], padded row stride: conflict-free);
+//  2. lane group (p, part) of the same wave sums a slice of the rows for pair
+//     p, the parts are combined with xor shuffles; the first lane of the pair
+//     computes the rotation (threshold test and angle in double precision)
+//     and writes (c, s e^{-i phi}, flag) to a double-buffered LDS slot;
+//  3. after one work-group barrier every lane of both waves reads the
+//     parameters (broadcast) and applies the pair rotations to its registers.
+//     The Q wave only applies, so it runs a step behind the G wave and its
+//     work overlaps the next step's inner products.  A rotation that is not
+//     needed is the identity (c = 1, s = 0), applied without a branch.
+// One work-group barrier per step; no LDS traffic for G or Q themselves.
+
+
+
+template <typename R>
+__device__ __forceinline__ R skey(R v) {
+    return v == v ? v : R(-1);
+}
+
+
+template <int NC, typename T>
+__device__ __forceinline__ void rotate_positions(T (&g)[NC]) {
+    // new[1] = old[NC-1], new[i] = old[i-1] for i = 2..NC-1
+    const T last = g[NC - 1];
+#pragma unroll
+    for (int i = NC - 1; i >= 2; --i) g[i] = g[i - 1];
+    g[1] = last;
+}
+
+__device__ __forceinline__ void phase_of(const double* tw, const LayerDesc& d, int theta, int t,
+                                         double& re, double& im) {
+    const int p = theta / d.m, q = theta - (theta / d.m) * d.m;
+    const int a = t / d.kw, b = t - (t / d.kw) * d.kw;
+    const int y1 = a - (d.kh - 1) / 2, y2 = b - (d.kw - 1) / 2;
+    int i1 = (p * y1) % d.n;
+    if (i1 < 0) i1 += d.n;
+    int i2 = (q * y2) % d.m;
+    if (i2 < 0) i2 += d.m;
+    const double ar = tw[2 * (d.tw_n + i1)], ai = tw[2 * (d.tw_n + i1) + 1];
+    const double br = tw[2 * (d.tw_m + i2)], bi = tw[2 * (d.tw_m + i2) + 1];
+    re = ar * br - ai * bi;
+    im = ar * bi + ai * br;
+}
+
+template <int NC, int ML>
+struct WaveShape {
+    static constexpr int SPW = 64 / ML;   // symbols per wave
+    static constexpr int NP = NC / 2;     // pairs per step
+    static constexpr int LP = ML / NP;    // lanes summing one pair (>= 2 since NC <= ML)
+    static constexpr int RPL = NP;        // rows summed by one lane
+    static constexpr int PST = 2 * NC + 4;  // partial row stride (elements), padded
+};
+
+// Elements of the partial-sum region (it also holds the assembled symbols
+// during the load and the staged outputs during the finish: both fit in
+// SPW*ML*PST since M <= ML and N <= NC), followed by the phase table.
+template <typename R, int NC, int ML>
+constexpr int wave_part_elems() {
+    using S = WaveShape<NC, ML>;
+    return S::SPW * ML * S::PST + S::SPW * kMaxTaps * 2;
+}
+
+template <typename R, int NC, int ML>
+size_t wave_lds_bytes() {
+    using S = WaveShape<NC, ML>;
+    const size_t part = (size_t)wave_part_elems<R, NC, ML>() * sizeof(R);
+    const size_t prm = 2 * (size_t)S::SPW * S::NP * 4 * sizeof(R);   // double-buffered
+    const size_t small = (size_t)S::SPW * NC * (sizeof(R) + 2 * sizeof(int)) + 64 * sizeof(int);
+    return part + prm + small + 64;
+}
+
+// Synchronisation of the threads working on one group of symbols: the whole
+// work-group, or a single wave ("solo": a wave of a larger work-group that
+// works alone; its LDS operations complete in order).
+__device__ __forceinline__ void wsync(bool solo) {
+    if (solo) {
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+    } else {
+        __syncthreads();
+    }
+}
+
+// One group of SPW symbols (items base .. base+SPW-1) by `nthr` threads with
+// index `tid`: 64 (G only) or 128 (G wave + Q wave, not solo).
+template <typename R, int NC, int ML>
+__device__ void wave_group(const SvdArgs<R>& a, char* lds_raw, int base, int tid, int nthr,
+                           bool solo) {
+    using S = WaveShape<NC, ML>;
+    constexpr int SPW = S::SPW, NP = S::NP, LP = S::LP, RPL = S::RPL, PST = S::PST;
+    R* part = reinterpret_cast<R*>(lds_raw);                       // [SPW][ML][PST]
+    quad<R>* prm = reinterpret_cast<quad<R>*>(part + wave_part_elems<R, NC, ML>());   // [2][SPW][NP]
+    R* sigs = reinterpret_cast<R*>(prm + 2 * SPW * NP);             // [SPW][NC]
+    int* rankof = reinterpret_cast<int*>(sigs + SPW * NC);          // [SPW][NC]
+    int* nzero = rankof + SPW * NC;                                 // [SPW] zero columns
+    int* flags = nzero + SPW;                                       // [SPW] rotated this sweep
+
+    const LayerDesc& d = a.d;
+    const int lane = tid & 63;
+    const int wave = tid >> 6;                     // 0: G rows, 1: Q rows
+    const bool acc = nthr > 64;
+    const int sym = lane / ML, row = lane - (lane / ML) * ML;
+    const int M = d.M, N = d.N;
+    const int count = item_count(a);
+    const int T = d.kh * d.kw;
+    const double tol = a.tol;
+
+    {
+        const int item = base + sym;
+        const bool active = item < count;
+        const Target tg = active ? target_of(a, item) : Target{0, 0, -1};
+
+        // ---------------------------------------------------------- load
+        // The work-group assembles (or copies) the symbols of the wave into an
+        // LDS tile in G layout, [s][row][col] with ML x NC entries per symbol,
+        // zero outside M x N: G = A (row o, column i), or G = A^H (row i,
+        // column o) when c_out < c_in.  Every G lane then loads its row with
+        // constant offsets.
+        cplx<R>* tile = reinterpret_cast<cplx<R>*>(part);        // [SPW][ML][NC]
+        cplx<R>* ph = reinterpret_cast<cplx<R>*>(part + SPW * ML * PST);   // [SPW][T]
+        if (a.A == nullptr) {
+            for (int x = tid; x < SPW * T; x += nthr) {
+                const int s = x / T, t = x - (x / T) * T;
+                const int it = base + s;
+                double re = 1.0, im = 0.0;
+                if (it < count) phase_of(a.tw, d, target_of(a, it).theta, t, re, im);
+                ph[x] = {R(re), R(im)};
+            }
+            wsync(solo);
+        }
+        for (int x = tid; x < SPW * ML * NC; x += nthr) {
+            const int s = x / (ML * NC), rc = x - s * (ML * NC);
+            const int r = rc / NC, c = rc - (rc / NC) * NC;
+            const int it = base + s;
+            cplx<R> v = {R(0), R(0)};
+            if (it < count && r < M && c < N) {
+                const int o = d.transposed ? c : r, i = d.transposed ? r : c;
+                const size_t e = (size_t)o * d.c_in + i;
+                if (a.A == nullptr) {
+                    const R* w = a.W + e * T;
+                    for (int t = 0; t < T; ++t) {
+                        const R wt = w[t];
+                        const cplx<R> p = ph[s * T + t];
+                        v.x = fma(wt, p.x, v.x);
+                        v.y = fma(wt, p.y, v.y);
+                    }
+                } else {
+                    v = a.A[(size_t)target_of(a, it).theta * d.c_out * d.c_in + e];
+                }
+                if (d.transposed) v.y = -v.y;
+            }
+            tile[x] = v;
+        }
+        wsync(solo);
+        cplx<R> g[NC];
+#pragma unroll
+        for (int j = 0; j < NC; ++j) g[j] = tile[(sym * ML + row) * NC + j];
+        if (wave != 0) {
+#pragma unroll
+            for (int j = 0; j < NC; ++j) g[j] = {R(0), R(0)};
+        }
+        wsync(solo);
+        if (wave == 1) {
+            // accumulator rows: Q = I (N x N), zero beyond N
+#pragma unroll
+            for (int j = 0; j < NC; ++j) g[j] = {R((row == j && j < N) ? 1 : 0), R(0)};
+        }
+
+        // -------------------------------------------------------- sweeps
+        int sweeps = 0;
+        bool my_conv = false;       // symbol of this lane converged
+        int conv_at = 0;            // sweeps used by this lane's symbol
+        int buf = 0;                // parameter buffer of the current step
+        for (int sw = 0; sw < a.max_sweeps; ++sw) {
+            if (tid < SPW) flags[tid] = 0;
+            bool rotated = false;
+            for (int step = 0; step < NC - 1; ++step) {
+                quad<R>* prm_b = prm + buf * (SPW * NP);
+                if (wave == 0) {
+                    // 1. partial inner products of this lane's row
+#pragma unroll
+                    for (int p = 0; p < NP; ++p) {
+                        const cplx<R> x = g[p], y = g[NC - 1 - p];
+                        quad<R> q;
+                        q.a = fma(x.x, x.x, x.y * x.y);
+                        q.b = fma(y.x, y.x, y.y * y.y);
+                        q.c = fma(x.x, y.x, x.y * y.y);
+                        q.d = fma(x.x, y.y, -x.y * y.x);
+                        *reinterpret_cast<quad<R>*>(part + (sym * ML + row) * PST + 4 * p) = q;
+                        if ((p & 7) == 7) __builtin_amdgcn_sched_barrier(0);
+                    }
+                    // the partials were written by other lanes of this wave:
+                    // LDS operations of one wave complete in order
+                    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+                    __builtin_amdgcn_wave_barrier();
+                    // 2. sums over the rows, 3. rotation of pair p
+                    const int p = row % NP, k = row / NP;
+                    R s0 = 0, s1 = 0, s2 = 0, s3 = 0;
+#pragma unroll 4
+                    for (int r = 0; r < RPL; ++r) {
+                        const quad<R> q =
+                            *reinterpret_cast<const quad<R>*>(part + (sym * ML + k * RPL + r) * PST + 4 * p);
+                        s0 += q.a;
+                        s1 += q.b;
+                        s2 += q.c;
+                        s3 += q.d;
+                    }
+#pragma unroll
+                    for (int off = NP; off < ML; off <<= 1) {
+                        s0 += __shfl_xor(s0, off, 64);
+                        s1 += __shfl_xor(s1, off, 64);
+                        s2 += __shfl_xor(s2, off, 64);
+                        s3 += __shfl_xor(s3, off, 64);
+                    }
+                    if (k == 0) {
+                        const quad<R> q = rotation<R>(s0, s1, s2, s3, tol);
+                        rotated |= q.d != R(0);
+                        prm_b[sym * NP + p] = q;
+                    }
+                }
+                // parameters of this step visible to both waves; the Q wave
+                // applies step s while the G wave already works on step s+1
+                // (double-buffered parameters, one barrier per step)
+                wsync(solo);
+#pragma unroll
+                for (int p0 = 0; p0 < NP; p0 += 8) {
+#pragma unroll
+                    for (int p = p0; p < p0 + 8 && p < NP; ++p) {
+                        const quad<R> q = prm_b[sym * NP + p];
+                        rot_apply(g[p], g[NC - 1 - p], q.a, q.b, q.c);
+                    }
+                    __builtin_amdgcn_sched_barrier(0);
+                }
+                rotate_positions<NC>(g);
+                buf ^= 1;
+            }
+            ++sweeps;
+            // convergence: a sweep without rotations, per symbol
+            if (rotated) flags[sym] = 1;
+            wsync(solo);
+            const bool conv_now = flags[sym] == 0;
+            if (!my_conv && conv_now) {
+                my_conv = true;
+                conv_at = sweeps;
+            }
+            bool all = true;
+#pragma unroll
+            for (int s = 0; s < SPW; ++s) all = all && (flags[s] == 0);
+            wsync(solo);
+            if (all) break;
+        }
+        if (!my_conv) conv_at = sweeps;
+
+        // -------------------------------------------------------- finish
+        // column norms
+        if (wave == 0) {
+#pragma unroll
+            for (int j = 0; j < NC; ++j)
+                part[(sym * ML + row) * PST + j] = fma(g[j].x, g[j].x, g[j].y * g[j].y);
+        }
+        wsync(solo);
+        if (wave == 0 && row < NC) {
+            R s = 0;
+            for (int r = 0; r < ML; ++r) s += part[(sym * ML + r) * PST + row];
+            sigs[sym * NC + row] = sqrt(s);
+        }
+        wsync(solo);
+        // rank sort of the N real columns: descending, ties by index
+        if (wave == 0 && row < N) {
+            const R sj = skey(sigs[sym * NC + row]);
+            int rank = 0;
+            for (int k = 0; k < N; ++k) {
+                const R sk = skey(sigs[sym * NC + k]);
+                rank += (sk > sj) || (sk == sj && k < row);
+            }
+            rankof[sym * NC + row] = rank;
+            if (active) {
+                a.sigma[(size_t)tg.out * N + rank] = sigs[sym * NC + row];
+                if (tg.mirror >= 0) a.sigma[(size_t)tg.mirror * N + rank] = sigs[sym * NC + row];
+            }
+        }
+        if (tid < SPW) {
+            int z = 0;
+            for (int k = 0; k < N; ++k) z += sigs[tid * NC + k] == R(0);
+            nzero[tid] = z;
+        }
+        wsync(solo);
+        if (a.info && wave == 0 && row == 0 && active) {
+            atomicAdd(&a.info[LFA_INFO_SUM_SWEEPS], conv_at);
+            atomicMax(&a.info[LFA_INFO_MAX_SWEEPS], conv_at);
+            if (!my_conv) atomicAdd(&a.info[LFA_INFO_NONCONVERGED], 1);
+            bool bad = false;
+            for (int k = 0; k < N; ++k) bad |= !isfinite(sigs[sym * NC + k]);
+            if (bad) atomicOr(&a.info[LFA_INFO_NONFINITE], 1);
+        }
+        cplx<R>* left = d.transposed ? a.V : a.U;
+        cplx<R>* right = d.transposed ? a.U : a.V;
+        cplx<R>* stage = reinterpret_cast<cplx<R>*>(part);   // [SPW][M][N] output staging
+        if (left) {
+            if (wave == 0 && row < M) {
+#pragma unroll
+                for (int j = 0; j < NC; ++j) {
+                    if (j < N) {
+                        const R sj = sigs[sym * NC + j];
+                        const R inv = sj > R(0) ? R(1) / sj : R(0);
+                        stage[(size_t)(sym * M + row) * N + rankof[sym * NC + j]] = {g[j].x * inv, g[j].y * inv};
+                    }
+                    if ((j & 7) == 7) __builtin_amdgcn_sched_barrier(0);
+                }
+            }
+            wsync(solo);
+            // Columns with sigma == 0 (sorted last): orthonormal completion by
+            // two passes of classical Gram-Schmidt of unit vectors against the
+            // accepted columns, one symbol at a time, by the G wave alone
+            // (lane = row); every loop bound below is uniform over that wave.
+            if (wave == 0) {
+                for (int s = 0; s < SPW; ++s) {
+                    const int nz = nzero[s];
+                    int cand = 0;
+                    R thresh = R(0.5);
+                    for (int c = N - nz; c < N; ++c) {
+                        bool done = false;
+                        for (int tries = 0; !done && tries < 4 * M; ++tries) {
+                            if (cand == M) {
+                                cand = 0;
+                                thresh *= R(0.2);
+                            }
+                            cplx<R> x = {R(lane == cand ? 1 : 0), R(0)};
+                            for (int pass = 0; pass < 2; ++pass) {
+                                cplx<R> y = x;
+                                for (int col = 0; col < c; ++col) {
+                                    cplx<R> u = {R(0), R(0)};
+                                    if (lane < M) u = stage[(size_t)(s * M + lane) * N + col];
+                                    R cr = u.x * x.x + u.y * x.y;
+                                    R ci = u.x * x.y - u.y * x.x;
+#pragma unroll
+                                    for (int off = 32; off >= 1; off >>= 1) {
+                                        cr += __shfl_xor(cr, off, 64);
+                                        ci += __shfl_xor(ci, off, 64);
+                                    }
+                                    y.x -= cr * u.x - ci * u.y;
+                                    y.y -= cr * u.y + ci * u.x;
+                                }
+                                x = y;
+                            }
+                            R nrm = x.x * x.x + x.y * x.y;
+#pragma unroll
+                            for (int off = 32; off >= 1; off >>= 1) nrm += __shfl_xor(nrm, off, 64);
+                            nrm = sqrt(nrm);
+                            if (nrm > thresh) {
+                                if (lane < M) stage[(size_t)(s * M + lane) * N + c] = {x.x / nrm, x.y / nrm};
+                                done = true;
+                            }
+                            ++cand;
+                            // the next candidate reads the column just written
+                            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+                            __builtin_amdgcn_wave_barrier();
+                        }
+                    }
+                }
+            }
+            wsync(solo);
+            for (int e = tid; e < SPW * M * N; e += nthr) {
+                const int s = e / (M * N);
+                const int it = base + s;
+                if (it < count) {
+                    const Target t = target_of(a, it);
+                    const cplx<R> v = stage[e];
+                    left[(size_t)t.out * M * N + (e - s * M * N)] = v;
+                    if (t.mirror >= 0) left[(size_t)t.mirror * M * N + (e - s * M * N)] = {v.x, -v.y};
+                }
+            }
+            wsync(solo);
+        }
+        if (right && acc) {
+            if (wave == 1 && row < N) {
+#pragma unroll
+                for (int j = 0; j < NC; ++j)
+                    if (j < N) stage[(size_t)(sym * N + row) * N + rankof[sym * NC + j]] = g[j];
+            }
+            wsync(solo);
+            for (int e = tid; e < SPW * N * N; e += nthr) {
+                const int s = e / (N * N);
+                const int it = base + s;
+                if (it < count) {
+                    const Target t = target_of(a, it);
+                    const cplx<R> v = stage[e];
+                    right[(size_t)t.out * N * N + (e - s * N * N)] = v;
+                    if (t.mirror >= 0) right[(size_t)t.mirror * N * N + (e - s * N * N)] = {v.x, -v.y};
+                }
+            }
+            wsync(solo);
+        }
+    }
+}
+
+
+}  // namespace dev
+}  // namespace lfa

@@ -123,10 +123,15 @@ __device__ inline Target target_of(const A& a, int item) {
     return t;
 }
 
-// One item of the persistent work list: a (layer, first symbol) pair.
+// One item of the persistent work list.
+//  kind 0 ("bundle"): the work-group's waves each take SPW consecutive
+//         work items of the layer, starting at `item` (register kernel, one
+//         wave per symbol group);
+//  kind 1 ("member"): member `member` of a team of W work-groups on work item
+//         `item` of the layer (blocked kernel); `team` indexes the team's
+//         barrier counters.
 struct WorkItem {
-    int layer;
-    int theta;
+    int layer, kind, item, member, W, team;
 };
 
 constexpr int kMaxLayers = 64;        // layers per plan
@@ -221,13 +226,25 @@ hipError_t launch_adjoint_f64(const AdjointArgs<double>& a, hipStream_t s);
 // Persistent launch over a work list covering several layers.
 template <typename R>
 struct PersistentArgs {
-    SvdArgs<R> layer[kMaxLaunchLayers];   // per-layer arguments (d, pointers)
+    SvdArgs<R> layer[kMaxLaunchLayers];   // per-layer arguments (d, pointers; gws = slot base)
     int num_layers;
-    const WorkItem* items;          // device work list, largest work first
+    const WorkItem* items;          // device work list, longest first
     int num_items;
     int32_t* counter;               // device dequeue counter (cleared before launch)
-    int threads;                    // common work-group size
+    int32_t* team_counters;         // 4 per team + error word (cleared before launch)
+    int num_teams;
+    int wave_slots;                 // waves of a work-group that run bundles
+    int wave_lds;                   // LDS bytes of one wave's bundle
+    int threads;                    // work-group size (256)
 };
+constexpr int kPersistentThreads = 256;
+
+// LDS bytes of the persistent launch for the layers of `descs` (kind 1 bundles
+// with `wave_slots` waves, kind 2 blocked items with 256 threads), and the
+// number of work-groups of the launch that fit on the device at once.
+size_t persistent_lds_bytes(const LayerDesc* descs, int n, bool accumulate, int elem_bytes,
+                            int wave_slots);
+int persistent_resident(size_t lds, int elem_bytes);
 hipError_t launch_persistent_f32(const PersistentArgs<float>& a, int grid, size_t lds,
                                  hipStream_t s);
 hipError_t launch_persistent_f64(const PersistentArgs<double>& a, int grid, size_t lds,

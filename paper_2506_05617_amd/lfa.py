@@ -184,7 +184,7 @@ class Plan:
               "lfa_adjoint")
         return dW
 
-    def sigma_grad(self, Ws, idx, grad, out=None):
+    def sigma_grad(self, Ws, idx, grad, out=None, persistent=False):
         dev = self._check_weights(Ws)
         k = idx.shape[1]
         dW = out if out is not None else [
@@ -194,10 +194,11 @@ class Plan:
         d_arr, _k2 = ptr_array([x.data_ptr() for x in dW])
         idx = idx.contiguous()
         grad = grad.to(self.dtype).contiguous()
-        check(self.lib.lfa_sigma_grad(self.handle, w_arr, ctypes.c_void_p(idx.data_ptr()),
-                                      ctypes.c_void_p(grad.data_ptr()), k, d_arr,
-                                      ctypes.c_void_p(ws.data_ptr()), ctypes.c_size_t(ws.numel()),
-                                      _stream_ptr()), "lfa_sigma_grad")
+        fn = self.lib.lfa_sigma_grad_persistent if persistent else self.lib.lfa_sigma_grad
+        check(fn(self.handle, w_arr, ctypes.c_void_p(idx.data_ptr()),
+                 ctypes.c_void_p(grad.data_ptr()), k, d_arr,
+                 ctypes.c_void_p(ws.data_ptr()), ctypes.c_size_t(ws.numel()),
+                 _stream_ptr()), "lfa_sigma_grad_persistent" if persistent else "lfa_sigma_grad")
         return dW
 
     def autotune(self, Ws):
@@ -314,7 +315,7 @@ class SigmaTopK(torch.autograd.Function):
     @staticmethod
     def backward(ctx, grad_vals, _grad_idx):
         idx, *Ws = ctx.saved_tensors
-        dW = ctx.plan.sigma_grad(list(Ws), idx, grad_vals.contiguous())
+        dW = ctx.plan.sigma_grad(list(Ws), idx, grad_vals.contiguous(), persistent=True)
         return (None, None, *dW)
 
 

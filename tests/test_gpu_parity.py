@@ -249,6 +249,7 @@ def test_sigma_grad_matches_oracle_and_adjoint():
     vals, idx = plan.topk(S, k)
     g = torch.linspace(0.5, 1.5, k, device=DEV).repeat(len(layers), 1)
     dW = plan.sigma_grad(Wt, idx, g)
+    dWp = plan.sigma_grad(Wt, idx, g, persistent=True)
     # the same adjoint from full U, V of a vectors plan
     plan_uv = lfa().Plan(specs, want_u=True, want_v=True)
     _, U, V, _ = plan_uv.svd(Wt)
@@ -262,7 +263,8 @@ def test_sigma_grad_matches_oracle_and_adjoint():
         scale = np.linalg.norm(ref)
         err1 = np.linalg.norm(to_np(dW[li]) - ref) / scale
         err2 = np.linalg.norm(to_np(dW2[li]) - ref) / scale
-        assert err1 <= 1e-3 and err2 <= 1e-3, (li, err1, err2)
+        err3 = np.linalg.norm(to_np(dWp[li]) - ref) / scale
+        assert err1 <= 1e-3 and err2 <= 1e-3 and err3 <= 1e-3, (li, err1, err2, err3)
 
 
 def test_sigma_topk_autograd_finite_differences():
