@@ -46,6 +46,23 @@ METRIC = "singular values/s (with vectors) and σ-grad layers/s vs plain at σ r
 PEAK_FP32_VECTOR_TFLOPS = 157.3     # MI355X, packed FP32 (this build issues unpacked FP32: half)
 PEAK_HBM_GBS = 8000.0
 
+# HBM bytes per launch of the headline kernel from the PMC passes recorded in
+# profiles/wave_svd_kernel_single_layer_64x64_uv.md (FETCH_SIZE x 2.00 +
+# WRITE_SIZE x 1.00, calibrated with a copy of known size), valid only for the
+# kernel source they were taken on.
+HEAD_TRAFFIC = {"bytes": 2.40e6 + 269.6e6, "source_hash": "bc5ea00cf2660d2e",
+                "files": ("jacobi_device.hpp", "jacobi_wave.hip", "lfa_internal.hpp")}
+
+
+def source_hash(files):
+    import hashlib
+
+    h = hashlib.sha256()
+    for f in files:
+        with open(os.path.join(ROOT, "paper_2506_05617_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
 
 def jacobi_flops(layer, sum_sweeps: int, vectors: bool) -> float:
     """Algorithmic FLOP of the one-sided Jacobi sweeps: per column pair and
@@ -236,6 +253,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--quick", action="store_true", help="headline workload only")
+    ap.add_argument("--only", default=None,
+                    help="run one extra workload after the headline: fp64, rect, stack, large, assembly")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the LFA SVD shards over frequencies, but this build "
@@ -267,18 +286,24 @@ def main():
         "sweeps": {"sum": head["info"][2], "max": head["info"][1], "nonconverged": head["info"][0]},
         "roofline": {"bound": "alu", "kernel": "wave_svd_kernel<float,64,64> (fused assembly + Jacobi + sort/write)",
                      "achieved": achieved, "peak": PEAK_FP32_VECTOR_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_FP32_VECTOR_TFLOPS, "traffic": None,
+                     "frac": achieved / PEAK_FP32_VECTOR_TFLOPS,
+                     "traffic": (HEAD_TRAFFIC["bytes"]
+                                 if source_hash(HEAD_TRAFFIC["files"]) == HEAD_TRAFFIC["source_hash"]
+                                 else None),
                      "kernel_ms": head["kernel_ms"]},
     }
     extra = {}
+    sel = (lambda name: args.only in (None, name)) if not args.quick else (lambda name: False)
     if not args.quick:
         reps = 3
         wl = {}
+    if sel("fp64"):
         L1, W1 = workloads.single_layer_16()
         r = run_layer(L1, W1, dev, True, reps * 3, 1, dtype=torch.float64)
         extra["single_layer_16_fp64"] = r
         wl["single_layer_16_fp64"] = dict(ms=r["ms"], sigma_per_s=r["sigma_per_s"], sweeps=r["info"][1:3],
                                           vectors=True, dtype="f64")
+    if sel("rect"):
         L3, W3 = workloads.rectangular_256_512()
         for vec in (False, True):
             r = run_layer(L3, W3, dev, vec, reps, 1)
@@ -290,6 +315,7 @@ def main():
         r = run_layer(L3r, W3r, dev, True, reps, 1)
         extra["rank_one_512x256"] = r
         wl["rank_one_512x256_uv"] = dict(ms=r["ms"], sigma_per_s=r["sigma_per_s"], sweeps=r["info"][1:3])
+    if sel("stack"):
         st = bench_stack(dev, reps)
         extra["stack"] = st
         wl["resnet18_stack_sigma_grad"] = {
@@ -297,17 +323,20 @@ def main():
             "plain_layers_per_s": st["plain_layers_per_s"], "batched_layers_per_s": st["batched_layers_per_s"],
             "plain_ms": st["plain_ms"], "batched_ms": st["batched_ms"],
             "speedup_batched_vs_plain": st["batched_layers_per_s"] / st["plain_layers_per_s"]}
+    if sel("large"):
         L5, W5, _ = workloads.large_grid_7x7()
         for asm in (None, "bf16x2", "bf16x3"):
             r = run_layer(L5, W5, dev, False, reps, 1, asm=asm)
             key = "large_grid_7x7_" + (asm or "fp32")
             extra[key] = r
             wl[key] = dict(ms=r["ms"], sigma_per_s=r["sigma_per_s"], sweeps=r["info"][1:3], vectors=False)
+    if sel("assembly"):
         for asm in ("valu", "mfma", "bf16x3"):
             a = bench_assembly(dev, 5, asm)
             extra["assembly_" + asm] = a
             wl["assembly_224x224_7x7_" + asm] = dict(ms=a["ms"], hbm_gbs=a["gbs"],
                                                      frac_of_hbm_peak=a["gbs"] / PEAK_HBM_GBS)
+    if not args.quick:
         line["workloads"] = wl
     if not args.no_cpu:
         cb, errors = cpu_leg(head, extra)
