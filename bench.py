@@ -189,12 +189,14 @@ def cpu_leg(head, extra):
     def work(fr):
         return fr, oracle.lfa_svd(W64, L.n, L.m, compute_uv=True, freqs=fr)
 
-    reps = 3
+    # Whole passes over the layer until at least 10 s of wall time (>= 3).
+    reps = 0
     with threadpool_limits(limits=1):
         t0 = time.perf_counter()
-        for _ in range(reps):
+        while reps < 3 or time.perf_counter() - t0 < 10.0:
             with ThreadPoolExecutor(max_workers=cores) as ex:
                 parts = list(ex.map(work, chunks))
+            reps += 1
         secs = (time.perf_counter() - t0) / reps
     S_ref = np.zeros((L.n, L.m, L.r))
     for fr, (s, _, _) in parts:
