@@ -814,19 +814,25 @@ __device__ void block_one(const SvdArgs<R>& a, char* lds, int item, char* gslot,
 //
 // Per step:
 //  1. every G lane forms its row's contributions to alpha_p = |g_j|^2,
-//     beta_p = |g_k|^2 and gamma_p = g_j^H g_k for all pairs and writes them
-//     to LDS ([symbol][row][4 * NC/2], padded row stride: conflict-free);
-//  2. lane group (p, part) of the same wave sums a slice of the rows for pair
-//     p, the parts are combined with xor shuffles; the first lane of the pair
-//     computes the rotation (threshold test and angle in double precision)
-//     and writes (c, s e^{-i phi}, flag) to a double-buffered LDS slot;
+//     beta_p = |g_k|^2 and gamma_p = g_j^H g_k for all pairs.  Groups of NB
+//     pairs are folded across lanes by transpose-add stages (lane^32 and
+//     lane^16 register swaps): after them a lane holds one pair's four
+//     partial sums over NB rows, and the lanes of block b = row / GL hold the
+//     pairs b*Q .. b*Q+Q-1.  The folded partials go to LDS, [symbol][row][4Q]
+//     (padded row stride);
+//  2. lane (p, k) of the same wave sums Q holder rows of pair p, the LP
+//     lanes of a pair are combined with xor exchanges, and every lane of the
+//     pair evaluates the rotation (threshold test and angle in double
+//     precision); one of them writes (c, s e^{-i phi}, flag) to a
+//     double-buffered LDS slot;
 //  3. after one work-group barrier every lane of both waves reads the
-//     parameters (broadcast) and applies the pair rotations to its registers.
-//     The Q wave only applies, so it runs a step behind the G wave and its
-//     work overlaps the next step's inner products.  A rotation that is not
-//     needed is the identity (c = 1, s = 0), applied without a branch.
-// One work-group barrier per step; no LDS traffic for G or Q themselves.
-
+//     parameters (broadcast) and applies the pair rotations to its registers
+//     (a pair below the threshold gets the identity, applied without a
+//     branch).  The Q wave only applies, so it runs a step behind the G wave and its work
+//     overlaps the next step's inner products.
+// One work-group barrier per step; no LDS traffic for G or Q themselves.  The
+// symbols are assembled into registers through a small LDS tile, a chunk of
+// columns at a time, and the results are written from registers.
 
 
 template <typename R>
@@ -859,18 +865,95 @@ __device__ __forceinline__ void phase_of(const double* tw, const LayerDesc& d, i
     im = ar * bi + ai * br;
 }
 
+// ---- cross-lane exchanges (gfx950 permlane swaps) ------------------------
+// xadd32(a, b): lanes 0-31 receive a(l) + a(l+32), lanes 32-63 b(l-32) + b(l).
+// xadd16(a, b): lanes whose bit 4 is clear receive a(l) + a(l+16), the others
+// b(l-16) + b(l).  With a == b both give the sum of a lane and its partner.
+__device__ __forceinline__ float xadd32(float a, float b) {
+    const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(a), __float_as_uint(b), false, false);
+    return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+}
+__device__ __forceinline__ float xadd16(float a, float b) {
+    const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(a), __float_as_uint(b), false, false);
+    return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+}
+__device__ __forceinline__ double xadd32(double a, double b) {
+    const unsigned long long ua = __double_as_longlong(a), ub = __double_as_longlong(b);
+    const auto lo = __builtin_amdgcn_permlane32_swap((unsigned)ua, (unsigned)ub, false, false);
+    const auto hi = __builtin_amdgcn_permlane32_swap((unsigned)(ua >> 32), (unsigned)(ub >> 32), false, false);
+    return __longlong_as_double((long long)(((unsigned long long)hi[0] << 32) | lo[0])) +
+           __longlong_as_double((long long)(((unsigned long long)hi[1] << 32) | lo[1]));
+}
+__device__ __forceinline__ double xadd16(double a, double b) {
+    const unsigned long long ua = __double_as_longlong(a), ub = __double_as_longlong(b);
+    const auto lo = __builtin_amdgcn_permlane16_swap((unsigned)ua, (unsigned)ub, false, false);
+    const auto hi = __builtin_amdgcn_permlane16_swap((unsigned)(ua >> 32), (unsigned)(ub >> 32), false, false);
+    return __longlong_as_double((long long)(((unsigned long long)hi[0] << 32) | lo[0])) +
+           __longlong_as_double((long long)(((unsigned long long)hi[1] << 32) | lo[1]));
+}
+
+// v + v(lane ^ OFF)
+template <int OFF, typename R>
+__device__ __forceinline__ R xsum(R v) {
+    if constexpr (OFF == 32) return xadd32(v, v);
+    else if constexpr (OFF == 16) return xadd16(v, v);
+    else return v + __shfl_xor(v, OFF, 64);
+}
+
+// Sum over the lanes l ^ OFF, l ^ 2 OFF, ..., below LIM (xor butterfly).
+template <int OFF, int LIM, typename R>
+__device__ __forceinline__ R xsum_range(R v) {
+    if constexpr (OFF < LIM) return xsum_range<2 * OFF, LIM>(xsum<OFF>(v));
+    else return v;
+}
+
+// Transpose-add stages on NV values per lane: stage 1 (S1) folds v[i] and
+// v[i + NV/2] across lane^32, stage 2 (S2) folds the first half of what is
+// left across lane^16.  The result is in v[0 .. NV >> (S1 + S2)).
+template <int S1, int S2, typename R, int NV>
+__device__ __forceinline__ void transpose_add(R (&v)[NV]) {
+    if constexpr (S1 != 0) {
+#pragma unroll
+        for (int i = 0; i < NV / 2; ++i) v[i] = xadd32(v[i], v[i + NV / 2]);
+    }
+    if constexpr (S2 != 0) {
+        constexpr int H = (NV >> S1) / 2;
+#pragma unroll
+        for (int i = 0; i < H; ++i) v[i] = xadd16(v[i], v[i + H]);
+    }
+}
+
+constexpr int pow2_floor(int x) {
+    int p = 1;
+    while (2 * p <= x) p *= 2;
+    return p;
+}
+
 template <int NC, int ML>
 struct WaveShape {
-    static constexpr int SPW = 64 / ML;   // symbols per wave
-    static constexpr int NP = NC / 2;     // pairs per step
-    static constexpr int LP = ML / NP;    // lanes summing one pair (>= 2 since NC <= ML)
-    static constexpr int RPL = NP;        // rows summed by one lane
-    static constexpr int PST = 2 * NC + 4;  // partial row stride (elements), padded
+    static constexpr int SPW = 64 / ML;                               // symbols per wave
+    static constexpr int NP = NC / 2;                                 // pairs per step
+    static constexpr int S1 = (ML == 64 && NP >= 2) ? 1 : 0;          // lane^32 stage
+    static constexpr int S2 = (ML >= 32 && NP >= (2 << S1)) ? 1 : 0;  // lane^16 stage
+    static constexpr int NB = 1 << (S1 + S2);                         // pairs folded per group
+    static constexpr int Q = NP / NB;                                 // groups = pairs per block
+    static constexpr int VPL = 4 * Q;                                 // partials per lane in LDS
+    static constexpr int GL = ML / NB;                                // lanes holding one block
+    static constexpr int LP = ML / NP;                                // lanes summing one pair
+    static constexpr int PST = VPL + 4;                               // LDS row stride, padded
+    // column norms at the end: the same stages on NC values
+    static constexpr int S1N = (ML == 64) ? 1 : 0;
+    static constexpr int S2N = (ML >= 32 && (NC >> S1N) >= 2) ? 1 : 0;
+    static constexpr int VPLN = NC >> (S1N + S2N);
+    static constexpr int GLN = ML >> (S1N + S2N);
+    // columns per chunk of the load tile (complex, inside the partial region)
+    static constexpr int NCH = pow2_floor(PST / 2) < NC ? pow2_floor(PST / 2) : NC;
+    static_assert(VPLN <= PST, "norm partials must fit a partial row");
+    static_assert(LP * Q == GL, "reduction lanes must cover a block");
 };
 
-// Elements of the partial-sum region (it also holds the assembled symbols
-// during the load and the staged outputs during the finish: both fit in
-// SPW*ML*PST since M <= ML and N <= NC), followed by the phase table.
+// Elements (of R) of the partial region (it also holds the load tile), then
+// the phase table.
 template <typename R, int NC, int ML>
 constexpr int wave_part_elems() {
     using S = WaveShape<NC, ML>;
@@ -882,7 +965,7 @@ size_t wave_lds_bytes() {
     using S = WaveShape<NC, ML>;
     const size_t part = (size_t)wave_part_elems<R, NC, ML>() * sizeof(R);
     const size_t prm = 2 * (size_t)S::SPW * S::NP * 4 * sizeof(R);   // double-buffered
-    const size_t small = (size_t)S::SPW * NC * (sizeof(R) + 2 * sizeof(int)) + 64 * sizeof(int);
+    const size_t small = (size_t)S::SPW * NC * (sizeof(R) + sizeof(int)) + (size_t)S::SPW * 2 * sizeof(int);
     return part + prm + small + 64;
 }
 
@@ -904,7 +987,8 @@ template <typename R, int NC, int ML>
 __device__ void wave_group(const SvdArgs<R>& a, char* lds_raw, int base, int tid, int nthr,
                            bool solo) {
     using S = WaveShape<NC, ML>;
-    constexpr int SPW = S::SPW, NP = S::NP, LP = S::LP, RPL = S::RPL, PST = S::PST;
+    constexpr int SPW = S::SPW, NP = S::NP, NB = S::NB, Q = S::Q, GL = S::GL, PST = S::PST;
+    constexpr int NCH = S::NCH;
     R* part = reinterpret_cast<R*>(lds_raw);                       // [SPW][ML][PST]
     quad<R>* prm = reinterpret_cast<quad<R>*>(part + wave_part_elems<R, NC, ML>());   // [2][SPW][NP]
     R* sigs = reinterpret_cast<R*>(prm + 2 * SPW * NP);             // [SPW][NC]
@@ -915,39 +999,39 @@ __device__ void wave_group(const SvdArgs<R>& a, char* lds_raw, int base, int tid
     const LayerDesc& d = a.d;
     const int lane = tid & 63;
     const int wave = tid >> 6;                     // 0: G rows, 1: Q rows
-    const bool acc = nthr > 64;
     const int sym = lane / ML, row = lane - (lane / ML) * ML;
     const int M = d.M, N = d.N;
     const int count = item_count(a);
     const int T = d.kh * d.kw;
     const double tol = a.tol;
 
-    {
-        const int item = base + sym;
-        const bool active = item < count;
-        const Target tg = active ? target_of(a, item) : Target{0, 0, -1};
+    const int item = base + sym;
+    const bool active = item < count;
+    const Target tg = active ? target_of(a, item) : Target{0, 0, -1};
 
-        // ---------------------------------------------------------- load
-        // The work-group assembles (or copies) the symbols of the wave into an
-        // LDS tile in G layout, [s][row][col] with ML x NC entries per symbol,
-        // zero outside M x N: G = A (row o, column i), or G = A^H (row i,
-        // column o) when c_out < c_in.  Every G lane then loads its row with
-        // constant offsets.
-        cplx<R>* tile = reinterpret_cast<cplx<R>*>(part);        // [SPW][ML][NC]
-        cplx<R>* ph = reinterpret_cast<cplx<R>*>(part + SPW * ML * PST);   // [SPW][T]
-        if (a.A == nullptr) {
-            for (int x = tid; x < SPW * T; x += nthr) {
-                const int s = x / T, t = x - (x / T) * T;
-                const int it = base + s;
-                double re = 1.0, im = 0.0;
-                if (it < count) phase_of(a.tw, d, target_of(a, it).theta, t, re, im);
-                ph[x] = {R(re), R(im)};
-            }
-            wsync(solo);
+    // ---------------------------------------------------------------- load
+    // The work-group assembles (or copies) the symbols of the wave into an LDS
+    // tile in G layout, [s][row][col], NCH columns at a time, zero outside
+    // M x N: G = A (row o, column i), or G = A^H (row i, column o) when
+    // c_out < c_in.  Every G lane then loads its row with constant offsets.
+    cplx<R>* tile = reinterpret_cast<cplx<R>*>(part);        // [SPW][ML][NCH]
+    cplx<R>* ph = reinterpret_cast<cplx<R>*>(part + SPW * ML * PST);   // [SPW][T]
+    if (a.A == nullptr) {
+        for (int x = tid; x < SPW * T; x += nthr) {
+            const int s = x / T, t = x - (x / T) * T;
+            const int it = base + s;
+            double re = 1.0, im = 0.0;
+            if (it < count) phase_of(a.tw, d, target_of(a, it).theta, t, re, im);
+            ph[x] = {R(re), R(im)};
         }
-        for (int x = tid; x < SPW * ML * NC; x += nthr) {
-            const int s = x / (ML * NC), rc = x - s * (ML * NC);
-            const int r = rc / NC, c = rc - (rc / NC) * NC;
+        wsync(solo);
+    }
+    cplx<R> g[NC];
+#pragma unroll
+    for (int c0 = 0; c0 < NC; c0 += NCH) {
+        for (int x = tid; x < SPW * ML * NCH; x += nthr) {
+            const int s = x / (ML * NCH), rc = x - s * (ML * NCH);
+            const int r = rc / NCH, c = c0 + (rc - (rc / NCH) * NCH);
             const int it = base + s;
             cplx<R> v = {R(0), R(0)};
             if (it < count && r < M && c < N) {
@@ -969,246 +1053,247 @@ __device__ void wave_group(const SvdArgs<R>& a, char* lds_raw, int base, int tid
             tile[x] = v;
         }
         wsync(solo);
-        cplx<R> g[NC];
 #pragma unroll
-        for (int j = 0; j < NC; ++j) g[j] = tile[(sym * ML + row) * NC + j];
-        if (wave != 0) {
-#pragma unroll
-            for (int j = 0; j < NC; ++j) g[j] = {R(0), R(0)};
-        }
+        for (int jj = 0; jj < NCH; ++jj) g[c0 + jj] = tile[(sym * ML + row) * NCH + jj];
         wsync(solo);
-        if (wave == 1) {
-            // accumulator rows: Q = I (N x N), zero beyond N
+    }
+    if (wave == 1) {
+        // accumulator rows: Q = I (N x N), zero beyond N
 #pragma unroll
-            for (int j = 0; j < NC; ++j) g[j] = {R((row == j && j < N) ? 1 : 0), R(0)};
-        }
+        for (int j = 0; j < NC; ++j) g[j] = {R((row == j && j < N) ? 1 : 0), R(0)};
+    }
 
-        // -------------------------------------------------------- sweeps
-        int sweeps = 0;
-        bool my_conv = false;       // symbol of this lane converged
-        int conv_at = 0;            // sweeps used by this lane's symbol
-        int buf = 0;                // parameter buffer of the current step
-        for (int sw = 0; sw < a.max_sweeps; ++sw) {
-            if (tid < SPW) flags[tid] = 0;
-            bool rotated = false;
-            for (int step = 0; step < NC - 1; ++step) {
-                quad<R>* prm_b = prm + buf * (SPW * NP);
-                if (wave == 0) {
-                    // 1. partial inner products of this lane's row
-#pragma unroll
-                    for (int p = 0; p < NP; ++p) {
-                        const cplx<R> x = g[p], y = g[NC - 1 - p];
-                        quad<R> q;
-                        q.a = fma(x.x, x.x, x.y * x.y);
-                        q.b = fma(y.x, y.x, y.y * y.y);
-                        q.c = fma(x.x, y.x, x.y * y.y);
-                        q.d = fma(x.x, y.y, -x.y * y.x);
-                        *reinterpret_cast<quad<R>*>(part + (sym * ML + row) * PST + 4 * p) = q;
-                        if ((p & 7) == 7) __builtin_amdgcn_sched_barrier(0);
-                    }
-                    // the partials were written by other lanes of this wave:
-                    // LDS operations of one wave complete in order
-                    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-                    __builtin_amdgcn_wave_barrier();
-                    // 2. sums over the rows, 3. rotation of pair p
-                    const int p = row % NP, k = row / NP;
-                    R s0 = 0, s1 = 0, s2 = 0, s3 = 0;
-#pragma unroll 4
-                    for (int r = 0; r < RPL; ++r) {
-                        const quad<R> q =
-                            *reinterpret_cast<const quad<R>*>(part + (sym * ML + k * RPL + r) * PST + 4 * p);
-                        s0 += q.a;
-                        s1 += q.b;
-                        s2 += q.c;
-                        s3 += q.d;
-                    }
-#pragma unroll
-                    for (int off = NP; off < ML; off <<= 1) {
-                        s0 += __shfl_xor(s0, off, 64);
-                        s1 += __shfl_xor(s1, off, 64);
-                        s2 += __shfl_xor(s2, off, 64);
-                        s3 += __shfl_xor(s3, off, 64);
-                    }
-                    if (k == 0) {
-                        const quad<R> q = rotation<R>(s0, s1, s2, s3, tol);
-                        rotated |= q.d != R(0);
-                        prm_b[sym * NP + p] = q;
-                    }
-                }
-                // parameters of this step visible to both waves; the Q wave
-                // applies step s while the G wave already works on step s+1
-                // (double-buffered parameters, one barrier per step)
-                wsync(solo);
-#pragma unroll
-                for (int p0 = 0; p0 < NP; p0 += 8) {
-#pragma unroll
-                    for (int p = p0; p < p0 + 8 && p < NP; ++p) {
-                        const quad<R> q = prm_b[sym * NP + p];
-                        rot_apply(g[p], g[NC - 1 - p], q.a, q.b, q.c);
-                    }
-                    __builtin_amdgcn_sched_barrier(0);
-                }
-                rotate_positions<NC>(g);
-                buf ^= 1;
-            }
-            ++sweeps;
-            // convergence: a sweep without rotations, per symbol
-            if (rotated) flags[sym] = 1;
-            wsync(solo);
-            const bool conv_now = flags[sym] == 0;
-            if (!my_conv && conv_now) {
-                my_conv = true;
-                conv_at = sweeps;
-            }
-            bool all = true;
-#pragma unroll
-            for (int s = 0; s < SPW; ++s) all = all && (flags[s] == 0);
-            wsync(solo);
-            if (all) break;
-        }
-        if (!my_conv) conv_at = sweeps;
-
-        // -------------------------------------------------------- finish
-        // column norms
-        if (wave == 0) {
-#pragma unroll
-            for (int j = 0; j < NC; ++j)
-                part[(sym * ML + row) * PST + j] = fma(g[j].x, g[j].x, g[j].y * g[j].y);
-        }
-        wsync(solo);
-        if (wave == 0 && row < NC) {
-            R s = 0;
-            for (int r = 0; r < ML; ++r) s += part[(sym * ML + r) * PST + row];
-            sigs[sym * NC + row] = sqrt(s);
-        }
-        wsync(solo);
-        // rank sort of the N real columns: descending, ties by index
-        if (wave == 0 && row < N) {
-            const R sj = skey(sigs[sym * NC + row]);
-            int rank = 0;
-            for (int k = 0; k < N; ++k) {
-                const R sk = skey(sigs[sym * NC + k]);
-                rank += (sk > sj) || (sk == sj && k < row);
-            }
-            rankof[sym * NC + row] = rank;
-            if (active) {
-                a.sigma[(size_t)tg.out * N + rank] = sigs[sym * NC + row];
-                if (tg.mirror >= 0) a.sigma[(size_t)tg.mirror * N + rank] = sigs[sym * NC + row];
-            }
-        }
-        if (tid < SPW) {
-            int z = 0;
-            for (int k = 0; k < N; ++k) z += sigs[tid * NC + k] == R(0);
-            nzero[tid] = z;
-        }
-        wsync(solo);
-        if (a.info && wave == 0 && row == 0 && active) {
-            atomicAdd(&a.info[LFA_INFO_SUM_SWEEPS], conv_at);
-            atomicMax(&a.info[LFA_INFO_MAX_SWEEPS], conv_at);
-            if (!my_conv) atomicAdd(&a.info[LFA_INFO_NONCONVERGED], 1);
-            bool bad = false;
-            for (int k = 0; k < N; ++k) bad |= !isfinite(sigs[sym * NC + k]);
-            if (bad) atomicOr(&a.info[LFA_INFO_NONFINITE], 1);
-        }
-        cplx<R>* left = d.transposed ? a.V : a.U;
-        cplx<R>* right = d.transposed ? a.U : a.V;
-        cplx<R>* stage = reinterpret_cast<cplx<R>*>(part);   // [SPW][M][N] output staging
-        if (left) {
-            if (wave == 0 && row < M) {
-#pragma unroll
-                for (int j = 0; j < NC; ++j) {
-                    if (j < N) {
-                        const R sj = sigs[sym * NC + j];
-                        const R inv = sj > R(0) ? R(1) / sj : R(0);
-                        stage[(size_t)(sym * M + row) * N + rankof[sym * NC + j]] = {g[j].x * inv, g[j].y * inv};
-                    }
-                    if ((j & 7) == 7) __builtin_amdgcn_sched_barrier(0);
-                }
-            }
-            wsync(solo);
-            // Columns with sigma == 0 (sorted last): orthonormal completion by
-            // two passes of classical Gram-Schmidt of unit vectors against the
-            // accepted columns, one symbol at a time, by the G wave alone
-            // (lane = row); every loop bound below is uniform over that wave.
+    // -------------------------------------------------------------- sweeps
+    int sweeps = 0;
+    bool my_conv = false;       // symbol of this lane converged
+    int conv_at = 0;            // sweeps used by this lane's symbol
+    int buf = 0;                // parameter buffer of the current step
+    for (int sw = 0; sw < a.max_sweeps; ++sw) {
+        if (tid < SPW) flags[tid] = 0;
+        bool rotated = false;
+        for (int step = 0; step < NC - 1; ++step) {
+            quad<R>* prm_b = prm + buf * (SPW * NP);
             if (wave == 0) {
-                for (int s = 0; s < SPW; ++s) {
-                    const int nz = nzero[s];
-                    int cand = 0;
-                    R thresh = R(0.5);
-                    for (int c = N - nz; c < N; ++c) {
-                        bool done = false;
-                        for (int tries = 0; !done && tries < 4 * M; ++tries) {
-                            if (cand == M) {
-                                cand = 0;
-                                thresh *= R(0.2);
-                            }
-                            cplx<R> x = {R(lane == cand ? 1 : 0), R(0)};
-                            for (int pass = 0; pass < 2; ++pass) {
-                                cplx<R> y = x;
-                                for (int col = 0; col < c; ++col) {
-                                    cplx<R> u = {R(0), R(0)};
-                                    if (lane < M) u = stage[(size_t)(s * M + lane) * N + col];
-                                    R cr = u.x * x.x + u.y * x.y;
-                                    R ci = u.x * x.y - u.y * x.x;
+                // 1. partial inner products, folded across lanes by groups of
+                //    NB pairs (gi + b Q, b < NB)
 #pragma unroll
-                                    for (int off = 32; off >= 1; off >>= 1) {
-                                        cr += __shfl_xor(cr, off, 64);
-                                        ci += __shfl_xor(ci, off, 64);
-                                    }
-                                    y.x -= cr * u.x - ci * u.y;
-                                    y.y -= cr * u.y + ci * u.x;
-                                }
-                                x = y;
-                            }
-                            R nrm = x.x * x.x + x.y * x.y;
+                for (int gi = 0; gi < Q; ++gi) {
+                    R v[4 * NB];
 #pragma unroll
-                            for (int off = 32; off >= 1; off >>= 1) nrm += __shfl_xor(nrm, off, 64);
-                            nrm = sqrt(nrm);
-                            if (nrm > thresh) {
-                                if (lane < M) stage[(size_t)(s * M + lane) * N + c] = {x.x / nrm, x.y / nrm};
-                                done = true;
-                            }
-                            ++cand;
-                            // the next candidate reads the column just written
-                            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-                            __builtin_amdgcn_wave_barrier();
-                        }
+                    for (int b = 0; b < NB; ++b) {
+                        const cplx<R> x = g[gi + b * Q], y = g[NC - 1 - gi - b * Q];
+                        v[4 * b + 0] = fma(x.x, x.x, x.y * x.y);
+                        v[4 * b + 1] = fma(y.x, y.x, y.y * y.y);
+                        v[4 * b + 2] = fma(x.x, y.x, x.y * y.y);
+                        v[4 * b + 3] = fma(x.x, y.y, -x.y * y.x);
                     }
+                    transpose_add<S::S1, S::S2>(v);
+                    *reinterpret_cast<quad<R>*>(part + (sym * ML + row) * PST + 4 * gi) =
+                        quad<R>{v[0], v[1], v[2], v[3]};
+                    if ((gi & 1) == 1) __builtin_amdgcn_sched_barrier(0);
                 }
-            }
-            wsync(solo);
-            for (int e = tid; e < SPW * M * N; e += nthr) {
-                const int s = e / (M * N);
-                const int it = base + s;
-                if (it < count) {
-                    const Target t = target_of(a, it);
-                    const cplx<R> v = stage[e];
-                    left[(size_t)t.out * M * N + (e - s * M * N)] = v;
-                    if (t.mirror >= 0) left[(size_t)t.mirror * M * N + (e - s * M * N)] = {v.x, -v.y};
-                }
-            }
-            wsync(solo);
-        }
-        if (right && acc) {
-            if (wave == 1 && row < N) {
+                // the partials were written by other lanes of this wave:
+                // LDS operations of one wave complete in order
+                __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                // 2. sums over the holder rows of pair p, 3. its rotation
+                const int p = row % NP, k = row / NP;
+                const R* src = part + (sym * ML + (p / Q) * GL + k * Q) * PST + 4 * (p % Q);
+                R s0 = 0, s1 = 0, s2 = 0, s3 = 0;
 #pragma unroll
-                for (int j = 0; j < NC; ++j)
-                    if (j < N) stage[(size_t)(sym * N + row) * N + rankof[sym * NC + j]] = g[j];
-            }
-            wsync(solo);
-            for (int e = tid; e < SPW * N * N; e += nthr) {
-                const int s = e / (N * N);
-                const int it = base + s;
-                if (it < count) {
-                    const Target t = target_of(a, it);
-                    const cplx<R> v = stage[e];
-                    right[(size_t)t.out * N * N + (e - s * N * N)] = v;
-                    if (t.mirror >= 0) right[(size_t)t.mirror * N * N + (e - s * N * N)] = {v.x, -v.y};
+                for (int r = 0; r < Q; ++r) {
+                    const quad<R> q = *reinterpret_cast<const quad<R>*>(src + r * PST);
+                    s0 += q.a;
+                    s1 += q.b;
+                    s2 += q.c;
+                    s3 += q.d;
                 }
+                s0 = xsum_range<NP, ML>(s0);
+                s1 = xsum_range<NP, ML>(s1);
+                s2 = xsum_range<NP, ML>(s2);
+                s3 = xsum_range<NP, ML>(s3);
+                const quad<R> q = rotation<R>(s0, s1, s2, s3, tol);
+                const bool rot = q.d != R(0);
+                rotated |= rot;
+                if (k == 0) prm_b[sym * NP + p] = q;
             }
+            // parameters of this step visible to both waves; the Q wave
+            // applies step s while the G wave already works on step s+1
+            // (double-buffered parameters, one barrier per step)
             wsync(solo);
+#pragma unroll
+            for (int p0 = 0; p0 < NP; p0 += 8) {
+#pragma unroll
+                for (int p = p0; p < p0 + 8 && p < NP; ++p) {
+                    const quad<R> q = prm_b[sym * NP + p];
+                    rot_apply(g[p], g[NC - 1 - p], q.a, q.b, q.c);
+                }
+                __builtin_amdgcn_sched_barrier(0);
+            }
+            rotate_positions<NC>(g);
+            buf ^= 1;
+        }
+        ++sweeps;
+        // convergence: a sweep without rotations, per symbol
+        if (rotated) flags[sym] = 1;
+        wsync(solo);
+        const bool conv_now = flags[sym] == 0;
+        if (!my_conv && conv_now) {
+            my_conv = true;
+            conv_at = sweeps;
+        }
+        bool all = true;
+#pragma unroll
+        for (int s = 0; s < SPW; ++s) all = all && (flags[s] == 0);
+        wsync(solo);
+        if (all) break;
+    }
+    if (!my_conv) conv_at = sweeps;
+
+    // -------------------------------------------------------------- finish
+    // column norms: |g_j|^2 folded across lanes, then summed over the holders
+    if (wave == 0) {
+        R nv[NC];
+#pragma unroll
+        for (int j = 0; j < NC; ++j) nv[j] = fma(g[j].x, g[j].x, g[j].y * g[j].y);
+        transpose_add<S::S1N, S::S2N>(nv);
+#pragma unroll
+        for (int i = 0; i < S::VPLN; ++i) part[(sym * ML + row) * PST + i] = nv[i];
+    }
+    wsync(solo);
+    if (wave == 0 && row < NC) {
+        const int b = row / S::VPLN, slot = row - (row / S::VPLN) * S::VPLN;
+        R s = 0;
+        for (int h = 0; h < S::GLN; ++h) s += part[(sym * ML + b * S::GLN + h) * PST + slot];
+        sigs[sym * NC + row] = sqrt(s);
+    }
+    wsync(solo);
+    // rank sort of the N real columns: descending, ties by index
+    if (wave == 0 && row < N) {
+        const R sj = skey(sigs[sym * NC + row]);
+        int rank = 0;
+        for (int k = 0; k < N; ++k) {
+            const R sk = skey(sigs[sym * NC + k]);
+            rank += (sk > sj) || (sk == sj && k < row);
+        }
+        rankof[sym * NC + row] = rank;
+        if (active) {
+            a.sigma[(size_t)tg.out * N + rank] = sigs[sym * NC + row];
+            if (tg.mirror >= 0) a.sigma[(size_t)tg.mirror * N + rank] = sigs[sym * NC + row];
         }
     }
+    if (tid < SPW) {
+        int z = 0;
+        for (int k = 0; k < N; ++k) z += sigs[tid * NC + k] == R(0);
+        nzero[tid] = z;
+    }
+    wsync(solo);
+    if (a.info && wave == 0 && row == 0 && active) {
+        atomicAdd(&a.info[LFA_INFO_SUM_SWEEPS], conv_at);
+        atomicMax(&a.info[LFA_INFO_MAX_SWEEPS], conv_at);
+        if (!my_conv) atomicAdd(&a.info[LFA_INFO_NONCONVERGED], 1);
+        bool bad = false;
+        for (int k = 0; k < N; ++k) bad |= !isfinite(sigs[sym * NC + k]);
+        if (bad) atomicOr(&a.info[LFA_INFO_NONFINITE], 1);
+    }
+    cplx<R>* left = d.transposed ? a.V : a.U;
+    cplx<R>* right = d.transposed ? a.U : a.V;
+    if (left && wave == 0) {
+        // u_j = g_j / sigma_j; columns with sigma_j == 0 are zero here
+        bool accd[NC];
+#pragma unroll
+        for (int j = 0; j < NC; ++j) {
+            const R sj = sigs[sym * NC + j];
+            const R inv = (j < N && sj > R(0)) ? R(1) / sj : R(0);
+            g[j] = {g[j].x * inv, g[j].y * inv};
+            accd[j] = j < N && sj != R(0);
+        }
+        int nzmax = 0;
+#pragma unroll
+        for (int s = 0; s < SPW; ++s) nzmax = max(nzmax, nzero[s]);
+        // Columns with sigma == 0 (sorted last, by index): orthonormal
+        // completion by two passes of classical Gram-Schmidt of unit vectors
+        // e_cand against the accepted columns.  Every lane keeps its own row;
+        // inner products are sums over the ML lanes of its symbol, and every
+        // loop bound is uniform over the wave (symbols with fewer zero
+        // columns idle through the extra iterations).
+        for (int c = 0; c < nzmax; ++c) {
+            int jz = -1, cnt = 0;
+#pragma unroll
+            for (int j = 0; j < NC; ++j) {
+                if (j < N && sigs[sym * NC + j] == R(0)) {
+                    if (cnt == c) jz = j;
+                    ++cnt;
+                }
+            }
+            bool done = jz < 0;
+            int cand = 0;
+            R thresh = R(0.5);
+            for (int tries = 0; tries < 4 * M; ++tries) {
+                if (__all(done)) break;
+                if (cand == M) {
+                    cand = 0;
+                    thresh *= R(0.2);
+                }
+                cplx<R> x = {R(row == cand ? 1 : 0), R(0)};
+                for (int pass = 0; pass < 2; ++pass) {
+                    cplx<R> y = x;
+#pragma unroll
+                    for (int j = 0; j < NC; ++j) {
+                        R cr = g[j].x * x.x + g[j].y * x.y;
+                        R ci = g[j].x * x.y - g[j].y * x.x;
+                        cr = xsum_range<1, ML>(cr);
+                        ci = xsum_range<1, ML>(ci);
+                        if (!accd[j]) {
+                            cr = R(0);
+                            ci = R(0);
+                        }
+                        y.x -= cr * g[j].x - ci * g[j].y;
+                        y.y -= cr * g[j].y + ci * g[j].x;
+                    }
+                    x = y;
+                }
+                const R nrm = sqrt(xsum_range<1, ML>(x.x * x.x + x.y * x.y));
+                if (!done && nrm > thresh) {
+#pragma unroll
+                    for (int j = 0; j < NC; ++j) {
+                        if (j == jz) {
+                            g[j] = {x.x / nrm, x.y / nrm};
+                            accd[j] = true;
+                        }
+                    }
+                    done = true;
+                }
+                if (!done) ++cand;
+            }
+        }
+        if (active && row < M) {
+            cplx<R>* out = left + (size_t)tg.out * M * N + (size_t)row * N;
+            cplx<R>* mir = tg.mirror >= 0 ? left + (size_t)tg.mirror * M * N + (size_t)row * N : nullptr;
+#pragma unroll
+            for (int j = 0; j < NC; ++j) {
+                if (j < N) {
+                    const int rk = rankof[sym * NC + j];
+                    out[rk] = g[j];
+                    if (mir) mir[rk] = {g[j].x, -g[j].y};
+                }
+            }
+        }
+    }
+    if (right && wave == 1 && active && row < N) {
+        cplx<R>* out = right + (size_t)tg.out * N * N + (size_t)row * N;
+        cplx<R>* mir = tg.mirror >= 0 ? right + (size_t)tg.mirror * N * N + (size_t)row * N : nullptr;
+#pragma unroll
+        for (int j = 0; j < NC; ++j) {
+            if (j < N) {
+                const int rk = rankof[sym * NC + j];
+                out[rk] = g[j];
+                if (mir) mir[rk] = {g[j].x, -g[j].y};
+            }
+        }
+    }
+    // the LDS of this group is reused by the next one
+    wsync(solo);
 }
 
 

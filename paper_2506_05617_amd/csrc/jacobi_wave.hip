@@ -10,7 +10,7 @@ namespace {
 using namespace dev;
 
 template <typename R, int NC, int ML>
-__global__ void __launch_bounds__(128) wave_svd_kernel(SvdArgs<R> a) {
+__device__ __forceinline__ void wave_svd_body(const SvdArgs<R>& a) {
     extern __shared__ __align__(16) char lds_raw[];
     using S = WaveShape<NC, ML>;
     const int count = item_count(a);
@@ -18,15 +18,39 @@ __global__ void __launch_bounds__(128) wave_svd_kernel(SvdArgs<R> a) {
         wave_group<R, NC, ML>(a, lds_raw, base, threadIdx.x, blockDim.x, false);
 }
 
+// FP64: the registers of a whole SIMD lane if needed (one wave per SIMD).
+template <typename R, int NC, int ML>
+__global__ void __launch_bounds__(128) wave_svd_kernel(SvdArgs<R> a) {
+    wave_svd_body<R, NC, ML>(a);
+}
+
+// FP32: at most 256 VGPRs, so that two waves share a SIMD and hide each
+// other's LDS and barrier latency.
+template <int NC, int ML>
+__global__ void __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(2, 2)))
+wave_svd_kernel_f32(SvdArgs<float> a) {
+    wave_svd_body<float, NC, ML>(a);
+}
+
+template <typename K>
+hipError_t allow_wave_lds(K kernel, size_t lds) {
+    if (lds <= 65536) return hipSuccess;
+    return hipFuncSetAttribute(reinterpret_cast<const void*>(kernel),
+                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+}
+
 template <typename R, int NC, int ML>
 hipError_t launch_wave_t(const SvdArgs<R>& a, int grid, hipStream_t st) {
     const size_t lds = wave_lds_bytes<R, NC, ML>();
-    if (lds > 65536) {
-        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(wave_svd_kernel<R, NC, ML>),
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if constexpr (sizeof(R) == 4) {
+        hipError_t e = allow_wave_lds(wave_svd_kernel_f32<NC, ML>, lds);
         if (e != hipSuccess) return e;
+        hipLaunchKernelGGL((wave_svd_kernel_f32<NC, ML>), dim3(grid), dim3(a.d.threads), lds, st, a);
+    } else {
+        hipError_t e = allow_wave_lds(wave_svd_kernel<R, NC, ML>, lds);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL((wave_svd_kernel<R, NC, ML>), dim3(grid), dim3(a.d.threads), lds, st, a);
     }
-    hipLaunchKernelGGL((wave_svd_kernel<R, NC, ML>), dim3(grid), dim3(a.d.threads), lds, st, a);
     return hipGetLastError();
 }
 
