@@ -813,18 +813,22 @@ __device__ void block_one(const SvdArgs<R>& a, char* lds, int item, char* gslot,
 // order is the original one.
 //
 // Per step:
-//  1. every G lane forms its row's contributions to alpha_p = |g_j|^2,
-//     beta_p = |g_k|^2 and gamma_p = g_j^H g_k for all pairs.  Groups of NB
-//     pairs are folded across lanes by transpose-add stages (lane^32 and
-//     lane^16 register swaps): after them a lane holds one pair's four
-//     partial sums over NB rows, and the lanes of block b = row / GL hold the
-//     pairs b*Q .. b*Q+Q-1.  The folded partials go to LDS, [symbol][row][4Q]
-//     (padded row stride);
+//  1. every G lane forms its row's contributions to gamma_p = g_j^H g_k for
+//     all pairs.  Groups of NB pairs are folded across lanes by transpose-add
+//     stages (lane^32 and lane^16 register swaps): after them a lane holds
+//     one pair's partial sum over NB rows, and the lanes of block b = row /
+//     GL hold the pairs b*Q .. b*Q+Q-1.  The folded partials go to LDS,
+//     [symbol][row][2Q] (padded row stride);
 //  2. lane (p, k) of the same wave sums Q holder rows of pair p, the LP
 //     lanes of a pair are combined with xor exchanges, and every lane of the
 //     pair evaluates the rotation (threshold test and angle in double
-//     precision); one of them writes (c, s e^{-i phi}, flag) to a
-//     double-buffered LDS slot;
+//     precision) from gamma_p and the squared norms alpha = |g_j|^2,
+//     beta = |g_k|^2.  The norms are not summed again each step: they are
+//     computed exactly at the start of every sweep and updated with each
+//     rotation (alpha - t|gamma|, beta + t|gamma|), so the convergence test
+//     of the final, rotation-free sweep uses exact norms.  One lane of the
+//     pair's set writes (c, s e^{-i phi}, flag) to a double-buffered LDS
+//     slot;
 //  3. after one work-group barrier every lane of both waves reads the
 //     parameters (broadcast) and applies the pair rotations to its registers
 //     (a pair below the threshold gets the identity, applied without a
@@ -937,10 +941,10 @@ struct WaveShape {
     static constexpr int S2 = (ML >= 32 && NP >= (2 << S1)) ? 1 : 0;  // lane^16 stage
     static constexpr int NB = 1 << (S1 + S2);                         // pairs folded per group
     static constexpr int Q = NP / NB;                                 // groups = pairs per block
-    static constexpr int VPL = 4 * Q;                                 // partials per lane in LDS
+    static constexpr int VPL = 2 * Q;                                 // partials per lane in LDS
     static constexpr int GL = ML / NB;                                // lanes holding one block
     static constexpr int LP = ML / NP;                                // lanes summing one pair
-    static constexpr int PST = VPL + 4;                               // LDS row stride, padded
+    static constexpr int PST = VPL + 2;                               // LDS row stride, padded
     // column norms at the end: the same stages on NC values
     static constexpr int S1N = (ML == 64) ? 1 : 0;
     static constexpr int S2N = (ML >= 32 && (NC >> S1N) >= 2) ? 1 : 0;
@@ -965,7 +969,8 @@ size_t wave_lds_bytes() {
     using S = WaveShape<NC, ML>;
     const size_t part = (size_t)wave_part_elems<R, NC, ML>() * sizeof(R);
     const size_t prm = 2 * (size_t)S::SPW * S::NP * 4 * sizeof(R);   // double-buffered
-    const size_t small = (size_t)S::SPW * NC * (sizeof(R) + sizeof(int)) + (size_t)S::SPW * 2 * sizeof(int);
+    const size_t small = (size_t)S::SPW * NC * (sizeof(double) + sizeof(R) + sizeof(int)) +
+                         (size_t)S::SPW * 2 * sizeof(int);
     return part + prm + small + 64;
 }
 
@@ -981,6 +986,30 @@ __device__ __forceinline__ void wsync(bool solo) {
     }
 }
 
+// Squared column norms of the G rows held by one wave: |g_j|^2 folded across
+// lanes into the partial region; after the wave's LDS writes are complete,
+// column_norm() sums the holder rows of column j (lanes with row < NC).
+template <typename R, int NC, int ML>
+__device__ __forceinline__ void fold_column_norms(const cplx<R> (&g)[NC], R* part, int sym, int row) {
+    using S = WaveShape<NC, ML>;
+    R nv[NC];
+#pragma unroll
+    for (int j = 0; j < NC; ++j) nv[j] = fma(g[j].x, g[j].x, g[j].y * g[j].y);
+    transpose_add<S::S1N, S::S2N>(nv);
+#pragma unroll
+    for (int i = 0; i < S::VPLN; ++i) part[(sym * ML + row) * S::PST + i] = nv[i];
+}
+
+template <typename R, int NC, int ML>
+__device__ __forceinline__ R column_norm(const R* part, int sym, int j) {
+    using S = WaveShape<NC, ML>;
+    const int b = j / S::VPLN, slot = j - (j / S::VPLN) * S::VPLN;
+    R s = 0;
+#pragma unroll 4
+    for (int h = 0; h < S::GLN; ++h) s += part[(sym * ML + b * S::GLN + h) * S::PST + slot];
+    return s;
+}
+
 // One group of SPW symbols (items base .. base+SPW-1) by `nthr` threads with
 // index `tid`: 64 (G only) or 128 (G wave + Q wave, not solo).
 template <typename R, int NC, int ML>
@@ -991,14 +1020,15 @@ __device__ void wave_group(const SvdArgs<R>& a, char* lds_raw, int base, int tid
     constexpr int NCH = S::NCH;
     R* part = reinterpret_cast<R*>(lds_raw);                       // [SPW][ML][PST]
     quad<R>* prm = reinterpret_cast<quad<R>*>(part + wave_part_elems<R, NC, ML>());   // [2][SPW][NP]
-    R* sigs = reinterpret_cast<R*>(prm + 2 * SPW * NP);             // [SPW][NC]
+    double* nrm = reinterpret_cast<double*>(prm + 2 * SPW * NP);    // [SPW][NC] |g_j|^2 (tracked)
+    R* sigs = reinterpret_cast<R*>(nrm + SPW * NC);                 // [SPW][NC]
     int* rankof = reinterpret_cast<int*>(sigs + SPW * NC);          // [SPW][NC]
     int* nzero = rankof + SPW * NC;                                 // [SPW] zero columns
     int* flags = nzero + SPW;                                       // [SPW] rotated this sweep
 
     const LayerDesc& d = a.d;
     const int lane = tid & 63;
-    const int wave = tid >> 6;                     // 0: G rows, 1: Q rows
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);   // 0: G rows, 1: Q rows
     const int sym = lane / ML, row = lane - (lane / ML) * ML;
     const int M = d.M, N = d.N;
     const int count = item_count(a);
@@ -1071,51 +1101,64 @@ __device__ void wave_group(const SvdArgs<R>& a, char* lds_raw, int base, int tid
     for (int sw = 0; sw < a.max_sweeps; ++sw) {
         if (tid < SPW) flags[tid] = 0;
         bool rotated = false;
+        if (wave == 0) {
+            // exact squared column norms at the start of every sweep; the
+            // steps update them with each rotation
+            fold_column_norms<R, NC, ML>(g, part, sym, row);
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            if (row < NC) nrm[sym * NC + row] = double(column_norm<R, NC, ML>(part, sym, row));
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+        }
         for (int step = 0; step < NC - 1; ++step) {
             quad<R>* prm_b = prm + buf * (SPW * NP);
             if (wave == 0) {
-                // 1. partial inner products, folded across lanes by groups of
-                //    NB pairs (gi + b Q, b < NB)
+                // 1. partial inner products gamma_p = g_j^H g_k, folded across
+                //    lanes by groups of NB pairs (gi + b Q, b < NB)
 #pragma unroll
                 for (int gi = 0; gi < Q; ++gi) {
-                    R v[4 * NB];
+                    R v[2 * NB];
 #pragma unroll
                     for (int b = 0; b < NB; ++b) {
                         const cplx<R> x = g[gi + b * Q], y = g[NC - 1 - gi - b * Q];
-                        v[4 * b + 0] = fma(x.x, x.x, x.y * x.y);
-                        v[4 * b + 1] = fma(y.x, y.x, y.y * y.y);
-                        v[4 * b + 2] = fma(x.x, y.x, x.y * y.y);
-                        v[4 * b + 3] = fma(x.x, y.y, -x.y * y.x);
+                        v[2 * b + 0] = fma(x.x, y.x, x.y * y.y);
+                        v[2 * b + 1] = fma(x.x, y.y, -x.y * y.x);
                     }
                     transpose_add<S::S1, S::S2>(v);
-                    *reinterpret_cast<quad<R>*>(part + (sym * ML + row) * PST + 4 * gi) =
-                        quad<R>{v[0], v[1], v[2], v[3]};
-                    if ((gi & 1) == 1) __builtin_amdgcn_sched_barrier(0);
+                    *reinterpret_cast<cplx<R>*>(part + (sym * ML + row) * PST + 2 * gi) = cplx<R>{v[0], v[1]};
+                    if ((gi & 3) == 3) __builtin_amdgcn_sched_barrier(0);
                 }
                 // the partials were written by other lanes of this wave:
                 // LDS operations of one wave complete in order
                 __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
                 __builtin_amdgcn_wave_barrier();
-                // 2. sums over the holder rows of pair p, 3. its rotation
+                // 2. sums over the holder rows of pair p, 3. its rotation from
+                //    the tracked norms of the two columns at positions p and
+                //    NC-1-p (column c sits at position 1 + (c - 1 + step) mod
+                //    (NC - 1) during step `step`; column 0 stays at 0)
                 const int p = row % NP, k = row / NP;
-                const R* src = part + (sym * ML + (p / Q) * GL + k * Q) * PST + 4 * (p % Q);
-                R s0 = 0, s1 = 0, s2 = 0, s3 = 0;
+                const R* src = part + (sym * ML + (p / Q) * GL + k * Q) * PST + 2 * (p % Q);
+                R s0 = 0, s1 = 0;
 #pragma unroll
                 for (int r = 0; r < Q; ++r) {
-                    const quad<R> q = *reinterpret_cast<const quad<R>*>(src + r * PST);
-                    s0 += q.a;
-                    s1 += q.b;
-                    s2 += q.c;
-                    s3 += q.d;
+                    const cplx<R> q = *reinterpret_cast<const cplx<R>*>(src + r * PST);
+                    s0 += q.x;
+                    s1 += q.y;
                 }
                 s0 = xsum_range<NP, ML>(s0);
                 s1 = xsum_range<NP, ML>(s1);
-                s2 = xsum_range<NP, ML>(s2);
-                s3 = xsum_range<NP, ML>(s3);
-                const quad<R> q = rotation<R>(s0, s1, s2, s3, tol);
-                const bool rot = q.d != R(0);
-                rotated |= rot;
-                if (k == 0) prm_b[sym * NP + p] = q;
+                int cj = p - 1 - step, ck = NC - 2 - p - step;
+                cj = p == 0 ? 0 : 1 + (cj < 0 ? cj + (NC - 1) : cj);
+                ck = 1 + (ck < 0 ? ck + (NC - 1) : ck);
+                double al = nrm[sym * NC + cj], be = nrm[sym * NC + ck];
+                const quad<R> q = rotation_tracked<R>(al, be, s0, s1, tol);
+                rotated |= q.d != R(0);
+                // the LP lanes of a pair hold identical sums, parameters and
+                // norms: all of them store (same value, same address)
+                prm_b[sym * NP + p] = q;
+                nrm[sym * NC + cj] = al;
+                nrm[sym * NC + ck] = be;
             }
             // parameters of this step visible to both waves; the Q wave
             // applies step s while the G wave already works on step s+1
@@ -1152,21 +1195,9 @@ __device__ void wave_group(const SvdArgs<R>& a, char* lds_raw, int base, int tid
 
     // -------------------------------------------------------------- finish
     // column norms: |g_j|^2 folded across lanes, then summed over the holders
-    if (wave == 0) {
-        R nv[NC];
-#pragma unroll
-        for (int j = 0; j < NC; ++j) nv[j] = fma(g[j].x, g[j].x, g[j].y * g[j].y);
-        transpose_add<S::S1N, S::S2N>(nv);
-#pragma unroll
-        for (int i = 0; i < S::VPLN; ++i) part[(sym * ML + row) * PST + i] = nv[i];
-    }
+    if (wave == 0) fold_column_norms<R, NC, ML>(g, part, sym, row);
     wsync(solo);
-    if (wave == 0 && row < NC) {
-        const int b = row / S::VPLN, slot = row - (row / S::VPLN) * S::VPLN;
-        R s = 0;
-        for (int h = 0; h < S::GLN; ++h) s += part[(sym * ML + b * S::GLN + h) * PST + slot];
-        sigs[sym * NC + row] = sqrt(s);
-    }
+    if (wave == 0 && row < NC) sigs[sym * NC + row] = sqrt(column_norm<R, NC, ML>(part, sym, row));
     wsync(solo);
     // rank sort of the N real columns: descending, ties by index
     if (wave == 0 && row < N) {

@@ -89,6 +89,39 @@ __device__ __forceinline__ quad<R> rotation(R al, R be, R gr, R gi, double tol) 
     return q;
 }
 
+// As rotation(), from squared column norms al = |g_j|^2 and be = |g_k|^2 that
+// the caller tracks instead of recomputing: the rotation maps them to
+// al - t |gamma| and be + t |gamma| (t = tan of the rotation angle), which
+// are returned through al and be (al clamped at 0; unchanged without a
+// rotation).
+template <typename R>
+__device__ __forceinline__ quad<R> rotation_tracked(double& al, double& be, R gr, R gi, double tol) {
+    const double g2 = double(gr) * double(gr) + double(gi) * double(gi);
+    quad<R> q = {R(1), R(0), R(0), R(0)};
+    if (!(g2 > tol * tol * (al * be))) return q;
+    double rg, t, c;
+    if constexpr (sizeof(R) == 4) {
+        rg = __builtin_amdgcn_rsq(g2);                                // 1/|gamma|
+        const double z = 0.5 * (be - al) * rg;                        // zeta
+        const double az = fabs(z);
+        const double w = fma(az, az, 1.0);
+        t = copysign(__builtin_amdgcn_rcp(az + w * __builtin_amdgcn_rsq(w)), z);
+        c = __builtin_amdgcn_rsq(fma(t, t, 1.0));
+    } else {
+        const double gg = sqrt(g2);
+        rg = 1.0 / gg;
+        const double z = (be - al) / (2.0 * gg);
+        t = copysign(1.0, z) / (fabs(z) + sqrt(1.0 + z * z));
+        c = 1.0 / sqrt(1.0 + t * t);
+    }
+    const double sn = c * t * rg;
+    const double tg = t * g2 * rg;                                    // t |gamma|
+    al = fmax(al - tg, 0.0);
+    be = be + tg;
+    q = {R(c), R(sn * double(gr)), R(-sn * double(gi)), R(1)};
+    return q;
+}
+
 // Work item -> (frequency decomposed, output position, mirror output or -1).
 // Real weights give A_{-k} = conj(A_k): sigma(-k) = sigma(k), U_{-k} =
 // conj(U_k), V_{-k} = conj(V_k), so one symbol per conjugate pair is enough.
