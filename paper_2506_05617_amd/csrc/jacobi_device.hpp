@@ -927,6 +927,20 @@ __device__ __forceinline__ void transpose_add(R (&v)[NV]) {
     }
 }
 
+// Column held at register position `pos` during round-robin step `step` of a
+// sweep (positions 1..NC-1 rotate by one per step; position 0 is fixed).
+template <int NC>
+__device__ __forceinline__ int col_at(int pos, int step) {
+    if (pos == 0) return 0;
+    const int c = pos - 1 - step;
+    return 1 + (c < 0 ? c + (NC - 1) : c);
+}
+
+// Steps between two foldings of the column scales into the stored columns:
+// a column is rotated at most once per step and each rotation multiplies its
+// scale by c >= 1/sqrt(2), so stored entries stay within 2^16 of the true ones.
+constexpr int kWaveRenorm = 32;
+
 constexpr int pow2_floor(int x) {
     int p = 1;
     while (2 * p <= x) p *= 2;
@@ -969,7 +983,7 @@ size_t wave_lds_bytes() {
     using S = WaveShape<NC, ML>;
     const size_t part = (size_t)wave_part_elems<R, NC, ML>() * sizeof(R);
     const size_t prm = 2 * (size_t)S::SPW * S::NP * 4 * sizeof(R);   // double-buffered
-    const size_t small = (size_t)S::SPW * NC * (sizeof(double) + sizeof(R) + sizeof(int)) +
+    const size_t small = (size_t)S::SPW * NC * (sizeof(double) + 3 * sizeof(R) + sizeof(int)) +
                          (size_t)S::SPW * 2 * sizeof(int);
     return part + prm + small + 64;
 }
@@ -1020,8 +1034,9 @@ __device__ void wave_group(const SvdArgs<R>& a, char* lds_raw, int base, int tid
     constexpr int NCH = S::NCH;
     R* part = reinterpret_cast<R*>(lds_raw);                       // [SPW][ML][PST]
     quad<R>* prm = reinterpret_cast<quad<R>*>(part + wave_part_elems<R, NC, ML>());   // [2][SPW][NP]
-    double* nrm = reinterpret_cast<double*>(prm + 2 * SPW * NP);    // [SPW][NC] |g_j|^2 (tracked)
-    R* sigs = reinterpret_cast<R*>(nrm + SPW * NC);                 // [SPW][NC]
+    double* nrm = reinterpret_cast<double*>(prm + 2 * SPW * NP);    // [SPW][NC] |G_j|^2 (tracked)
+    R* dsc = reinterpret_cast<R*>(nrm + SPW * NC);                  // [2][SPW][NC] column scales
+    R* sigs = dsc + 2 * SPW * NC;                                   // [SPW][NC]
     int* rankof = reinterpret_cast<int*>(sigs + SPW * NC);          // [SPW][NC]
     int* nzero = rankof + SPW * NC;                                 // [SPW] zero columns
     int* flags = nzero + SPW;                                       // [SPW] rotated this sweep
@@ -1092,6 +1107,17 @@ __device__ void wave_group(const SvdArgs<R>& a, char* lds_raw, int base, int tid
 #pragma unroll
         for (int j = 0; j < NC; ++j) g[j] = {R((row == j && j < N) ? 1 : 0), R(0)};
     }
+    // Columns of G and of Q are stored scaled: true column = stored * d_j
+    // (the same d_j for G and Q).  A sweep runs in segments of kWaveRenorm
+    // steps; at the start of a segment both waves fold the scales of the
+    // previous segment into their stored columns and the rotations of the
+    // segment update the other buffer, so the Q wave (a step behind) never
+    // reads a scale the G wave is changing.  Both buffers start at 1.
+    if (wave == 0 && row < NC) {
+        dsc[sym * NC + row] = R(1);
+        dsc[SPW * NC + sym * NC + row] = R(1);
+    }
+    int cur = 0;                // scale buffer of the current segment
 
     // -------------------------------------------------------------- sweeps
     int sweeps = 0;
@@ -1101,80 +1127,100 @@ __device__ void wave_group(const SvdArgs<R>& a, char* lds_raw, int base, int tid
     for (int sw = 0; sw < a.max_sweeps; ++sw) {
         if (tid < SPW) flags[tid] = 0;
         bool rotated = false;
-        if (wave == 0) {
-            // exact squared column norms at the start of every sweep; the
-            // steps update them with each rotation
-            fold_column_norms<R, NC, ML>(g, part, sym, row);
-            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-            __builtin_amdgcn_wave_barrier();
-            if (row < NC) nrm[sym * NC + row] = double(column_norm<R, NC, ML>(part, sym, row));
-            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-            __builtin_amdgcn_wave_barrier();
-        }
-        for (int step = 0; step < NC - 1; ++step) {
-            quad<R>* prm_b = prm + buf * (SPW * NP);
+        for (int seg0 = 0; seg0 < NC - 1; seg0 += kWaveRenorm) {
+            // segment start: fold the previous segment's scales (positions
+            // of step seg0) into G and Q, start the new scales at 1
+            const R* dprev = dsc + cur * (SPW * NC);
+            cur ^= 1;
+            R* dcur = dsc + cur * (SPW * NC);
+#pragma unroll
+            for (int pos = 0; pos < NC; ++pos) {
+                const R f = dprev[sym * NC + col_at<NC>(pos, seg0)];
+                g[pos] = {g[pos].x * f, g[pos].y * f};
+            }
             if (wave == 0) {
-                // 1. partial inner products gamma_p = g_j^H g_k, folded across
-                //    lanes by groups of NB pairs (gi + b Q, b < NB)
-#pragma unroll
-                for (int gi = 0; gi < Q; ++gi) {
-                    R v[2 * NB];
-#pragma unroll
-                    for (int b = 0; b < NB; ++b) {
-                        const cplx<R> x = g[gi + b * Q], y = g[NC - 1 - gi - b * Q];
-                        v[2 * b + 0] = fma(x.x, y.x, x.y * y.y);
-                        v[2 * b + 1] = fma(x.x, y.y, -x.y * y.x);
-                    }
-                    transpose_add<S::S1, S::S2>(v);
-                    *reinterpret_cast<cplx<R>*>(part + (sym * ML + row) * PST + 2 * gi) = cplx<R>{v[0], v[1]};
-                    if ((gi & 3) == 3) __builtin_amdgcn_sched_barrier(0);
+                if (row < NC) dcur[sym * NC + row] = R(1);
+                if (seg0 == 0) {
+                    // exact squared column norms at the start of every
+                    // sweep; the steps update them with each rotation
+                    fold_column_norms<R, NC, ML>(g, part, sym, row);
+                    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+                    __builtin_amdgcn_wave_barrier();
+                    if (row < NC) nrm[sym * NC + row] = double(column_norm<R, NC, ML>(part, sym, row));
                 }
-                // the partials were written by other lanes of this wave:
-                // LDS operations of one wave complete in order
                 __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
                 __builtin_amdgcn_wave_barrier();
-                // 2. sums over the holder rows of pair p, 3. its rotation from
-                //    the tracked norms of the two columns at positions p and
-                //    NC-1-p (column c sits at position 1 + (c - 1 + step) mod
-                //    (NC - 1) during step `step`; column 0 stays at 0)
-                const int p = row % NP, k = row / NP;
-                const R* src = part + (sym * ML + (p / Q) * GL + k * Q) * PST + 2 * (p % Q);
-                R s0 = 0, s1 = 0;
-#pragma unroll
-                for (int r = 0; r < Q; ++r) {
-                    const cplx<R> q = *reinterpret_cast<const cplx<R>*>(src + r * PST);
-                    s0 += q.x;
-                    s1 += q.y;
-                }
-                s0 = xsum_range<NP, ML>(s0);
-                s1 = xsum_range<NP, ML>(s1);
-                int cj = p - 1 - step, ck = NC - 2 - p - step;
-                cj = p == 0 ? 0 : 1 + (cj < 0 ? cj + (NC - 1) : cj);
-                ck = 1 + (ck < 0 ? ck + (NC - 1) : ck);
-                double al = nrm[sym * NC + cj], be = nrm[sym * NC + ck];
-                const quad<R> q = rotation_tracked<R>(al, be, s0, s1, tol);
-                rotated |= q.d != R(0);
-                // the LP lanes of a pair hold identical sums, parameters and
-                // norms: all of them store (same value, same address)
-                prm_b[sym * NP + p] = q;
-                nrm[sym * NC + cj] = al;
-                nrm[sym * NC + ck] = be;
             }
-            // parameters of this step visible to both waves; the Q wave
-            // applies step s while the G wave already works on step s+1
-            // (double-buffered parameters, one barrier per step)
-            wsync(solo);
+            const int seg1 = seg0 + kWaveRenorm < NC - 1 ? seg0 + kWaveRenorm : NC - 1;
+            for (int step = seg0; step < seg1; ++step) {
+                quad<R>* prm_b = prm + buf * (SPW * NP);
+                if (wave == 0) {
+                    // 1. partial inner products gamma_p = g_j^H g_k (stored
+                    //    columns), folded across lanes by groups of NB pairs
+                    //    (gi + b Q, b < NB)
 #pragma unroll
-            for (int p0 = 0; p0 < NP; p0 += 8) {
+                    for (int gi = 0; gi < Q; ++gi) {
+                        R v[2 * NB];
 #pragma unroll
-                for (int p = p0; p < p0 + 8 && p < NP; ++p) {
-                    const quad<R> q = prm_b[sym * NP + p];
-                    rot_apply(g[p], g[NC - 1 - p], q.a, q.b, q.c);
+                        for (int b = 0; b < NB; ++b) {
+                            const cplx<R> x = g[gi + b * Q], y = g[NC - 1 - gi - b * Q];
+                            v[2 * b + 0] = fma(x.x, y.x, x.y * y.y);
+                            v[2 * b + 1] = fma(x.x, y.y, -x.y * y.x);
+                        }
+                        transpose_add<S::S1, S::S2>(v);
+                        *reinterpret_cast<cplx<R>*>(part + (sym * ML + row) * PST + 2 * gi) =
+                            cplx<R>{v[0], v[1]};
+                        if ((gi & 3) == 3) __builtin_amdgcn_sched_barrier(0);
+                    }
+                    // the partials were written by other lanes of this wave:
+                    // LDS operations of one wave complete in order
+                    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+                    __builtin_amdgcn_wave_barrier();
+                    // 2. sums over the holder rows of pair p, 3. its rotation
+                    //    from the tracked norms and scales of the columns at
+                    //    positions p and NC-1-p
+                    const int p = row % NP, k = row / NP;
+                    const R* src = part + (sym * ML + (p / Q) * GL + k * Q) * PST + 2 * (p % Q);
+                    R s0 = 0, s1 = 0;
+#pragma unroll
+                    for (int r = 0; r < Q; ++r) {
+                        const cplx<R> q = *reinterpret_cast<const cplx<R>*>(src + r * PST);
+                        s0 += q.x;
+                        s1 += q.y;
+                    }
+                    s0 = xsum_range<NP, ML>(s0);
+                    s1 = xsum_range<NP, ML>(s1);
+                    const int cj = col_at<NC>(p, step), ck = col_at<NC>(NC - 1 - p, step);
+                    double al = nrm[sym * NC + cj], be = nrm[sym * NC + ck];
+                    R dj = dcur[sym * NC + cj], dk = dcur[sym * NC + ck];
+                    const double gs = double(dj) * double(dk);   // true gamma = d_j d_k gamma
+                    quad<R> q;
+                    rotated |= rotation_scaled<R>(al, be, double(s0) * gs, double(s1) * gs, tol, dj, dk, q);
+                    // the LP lanes of a pair hold identical sums, parameters,
+                    // norms and scales: all of them store (same value, same
+                    // address)
+                    prm_b[sym * NP + p] = q;
+                    nrm[sym * NC + cj] = al;
+                    nrm[sym * NC + ck] = be;
+                    dcur[sym * NC + cj] = dj;
+                    dcur[sym * NC + ck] = dk;
                 }
-                __builtin_amdgcn_sched_barrier(0);
+                // parameters of this step visible to both waves; the Q wave
+                // applies step s while the G wave already works on step s+1
+                // (double-buffered parameters, one barrier per step)
+                wsync(solo);
+#pragma unroll
+                for (int p0 = 0; p0 < NP; p0 += 8) {
+#pragma unroll
+                    for (int p = p0; p < p0 + 8 && p < NP; ++p) {
+                        const quad<R> q = prm_b[sym * NP + p];
+                        rot_apply_scaled(g[p], g[NC - 1 - p], q.a, q.b, q.c, q.d);
+                    }
+                    __builtin_amdgcn_sched_barrier(0);
+                }
+                rotate_positions<NC>(g);
+                buf ^= 1;
             }
-            rotate_positions<NC>(g);
-            buf ^= 1;
         }
         ++sweeps;
         // convergence: a sweep without rotations, per symbol
@@ -1194,6 +1240,13 @@ __device__ void wave_group(const SvdArgs<R>& a, char* lds_raw, int base, int tid
     if (!my_conv) conv_at = sweeps;
 
     // -------------------------------------------------------------- finish
+    // true columns of G and Q: fold the last segment's scales (positions
+    // are the identity after a whole sweep; the G wave no longer changes them)
+#pragma unroll
+    for (int j = 0; j < NC; ++j) {
+        const R f = dsc[cur * (SPW * NC) + sym * NC + j];
+        g[j] = {g[j].x * f, g[j].y * f};
+    }
     // column norms: |g_j|^2 folded across lanes, then summed over the holders
     if (wave == 0) fold_column_norms<R, NC, ML>(g, part, sym, row);
     wsync(solo);

@@ -122,6 +122,71 @@ __device__ __forceinline__ quad<R> rotation_tracked(double& al, double& be, R gr
     return q;
 }
 
+// Scaled ("fast") form of the rotation for columns stored as g_j = G_j / d_j
+// with per-column scale factors d_j.  gr, gi is the true gamma (of G).  The
+// true rotation G_j' = c G_j - sn G_k, G_k' = c G_k + conj(sn) G_j becomes,
+// with the scales multiplied by c, g_j' = g_j - tau1 g_k and
+// g_k' = g_k + tau2 g_j (tau = sn / c, tau1 = tau d_k/d_j,
+// tau2 = conj(tau) d_j/d_k): two complex multiply-adds per row instead of
+// four real-by-complex products.  Returns (tau1, tau2) in q, updates the
+// tracked squared norms (as rotation_tracked) and the scales, or leaves
+// everything unchanged and returns the identity (zeros) below the threshold.
+template <typename R>
+__device__ __forceinline__ bool rotation_scaled(double& al, double& be, double gr, double gi, double tol,
+                                                R& dj, R& dk, quad<R>& q) {
+    q = {R(0), R(0), R(0), R(0)};
+    const double g2 = gr * gr + gi * gi;
+    if (!(g2 > tol * tol * (al * be))) return false;
+    double rg, t, c, rjk, rkj;
+    if constexpr (sizeof(R) == 4) {
+        // The tangent t only selects the rotation and may be approximate.
+        // What makes the applied transform orthogonal is c = 1/sqrt(1+t^2)
+        // for that t and consistent 1/|gamma|, d_k/d_j and d_j/d_k: the
+        // hardware reciprocal (square root) approximations are refined by one
+        // Newton step each, to about 2^-46.
+        rg = __builtin_amdgcn_rsq(g2);                                // 1/|gamma|
+        rg = rg * fma(-0.5 * g2 * rg, rg, 1.5);
+        const double z = 0.5 * (be - al) * rg;                        // zeta
+        const double az = fabs(z);
+        const double w = fma(az, az, 1.0);
+        t = copysign(__builtin_amdgcn_rcp(az + w * __builtin_amdgcn_rsq(w)), z);
+        const double w1 = fma(t, t, 1.0);
+        c = __builtin_amdgcn_rsq(w1);
+        c = c * fma(-0.5 * w1 * c, c, 1.5);
+        double ij = __builtin_amdgcn_rcp(double(dj)), ik = __builtin_amdgcn_rcp(double(dk));
+        ij = fma(ij, fma(-double(dj), ij, 1.0), ij);
+        ik = fma(ik, fma(-double(dk), ik, 1.0), ik);
+        rjk = double(dk) * ij;
+        rkj = double(dj) * ik;
+    } else {
+        const double gg = sqrt(g2);
+        rg = 1.0 / gg;
+        const double z = (be - al) / (2.0 * gg);
+        t = copysign(1.0, z) / (fabs(z) + sqrt(1.0 + z * z));
+        c = 1.0 / sqrt(1.0 + t * t);
+        rjk = double(dk) / double(dj);
+        rkj = double(dj) / double(dk);
+    }
+    const double tg = t * g2 * rg;                                    // t |gamma|
+    al = fmax(al - tg, 0.0);
+    be = be + tg;
+    const double tr = t * gr * rg, ti = -t * gi * rg;                 // tau = t conj(gamma)/|gamma|
+    q = {R(tr * rjk), R(ti * rjk), R(tr * rkj), R(-ti * rkj)};
+    dj = R(c * double(dj));
+    dk = R(c * double(dk));
+    return true;
+}
+
+// g_j' = g_j - tau1 g_k, g_k' = g_k + tau2 g_j (see rotation_scaled).
+template <typename R>
+__device__ __forceinline__ void rot_apply_scaled(cplx<R>& x, cplx<R>& y, R t1r, R t1i, R t2r, R t2i) {
+    const cplx<R> xv = x, yv = y;
+    x.x = fma(-t1r, yv.x, fma(t1i, yv.y, xv.x));
+    x.y = fma(-t1r, yv.y, fma(-t1i, yv.x, xv.y));
+    y.x = fma(t2r, xv.x, fma(-t2i, xv.y, yv.x));
+    y.y = fma(t2r, xv.y, fma(t2i, xv.x, yv.y));
+}
+
 // Work item -> (frequency decomposed, output position, mirror output or -1).
 // Real weights give A_{-k} = conj(A_k): sigma(-k) = sigma(k), U_{-k} =
 // conj(U_k), V_{-k} = conj(V_k), so one symbol per conjugate pair is enough.
