@@ -54,6 +54,12 @@ HEAD_TRAFFIC = {"bytes": 2.40e6 + 269.6e6, "source_hash": "bc5ea00cf2660d2e",
                 "files": ("jacobi_device.hpp", "jacobi_wave.hip", "lfa_internal.hpp")}
 
 
+# The paper's LFA wall-clock times for c = 16 (sigma only; Xeon Gold 6242,
+# 16 cores, NumPy), Table II: context for the paper-scale workload.
+PAPER_TABLE2_SECONDS = {256: 2.30, 512: 8.49, 1024: 33.01, 2048: 130.20, 4096: 520.21,
+                        8192: 2077.44, 16384: 7521.93}
+
+
 def source_hash(files):
     import hashlib
 
@@ -256,7 +262,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--quick", action="store_true", help="headline workload only")
     ap.add_argument("--only", default=None,
-                    help="run one extra workload after the headline: fp64, rect, stack, large, assembly")
+                    help="run one extra workload after the headline: fp64, rect, stack, large, "
+                         "assembly, paper")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the LFA SVD shards over frequencies, but this build "
@@ -338,6 +345,17 @@ def main():
             extra["assembly_" + asm] = a
             wl["assembly_224x224_7x7_" + asm] = dict(ms=a["ms"], hbm_gbs=a["gbs"],
                                                      frac_of_hbm_peak=a["gbs"] / PEAK_HBM_GBS)
+    if sel("paper"):
+        # the paper's own runtime study (Tables II, III): c = 16, 3x3, sigma only
+        for n in (1024, 16384):
+            Lp, Wp = workloads.paper_scale(n)
+            r = run_layer(Lp, Wp, dev, False, 2 if n > 4096 else reps, 1)
+            key = f"paper_scale_c16_n{n}"
+            extra[key] = r
+            wl[key] = dict(ms=r["ms"], sigma_per_s=r["sigma_per_s"], sweeps=r["info"][1:3], vectors=False,
+                           paper_cpu_seconds=PAPER_TABLE2_SECONDS[n],
+                           paper_hardware="Xeon Gold 6242, 16 cores, NumPy (Table II)",
+                           speedup_vs_paper=PAPER_TABLE2_SECONDS[n] / (r["ms"] * 1e-3))
     if not args.quick:
         line["workloads"] = wl
     if not args.no_cpu:

@@ -80,14 +80,11 @@ struct lfa_plan {
     std::vector<double> tw_host;          // (re, im) pairs
     std::vector<WorkItem> items;          // persistent work list, LPT order per chunk
     std::vector<int> chunk_first;         // first item of each chunk of layers (+ end)
-    std::vector<int32_t> canon_host;      // canonical frequencies of every layer, concatenated
-    std::vector<int> canon_off;           // offset of each layer in canon_host
     double tol = 0;
     std::mutex mu;
     int device = -1;
     double* tw_dev = nullptr;
     WorkItem* items_dev = nullptr;
-    int32_t* canon_dev = nullptr;
     int num_cus = 0;
     // persistent launch: slots of the blocked layers, team counters, schedule
     std::vector<size_t> pers_slot_off;    // byte offset of each layer's slots (blocked layers)
@@ -358,9 +355,6 @@ int ensure_device(lfa_plan* p) {
     HIP_TRY(hipMalloc(&p->tw_dev, p->tw_host.size() * sizeof(double)));
     HIP_TRY(hipMemcpy(p->tw_dev, p->tw_host.data(), p->tw_host.size() * sizeof(double),
                       hipMemcpyHostToDevice));
-    HIP_TRY(hipMalloc(&p->canon_dev, std::max<size_t>(1, p->canon_host.size()) * sizeof(int32_t)));
-    HIP_TRY(hipMemcpy(p->canon_dev, p->canon_host.data(), p->canon_host.size() * sizeof(int32_t),
-                      hipMemcpyHostToDevice));
     // Devices reporting less LDS than the plan assumed: move layers to global slots.
     const size_t lds_dev = prop.sharedMemPerBlock;
     const int eb = elem_bytes(p->dtype);
@@ -385,10 +379,10 @@ template <typename R>
 int run_svd_layer(const lfa_plan* p, const LayerDesc& d, const void* W, const void* A,
                   void* sigma, void* U, void* V, int32_t* info, char* region,
                   const int32_t* theta_list, int theta_stride, int theta_count,
-                  hipStream_t st, const int32_t* canon = nullptr) {
+                  hipStream_t st, bool canon = false) {
     SvdArgs<R> a{};
     a.d = d;
-    a.canon = theta_list ? nullptr : canon;
+    a.canon = theta_list ? 0 : (canon ? 1 : 0);
     a.W = static_cast<const R*>(W);
     a.A = static_cast<const cplx<R>*>(A);
     a.sigma = static_cast<R*>(sigma);
@@ -477,7 +471,7 @@ int svd_impl(const lfa_plan* p, const void* const* W, const void* const* A, void
         }
         // weights are real: decompose one symbol per conjugate pair.  Symbols
         // handed in by the caller carry no such guarantee.
-        const int32_t* canon = A ? nullptr : p->canon_dev + p->canon_off[i];
+        const bool canon = A == nullptr;
         LFA_TRY(run_svd_layer<R>(p, d, Wi, Ai, sigma[i], wu ? U[i] : nullptr,
                                  wv ? V[i] : nullptr,
                                  info ? info + i * LFA_INFO_WORDS : nullptr, slots, nullptr, 0, 0,
@@ -523,7 +517,7 @@ int persistent_impl(const lfa_plan* p, const void* const* W, void* const* sigma,
             a.tw = p->tw_dev;
             a.max_sweeps = kMaxSweeps;
             a.tol = jacobi_tol(p->tol, d.M);
-            a.canon = p->canon_dev + p->canon_off[i];
+            a.canon = 1;
             if (d.kind == 2) {
                 a.slot_bytes = (long long)slot_bytes(d, acc, sizeof(R));
                 a.gws = slots + p->pers_slot_off[i];
@@ -848,22 +842,10 @@ int lfa_plan_create(lfa_plan** out, const lfa_layer* layers, int32_t num_layers,
             }
         }
     }
-    // canonical frequencies: index t with t <= index of its mirror -k
-    for (const lfa_layer& l : p->layers) {
-        p->canon_off.push_back((int)p->canon_host.size());
-        for (int t = 0; t < l.n * l.m; ++t) {
-            const int pp = t / l.m, qq = t % l.m;
-            const int mi = ((l.n - pp) % l.n) * l.m + (l.m - qq) % l.m;
-            if (t <= mi) p->canon_host.push_back(t);
-        }
-    }
     const bool wu = flags & LFA_WANT_U, wv = flags & LFA_WANT_V;
-    int li = 0;
     for (const lfa_layer& l : p->layers) {
-        const int ncanon = (li + 1 < (int)p->canon_off.size() ? p->canon_off[li + 1]
-                                                               : (int)p->canon_host.size()) -
-                           p->canon_off[li];
-        ++li;
+        // one symbol per conjugate pair (canonical_theta enumerates them)
+        const int ncanon = lfa::canonical_count(l.n, l.m);
         p->tw_n.push_back(off[l.n]);
         p->tw_m.push_back(off[l.m]);
         LayerDesc d = make_desc(l, off[l.n], off[l.m], false, eb, kLdsCap);
@@ -908,7 +890,6 @@ int lfa_plan_destroy(lfa_plan* plan) {
     if (!plan) return LFA_OK;
     if (plan->tw_dev) (void)hipFree(plan->tw_dev);
     if (plan->items_dev) (void)hipFree(plan->items_dev);
-    if (plan->canon_dev) (void)hipFree(plan->canon_dev);
     for (auto& kv : plan->grad_sched)
         if (kv.second.items_dev) (void)hipFree(kv.second.items_dev);
     delete plan;
@@ -1169,13 +1150,11 @@ int lfa_autotune(lfa_plan* plan, const void* const* W, void* const* sigma, void*
                 if (plan->dtype == LFA_F64)
                     status = run_svd_layer<double>(plan, d, W[i], nullptr, sigma[i],
                                                    wu ? U[i] : nullptr, wv ? V[i] : nullptr,
-                                                   nullptr, region, nullptr, 0, 0, st,
-                                                   plan->canon_dev + plan->canon_off[i]);
+                                                   nullptr, region, nullptr, 0, 0, st, true);
                 else
                     status = run_svd_layer<float>(plan, d, W[i], nullptr, sigma[i],
                                                   wu ? U[i] : nullptr, wv ? V[i] : nullptr,
-                                                  nullptr, region, nullptr, 0, 0, st,
-                                                  plan->canon_dev + plan->canon_off[i]);
+                                                  nullptr, region, nullptr, 0, 0, st, true);
                 if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
                     status = LFA_ERR_HIP;
                     break;

@@ -199,6 +199,23 @@ __host__ __device__ inline int item_count(const A& a) {
     return a.theta_list ? a.theta_count : (a.canon ? a.d.num_canon : a.d.num_symbols);
 }
 
+// Canonical frequencies: flat index t = p m + q with t <= the index of its
+// mirror -k = ((n-p) mod n, (m-q) mod m), in increasing order.  They are
+// row p = 0 with q <= m/2, every q of the rows 0 < p < n - p, and (n even)
+// row n/2 with q <= m/2.
+__host__ __device__ inline int canonical_count(int n, int m) {
+    const int h = m / 2 + 1, full = (n + 1) / 2 - 1;
+    return h + full * m + (n % 2 == 0 && n > 1 ? h : 0);
+}
+
+__host__ __device__ inline int canonical_theta(int n, int m, int item) {
+    const int h = m / 2 + 1, full = (n + 1) / 2 - 1;
+    if (item < h) return item;
+    const int r = item - h;
+    if (r < full * m) return (1 + r / m) * m + r % m;
+    return (n / 2) * m + (r - full * m);
+}
+
 template <typename A>
 __device__ inline Target target_of(const A& a, int item) {
     Target t;
@@ -208,7 +225,7 @@ __device__ inline Target target_of(const A& a, int item) {
         t.out = item;
         t.mirror = -1;
     } else if (a.canon) {
-        t.theta = a.canon[item];
+        t.theta = canonical_theta(a.d.n, a.d.m, item);
         t.out = t.theta;
         const int p = t.theta / a.d.m, q = t.theta - (t.theta / a.d.m) * a.d.m;
         const int mi = ((a.d.n - p) % a.d.n) * a.d.m + (a.d.m - q) % a.d.m;
@@ -252,7 +269,7 @@ struct SvdArgs {
     const double* tw;            // twiddle table, (re, im) pairs
     char* gws;                   // global working storage, one slot per block
     long long slot_bytes;        // bytes per slot
-    const int32_t* canon;        // optional: canonical frequencies (one per conjugate pair);
+    int canon;                   // 1: decompose the canonical frequencies (one per conjugate pair);
                                  // outputs are also written for the mirror frequency
     const int32_t* theta_list;   // optional: symbol indices to process
     int theta_stride;            // element stride in theta_list (3 for (p,q,j) triples)

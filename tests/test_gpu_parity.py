@@ -191,6 +191,34 @@ def test_single_layer_64_full_size_sampled():
     assert abs(ps - 1) <= 1e-6
 
 
+# ------------------------------------------------------ paper-scale grid --
+
+def test_paper_scale_n16384_sampled():
+    """The runtime study's largest case (Sec. IV, Table II): 16 -> 16 channels,
+    3x3, 16384 x 16384 grid, sigma only (4.29e9 values, 17 GB).  64 sampled
+    symbols against the oracle, including k = 0, the last frequency and the
+    real symbol at (n/2, n/2); Parseval over the whole grid."""
+    banner("paper scale n=16384")
+    n = 16384
+    L, W = workloads.paper_scale(n)
+    S, info = lfa().svd(_w(W), n, n, compute_uv=False, return_info=True)
+    torch.cuda.synchronize()
+    assert info[0] == 0 and info[3] == 0, f"info {info}"
+    rng = np.random.default_rng(3)
+    fr = rng.integers(0, n, size=(64, 2))
+    fr[0] = (0, 0)
+    fr[1] = (n - 1, n - 1)
+    fr[2] = (n // 2, n // 2)
+    fr[3] = (n // 2, 0)
+    Sg = S[fr[:, 0], fr[:, 1]].cpu().numpy()
+    S_ref = oracle.lfa_svd(W.astype(np.float64), n, n, freqs=fr)
+    assert oracle.sigma_error(Sg, S_ref) <= 1e-5
+    ss = torch.sum(S.double() ** 2).item()
+    assert abs(ss / (n * n * np.sum(W.astype(np.float64) ** 2)) - 1) <= 1e-5
+    del S
+    torch.cuda.empty_cache()
+
+
 # --------------------------------------------- persistent, top-k, gradient --
 
 def _small_stack(seed=4):

@@ -128,6 +128,16 @@ def large_grid_7x7(seed: int = 5, n: int = 224, scaled_taps: int = 5, scale: flo
     return L, W.astype(np.float32), np.sort(taps)
 
 
+def paper_scale(n: int, seed: int = 6):
+    """16 -> 16 channels, 3x3, n x n grid, float32 weights N(0, 1/(9*16)):
+    the channel count and kernel of the runtime study (Sec. IV, Tables II
+    and III), sigma only, n up to 16384."""
+    L = Layer(16, 16, 3, 3, n, n)
+    rng = np.random.default_rng(seed)
+    W = gaussian(rng, (16, 16, 3, 3), np.sqrt(1.0 / (9 * 16)), np.float32)
+    return L, W
+
+
 def random_layer(c_out, c_in, kh, kw, n, m=None, seed=0, dtype=np.float32):
     """Generic N(0, 1/(kh*kw*c_in)) layer for parity tests."""
     m = n if m is None else m
