@@ -45,7 +45,7 @@ constexpr int kGlobalGrid = 1024;              // blocks of a launch using globa
 constexpr int kPersistentGrid = 1024;          // upper bound of the persistent grid
 
 constexpr int kMaxTopk = 64;
-constexpr int kBlockCols = 8;                     // column block of the blocked kernel
+constexpr int kBlockCols = 16;                    // column block of the blocked kernel
 constexpr size_t kCounterBytes = 256 * ((4 * (4 * 1024 + 4) + 255) / 256);   // team counters
 constexpr int kMaxSweeps = 40;
 
@@ -280,7 +280,7 @@ void build_schedule(lfa_plan* p) {
         const bool acc_any = wu || wv;
         const size_t lds = persistent_lds_bytes(p->desc_pers.data() + l0, l1 - l0, acc_any, eb,
                                                 p->pers_wave_slots);
-        int grid = persistent_resident(lds, eb);
+        int grid = persistent_resident(lds, eb, acc_any);
         if (grid <= 0) grid = std::max(1, p->num_cus);
         p->pers_lds.push_back(lds);
         p->pers_grid.push_back(grid);
@@ -506,7 +506,7 @@ int persistent_impl(const lfa_plan* p, const void* const* W, void* const* sigma,
         pa.threads = kPersistentThreads;
         for (int i = l0; i < l1; ++i) {
             const LayerDesc& d = p->desc_pers[i];
-            const bool acc = accumulates(d, wu, wv);
+            const bool acc = wu || wv;      // as the plan sized the slots
             SvdArgs<R>& a = pa.layer[i - l0];
             a.d = d;
             a.W = static_cast<const R*>(W[i]);
@@ -544,8 +544,8 @@ int persistent_impl(const lfa_plan* p, const void* const* W, void* const* sigma,
         HIP_TRY(launch_fill_i32(team_counters, 0, 4LL * p->pers_teams + 4, st));
         const int grid = std::min(p->pers_grid[chunk], count);
         hipError_t e;
-        if constexpr (sizeof(R) == 4) e = launch_persistent_f32(pa, grid, p->pers_lds[chunk], st);
-        else e = launch_persistent_f64(pa, grid, p->pers_lds[chunk], st);
+        if constexpr (sizeof(R) == 4) e = launch_persistent_f32(pa, grid, p->pers_lds[chunk], wu || wv, st);
+        else e = launch_persistent_f64(pa, grid, p->pers_lds[chunk], wu || wv, st);
         HIP_TRY(e);
     }
     return LFA_OK;
@@ -657,7 +657,7 @@ int ensure_grad_schedule(lfa_plan* p, int k) {
         const int l1 = std::min(nl, l0 + kMaxLaunchLayers);
         gs.chunk_first.push_back((int)items.size());
         const size_t lds = persistent_lds_bytes(p->desc_gsel.data() + l0, l1 - l0, true, eb, 1);
-        int grid = persistent_resident(lds, eb);
+        int grid = persistent_resident(lds, eb, true);
         if (grid <= 0) grid = std::max(1, p->num_cus);
         gs.lds.push_back(lds);
         gs.grid.push_back(grid);
@@ -761,8 +761,8 @@ int sigma_grad_persistent_impl(const lfa_plan* p, const void* const* W, const in
         HIP_TRY(launch_fill_i32(team_counters, 0, 4LL * gs.teams + 4, st));
         const int grid = std::min(gs.grid[chunk], count);
         hipError_t e;
-        if constexpr (sizeof(R) == 4) e = launch_persistent_f32(pa, grid, gs.lds[chunk], st);
-        else e = launch_persistent_f64(pa, grid, gs.lds[chunk], st);
+        if constexpr (sizeof(R) == 4) e = launch_persistent_f32(pa, grid, gs.lds[chunk], true, st);
+        else e = launch_persistent_f64(pa, grid, gs.lds[chunk], true, st);
         HIP_TRY(e);
     }
     for (int l0 = 0; l0 < nl; l0 += kMaxLaunchLayers) {
@@ -854,7 +854,9 @@ int lfa_plan_create(lfa_plan** out, const lfa_layer* layers, int32_t num_layers,
         p->desc_sel.push_back(make_desc(l, off[l.n], off[l.m], true, eb, kLdsCap));
         // persistent launch: bundles of the register kernel for small symbols
         // without vectors, the blocked kernel (256 threads) otherwise
-        const bool pacc = accumulates(d, wu, wv);
+        // one accumulator setting for the whole persistent launch (its kernel
+        // is compiled with or without the accumulator)
+        const bool pacc = wu || wv;
         LayerDesc dp = make_desc(l, off[l.n], off[l.m], pacc, eb, kLdsCap);
         if (dp.kind != 1 || pacc) {
             dp = make_desc(l, off[l.n], off[l.m], pacc, eb, kLdsCap);

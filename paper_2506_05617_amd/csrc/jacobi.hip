@@ -12,7 +12,7 @@ using namespace dev;
 // Grid = teams x W work-groups, all resident at once (the host sizes the
 // grid from the occupancy of this kernel).  Team t owns slot t and works on
 // items t, t + teams, ...
-template <typename R>
+template <typename R, bool ACC>
 __global__ void __launch_bounds__(512) block_kernel(SvdArgs<R> a, int W, int32_t* counters) {
     extern __shared__ __align__(16) char lds[];
     const int teams = gridDim.x / W;
@@ -26,7 +26,7 @@ __global__ void __launch_bounds__(512) block_kernel(SvdArgs<R> a, int W, int32_t
     team.target = 0;
     char* gslot = a.gws + (size_t)tix * a.slot_bytes;
     const int count = item_count(a);
-    for (int item = tix; item < count; item += teams) block_one<R, 1>(a, lds, item, gslot, team);
+    for (int item = tix; item < count; item += teams) block_one<R, 1, ACC>(a, lds, item, gslot, team);
 }
 
 template <typename R, int L>
@@ -97,28 +97,36 @@ size_t block_lds_bytes(const LayerDesc& d, bool accumulate, int elem_bytes) {
     dg.kind = 0;
     dg.storage = kGlobal;
     const int nw = d.threads / 64;
+    // BlockLds: wpart, wsum (two buffers), wprm (quads), wdsc, rflag
     return lds_bytes_for(dg, accumulate, elem_bytes) +
-           (size_t)elem_bytes * (nw * 64 * (4 * kBlk + 4) + nw * 4 * kBlk + 4 * kBlk) + 16 + 64;
+           (size_t)elem_bytes * (nw * 64 * kBlkPST + 2 * nw * 4 * kBlk + nw * kBlk * 4 + nw * 2 * kBlk) +
+           16 + 64;
+}
+
+template <typename R, bool ACC>
+hipError_t launch_block_t(const SvdArgs<R>& a, int teams, int W, int32_t* counters, hipStream_t st) {
+    const size_t lds = block_lds_bytes(a.d, ACC, sizeof(R));
+    hipError_t e = allow_lds(block_kernel<R, ACC>, lds);
+    if (e != hipSuccess) return e;
+    e = launch_fill_i32(counters, 0, 4LL * teams + 4, st);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((block_kernel<R, ACC>), dim3(teams * W), dim3(a.d.threads), lds, st, a, W, counters);
+    return hipGetLastError();
 }
 
 template <typename R>
 hipError_t launch_block(const SvdArgs<R>& a, int teams, int W, int32_t* counters, hipStream_t st) {
     const bool acc = (a.d.transposed ? a.U : a.V) != nullptr;
-    const size_t lds = block_lds_bytes(a.d, acc, sizeof(R));
-    hipError_t e = allow_lds(block_kernel<R>, lds);
-    if (e != hipSuccess) return e;
-    e = launch_fill_i32(counters, 0, 4LL * teams + 4, st);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(block_kernel<R>, dim3(teams * W), dim3(a.d.threads), lds, st, a, W, counters);
-    return hipGetLastError();
+    return acc ? launch_block_t<R, true>(a, teams, W, counters, st)
+               : launch_block_t<R, false>(a, teams, W, counters, st);
 }
 
-template <typename R>
-int block_resident_t(const LayerDesc& d, bool acc) {
-    const size_t lds = block_lds_bytes(d, acc, sizeof(R));
-    if (allow_lds(block_kernel<R>, lds) != hipSuccess) return 0;
+template <typename R, bool ACC>
+int block_resident_t(const LayerDesc& d) {
+    const size_t lds = block_lds_bytes(d, ACC, sizeof(R));
+    if (allow_lds(block_kernel<R, ACC>, lds) != hipSuccess) return 0;
     int per_cu = 0, dev = 0, cus = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, block_kernel<R>, d.threads, lds) !=
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, block_kernel<R, ACC>, d.threads, lds) !=
         hipSuccess)
         return 0;
     if (hipGetDevice(&dev) != hipSuccess ||
@@ -136,7 +144,8 @@ hipError_t launch_block_svd_f64(const SvdArgs<double>& a, int teams, int W, int3
     return launch_block<double>(a, teams, W, counters, s);
 }
 int block_resident(const LayerDesc& d, bool acc, int elem_bytes) {
-    return elem_bytes == 8 ? block_resident_t<double>(d, acc) : block_resident_t<float>(d, acc);
+    if (elem_bytes == 8) return acc ? block_resident_t<double, true>(d) : block_resident_t<double, false>(d);
+    return acc ? block_resident_t<float, true>(d) : block_resident_t<float, false>(d);
 }
 
 hipError_t launch_svd_f32(const SvdArgs<float>& a, int grid, size_t lds, hipStream_t s) {

@@ -463,412 +463,6 @@ __device__ void svd_one(const SvdArgs<R>& a, char* lds, int item, char* gslot) {
     finish<R, L>(a, s, tg.out, tg.mirror, sweeps, converged);
 }
 
-// ---------------------------------------------------------------------------
-// Blocked one-sided Jacobi for symbols with more than 64 rows.
-//
-// Thread t of the work-group owns row t of G (M x N, column-major in a global
-// slot) and row t of the accumulator Q (N x N): it is the only thread that
-// ever reads or writes those rows, so the global traffic of the sweeps needs
-// no synchronisation.  Columns are taken B at a time: a block pair (2B columns
-// of the thread's row, and of its Q row) sits in registers while its column
-// pairs are rotated, then goes back to the slot.
-//
-// One sweep visits every column pair exactly once:
-//  * intra pass: blocks (2i, 2i+1) are loaded together and the pairs inside
-//    each block are rotated by a round-robin of B-1 steps;
-//  * cross passes: a round-robin over the blocks (NB-1 outer steps); in a
-//    block pair (a, b), step t rotates (a_p, b_{(p+t) mod B}) for all p.
-// Inner products are reduced over rows by a per-wave LDS transpose and a sum
-// over the waves; one thread per pair computes the rotation.
-// ---------------------------------------------------------------------------
-constexpr int kBlk = 8;   // columns per block
-
-template <typename R>
-struct BlockLds {
-    R* wpart;        // [waves][64][4B+4]
-    R* wsum;         // [waves][4B]
-    quad<R>* prm;    // [B]
-    int* rflag;      // rotation made in this sweep
-};
-
-template <typename R>
-__device__ __forceinline__ BlockLds<R> carve_block(char* lds, size_t off) {
-    constexpr int B = kBlk, PST = 4 * B + 4;
-    const int nw = blockDim.x >> 6;
-    BlockLds<R> b;
-    R* p = reinterpret_cast<R*>(lds + ((off + 63) & ~size_t(63)));
-    b.wpart = p;
-    p += nw * 64 * PST;
-    b.wsum = p;
-    p += nw * 4 * B;
-    b.prm = reinterpret_cast<quad<R>*>(p);
-    b.rflag = reinterpret_cast<int*>(b.prm + B);
-    return b;
-}
-
-// Sum the per-row contributions q[p] (p < B pairs) over all rows and compute
-// the B rotations into bl.prm.  Contains two work-group barriers.
-template <typename R>
-__device__ __forceinline__ void block_reduce_rotate(const BlockLds<R>& bl, quad<R> (&q)[kBlk],
-                                                    double tol) {
-    constexpr int B = kBlk, PST = 4 * B + 4, Q = 4 * B, H = 64 / Q;
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nw = blockDim.x >> 6;
-    R* wp = bl.wpart + wave * 64 * PST;
-#pragma unroll
-    for (int p = 0; p < B; ++p) *reinterpret_cast<quad<R>*>(wp + lane * PST + 4 * p) = q[p];
-    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    const int qi = lane % Q, h = lane / Q;
-    R sum = 0;
-#pragma unroll 8
-    for (int r = h * (64 / H); r < (h + 1) * (64 / H); ++r) sum += wp[r * PST + qi];
-#pragma unroll
-    for (int off = Q; off < 64; off <<= 1) sum += __shfl_xor(sum, off, 64);
-    if (lane < Q) bl.wsum[wave * Q + qi] = sum;
-    __syncthreads();
-    if (tid < B) {
-        R s0 = 0, s1 = 0, s2 = 0, s3 = 0;
-        for (int w = 0; w < nw; ++w) {
-            const R* ws = bl.wsum + w * Q + 4 * tid;
-            s0 += ws[0];
-            s1 += ws[1];
-            s2 += ws[2];
-            s3 += ws[3];
-        }
-        const quad<R> r = rotation<R>(s0, s1, s2, s3, tol);
-        bl.prm[tid] = r;
-        if (r.d != R(0)) *bl.rflag = 1;
-    }
-    __syncthreads();
-}
-
-template <typename R>
-__device__ __forceinline__ quad<R> pair_partials(cplx<R> x, cplx<R> y) {
-    quad<R> q;
-    q.a = fma(x.x, x.x, x.y * x.y);
-    q.b = fma(y.x, y.x, y.y * y.y);
-    q.c = fma(x.x, y.x, x.y * y.y);
-    q.d = fma(x.x, y.y, -x.y * y.x);
-    return q;
-}
-
-// Load / store block `blk` (columns blk*B ..) of this thread's row.
-template <typename R>
-__device__ __forceinline__ void load_block(const cplx<R>* base, int ld, int blk, int ncols, int row,
-                                           bool row_ok, cplx<R> (&x)[kBlk]) {
-#pragma unroll
-    for (int k = 0; k < kBlk; ++k) {
-        const int c = blk * kBlk + k;
-        x[k] = (row_ok && c < ncols) ? base[(size_t)c * ld + row] : cplx<R>{R(0), R(0)};
-    }
-}
-template <typename R>
-__device__ __forceinline__ void store_block(cplx<R>* base, int ld, int blk, int ncols, int row,
-                                            bool row_ok, const cplx<R> (&x)[kBlk]) {
-#pragma unroll
-    for (int k = 0; k < kBlk; ++k) {
-        const int c = blk * kBlk + k;
-        if (row_ok && c < ncols) base[(size_t)c * ld + row] = x[k];
-    }
-}
-
-// Team of W work-groups working on one symbol.  Counters live in device
-// memory, cleared before the launch; `target` counts the barriers passed.
-struct Team {
-    int member, W;
-    int32_t* bar;        // arrivals (monotonic)
-    int32_t* rot;        // work-groups that rotated, summed over the sweeps (monotonic)
-    int32_t* err;        // bit 1 set when a barrier timed out
-    int target;
-};
-
-// All W work-groups of the team arrive before any leaves; global writes
-// before the barrier are visible to every member after it (release/acquire
-// at agent scope).  The wait is bounded: on timeout the error bit is set and
-// this and every later barrier return at once, so no wave ever hangs.
-__device__ void team_barrier(Team& t) {
-    t.target += t.W;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        __threadfence();
-        __hip_atomic_fetch_add(t.bar, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-        int spins = 0;
-        while (__hip_atomic_load(t.bar, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < t.target) {
-            if (__hip_atomic_load(t.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & 2) break;
-            __builtin_amdgcn_s_sleep(4);
-            if (++spins > (1 << 24)) {
-                __hip_atomic_fetch_or(t.err, 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                break;
-            }
-        }
-        __threadfence();
-    }
-    __syncthreads();
-}
-
-// RPT rows per thread: thread t owns rows t, t + nt, ..., t + (RPT-1) nt.
-template <typename R, int RPT>
-__device__ void block_sweeps(const LayerDesc& d, const Shared<R>& s, const BlockLds<R>& bl,
-                             int max_sweeps, double tol, Team& team, int& sweeps_out,
-                             bool& conv_out) {
-    constexpr int B = kBlk;
-    const int tid = threadIdx.x, nt = blockDim.x;
-    const int member = team.member, W = team.W;
-    const int M = d.M, N = d.N;
-    const int NB = (N + B - 1) / B, NBP = NB + (NB & 1);
-    const bool acc = s.Q != nullptr;
-    int rows[RPT];
-    bool grow[RPT], qrow[RPT];
-#pragma unroll
-    for (int r = 0; r < RPT; ++r) {
-        rows[r] = tid + r * nt;
-        grow[r] = rows[r] < M;
-        qrow[r] = acc && rows[r] < N;
-    }
-    cplx<R> ga[RPT][B], gb[RPT][B], va[RPT][B], vb[RPT][B];
-    quad<R> q[B];
-    auto load2 = [&](int ba, int bb) {
-#pragma unroll
-        for (int r = 0; r < RPT; ++r) {
-            load_block(s.G, d.ldg, ba, N, rows[r], grow[r], ga[r]);
-            load_block(s.G, d.ldg, bb, N, rows[r], grow[r], gb[r]);
-            if (acc) {
-                load_block(s.Q, d.ldv, ba, N, rows[r], qrow[r], va[r]);
-                load_block(s.Q, d.ldv, bb, N, rows[r], qrow[r], vb[r]);
-            }
-        }
-    };
-    auto store2 = [&](int ba, int bb) {
-#pragma unroll
-        for (int r = 0; r < RPT; ++r) {
-            store_block(s.G, d.ldg, ba, N, rows[r], grow[r], ga[r]);
-            store_block(s.G, d.ldg, bb, N, rows[r], grow[r], gb[r]);
-            if (acc) {
-                store_block(s.Q, d.ldv, ba, N, rows[r], qrow[r], va[r]);
-                store_block(s.Q, d.ldv, bb, N, rows[r], qrow[r], vb[r]);
-            }
-        }
-    };
-    int sweeps = 0;
-    bool converged = (N < 2);
-    while (!converged && sweeps < max_sweeps) {
-        if (tid == 0) *bl.rflag = 0;
-        __syncthreads();
-        // team: rotations counted before this sweep (all earlier increments
-        // happened before the barrier that ended the previous sweep)
-        const int rot_before =
-            W > 1 ? __hip_atomic_load(team.rot, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) : 0;
-        // ---- intra pass: pairs inside blocks 2i and 2i+1
-        for (int i = member; 2 * i < NB; i += W) {
-            const int ba = 2 * i, bb = 2 * i + 1;
-            load2(ba, bb);
-            for (int step = 0; step < B - 1; ++step) {
-#pragma unroll
-                for (int p = 0; p < B / 2; ++p) {
-                    q[p] = pair_partials(ga[0][p], ga[0][B - 1 - p]);
-                    q[B / 2 + p] = pair_partials(gb[0][p], gb[0][B - 1 - p]);
-#pragma unroll
-                    for (int r = 1; r < RPT; ++r) {
-                        const quad<R> x = pair_partials(ga[r][p], ga[r][B - 1 - p]);
-                        const quad<R> y = pair_partials(gb[r][p], gb[r][B - 1 - p]);
-                        q[p] = {q[p].a + x.a, q[p].b + x.b, q[p].c + x.c, q[p].d + x.d};
-                        q[B / 2 + p] = {q[B / 2 + p].a + y.a, q[B / 2 + p].b + y.b,
-                                        q[B / 2 + p].c + y.c, q[B / 2 + p].d + y.d};
-                    }
-                }
-                block_reduce_rotate<R>(bl, q, tol);
-#pragma unroll
-                for (int p = 0; p < B / 2; ++p) {
-                    const quad<R> ra = bl.prm[p], rb = bl.prm[B / 2 + p];
-#pragma unroll
-                    for (int r = 0; r < RPT; ++r) {
-                        rot_apply(ga[r][p], ga[r][B - 1 - p], ra.a, ra.b, ra.c);
-                        rot_apply(gb[r][p], gb[r][B - 1 - p], rb.a, rb.b, rb.c);
-                        if (acc) {
-                            rot_apply(va[r][p], va[r][B - 1 - p], ra.a, ra.b, ra.c);
-                            rot_apply(vb[r][p], vb[r][B - 1 - p], rb.a, rb.b, rb.c);
-                        }
-                    }
-                }
-                // round-robin: positions 1..B-1 move by one
-#pragma unroll
-                for (int r = 0; r < RPT; ++r) {
-                    const cplx<R> la = ga[r][B - 1], lb = gb[r][B - 1], lva = va[r][B - 1],
-                                  lvb = vb[r][B - 1];
-#pragma unroll
-                    for (int k = B - 1; k >= 2; --k) {
-                        ga[r][k] = ga[r][k - 1];
-                        gb[r][k] = gb[r][k - 1];
-                        va[r][k] = va[r][k - 1];
-                        vb[r][k] = vb[r][k - 1];
-                    }
-                    ga[r][1] = la;
-                    gb[r][1] = lb;
-                    va[r][1] = lva;
-                    vb[r][1] = lvb;
-                }
-            }
-            // B-1 steps bring every position back: store in place
-            store2(ba, bb);
-        }
-        if (W > 1) team_barrier(team);
-        // ---- cross passes: round-robin over block pairs
-        for (int os = 0; os < NBP - 1; ++os) {
-            for (int bp = member; bp < NBP / 2; bp += W) {
-                int ba, bb;
-                rr_pair(bp, os, NBP, ba, bb);
-                if (ba >= NB || bb >= NB) continue;
-                load2(ba, bb);
-                for (int t = 0; t < B; ++t) {
-#pragma unroll
-                    for (int p = 0; p < B; ++p) {
-                        q[p] = pair_partials(ga[0][p], gb[0][p]);
-#pragma unroll
-                        for (int r = 1; r < RPT; ++r) {
-                            const quad<R> x = pair_partials(ga[r][p], gb[r][p]);
-                            q[p] = {q[p].a + x.a, q[p].b + x.b, q[p].c + x.c, q[p].d + x.d};
-                        }
-                    }
-                    block_reduce_rotate<R>(bl, q, tol);
-#pragma unroll
-                    for (int p = 0; p < B; ++p) {
-                        const quad<R> rr = bl.prm[p];
-#pragma unroll
-                        for (int r = 0; r < RPT; ++r) {
-                            rot_apply(ga[r][p], gb[r][p], rr.a, rr.b, rr.c);
-                            if (acc) rot_apply(va[r][p], vb[r][p], rr.a, rr.b, rr.c);
-                        }
-                    }
-                    // block b shifts by one against block a
-#pragma unroll
-                    for (int r = 0; r < RPT; ++r) {
-                        const cplx<R> fb = gb[r][0], fv = vb[r][0];
-#pragma unroll
-                        for (int k = 0; k < B - 1; ++k) {
-                            gb[r][k] = gb[r][k + 1];
-                            vb[r][k] = vb[r][k + 1];
-                        }
-                        gb[r][B - 1] = fb;
-                        vb[r][B - 1] = fv;
-                    }
-                }
-                // B shifts bring block b back to its order
-                store2(ba, bb);
-            }
-            if (W > 1 && os < NBP - 2) team_barrier(team);
-        }
-        __syncthreads();
-        if (W > 1) {
-            if (tid == 0 && *bl.rflag)
-                __hip_atomic_fetch_add(team.rot, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            team_barrier(team);
-            converged = __hip_atomic_load(team.rot, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) ==
-                        rot_before;
-        } else {
-            converged = (*bl.rflag == 0);
-        }
-        ++sweeps;
-        __syncthreads();
-    }
-    sweeps_out = sweeps;
-    conv_out = converged;
-}
-
-template <typename R, int RPT>
-__device__ void block_one(const SvdArgs<R>& a, char* lds, int item, char* gslot, Team& team) {
-    const Target tg = target_of(a, item);
-    const bool acc = (a.d.transposed ? a.U : a.V) != nullptr;
-    const Shared<R> s = carve<R>(lds, a.d, acc, gslot);
-    const BlockLds<R> bl = carve_block<R>(lds, s.small_end);
-    if (team.member == 0) load_symbol<R>(a, s, tg.theta);
-    if (team.W > 1) team_barrier(team);
-    else __syncthreads();
-    int sweeps;
-    bool converged;
-    block_sweeps<R, RPT>(a.d, s, bl, a.max_sweeps, a.tol, team, sweeps, converged);
-    if (team.member == 0) finish<R, 64>(a, s, tg.out, tg.mirror, sweeps, converged);
-    // the slot is reused for the team's next symbol: members wait for the finish
-    if (team.W > 1) team_barrier(team);
-    if (a.info && threadIdx.x == 0 && team.member == 0 &&
-        (__hip_atomic_load(team.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & 2))
-        atomicOr(&a.info[LFA_INFO_NONFINITE], 2);
-}
-
-
-// ===================== register (rows-in-lanes) kernel =====================
-// Register-resident one-sided Jacobi SVD for symbols of at most 64 rows and
-// 64 columns (rows-in-lanes layout), gfx950.
-//
-// A work-group is one wavefront for G (plus one for the rotation accumulator
-// when singular vectors are wanted).  Lane l of the G wave owns row l of the
-// M x N working matrix G of its symbol in registers, all NC (>= N, power of
-// two) columns; with ML lanes per symbol (16, 32 or 64) one wave holds
-// 64/ML symbols.  Lane l of the second wave owns row l of the N x N
-// accumulator Q.
-//
-// One round-robin step pairs the columns at positions (p, NC-1-p),
-// p < NC/2 -- all compile-time register indices -- and then rotates the
-// positions 1..NC-1 by one (register moves).  After NC-1 steps, i.e. one
-// sweep, every column is back at its starting position, so the final column
-// order is the original one.
-//
-// Per step:
-//  1. every G lane forms its row's contributions to gamma_p = g_j^H g_k for
-//     all pairs.  Groups of NB pairs are folded across lanes by transpose-add
-//     stages (lane^32 and lane^16 register swaps): after them a lane holds
-//     one pair's partial sum over NB rows, and the lanes of block b = row /
-//     GL hold the pairs b*Q .. b*Q+Q-1.  The folded partials go to LDS,
-//     [symbol][row][2Q] (padded row stride);
-//  2. lane (p, k) of the same wave sums Q holder rows of pair p, the LP
-//     lanes of a pair are combined with xor exchanges, and every lane of the
-//     pair evaluates the rotation (threshold test and angle in double
-//     precision) from gamma_p and the squared norms alpha = |g_j|^2,
-//     beta = |g_k|^2.  The norms are not summed again each step: they are
-//     computed exactly at the start of every sweep and updated with each
-//     rotation (alpha - t|gamma|, beta + t|gamma|), so the convergence test
-//     of the final, rotation-free sweep uses exact norms.  One lane of the
-//     pair's set writes (c, s e^{-i phi}, flag) to a double-buffered LDS
-//     slot;
-//  3. after one work-group barrier every lane of both waves reads the
-//     parameters (broadcast) and applies the pair rotations to its registers
-//     (a pair below the threshold gets the identity, applied without a
-//     branch).  The Q wave only applies, so it runs a step behind the G wave and its work
-//     overlaps the next step's inner products.
-// One work-group barrier per step; no LDS traffic for G or Q themselves.  The
-// symbols are assembled into registers through a small LDS tile, a chunk of
-// columns at a time, and the results are written from registers.
-
-
-template <typename R>
-__device__ __forceinline__ R skey(R v) {
-    return v == v ? v : R(-1);
-}
-
-
-template <int NC, typename T>
-__device__ __forceinline__ void rotate_positions(T (&g)[NC]) {
-    // new[1] = old[NC-1], new[i] = old[i-1] for i = 2..NC-1
-    const T last = g[NC - 1];
-#pragma unroll
-    for (int i = NC - 1; i >= 2; --i) g[i] = g[i - 1];
-    g[1] = last;
-}
-
-__device__ __forceinline__ void phase_of(const double* tw, const LayerDesc& d, int theta, int t,
-                                         double& re, double& im) {
-    const int p = theta / d.m, q = theta - (theta / d.m) * d.m;
-    const int a = t / d.kw, b = t - (t / d.kw) * d.kw;
-    const int y1 = a - (d.kh - 1) / 2, y2 = b - (d.kw - 1) / 2;
-    int i1 = (p * y1) % d.n;
-    if (i1 < 0) i1 += d.n;
-    int i2 = (q * y2) % d.m;
-    if (i2 < 0) i2 += d.m;
-    const double ar = tw[2 * (d.tw_n + i1)], ai = tw[2 * (d.tw_n + i1) + 1];
-    const double br = tw[2 * (d.tw_m + i2)], bi = tw[2 * (d.tw_m + i2) + 1];
-    re = ar * br - ai * bi;
-    im = ar * bi + ai * br;
-}
-
 // ---- cross-lane exchanges (gfx950 permlane swaps) ------------------------
 // xadd32(a, b): lanes 0-31 receive a(l) + a(l+32), lanes 32-63 b(l-32) + b(l).
 // xadd16(a, b): lanes whose bit 4 is clear receive a(l) + a(l+16), the others
@@ -940,6 +534,501 @@ __device__ __forceinline__ int col_at(int pos, int step) {
 // a column is rotated at most once per step and each rotation multiplies its
 // scale by c >= 1/sqrt(2), so stored entries stay within 2^16 of the true ones.
 constexpr int kWaveRenorm = 32;
+
+// Round-robin ("circle") move of NC register positions: position 0 stays,
+// positions 1..NC-1 rotate by one.
+template <int NC, typename T>
+__device__ __forceinline__ void rotate_positions(T (&g)[NC]) {
+    // new[1] = old[NC-1], new[i] = old[i-1] for i = 2..NC-1
+    const T last = g[NC - 1];
+#pragma unroll
+    for (int i = NC - 1; i >= 2; --i) g[i] = g[i - 1];
+    g[1] = last;
+}
+
+// ---------------------------------------------------------------------------
+// Blocked one-sided Jacobi for symbols with more than 64 rows.
+//
+// Thread t of the work-group owns row t of G (M x N, column-major in a global
+// slot) and row t of the accumulator Q (N x N): it is the only thread that
+// ever reads or writes those rows, so the global traffic of the sweeps needs
+// no synchronisation.  Columns are taken B at a time: a block pair (2B columns
+// of the thread's row, and of its Q row) sits in registers while its column
+// pairs are rotated, then goes back to the slot.
+//
+// One sweep visits every column pair exactly once:
+//  * intra pass: blocks (2i, 2i+1) are loaded together and the pairs inside
+//    each block are rotated by a round-robin of B-1 steps;
+//  * cross passes: a round-robin over the blocks (NB-1 outer steps); in a
+//    block pair (a, b), step t rotates (a_p, b_{(p+t) mod B}) for all p.
+//
+// One step (B pairs):
+//  1. every thread forms its rows' contributions to |g_j|^2, |g_k|^2 and
+//     g_j^H g_k for the B pairs; they are folded across the lanes of the wave
+//     (lane^32 and lane^16 register swaps, then an LDS transpose) into the
+//     wave's sums, which go to a per-wave slot (double-buffered by step);
+//  2. one work-group barrier;
+//  3. every wave sums the per-wave slots and evaluates the B rotations itself
+//     (identical inputs give identical results in every wave), so no second
+//     barrier is needed;
+//  4. the rotations are applied in scaled form: block columns are held as
+//     g_j = G_j / d_j with per-column scales that the rotations multiply by
+//     c (two complex multiply-adds per row and pair instead of four
+//     real-by-complex products); every wave keeps its own copy of the 2B
+//     scales, and they are folded into the columns before the block pair goes
+//     back to the slot, so the slot always holds true columns.
+// ---------------------------------------------------------------------------
+constexpr int kBlk = 16;                  // columns per block
+constexpr int kBlkPST = kBlk + 4;         // folded partials per lane (4B / 4) + padding
+
+template <typename R>
+struct BlockLds {
+    R* wpart;        // [waves][64][kBlkPST] folded partials of each wave
+    R* wsum;         // [2][waves][4B] per-wave sums of the step, by step parity
+    quad<R>* wprm;   // [waves][B] rotation parameters (each wave its own)
+    R* wdsc;         // [waves][2B] column scales of the block pair (each wave its own)
+    int* rflag;      // rotation made in this sweep
+};
+
+template <typename R>
+__device__ __forceinline__ BlockLds<R> carve_block(char* lds, size_t off) {
+    constexpr int B = kBlk;
+    const int nw = blockDim.x >> 6;
+    BlockLds<R> b;
+    R* p = reinterpret_cast<R*>(lds + ((off + 63) & ~size_t(63)));
+    b.wpart = p;
+    p += nw * 64 * kBlkPST;
+    b.wsum = p;
+    p += 2 * nw * 4 * B;
+    b.wprm = reinterpret_cast<quad<R>*>(p);
+    p = reinterpret_cast<R*>(b.wprm + nw * B);
+    b.wdsc = p;
+    p += nw * 2 * B;
+    b.rflag = reinterpret_cast<int*>(p);
+    return b;
+}
+
+// Partial sums of the step -> the wave's sums in wsum[par][wave][4p .. 4p+3].
+// part(p) gives pair p's four sums over the thread's rows.  Groups of four
+// pairs (gi, gi+4, gi+8, gi+12) are formed and folded by two register-swap
+// stages (lane^32, lane^16): lane l then holds pair gi + 4 (l / 16), summed
+// over four rows; the 16 lanes of each quarter are summed through LDS.
+template <typename R, typename F>
+__device__ __forceinline__ void block_wave_sums(const BlockLds<R>& bl, F part, int par) {
+    constexpr int B = kBlk;
+    static_assert(B == 16, "the fold below assumes four groups of four pairs");
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    R* wp = bl.wpart + wave * 64 * kBlkPST;
+#pragma unroll
+    for (int gi = 0; gi < 4; ++gi) {
+        R v[16];
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            const quad<R> x = part(gi + 4 * b);
+            v[4 * b + 0] = x.a;
+            v[4 * b + 1] = x.b;
+            v[4 * b + 2] = x.c;
+            v[4 * b + 3] = x.d;
+        }
+        transpose_add<1, 1>(v);
+        *reinterpret_cast<quad<R>*>(wp + lane * kBlkPST + 4 * gi) = quad<R>{v[0], v[1], v[2], v[3]};
+    }
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    // lane l: value l = 4 p + c of pair p = l / 4, held by lanes 16 (p / 4) ..
+    // +15 at slot l % 16
+    const int blk = lane >> 4, slot = lane & 15;
+    R s = 0;
+#pragma unroll
+    for (int h = 0; h < 16; ++h) s += wp[(blk * 16 + h) * kBlkPST + slot];
+    bl.wsum[(par * nw + wave) * 4 * B + lane] = s;
+}
+
+// After the barrier: lanes p < B of every wave sum the per-wave slots of pair
+// p, take its rotation in scaled form (scales of its columns cj, ck in the
+// wave's copy) and publish it to the wave.  Returns true if this lane's pair
+// rotated.
+template <typename R>
+__device__ __forceinline__ bool block_rotations(const BlockLds<R>& bl, int par, int cj, int ck, double tol) {
+    constexpr int B = kBlk;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    bool rot = false;
+    if (lane < B) {
+        double s0 = 0, s1 = 0, s2 = 0, s3 = 0;
+        for (int w = 0; w < nw; ++w) {
+            const quad<R> x = *reinterpret_cast<const quad<R>*>(bl.wsum + (par * nw + w) * 4 * B + 4 * lane);
+            s0 += double(x.a);
+            s1 += double(x.b);
+            s2 += double(x.c);
+            s3 += double(x.d);
+        }
+        R* dsc = bl.wdsc + wave * 2 * B;
+        R dj = dsc[cj], dk = dsc[ck];
+        const double ddj = double(dj), ddk = double(dk);
+        double al = s0 * ddj * ddj, be = s1 * ddk * ddk;
+        quad<R> q;
+        rot = rotation_scaled<R>(al, be, s2 * ddj * ddk, s3 * ddj * ddk, tol, dj, dk, q);
+        dsc[cj] = dj;
+        dsc[ck] = dk;
+        bl.wprm[wave * B + lane] = q;
+    }
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    return rot;
+}
+
+template <typename R>
+__device__ __forceinline__ quad<R> pair_partials(cplx<R> x, cplx<R> y) {
+    quad<R> q;
+    q.a = fma(x.x, x.x, x.y * x.y);
+    q.b = fma(y.x, y.x, y.y * y.y);
+    q.c = fma(x.x, y.x, x.y * y.y);
+    q.d = fma(x.x, y.y, -x.y * y.x);
+    return q;
+}
+
+// Load / store block `blk` (columns blk*B ..) of this thread's row.
+template <typename R>
+__device__ __forceinline__ void load_block(const cplx<R>* base, int ld, int blk, int ncols, int row,
+                                           bool row_ok, cplx<R> (&x)[kBlk]) {
+#pragma unroll
+    for (int k = 0; k < kBlk; ++k) {
+        const int c = blk * kBlk + k;
+        x[k] = (row_ok && c < ncols) ? base[(size_t)c * ld + row] : cplx<R>{R(0), R(0)};
+    }
+}
+template <typename R>
+__device__ __forceinline__ void store_block(cplx<R>* base, int ld, int blk, int ncols, int row,
+                                            bool row_ok, const cplx<R> (&x)[kBlk]) {
+#pragma unroll
+    for (int k = 0; k < kBlk; ++k) {
+        const int c = blk * kBlk + k;
+        if (row_ok && c < ncols) base[(size_t)c * ld + row] = x[k];
+    }
+}
+
+// Team of W work-groups working on one symbol.  Counters live in device
+// memory, cleared before the launch; `target` counts the barriers passed.
+struct Team {
+    int member, W;
+    int32_t* bar;        // arrivals (monotonic)
+    int32_t* rot;        // work-groups that rotated, summed over the sweeps (monotonic)
+    int32_t* err;        // bit 1 set when a barrier timed out
+    int target;
+};
+
+// All W work-groups of the team arrive before any leaves; global writes
+// before the barrier are visible to every member after it (release/acquire
+// at agent scope).  The wait is bounded: on timeout the error bit is set and
+// this and every later barrier return at once, so no wave ever hangs.
+__device__ void team_barrier(Team& t) {
+    t.target += t.W;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __threadfence();
+        __hip_atomic_fetch_add(t.bar, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        int spins = 0;
+        while (__hip_atomic_load(t.bar, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < t.target) {
+            if (__hip_atomic_load(t.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & 2) break;
+            __builtin_amdgcn_s_sleep(4);
+            if (++spins > (1 << 24)) {
+                __hip_atomic_fetch_or(t.err, 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                break;
+            }
+        }
+        __threadfence();
+    }
+    __syncthreads();
+}
+
+// RPT rows per thread: thread t owns rows t, t + nt, ..., t + (RPT-1) nt.
+// ACC: the accumulator Q is present (singular vectors wanted).
+template <typename R, int RPT, bool ACC>
+__device__ void block_sweeps(const LayerDesc& d, const Shared<R>& s, const BlockLds<R>& bl,
+                             int max_sweeps, double tol, Team& team, int& sweeps_out,
+                             bool& conv_out) {
+    constexpr int B = kBlk;
+    const int tid = threadIdx.x, nt = blockDim.x;
+    const int lane = tid & 63, wave = tid >> 6;
+    const int member = team.member, W = team.W;
+    const int M = d.M, N = d.N;
+    const int NB = (N + B - 1) / B, NBP = NB + (NB & 1);
+    constexpr bool acc = ACC;
+    int rows[RPT];
+    bool grow[RPT], qrow[RPT];
+#pragma unroll
+    for (int r = 0; r < RPT; ++r) {
+        rows[r] = tid + r * nt;
+        grow[r] = rows[r] < M;
+        qrow[r] = acc && rows[r] < N;
+    }
+    cplx<R> ga[RPT][B], gb[RPT][B], va[ACC ? RPT : 1][ACC ? B : 1], vb[ACC ? RPT : 1][ACC ? B : 1];
+    R* dsc = bl.wdsc + wave * 2 * B;
+    int par = 0;                 // step parity (per-wave sums buffer)
+    // block pair in: unit scales (this wave's copy)
+    auto load2 = [&](int ba, int bb) {
+        if (lane < 2 * B) dsc[lane] = R(1);
+#pragma unroll
+        for (int r = 0; r < RPT; ++r) {
+            load_block(s.G, d.ldg, ba, N, rows[r], grow[r], ga[r]);
+            load_block(s.G, d.ldg, bb, N, rows[r], grow[r], gb[r]);
+            if constexpr (ACC) {
+                load_block(s.Q, d.ldv, ba, N, rows[r], qrow[r], va[r]);
+                load_block(s.Q, d.ldv, bb, N, rows[r], qrow[r], vb[r]);
+            }
+        }
+    };
+    // block pair out: fold the scales (positions are the identity again)
+    auto store2 = [&](int ba, int bb) {
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+#pragma unroll
+        for (int k = 0; k < B; ++k) {
+            const R fa = dsc[k], fb = dsc[B + k];
+#pragma unroll
+            for (int r = 0; r < RPT; ++r) {
+                ga[r][k] = {ga[r][k].x * fa, ga[r][k].y * fa};
+                gb[r][k] = {gb[r][k].x * fb, gb[r][k].y * fb};
+                if constexpr (ACC) {
+                    va[r][k] = {va[r][k].x * fa, va[r][k].y * fa};
+                    vb[r][k] = {vb[r][k].x * fb, vb[r][k].y * fb};
+                }
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < RPT; ++r) {
+            store_block(s.G, d.ldg, ba, N, rows[r], grow[r], ga[r]);
+            store_block(s.G, d.ldg, bb, N, rows[r], grow[r], gb[r]);
+            if constexpr (ACC) {
+                store_block(s.Q, d.ldv, ba, N, rows[r], qrow[r], va[r]);
+                store_block(s.Q, d.ldv, bb, N, rows[r], qrow[r], vb[r]);
+            }
+        }
+    };
+    int sweeps = 0;
+    bool converged = (N < 2);
+    while (!converged && sweeps < max_sweeps) {
+        if (tid == 0) *bl.rflag = 0;
+        __syncthreads();
+        // team: rotations counted before this sweep (all earlier increments
+        // happened before the barrier that ended the previous sweep)
+        const int rot_before =
+            W > 1 ? __hip_atomic_load(team.rot, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) : 0;
+        bool rotated = false;
+        // ---- intra pass: pairs inside blocks 2i and 2i+1
+        for (int i = member; 2 * i < NB; i += W) {
+            const int ba = 2 * i, bb = 2 * i + 1;
+            load2(ba, bb);
+            for (int step = 0; step < B - 1; ++step) {
+                // pair p < B/2: positions (p, B-1-p) of block a, else of block b
+                block_wave_sums<R>(bl, [&](int p) {
+                    quad<R> q = {R(0), R(0), R(0), R(0)};
+#pragma unroll
+                    for (int r = 0; r < RPT; ++r) {
+                        const quad<R> x = p < B / 2 ? pair_partials(ga[r][p], ga[r][B - 1 - p])
+                                                    : pair_partials(gb[r][p - B / 2], gb[r][B - 1 - (p - B / 2)]);
+                        q = {q.a + x.a, q.b + x.b, q.c + x.c, q.d + x.d};
+                    }
+                    return q;
+                }, par);
+                __syncthreads();
+                {
+                    // columns of pair `lane` (lanes >= B compute nothing)
+                    const int pp = lane < B / 2 ? lane : lane - B / 2, off = lane < B / 2 ? 0 : B;
+                    const int cj = off + col_at<B>(pp, step), ck = off + col_at<B>(B - 1 - pp, step);
+                    rotated |= block_rotations<R>(bl, par, cj, ck, tol);
+                }
+                par ^= 1;
+                const quad<R>* prm = bl.wprm + wave * B;
+#pragma unroll
+                for (int p = 0; p < B / 2; ++p) {
+                    const quad<R> ra = prm[p], rb = prm[B / 2 + p];
+#pragma unroll
+                    for (int r = 0; r < RPT; ++r) {
+                        rot_apply_scaled(ga[r][p], ga[r][B - 1 - p], ra.a, ra.b, ra.c, ra.d);
+                        rot_apply_scaled(gb[r][p], gb[r][B - 1 - p], rb.a, rb.b, rb.c, rb.d);
+                        if constexpr (ACC) {
+                            rot_apply_scaled(va[r][p], va[r][B - 1 - p], ra.a, ra.b, ra.c, ra.d);
+                            rot_apply_scaled(vb[r][p], vb[r][B - 1 - p], rb.a, rb.b, rb.c, rb.d);
+                        }
+                    }
+                }
+                // round-robin: positions 1..B-1 move by one
+#pragma unroll
+                for (int r = 0; r < RPT; ++r) {
+                    rotate_positions<B>(ga[r]);
+                    rotate_positions<B>(gb[r]);
+                    if constexpr (ACC) {
+                        rotate_positions<B>(va[r]);
+                        rotate_positions<B>(vb[r]);
+                    }
+                }
+            }
+            // B-1 steps bring every position back: store in place
+            store2(ba, bb);
+        }
+        if (W > 1) team_barrier(team);
+        // ---- cross passes: round-robin over block pairs
+        for (int os = 0; os < NBP - 1; ++os) {
+            for (int bp = member; bp < NBP / 2; bp += W) {
+                int ba, bb;
+                rr_pair(bp, os, NBP, ba, bb);
+                if (ba >= NB || bb >= NB) continue;
+                load2(ba, bb);
+                for (int t = 0; t < B; ++t) {
+                    block_wave_sums<R>(bl, [&](int p) {
+                        quad<R> q = {R(0), R(0), R(0), R(0)};
+#pragma unroll
+                        for (int r = 0; r < RPT; ++r) {
+                            const quad<R> x = pair_partials(ga[r][p], gb[r][p]);
+                            q = {q.a + x.a, q.b + x.b, q.c + x.c, q.d + x.d};
+                        }
+                        return q;
+                    }, par);
+                    __syncthreads();
+                    {
+                        const int cj = lane < B ? lane : 0;
+                        const int ck = B + ((cj + t) & (B - 1));
+                        rotated |= block_rotations<R>(bl, par, cj, ck, tol);
+                    }
+                    par ^= 1;
+                    const quad<R>* prm = bl.wprm + wave * B;
+#pragma unroll
+                    for (int p = 0; p < B; ++p) {
+                        const quad<R> rr = prm[p];
+#pragma unroll
+                        for (int r = 0; r < RPT; ++r) {
+                            rot_apply_scaled(ga[r][p], gb[r][p], rr.a, rr.b, rr.c, rr.d);
+                            if constexpr (ACC) rot_apply_scaled(va[r][p], vb[r][p], rr.a, rr.b, rr.c, rr.d);
+                        }
+                    }
+                    // block b shifts by one against block a
+#pragma unroll
+                    for (int r = 0; r < RPT; ++r) {
+                        const cplx<R> fb = gb[r][0];
+#pragma unroll
+                        for (int k = 0; k < B - 1; ++k) gb[r][k] = gb[r][k + 1];
+                        gb[r][B - 1] = fb;
+                        if constexpr (ACC) {
+                            const cplx<R> fv = vb[r][0];
+#pragma unroll
+                            for (int k = 0; k < B - 1; ++k) vb[r][k] = vb[r][k + 1];
+                            vb[r][B - 1] = fv;
+                        }
+                    }
+                }
+                // B shifts bring block b back to its order
+                store2(ba, bb);
+            }
+            if (W > 1 && os < NBP - 2) team_barrier(team);
+        }
+        // every wave computed the same rotations: wave 0 reports them
+        if (wave == 0 && __any(rotated)) {
+            if (lane == 0) *bl.rflag = 1;
+        }
+        __syncthreads();
+        if (W > 1) {
+            if (tid == 0 && *bl.rflag)
+                __hip_atomic_fetch_add(team.rot, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            team_barrier(team);
+            converged = __hip_atomic_load(team.rot, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) ==
+                        rot_before;
+        } else {
+            converged = (*bl.rflag == 0);
+        }
+        ++sweeps;
+        __syncthreads();
+    }
+    sweeps_out = sweeps;
+    conv_out = converged;
+}
+
+template <typename R, int RPT, bool ACC>
+__device__ void block_one(const SvdArgs<R>& a, char* lds, int item, char* gslot, Team& team) {
+    // ACC must match the arguments: the right singular vectors (left when
+    // transposed) are wanted exactly when the accumulator is kept
+    const Target tg = target_of(a, item);
+    const Shared<R> s = carve<R>(lds, a.d, ACC, gslot);
+    const BlockLds<R> bl = carve_block<R>(lds, s.small_end);
+    if (team.member == 0) load_symbol<R>(a, s, tg.theta);
+    if (team.W > 1) team_barrier(team);
+    else __syncthreads();
+    int sweeps;
+    bool converged;
+    block_sweeps<R, RPT, ACC>(a.d, s, bl, a.max_sweeps, a.tol, team, sweeps, converged);
+    if (team.member == 0) finish<R, 64>(a, s, tg.out, tg.mirror, sweeps, converged);
+    // the slot is reused for the team's next symbol: members wait for the finish
+    if (team.W > 1) team_barrier(team);
+    if (a.info && threadIdx.x == 0 && team.member == 0 &&
+        (__hip_atomic_load(team.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & 2))
+        atomicOr(&a.info[LFA_INFO_NONFINITE], 2);
+}
+
+
+// ===================== register (rows-in-lanes) kernel =====================
+// Register-resident one-sided Jacobi SVD for symbols of at most 64 rows and
+// 64 columns (rows-in-lanes layout), gfx950.
+//
+// A work-group is one wavefront for G (plus one for the rotation accumulator
+// when singular vectors are wanted).  Lane l of the G wave owns row l of the
+// M x N working matrix G of its symbol in registers, all NC (>= N, power of
+// two) columns; with ML lanes per symbol (16, 32 or 64) one wave holds
+// 64/ML symbols.  Lane l of the second wave owns row l of the N x N
+// accumulator Q.
+//
+// One round-robin step pairs the columns at positions (p, NC-1-p),
+// p < NC/2 -- all compile-time register indices -- and then rotates the
+// positions 1..NC-1 by one (register moves).  After NC-1 steps, i.e. one
+// sweep, every column is back at its starting position, so the final column
+// order is the original one.
+//
+// Per step:
+//  1. every G lane forms its row's contributions to gamma_p = g_j^H g_k for
+//     all pairs.  Groups of NB pairs are folded across lanes by transpose-add
+//     stages (lane^32 and lane^16 register swaps): after them a lane holds
+//     one pair's partial sum over NB rows, and the lanes of block b = row /
+//     GL hold the pairs b*Q .. b*Q+Q-1.  The folded partials go to LDS,
+//     [symbol][row][2Q] (padded row stride);
+//  2. lane (p, k) of the same wave sums Q holder rows of pair p, the LP
+//     lanes of a pair are combined with xor exchanges, and every lane of the
+//     pair evaluates the rotation (threshold test and angle in double
+//     precision) from gamma_p and the squared norms alpha = |g_j|^2,
+//     beta = |g_k|^2.  The norms are not summed again each step: they are
+//     computed exactly at the start of every sweep and updated with each
+//     rotation (alpha - t|gamma|, beta + t|gamma|), so the convergence test
+//     of the final, rotation-free sweep uses exact norms.  One lane of the
+//     pair's set writes (c, s e^{-i phi}, flag) to a double-buffered LDS
+//     slot;
+//  3. after one work-group barrier every lane of both waves reads the
+//     parameters (broadcast) and applies the pair rotations to its registers
+//     (a pair below the threshold gets the identity, applied without a
+//     branch).  The Q wave only applies, so it runs a step behind the G wave and its work
+//     overlaps the next step's inner products.
+// One work-group barrier per step; no LDS traffic for G or Q themselves.  The
+// symbols are assembled into registers through a small LDS tile, a chunk of
+// columns at a time, and the results are written from registers.
+
+
+template <typename R>
+__device__ __forceinline__ R skey(R v) {
+    return v == v ? v : R(-1);
+}
+
+
+__device__ __forceinline__ void phase_of(const double* tw, const LayerDesc& d, int theta, int t,
+                                         double& re, double& im) {
+    const int p = theta / d.m, q = theta - (theta / d.m) * d.m;
+    const int a = t / d.kw, b = t - (t / d.kw) * d.kw;
+    const int y1 = a - (d.kh - 1) / 2, y2 = b - (d.kw - 1) / 2;
+    int i1 = (p * y1) % d.n;
+    if (i1 < 0) i1 += d.n;
+    int i2 = (q * y2) % d.m;
+    if (i2 < 0) i2 += d.m;
+    const double ar = tw[2 * (d.tw_n + i1)], ai = tw[2 * (d.tw_n + i1) + 1];
+    const double br = tw[2 * (d.tw_m + i2)], bi = tw[2 * (d.tw_m + i2) + 1];
+    re = ar * br - ai * bi;
+    im = ar * bi + ai * br;
+}
 
 constexpr int pow2_floor(int x) {
     int p = 1;

@@ -359,10 +359,10 @@ constexpr int kPersistentThreads = 256;
 // number of work-groups of the launch that fit on the device at once.
 size_t persistent_lds_bytes(const LayerDesc* descs, int n, bool accumulate, int elem_bytes,
                             int wave_slots);
-int persistent_resident(size_t lds, int elem_bytes);
-hipError_t launch_persistent_f32(const PersistentArgs<float>& a, int grid, size_t lds,
+int persistent_resident(size_t lds, int elem_bytes, bool accumulate);
+hipError_t launch_persistent_f32(const PersistentArgs<float>& a, int grid, size_t lds, bool accumulate,
                                  hipStream_t s);
-hipError_t launch_persistent_f64(const PersistentArgs<double>& a, int grid, size_t lds,
+hipError_t launch_persistent_f64(const PersistentArgs<double>& a, int grid, size_t lds, bool accumulate,
                                  hipStream_t s);
 
 }  // namespace lfa

@@ -33,7 +33,9 @@ __device__ void run_bundle(const SvdArgs<R>& a, char* lds, int base, int wave_sl
 #undef LFA_CASE
 }
 
-template <typename R>
+// ACC: the blocked items keep the accumulator (singular vectors wanted);
+// bundles of the register kernel occur only without it.
+template <typename R, bool ACC>
 __global__ void __launch_bounds__(256) persistent_kernel(PersistentArgs<R> pa_arg) {
     extern __shared__ __align__(16) char lds[];
     __shared__ int item_sh;
@@ -54,7 +56,7 @@ __global__ void __launch_bounds__(256) persistent_kernel(PersistentArgs<R> pa_ar
         const WorkItem w = pa.items[idx];
         const SvdArgs<R>& a = pa.layer[w.layer];
         if (w.kind == 0) {
-            run_bundle<R>(a, lds, w.item, pa.wave_slots, pa.wave_lds);
+            if constexpr (!ACC) run_bundle<R>(a, lds, w.item, pa.wave_slots, pa.wave_lds);
             __syncthreads();
         } else {
             Team team;
@@ -65,8 +67,8 @@ __global__ void __launch_bounds__(256) persistent_kernel(PersistentArgs<R> pa_ar
             team.err = pa.team_counters + 4 * pa.num_teams;
             team.target = 0;
             char* gslot = a.gws + (size_t)w.item * a.slot_bytes;
-            if (a.d.M > 256) block_one<R, 2>(a, lds, w.item, gslot, team);
-            else block_one<R, 1>(a, lds, w.item, gslot, team);
+            if (a.d.M > 256) block_one<R, 2, ACC>(a, lds, w.item, gslot, team);
+            else block_one<R, 1, ACC>(a, lds, w.item, gslot, team);
         }
     }
 }
@@ -78,19 +80,19 @@ hipError_t allow_lds_p(K kernel, size_t lds) {
                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
 }
 
-template <typename R>
+template <typename R, bool ACC>
 hipError_t launch_p(const PersistentArgs<R>& a, int grid, size_t lds, hipStream_t s) {
-    hipError_t e = allow_lds_p(persistent_kernel<R>, lds);
+    hipError_t e = allow_lds_p(persistent_kernel<R, ACC>, lds);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(persistent_kernel<R>, dim3(grid), dim3(a.threads), lds, s, a);
+    hipLaunchKernelGGL((persistent_kernel<R, ACC>), dim3(grid), dim3(a.threads), lds, s, a);
     return hipGetLastError();
 }
 
-template <typename R>
+template <typename R, bool ACC>
 int resident_p(size_t lds) {
-    if (allow_lds_p(persistent_kernel<R>, lds) != hipSuccess) return 0;
+    if (allow_lds_p(persistent_kernel<R, ACC>, lds) != hipSuccess) return 0;
     int per_cu = 0, dev = 0, cus = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, persistent_kernel<R>,
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, persistent_kernel<R, ACC>,
                                                      kPersistentThreads, lds) != hipSuccess)
         return 0;
     if (hipGetDevice(&dev) != hipSuccess ||
@@ -117,17 +119,18 @@ size_t persistent_lds_bytes(const LayerDesc* descs, int n, bool accumulate, int 
     return lds;
 }
 
-int persistent_resident(size_t lds, int elem_bytes) {
-    return elem_bytes == 8 ? resident_p<double>(lds) : resident_p<float>(lds);
+int persistent_resident(size_t lds, int elem_bytes, bool accumulate) {
+    if (elem_bytes == 8) return accumulate ? resident_p<double, true>(lds) : resident_p<double, false>(lds);
+    return accumulate ? resident_p<float, true>(lds) : resident_p<float, false>(lds);
 }
 
-hipError_t launch_persistent_f32(const PersistentArgs<float>& a, int grid, size_t lds,
+hipError_t launch_persistent_f32(const PersistentArgs<float>& a, int grid, size_t lds, bool accumulate,
                                  hipStream_t s) {
-    return launch_p<float>(a, grid, lds, s);
+    return accumulate ? launch_p<float, true>(a, grid, lds, s) : launch_p<float, false>(a, grid, lds, s);
 }
-hipError_t launch_persistent_f64(const PersistentArgs<double>& a, int grid, size_t lds,
+hipError_t launch_persistent_f64(const PersistentArgs<double>& a, int grid, size_t lds, bool accumulate,
                                  hipStream_t s) {
-    return launch_p<double>(a, grid, lds, s);
+    return accumulate ? launch_p<double, true>(a, grid, lds, s) : launch_p<double, false>(a, grid, lds, s);
 }
 
 }  // namespace lfa
