@@ -20,6 +20,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "lfa_internal.hpp"
 
 namespace lfa {
@@ -38,6 +40,16 @@ __device__ __forceinline__ void phase_d(const double* tw, const LayerDesc& d, in
     const double br = tw[2 * (d.tw_m + i2)], bi = tw[2 * (d.tw_m + i2) + 1];
     re = ar * br - ai * bi;
     im = ar * bi + ai * br;
+}
+
+// Symbols are written once and not read back by the kernel: streaming
+// (non-temporal) stores keep them from displacing W and the twiddles in the
+// caches and write at a markedly higher rate.
+template <typename R>
+__device__ __forceinline__ void store_stream(cplx<R>* dst, R re, R im) {
+    R* p = reinterpret_cast<R*>(dst);
+    __builtin_nontemporal_store(re, p);
+    __builtin_nontemporal_store(im, p + 1);
 }
 
 constexpr int kValuThetaTile = 16;
@@ -76,7 +88,7 @@ __global__ void __launch_bounds__(256) symbols_valu(LayerDesc d, const R* __rest
     }
 #pragma unroll
     for (int th = 0; th < kValuThetaTile; ++th)
-        if (th < nth) A[(size_t)(theta0 + th) * E + e] = {re[th], im[th]};
+        if (th < nth) store_stream(A + (size_t)(theta0 + th) * E + e, re[th], im[th]);
 }
 
 // ---------------------------------------------------------------- MFMA ----
@@ -201,9 +213,189 @@ __global__ void __launch_bounds__(256) symbols_mfma(LayerDesc d, const float* __
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
             const int th = theta0 + 4 * lk + v;
-            if (th < HW && e < E) A[(size_t)th * E + e] = {acc_re[s][v], acc_im[s][v]};
+            if (th < HW && e < E) store_stream(A + (size_t)th * E + e, acc_re[s][v], acc_im[s][v]);
         }
     }
+}
+
+// ---------------------------------------------- MFMA, phases held --------
+// For up to kMfma2MaxTaps taps.  A block of 4 waves owns 64 frequencies (16
+// per wave) and loops over column tiles of 64 e: the phases of its
+// frequencies are evaluated once, as ready MFMA A-fragments in registers
+// (one set per bfloat16 split term in the split modes), and each 64 x T tile
+// of W is staged once in LDS (as its split terms) and shared by the four
+// waves.  The split modes run one accumulation pass over K = taps per product
+// (A term, W term) of kSegA / kSegB into the same accumulators.
+constexpr int kMfma2MaxTaps = 64;
+
+// Products of split terms, (A term, W term), in the order of kSegA / kSegB.
+constexpr int kProdA[2][6] = {{0, 0, 1, 0, 0, 0}, {0, 0, 1, 0, 1, 2}};
+constexpr int kProdB[2][6] = {{0, 1, 0, 0, 0, 0}, {0, 1, 0, 2, 1, 0}};
+
+template <int MODE>
+struct Mfma2 {
+    static constexpr int TERMS = MODE == 0 ? 1 : (MODE == 2 ? 2 : 3);
+    static constexpr int NPROD = MODE == 0 ? 1 : (MODE == 2 ? 3 : 6);
+    static constexpr int KSTEP = MODE == 0 ? 4 : 16;
+    static constexpr int KS = kMfma2MaxTaps / KSTEP;                         // max K steps
+    static constexpr int ROW = MODE == 0 ? kMfma2MaxTaps + 1 : kMfma2MaxTaps + 4;   // LDS row, padded
+};
+
+template <int MODE>
+__global__ void __launch_bounds__(256) symbols_mfma2(LayerDesc d, const float* __restrict__ W,
+                                                     cplx<float>* __restrict__ A,
+                                                     const double* __restrict__ tw, int echunk) {
+    using C = Mfma2<MODE>;
+    constexpr int ms = MODE == 3 ? 1 : 0;
+    extern __shared__ __align__(16) char lds_raw[];
+    const int T = d.kh * d.kw;
+    const int E = d.c_out * d.c_in;
+    const int HW = d.num_symbols;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int li = lane & 15, lk = lane >> 4;
+    const int theta0 = blockIdx.y * 64 + wave * 16;
+    const int theta_a = theta0 + li;
+    const int ks = (T + C::KSTEP - 1) / C::KSTEP;     // K steps actually used
+
+    // A-fragments (phases) of this wave's 16 frequencies: lane (li, lk) holds
+    // row theta0 + li at taps 4 kt + lk (FP32) or 16 kt + 4 lk + v (bf16)
+    float pr[MODE == 0 ? C::KS : 1], pi[MODE == 0 ? C::KS : 1];
+    bf16x4 ar[C::TERMS][MODE == 0 ? 1 : C::KS], ai[C::TERMS][MODE == 0 ? 1 : C::KS];
+#pragma unroll
+    for (int kt = 0; kt < C::KS; ++kt) {
+        if constexpr (MODE == 0) {
+            const int t = 4 * kt + lk;
+            float r = 0.f, im = 0.f;
+            if (kt < ks && t < T && theta_a < HW) {
+                double re, imd;
+                phase_d(tw, d, theta_a, t, re, imd);
+                r = float(re);
+                im = float(imd);
+            }
+            pr[kt] = r;
+            pi[kt] = im;
+        } else {
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int t = 16 * kt + 4 * lk + v;
+                unsigned short sr[3] = {0, 0, 0}, si[3] = {0, 0, 0};
+                if (kt < ks && t < T && theta_a < HW) {
+                    double re, imd;
+                    phase_d(tw, d, theta_a, t, re, imd);
+                    split_bf16(float(re), C::TERMS, sr);
+                    split_bf16(float(imd), C::TERMS, si);
+                }
+#pragma unroll
+                for (int u = 0; u < C::TERMS; ++u) {
+                    ar[u][kt][v] = (short)sr[u];
+                    ai[u][kt][v] = (short)si[u];
+                }
+            }
+        }
+    }
+
+    const int e_begin = blockIdx.x * echunk, e_end = min(E, e_begin + echunk);
+    for (int e0 = e_begin; e0 < e_end; e0 += 64) {
+        // stage the W tile: rows e0 .. e0+63 of T taps each (contiguous in W),
+        // zero beyond T; split modes: one plane per split term
+        __syncthreads();
+        for (int x = threadIdx.x; x < 64 * C::ROW; x += blockDim.x) {
+            const int r = x / C::ROW, t = x - r * C::ROW;
+            const int e = e0 + r;
+            const float w = (t < T && e < E) ? W[(size_t)e * T + t] : 0.f;
+            if constexpr (MODE == 0) {
+                reinterpret_cast<float*>(lds_raw)[x] = w;
+            } else {
+                unsigned short sw[3] = {0, 0, 0};
+                split_bf16(w, C::TERMS, sw);
+#pragma unroll
+                for (int u = 0; u < C::TERMS; ++u)
+                    reinterpret_cast<unsigned short*>(lds_raw)[u * 64 * C::ROW + x] = sw[u];
+            }
+        }
+        __syncthreads();
+        floatx4 acc_re[4], acc_im[4];
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+            acc_re[s] = floatx4{0.f, 0.f, 0.f, 0.f};
+            acc_im[s] = floatx4{0.f, 0.f, 0.f, 0.f};
+        }
+        if constexpr (MODE == 0) {
+            const float* wl = reinterpret_cast<const float*>(lds_raw);
+#pragma unroll
+            for (int kt = 0; kt < C::KS; ++kt) {
+                if (kt < ks) {
+#pragma unroll
+                    for (int s = 0; s < 4; ++s) {
+                        const float b = wl[(s * 16 + li) * C::ROW + 4 * kt + lk];
+                        acc_re[s] = __builtin_amdgcn_mfma_f32_16x16x4f32(pr[kt], b, acc_re[s], 0, 0, 0);
+                        acc_im[s] = __builtin_amdgcn_mfma_f32_16x16x4f32(pi[kt], b, acc_im[s], 0, 0, 0);
+                    }
+                }
+            }
+        } else {
+            const unsigned short* wl = reinterpret_cast<const unsigned short*>(lds_raw);
+#pragma unroll
+            for (int pp = 0; pp < C::NPROD; ++pp) {
+                const int ta = kProdA[ms][pp], tb = kProdB[ms][pp];
+#pragma unroll
+                for (int kt = 0; kt < C::KS; ++kt) {
+                    if (kt < ks) {
+                        // split terms are selected with compile-time indices
+                        bf16x4 fa_r = ar[0][kt], fa_i = ai[0][kt];
+#pragma unroll
+                        for (int u = 1; u < C::TERMS; ++u)
+                            if (ta == u) {
+                                fa_r = ar[u][kt];
+                                fa_i = ai[u][kt];
+                            }
+#pragma unroll
+                        for (int s = 0; s < 4; ++s) {
+                            const bf16x4 b = *reinterpret_cast<const bf16x4*>(
+                                wl + tb * 64 * C::ROW + (s * 16 + li) * C::ROW + 16 * kt + 4 * lk);
+                            acc_re[s] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(fa_r, b, acc_re[s], 0, 0, 0);
+                            acc_im[s] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(fa_i, b, acc_im[s], 0, 0, 0);
+                        }
+                    }
+                }
+            }
+        }
+        // D[i][j]: j = lane & 15 (e), i = 4*(lane >> 4) + v (frequency)
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+            const int e = e0 + s * 16 + li;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int th = theta0 + 4 * lk + v;
+                if (th < HW && e < E) store_stream(A + (size_t)th * E + e, acc_re[s][v], acc_im[s][v]);
+            }
+        }
+    }
+}
+
+template <int MODE>
+constexpr size_t mfma2_lds_bytes() {
+    return 64 * (size_t)Mfma2<MODE>::ROW * (MODE == 0 ? sizeof(float) : Mfma2<MODE>::TERMS * sizeof(unsigned short));
+}
+
+template <int MODE>
+hipError_t launch_mfma2(const LayerDesc& d, const float* W, cplx<float>* A, const double* tw, hipStream_t s) {
+    const int E = d.c_out * d.c_in;
+    const int tblocks = (d.num_symbols + 63) / 64;
+    // enough blocks for the device: split the e range when there are few
+    // frequency tiles (each block still covers >= 64 columns)
+    const int etiles = (E + 63) / 64;
+    const int split = std::max(1, std::min(etiles, (2048 + tblocks - 1) / tblocks));
+    const int echunk = 64 * ((etiles + split - 1) / split);
+    const dim3 grid((E + echunk - 1) / echunk, tblocks);
+    const size_t lds = mfma2_lds_bytes<MODE>();
+    if (lds > 65536) {
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(symbols_mfma2<MODE>),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(symbols_mfma2<MODE>, grid, dim3(256), lds, s, d, W, A, tw, echunk);
+    return hipGetLastError();
 }
 
 }  // namespace
@@ -226,6 +418,11 @@ hipError_t launch_symbols_valu_f64(const LayerDesc& d, const double* W, cplx<dou
 
 hipError_t launch_symbols_mfma(const LayerDesc& d, const float* W, cplx<float>* A,
                                const double* tw, int mode, hipStream_t s) {
+    if (d.kh * d.kw <= kMfma2MaxTaps) {
+        if (mode == 0) return launch_mfma2<0>(d, W, A, tw, s);
+        if (mode == 2) return launch_mfma2<2>(d, W, A, tw, s);
+        if (mode == 3) return launch_mfma2<3>(d, W, A, tw, s);
+    }
     const int E = d.c_out * d.c_in;
     const dim3 grid((E + kMfmaETile - 1) / kMfmaETile, (d.num_symbols + 63) / 64);
     hipLaunchKernelGGL(symbols_mfma, grid, dim3(256), 0, s, d, W, A, tw, mode);
