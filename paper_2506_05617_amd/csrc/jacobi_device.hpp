@@ -1206,6 +1206,8 @@ __device__ void wave_group(const SvdArgs<R>& a, char* lds_raw, int base, int tid
         dsc[sym * NC + row] = R(1);
         dsc[SPW * NC + sym * NC + row] = R(1);
     }
+    // the Q wave reads the scales at the first segment start
+    wsync(solo);
     int cur = 0;                // scale buffer of the current segment
 
     // -------------------------------------------------------------- sweeps
@@ -1356,8 +1358,10 @@ __device__ void wave_group(const SvdArgs<R>& a, char* lds_raw, int base, int tid
         }
     }
     if (tid < SPW) {
+        // slots past the last item hold no symbol: nothing to complete
         int z = 0;
-        for (int k = 0; k < N; ++k) z += sigs[tid * NC + k] == R(0);
+        if (base + tid < count)
+            for (int k = 0; k < N; ++k) z += sigs[tid * NC + k] == R(0);
         nzero[tid] = z;
     }
     wsync(solo);
@@ -1390,6 +1394,10 @@ __device__ void wave_group(const SvdArgs<R>& a, char* lds_raw, int base, int tid
         // inner products are sums over the ML lanes of its symbol, and every
         // loop bound is uniform over the wave (symbols with fewer zero
         // columns idle through the extra iterations).
+        // candidates e_cand continue across the zero columns of a symbol
+        // (those already used are in the span of the accepted columns)
+        int cand = 0;
+        R thresh = R(0.5);
         for (int c = 0; c < nzmax; ++c) {
             int jz = -1, cnt = 0;
 #pragma unroll
@@ -1400,8 +1408,6 @@ __device__ void wave_group(const SvdArgs<R>& a, char* lds_raw, int base, int tid
                 }
             }
             bool done = jz < 0;
-            int cand = 0;
-            R thresh = R(0.5);
             for (int tries = 0; tries < 4 * M; ++tries) {
                 if (__all(done)) break;
                 if (cand == M) {

@@ -191,6 +191,22 @@ def test_single_layer_64_full_size_sampled():
     assert abs(ps - 1) <= 1e-6
 
 
+# ------------------------------------------- repeated vectors, 64 x 64 --
+
+@pytest.mark.parametrize("dt", [np.float64, np.float32])
+def test_register_kernel_vectors_repeated(dt):
+    """The register kernel's two waves (working matrix and accumulator) share
+    LDS state; a missing synchronisation shows up as a wrong V on some runs
+    only.  Several seeds, every symbol checked (residual and orthonormality)."""
+    banner(f"repeated 64x64 vectors {dt.__name__}")
+    tdt = torch.float32 if dt == np.float32 else torch.float64
+    for seed in (11, 12, 13, 14):
+        _, W = workloads.random_layer(64, 64, 3, 3, 6, 5, seed=seed, dtype=dt)
+        S, U, V, info = _run_svd(W, 6, 5, True)
+        A = oracle.symbols(W.astype(np.float64), 6, 5)
+        check_vectors(A, to_np(S), to_np(U), to_np(V), tdt, f"seed {seed}")
+
+
 # ------------------------------------------------------ paper-scale grid --
 
 def test_paper_scale_n16384_sampled():
