@@ -1068,13 +1068,23 @@ constexpr int wave_part_elems() {
 }
 
 template <typename R, int NC, int ML>
-size_t wave_lds_bytes() {
+__host__ __device__ constexpr size_t wave_lds_bytes() {
     using S = WaveShape<NC, ML>;
     const size_t part = (size_t)wave_part_elems<R, NC, ML>() * sizeof(R);
     const size_t prm = 2 * (size_t)S::SPW * S::NP * 4 * sizeof(R);   // double-buffered
-    const size_t small = (size_t)S::SPW * NC * (sizeof(double) + 3 * sizeof(R) + sizeof(int)) +
+    const size_t small = (size_t)S::SPW * NC * (sizeof(double) + 3 * sizeof(R) + 2 * sizeof(int)) +
                          (size_t)S::SPW * 2 * sizeof(int);
     return part + prm + small + 64;
+}
+
+// Output staging of launches with singular vectors, after the other LDS
+// arrays: chunks of up to 32 rows (padded by one element) per symbol.
+template <int ML>
+__host__ __device__ constexpr int wave_stage_rows() { return ML < 32 ? ML : 32; }
+
+template <typename R, int NC, int ML>
+__host__ __device__ constexpr size_t wave_stage_bytes() {
+    return (size_t)(64 / ML) * wave_stage_rows<ML>() * (NC + 1) * sizeof(cplx<R>) + 64;
 }
 
 // Synchronisation of the threads working on one group of symbols: the whole
@@ -1113,6 +1123,40 @@ __device__ __forceinline__ R column_norm(const R* part, int sym, int j) {
     return s;
 }
 
+// Writes the rows of one output matrix per symbol, [rows][N] row-major (row
+// r held by lane r of the symbol's ML lanes; column j of the registers goes
+// to output column rank[j]), with coalesced stores: chunks of rows are copied
+// into LDS in register order, and the lanes write them back in memory order,
+// output column c taken from register column inv[c] (inv = rank^-1), whole
+// cache lines per instruction instead of one element of each of 64 rows.
+// Every lane of the wave calls it; out / mir may be null (inactive symbol,
+// no mirror).
+template <typename R, int NC, int ML>
+__device__ void store_rows(cplx<R>* out, cplx<R>* mir, int rows, int N, const int* inv,
+                           const cplx<R> (&g)[NC], cplx<R>* stage, int sym, int row) {
+    constexpr int LD = NC + 1, RC = wave_stage_rows<ML>();   // padded row, rows per chunk
+    cplx<R>* st = stage + sym * RC * LD;                       // this symbol's chunk [RC][LD]
+    for (int c0 = 0; c0 < rows; c0 += RC) {
+        const int r = row - c0;
+        if (r >= 0 && r < RC) {
+#pragma unroll
+            for (int j = 0; j < NC; ++j) st[r * LD + j] = g[j];
+        }
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        const int nrow = min(RC, rows - c0);
+        for (int e = row; e < nrow * N; e += ML) {
+            const int rr = e / N, cc = e - (e / N) * N;
+            const cplx<R> v = st[rr * LD + inv[cc]];
+            const size_t at = (size_t)(c0 + rr) * N + cc;
+            if (out) out[at] = v;
+            if (mir) mir[at] = {v.x, -v.y};
+        }
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+    }
+}
+
 // One group of SPW symbols (items base .. base+SPW-1) by `nthr` threads with
 // index `tid`: 64 (G only) or 128 (G wave + Q wave, not solo).
 template <typename R, int NC, int ML>
@@ -1129,6 +1173,10 @@ __device__ void wave_group(const SvdArgs<R>& a, char* lds_raw, int base, int tid
     int* rankof = reinterpret_cast<int*>(sigs + SPW * NC);          // [SPW][NC]
     int* nzero = rankof + SPW * NC;                                 // [SPW] zero columns
     int* flags = nzero + SPW;                                       // [SPW] rotated this sweep
+    int* colof = flags + SPW;                                       // [SPW][NC] rank -> column
+    // output staging (launches with vectors only): after everything else
+    cplx<R>* stage = reinterpret_cast<cplx<R>*>(
+        reinterpret_cast<char*>(lds_raw) + ((wave_lds_bytes<R, NC, ML>() + 63) & ~size_t(63)));
 
     const LayerDesc& d = a.d;
     const int lane = tid & 63;
@@ -1352,6 +1400,7 @@ __device__ void wave_group(const SvdArgs<R>& a, char* lds_raw, int base, int tid
             rank += (sk > sj) || (sk == sj && k < row);
         }
         rankof[sym * NC + row] = rank;
+        colof[sym * NC + rank] = row;
         if (active) {
             a.sigma[(size_t)tg.out * N + rank] = sigs[sym * NC + row];
             if (tg.mirror >= 0) a.sigma[(size_t)tg.mirror * N + rank] = sigs[sym * NC + row];
@@ -1446,30 +1495,16 @@ __device__ void wave_group(const SvdArgs<R>& a, char* lds_raw, int base, int tid
                 if (!done) ++cand;
             }
         }
-        if (active && row < M) {
-            cplx<R>* out = left + (size_t)tg.out * M * N + (size_t)row * N;
-            cplx<R>* mir = tg.mirror >= 0 ? left + (size_t)tg.mirror * M * N + (size_t)row * N : nullptr;
-#pragma unroll
-            for (int j = 0; j < NC; ++j) {
-                if (j < N) {
-                    const int rk = rankof[sym * NC + j];
-                    out[rk] = g[j];
-                    if (mir) mir[rk] = {g[j].x, -g[j].y};
-                }
-            }
-        }
+        store_rows<R, NC, ML>(active ? left + (size_t)tg.out * M * N : nullptr,
+                              active && tg.mirror >= 0 ? left + (size_t)tg.mirror * M * N : nullptr, M, N,
+                              colof + sym * NC, g, stage, sym, row);
     }
-    if (right && wave == 1 && active && row < N) {
-        cplx<R>* out = right + (size_t)tg.out * N * N + (size_t)row * N;
-        cplx<R>* mir = tg.mirror >= 0 ? right + (size_t)tg.mirror * N * N + (size_t)row * N : nullptr;
-#pragma unroll
-        for (int j = 0; j < NC; ++j) {
-            if (j < N) {
-                const int rk = rankof[sym * NC + j];
-                out[rk] = g[j];
-                if (mir) mir[rk] = {g[j].x, -g[j].y};
-            }
-        }
+    // the two waves stage through the same LDS: U first, then V
+    wsync(solo);
+    if (right && wave == 1) {
+        store_rows<R, NC, ML>(active ? right + (size_t)tg.out * N * N : nullptr,
+                              active && tg.mirror >= 0 ? right + (size_t)tg.mirror * N * N : nullptr, N, N,
+                              colof + sym * NC, g, stage, sym, row);
     }
     // the LDS of this group is reused by the next one
     wsync(solo);

@@ -41,7 +41,9 @@ hipError_t allow_wave_lds(K kernel, size_t lds) {
 
 template <typename R, int NC, int ML>
 hipError_t launch_wave_t(const SvdArgs<R>& a, int grid, hipStream_t st) {
-    const size_t lds = wave_lds_bytes<R, NC, ML>();
+    // output staging after the other arrays when singular vectors are written
+    const size_t base = (wave_lds_bytes<R, NC, ML>() + 63) & ~size_t(63);
+    const size_t lds = (a.U || a.V) ? base + wave_stage_bytes<R, NC, ML>() : base;
     if constexpr (sizeof(R) == 4) {
         hipError_t e = allow_wave_lds(wave_svd_kernel_f32<NC, ML>, lds);
         if (e != hipSuccess) return e;
