@@ -50,7 +50,7 @@ PEAK_HBM_GBS = 8000.0
 # profiles/wave_svd_kernel_single_layer_64x64_uv.md (FETCH_SIZE x 2.00 +
 # WRITE_SIZE x 1.00, calibrated with a copy of known size), valid only for the
 # kernel source they were taken on.
-HEAD_TRAFFIC = {"bytes": 2.40e6 + 269.6e6, "source_hash": "bc5ea00cf2660d2e",
+HEAD_TRAFFIC = {"bytes": 30.81e6 + 320.0e6, "source_hash": "079ae0689be1c655",
                 "files": ("jacobi_device.hpp", "jacobi_wave.hip", "lfa_internal.hpp")}
 
 
