@@ -204,6 +204,7 @@ def cpu_leg(head, extra):
                 parts = list(ex.map(work, chunks))
             reps += 1
         secs = (time.perf_counter() - t0) / reps
+    note(f"oracle timing: {reps} passes, {secs:.3f} s each")
     S_ref = np.zeros((L.n, L.m, L.r))
     for fr, (s, _, _) in parts:
         S_ref[fr[:, 0], fr[:, 1]] = s
@@ -248,10 +249,16 @@ def cpu_leg(head, extra):
                 errors[name + "_symbol_rel"] = float(np.max(np.abs(got - ref)) / scale)
             else:
                 sampled(name, res)
+            note(f"oracle check of {name} done")
     nsig = L.n * L.m * L.r
     return dict(value=nsig / secs, unit="singular values/s", cores=cores, kind="oracle",
                 sample=f"all {L.n * L.m} symbols of the 64x64 layer, sigma+U+V, complex128 "
                        f"NumPy/LAPACK, {cores} threads, mean of {reps} passes ({secs:.3f} s each)"), errors
+
+
+def note(msg):
+    """Progress line on stderr; stdout carries only the JSON result."""
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
 def main():
@@ -275,6 +282,7 @@ def main():
 
     L, W = workloads.single_layer_64()
     head = run_layer(L, W, dev, True, args.steps, args.warmup)
+    note(f"headline: {head['ms']:.3f} ms per step")
     achieved = head["flops"] / (head["kernel_ms"] * 1e-3) / 1e12
     line = {
         "metric": METRIC,
@@ -312,6 +320,7 @@ def main():
         extra["single_layer_16_fp64"] = r
         wl["single_layer_16_fp64"] = dict(ms=r["ms"], sigma_per_s=r["sigma_per_s"], sweeps=r["info"][1:3],
                                           vectors=True, dtype="f64")
+        note("fp64 single layer done")
     if sel("rect"):
         L3, W3 = workloads.rectangular_256_512()
         for vec in (False, True):
@@ -324,6 +333,7 @@ def main():
         r = run_layer(L3r, W3r, dev, True, reps, 1)
         extra["rank_one_512x256"] = r
         wl["rank_one_512x256_uv"] = dict(ms=r["ms"], sigma_per_s=r["sigma_per_s"], sweeps=r["info"][1:3])
+        note("rectangular layers done")
     if sel("stack"):
         st = bench_stack(dev, reps)
         extra["stack"] = st
@@ -332,6 +342,7 @@ def main():
             "plain_layers_per_s": st["plain_layers_per_s"], "batched_layers_per_s": st["batched_layers_per_s"],
             "plain_ms": st["plain_ms"], "batched_ms": st["batched_ms"],
             "speedup_batched_vs_plain": st["batched_layers_per_s"] / st["plain_layers_per_s"]}
+        note("ResNet-18 stack done")
     if sel("large"):
         L5, W5, _ = workloads.large_grid_7x7()
         for asm in (None, "bf16x2", "bf16x3"):
@@ -339,12 +350,14 @@ def main():
             key = "large_grid_7x7_" + (asm or "fp32")
             extra[key] = r
             wl[key] = dict(ms=r["ms"], sigma_per_s=r["sigma_per_s"], sweeps=r["info"][1:3], vectors=False)
+            note(f"large grid {key} done")
     if sel("assembly"):
         for asm in ("valu", "mfma", "bf16x3"):
             a = bench_assembly(dev, 5, asm)
             extra["assembly_" + asm] = a
             wl["assembly_224x224_7x7_" + asm] = dict(ms=a["ms"], hbm_gbs=a["gbs"],
                                                      frac_of_hbm_peak=a["gbs"] / PEAK_HBM_GBS)
+        note("assembly kernels done")
     if sel("paper"):
         # the paper's own runtime study (Tables II, III): c = 16, 3x3, sigma only
         for n in (1024, 16384):
@@ -356,9 +369,11 @@ def main():
                            paper_cpu_seconds=PAPER_TABLE2_SECONDS[n],
                            paper_hardware="Xeon Gold 6242, 16 cores, NumPy (Table II)",
                            speedup_vs_paper=PAPER_TABLE2_SECONDS[n] / (r["ms"] * 1e-3))
+            note(f"paper scale n={n} done")
     if not args.quick:
         line["workloads"] = wl
     if not args.no_cpu:
+        note("oracle legs (CPU) start")
         cb, errors = cpu_leg(head, extra)
         line["cpu_baseline"] = cb
         line["sigma_error_vs_oracle"] = errors
