@@ -546,6 +546,40 @@ __device__ __forceinline__ void rotate_positions(T (&g)[NC]) {
     g[1] = last;
 }
 
+// Register of round-robin position p, K steps after the registers were last
+// moved: K moves by one would have put the value of register reg_of(p) at p.
+template <int NC, int K>
+__host__ __device__ constexpr int reg_of(int p) {
+    return p == 0 ? 0 : 1 + (p - 1 - K % (NC - 1) + (NC - 1)) % (NC - 1);
+}
+
+// U moves by one at once: the registers permuted along the cycles of the
+// rotation (about NC moves instead of U (NC - 1)).
+template <int NC, int U, typename T>
+__device__ __forceinline__ void rotate_positions_by(T (&g)[NC]) {
+    T old[NC];
+#pragma unroll
+    for (int i = 0; i < NC; ++i) old[i] = g[i];
+#pragma unroll
+    for (int i = 1; i < NC; ++i) g[i] = old[reg_of<NC, U>(i)];
+}
+
+// Steps of the register kernel unrolled together (a divisor of the NC - 1
+// steps of a sweep): the positions of the unrolled steps are compile-time
+// register names, and the registers move once per U steps.
+// FP64 with 64 columns stays at one step: its registers are already full.
+template <typename R, int NC>
+constexpr int wave_unroll() {
+    if (sizeof(R) == 8 && NC == 64) return 1;
+    return (NC - 1) % 3 == 0 ? 3 : ((NC - 1) <= 7 ? NC - 1 : 1);
+}
+
+// f(integral_constant<int, 0>), ..., f(integral_constant<int, U - 1>)
+template <typename F, int... I>
+__device__ __forceinline__ void for_steps(F&& f, std::integer_sequence<int, I...>) {
+    (f(std::integral_constant<int, I>{}), ...);
+}
+
 // ---------------------------------------------------------------------------
 // Blocked one-sided Jacobi for symbols with more than 64 rows.
 //
@@ -1245,8 +1279,8 @@ __device__ void wave_group(const SvdArgs<R>& a, char* lds_raw, int base, int tid
         for (int j = 0; j < NC; ++j) g[j] = {R((row == j && j < N) ? 1 : 0), R(0)};
     }
     // Columns of G and of Q are stored scaled: true column = stored * d_j
-    // (the same d_j for G and Q).  A sweep runs in segments of kWaveRenorm
-    // steps; at the start of a segment both waves fold the scales of the
+    // (the same d_j for G and Q).  A sweep runs in segments of SEGL (about
+    // kWaveRenorm) steps; at the start of a segment both waves fold the scales of the
     // previous segment into their stored columns and the rotations of the
     // segment update the other buffer, so the Q wave (a step behind) never
     // reads a scale the G wave is changing.  Both buffers start at 1.
@@ -1263,10 +1297,15 @@ __device__ void wave_group(const SvdArgs<R>& a, char* lds_raw, int base, int tid
     bool my_conv = false;       // symbol of this lane converged
     int conv_at = 0;            // sweeps used by this lane's symbol
     int buf = 0;                // parameter buffer of the current step
+    // U steps at a time (compile-time register names), segments of whole
+    // blocks of U steps
+    constexpr int U = wave_unroll<R, NC>();
+    constexpr int SEGL = U * ((kWaveRenorm + U - 1) / U);
+    static_assert((NC - 1) % U == 0, "unrolled steps must divide a sweep");
     for (int sw = 0; sw < a.max_sweeps; ++sw) {
         if (tid < SPW) flags[tid] = 0;
         bool rotated = false;
-        for (int seg0 = 0; seg0 < NC - 1; seg0 += kWaveRenorm) {
+        for (int seg0 = 0; seg0 < NC - 1; seg0 += SEGL) {
             // segment start: fold the previous segment's scales (positions
             // of step seg0) into G and Q, start the new scales at 1
             const R* dprev = dsc + cur * (SPW * NC);
@@ -1290,8 +1329,13 @@ __device__ void wave_group(const SvdArgs<R>& a, char* lds_raw, int base, int tid
                 __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
                 __builtin_amdgcn_wave_barrier();
             }
-            const int seg1 = seg0 + kWaveRenorm < NC - 1 ? seg0 + kWaveRenorm : NC - 1;
-            for (int step = seg0; step < seg1; ++step) {
+            const int seg1 = seg0 + SEGL < NC - 1 ? seg0 + SEGL : NC - 1;
+            for (int step0 = seg0; step0 < seg1; step0 += U) {
+              for_steps([&](auto kc) {
+                // step step0 + K of the sweep; position x is in register
+                // reg_of<NC, K>(x)
+                constexpr int K = decltype(kc)::value;
+                const int step = step0 + K;
                 quad<R>* prm_b = prm + buf * (SPW * NP);
                 if (wave == 0) {
                     // 1. partial inner products gamma_p = g_j^H g_k (stored
@@ -1302,7 +1346,8 @@ __device__ void wave_group(const SvdArgs<R>& a, char* lds_raw, int base, int tid
                         R v[2 * NB];
 #pragma unroll
                         for (int b = 0; b < NB; ++b) {
-                            const cplx<R> x = g[gi + b * Q], y = g[NC - 1 - gi - b * Q];
+                            const cplx<R> x = g[reg_of<NC, K>(gi + b * Q)];
+                            const cplx<R> y = g[reg_of<NC, K>(NC - 1 - gi - b * Q)];
                             v[2 * b + 0] = fma(x.x, y.x, x.y * y.y);
                             v[2 * b + 1] = fma(x.x, y.y, -x.y * y.x);
                         }
@@ -1353,12 +1398,14 @@ __device__ void wave_group(const SvdArgs<R>& a, char* lds_raw, int base, int tid
 #pragma unroll
                     for (int p = p0; p < p0 + 8 && p < NP; ++p) {
                         const quad<R> q = prm_b[sym * NP + p];
-                        rot_apply_scaled(g[p], g[NC - 1 - p], q.a, q.b, q.c, q.d);
+                        rot_apply_scaled(g[reg_of<NC, K>(p)], g[reg_of<NC, K>(NC - 1 - p)], q.a, q.b, q.c,
+                                         q.d);
                     }
                     __builtin_amdgcn_sched_barrier(0);
                 }
-                rotate_positions<NC>(g);
                 buf ^= 1;
+              }, std::make_integer_sequence<int, U>{});
+              rotate_positions_by<NC, U>(g);
             }
         }
         ++sweeps;
