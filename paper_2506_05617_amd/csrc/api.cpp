@@ -168,6 +168,10 @@ LayerDesc make_desc(const lfa_layer& l, int tw_n, int tw_m, bool acc, int eb, si
 
 int wave_symbols_per_group(const LayerDesc& d) { return d.kind == 1 ? 64 / d.wave_ml : 1; }
 
+// Register kernel: resident work-groups take groups from a counter when the
+// groups fill the device at most this many times.
+constexpr int kWaveTurnRounds = 4;
+
 size_t slot_bytes(const LayerDesc& d, bool acc, int eb) {
     if (d.storage != kGlobal) return 0;
     const size_t cb = 2 * (size_t)eb;
@@ -360,6 +364,9 @@ int ensure_device(lfa_plan* p) {
     const int eb = elem_bytes(p->dtype);
     const bool wu = p->flags & LFA_WANT_U, wv = p->flags & LFA_WANT_V;
     for (size_t i = 0; i < p->layers.size(); ++i) {
+        LayerDesc& d = p->desc[i];
+        if (d.kind == 1)
+            d.wave_cap = wave_blocks_per_cu(d.wave_nc, d.wave_ml, eb, d.threads, wu || wv) * p->num_cus;
         if (lds_bytes_for(p->desc[i], accumulates(p->desc[i], wu, wv), eb) > lds_dev)
             p->desc[i].storage = kGlobal;
         if (lds_bytes_for(p->desc_sel[i], true, eb) > lds_dev) p->desc_sel[i].storage = kGlobal;
@@ -402,7 +409,17 @@ int run_svd_layer(const lfa_plan* p, const LayerDesc& d, const void* W, const vo
     if (d.kind == 1) {
         if (acc != (d.threads > 64)) return LFA_ERR_INVALID_ARG;   // shape made for other outputs
         const int spg = wave_symbols_per_group(d);
-        const int grid = (count + spg - 1) / spg;
+        const int groups = (count + spg - 1) / spg;
+        int grid = groups;
+        if (d.wave_cap > 0 && groups <= kWaveTurnRounds * d.wave_cap) {
+            // resident work-groups take the groups in turn from a counter at
+            // the start of the region (a few rounds of groups: there the
+            // hardware's dispatch order leaves CUs idle in the last rounds;
+            // with many rounds, one work-group per group measured faster)
+            a.wctr = reinterpret_cast<int32_t*>(region);
+            HIP_TRY(launch_fill_i32(a.wctr, 0, 1, st));
+            grid = std::min(groups, d.wave_cap);
+        }
         if constexpr (sizeof(R) == 4) e = launch_wave_svd_f32(a, grid, st);
         else e = launch_wave_svd_f64(a, grid, st);
         HIP_TRY(e);
@@ -1146,6 +1163,10 @@ int lfa_autotune(lfa_plan* plan, const void* const* W, void* const* sigma, void*
         char* region = static_cast<char*>(ws) + kAlign;
         for (LayerDesc d : cands) {
             d.num_canon = base.num_canon;
+            // resident work-groups of the plan's own register-kernel shape
+            const bool same = d.kind == 1 && base.kind == 1 && d.wave_nc == base.wave_nc &&
+                              d.wave_ml == base.wave_ml && d.threads == base.threads;
+            d.wave_cap = same ? base.wave_cap : 0;
             float ms = 0;
             for (int rep = 0; rep < 2 && status == LFA_OK; ++rep) {
                 if (hipEventRecord(e0, st) != hipSuccess) { status = LFA_ERR_HIP; break; }

@@ -37,6 +37,8 @@ struct LayerDesc {
     int wave_nc;       // wave kernel: padded column count (power of two)
     int wave_ml;       // wave kernel: lanes per symbol (16, 32 or 64)
     long long sym_offset;   // first symbol of this layer in the plan's work list
+    int wave_cap;      // wave kernel: work-groups resident at once on the device
+                       // (0: unknown; one work-group per group of symbols)
 };
 
 // ---- device helpers shared by the Jacobi kernels -------------------------
@@ -276,6 +278,8 @@ struct SvdArgs {
     int theta_count;             // number of symbols to process
     int max_sweeps;
     double tol;
+    int32_t* wctr;               // register kernel: group counter (cleared) of a grid of
+                                 // resident work-groups taking groups in turn, or null
 };
 
 size_t lds_bytes_for(const LayerDesc& d, bool accumulate, int elem_bytes);
@@ -294,6 +298,10 @@ int block_resident(const LayerDesc& d, bool accumulate, int elem_bytes);
 // Launchers (each returns a hipError_t).
 hipError_t launch_wave_svd_f32(const SvdArgs<float>& a, int grid, hipStream_t s);
 hipError_t launch_wave_svd_f64(const SvdArgs<double>& a, int grid, hipStream_t s);
+// Work-groups of the register kernel of shape (nc, ml) with `threads` per
+// work-group that fit on one CU; `vectors`: U or V is written (output
+// staging LDS).  0 on error or for an unsupported shape.
+int wave_blocks_per_cu(int nc, int ml, int elem_bytes, int threads, bool vectors);
 hipError_t launch_svd_f32(const SvdArgs<float>& a, int grid, size_t lds, hipStream_t s);
 hipError_t launch_svd_f64(const SvdArgs<double>& a, int grid, size_t lds, hipStream_t s);
 
