@@ -242,6 +242,23 @@ int lfa_autotune(lfa_plan* plan, const void* const* W, void* const* sigma, void*
 int lfa_plan_launch_shape(const lfa_plan* plan, int32_t layer, int32_t* lanes_per_pair,
                           int32_t* threads, int32_t* symbols_per_group, int32_t* storage);
 
+/* Work-queue launch of a layer's register kernel (symbols of at most 64
+ * rows) on the current device.  When the groups of symbols fill the resident
+ * work-groups more than once (and at most 16 times), lfa_svd runs a grid of
+ * resident work-groups that take groups from a device queue a few sweeps at
+ * a time, saving the state of unfinished groups in the workspace, so that no
+ * group starts late in a partly filled last round; the results are bitwise
+ * those of the one-work-group-per-group launch.
+ *   resident        : work-groups of that launch that fit on the device at
+ *                     once (0: no work-queue launch for this layer)
+ *   sweeps_per_turn : sweeps a group runs per turn for lfa_svd of the
+ *                     layer (0: one work-group per group instead)
+ * The environment variable LFA_WAVE_QUEUE, read by lfa_plan_create, turns
+ * the work queue off ("0") or forces it with k sweeps per turn ("1" .. "8").
+ * Needs a gfx950 device (LFA_ERR_NO_DEVICE otherwise). */
+int lfa_plan_queue_info(lfa_plan* plan, int32_t layer, int32_t* resident,
+                        int32_t* sweeps_per_turn);
+
 /* Static text for a status code; never NULL. */
 const char* lfa_status_string(int status);
 

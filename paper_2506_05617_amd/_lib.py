@@ -64,6 +64,7 @@ SIGNATURES = {
     "lfa_graph_destroy": (I32, [P]),
     "lfa_autotune": (I32, [P, PP, PP, PP, PP, P, SZ, P]),
     "lfa_plan_launch_shape": (I32, [P, I32, I32P, I32P, I32P, I32P]),
+    "lfa_plan_queue_info": (I32, [P, I32, I32P, I32P]),
     "lfa_status_string": (ctypes.c_char_p, [I32]),
     "lfa_last_hip_error": (I32, []),
     "lfa_version": (I32, []),

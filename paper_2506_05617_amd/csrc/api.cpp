@@ -5,6 +5,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <mutex>
@@ -81,6 +82,7 @@ struct lfa_plan {
     std::vector<WorkItem> items;          // persistent work list, LPT order per chunk
     std::vector<int> chunk_first;         // first item of each chunk of layers (+ end)
     double tol = 0;
+    int wq_force = -1;                    // work queue: -1 automatic, 0 off, k > 0 forced
     std::mutex mu;
     int device = -1;
     double* tw_dev = nullptr;
@@ -172,6 +174,57 @@ int wave_symbols_per_group(const LayerDesc& d) { return d.kind == 1 ? 64 / d.wav
 // groups fill the device at most this many times.
 constexpr int kWaveTurnRounds = 4;
 
+// Work-queue launch of the register kernel.  It pays off when the groups of
+// symbols fill the resident work-groups more than once but only a few times:
+// one work-group per group then leaves a last, partly filled round.
+constexpr int kQueueMaxRounds = 4;
+constexpr size_t kQueueMaxBytes = size_t(1) << 30;   // workspace for queue state, per layer
+
+int wave_groups(const LayerDesc& d, int count) {
+    const int spg = wave_symbols_per_group(d);
+    return (count + spg - 1) / spg;
+}
+
+// A group runs at least one sweep per turn, so it is queued again at most
+// kMaxSweeps - 1 times.
+long long wave_queue_entries(int groups, int seg) {
+    return (long long)groups * ((kMaxSweeps + seg - 1) / seg);
+}
+
+size_t wave_queue_state_bytes(const LayerDesc& d, bool acc, int eb) {
+    return (size_t)(acc ? 2 : 1) * 64 * d.wave_nc * 2 * eb;
+}
+
+size_t wave_queue_bytes(const LayerDesc& d, bool acc, int eb, int groups) {
+    return align_up(sizeof(int32_t) * (kWaveQueueCtl + wave_queue_entries(groups, 1))) +
+           align_up(sizeof(int32_t) * kWaveMeta * (size_t)groups) +
+           align_up((size_t)groups * wave_queue_state_bytes(d, acc, eb));
+}
+
+// Groups the workspace reserves queue state for: every symbol of the layer
+// (the largest count of any entry point), or none beyond kQueueMaxBytes.
+int wave_queue_reserved(const LayerDesc& d, bool acc, int eb) {
+    if (d.kind != 1) return 0;
+    const int g = wave_groups(d, d.num_symbols);
+    return wave_queue_bytes(d, acc, eb, g) <= kQueueMaxBytes ? g : 0;
+}
+
+// Sweeps per turn of a group in the work-queue launch (0: no work queue).
+// A turn costs the save and restore of the group's rows and an L2 write-back
+// and invalidation; measured on the 64 x 64 layer on the 64 x 64 grid (2050
+// groups, 1024 or 2048 resident), 5 sweeps per turn was best or within noise
+// of best for sigma only and with vectors (1 sweep per turn was slower than
+// no work queue).
+constexpr int kQueueSweepsPerTurn = 5;
+int wave_queue_seg(const LayerDesc& d, int groups, int force) {
+    if (d.kind != 1 || d.wave_qcap <= 0 || groups > d.wave_qgroups || force == 0) return 0;
+    if (force > 0) return force;
+    if (groups <= d.wave_qcap) return 0;
+    const long long rounds = ((long long)groups + d.wave_qcap - 1) / d.wave_qcap;
+    if (rounds > kQueueMaxRounds) return 0;
+    return kQueueSweepsPerTurn;
+}
+
 size_t slot_bytes(const LayerDesc& d, bool acc, int eb) {
     if (d.storage != kGlobal) return 0;
     const size_t cb = 2 * (size_t)eb;
@@ -222,7 +275,10 @@ size_t workspace_bytes(const lfa_plan& p) {
         LayerDesc dg = d;
         dg.storage = (lds_bytes_for(d, acc, eb) > kLdsSafe) ? kGlobal : d.storage;
         size_t s = (size_t)svd_grid(dg, d.num_symbols) * slot_bytes(dg, acc, eb);
-        if (asm_materialized(p.flags)) s += symbols_bytes(p.layers[i], eb);
+        const size_t sym = asm_materialized(p.flags) ? symbols_bytes(p.layers[i], eb) : 0;
+        s += sym;
+        // register kernel: work-queue control, entries, meta and saved state
+        if (d.wave_qgroups > 0) s = std::max(s, sym + wave_queue_bytes(d, acc, eb, d.wave_qgroups));
         need = std::max(need, s);
         // lfa_sigma_grad: compact outputs of <= kMaxTopk symbols + slots
         const LayerDesc& ds = p.desc_sel[i];
@@ -365,8 +421,12 @@ int ensure_device(lfa_plan* p) {
     const bool wu = p->flags & LFA_WANT_U, wv = p->flags & LFA_WANT_V;
     for (size_t i = 0; i < p->layers.size(); ++i) {
         LayerDesc& d = p->desc[i];
-        if (d.kind == 1)
+        if (d.kind == 1) {
             d.wave_cap = wave_blocks_per_cu(d.wave_nc, d.wave_ml, eb, d.threads, wu || wv) * p->num_cus;
+            if (d.wave_qgroups > 0)
+                d.wave_qcap =
+                    wave_queue_blocks_per_cu(d.wave_nc, d.wave_ml, eb, d.threads, wu || wv) * p->num_cus;
+        }
         if (lds_bytes_for(p->desc[i], accumulates(p->desc[i], wu, wv), eb) > lds_dev)
             p->desc[i].storage = kGlobal;
         if (lds_bytes_for(p->desc_sel[i], true, eb) > lds_dev) p->desc_sel[i].storage = kGlobal;
@@ -386,7 +446,7 @@ template <typename R>
 int run_svd_layer(const lfa_plan* p, const LayerDesc& d, const void* W, const void* A,
                   void* sigma, void* U, void* V, int32_t* info, char* region,
                   const int32_t* theta_list, int theta_stride, int theta_count,
-                  hipStream_t st, bool canon = false) {
+                  hipStream_t st, bool canon = false, bool queue_ok = true) {
     SvdArgs<R> a{};
     a.d = d;
     a.canon = theta_list ? 0 : (canon ? 1 : 0);
@@ -408,8 +468,26 @@ int run_svd_layer(const lfa_plan* p, const LayerDesc& d, const void* W, const vo
     hipError_t e;
     if (d.kind == 1) {
         if (acc != (d.threads > 64)) return LFA_ERR_INVALID_ARG;   // shape made for other outputs
-        const int spg = wave_symbols_per_group(d);
-        const int groups = (count + spg - 1) / spg;
+        const int groups = wave_groups(d, count);
+        const int seg = queue_ok ? wave_queue_seg(d, groups, p->wq_force) : 0;
+        if (seg > 0) {
+            // work queue in the region: control words and entries, meta, state
+            const long long ents = wave_queue_entries(groups, seg);
+            char* q = region;
+            a.wq = reinterpret_cast<int32_t*>(q);
+            q += align_up(sizeof(int32_t) * (kWaveQueueCtl + wave_queue_entries(d.wave_qgroups, 1)));
+            a.wq_meta = reinterpret_cast<int32_t*>(q);
+            q += align_up(sizeof(int32_t) * kWaveMeta * (size_t)d.wave_qgroups);
+            a.wq_state = q;
+            a.wq_cap = (int)ents;
+            a.wq_seg = seg;
+            HIP_TRY(launch_fill_i32(a.wq, 0, kWaveQueueCtl + ents, st));
+            const int grid = std::min(groups, d.wave_qcap);
+            if constexpr (sizeof(R) == 4) e = launch_wave_queue_f32(a, grid, st);
+            else e = launch_wave_queue_f64(a, grid, st);
+            HIP_TRY(e);
+            return LFA_OK;
+        }
         int grid = groups;
         if (d.wave_cap > 0 && groups <= kWaveTurnRounds * d.wave_cap) {
             // resident work-groups take the groups in turn from a counter at
@@ -843,6 +921,13 @@ int lfa_plan_create(lfa_plan** out, const lfa_layer* layers, int32_t num_layers,
     const int eb = elem_bytes(dtype);
     // unit roundoff of the working precision (see jacobi_tol)
     p->tol = dtype == LFA_F64 ? std::ldexp(1.0, -53) : std::ldexp(1.0, -24);
+    // LFA_WAVE_QUEUE: "0" turns the work-queue launch off, k in 1..8 forces it
+    // with k sweeps per turn (tests, tuning); unset or other values: automatic
+    if (const char* env = std::getenv("LFA_WAVE_QUEUE")) {
+        const int v = std::atoi(env);
+        if (std::strcmp(env, "0") == 0) p->wq_force = 0;
+        else if (v >= 1 && v <= 8) p->wq_force = v;
+    }
 
     // twiddles exp(2 pi i j / L) for every distinct grid length L
     std::map<int, int> off;
@@ -890,6 +975,7 @@ int lfa_plan_create(lfa_plan** out, const lfa_layer* layers, int32_t num_layers,
             p->desc_gsel.push_back(dg);
         }
         p->desc.back().num_canon = ncanon;
+        p->desc.back().wave_qgroups = wave_queue_reserved(p->desc.back(), accumulates(p->desc.back(), wu, wv), eb);
         p->desc_sel.back().num_canon = ncanon;
         dp.num_canon = ncanon;
         p->desc_pers.push_back(dp);
@@ -941,6 +1027,15 @@ int lfa_plan_launch_shape(const lfa_plan* plan, int32_t layer, int32_t* lanes_pe
     if (threads) *threads = d.threads;
     if (symbols_per_group) *symbols_per_group = wave_symbols_per_group(d);
     if (storage) *storage = d.storage;
+    return LFA_OK;
+}
+
+int lfa_plan_queue_info(lfa_plan* plan, int32_t layer, int32_t* resident, int32_t* sweeps_per_turn) {
+    if (!plan || layer < 0 || layer >= (int32_t)plan->layers.size()) return LFA_ERR_INVALID_ARG;
+    LFA_TRY(ensure_device(plan));
+    const LayerDesc& d = plan->desc[layer];
+    if (resident) *resident = d.kind == 1 && d.wave_qgroups > 0 ? d.wave_qcap : 0;
+    if (sweeps_per_turn) *sweeps_per_turn = wave_queue_seg(d, wave_groups(d, d.num_canon), plan->wq_force);
     return LFA_OK;
 }
 
@@ -1163,10 +1258,13 @@ int lfa_autotune(lfa_plan* plan, const void* const* W, void* const* sigma, void*
         char* region = static_cast<char*>(ws) + kAlign;
         for (LayerDesc d : cands) {
             d.num_canon = base.num_canon;
-            // resident work-groups of the plan's own register-kernel shape
+            // resident work-groups (and the work queue) of the plan's own
+            // register-kernel shape
             const bool same = d.kind == 1 && base.kind == 1 && d.wave_nc == base.wave_nc &&
                               d.wave_ml == base.wave_ml && d.threads == base.threads;
             d.wave_cap = same ? base.wave_cap : 0;
+            d.wave_qcap = same ? base.wave_qcap : 0;
+            d.wave_qgroups = same ? base.wave_qgroups : 0;
             float ms = 0;
             for (int rep = 0; rep < 2 && status == LFA_OK; ++rep) {
                 if (hipEventRecord(e0, st) != hipSuccess) { status = LFA_ERR_HIP; break; }

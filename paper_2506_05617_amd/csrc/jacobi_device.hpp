@@ -1191,11 +1191,31 @@ __device__ void store_rows(cplx<R>* out, cplx<R>* mir, int rows, int N, const in
     }
 }
 
+// A resumable run of a wave group (work-queue launch): the group's saved
+// state is its G and Q rows after a whole number of sweeps, with the column
+// scales folded in, plus the sweep count and per-symbol convergence sweep.
+//   state : [waves][NC/2][64 lanes] column pairs (quad = two complex values),
+//           so one load or store instruction moves 64 consecutive pairs
+//   meta  : [0] sweeps done, [1 + s] sweep at which symbol s converged (0: not)
+//   first : no saved state yet (assemble G, Q = I)
+//   budget: sweeps to run before the state is saved again
+template <typename R>
+struct WaveSeg {
+    quad<R>* state;
+    int* meta;
+    int first;
+    int budget;
+};
+
 // One group of SPW symbols (items base .. base+SPW-1) by `nthr` threads with
-// index `tid`: 64 (G only) or 128 (G wave + Q wave, not solo).
-template <typename R, int NC, int ML>
-__device__ void wave_group(const SvdArgs<R>& a, char* lds_raw, int base, int tid, int nthr,
-                           bool solo) {
+// index `tid`: 64 (G only) or 128 (G wave + Q wave, not solo).  With SEG the
+// group runs at most seg.budget sweeps from its saved state; it returns true
+// when the group is finished (outputs written), false when its state was
+// saved for a later run.  The arithmetic is the same as one uninterrupted
+// run: results are bitwise identical.
+template <typename R, int NC, int ML, bool SEG = false>
+__device__ bool wave_group(const SvdArgs<R>& a, char* lds_raw, int base, int tid, int nthr,
+                           bool solo, const WaveSeg<R>& seg = WaveSeg<R>{nullptr, nullptr, 1, 0}) {
     using S = WaveShape<NC, ML>;
     constexpr int SPW = S::SPW, NP = S::NP, NB = S::NB, Q = S::Q, GL = S::GL, PST = S::PST;
     constexpr int NCH = S::NCH;
@@ -1232,7 +1252,20 @@ __device__ void wave_group(const SvdArgs<R>& a, char* lds_raw, int base, int tid
     // c_out < c_in.  Every G lane then loads its row with constant offsets.
     cplx<R>* tile = reinterpret_cast<cplx<R>*>(part);        // [SPW][ML][NCH]
     cplx<R>* ph = reinterpret_cast<cplx<R>*>(part + SPW * ML * PST);   // [SPW][T]
-    if (a.A == nullptr) {
+    cplx<R> g[NC];
+    const bool fresh = !SEG || seg.first;
+    if (!fresh) {
+        // saved rows of this wave (written by another work-group, made
+        // visible by the queue's release/acquire)
+        const quad<R>* src = seg.state + (size_t)wave * (NC / 2) * 64 + lane;
+#pragma unroll
+        for (int jp = 0; jp < NC / 2; ++jp) {
+            const quad<R> v = src[jp * 64];
+            g[2 * jp] = {v.a, v.b};
+            g[2 * jp + 1] = {v.c, v.d};
+        }
+    }
+    if (fresh && a.A == nullptr) {
         for (int x = tid; x < SPW * T; x += nthr) {
             const int s = x / T, t = x - (x / T) * T;
             const int it = base + s;
@@ -1242,9 +1275,8 @@ __device__ void wave_group(const SvdArgs<R>& a, char* lds_raw, int base, int tid
         }
         wsync(solo);
     }
-    cplx<R> g[NC];
 #pragma unroll
-    for (int c0 = 0; c0 < NC; c0 += NCH) {
+    for (int c0 = 0; c0 < (fresh ? NC : 0); c0 += NCH) {
         for (int x = tid; x < SPW * ML * NCH; x += nthr) {
             const int s = x / (ML * NCH), rc = x - s * (ML * NCH);
             const int r = rc / NCH, c = c0 + (rc - (rc / NCH) * NCH);
@@ -1273,7 +1305,7 @@ __device__ void wave_group(const SvdArgs<R>& a, char* lds_raw, int base, int tid
         for (int jj = 0; jj < NCH; ++jj) g[c0 + jj] = tile[(sym * ML + row) * NCH + jj];
         wsync(solo);
     }
-    if (wave == 1) {
+    if (fresh && wave == 1) {
         // accumulator rows: Q = I (N x N), zero beyond N
 #pragma unroll
         for (int j = 0; j < NC; ++j) g[j] = {R((row == j && j < N) ? 1 : 0), R(0)};
@@ -1293,16 +1325,22 @@ __device__ void wave_group(const SvdArgs<R>& a, char* lds_raw, int base, int tid
     int cur = 0;                // scale buffer of the current segment
 
     // -------------------------------------------------------------- sweeps
-    int sweeps = 0;
-    bool my_conv = false;       // symbol of this lane converged
-    int conv_at = 0;            // sweeps used by this lane's symbol
+    // (uniform over the work-group: the loop bounds below stay scalar)
+    int sweeps = fresh ? 0
+                       : __builtin_amdgcn_readfirstlane(
+                             __hip_atomic_load(&seg.meta[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+    // sweeps used by this lane's symbol
+    int conv_at = fresh ? 0 : __hip_atomic_load(&seg.meta[1 + sym], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    bool my_conv = conv_at > 0;                    // symbol of this lane converged
     int buf = 0;                // parameter buffer of the current step
     // U steps at a time (compile-time register names), segments of whole
     // blocks of U steps
     constexpr int U = wave_unroll<R, NC>();
     constexpr int SEGL = U * ((kWaveRenorm + U - 1) / U);
     static_assert((NC - 1) % U == 0, "unrolled steps must divide a sweep");
-    for (int sw = 0; sw < a.max_sweeps; ++sw) {
+    const int sw_end = SEG ? min(a.max_sweeps, sweeps + seg.budget) : a.max_sweeps;
+    bool all = false;
+    for (int sw = sweeps; sw < sw_end; ++sw) {
         if (tid < SPW) flags[tid] = 0;
         bool rotated = false;
         for (int seg0 = 0; seg0 < NC - 1; seg0 += SEGL) {
@@ -1417,11 +1455,32 @@ __device__ void wave_group(const SvdArgs<R>& a, char* lds_raw, int base, int tid
             my_conv = true;
             conv_at = sweeps;
         }
-        bool all = true;
+        all = true;
 #pragma unroll
         for (int s = 0; s < SPW; ++s) all = all && (flags[s] == 0);
         wsync(solo);
         if (all) break;
+    }
+    if (SEG && !all && sweeps < a.max_sweeps) {
+        // ------------------------------------------------------------ save
+        // fold the last segment's scales (as the finish does) and save the
+        // rows; the next run starts from scales 1, so the values it sees are
+        // those an uninterrupted run would see
+        quad<R>* dst = seg.state + (size_t)wave * (NC / 2) * 64 + lane;
+#pragma unroll
+        for (int jp = 0; jp < NC / 2; ++jp) {
+            const R f0 = dsc[cur * (SPW * NC) + sym * NC + 2 * jp];
+            const R f1 = dsc[cur * (SPW * NC) + sym * NC + 2 * jp + 1];
+            dst[jp * 64] = quad<R>{g[2 * jp].x * f0, g[2 * jp].y * f0,
+                                   g[2 * jp + 1].x * f1, g[2 * jp + 1].y * f1};
+        }
+        if (wave == 0 && row == 0) seg.meta[1 + sym] = my_conv ? conv_at : 0;
+        if (wave == 0 && lane == 0) seg.meta[0] = sweeps;
+        // this wave's stores complete and visible to the device before the
+        // group is queued again
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        wsync(solo);
+        return false;
     }
     if (!my_conv) conv_at = sweeps;
 
@@ -1555,6 +1614,7 @@ __device__ void wave_group(const SvdArgs<R>& a, char* lds_raw, int base, int tid
     }
     // the LDS of this group is reused by the next one
     wsync(solo);
+    return true;
 }
 
 

@@ -39,6 +39,9 @@ struct LayerDesc {
     long long sym_offset;   // first symbol of this layer in the plan's work list
     int wave_cap;      // wave kernel: work-groups resident at once on the device
                        // (0: unknown; one work-group per group of symbols)
+    int wave_qcap;     // wave kernel: the same for its work-queue launch
+                       // (0: work-queue launch not available)
+    int wave_qgroups;  // wave kernel: groups the workspace holds queue state for
 };
 
 // ---- device helpers shared by the Jacobi kernels -------------------------
@@ -280,7 +283,20 @@ struct SvdArgs {
     double tol;
     int32_t* wctr;               // register kernel: group counter (cleared) of a grid of
                                  // resident work-groups taking groups in turn, or null
+    // work-queue launch of the register kernel (wq null: one work-group per
+    // group of symbols, run to the end)
+    int32_t* wq;                 // [kWaveQueueCtl] control words, then [wq_cap] entries
+    void* wq_state;              // [groups] saved rows (see WaveSeg)
+    int32_t* wq_meta;            // [groups][kWaveMeta]
+    int wq_cap;                  // queue entries
+    int wq_seg;                  // sweeps per run of a group
 };
+
+// Work queue of the register kernel: control words head (next entry to
+// take), tail (next entry to fill), done (finished groups), err; the entries
+// follow, 0 while empty, group + 1 once filled.
+constexpr int kWaveQueueCtl = 64;
+constexpr int kWaveMeta = 8;    // meta ints per group of the work queue (1 + SPW <= 5 used)
 
 size_t lds_bytes_for(const LayerDesc& d, bool accumulate, int elem_bytes);
 
@@ -302,6 +318,12 @@ hipError_t launch_wave_svd_f64(const SvdArgs<double>& a, int grid, hipStream_t s
 // work-group that fit on one CU; `vectors`: U or V is written (output
 // staging LDS).  0 on error or for an unsupported shape.
 int wave_blocks_per_cu(int nc, int ml, int elem_bytes, int threads, bool vectors);
+// Work-queue launch of the register kernel (a.wq set, control words and
+// entries cleared): `grid` work-groups, all resident at once.
+hipError_t launch_wave_queue_f32(const SvdArgs<float>& a, int grid, hipStream_t s);
+hipError_t launch_wave_queue_f64(const SvdArgs<double>& a, int grid, hipStream_t s);
+// The same for the work-queue launch.
+int wave_queue_blocks_per_cu(int nc, int ml, int elem_bytes, int threads, bool vectors);
 hipError_t launch_svd_f32(const SvdArgs<float>& a, int grid, size_t lds, hipStream_t s);
 hipError_t launch_svd_f64(const SvdArgs<double>& a, int grid, size_t lds, hipStream_t s);
 

@@ -26,7 +26,10 @@ __device__ void run_bundle(const SvdArgs<R>& a, char* lds, int base, int wave_sl
     if (b >= item_count(a)) return;
     const int NC = a.d.wave_nc, ML = a.d.wave_ml;
 #define LFA_CASE(nc, ml) \
-    if (NC == nc && ML == ml) return wave_group<R, nc, ml>(a, my, b, lane, 64, true);
+    if (NC == nc && ML == ml) {                                      \
+        (void)wave_group<R, nc, ml>(a, my, b, lane, 64, true);          \
+        return;                                                         \
+    }
     LFA_CASE(4, 16) LFA_CASE(8, 16) LFA_CASE(16, 16)
     LFA_CASE(4, 32) LFA_CASE(8, 32) LFA_CASE(16, 32) LFA_CASE(32, 32)
     LFA_CASE(4, 64) LFA_CASE(8, 64) LFA_CASE(16, 64) LFA_CASE(32, 64) LFA_CASE(64, 64)

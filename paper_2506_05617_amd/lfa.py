@@ -92,6 +92,14 @@ class Plan:
             self._ws = torch.empty(max(self.ws_bytes, 256), dtype=torch.uint8, device=device)
         return self._ws
 
+    def queue_info(self, layer):
+        """(resident work-groups, sweeps per turn) of the layer's work-queue
+        launch on the current device; (0, ...) when it has none."""
+        vals = [ctypes.c_int32() for _ in range(2)]
+        check(self.lib.lfa_plan_queue_info(self.handle, layer, *[ctypes.byref(v) for v in vals]),
+              "lfa_plan_queue_info")
+        return tuple(v.value for v in vals)
+
     def launch_shape(self, layer):
         vals = [ctypes.c_int32() for _ in range(4)]
         check(self.lib.lfa_plan_launch_shape(self.handle, layer, *[ctypes.byref(v) for v in vals]),

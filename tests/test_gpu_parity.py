@@ -207,6 +207,86 @@ def test_register_kernel_vectors_repeated(dt):
         check_vectors(A, to_np(S), to_np(U), to_np(V), tdt, f"seed {seed}")
 
 
+# ------------------------------------------------------------ work queue --
+
+def _plan_svd(W, n, m, vectors, queue):
+    """SVD of one layer by a fresh plan created with LFA_WAVE_QUEUE = queue
+    (None: automatic)."""
+    import os
+    c_out, c_in, kh, kw = W.shape
+    old = os.environ.pop("LFA_WAVE_QUEUE", None)
+    try:
+        if queue is not None:
+            os.environ["LFA_WAVE_QUEUE"] = str(queue)
+        plan = lfa().Plan([lfa().LayerSpec(c_out, c_in, kh, kw, n, m)],
+                          torch.float32 if W.dtype == np.float32 else torch.float64, vectors, vectors)
+    finally:
+        os.environ.pop("LFA_WAVE_QUEUE", None)
+        if old is not None:
+            os.environ["LFA_WAVE_QUEUE"] = old
+    S, U, V, info = plan.svd([_w(W)])
+    torch.cuda.synchronize()
+    return plan, S[0], (U[0] if vectors else None), (V[0] if vectors else None), to_np(info[0])
+
+
+QUEUE_CASES = [
+    # c_out, c_in, n, m, dtype, vectors, LFA_WAVE_QUEUE of the queued run
+    (16, 16, 24, 20, np.float32, True, 1),    # four symbols per wave
+    (16, 16, 24, 20, np.float64, True, 2),
+    (40, 24, 10, 9, np.float32, True, 3),     # 64 rows, 32 padded columns
+    (24, 40, 9, 10, np.float64, False, 1),    # c_out < c_in, sigma only
+    (5, 3, 6, 5, np.float32, True, 1),        # smallest shape (4 columns)
+    (64, 64, 7, 6, np.float32, False, 2),
+]
+
+
+@pytest.mark.parametrize("case", QUEUE_CASES)
+def test_work_queue_is_bitwise_the_plain_launch(case):
+    """The work-queue launch (groups run a few sweeps per turn, their state
+    saved and restored in between) performs the same arithmetic as one
+    uninterrupted run: sigma, U, V and the sweep counts are bitwise equal."""
+    c_out, c_in, n, m, dt, vectors, k = case
+    banner(f"work queue {case}")
+    _, W = workloads.random_layer(c_out, c_in, 3, 3, n, m, seed=21, dtype=dt)
+    pq, Sq, Uq, Vq, iq = _plan_svd(W, n, m, vectors, k)
+    assert pq.queue_info(0)[1] == k
+    pp, Sp, Up, Vp, ip = _plan_svd(W, n, m, vectors, 0)
+    assert pp.queue_info(0)[1] == 0
+    assert np.array_equal(iq, ip), (iq, ip)
+    assert torch.equal(Sq, Sp)
+    if vectors:
+        assert torch.equal(Uq, Up) and torch.equal(Vq, Vp)
+    S_ref = oracle.lfa_svd(W.astype(np.float64), n, m)
+    tdt = torch.float32 if dt == np.float32 else torch.float64
+    assert oracle.sigma_error(to_np(Sq), S_ref) <= sigma_gate(tdt)
+
+
+@pytest.mark.parametrize("vectors", [True, False])
+def test_work_queue_headline_shape(vectors):
+    """64 -> 64 channels on the 64 x 64 grid: 2050 groups, more than the
+    device holds at once, so the automatic choice is the work queue.  Bitwise
+    equal to the plain launch, every symbol checked against the oracle, and
+    repeated (the queue state is rebuilt by every call)."""
+    banner(f"work queue headline vectors={vectors}")
+    L, W = workloads.single_layer_64()
+    pq, Sq, Uq, Vq, iq = _plan_svd(W, 64, 64, vectors, None)
+    resident, seg = pq.queue_info(0)
+    assert 0 < resident < 2050 and seg >= 1, (resident, seg)
+    _, Sp, Up, Vp, ip = _plan_svd(W, 64, 64, vectors, 0)
+    assert np.array_equal(iq, ip) and iq[0] == 0 and iq[3] == 0, (iq, ip)
+    assert torch.equal(Sq, Sp)
+    if vectors:
+        assert torch.equal(Uq, Up) and torch.equal(Vq, Vp)
+    for _ in range(2):
+        S2, U2, V2, i2 = pq.svd([_w(W)])
+        torch.cuda.synchronize()
+        assert torch.equal(S2[0], Sq) and np.array_equal(to_np(i2[0]), iq)
+        if vectors:
+            assert torch.equal(U2[0], Uq) and torch.equal(V2[0], Vq)
+    S_ref = oracle.lfa_svd(W.astype(np.float64), 64, 64)
+    assert oracle.sigma_error(to_np(Sq), S_ref) <= sigma_gate(torch.float32)
+
+
 # ------------------------------------------------------ paper-scale grid --
 
 def test_paper_scale_n16384_sampled():
