@@ -47,11 +47,11 @@ PEAK_FP32_VECTOR_TFLOPS = 157.3     # MI355X, packed FP32 (this build issues unp
 PEAK_HBM_GBS = 8000.0
 
 # HBM bytes per launch of the headline kernel from the PMC passes recorded in
-# profiles/wave_svd_kernel_single_layer_64x64_uv.md (FETCH_SIZE x 2.00 +
+# profiles/wave_queue_kernel_single_layer_64x64_uv.md (FETCH_SIZE x 2.00 +
 # WRITE_SIZE x 1.00, calibrated with a copy of known size), valid only for the
 # kernel source they were taken on.
-HEAD_TRAFFIC = {"bytes": 30.81e6 + 320.0e6, "source_hash": "079ae0689be1c655",
-                "files": ("jacobi_device.hpp", "jacobi_wave.hip", "lfa_internal.hpp")}
+HEAD_TRAFFIC = {"bytes": 152.53e6 + 432.40e6, "source_hash": "c84ad4eeda16bb81",
+                "files": ("jacobi_device.hpp", "jacobi_wave.hip", "lfa_internal.hpp", "api.cpp")}
 
 
 # The paper's LFA wall-clock times for c = 16 (sigma only; Xeon Gold 6242,
@@ -301,7 +301,7 @@ def main():
                                "4096 symbols 64x64, sigma+U+V",
                    "c_in": 64, "c_out": 64, "kernel": 3, "n": 64, "symbols": 4096},
         "sweeps": {"sum": head["info"][2], "max": head["info"][1], "nonconverged": head["info"][0]},
-        "roofline": {"bound": "alu", "kernel": "wave_svd_kernel<float,64,64> (fused assembly + Jacobi + sort/write)",
+        "roofline": {"bound": "alu", "kernel": "wave_queue_kernel_f32<64,64> (work queue of groups, 5 sweeps per turn; fused assembly + Jacobi + sort/write)",
                      "achieved": achieved, "peak": PEAK_FP32_VECTOR_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP32_VECTOR_TFLOPS,
                      "traffic": (HEAD_TRAFFIC["bytes"]
