@@ -564,6 +564,16 @@ __device__ __forceinline__ void rotate_positions_by(T (&g)[NC]) {
     for (int i = 1; i < NC; ++i) g[i] = old[reg_of<NC, U>(i)];
 }
 
+// Cyclic shift of B registers by U: new[k] = old[(k + U) mod B].
+template <int B, int U, typename T>
+__device__ __forceinline__ void shift_positions_by(T (&g)[B]) {
+    T old[B];
+#pragma unroll
+    for (int i = 0; i < B; ++i) old[i] = g[i];
+#pragma unroll
+    for (int i = 0; i < B; ++i) g[i] = old[(i + U) % B];
+}
+
 // Steps of the register kernel unrolled together (a divisor of the NC - 1
 // steps of a sweep): the positions of the unrolled steps are compile-time
 // register names, and the registers move once per U steps.
@@ -782,6 +792,13 @@ __device__ void block_sweeps(const LayerDesc& d, const Shared<R>& s, const Block
                              int max_sweeps, double tol, Team& team, int& sweeps_out,
                              bool& conv_out) {
     constexpr int B = kBlk;
+    // steps unrolled together in the intra passes (B - 1 steps) and the
+    // cross passes (B steps); with the accumulator, larger blocks of steps
+    // spill registers (measured: 3 and 4 made the 512 x 256 layer with
+    // vectors 1.7x slower, 1 and 2 made it 3 % faster); FP64 keeps one step
+    constexpr bool F64 = sizeof(R) == 8;
+    constexpr int KI = (ACC || F64) ? 1 : 3, KC = F64 ? 1 : (ACC ? 2 : 4);
+    static_assert((B - 1) % KI == 0 && B % KC == 0, "unrolled steps must divide a pass");
     const int tid = threadIdx.x, nt = blockDim.x;
     const int lane = tid & 63, wave = tid >> 6;
     const int member = team.member, W = team.W;
@@ -853,14 +870,21 @@ __device__ void block_sweeps(const LayerDesc& d, const Shared<R>& s, const Block
         for (int i = member; 2 * i < NB; i += W) {
             const int ba = 2 * i, bb = 2 * i + 1;
             load2(ba, bb);
-            for (int step = 0; step < B - 1; ++step) {
+            // KI round-robin steps at a time: position x of step step0 + K is
+            // register reg_of<B, K>(x); the registers move once per KI steps
+            for (int step0 = 0; step0 < B - 1; step0 += KI) {
+              for_steps([&](auto kc) __attribute__((always_inline)) {
+                constexpr int K = decltype(kc)::value;
+                const int step = step0 + K;
                 // pair p < B/2: positions (p, B-1-p) of block a, else of block b
                 block_wave_sums<R>(bl, [&](int p) {
                     quad<R> q = {R(0), R(0), R(0), R(0)};
 #pragma unroll
                     for (int r = 0; r < RPT; ++r) {
-                        const quad<R> x = p < B / 2 ? pair_partials(ga[r][p], ga[r][B - 1 - p])
-                                                    : pair_partials(gb[r][p - B / 2], gb[r][B - 1 - (p - B / 2)]);
+                        const quad<R> x =
+                            p < B / 2 ? pair_partials(ga[r][reg_of<B, K>(p)], ga[r][reg_of<B, K>(B - 1 - p)])
+                                      : pair_partials(gb[r][reg_of<B, K>(p - B / 2)],
+                                                      gb[r][reg_of<B, K>(B - 1 - (p - B / 2))]);
                         q = {q.a + x.a, q.b + x.b, q.c + x.c, q.d + x.d};
                     }
                     return q;
@@ -877,26 +901,28 @@ __device__ void block_sweeps(const LayerDesc& d, const Shared<R>& s, const Block
 #pragma unroll
                 for (int p = 0; p < B / 2; ++p) {
                     const quad<R> ra = prm[p], rb = prm[B / 2 + p];
+                    const int j = reg_of<B, K>(p), k = reg_of<B, K>(B - 1 - p);
 #pragma unroll
                     for (int r = 0; r < RPT; ++r) {
-                        rot_apply_scaled(ga[r][p], ga[r][B - 1 - p], ra.a, ra.b, ra.c, ra.d);
-                        rot_apply_scaled(gb[r][p], gb[r][B - 1 - p], rb.a, rb.b, rb.c, rb.d);
+                        rot_apply_scaled(ga[r][j], ga[r][k], ra.a, ra.b, ra.c, ra.d);
+                        rot_apply_scaled(gb[r][j], gb[r][k], rb.a, rb.b, rb.c, rb.d);
                         if constexpr (ACC) {
-                            rot_apply_scaled(va[r][p], va[r][B - 1 - p], ra.a, ra.b, ra.c, ra.d);
-                            rot_apply_scaled(vb[r][p], vb[r][B - 1 - p], rb.a, rb.b, rb.c, rb.d);
+                            rot_apply_scaled(va[r][j], va[r][k], ra.a, ra.b, ra.c, ra.d);
+                            rot_apply_scaled(vb[r][j], vb[r][k], rb.a, rb.b, rb.c, rb.d);
                         }
                     }
                 }
-                // round-robin: positions 1..B-1 move by one
+              }, std::make_integer_sequence<int, KI>{});
+              // round-robin: positions 1..B-1 move by KI
 #pragma unroll
-                for (int r = 0; r < RPT; ++r) {
-                    rotate_positions<B>(ga[r]);
-                    rotate_positions<B>(gb[r]);
-                    if constexpr (ACC) {
-                        rotate_positions<B>(va[r]);
-                        rotate_positions<B>(vb[r]);
-                    }
-                }
+              for (int r = 0; r < RPT; ++r) {
+                  rotate_positions_by<B, KI>(ga[r]);
+                  rotate_positions_by<B, KI>(gb[r]);
+                  if constexpr (ACC) {
+                      rotate_positions_by<B, KI>(va[r]);
+                      rotate_positions_by<B, KI>(vb[r]);
+                  }
+              }
             }
             // B-1 steps bring every position back: store in place
             store2(ba, bb);
@@ -909,12 +935,18 @@ __device__ void block_sweeps(const LayerDesc& d, const Shared<R>& s, const Block
                 rr_pair(bp, os, NBP, ba, bb);
                 if (ba >= NB || bb >= NB) continue;
                 load2(ba, bb);
-                for (int t = 0; t < B; ++t) {
+                // KC steps at a time: at step t0 + K, column p of block a
+                // meets register (p + K) mod B of block b; block b's
+                // registers shift once per KC steps
+                for (int t0 = 0; t0 < B; t0 += KC) {
+                  for_steps([&](auto kc) __attribute__((always_inline)) {
+                    constexpr int K = decltype(kc)::value;
+                    const int t = t0 + K;
                     block_wave_sums<R>(bl, [&](int p) {
                         quad<R> q = {R(0), R(0), R(0), R(0)};
 #pragma unroll
                         for (int r = 0; r < RPT; ++r) {
-                            const quad<R> x = pair_partials(ga[r][p], gb[r][p]);
+                            const quad<R> x = pair_partials(ga[r][p], gb[r][(p + K) % B]);
                             q = {q.a + x.a, q.b + x.b, q.c + x.c, q.d + x.d};
                         }
                         return q;
@@ -932,24 +964,18 @@ __device__ void block_sweeps(const LayerDesc& d, const Shared<R>& s, const Block
                         const quad<R> rr = prm[p];
 #pragma unroll
                         for (int r = 0; r < RPT; ++r) {
-                            rot_apply_scaled(ga[r][p], gb[r][p], rr.a, rr.b, rr.c, rr.d);
-                            if constexpr (ACC) rot_apply_scaled(va[r][p], vb[r][p], rr.a, rr.b, rr.c, rr.d);
+                            rot_apply_scaled(ga[r][p], gb[r][(p + K) % B], rr.a, rr.b, rr.c, rr.d);
+                            if constexpr (ACC)
+                                rot_apply_scaled(va[r][p], vb[r][(p + K) % B], rr.a, rr.b, rr.c, rr.d);
                         }
                     }
-                    // block b shifts by one against block a
+                  }, std::make_integer_sequence<int, KC>{});
+                  // block b shifts by KC against block a
 #pragma unroll
-                    for (int r = 0; r < RPT; ++r) {
-                        const cplx<R> fb = gb[r][0];
-#pragma unroll
-                        for (int k = 0; k < B - 1; ++k) gb[r][k] = gb[r][k + 1];
-                        gb[r][B - 1] = fb;
-                        if constexpr (ACC) {
-                            const cplx<R> fv = vb[r][0];
-#pragma unroll
-                            for (int k = 0; k < B - 1; ++k) vb[r][k] = vb[r][k + 1];
-                            vb[r][B - 1] = fv;
-                        }
-                    }
+                  for (int r = 0; r < RPT; ++r) {
+                      shift_positions_by<B, KC>(gb[r]);
+                      if constexpr (ACC) shift_positions_by<B, KC>(vb[r]);
+                  }
                 }
                 // B shifts bring block b back to its order
                 store2(ba, bb);
@@ -1369,7 +1395,7 @@ __device__ bool wave_group(const SvdArgs<R>& a, char* lds_raw, int base, int tid
             }
             const int seg1 = seg0 + SEGL < NC - 1 ? seg0 + SEGL : NC - 1;
             for (int step0 = seg0; step0 < seg1; step0 += U) {
-              for_steps([&](auto kc) {
+              for_steps([&](auto kc) __attribute__((always_inline)) {
                 // step step0 + K of the sweep; position x is in register
                 // reg_of<NC, K>(x)
                 constexpr int K = decltype(kc)::value;
