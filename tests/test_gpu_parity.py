@@ -287,6 +287,36 @@ def test_work_queue_headline_shape(vectors):
     assert oracle.sigma_error(to_np(Sq), S_ref) <= sigma_gate(torch.float32)
 
 
+def test_work_queue_caller_symbols():
+    """lfa_svd_symbols (symbols handed in by the caller: every frequency is
+    decomposed, no conjugate pairing) through the forced work queue, bitwise
+    equal to the plain launch and within the sigma gate of the oracle."""
+    import os
+    banner("work queue, caller symbols")
+    n, m = 10, 9
+    _, W = workloads.random_layer(40, 24, 3, 3, n, m, seed=23, dtype=np.float32)
+    A = lfa().symbols(_w(W), n, m)
+    res = []
+    for q in ("2", "0"):
+        old = os.environ.pop("LFA_WAVE_QUEUE", None)
+        os.environ["LFA_WAVE_QUEUE"] = q
+        try:
+            plan = lfa().Plan([lfa().LayerSpec(40, 24, 3, 3, n, m)], torch.float32, True, True)
+        finally:
+            os.environ.pop("LFA_WAVE_QUEUE", None)
+            if old is not None:
+                os.environ["LFA_WAVE_QUEUE"] = old
+        assert plan.queue_info(0)[1] == int(q)
+        S, U, V, info = plan.svd_symbols([A])
+        torch.cuda.synchronize()
+        res.append((S[0], U[0], V[0], to_np(info[0])))
+    (Sq, Uq, Vq, iq), (Sp, Up, Vp, ip) = res
+    assert np.array_equal(iq, ip) and iq[0] == 0 and iq[3] == 0, (iq, ip)
+    assert torch.equal(Sq, Sp) and torch.equal(Uq, Up) and torch.equal(Vq, Vp)
+    S_ref = oracle.svd_symbols(to_np(A).astype(np.complex128), compute_uv=False)
+    assert oracle.sigma_error(to_np(Sq), S_ref) <= sigma_gate(torch.float32)
+
+
 # ------------------------------------------------------ paper-scale grid --
 
 def test_paper_scale_n16384_sampled():
