@@ -29,6 +29,11 @@ complex128, with NumPy/LAPACK as the only library primitives:
   tie order.
 * ``dirichlet_operator`` -- the zero-padded (Dirichlet) operator the paper
   compares against (Sec. III "Boundary Conditions"; Sec. IV).
+* ``apply_spectral``   -- ``y = U f(Sigma) V^* x`` for the identity, a
+  pseudo-inverse or singular-value clipping, through the per-symbol SVD
+  (Sec. III "Convolution Theorem": the global SVD is the lift of the
+  symbols' SVDs); ``apply_spectral_dense`` is the same from the SVD of the
+  unrolled operator.
 
 Parity pins: every function above is pinned by tests in
 ``tests/test_oracle_pins.py`` against brute force, closed forms, invariants,
@@ -46,6 +51,9 @@ from .lfa64 import (  # noqa: F401
     dirichlet_operator,
     fourier_basis,
     lift,
+    spectral_factor,
+    apply_spectral,
+    apply_spectral_dense,
     sigma_grad,
     topk,
     sigma_error,

@@ -194,6 +194,77 @@ def lift(U, V, n: int, m: int, p: int, q: int):
 
 
 # ---------------------------------------------------------------------------
+# Spectral functions of the operator applied through the per-symbol SVD
+# ---------------------------------------------------------------------------
+
+def spectral_factor(sigma, kind: str, param: float = 0.0):
+    """``f(sigma)`` of the spectral functions applied below: ``identity`` (the
+    operator itself), ``clip`` (``min(sigma, param)``: the operator with its
+    singular values clipped at ``param``) and ``pinv`` (``1/sigma`` above the
+    absolute cut-off ``param``, else 0: the pseudo-inverse restricted to the
+    kept singular values)."""
+    s = np.asarray(sigma, dtype=np.float64)
+    if kind == "identity":
+        return s.copy()
+    if kind == "pinv":
+        out = np.zeros_like(s)
+        keep = s > param
+        out[keep] = 1.0 / s[keep]
+        return out
+    if kind == "clip":
+        return np.minimum(s, param)
+    raise ValueError(kind)
+
+
+def apply_spectral(W, x, n: int, m: int | None, kind: str, param: float = 0.0):
+    """A spectral function of the periodic operator ``A = U Sigma V^*``
+    applied to ``x``, evaluated frequency by frequency (Sec. III "Convolution
+    Theorem": the global singular vectors are Fourier modes times the
+    singular vectors of the symbols):
+
+    * ``identity`` and ``clip``: ``y = U f(Sigma) V^* x``, ``x [B, c_in, n, m]``
+      real, ``y [B, c_out, n, m]``;
+    * ``pinv``: ``y = V f(Sigma) U^* x`` (the pseudo-inverse maps back from the
+      output channels), ``x [B, c_out, n, m]``, ``y [B, c_in, n, m]``.
+
+    With ``x_hat_k = sum_x x(x) e^{-2 pi i <k, x>}`` the operator maps
+    ``x_hat_k`` to ``A_k x_hat_k``; here each ``x_hat_k`` goes to
+    ``U_k f(S_k) V_k^* x_hat_k`` (or ``V_k f(S_k) U_k^* x_hat_k``) and ``y`` is
+    the inverse transform (``1/(n m)`` and ``e^{+2 pi i <k, x>}``).  Returns
+    the real part in float64 (the imaginary part vanishes for real W and x).
+    """
+    m = n if m is None else m
+    x = np.asarray(x, dtype=np.float64)
+    xh = np.fft.fft2(x, axes=(-2, -1))
+    S, U, V = svd_symbols(symbols(W, n, m), compute_uv=True)  # [n, m, ...]
+    f = spectral_factor(S, kind, param)                      # [n, m, r]
+    left, right = (V, U) if kind == "pinv" else (U, V)
+    z = np.einsum("pqir,bipq->bpqr", np.conj(right), xh)
+    yh = np.einsum("pqor,pqr,bpqr->bopq", left, f, z)
+    return np.real(np.fft.ifft2(yh, axes=(-2, -1)))
+
+
+def apply_spectral_dense(W, x, n: int, m: int | None, kind: str, param: float = 0.0):
+    """The same spectral function from the SVD of the dense unrolled operator
+    (definition-level brute force, small grids only)."""
+    m = n if m is None else m
+    x = np.asarray(x, dtype=np.float64)
+    B, c = x.shape[:2]
+    A = unrolled_operator(W, n, m)
+    Ud, Sd, Vdh = np.linalg.svd(A)
+    r = Sd.size
+    f = spectral_factor(Sd, kind, param)
+    if kind == "pinv":
+        left, right = Vdh[:r].conj().T, Ud[:, :r]
+    else:
+        left, right = Ud[:, :r], Vdh[:r].conj().T
+    xv = np.transpose(x, (0, 2, 3, 1)).reshape(B, n * m * c)   # (x1 m + x2) c + channel
+    yv = ((xv @ right.conj()) * f) @ left.T
+    c_y = left.shape[0] // (n * m)
+    return np.transpose(yv.reshape(B, n, m, c_y), (0, 3, 1, 2))
+
+
+# ---------------------------------------------------------------------------
 # Top-k and gradient of a sum of singular values
 # ---------------------------------------------------------------------------
 

@@ -387,3 +387,92 @@ def test_dirichlet_spectrum_approaches_periodic():
         sd = np.sort(np.linalg.svd(oracle.dirichlet_operator(W, n), compute_uv=False))
         gaps.append(np.mean(np.abs(sp - sd)) / sp[-1])
     assert gaps[0] > gaps[1] > gaps[2]
+
+
+# --- spectral functions applied through the per-symbol SVD ------------------
+
+APPLY_CASES = [
+    # c_out, c_in, kh, kw, n, m, batch
+    (3, 2, 3, 3, 5, 4, 2),
+    (2, 4, 3, 3, 4, 6, 1),
+    (4, 4, 3, 3, 6, 6, 3),
+    (2, 2, 2, 2, 4, 5, 2),     # even kernel
+]
+
+
+@pytest.mark.parametrize("case", APPLY_CASES)
+def test_apply_identity_is_the_convolution(case):
+    """oracle.apply_spectral with f(sigma) = sigma is the operator itself:
+    torch's conv2d on a circularly padded input (the periodic cross-correlation
+    of Sec. III "Convolutional Mappings"), which shares nothing with the
+    oracle's transforms."""
+    c_out, c_in, kh, kw, n, m, B = case
+    rng = np.random.default_rng(31)
+    W = rng.standard_normal((c_out, c_in, kh, kw))
+    x = rng.standard_normal((B, c_in, n, m))
+    pad = ((kw - 1) // 2, kw // 2, (kh - 1) // 2, kh // 2)
+    xt = torch.nn.functional.pad(torch.from_numpy(x), pad, mode="circular")
+    ref = torch.nn.functional.conv2d(xt, torch.from_numpy(W)).numpy()
+    got = oracle.apply_spectral(W, x, n, m, "identity")
+    assert np.max(np.abs(got - ref)) <= 1e-12 * np.max(np.abs(ref))
+
+
+@pytest.mark.parametrize("case", APPLY_CASES)
+@pytest.mark.parametrize("kind", ["pinv", "clip"])
+def test_apply_spectral_matches_dense_svd(case, kind):
+    """Pseudo-inverse and clipping through the per-symbol SVD equal the same
+    spectral function of the dense operator's SVD (torch's circular operator
+    -> numpy.linalg.svd): A^+ = V f(S) U^T, clipped A = U f(S) V^T.  The
+    cut-off / clip level lies midway in a gap of the singular values near
+    their median (a level on a singular value would make the result depend
+    on rounding)."""
+    c_out, c_in, kh, kw, n, m, B = case
+    rng = np.random.default_rng(32)
+    W = rng.standard_normal((c_out, c_in, kh, kw))
+    A = torch_circular_operator(W, n, m)
+    Ud, Sd, Vdh = np.linalg.svd(A)
+    s = np.sort(Sd)
+    gaps = np.where(np.diff(s) > 1e-3 * s[-1])[0]
+    i = gaps[np.argmin(np.abs(gaps - s.size // 2))]
+    level = 0.5 * (s[i] + s[i + 1])
+    f = oracle.spectral_factor(Sd, kind, level)
+    if kind == "pinv":
+        assert np.all(f[Sd > level] == 1.0 / Sd[Sd > level]) and np.all(f[Sd <= level] == 0)
+    else:
+        assert np.all(f == np.minimum(Sd, level))
+    r = Sd.size
+    if kind == "pinv":
+        x = rng.standard_normal((B, c_out, n, m))
+        op = Vdh[:r].T @ np.diag(f) @ Ud[:, :r].T
+        c_y = c_in
+    else:
+        x = rng.standard_normal((B, c_in, n, m))
+        op = Ud[:, :r] @ np.diag(f) @ Vdh[:r]
+        c_y = c_out
+    xv = np.transpose(x, (0, 2, 3, 1)).reshape(B, -1)
+    ref = np.transpose((xv @ op.T).reshape(B, n, m, c_y), (0, 3, 1, 2))
+    got = oracle.apply_spectral(W, x, n, m, kind, level)
+    assert np.max(np.abs(got - ref)) <= 1e-11 * max(1.0, np.max(np.abs(ref)))
+    dense = oracle.apply_spectral_dense(W, x, n, m, kind, level)
+    assert np.max(np.abs(dense - ref)) <= 1e-11 * max(1.0, np.max(np.abs(ref)))
+    if kind == "pinv":
+        # Moore-Penrose with the truncated spectrum: A A^+ A = A_kept, and
+        # A^+ A A^+ = A^+
+        assert np.allclose(op @ A @ op, op, atol=1e-10 * np.abs(op).max())
+
+
+def test_apply_pinv_inverts_full_rank_and_clip_above_max_is_identity():
+    """For a square operator with every singular value kept, the pseudo-inverse
+    undoes the operator (A^+ A x = x); clipping at or above sigma_max changes
+    nothing."""
+    rng = np.random.default_rng(33)
+    W = rng.standard_normal((3, 3, 3, 3))
+    n, m = 6, 5
+    x = rng.standard_normal((2, 3, n, m))
+    Ax = oracle.apply_spectral(W, x, n, m, "identity")
+    S = oracle.lfa_svd(W, n, m)
+    assert S.min() > 1e-3 * S.max()
+    back = oracle.apply_spectral(W, Ax, n, m, "pinv", 0.0)
+    assert np.max(np.abs(back - x)) <= 1e-12 * np.max(np.abs(x)) * S.max() / S.min()
+    same = oracle.apply_spectral(W, x, n, m, "clip", S.max() * (1 + 1e-12))
+    assert np.max(np.abs(same - Ax)) <= 1e-12 * np.max(np.abs(Ax))
