@@ -229,6 +229,42 @@ int lfa_graph_create(lfa_plan* plan, const void* const* W, void* const* sigma, i
 int lfa_graph_launch(lfa_graph* graph, void* stream);
 int lfa_graph_destroy(lfa_graph* graph);
 
+/* ---- spectral functions of a layer's operator ------------------------- */
+
+/* The global SVD of the periodic operator is the lift of the symbols' SVDs
+ * (Sec. III "Convolution Theorem": its singular vectors are Fourier modes
+ * times the columns of U_k, V_k), so a function of its singular values acts
+ * frequency by frequency:
+ *   x_hat_k = sum_x x(x) e^{-2 pi i <k, x>},  y_hat_k = g_k(x_hat_k),
+ *   y(x) = (1/(n m)) sum_k y_hat_k e^{+2 pi i <k, x>}   (real part). */
+enum lfa_spectral_kind {
+    LFA_SPECTRAL_IDENTITY = 0, /* g_k = U_k S_k V_k^*: the convolution itself     */
+    LFA_SPECTRAL_CLIP = 1,     /* g_k = U_k min(S_k, param) V_k^*: singular values
+                                  clipped at param (a Lipschitz bound)           */
+    LFA_SPECTRAL_PINV = 2      /* g_k = V_k S_k^+ U_k^*: pseudo-inverse, 1/sigma for
+                                  sigma > param (absolute cut-off), 0 otherwise;
+                                  maps c_out channels back to c_in               */
+};
+
+/* Workspace (device bytes) of lfa_apply for `batch` images of layer `layer`:
+ * two complex buffers of batch * n * m * max(c_out, c_in) elements. */
+int lfa_apply_workspace_bytes(const lfa_plan* plan, int32_t layer, int32_t batch, size_t* bytes);
+
+/* Apply a spectral function of layer `layer`'s operator to a batch of
+ * images, using that layer's SVD as lfa_svd writes it (with LFA_WANT_U and
+ * LFA_WANT_V).  All pointers are device memory in the plan's dtype:
+ *   sigma [n][m][r], U [n][m][c_out][r], V [n][m][c_in][r]  (r = min(c_out, c_in))
+ *   x     [batch][c_x][n][m] real,  y [batch][c_y][n][m] real,
+ *         c_x = c_in, c_y = c_out (IDENTITY, CLIP); c_x = c_out, c_y = c_in (PINV)
+ *   kind  an lfa_spectral_kind; param >= 0 (CLIP level, PINV cut-off)
+ *   ws    at least lfa_apply_workspace_bytes(plan, layer, batch)
+ * Stream-ordered; batch == 0 does nothing.  x and y may not overlap.
+ * Errors: LFA_ERR_INVALID_ARG (layer, kind, param, batch < 0, NULL pointer),
+ * LFA_ERR_WORKSPACE, LFA_ERR_HIP. */
+int lfa_apply(const lfa_plan* plan, int32_t layer, const void* sigma, const void* U, const void* V,
+              int32_t kind, double param, const void* x, void* y, int32_t batch, void* ws,
+              size_t ws_bytes, void* stream);
+
 /* ---- tuning and diagnostics ------------------------------------------- */
 
 /* Time the candidate launch shapes of every layer on `stream` (running the

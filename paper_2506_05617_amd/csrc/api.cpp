@@ -1039,6 +1039,55 @@ int lfa_plan_queue_info(lfa_plan* plan, int32_t layer, int32_t* resident, int32_
     return LFA_OK;
 }
 
+int lfa_apply_workspace_bytes(const lfa_plan* plan, int32_t layer, int32_t batch, size_t* bytes) {
+    if (!plan || !bytes || layer < 0 || layer >= (int32_t)plan->layers.size() || batch < 0)
+        return LFA_ERR_INVALID_ARG;
+    const lfa_layer& l = plan->layers[layer];
+    const size_t c = (size_t)std::max(l.c_out, l.c_in);
+    *bytes = 2 * align_up((size_t)batch * l.n * l.m * c * 2 * elem_bytes(plan->dtype));
+    return LFA_OK;
+}
+
+int lfa_apply(const lfa_plan* plan, int32_t layer, const void* sigma, const void* U, const void* V,
+              int32_t kind, double param, const void* x, void* y, int32_t batch, void* ws,
+              size_t ws_bytes, void* stream) {
+    if (!plan || layer < 0 || layer >= (int32_t)plan->layers.size() || batch < 0) return LFA_ERR_INVALID_ARG;
+    if (kind != LFA_SPECTRAL_IDENTITY && kind != LFA_SPECTRAL_CLIP && kind != LFA_SPECTRAL_PINV)
+        return LFA_ERR_INVALID_ARG;
+    if (!(param >= 0.0) || !std::isfinite(param)) return LFA_ERR_INVALID_ARG;
+    if (batch == 0) return LFA_OK;
+    if (!sigma || !U || !V || !x || !y) return LFA_ERR_INVALID_ARG;
+    size_t need = 0;
+    LFA_TRY(lfa_apply_workspace_bytes(plan, layer, batch, &need));
+    if (!ws || ws_bytes < need) return LFA_ERR_WORKSPACE;
+    lfa_plan* p = const_cast<lfa_plan*>(plan);
+    LFA_TRY(ensure_device(p));
+    const lfa_layer& l = p->layers[layer];
+    const bool pinv = kind == LFA_SPECTRAL_PINV;
+    ApplyArgs a{};
+    a.batch = batch;
+    a.n = l.n;
+    a.m = l.m;
+    a.cx = pinv ? l.c_out : l.c_in;
+    a.cy = pinv ? l.c_in : l.c_out;
+    a.r = std::min(l.c_out, l.c_in);
+    a.kind = kind;
+    a.param = param;
+    a.sigma = sigma;
+    a.L = pinv ? V : U;
+    a.R = pinv ? U : V;
+    a.x = x;
+    a.y = y;
+    a.ws1 = ws;
+    a.ws2 = static_cast<char*>(ws) + need / 2;
+    a.tw = p->tw_dev;
+    a.tw_n = p->tw_n[layer];
+    a.tw_m = p->tw_m[layer];
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    HIP_TRY(p->dtype == LFA_F64 ? launch_apply_f64(a, st) : launch_apply_f32(a, st));
+    return LFA_OK;
+}
+
 int lfa_symbols(const lfa_plan* plan, const void* const* W, void* const* A, void* stream) {
     if (!plan) return LFA_ERR_INVALID_ARG;
     LFA_TRY(check_ptrs(plan, W, true));

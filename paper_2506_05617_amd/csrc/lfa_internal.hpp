@@ -298,6 +298,27 @@ struct SvdArgs {
 constexpr int kWaveQueueCtl = 64;
 constexpr int kWaveMeta = 8;    // meta ints per group of the work queue (1 + SPW <= 5 used)
 
+// Spectral function of one layer's operator applied to a batch of images
+// (the kernels in apply.hip).  x [batch][cx][n][m] real, y [batch][cy][n][m]
+// real; L [n*m][cy][r], R [n*m][cx][r] complex (U, V for identity and clip,
+// V, U for pinv); sigma [n*m][r]; ws1, ws2 each batch*n*m*max(cx, cy)
+// complex elements.
+struct ApplyArgs {
+    int batch, n, m, cx, cy, r, kind;
+    double param;
+    const void* sigma;
+    const void* L;
+    const void* R;
+    const void* x;
+    void* y;
+    void* ws1;
+    void* ws2;
+    const double* tw;
+    int tw_n, tw_m;
+};
+hipError_t launch_apply_f32(const ApplyArgs& a, hipStream_t s);
+hipError_t launch_apply_f64(const ApplyArgs& a, hipStream_t s);
+
 size_t lds_bytes_for(const LayerDesc& d, bool accumulate, int elem_bytes);
 
 size_t wave_lds_bytes_for(int nc, int ml, int elem_bytes);

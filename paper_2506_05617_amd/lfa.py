@@ -169,6 +169,37 @@ class Plan:
                 raise ValueError("symbols must be contiguous [n, m, c_out, c_in] complex")
         return self._svd_call(self.lib.lfa_svd_symbols, "lfa_svd_symbols", As, As[0].device, info)
 
+    def apply(self, layer, S, U, V, x, kind="identity", param=0.0):
+        """Spectral function of layer `layer`'s operator applied to images
+        ``x [batch, c_x, n, m]`` through its SVD ``S, U, V`` (as ``svd``
+        returns them for that layer, with U and V): ``identity`` (the
+        convolution), ``clip`` (singular values clipped at ``param``) or
+        ``pinv`` (pseudo-inverse with absolute cut-off ``param``; x has
+        c_out channels and y has c_in).  Returns ``y [batch, c_y, n, m]``."""
+        kinds = {"identity": _lib.LFA_SPECTRAL_IDENTITY, "clip": _lib.LFA_SPECTRAL_CLIP,
+                 "pinv": _lib.LFA_SPECTRAL_PINV}
+        l = self.layers[layer]
+        cx, cy = (l.c_out, l.c_in) if kind == "pinv" else (l.c_in, l.c_out)
+        if x.dtype != self.dtype or x.dim() != 4 or tuple(x.shape[1:]) != (cx, l.n, l.m) or not x.is_contiguous():
+            raise ValueError(f"x must be contiguous [batch, {cx}, {l.n}, {l.m}] {self.dtype}")
+        cdt = _complex_of(self.dtype)
+        r = l.r
+        if tuple(S.shape) != (l.n, l.m, r) or tuple(U.shape) != (l.n, l.m, l.c_out, r) or \
+                tuple(V.shape) != (l.n, l.m, l.c_in, r) or U.dtype != cdt or V.dtype != cdt or S.dtype != self.dtype:
+            raise ValueError("S, U, V must be this layer's SVD")
+        batch = x.shape[0]
+        y = torch.empty(batch, cy, l.n, l.m, dtype=self.dtype, device=x.device)
+        nbytes = ctypes.c_size_t()
+        check(self.lib.lfa_apply_workspace_bytes(self.handle, layer, batch, ctypes.byref(nbytes)),
+              "lfa_apply_workspace_bytes")
+        ws = torch.empty(max(nbytes.value, 256), dtype=torch.uint8, device=x.device)
+        check(self.lib.lfa_apply(self.handle, layer, ctypes.c_void_p(S.data_ptr()), ctypes.c_void_p(U.data_ptr()),
+                                 ctypes.c_void_p(V.data_ptr()), kinds[kind], float(param),
+                                 ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(y.data_ptr()), batch,
+                                 ctypes.c_void_p(ws.data_ptr()), ctypes.c_size_t(ws.numel()), _stream_ptr()),
+              "lfa_apply")
+        return y
+
     def topk(self, S, k):
         dev = S[0].device
         vals = torch.empty(len(self.layers), k, dtype=self.dtype, device=dev)

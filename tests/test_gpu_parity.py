@@ -467,3 +467,78 @@ def test_graph_replay_matches_eager():
         np.testing.assert_allclose(to_np(step.vals), to_np(vals), rtol=1e-5)
         for a, b in zip(step.dW, dW):
             assert float(torch.linalg.norm(a - b)) <= 1e-3 * float(torch.linalg.norm(b))
+
+
+# ------------------------------------------------- spectral functions --
+
+APPLY_GPU_CASES = [
+    # c_out, c_in, n, m, batch, dtype
+    (16, 16, 8, 8, 3, np.float32),
+    (24, 40, 6, 10, 2, np.float32),     # c_out < c_in
+    (40, 24, 7, 5, 2, np.float32),      # odd grid
+    (64, 64, 8, 8, 2, np.float32),
+    (12, 8, 6, 4, 2, np.float64),
+]
+
+
+def _gap_level(S, frac):
+    """A level near frac * sigma_max in a gap of the spectrum, at least
+    1e-3 sigma_max from every singular value (a cut-off on a singular value
+    would decide by rounding)."""
+    s = np.sort(S.ravel())
+    tgt = frac * s[-1]
+    gaps = np.where(np.diff(s) > 2e-3 * s[-1])[0]
+    i = gaps[np.argmin(np.abs(s[gaps] - tgt))]
+    return 0.5 * (s[i] + s[i + 1])
+
+
+@pytest.mark.parametrize("case", APPLY_GPU_CASES)
+@pytest.mark.parametrize("kind", ["identity", "clip", "pinv"])
+def test_apply_matches_oracle(case, kind):
+    """lfa_apply (transforms, per-frequency spectral map, inverse transforms)
+    on the GPU's own SVD, against the oracle's spectral function of the same
+    weights.  Gates: FP32 5e-5 of max|y| (1e-3 for the pseudo-inverse, whose
+    cut-off at ~0.1 sigma_max amplifies the SVD's errors up to 10x); FP64
+    1e-10."""
+    c_out, c_in, n, m, B, dt = case
+    banner(f"apply {kind} {case}")
+    _, W = workloads.random_layer(c_out, c_in, 3, 3, n, m, seed=41, dtype=dt)
+    tdt = torch.float32 if dt == np.float32 else torch.float64
+    plan = lfa().Plan([lfa().LayerSpec(c_out, c_in, 3, 3, n, m)], tdt, True, True)
+    S, U, V, info = plan.svd([_w(W)])
+    S_ref = oracle.lfa_svd(W.astype(np.float64), n, m)
+    param = 0.0
+    if kind == "clip":
+        param = _gap_level(S_ref, 0.5)
+    if kind == "pinv":
+        param = _gap_level(S_ref, 0.1)
+    cx = c_out if kind == "pinv" else c_in
+    rng = np.random.default_rng(42)
+    x = rng.standard_normal((B, cx, n, m)).astype(dt)
+    y = plan.apply(0, S[0], U[0], V[0], _w(x), kind, param)
+    torch.cuda.synchronize()
+    ref = oracle.apply_spectral(W.astype(np.float64), x.astype(np.float64), n, m, kind, param)
+    err = np.max(np.abs(to_np(y) - ref)) / np.max(np.abs(ref))
+    gate = (1e-3 if kind == "pinv" else 5e-5) if dt == np.float32 else 1e-10
+    assert err <= gate, f"{kind} {case}: {err:.3e}"
+
+
+def test_apply_pinv_round_trip_and_batch_independence():
+    """Pseudo-inverse after the operator returns the input (square, full
+    rank, no cut-off), and every image of a batch comes out as it would
+    alone."""
+    banner("apply round trip")
+    n = m = 8
+    _, W = workloads.random_layer(16, 16, 3, 3, n, m, seed=43, dtype=np.float64)
+    plan = lfa().Plan([lfa().LayerSpec(16, 16, 3, 3, n, m)], torch.float64, True, True)
+    S, U, V, info = plan.svd([_w(W)])
+    smin, smax = float(S[0].min()), float(S[0].max())
+    assert smin > 1e-3 * smax
+    rng = np.random.default_rng(44)
+    x = _w(rng.standard_normal((3, 16, n, m)))
+    Ax = plan.apply(0, S[0], U[0], V[0], x, "identity")
+    back = plan.apply(0, S[0], U[0], V[0], Ax, "pinv", 0.0)
+    torch.cuda.synchronize()
+    assert float((back - x).abs().max()) <= 1e-12 * float(x.abs().max()) * smax / smin
+    one = plan.apply(0, S[0], U[0], V[0], x[1:2].contiguous(), "identity")
+    assert torch.equal(one[0], Ax[1])
