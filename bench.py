@@ -175,6 +175,31 @@ def bench_assembly(dev, steps, asm):
     return dict(ms=ms, gbs=bytes_moved / (ms * 1e-3) / 1e9, bytes=bytes_moved, A=A, L=L, W=W)
 
 
+def bench_apply(head, dev, kind, batch=8, steps=10):
+    """A spectral function of the headline layer's operator applied to
+    `batch` images through its SVD (lfa_apply: forward transforms, the
+    per-frequency map U f(S) V^* or V f(S) U^*, inverse transforms).  The
+    per-frequency map reads U and V once for the batch: HBM-bound."""
+    L, plan = head["layer"], head["plan"]
+    S, U, V = head["S"], head["U"], head["V"]
+    rng = np.random.default_rng(7)
+    cx = L.c_out if kind == "pinv" else L.c_in
+    x = torch.from_numpy(rng.standard_normal((batch, cx, L.n, L.m)).astype(np.float32)).to(dev)
+    param = 0.0
+    out = {}
+
+    def step():
+        out["y"] = plan.apply(0, S, U, V, x, kind, param)
+
+    _, ev = event_times(step, steps, 2)
+    ms = float(np.mean(ev))
+    y = out["y"]
+    bytes_moved = (U.numel() * U.element_size() + V.numel() * V.element_size() + S.numel() * S.element_size()
+                   + x.numel() * x.element_size() + y.numel() * y.element_size())
+    return dict(ms=ms, gbs=bytes_moved / (ms * 1e-3) / 1e9, bytes=bytes_moved, x=x, y=y, kind=kind,
+                param=param, W=head["W"], layer=L, batch=batch)
+
+
 def cpu_leg(head, extra):
     """FP64 oracle on the host: timed on the headline layer (all 4096 symbols,
     sigma+U+V, thread pool over frequency chunks, one BLAS thread each), and
@@ -241,6 +266,11 @@ def cpu_leg(head, extra):
                 Sall = res["S"].cpu().numpy().astype(np.float64)
                 Lx = res["layer"]
                 errors[name + "_parseval_rel"] = float(abs(np.sum(Sall ** 2) / (Lx.n * Lx.m * np.sum(W64 ** 2)) - 1))
+            elif name.startswith("apply"):
+                Lx = res["layer"]
+                ref = oracle.apply_spectral(res["W"].astype(np.float64), res["x"].cpu().numpy().astype(np.float64),
+                                            Lx.n, Lx.m, res["kind"], res["param"])
+                errors[name + "_rel_max"] = float(np.max(np.abs(res["y"].cpu().numpy() - ref)) / np.max(np.abs(ref)))
             elif name.startswith("assembly"):
                 fr = np.stack([rng.integers(0, res["L"].n, 32), rng.integers(0, res["L"].m, 32)], axis=1)
                 ref = oracle.symbols(res["W"].astype(np.float64), res["L"].n, res["L"].m, fr)
@@ -269,7 +299,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--quick", action="store_true", help="headline workload only")
     ap.add_argument("--only", default=None,
-                    help="run one extra workload after the headline: fp64, rect, stack, large, "
+                    help="run one extra workload after the headline: apply, fp64, rect, stack, large, "
                          "assembly, paper")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -314,6 +344,14 @@ def main():
     if not args.quick:
         reps = 3
         wl = {}
+    if sel("apply"):
+        # spectral functions of the headline layer through its SVD (8 images)
+        for kind in ("identity", "pinv"):
+            a = bench_apply(head, dev, kind)
+            extra["apply_" + kind] = a
+            wl["apply_64x64_" + kind + "_b8"] = dict(ms=a["ms"], hbm_gbs=a["gbs"],
+                                                    frac_of_hbm_peak=a["gbs"] / PEAK_HBM_GBS, batch=a["batch"])
+        note("spectral apply done")
     if sel("fp64"):
         L1, W1 = workloads.single_layer_16()
         r = run_layer(L1, W1, dev, True, reps * 3, 1, dtype=torch.float64)

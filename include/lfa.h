@@ -260,7 +260,9 @@ int lfa_apply_workspace_bytes(const lfa_plan* plan, int32_t layer, int32_t batch
  *   ws    at least lfa_apply_workspace_bytes(plan, layer, batch)
  * Stream-ordered; batch == 0 does nothing.  x and y may not overlap.
  * Errors: LFA_ERR_INVALID_ARG (layer, kind, param, batch < 0, NULL pointer),
- * LFA_ERR_WORKSPACE, LFA_ERR_HIP. */
+ * LFA_ERR_WORKSPACE, LFA_ERR_UNSUPPORTED (the per-frequency map of 8 images
+ * does not fit one work-group's LDS: c_x + r beyond about 2200 in FP32,
+ * 1000 in FP64), LFA_ERR_HIP. */
 int lfa_apply(const lfa_plan* plan, int32_t layer, const void* sigma, const void* U, const void* V,
               int32_t kind, double param, const void* x, void* y, int32_t batch, void* ws,
               size_t ws_bytes, void* stream);

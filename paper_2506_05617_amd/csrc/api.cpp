@@ -1064,6 +1064,8 @@ int lfa_apply(const lfa_plan* plan, int32_t layer, const void* sigma, const void
     LFA_TRY(ensure_device(p));
     const lfa_layer& l = p->layers[layer];
     const bool pinv = kind == LFA_SPECTRAL_PINV;
+    if (!apply_supported(pinv ? l.c_out : l.c_in, std::min(l.c_out, l.c_in), elem_bytes(p->dtype)))
+        return LFA_ERR_UNSUPPORTED;
     ApplyArgs a{};
     a.batch = batch;
     a.n = l.n;

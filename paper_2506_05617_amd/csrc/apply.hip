@@ -65,57 +65,163 @@ __global__ void __launch_bounds__(256) dft_axis_kernel(const void* in_v, void* o
     }
 }
 
-// One work-group per frequency k: for every image b,
-//   z_j = fac_j * sum_c conj(Rt[k][c][j]) xh[b][k][c]   (j < r, c < cx)
-//   yh[b][k][o] = sum_j Lt[k][o][j] z_j                  (o < cy)
-// with fac_j = f(sigma_j(k)).  Rt[k] is read with consecutive j across the
-// threads of the work-group; row o of Lt[k] is read by thread o (each
-// thread's row is contiguous, so the cache lines of a row serve that thread's
-// next reads).  U and V of a frequency are read once for the whole batch.
+// The same transform with the work-group's lines and the twiddles of L in
+// LDS: LPB = max(1, 256 / L) lines per work-group, each input element read
+// from memory once, every product taken from LDS.  L <= kDftLdsMaxL.
+constexpr int kDftThreads = 256;
+constexpr int kDftLdsMaxL = 2048;
+
+template <typename R, bool REAL_IN, bool REAL_OUT>
+__global__ void __launch_bounds__(kDftThreads) dft_axis_lds_kernel(const void* in_v, void* out_v, long long lines,
+                                                                   int L, int lpb, AxisMap mp, const double* tw,
+                                                                   int sign, R scale) {
+    extern __shared__ __align__(16) char lds[];
+    cplx<R>* w = reinterpret_cast<cplx<R>*>(lds);      // [L] e^{sign 2 pi i j / L}
+    cplx<R>* xs = w + L;                               // [lpb][L]
+    const int tid = threadIdx.x;
+    const long long line0 = (long long)blockIdx.x * lpb;
+    for (int j = tid; j < L; j += kDftThreads) w[j] = {R(tw[2 * j]), R(sign) * R(tw[2 * j + 1])};
+    for (int e = tid; e < lpb * L; e += kDftThreads) {
+        const int li = e / L, t = e - (e / L) * L;
+        const long long line = line0 + li;
+        cplx<R> v = {R(0), R(0)};
+        if (line < lines) {
+            const long long i2 = line % mp.N2, i01 = line / mp.N2;
+            const long long i1 = i01 % mp.N1, i0 = i01 / mp.N1;
+            const long long off = i0 * mp.is0 + i1 * mp.is1 + i2 * mp.is2 + (long long)t * mp.ist;
+            if constexpr (REAL_IN) v.x = static_cast<const R*>(in_v)[off];
+            else v = static_cast<const cplx<R>*>(in_v)[off];
+        }
+        xs[e] = v;
+    }
+    __syncthreads();
+    for (int e = tid; e < lpb * L; e += kDftThreads) {
+        const int li = e / L, f = e - (e / L) * L;
+        const long long line = line0 + li;
+        if (line >= lines) continue;
+        const cplx<R>* x = xs + li * L;
+        R ar = 0, ai = 0;
+        int j = 0;   // (f * t) mod L
+        for (int t = 0; t < L; ++t) {
+            const cplx<R> c = w[j], v = x[t];
+            ar = fma(v.x, c.x, fma(-v.y, c.y, ar));
+            ai = fma(v.x, c.y, fma(v.y, c.x, ai));
+            j += f;
+            if (j >= L) j -= L;
+        }
+        const long long i2 = line % mp.N2, i01 = line / mp.N2;
+        const long long i1 = i01 % mp.N1, i0 = i01 / mp.N1;
+        const long long off = i0 * mp.os0 + i1 * mp.os1 + i2 * mp.os2 + (long long)f * mp.ost;
+        if constexpr (REAL_OUT) static_cast<R*>(out_v)[off] = ar * scale;
+        else static_cast<cplx<R>*>(out_v)[off] = {ar * scale, ai * scale};
+    }
+}
+
+// One work-group (64 threads) per frequency k, images in chunks of BC:
+//   z[b][j] = fac_j * sum_c conj(Rt[k][c][j]) xh[b][k][c]   (j < r, c < cx)
+//   yh[b][k][o] = sum_j Lt[k][o][j] z[b][j]                  (o < cy)
+// with fac_j = f(sigma_j(k)).  The chunk's x_hat vectors and z sit in LDS;
+// Rt[k] is read once per chunk with consecutive j across the threads, and
+// Lt[k] passes through a padded LDS tile of 64 rows x 32 columns (coalesced
+// loads, row reads one per thread), so U and V of a frequency are read once
+// per chunk of images.
+constexpr int kApplyThreads = 64;
+constexpr size_t kApplyMaxLds = 160 * 1024 - 1024;   // gfx950 LDS per work-group
+constexpr int kApplyBC = 8;        // images per chunk
+constexpr int kApplyTO = 64;       // rows of an Lt tile (one per thread)
+constexpr int kApplyTJ = 32;       // columns of an Lt tile
+
 template <typename R>
-__global__ void __launch_bounds__(256) spectral_apply_kernel(const R* sigma, const cplx<R>* Lt, const cplx<R>* Rt,
-                                                             const cplx<R>* xh, cplx<R>* yh, int nfreq, int batch,
-                                                             int cx, int cy, int r, int kind, R param) {
+size_t apply_lds_bytes(int cx, int r) {
+    return sizeof(R) * (size_t)((r + 1) & ~1) + sizeof(cplx<R>) * (size_t)kApplyBC * (cx + r) +
+           sizeof(cplx<R>) * (size_t)kApplyTO * (kApplyTJ + 1);
+}
+
+template <typename R>
+__global__ void __launch_bounds__(kApplyThreads) spectral_apply_kernel(
+    const R* sigma, const cplx<R>* Lt, const cplx<R>* Rt, const cplx<R>* xh, cplx<R>* yh, int nfreq, int batch,
+    int cx, int cy, int r, int kind, R param) {
     extern __shared__ __align__(16) char lds[];
     const int k = blockIdx.x;
     if (k >= nfreq) return;
-    const int tid = threadIdx.x, nt = blockDim.x;
-    R* fac = reinterpret_cast<R*>(lds);                            // [r]
-    cplx<R>* xs = reinterpret_cast<cplx<R>*>(fac + ((r + 1) & ~1));  // [cx]
-    cplx<R>* zs = xs + cx;                                         // [r]
-    for (int j = tid; j < r; j += nt) {
+    const int tid = threadIdx.x;
+    constexpr int NT = kApplyThreads, BC = kApplyBC, TO = kApplyTO, TJ = kApplyTJ;
+    static_assert(TO == NT, "one tile row per thread");
+    R* fac = reinterpret_cast<R*>(lds);                                  // [r]
+    cplx<R>* xs = reinterpret_cast<cplx<R>*>(fac + ((r + 1) & ~1));      // [BC][cx]
+    cplx<R>* zs = xs + BC * cx;                                          // [BC][r]
+    cplx<R>* lt = zs + BC * r;                                           // [TO][TJ + 1]
+    for (int j = tid; j < r; j += NT) {
         const R s = sigma[(size_t)k * r + j];
-        R f = s;                                                   // identity
+        R f = s;                                                         // identity
         if (kind == LFA_SPECTRAL_CLIP) f = s < param ? s : param;
         if (kind == LFA_SPECTRAL_PINV) f = s > param ? R(1) / s : R(0);
         fac[j] = f;
     }
     const cplx<R>* Rk = Rt + (size_t)k * cx * r;
     const cplx<R>* Lk = Lt + (size_t)k * cy * r;
-    for (int b = 0; b < batch; ++b) {
+    for (int b0 = 0; b0 < batch; b0 += BC) {
+        const int nb = batch - b0 < BC ? batch - b0 : BC;
         __syncthreads();
-        for (int c = tid; c < cx; c += nt) xs[c] = xh[((size_t)b * nfreq + k) * cx + c];
-        __syncthreads();
-        for (int j = tid; j < r; j += nt) {
-            R zr = 0, zi = 0;
-            for (int c = 0; c < cx; ++c) {
-                const cplx<R> a = Rk[(size_t)c * r + j], v = xs[c];
-                // conj(a) * v
-                zr = fma(a.x, v.x, fma(a.y, v.y, zr));
-                zi = fma(a.x, v.y, fma(-a.y, v.x, zi));
-            }
-            zs[j] = {zr * fac[j], zi * fac[j]};
+        for (int e = tid; e < nb * cx; e += NT) {
+            const int b = e / cx, c = e - (e / cx) * cx;
+            xs[b * cx + c] = xh[((size_t)(b0 + b) * nfreq + k) * cx + c];
         }
         __syncthreads();
-        for (int o = tid; o < cy; o += nt) {
-            R yr = 0, yi = 0;
-            const cplx<R>* row = Lk + (size_t)o * r;
-            for (int j = 0; j < r; ++j) {
-                const cplx<R> a = row[j], z = zs[j];
-                yr = fma(a.x, z.x, fma(-a.y, z.y, yr));
-                yi = fma(a.x, z.y, fma(a.y, z.x, yi));
+        // z = fac * R^H x for the chunk
+        for (int j = tid; j < r; j += NT) {
+            R zr[BC], zi[BC];
+#pragma unroll
+            for (int b = 0; b < BC; ++b) zr[b] = zi[b] = R(0);
+#pragma unroll 8
+            for (int c = 0; c < cx; ++c) {
+                const cplx<R> a = Rk[(size_t)c * r + j];
+#pragma unroll
+                for (int b = 0; b < BC; ++b) {
+                    if (b < nb) {
+                        const cplx<R> v = xs[b * cx + c];
+                        zr[b] = fma(a.x, v.x, fma(a.y, v.y, zr[b]));
+                        zi[b] = fma(a.x, v.y, fma(-a.y, v.x, zi[b]));
+                    }
+                }
             }
-            yh[((size_t)b * nfreq + k) * cy + o] = {yr, yi};
+#pragma unroll
+            for (int b = 0; b < BC; ++b)
+                if (b < nb) zs[b * r + j] = {zr[b] * fac[j], zi[b] * fac[j]};
+        }
+        // y = L z, tile by tile of L (TO rows x TJ columns)
+        for (int o0 = 0; o0 < cy; o0 += TO) {
+            const int o = o0 + tid;
+            R yr[BC], yi[BC];
+#pragma unroll
+            for (int b = 0; b < BC; ++b) yr[b] = yi[b] = R(0);
+            for (int j0 = 0; j0 < r; j0 += TJ) {
+                __syncthreads();
+#pragma unroll 8
+                for (int it = 0; it < TO * TJ / NT; ++it) {
+                    const int e = it * NT + tid, rr = e / TJ, cc = e - (e / TJ) * TJ;
+                    const int oo = o0 + rr, jj = j0 + cc;
+                    lt[rr * (TJ + 1) + cc] = (oo < cy && jj < r) ? Lk[(size_t)oo * r + jj] : cplx<R>{R(0), R(0)};
+                }
+                __syncthreads();
+                const int jn = r - j0 < TJ ? r - j0 : TJ;
+                for (int jj = 0; jj < jn; ++jj) {
+                    const cplx<R> a = lt[tid * (TJ + 1) + jj];
+#pragma unroll
+                    for (int b = 0; b < BC; ++b) {
+                        if (b < nb) {
+                            const cplx<R> z = zs[b * r + j0 + jj];
+                            yr[b] = fma(a.x, z.x, fma(-a.y, z.y, yr[b]));
+                            yi[b] = fma(a.x, z.y, fma(a.y, z.x, yi[b]));
+                        }
+                    }
+                }
+            }
+            if (o < cy) {
+#pragma unroll
+                for (int b = 0; b < BC; ++b)
+                    if (b < nb) yh[((size_t)(b0 + b) * nfreq + k) * cy + o] = {yr[b], yi[b]};
+            }
         }
     }
 }
@@ -125,6 +231,20 @@ hipError_t launch_axis(const void* in, void* out, long long lines, int L, const 
                        int sign, R scale, hipStream_t st) {
     const long long total = lines * L;
     if (total <= 0) return hipSuccess;
+    if (L <= kDftLdsMaxL) {
+        const int lpb = L >= kDftThreads ? 1 : kDftThreads / L;
+        const long long blocks = (lines + lpb - 1) / lpb;
+        if (blocks > 0x7fffffffLL) return hipErrorInvalidValue;
+        const size_t lds = sizeof(cplx<R>) * (size_t)L * (1 + lpb);
+        if (lds > 65536) {
+            hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(dft_axis_lds_kernel<R, RI, RO>),
+                                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+            if (e != hipSuccess) return e;
+        }
+        hipLaunchKernelGGL((dft_axis_lds_kernel<R, RI, RO>), dim3((unsigned)blocks), dim3(kDftThreads), lds, st, in,
+                           out, lines, L, lpb, mp, tw, sign, scale);
+        return hipGetLastError();
+    }
     const int threads = 256;
     const long long blocks = (total + threads - 1) / threads;
     if (blocks > 0x7fffffffLL) return hipErrorInvalidValue;
@@ -155,10 +275,14 @@ hipError_t apply_t(const ApplyArgs& a, hipStream_t st) {
     }
     // C: per frequency, T2 -> T1 = y_hat [B][n][m][cy]
     {
-        const int threads = 64;
-        const size_t lds = sizeof(R) * ((a.r + 1) & ~1) + sizeof(cplx<R>) * (cx + a.r);
-        if (lds > 65536) return hipErrorInvalidValue;
-        hipLaunchKernelGGL((spectral_apply_kernel<R>), dim3((unsigned)nm), dim3(threads), lds, st,
+        const size_t lds = apply_lds_bytes<R>((int)cx, a.r);
+        if (lds > kApplyMaxLds) return hipErrorInvalidValue;
+        if (lds > 65536) {
+            e = hipFuncSetAttribute(reinterpret_cast<const void*>(spectral_apply_kernel<R>),
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+            if (e != hipSuccess) return e;
+        }
+        hipLaunchKernelGGL((spectral_apply_kernel<R>), dim3((unsigned)nm), dim3(kApplyThreads), lds, st,
                            static_cast<const R*>(a.sigma), static_cast<const cplx<R>*>(a.L),
                            static_cast<const cplx<R>*>(a.R), T2, T1, (int)nm, (int)B, (int)cx, (int)cy, a.r,
                            a.kind, R(a.param));
@@ -181,6 +305,11 @@ hipError_t apply_t(const ApplyArgs& a, hipStream_t st) {
 }
 
 }  // namespace
+
+bool apply_supported(int cx, int r, int elem_bytes) {
+    const size_t lds = elem_bytes == 8 ? apply_lds_bytes<double>(cx, r) : apply_lds_bytes<float>(cx, r);
+    return lds <= kApplyMaxLds;
+}
 
 hipError_t launch_apply_f32(const ApplyArgs& a, hipStream_t s) { return apply_t<float>(a, s); }
 hipError_t launch_apply_f64(const ApplyArgs& a, hipStream_t s) { return apply_t<double>(a, s); }

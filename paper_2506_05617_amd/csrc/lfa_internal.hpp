@@ -317,6 +317,8 @@ struct ApplyArgs {
     int tw_n, tw_m;
 };
 hipError_t launch_apply_f32(const ApplyArgs& a, hipStream_t s);
+// The per-frequency map of an image chunk fits the LDS of a work-group.
+bool apply_supported(int cx, int r, int elem_bytes);
 hipError_t launch_apply_f64(const ApplyArgs& a, hipStream_t s);
 
 size_t lds_bytes_for(const LayerDesc& d, bool accumulate, int elem_bytes);
