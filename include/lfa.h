@@ -241,9 +241,15 @@ enum lfa_spectral_kind {
     LFA_SPECTRAL_IDENTITY = 0, /* g_k = U_k S_k V_k^*: the convolution itself     */
     LFA_SPECTRAL_CLIP = 1,     /* g_k = U_k min(S_k, param) V_k^*: singular values
                                   clipped at param (a Lipschitz bound)           */
-    LFA_SPECTRAL_PINV = 2      /* g_k = V_k S_k^+ U_k^*: pseudo-inverse, 1/sigma for
+    LFA_SPECTRAL_PINV = 2,     /* g_k = V_k S_k^+ U_k^*: pseudo-inverse, 1/sigma for
                                   sigma > param (absolute cut-off), 0 otherwise;
                                   maps c_out channels back to c_in               */
+    LFA_SPECTRAL_TRUNCATE = 3  /* g_k = U_k T(S_k) V_k^*, T(sigma) = sigma for
+                                  sigma > param, else 0: the low-rank truncation
+                                  of the operator that keeps its singular values
+                                  above param (with param = the R-th largest
+                                  singular value of the layer and distinct values,
+                                  the best rank-(R-1) approximation)             */
 };
 
 /* Workspace (device bytes) of lfa_apply for `batch` images of layer `layer`:
@@ -255,8 +261,8 @@ int lfa_apply_workspace_bytes(const lfa_plan* plan, int32_t layer, int32_t batch
  * LFA_WANT_V).  All pointers are device memory in the plan's dtype:
  *   sigma [n][m][r], U [n][m][c_out][r], V [n][m][c_in][r]  (r = min(c_out, c_in))
  *   x     [batch][c_x][n][m] real,  y [batch][c_y][n][m] real,
- *         c_x = c_in, c_y = c_out (IDENTITY, CLIP); c_x = c_out, c_y = c_in (PINV)
- *   kind  an lfa_spectral_kind; param >= 0 (CLIP level, PINV cut-off)
+ *         c_x = c_in, c_y = c_out (IDENTITY, CLIP, TRUNCATE); c_x = c_out, c_y = c_in (PINV)
+ *   kind  an lfa_spectral_kind; param >= 0 (CLIP level, PINV and TRUNCATE cut-off)
  *   ws    at least lfa_apply_workspace_bytes(plan, layer, batch)
  * Stream-ordered; batch == 0 does nothing.  x and y may not overlap.
  * Errors: LFA_ERR_INVALID_ARG (layer, kind, param, batch < 0, NULL pointer),
@@ -266,6 +272,25 @@ int lfa_apply_workspace_bytes(const lfa_plan* plan, int32_t layer, int32_t batch
 int lfa_apply(const lfa_plan* plan, int32_t layer, const void* sigma, const void* U, const void* V,
               int32_t kind, double param, const void* x, void* y, int32_t batch, void* ws,
               size_t ws_bytes, void* stream);
+
+/* Global singular vectors of the periodic operator (Sec. III "Convolution
+ * Theorem": they are the Fourier modes of a frequency k times the singular
+ * vectors of the symbol A_k) for `count` picks (p, q, j) of layer `layer`,
+ * as complex images:
+ *   u_hat[t][o][x1][x2] = e^{2 pi i (p x1 / n + q x2 / m)} U[p][q][o][j] / sqrt(n m)
+ *   v_hat[t][i][x1][x2] = e^{2 pi i (p x1 / n + q x2 / m)} V[p][q][i][j] / sqrt(n m)
+ * so that the operator maps v_hat to sigma_j(k) u_hat, and both have unit
+ * norm.  All pointers are device memory:
+ *   U [n][m][c_out][r], V [n][m][c_in][r]  complex, as lfa_svd writes them
+ *   idx   int32 [count][3] = (p, q, j), e.g. one layer's rows of lfa_topk
+ *   u_hat [count][c_out][n][m], v_hat [count][c_in][n][m]  complex, plan's dtype
+ * u_hat or v_hat may be NULL (not written; then U or V may be NULL too).  A
+ * pick out of range (p not in [0, n), q not in [0, m) or j not in [0, r))
+ * gives zero vectors.  Stream-ordered; count == 0 does nothing.
+ * Errors: LFA_ERR_INVALID_ARG (layer, count < 0, idx NULL, an output without
+ * its input), LFA_ERR_HIP. */
+int lfa_lift(const lfa_plan* plan, int32_t layer, const void* U, const void* V, const int32_t* idx,
+             int32_t count, void* u_hat, void* v_hat, void* stream);
 
 /* ---- tuning and diagnostics ------------------------------------------- */
 
@@ -282,7 +307,7 @@ int lfa_plan_launch_shape(const lfa_plan* plan, int32_t layer, int32_t* lanes_pe
 
 /* Work-queue launch of a layer's register kernel (symbols of at most 64
  * rows) on the current device.  When the groups of symbols fill the resident
- * work-groups more than once (and at most 16 times), lfa_svd runs a grid of
+ * work-groups more than once (and at most 4 times), lfa_svd runs a grid of
  * resident work-groups that take groups from a device queue a few sweeps at
  * a time, saving the state of unfinished groups in the workspace, so that no
  * group starts late in a partly filled last round; the results are bitwise

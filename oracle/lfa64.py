@@ -200,9 +200,10 @@ def lift(U, V, n: int, m: int, p: int, q: int):
 def spectral_factor(sigma, kind: str, param: float = 0.0):
     """``f(sigma)`` of the spectral functions applied below: ``identity`` (the
     operator itself), ``clip`` (``min(sigma, param)``: the operator with its
-    singular values clipped at ``param``) and ``pinv`` (``1/sigma`` above the
-    absolute cut-off ``param``, else 0: the pseudo-inverse restricted to the
-    kept singular values)."""
+    singular values clipped at ``param``), ``truncate`` (``sigma`` above
+    ``param``, else 0: the low-rank truncation of the operator) and ``pinv``
+    (``1/sigma`` above the absolute cut-off ``param``, else 0: the
+    pseudo-inverse restricted to the kept singular values)."""
     s = np.asarray(sigma, dtype=np.float64)
     if kind == "identity":
         return s.copy()
@@ -213,6 +214,8 @@ def spectral_factor(sigma, kind: str, param: float = 0.0):
         return out
     if kind == "clip":
         return np.minimum(s, param)
+    if kind == "truncate":
+        return np.where(s > param, s, 0.0)
     raise ValueError(kind)
 
 
@@ -222,7 +225,7 @@ def apply_spectral(W, x, n: int, m: int | None, kind: str, param: float = 0.0):
     Theorem": the global singular vectors are Fourier modes times the
     singular vectors of the symbols):
 
-    * ``identity`` and ``clip``: ``y = U f(Sigma) V^* x``, ``x [B, c_in, n, m]``
+    * ``identity``, ``clip`` and ``truncate``: ``y = U f(Sigma) V^* x``, ``x [B, c_in, n, m]``
       real, ``y [B, c_out, n, m]``;
     * ``pinv``: ``y = V f(Sigma) U^* x`` (the pseudo-inverse maps back from the
       output channels), ``x [B, c_out, n, m]``, ``y [B, c_in, n, m]``.

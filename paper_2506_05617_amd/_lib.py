@@ -23,6 +23,7 @@ LFA_ASM_BF16X3 = 16
 LFA_SPECTRAL_IDENTITY = 0
 LFA_SPECTRAL_CLIP = 1
 LFA_SPECTRAL_PINV = 2
+LFA_SPECTRAL_TRUNCATE = 3
 
 LFA_OK = 0
 LFA_ERR_INVALID_ARG = -1
@@ -70,6 +71,7 @@ SIGNATURES = {
     "lfa_plan_launch_shape": (I32, [P, I32, I32P, I32P, I32P, I32P]),
     "lfa_apply_workspace_bytes": (I32, [P, I32, I32, ctypes.POINTER(SZ)]),
     "lfa_apply": (I32, [P, I32, P, P, P, I32, ctypes.c_double, P, P, I32, P, SZ, P]),
+    "lfa_lift": (I32, [P, I32, P, P, P, I32, P, P, P]),
     "lfa_plan_queue_info": (I32, [P, I32, I32P, I32P]),
     "lfa_status_string": (ctypes.c_char_p, [I32]),
     "lfa_last_hip_error": (I32, []),

@@ -1052,7 +1052,8 @@ int lfa_apply(const lfa_plan* plan, int32_t layer, const void* sigma, const void
               int32_t kind, double param, const void* x, void* y, int32_t batch, void* ws,
               size_t ws_bytes, void* stream) {
     if (!plan || layer < 0 || layer >= (int32_t)plan->layers.size() || batch < 0) return LFA_ERR_INVALID_ARG;
-    if (kind != LFA_SPECTRAL_IDENTITY && kind != LFA_SPECTRAL_CLIP && kind != LFA_SPECTRAL_PINV)
+    if (kind != LFA_SPECTRAL_IDENTITY && kind != LFA_SPECTRAL_CLIP && kind != LFA_SPECTRAL_PINV &&
+        kind != LFA_SPECTRAL_TRUNCATE)
         return LFA_ERR_INVALID_ARG;
     if (!(param >= 0.0) || !std::isfinite(param)) return LFA_ERR_INVALID_ARG;
     if (batch == 0) return LFA_OK;
@@ -1087,6 +1088,35 @@ int lfa_apply(const lfa_plan* plan, int32_t layer, const void* sigma, const void
     a.tw_m = p->tw_m[layer];
     hipStream_t st = static_cast<hipStream_t>(stream);
     HIP_TRY(p->dtype == LFA_F64 ? launch_apply_f64(a, st) : launch_apply_f32(a, st));
+    return LFA_OK;
+}
+
+int lfa_lift(const lfa_plan* plan, int32_t layer, const void* U, const void* V, const int32_t* idx,
+             int32_t count, void* u_hat, void* v_hat, void* stream) {
+    if (!plan || layer < 0 || layer >= (int32_t)plan->layers.size() || count < 0) return LFA_ERR_INVALID_ARG;
+    if ((u_hat && !U) || (v_hat && !V)) return LFA_ERR_INVALID_ARG;
+    if (count == 0 || (!u_hat && !v_hat)) return LFA_OK;
+    if (!idx) return LFA_ERR_INVALID_ARG;
+    lfa_plan* p = const_cast<lfa_plan*>(plan);
+    LFA_TRY(ensure_device(p));
+    const lfa_layer& l = p->layers[layer];
+    LiftArgs a{};
+    a.count = count;
+    a.n = l.n;
+    a.m = l.m;
+    a.c_out = l.c_out;
+    a.c_in = l.c_in;
+    a.r = std::min(l.c_out, l.c_in);
+    a.idx = idx;
+    a.U = U;
+    a.V = V;
+    a.u_hat = u_hat;
+    a.v_hat = v_hat;
+    a.tw = p->tw_dev;
+    a.tw_n = p->tw_n[layer];
+    a.tw_m = p->tw_m[layer];
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    HIP_TRY(p->dtype == LFA_F64 ? launch_lift_f64(a, st) : launch_lift_f32(a, st));
     return LFA_OK;
 }
 

@@ -3,14 +3,19 @@
 // singular vectors of the operator are Fourier modes times the singular
 // vectors U_k, V_k of the symbols).
 //
-//   identity, clip:  y = U f(Sigma) V^* x   (x: c_in channels, y: c_out)
+//   identity, clip, truncate:  y = U f(Sigma) V^* x   (x: c_in channels, y: c_out)
 //   pinv:            y = V f(Sigma) U^* x   (x: c_out channels, y: c_in)
 //
 // Per image: x_hat_k = sum_x x(x) e^{-2 pi i <k, x>} (two passes of a
 // one-axis DFT), y_hat_k = L_k f(S_k) R_k^H x_hat_k at every frequency
 // (one work-group per frequency, L, R = U, V or V, U), and the inverse
 // transform with e^{+2 pi i <k, x>} / (n m), real part (two passes).
+//
+// Also here: the global singular vectors themselves (the lift of chosen
+// columns of U_k and V_k by the Fourier mode of k), written as images.
 #include <hip/hip_runtime.h>
+
+#include <cmath>
 
 #include "lfa_internal.hpp"
 
@@ -156,6 +161,7 @@ __global__ void __launch_bounds__(kApplyThreads) spectral_apply_kernel(
         R f = s;                                                         // identity
         if (kind == LFA_SPECTRAL_CLIP) f = s < param ? s : param;
         if (kind == LFA_SPECTRAL_PINV) f = s > param ? R(1) / s : R(0);
+        if (kind == LFA_SPECTRAL_TRUNCATE) f = s > param ? s : R(0);
         fac[j] = f;
     }
     const cplx<R>* Rk = Rt + (size_t)k * cx * r;
@@ -304,6 +310,60 @@ hipError_t apply_t(const ApplyArgs& a, hipStream_t st) {
     return hipSuccess;
 }
 
+// Global singular vector of one pick, as images: one work-group per
+// (pick t, channel c) row of n*m elements, x2 fastest (coalesced writes).
+// The phase index is reduced exactly in integers, (p x1) mod n and
+// (q x2) mod m, and the two FP64 table entries are multiplied in FP64.
+constexpr int kLiftThreads = 256;
+
+template <typename R>
+__global__ void __launch_bounds__(kLiftThreads) lift_kernel(const cplx<R>* W, const int32_t* idx,
+                                                            cplx<R>* out, int n, int m, int c, int r,
+                                                            const double* twn, const double* twm,
+                                                            double scale) {
+    const long long row = blockIdx.x;   // t * c + channel
+    const long long t = row / c;
+    const int ch = (int)(row - t * c);
+    const int p = idx[3 * t], q = idx[3 * t + 1], j = idx[3 * t + 2];
+    const int nm = n * m;
+    cplx<R>* o = out + row * nm;
+    if (p < 0 || p >= n || q < 0 || q >= m || j < 0 || j >= r) {
+        for (int pos = threadIdx.x; pos < nm; pos += blockDim.x) o[pos] = cplx<R>{R(0), R(0)};
+        return;
+    }
+    const cplx<R> w = W[(((long long)p * m + q) * c + ch) * r + j];
+    const double wr = double(w.x) * scale, wi = double(w.y) * scale;
+    for (int pos = threadIdx.x; pos < nm; pos += blockDim.x) {
+        const int x1 = pos / m, x2 = pos - x1 * m;
+        const int a1 = (int)(((long long)p * x1) % n), a2 = (int)(((long long)q * x2) % m);
+        const double er = twn[2 * a1], ei = twn[2 * a1 + 1];
+        const double fr = twm[2 * a2], fi = twm[2 * a2 + 1];
+        const double cr = er * fr - ei * fi, ci = er * fi + ei * fr;
+        o[pos] = cplx<R>{R(cr * wr - ci * wi), R(cr * wi + ci * wr)};
+    }
+}
+
+template <typename R>
+hipError_t lift_t(const LiftArgs& a, hipStream_t st) {
+    const double* twn = a.tw + 2 * (size_t)a.tw_n;
+    const double* twm = a.tw + 2 * (size_t)a.tw_m;
+    const double scale = 1.0 / std::sqrt(double(a.n) * double(a.m));
+    const void* src[2] = {a.U, a.V};
+    void* dst[2] = {a.u_hat, a.v_hat};
+    const int rows[2] = {a.c_out, a.c_in};
+    for (int s = 0; s < 2; ++s) {
+        if (!dst[s]) continue;
+        const long long blocks = (long long)a.count * rows[s];
+        if (blocks <= 0) continue;
+        hipLaunchKernelGGL((lift_kernel<R>), dim3((unsigned)blocks), dim3(kLiftThreads), 0, st,
+                           static_cast<const cplx<R>*>(src[s]), a.idx, static_cast<cplx<R>*>(dst[s]), a.n,
+                           a.m, rows[s], a.r, twn, twm, scale);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
 }  // namespace
 
 bool apply_supported(int cx, int r, int elem_bytes) {
@@ -313,5 +373,7 @@ bool apply_supported(int cx, int r, int elem_bytes) {
 
 hipError_t launch_apply_f32(const ApplyArgs& a, hipStream_t s) { return apply_t<float>(a, s); }
 hipError_t launch_apply_f64(const ApplyArgs& a, hipStream_t s) { return apply_t<double>(a, s); }
+hipError_t launch_lift_f32(const LiftArgs& a, hipStream_t s) { return lift_t<float>(a, s); }
+hipError_t launch_lift_f64(const LiftArgs& a, hipStream_t s) { return lift_t<double>(a, s); }
 
 }  // namespace lfa

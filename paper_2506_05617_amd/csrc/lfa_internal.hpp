@@ -321,6 +321,23 @@ hipError_t launch_apply_f32(const ApplyArgs& a, hipStream_t s);
 bool apply_supported(int cx, int r, int elem_bytes);
 hipError_t launch_apply_f64(const ApplyArgs& a, hipStream_t s);
 
+// Global singular vectors of `count` picks idx[t] = (p, q, j) (device int32):
+// u_hat[t][o][x1][x2] = e^{2 pi i (p x1 / n + q x2 / m)} U[p][q][o][j] / sqrt(n m),
+// v_hat likewise from V with c_in rows; a NULL output is skipped, a pick out
+// of range gives zeros.
+struct LiftArgs {
+    int count, n, m, c_out, c_in, r;
+    const int32_t* idx;
+    const void* U;
+    const void* V;
+    void* u_hat;
+    void* v_hat;
+    const double* tw;
+    int tw_n, tw_m;
+};
+hipError_t launch_lift_f32(const LiftArgs& a, hipStream_t s);
+hipError_t launch_lift_f64(const LiftArgs& a, hipStream_t s);
+
 size_t lds_bytes_for(const LayerDesc& d, bool accumulate, int elem_bytes);
 
 size_t wave_lds_bytes_for(int nc, int ml, int elem_bytes);

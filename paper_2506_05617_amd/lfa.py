@@ -173,11 +173,13 @@ class Plan:
         """Spectral function of layer `layer`'s operator applied to images
         ``x [batch, c_x, n, m]`` through its SVD ``S, U, V`` (as ``svd``
         returns them for that layer, with U and V): ``identity`` (the
-        convolution), ``clip`` (singular values clipped at ``param``) or
-        ``pinv`` (pseudo-inverse with absolute cut-off ``param``; x has
-        c_out channels and y has c_in).  Returns ``y [batch, c_y, n, m]``."""
+        convolution), ``clip`` (singular values clipped at ``param``),
+        ``truncate`` (singular values at or below ``param`` dropped: a
+        low-rank truncation) or ``pinv`` (pseudo-inverse with absolute
+        cut-off ``param``; x has c_out channels and y has c_in).  Returns
+        ``y [batch, c_y, n, m]``."""
         kinds = {"identity": _lib.LFA_SPECTRAL_IDENTITY, "clip": _lib.LFA_SPECTRAL_CLIP,
-                 "pinv": _lib.LFA_SPECTRAL_PINV}
+                 "pinv": _lib.LFA_SPECTRAL_PINV, "truncate": _lib.LFA_SPECTRAL_TRUNCATE}
         l = self.layers[layer]
         cx, cy = (l.c_out, l.c_in) if kind == "pinv" else (l.c_in, l.c_out)
         if x.dtype != self.dtype or x.dim() != 4 or tuple(x.shape[1:]) != (cx, l.n, l.m) or not x.is_contiguous():
@@ -199,6 +201,28 @@ class Plan:
                                  ctypes.c_void_p(ws.data_ptr()), ctypes.c_size_t(ws.numel()), _stream_ptr()),
               "lfa_apply")
         return y
+
+    def lift(self, layer, U, V, idx):
+        """Global singular vectors of layer `layer` for picks ``idx [count, 3]``
+        (int32 (p, q, j) on the device): ``(u_hat [count, c_out, n, m],
+        v_hat [count, c_in, n, m])`` complex, the Fourier mode of (p, q) times
+        column j of U and V at (p, q), unit norm.  U or V may be None (that
+        output is then None)."""
+        l = self.layers[layer]
+        cdt = _complex_of(self.dtype)
+        for T, c in ((U, l.c_out), (V, l.c_in)):
+            if T is not None and (tuple(T.shape) != (l.n, l.m, c, l.r) or T.dtype != cdt or not T.is_contiguous()):
+                raise ValueError("U, V must be this layer's singular vectors")
+        if idx.dtype != torch.int32 or idx.dim() != 2 or idx.shape[1] != 3 or not idx.is_contiguous():
+            raise ValueError("idx must be contiguous int32 [count, 3]")
+        count = idx.shape[0]
+        dev = idx.device
+        uh = None if U is None else torch.empty(count, l.c_out, l.n, l.m, dtype=cdt, device=dev)
+        vh = None if V is None else torch.empty(count, l.c_in, l.n, l.m, dtype=cdt, device=dev)
+        ptr = lambda t: ctypes.c_void_p(None if t is None else t.data_ptr())
+        check(self.lib.lfa_lift(self.handle, layer, ptr(U), ptr(V), ptr(idx), count, ptr(uh), ptr(vh),
+                                _stream_ptr()), "lfa_lift")
+        return uh, vh
 
     def topk(self, S, k):
         dev = S[0].device

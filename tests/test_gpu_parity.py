@@ -493,7 +493,7 @@ def _gap_level(S, frac):
 
 
 @pytest.mark.parametrize("case", APPLY_GPU_CASES)
-@pytest.mark.parametrize("kind", ["identity", "clip", "pinv"])
+@pytest.mark.parametrize("kind", ["identity", "clip", "truncate", "pinv"])
 def test_apply_matches_oracle(case, kind):
     """lfa_apply (transforms, per-frequency spectral map, inverse transforms)
     on the GPU's own SVD, against the oracle's spectral function of the same
@@ -508,7 +508,7 @@ def test_apply_matches_oracle(case, kind):
     S, U, V, info = plan.svd([_w(W)])
     S_ref = oracle.lfa_svd(W.astype(np.float64), n, m)
     param = 0.0
-    if kind == "clip":
+    if kind in ("clip", "truncate"):
         param = _gap_level(S_ref, 0.5)
     if kind == "pinv":
         param = _gap_level(S_ref, 0.1)
@@ -542,3 +542,62 @@ def test_apply_pinv_round_trip_and_batch_independence():
     assert float((back - x).abs().max()) <= 1e-12 * float(x.abs().max()) * smax / smin
     one = plan.apply(0, S[0], U[0], V[0], x[1:2].contiguous(), "identity")
     assert torch.equal(one[0], Ax[1])
+
+
+# ---------------------------------------------------------------- lift --
+
+LIFT_CASES = [
+    # c_out, c_in, n, m, dtype
+    (16, 16, 8, 8, np.float32),
+    (24, 40, 6, 10, np.float32),
+    (12, 8, 7, 5, np.float64),
+]
+
+
+@pytest.mark.parametrize("case", LIFT_CASES)
+def test_lift_matches_oracle_and_maps_v_to_sigma_u(case):
+    """lfa_lift against the oracle's lift (Fourier basis times the symbol's
+    singular vectors) of the same U, V columns, for the layer's top-k picks
+    plus a conjugate-side pick and an out-of-range one; the lifted vectors
+    have unit norm and the operator (lfa_apply, identity, on the real and
+    imaginary parts) maps v_hat to sigma u_hat."""
+    c_out, c_in, n, m, dt = case
+    banner(f"lift {case}")
+    _, W = workloads.random_layer(c_out, c_in, 3, 3, n, m, seed=45, dtype=dt)
+    tdt = torch.float32 if dt == np.float32 else torch.float64
+    plan = lfa().Plan([lfa().LayerSpec(c_out, c_in, 3, 3, n, m)], tdt, True, True)
+    S, U, V, info = plan.svd([_w(W)])
+    vals, idx = plan.topk(S, 4)
+    picks = torch.cat([idx[0], torch.tensor([[n - 1, m - 1, 1], [n, 0, 0]], dtype=torch.int32, device=DEV)])
+    uh, vh = plan.lift(0, U[0], V[0], picks.contiguous())
+    torch.cuda.synchronize()
+    Un, Vn, Sn = to_np(U[0]).astype(np.complex128), to_np(V[0]).astype(np.complex128), to_np(S[0])
+    pk = picks.cpu().numpy()
+    tol = 2e-6 if dt == np.float32 else 1e-13
+    for t in range(len(pk) - 1):
+        p, q, j = (int(v) for v in pk[t])
+        Uo, Vo = oracle.lift(Un[p, q], Vn[p, q], n, m, p, q)      # [(x1 m + x2) c + ch, r]
+        uo = Uo[:, j].reshape(n, m, c_out).transpose(2, 0, 1)
+        vo = Vo[:, j].reshape(n, m, c_in).transpose(2, 0, 1)
+        ug, vg = to_np(uh[t]), to_np(vh[t])
+        assert np.max(np.abs(ug - uo)) <= tol * np.max(np.abs(uo)), (t, p, q, j)
+        assert np.max(np.abs(vg - vo)) <= tol * np.max(np.abs(vo)), (t, p, q, j)
+        assert abs(np.linalg.norm(ug) - 1.0) <= 1e-5 and abs(np.linalg.norm(vg) - 1.0) <= 1e-5
+    assert float(uh[-1].abs().max()) == 0.0 and float(vh[-1].abs().max()) == 0.0
+    # the operator maps v_hat to sigma u_hat (apply is real-linear)
+    count = len(pk) - 1
+    xr = vh[:count].real.contiguous()
+    xi = vh[:count].imag.contiguous()
+    yr = plan.apply(0, S[0], U[0], V[0], xr, "identity")
+    yi = plan.apply(0, S[0], U[0], V[0], xi, "identity")
+    torch.cuda.synchronize()
+    Av = to_np(yr).astype(np.complex128) + 1j * to_np(yi)
+    for t in range(count):
+        p, q, j = (int(v) for v in pk[t])
+        su = Sn[p, q, j] * to_np(uh[t])
+        gate = (5e-5 if dt == np.float32 else 1e-11) * float(Sn.max())
+        assert np.max(np.abs(Av[t] - su)) <= gate * np.max(np.abs(to_np(uh[t]))), (t, p, q, j)
+    # one output only
+    only_u, none_v = plan.lift(0, U[0], None, picks[:2].contiguous())
+    torch.cuda.synchronize()
+    assert none_v is None and torch.equal(only_u, uh[:2])

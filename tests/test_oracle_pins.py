@@ -418,11 +418,12 @@ def test_apply_identity_is_the_convolution(case):
 
 
 @pytest.mark.parametrize("case", APPLY_CASES)
-@pytest.mark.parametrize("kind", ["pinv", "clip"])
+@pytest.mark.parametrize("kind", ["pinv", "clip", "truncate"])
 def test_apply_spectral_matches_dense_svd(case, kind):
-    """Pseudo-inverse and clipping through the per-symbol SVD equal the same
-    spectral function of the dense operator's SVD (torch's circular operator
-    -> numpy.linalg.svd): A^+ = V f(S) U^T, clipped A = U f(S) V^T.  The
+    """Pseudo-inverse, clipping and low-rank truncation through the per-symbol
+    SVD equal the same spectral function of the dense operator's SVD (torch's
+    circular operator -> numpy.linalg.svd): A^+ = V f(S) U^T, clipped or
+    truncated A = U f(S) V^T.  The
     cut-off / clip level lies midway in a gap of the singular values near
     their median (a level on a singular value would make the result depend
     on rounding)."""
@@ -438,8 +439,10 @@ def test_apply_spectral_matches_dense_svd(case, kind):
     f = oracle.spectral_factor(Sd, kind, level)
     if kind == "pinv":
         assert np.all(f[Sd > level] == 1.0 / Sd[Sd > level]) and np.all(f[Sd <= level] == 0)
-    else:
+    elif kind == "clip":
         assert np.all(f == np.minimum(Sd, level))
+    else:
+        assert np.all(f[Sd > level] == Sd[Sd > level]) and np.all(f[Sd <= level] == 0)
     r = Sd.size
     if kind == "pinv":
         x = rng.standard_normal((B, c_out, n, m))
@@ -459,12 +462,19 @@ def test_apply_spectral_matches_dense_svd(case, kind):
         # Moore-Penrose with the truncated spectrum: A A^+ A = A_kept, and
         # A^+ A A^+ = A^+
         assert np.allclose(op @ A @ op, op, atol=1e-10 * np.abs(op).max())
+    if kind == "truncate":
+        # Eckart-Young: the kept part has rank #(sigma > level) and leaves a
+        # remainder of spectral norm max(sigma <= level)
+        kept = int(np.sum(Sd > level))
+        assert np.linalg.matrix_rank(op, tol=1e-9 * Sd.max()) == kept
+        assert abs(np.linalg.norm(A - op, 2) - Sd[Sd <= level].max()) <= 1e-10 * Sd.max()
 
 
 def test_apply_pinv_inverts_full_rank_and_clip_above_max_is_identity():
     """For a square operator with every singular value kept, the pseudo-inverse
     undoes the operator (A^+ A x = x); clipping at or above sigma_max changes
-    nothing."""
+    nothing, nor does truncating below sigma_min, while truncating at
+    sigma_max leaves nothing."""
     rng = np.random.default_rng(33)
     W = rng.standard_normal((3, 3, 3, 3))
     n, m = 6, 5
@@ -476,3 +486,9 @@ def test_apply_pinv_inverts_full_rank_and_clip_above_max_is_identity():
     assert np.max(np.abs(back - x)) <= 1e-12 * np.max(np.abs(x)) * S.max() / S.min()
     same = oracle.apply_spectral(W, x, n, m, "clip", S.max() * (1 + 1e-12))
     assert np.max(np.abs(same - Ax)) <= 1e-12 * np.max(np.abs(Ax))
+    # truncation below sigma_min keeps the operator; at or above sigma_max
+    # it removes everything
+    keep = oracle.apply_spectral(W, x, n, m, "truncate", 0.5 * S.min())
+    assert np.max(np.abs(keep - Ax)) <= 1e-12 * np.max(np.abs(Ax))
+    gone = oracle.apply_spectral(W, x, n, m, "truncate", S.max())
+    assert np.max(np.abs(gone)) == 0.0
