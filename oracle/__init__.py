@@ -29,6 +29,9 @@ complex128, with NumPy/LAPACK as the only library primitives:
   tie order.
 * ``dirichlet_operator`` -- the zero-padded (Dirichlet) operator the paper
   compares against (Sec. III "Boundary Conditions"; Sec. IV).
+* ``strided_operator``, ``crystal_symbols`` -- a stride-s convolution as a
+  map between crystal tori: the input has s*s*c_in points per cell of the
+  coarse lattice (Sec. III "Introduction to Lattices and Crystals").
 * ``apply_spectral``   -- ``y = U f(Sigma) V^* x`` for the identity, a
   pseudo-inverse or singular-value clipping, through the per-symbol SVD
   (Sec. III "Convolution Theorem": the global SVD is the lift of the
@@ -49,6 +52,8 @@ from .lfa64 import (  # noqa: F401
     lfa_svd,
     unrolled_operator,
     dirichlet_operator,
+    strided_operator,
+    crystal_symbols,
     fourier_basis,
     lift,
     spectral_factor,

@@ -170,6 +170,76 @@ def dirichlet_operator(W, n: int, m: int | None = None) -> np.ndarray:
 
 
 # ---------------------------------------------------------------------------
+# Strided convolutions: crystals with s*s points per unit cell
+# ---------------------------------------------------------------------------
+
+def strided_operator(W, n: int, m: int, s: int) -> np.ndarray:
+    """Dense matrix of the stride-s periodic convolution
+    ``y(x) = sum_y M_y f(s x + y)``: f on the n x m torus, y on the
+    (n/s) x (m/s) torus (s divides n and m), taps centred as for stride 1.
+
+    Rows ``(x1*(m/s) + x2)*c_out + o``, columns ``(z1*m + z2)*c_in + i``.
+    Definition-level brute force (small grids only).
+    """
+    if n % s or m % s:
+        raise ValueError("the stride must divide the grid")
+    W = np.asarray(W, dtype=np.float64)
+    c_out, c_in, kh, kw = W.shape
+    y = tap_offsets(kh, kw)
+    nc, mc = n // s, m // s
+    M = np.zeros((nc * mc * c_out, n * m * c_in), dtype=np.float64)
+    for x1 in range(nc):
+        for x2 in range(mc):
+            row0 = (x1 * mc + x2) * c_out
+            for a in range(kh):
+                for b in range(kw):
+                    z1 = (s * x1 + int(y[a, b, 0])) % n
+                    z2 = (s * x2 + int(y[a, b, 1])) % m
+                    col0 = (z1 * m + z2) * c_in
+                    M[row0:row0 + c_out, col0:col0 + c_in] += W[:, :, a, b]
+    return M
+
+
+def crystal_symbols(W, n: int, m: int, s: int) -> np.ndarray:
+    """Symbols of the stride-s convolution, the input read as a crystal on the
+    coarse lattice ``s Z^2`` with ``s*s*c_in`` points per unit cell and the
+    output as the coarse torus with ``c_out`` points per cell (Sec. III
+    "Introduction to Lattices and Crystals" and "Convolutional Mappings": a
+    crystal torus has |det Z| times the points of its cell).
+
+    The input point ``z = s X + d`` (cell X, position ``d = (d1, d2)`` in
+    ``[0, s)^2``, channel i) is column ``i*s*s + d1*s + d2``; the Fourier mode
+    of frequency k on the coarse torus ``T*_{n/s, m/s}`` takes the value
+    ``e^{2 pi i <k, X>}`` there (the cell's coordinates; adding the point's
+    offset ``d/s`` inside the cell multiplies each column by a unit phase,
+    which leaves sigma and U unchanged).  A tap at offset y reaches the point
+    ``d = y mod s`` of cell ``X + floor(y / s)``, so
+
+        A_k[o, i*s*s + d1*s + d2] = sum over taps y with y mod s = d of
+                                    M_y[o, i] e^{2 pi i <k, floor(y/s)>}.
+
+    Returns ``[n/s, m/s, c_out, s*s*c_in]`` complex128.
+    """
+    if n % s or m % s:
+        raise ValueError("the stride must divide the grid")
+    W = np.asarray(W, dtype=np.float64)
+    c_out, c_in, kh, kw = W.shape
+    y = tap_offsets(kh, kw)
+    nc, mc = n // s, m // s
+    A = np.zeros((nc, mc, c_out, c_in * s * s), dtype=np.complex128)
+    p = np.arange(nc)[:, None]
+    q = np.arange(mc)[None, :]
+    for a in range(kh):
+        for b in range(kw):
+            Y1, d1 = divmod(int(y[a, b, 0]), s)      # floor division, d in [0, s)
+            Y2, d2 = divmod(int(y[a, b, 1]), s)
+            ph = np.exp(2j * np.pi * (np.mod(p * Y1, nc) / nc + np.mod(q * Y2, mc) / mc))
+            cols = np.arange(c_in) * s * s + d1 * s + d2
+            A[:, :, :, cols] += ph[:, :, None, None] * W[None, None, :, :, a, b]
+    return A
+
+
+# ---------------------------------------------------------------------------
 # Global singular vectors (lift)
 # ---------------------------------------------------------------------------
 

@@ -492,3 +492,85 @@ def test_apply_pinv_inverts_full_rank_and_clip_above_max_is_identity():
     assert np.max(np.abs(keep - Ax)) <= 1e-12 * np.max(np.abs(Ax))
     gone = oracle.apply_spectral(W, x, n, m, "truncate", S.max())
     assert np.max(np.abs(gone)) == 0.0
+
+
+# --- strided convolutions as crystals -------------------------------------------
+
+def torch_strided_operator(W, n, m, s):
+    """The stride-s periodic convolution unrolled with torch: circular padding
+    as for stride 1, then conv2d with stride s, on every basis vector."""
+    W = torch.as_tensor(np.asarray(W, dtype=np.float64))
+    c_out, c_in, kh, kw = W.shape
+    N = n * m * c_in
+    eye = torch.eye(N, dtype=torch.float64).reshape(N, n, m, c_in).permute(0, 3, 1, 2)
+    pad = ((kw - 1) // 2, kw // 2, (kh - 1) // 2, kh // 2)
+    y = torch.nn.functional.conv2d(torch.nn.functional.pad(eye, pad, mode="circular"), W, stride=s)
+    assert tuple(y.shape[2:]) == (n // s, m // s)
+    return y.permute(0, 2, 3, 1).reshape(N, -1).T.numpy()
+
+
+STRIDED_CASES = [
+    # c_out, c_in, kh, kw, n, m, s
+    (3, 2, 3, 3, 8, 6, 2),
+    (2, 3, 3, 3, 6, 6, 3),
+    (4, 1, 7, 7, 8, 8, 2),      # stem-like 7x7, stride 2
+    (3, 2, 1, 1, 6, 4, 2),      # 1x1 shortcut, stride 2
+    (2, 2, 2, 4, 8, 8, 2),      # even extents
+    (2, 3, 3, 3, 5, 4, 1),      # stride 1
+]
+
+
+@pytest.mark.parametrize("case", STRIDED_CASES)
+def test_strided_operator_matches_torch(case):
+    c_out, c_in, kh, kw, n, m, s = case
+    W = np.random.default_rng(51).standard_normal((c_out, c_in, kh, kw))
+    np.testing.assert_allclose(oracle.strided_operator(W, n, m, s), torch_strided_operator(W, n, m, s),
+                               rtol=0, atol=1e-14)
+
+
+@pytest.mark.parametrize("case", STRIDED_CASES)
+def test_crystal_symbols_brute_force_and_modes(case):
+    """The singular values of the crystal symbols are those of the dense
+    strided operator (brute force), their count is (n/s)(m/s) min(c_out,
+    s^2 c_in), and the operator maps each crystal Fourier mode to the mode
+    of the same frequency on the output torus with coefficients A_k v: this
+    fixes the phase convention and the column order of the symbol."""
+    c_out, c_in, kh, kw, n, m, s = case
+    rng = np.random.default_rng(52)
+    W = rng.standard_normal((c_out, c_in, kh, kw))
+    A = oracle.crystal_symbols(W, n, m, s)
+    nc, mc = n // s, m // s
+    assert A.shape == (nc, mc, c_out, s * s * c_in)
+    S = np.linalg.svd(A, compute_uv=False)
+    D = oracle.strided_operator(W, n, m, s)
+    Sd = np.linalg.svd(D, compute_uv=False)
+    r = min(c_out, s * s * c_in)
+    assert S.size == nc * mc * r == min(D.shape)
+    np.testing.assert_allclose(np.sort(S.ravel()), np.sort(Sd), rtol=0, atol=1e-12 * Sd.max())
+    # modes: f(s X + d)[i] = e^{2 pi i <k, X>} v[i s^2 + d1 s + d2]
+    for (p, q) in [(0, 0), (1, 0), (nc - 1, mc - 1), (nc // 2, 1 % mc)]:
+        v = rng.standard_normal(s * s * c_in) + 1j * rng.standard_normal(s * s * c_in)
+        f = np.zeros((n, m, c_in), dtype=np.complex128)
+        for z1 in range(n):
+            for z2 in range(m):
+                X1, d1 = divmod(z1, s)
+                X2, d2 = divmod(z2, s)
+                ph = np.exp(2j * np.pi * (p * X1 / nc + q * X2 / mc))
+                f[z1, z2, :] = ph * v[np.arange(c_in) * s * s + d1 * s + d2]
+        y = (D @ f.ravel()).reshape(nc, mc, c_out)
+        x1, x2 = np.meshgrid(np.arange(nc), np.arange(mc), indexing="ij")
+        want = np.exp(2j * np.pi * (p * x1 / nc + q * x2 / mc))[:, :, None] * (A[p, q] @ v)[None, None, :]
+        assert np.max(np.abs(y - want)) <= 1e-12 * np.max(np.abs(want))
+
+
+def test_crystal_symbols_stride_one_and_parseval():
+    """Stride 1 gives the ordinary symbols; for any stride, sum sigma^2 =
+    (n/s)(m/s) ||W||_F^2 while the kernel fits the grid (every output point
+    reads each tap once, at distinct input points)."""
+    rng = np.random.default_rng(53)
+    W = rng.standard_normal((4, 3, 3, 3))
+    np.testing.assert_allclose(oracle.crystal_symbols(W, 6, 5, 1), oracle.symbols(W, 6, 5), rtol=0, atol=1e-14)
+    for (n, m, s) in [(8, 8, 2), (9, 6, 3), (8, 4, 4)]:
+        S = np.linalg.svd(oracle.crystal_symbols(W, n, m, s), compute_uv=False)
+        total = (n // s) * (m // s) * np.sum(W ** 2)
+        assert abs(np.sum(S ** 2) - total) <= 1e-12 * total
