@@ -292,6 +292,40 @@ int lfa_apply(const lfa_plan* plan, int32_t layer, const void* sigma, const void
 int lfa_lift(const lfa_plan* plan, int32_t layer, const void* U, const void* V, const int32_t* idx,
              int32_t count, void* u_hat, void* v_hat, void* stream);
 
+/* ---- strided layers as crystals ------------------------------------------ */
+
+/* A stride-s periodic convolution y(x) = sum_y M_y f(s x + y) (f on the
+ * n x m torus, y on the (n/s) x (m/s) torus, taps centred as for stride 1)
+ * is, with its input read as a crystal of s*s*c_in points per cell of the
+ * coarse lattice (Sec. III, "Introduction to Lattices and Crystals"), a
+ * stride-1 layer on the coarse torus.  The point d = (d1, d2) in [0, s)^2 of
+ * cell X, channel i, is its input channel i*s*s + d1*s + d2 (the order of
+ * torch's pixel_unshuffle), and a tap at offset y reaches it through the
+ * coarse offset floor(y / s), with d = y mod s.  Its symbols, SVD, top-k,
+ * gradient and spectral functions are those of that stride-1 layer, with
+ * the plan's limits applying to it (kh' <= n/s, channels up to 512). */
+enum lfa_crystal_direction {
+    LFA_CRYSTAL_FORWARD = 0,   /* W [c_out][c_in][kh][kw] -> Wc [c_out][s*s*c_in][kh'][kw']
+                                  (taps of Wc that no tap of W reaches are 0) */
+    LFA_CRYSTAL_ADJOINT = 1    /* Wc -> W: each tap read from its place in Wc,
+                                  the transpose of FORWARD (maps a gradient with
+                                  respect to Wc to one with respect to W)      */
+};
+
+/* The stride-1 layer of the crystal form of `layer` with stride `stride`:
+ * {c_out, s*s*c_in, kh', kw', n/s, m/s}, kh' = max(2L+1, 2R) for the coarse
+ * offsets [-L, R] of the taps (3x3, s = 2: 3x3; 7x7, s = 2: 5x5; 1x1: 1x1).
+ * Host only.  Errors: LFA_ERR_INVALID_ARG (NULL, stride < 1, dims <= 0,
+ * kh > n or kw > m, s not dividing n and m). */
+int lfa_crystal_layer(const lfa_layer* layer, int32_t stride, lfa_layer* out);
+
+/* Repack weights between a stride-s layer and its crystal form (device
+ * pointers in `dtype`, src and dst not overlapping; dst fully written).
+ * Stream-ordered.  Errors: those of lfa_crystal_layer, LFA_ERR_INVALID_ARG
+ * (dtype, direction, NULL pointer), LFA_ERR_HIP. */
+int lfa_crystal_weights(const lfa_layer* layer, int32_t stride, int32_t dtype, const void* src, void* dst,
+                        int32_t direction, void* stream);
+
 /* ---- tuning and diagnostics ------------------------------------------- */
 
 /* Time the candidate launch shapes of every layer on `stream` (running the

@@ -8,6 +8,8 @@ from .lfa import (  # noqa: F401
     LayerSpec,
     Plan,
     SigmaTopK,
+    crystal_layer,
+    crystal_weights,
     sigma_topk,
     svd,
     symbols,

@@ -24,6 +24,8 @@ LFA_SPECTRAL_IDENTITY = 0
 LFA_SPECTRAL_CLIP = 1
 LFA_SPECTRAL_PINV = 2
 LFA_SPECTRAL_TRUNCATE = 3
+LFA_CRYSTAL_FORWARD = 0
+LFA_CRYSTAL_ADJOINT = 1
 
 LFA_OK = 0
 LFA_ERR_INVALID_ARG = -1
@@ -72,6 +74,8 @@ SIGNATURES = {
     "lfa_apply_workspace_bytes": (I32, [P, I32, I32, ctypes.POINTER(SZ)]),
     "lfa_apply": (I32, [P, I32, P, P, P, I32, ctypes.c_double, P, P, I32, P, SZ, P]),
     "lfa_lift": (I32, [P, I32, P, P, P, I32, P, P, P]),
+    "lfa_crystal_layer": (I32, [ctypes.POINTER(LfaLayer), I32, ctypes.POINTER(LfaLayer)]),
+    "lfa_crystal_weights": (I32, [ctypes.POINTER(LfaLayer), I32, I32, P, P, I32, P]),
     "lfa_plan_queue_info": (I32, [P, I32, I32P, I32P]),
     "lfa_status_string": (ctypes.c_char_p, [I32]),
     "lfa_last_hip_error": (I32, []),

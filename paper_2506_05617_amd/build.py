@@ -20,7 +20,8 @@ BUILD_DIR = os.path.join(ROOT, "_build")
 LIB_NAME = "liblfa.so"
 LIB_PATH = os.path.join(PKG, LIB_NAME)
 
-HIP_SOURCES = ["jacobi.hip", "jacobi_wave.hip", "persistent.hip", "assemble.hip", "topk.hip", "apply.hip"]
+HIP_SOURCES = ["jacobi.hip", "jacobi_wave.hip", "persistent.hip", "assemble.hip", "topk.hip", "apply.hip",
+               "crystal.hip"]
 HOST_SOURCES = ["api.cpp"]
 
 # Packed FP32 instructions are disabled for all device code.

@@ -1091,6 +1091,52 @@ int lfa_apply(const lfa_plan* plan, int32_t layer, const void* sigma, const void
     return LFA_OK;
 }
 
+int lfa_crystal_layer(const lfa_layer* layer, int32_t stride, lfa_layer* out) {
+    if (!layer || !out || stride < 1) return LFA_ERR_INVALID_ARG;
+    const lfa_layer& l = *layer;
+    if (l.c_out <= 0 || l.c_in <= 0 || l.kh <= 0 || l.kw <= 0 || l.n <= 0 || l.m <= 0)
+        return LFA_ERR_INVALID_ARG;
+    if (l.kh > l.n || l.kw > l.m || l.n % stride || l.m % stride) return LFA_ERR_INVALID_ARG;
+    if ((long long)stride * stride * l.c_in > (1LL << 30)) return LFA_ERR_UNSUPPORTED;
+    // coarse offsets floor(y / s) of the taps y in [-(k-1)/2, k-1-(k-1)/2]
+    // span [-L, R]; the centred stride-1 window of extent max(2L+1, 2R)
+    // covers them
+    auto extent = [stride](int k) {
+        const int c = (k - 1) / 2;
+        const int L = (c + stride - 1) / stride, R = (k - 1 - c) / stride;
+        return std::max(2 * L + 1, 2 * R);
+    };
+    lfa_layer o{};
+    o.c_out = l.c_out;
+    o.c_in = stride * stride * l.c_in;
+    o.kh = extent(l.kh);
+    o.kw = extent(l.kw);
+    o.n = l.n / stride;
+    o.m = l.m / stride;
+    *out = o;
+    return LFA_OK;
+}
+
+int lfa_crystal_weights(const lfa_layer* layer, int32_t stride, int32_t dtype, const void* src, void* dst,
+                        int32_t direction, void* stream) {
+    lfa_layer c{};
+    LFA_TRY(lfa_crystal_layer(layer, stride, &c));
+    if (dtype != LFA_F32 && dtype != LFA_F64) return LFA_ERR_INVALID_ARG;
+    if (direction != LFA_CRYSTAL_FORWARD && direction != LFA_CRYSTAL_ADJOINT) return LFA_ERR_INVALID_ARG;
+    if (!src || !dst) return LFA_ERR_INVALID_ARG;
+    CrystalArgs a{};
+    a.c_out = layer->c_out;
+    a.c_in = layer->c_in;
+    a.kh = layer->kh;
+    a.kw = layer->kw;
+    a.stride = stride;
+    a.kh2 = c.kh;
+    a.kw2 = c.kw;
+    HIP_TRY(launch_crystal_weights(a, elem_bytes(dtype), src, dst, direction == LFA_CRYSTAL_ADJOINT,
+                                   static_cast<hipStream_t>(stream)));
+    return LFA_OK;
+}
+
 int lfa_lift(const lfa_plan* plan, int32_t layer, const void* U, const void* V, const int32_t* idx,
              int32_t count, void* u_hat, void* v_hat, void* stream) {
     if (!plan || layer < 0 || layer >= (int32_t)plan->layers.size() || count < 0) return LFA_ERR_INVALID_ARG;

@@ -205,6 +205,14 @@ __device__ int jacobi(const LayerDesc& d, const Shared<R>& s, int max_sweeps, do
     cplx<R>* __restrict__ G = s.G;
     cplx<R>* __restrict__ Q = s.Q;
 
+    // numerically zero columns (see negligible_sq): ||G||_F^2 before the sweeps
+    R fro = 0;
+    for (int e = tid; e < N * M; e += blockDim.x) {
+        const int j = e / M, i = e - (e / M) * M;
+        const cplx<R> v = G[(size_t)j * ldg + i];
+        fro = fma(v.x, v.x, fma(v.y, v.y, fro));
+    }
+    const double floor = negligible_sq<R>() * double(block_sum<R>(fro, s.red));
     if (tid == 0) s.flags[0] = s.flags[1] = s.flags[2] = 0;
     __syncthreads();
     converged = (N < 2);
@@ -238,6 +246,7 @@ __device__ int jacobi(const LayerDesc& d, const Shared<R>& s, int max_sweeps, do
                 gi = group_sum<R, L>(gi);
                 const double g = sqrt(double(gr) * double(gr) + double(gi) * double(gi));
                 if (!(g > tol * sqrt(double(al) * double(be)))) continue;
+                if (!(fmin(double(al), double(be)) > floor)) continue;
                 // Real 2x2 symmetric Schur step on [[al, g], [g, be]] after the
                 // phase of gamma is moved into column k.
                 const double zeta = (double(be) - double(al)) / (2.0 * g);
@@ -312,6 +321,15 @@ __device__ void finish(const SvdArgs<R>& a, const Shared<R>& s, int out_idx, int
         if (lane == 0) s.sig[j] = sqrt(acc);
     }
     __syncthreads();
+    {
+        // numerically zero columns (see negligible_sq) are reported as 0
+        R tot = 0;
+        for (int j = tid; j < N; j += nt) tot = fma(s.sig[j], s.sig[j], tot);
+        const double floor = negligible_sq<R>() * double(block_sum<R>(tot, s.red));
+        for (int j = tid; j < N; j += nt)
+            if (double(s.sig[j]) * double(s.sig[j]) <= floor) s.sig[j] = R(0);
+        __syncthreads();
+    }
     // rank sort: descending, ties by column index; NaN sorts as -1 so the
     // ranks always form a permutation
     for (int j = tid; j < N; j += nt) {
@@ -693,7 +711,8 @@ __device__ __forceinline__ void block_wave_sums(const BlockLds<R>& bl, F part, i
 // wave's copy) and publish it to the wave.  Returns true if this lane's pair
 // rotated.
 template <typename R>
-__device__ __forceinline__ bool block_rotations(const BlockLds<R>& bl, int par, int cj, int ck, double tol) {
+__device__ __forceinline__ bool block_rotations(const BlockLds<R>& bl, int par, int cj, int ck, double tol,
+                                                double floor) {
     constexpr int B = kBlk;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
     bool rot = false;
@@ -711,7 +730,7 @@ __device__ __forceinline__ bool block_rotations(const BlockLds<R>& bl, int par, 
         const double ddj = double(dj), ddk = double(dk);
         double al = s0 * ddj * ddj, be = s1 * ddk * ddk;
         quad<R> q;
-        rot = rotation_scaled<R>(al, be, s2 * ddj * ddk, s3 * ddj * ddk, tol, dj, dk, q);
+        rot = rotation_scaled<R>(al, be, s2 * ddj * ddk, s3 * ddj * ddk, tol, floor, dj, dk, q);
         dsc[cj] = dj;
         dsc[ck] = dk;
         bl.wprm[wave * B + lane] = q;
@@ -856,6 +875,20 @@ __device__ void block_sweeps(const LayerDesc& d, const Shared<R>& s, const Block
             }
         }
     };
+    // numerically zero columns (see negligible_sq): ||G||_F^2 of the symbol
+    // in the slot, the same value in every member of the team
+    double floor;
+    {
+        R fro = 0;
+        for (int c = 0; c < N; ++c)
+#pragma unroll
+            for (int r = 0; r < RPT; ++r)
+                if (grow[r]) {
+                    const cplx<R> v = s.G[(size_t)c * d.ldg + rows[r]];
+                    fro = fma(v.x, v.x, fma(v.y, v.y, fro));
+                }
+        floor = negligible_sq<R>() * double(block_sum<R>(fro, s.red));
+    }
     int sweeps = 0;
     bool converged = (N < 2);
     while (!converged && sweeps < max_sweeps) {
@@ -894,7 +927,7 @@ __device__ void block_sweeps(const LayerDesc& d, const Shared<R>& s, const Block
                     // columns of pair `lane` (lanes >= B compute nothing)
                     const int pp = lane < B / 2 ? lane : lane - B / 2, off = lane < B / 2 ? 0 : B;
                     const int cj = off + col_at<B>(pp, step), ck = off + col_at<B>(B - 1 - pp, step);
-                    rotated |= block_rotations<R>(bl, par, cj, ck, tol);
+                    rotated |= block_rotations<R>(bl, par, cj, ck, tol, floor);
                 }
                 par ^= 1;
                 const quad<R>* prm = bl.wprm + wave * B;
@@ -955,7 +988,7 @@ __device__ void block_sweeps(const LayerDesc& d, const Shared<R>& s, const Block
                     {
                         const int cj = lane < B ? lane : 0;
                         const int ck = B + ((cj + t) & (B - 1));
-                        rotated |= block_rotations<R>(bl, par, cj, ck, tol);
+                        rotated |= block_rotations<R>(bl, par, cj, ck, tol, floor);
                     }
                     par ^= 1;
                     const quad<R>* prm = bl.wprm + wave * B;
@@ -1388,7 +1421,13 @@ __device__ bool wave_group(const SvdArgs<R>& a, char* lds_raw, int base, int tid
                     fold_column_norms<R, NC, ML>(g, part, sym, row);
                     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
                     __builtin_amdgcn_wave_barrier();
-                    if (row < NC) nrm[sym * NC + row] = double(column_norm<R, NC, ML>(part, sym, row));
+                    // numerically zero columns (see negligible_sq; the
+                    // symbol's ||G||_F^2 is the sum over its lanes) start the
+                    // sweep with tracked norm 0, which keeps them out of
+                    // every rotation of the sweep (floor 0 below)
+                    const double cn = row < NC ? double(column_norm<R, NC, ML>(part, sym, row)) : 0.0;
+                    const double fl = negligible_sq<R>() * xsum_range<1, ML>(cn);
+                    if (row < NC) nrm[sym * NC + row] = cn > fl ? cn : 0.0;
                 }
                 __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
                 __builtin_amdgcn_wave_barrier();
@@ -1443,7 +1482,7 @@ __device__ bool wave_group(const SvdArgs<R>& a, char* lds_raw, int base, int tid
                     R dj = dcur[sym * NC + cj], dk = dcur[sym * NC + ck];
                     const double gs = double(dj) * double(dk);   // true gamma = d_j d_k gamma
                     quad<R> q;
-                    rotated |= rotation_scaled<R>(al, be, double(s0) * gs, double(s1) * gs, tol, dj, dk, q);
+                    rotated |= rotation_scaled<R>(al, be, double(s0) * gs, double(s1) * gs, tol, 0.0, dj, dk, q);
                     // the LP lanes of a pair hold identical sums, parameters,
                     // norms and scales: all of them store (same value, same
                     // address)
@@ -1521,7 +1560,12 @@ __device__ bool wave_group(const SvdArgs<R>& a, char* lds_raw, int base, int tid
     // column norms: |g_j|^2 folded across lanes, then summed over the holders
     if (wave == 0) fold_column_norms<R, NC, ML>(g, part, sym, row);
     wsync(solo);
-    if (wave == 0 && row < NC) sigs[sym * NC + row] = sqrt(column_norm<R, NC, ML>(part, sym, row));
+    if (wave == 0) {
+        // numerically zero columns (see negligible_sq) are reported as 0
+        const R cn = row < NC ? column_norm<R, NC, ML>(part, sym, row) : R(0);
+        const double fl = negligible_sq<R>() * xsum_range<1, ML>(double(cn));
+        if (row < NC) sigs[sym * NC + row] = double(cn) <= fl ? R(0) : sqrt(cn);
+    }
     wsync(solo);
     // rank sort of the N real columns: descending, ties by index
     if (wave == 0 && row < N) {

@@ -94,16 +94,32 @@ __device__ __forceinline__ quad<R> rotation(R al, R be, R gr, R gi, double tol) 
     return q;
 }
 
+// Numerically zero columns.  A symbol of rank below its column count keeps,
+// in the columns that Jacobi drives to zero, rounding noise that every
+// rotation with a nonzero column renews; its direction stays arbitrary, so
+// the relative threshold below keeps rotating it until it underflows.  A
+// column whose squared norm is at most (2u)^2 ||G||_F^2 (u the unit roundoff
+// of R; ||G||_F is invariant under the rotations) therefore takes part in no
+// rotation, and its singular value is reported as 0 (an error of at most
+// 2u ||G||_F, below the normwise accuracy of the method).
+template <typename R>
+__host__ __device__ constexpr double negligible_sq() {
+    return sizeof(R) == 4 ? 0x1p-46 : 0x1p-104;
+}
+
 // As rotation(), from squared column norms al = |g_j|^2 and be = |g_k|^2 that
 // the caller tracks instead of recomputing: the rotation maps them to
 // al - t |gamma| and be + t |gamma| (t = tan of the rotation angle), which
-// are returned through al and be (al clamped at 0; unchanged without a
-// rotation).
+// are returned through al and be (both clamped at 0: tracked norms drift by
+// rounding, and a negative one would pass the threshold test with gamma = 0;
+// unchanged without a rotation).  No rotation either when a column is
+// numerically zero: min(al, be) <= floor (negligible_sq() ||G||_F^2).
 template <typename R>
-__device__ __forceinline__ quad<R> rotation_tracked(double& al, double& be, R gr, R gi, double tol) {
+__device__ __forceinline__ quad<R> rotation_tracked(double& al, double& be, R gr, R gi, double tol,
+                                                    double floor) {
     const double g2 = double(gr) * double(gr) + double(gi) * double(gi);
     quad<R> q = {R(1), R(0), R(0), R(0)};
-    if (!(g2 > tol * tol * (al * be))) return q;
+    if (!(g2 > tol * tol * (al * be)) || !(fmin(al, be) > floor)) return q;
     double rg, t, c;
     if constexpr (sizeof(R) == 4) {
         rg = __builtin_amdgcn_rsq(g2);                                // 1/|gamma|
@@ -122,7 +138,7 @@ __device__ __forceinline__ quad<R> rotation_tracked(double& al, double& be, R gr
     const double sn = c * t * rg;
     const double tg = t * g2 * rg;                                    // t |gamma|
     al = fmax(al - tg, 0.0);
-    be = be + tg;
+    be = fmax(be + tg, 0.0);
     q = {R(c), R(sn * double(gr)), R(-sn * double(gi)), R(1)};
     return q;
 }
@@ -135,13 +151,14 @@ __device__ __forceinline__ quad<R> rotation_tracked(double& al, double& be, R gr
 // tau2 = conj(tau) d_j/d_k): two complex multiply-adds per row instead of
 // four real-by-complex products.  Returns (tau1, tau2) in q, updates the
 // tracked squared norms (as rotation_tracked) and the scales, or leaves
-// everything unchanged and returns the identity (zeros) below the threshold.
+// everything unchanged and returns the identity (zeros) below the threshold
+// or for a numerically zero column (min(al, be) <= floor).
 template <typename R>
 __device__ __forceinline__ bool rotation_scaled(double& al, double& be, double gr, double gi, double tol,
-                                                R& dj, R& dk, quad<R>& q) {
+                                                double floor, R& dj, R& dk, quad<R>& q) {
     q = {R(0), R(0), R(0), R(0)};
     const double g2 = gr * gr + gi * gi;
-    if (!(g2 > tol * tol * (al * be))) return false;
+    if (!(g2 > tol * tol * (al * be)) || !(fmin(al, be) > floor)) return false;
     double rg, t, c, rjk, rkj;
     if constexpr (sizeof(R) == 4) {
         // The tangent t only selects the rotation and may be approximate.
@@ -174,7 +191,7 @@ __device__ __forceinline__ bool rotation_scaled(double& al, double& be, double g
     }
     const double tg = t * g2 * rg;                                    // t |gamma|
     al = fmax(al - tg, 0.0);
-    be = be + tg;
+    be = fmax(be + tg, 0.0);
     const double tr = t * gr * rg, ti = -t * gi * rg;                 // tau = t conj(gamma)/|gamma|
     q = {R(tr * rjk), R(ti * rjk), R(tr * rkj), R(-ti * rkj)};
     dj = R(c * double(dj));
@@ -337,6 +354,15 @@ struct LiftArgs {
 };
 hipError_t launch_lift_f32(const LiftArgs& a, hipStream_t s);
 hipError_t launch_lift_f64(const LiftArgs& a, hipStream_t s);
+
+// A stride-`stride` layer (c_out, c_in, kh, kw) and the stride-1 layer of its
+// crystal form (c_out, stride^2 c_in, kh2, kw2) on the coarse torus.
+struct CrystalArgs {
+    int c_out, c_in, kh, kw, stride, kh2, kw2;
+};
+// Forward: W -> Wc (the crystal layer's weights); adjoint: Wc -> W.
+hipError_t launch_crystal_weights(const CrystalArgs& a, int elem_bytes, const void* src, void* dst, bool adjoint,
+                                  hipStream_t s);
 
 size_t lds_bytes_for(const LayerDesc& d, bool accumulate, int elem_bytes);
 

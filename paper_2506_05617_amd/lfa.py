@@ -360,6 +360,36 @@ def svd(W, n, m=None, compute_uv=False, asm=None, return_info=False):
     return (out, info[0]) if return_info else out
 
 
+def crystal_layer(spec: LayerSpec, stride: int) -> LayerSpec:
+    """The stride-1 layer on the coarse torus of a stride-`stride` layer read
+    as a crystal (lfa_crystal_layer): (c_out, s*s*c_in, kh', kw', n/s, m/s)."""
+    lib = _lib.load()
+    out = _lib.LfaLayer()
+    src = _lib.LfaLayer(spec.c_out, spec.c_in, spec.kh, spec.kw, spec.n, spec.m)
+    check(lib.lfa_crystal_layer(ctypes.byref(src), stride, ctypes.byref(out)), "lfa_crystal_layer")
+    return LayerSpec(out.c_out, out.c_in, out.kh, out.kw, out.n, out.m)
+
+
+def crystal_weights(W, spec: LayerSpec, stride: int, adjoint=False):
+    """Weights of the crystal form of a stride-`stride` layer (lfa_crystal_weights):
+    ``W [c_out, c_in, kh, kw] -> Wc [c_out, s*s*c_in, kh', kw']``, or with
+    ``adjoint`` the transpose ``Wc -> W`` (for gradients)."""
+    lib = _lib.load()
+    c = crystal_layer(spec, stride)
+    shape_in, shape_out = (spec.c_out, spec.c_in, spec.kh, spec.kw), (c.c_out, c.c_in, c.kh, c.kw)
+    if adjoint:
+        shape_in, shape_out = shape_out, shape_in
+    if tuple(W.shape) != shape_in or not W.is_contiguous() or W.device.type != "cuda":
+        raise ValueError(f"expected a contiguous GPU tensor of shape {shape_in}")
+    out = torch.empty(shape_out, dtype=W.dtype, device=W.device)
+    src = _lib.LfaLayer(spec.c_out, spec.c_in, spec.kh, spec.kw, spec.n, spec.m)
+    check(lib.lfa_crystal_weights(ctypes.byref(src), stride, _dtype_code(W.dtype), ctypes.c_void_p(W.data_ptr()),
+                                  ctypes.c_void_p(out.data_ptr()),
+                                  _lib.LFA_CRYSTAL_ADJOINT if adjoint else _lib.LFA_CRYSTAL_FORWARD,
+                                  _stream_ptr()), "lfa_crystal_weights")
+    return out
+
+
 class SigmaTopK(torch.autograd.Function):
     """Per-layer top-k singular values of a stack of periodic convolutions,
     differentiable in the weights: forward = one persistent sigma-only SVD

@@ -117,3 +117,40 @@ def test_workspace_and_launch_shapes():
     assert big.ws_bytes > 512 * 256 * 8
     wide = lfa.Plan([lfa.LayerSpec(3, 64, 3, 3, 8, 8)])     # c_out < c_in: works on A^H
     assert wide.launch_shape(0)[0] == 8
+
+
+@needs_lib
+def test_crystal_layer_shapes_and_errors():
+    """lfa_crystal_layer (host only): the stride-1 layer of a strided layer's
+    crystal form; the kernel extent covers the coarse tap offsets
+    floor(y / s) of the centred taps y, which is checked here by listing
+    them."""
+    lib = lfa.load()
+
+    def call(spec, s):
+        out = _lib.LfaLayer()
+        st = lib.lfa_crystal_layer(ctypes.byref(_lib.LfaLayer(*spec)), s, ctypes.byref(out))
+        return st, (out.c_out, out.c_in, out.kh, out.kw, out.n, out.m)
+
+    for spec, s in [((64, 64, 3, 3, 32, 32), 2), ((64, 3, 7, 7, 224, 224), 2), ((128, 64, 1, 1, 32, 32), 2),
+                    ((8, 4, 4, 2, 12, 12), 3), ((8, 4, 3, 3, 10, 6), 1), ((8, 4, 5, 5, 20, 20), 4)]:
+        st, got = call(spec, s)
+        assert st == 0
+        c_out, c_in, kh, kw, n, m = spec
+        assert got[:2] == (c_out, s * s * c_in) and got[4:] == (n // s, m // s)
+        for k, k2 in ((kh, got[2]), (kw, got[3])):
+            Y = [(t - (k - 1) // 2) // s for t in range(k)]
+            lo, hi = -((k2 - 1) // 2), k2 // 2
+            assert lo <= min(Y) and max(Y) <= hi
+            assert k2 == 1 or lo == min(Y) or hi == max(Y)   # no larger than needed
+        if s == 1:
+            assert got == spec
+    assert call((64, 64, 3, 3, 32, 32), 2)[1][2:4] == (3, 3)
+    assert call((64, 3, 7, 7, 224, 224), 2)[1][2:4] == (5, 5)
+    for spec, s in [((4, 4, 3, 3, 9, 8), 2), ((4, 4, 3, 3, 8, 8), 0), ((4, 4, 9, 3, 8, 8), 2),
+                    ((0, 4, 3, 3, 8, 8), 2)]:
+        assert call(spec, s)[0] == _lib.LFA_ERR_INVALID_ARG
+    assert lib.lfa_crystal_weights(ctypes.byref(_lib.LfaLayer(4, 4, 3, 3, 8, 8)), 2, 0, None, None, 0, None) \
+        == _lib.LFA_ERR_INVALID_ARG
+    assert lib.lfa_crystal_weights(ctypes.byref(_lib.LfaLayer(4, 4, 3, 3, 8, 8)), 2, 0, ctypes.c_void_p(8),
+                                   ctypes.c_void_p(8), 7, None) == _lib.LFA_ERR_INVALID_ARG

@@ -601,3 +601,81 @@ def test_lift_matches_oracle_and_maps_v_to_sigma_u(case):
     only_u, none_v = plan.lift(0, U[0], None, picks[:2].contiguous())
     torch.cuda.synchronize()
     assert none_v is None and torch.equal(only_u, uh[:2])
+
+
+# ---------------------------------------------------------------- crystals --
+
+CRYSTAL_CASES = [
+    # c_out, c_in, kh, kw, n, m, stride, dtype
+    (16, 8, 3, 3, 16, 16, 2, np.float32),       # 3x3 stride 2 (downsampling)
+    (32, 3, 7, 7, 32, 32, 2, np.float32),       # 7x7 stride 2 stem
+    (24, 16, 1, 1, 12, 8, 2, np.float32),       # 1x1 stride-2 shortcut
+    (8, 4, 3, 3, 18, 12, 3, np.float32),
+    (12, 6, 4, 4, 16, 16, 2, np.float64),       # even extent
+    (64, 16, 3, 3, 16, 16, 2, np.float32),      # 64 x 64 symbols
+]
+
+
+def _crystal(case):
+    c_out, c_in, kh, kw, n, m, s, dt = case
+    spec = lfa().LayerSpec(c_out, c_in, kh, kw, n, m)
+    rng = np.random.default_rng(61)
+    W = (rng.standard_normal((c_out, c_in, kh, kw)) / np.sqrt(c_in * kh * kw)).astype(dt)
+    return spec, s, W, lfa().crystal_layer(spec, s)
+
+
+@pytest.mark.parametrize("case", CRYSTAL_CASES)
+def test_crystal_symbols_and_sigma_match_oracle(case):
+    """A strided layer through its crystal form: lfa_crystal_weights, then
+    the stride-1 symbols and SVD of the coarse layer, against the oracle's
+    crystal symbols (defined from the strided operator, not from a repack)
+    and their LAPACK SVD.  Symbols within 1e-6 (FP32) / 1e-13 (FP64) of their
+    largest entry; sigma within the usual gates; the adjoint repack returns W."""
+    spec, s, W, c = _crystal(case)
+    banner(f"crystal {case}")
+    tdt = torch.float32 if W.dtype == np.float32 else torch.float64
+    Wc = lfa().crystal_weights(_w(W), spec, s)
+    A = lfa().symbols(Wc, c.n, c.m)
+    back = lfa().crystal_weights(Wc, spec, s, adjoint=True)
+    torch.cuda.synchronize()
+    assert torch.equal(back, _w(W))
+    A_ref = oracle.crystal_symbols(W.astype(np.float64), spec.n, spec.m, s)
+    tol = 1e-6 if tdt == torch.float32 else 1e-13
+    assert np.max(np.abs(to_np(A) - A_ref)) <= tol * np.max(np.abs(A_ref))
+    S = lfa().svd(Wc, c.n, c.m)
+    torch.cuda.synchronize()
+    S_ref = np.linalg.svd(A_ref, compute_uv=False)
+    e = oracle.sigma_error(to_np(S), S_ref)
+    assert e <= sigma_gate(tdt), f"{case}: sigma error {e:.3e}"
+
+
+def test_crystal_sigma_grad_matches_finite_differences():
+    """Gradient of the sum of a strided layer's top-4 singular values: the
+    coarse layer's adjoint kernel (lfa_sigma_grad on the crystal weights),
+    pulled back to W by the adjoint repack, against central differences of
+    the oracle's crystal-symbol singular values at the same picks (FP64)."""
+    case = (8, 4, 3, 3, 12, 12, 2, np.float64)
+    spec, s, W, c = _crystal(case)
+    banner(f"crystal grad {case}")
+    plan = lfa().Plan([c], torch.float64, True, True)
+    Wc = lfa().crystal_weights(_w(W), spec, s)
+    S, _, _, _ = plan.svd([Wc])
+    vals, idx = plan.topk(S, 4)
+    grad = torch.ones(1, 4, dtype=torch.float64, device=DEV)
+    dWc = plan.sigma_grad([Wc], idx, grad)[0]
+    dW = to_np(lfa().crystal_weights(dWc.contiguous(), spec, s, adjoint=True))
+    torch.cuda.synchronize()
+    picks = idx[0].cpu().numpy()
+
+    def loss(Wx):
+        A = oracle.crystal_symbols(Wx, spec.n, spec.m, s)
+        Sx = np.linalg.svd(A, compute_uv=False)
+        return sum(Sx[p, q, j] for p, q, j in picks)
+
+    rng = np.random.default_rng(62)
+    for _ in range(3):
+        D = rng.standard_normal(W.shape)
+        h = 1e-6 * np.linalg.norm(W) / np.linalg.norm(D)
+        fd = (loss(W + h * D) - loss(W - h * D)) / (2 * h)
+        an = float(np.sum(dW * D))
+        assert abs(an - fd) <= 1e-6 * max(1.0, abs(fd)), (an, fd)
