@@ -98,6 +98,28 @@ def event_times(fn, steps, warmup):
     return wall, [s.elapsed_time(e) for s, e in zip(starts, ends)]
 
 
+def run_strided(L, stride, W, dev, steps, warmup):
+    """A stride-`stride` layer through its crystal form: weight repack and
+    SVD (sigma + U + V) of the coarse stride-1 layer, per step."""
+    Wt = torch.from_numpy(W).to(dev)
+    spec = lfa.LayerSpec(L.c_out, L.c_in, L.kh, L.kw, L.n, L.m)
+    c = lfa.crystal_layer(spec, stride)
+    plan = lfa.Plan([c], torch.float32, want_u=True, want_v=True)
+    S, U, V = plan._alloc_outputs(dev, True, True)
+    info = torch.zeros(1, 4, dtype=torch.int32, device=dev)
+
+    def step():
+        Wc = lfa.crystal_weights(Wt, spec, stride)
+        plan.svd([Wc], info=info, out=(S, U, V))
+
+    wall, ev = event_times(step, steps, warmup)
+    inf = info.cpu().numpy()[0]
+    ms = wall * 1e3 / steps
+    nsig = c.n * c.m * min(c.c_out, c.c_in)
+    return dict(layer=L, stride=stride, crystal=c, W=W, S=S[0], ms=ms, kernel_ms=float(np.mean(ev)),
+                info=[int(x) for x in inf], sigma_per_s=nsig / (ms * 1e-3))
+
+
 def run_layer(L, W, dev, vectors, steps, warmup, asm=None, dtype=torch.float32):
     Wt = torch.from_numpy(W).to(dev)
     spec = lfa.LayerSpec(L.c_out, L.c_in, L.kh, L.kw, L.n, L.m)
@@ -271,6 +293,13 @@ def cpu_leg(head, extra):
                 ref = oracle.apply_spectral(res["W"].astype(np.float64), res["x"].cpu().numpy().astype(np.float64),
                                             Lx.n, Lx.m, res["kind"], res["param"])
                 errors[name + "_rel_max"] = float(np.max(np.abs(res["y"].cpu().numpy() - ref)) / np.max(np.abs(ref)))
+            elif name.startswith("strided"):
+                Lx, s = res["layer"], res["stride"]
+                nc, mc = Lx.n // s, Lx.m // s
+                fr = np.stack([rng.integers(0, nc, 32), rng.integers(0, mc, 32)], axis=1)
+                A = oracle.crystal_symbols(res["W"].astype(np.float64), Lx.n, Lx.m, s)[fr[:, 0], fr[:, 1]]
+                ref = np.linalg.svd(A, compute_uv=False)
+                errors[name] = oracle.sigma_error(res["S"].cpu().numpy()[fr[:, 0], fr[:, 1]], ref)
             elif name.startswith("assembly"):
                 fr = np.stack([rng.integers(0, res["L"].n, 32), rng.integers(0, res["L"].m, 32)], axis=1)
                 ref = oracle.symbols(res["W"].astype(np.float64), res["L"].n, res["L"].m, fr)
@@ -299,8 +328,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--quick", action="store_true", help="headline workload only")
     ap.add_argument("--only", default=None,
-                    help="run one extra workload after the headline: apply, fp64, rect, stack, large, "
-                         "assembly, paper")
+                    help="run one extra workload after the headline: apply, fp64, rect, strided, stack, "
+                         "large, assembly, paper")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the LFA SVD shards over frequencies, but this build "
@@ -372,6 +401,17 @@ def main():
         extra["rank_one_512x256"] = r
         wl["rank_one_512x256_uv"] = dict(ms=r["ms"], sigma_per_s=r["sigma_per_s"], sweeps=r["info"][1:3])
         note("rectangular layers done")
+    if sel("strided"):
+        # stride-2 layers as crystals (s*s input points per coarse cell)
+        for name, Ls, s, Ws in workloads.resnet18_downsampling():
+            r = run_strided(Ls, s, Ws, dev, reps * 3, 1)
+            key = "strided_" + name
+            extra[key] = r
+            c = r["crystal"]
+            wl[key + "_64to128_32x32_s2_uv"] = dict(
+                ms=r["ms"], sigma_per_s=r["sigma_per_s"], sweeps=r["info"][1:3],
+                crystal_layer=[c.c_out, c.c_in, c.kh, c.kw, c.n, c.m])
+        note("strided layers done")
     if sel("stack"):
         st = bench_stack(dev, reps)
         extra["stack"] = st

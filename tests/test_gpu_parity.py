@@ -679,3 +679,55 @@ def test_crystal_sigma_grad_matches_finite_differences():
         fd = (loss(W + h * D) - loss(W - h * D)) / (2 * h)
         an = float(np.sum(dW * D))
         assert abs(an - fd) <= 1e-6 * max(1.0, abs(fd)), (an, fd)
+
+
+# ------------------------------------------------- rank-deficient symbols --
+
+RANK_DEFICIENT_CASES = [
+    # c_out, c_in, kh, n, m, z (channels of the long side kept), dtype, vectors
+    (64, 24, 1, 6, 4, 16, np.float32, False),     # register kernel, NC 32 > N 24
+    (64, 24, 1, 6, 4, 16, np.float32, True),
+    (24, 64, 3, 6, 4, 16, np.float32, False),     # wide (G = A^H)
+    (64, 24, 1, 6, 4, 16, np.float64, True),
+    (160, 96, 1, 4, 4, 40, np.float32, True),     # blocked kernel, rank 40 of 96
+    (160, 96, 1, 4, 4, 40, np.float64, False),
+]
+
+
+@pytest.mark.parametrize("case", RANK_DEFICIENT_CASES)
+def test_rank_deficient_symbols_converge(case):
+    """Symbols of rank z below their column count (the channels past z on the
+    long side of the symbol are zero: zero rows of the working matrix, whose
+    columns then span z dimensions only): every symbol converges in a normal
+    number of sweeps, sigma is finite and within the gate, the missing
+    singular values are exactly 0, and with vectors U and V are orthonormal
+    (zero columns completed).  Regression: the noise left in the vanishing
+    columns used to be rotated until it underflowed (FP32 turned it into
+    NaN; FP64 ran to the sweep limit)."""
+    c_out, c_in, kh, n, m, z, dt, vec = case
+    banner(f"rank-deficient {case}")
+    rng = np.random.default_rng(71)
+    W = (rng.standard_normal((c_out, c_in, kh, kh)) / np.sqrt(c_in * kh * kh)).astype(dt)
+    if c_out >= c_in:
+        W[z:, :] = 0
+    else:
+        W[:, z:] = 0
+    tdt = torch.float32 if dt == np.float32 else torch.float64
+    plan = lfa().Plan([lfa().LayerSpec(c_out, c_in, kh, kh, n, m)], tdt, vec, vec)
+    S, U, V, info = plan.svd([_w(W)])
+    torch.cuda.synchronize()
+    info = to_np(info[0])
+    S = to_np(S[0])
+    assert np.all(np.isfinite(S)) and info[lfa()._lib.LFA_INFO_NONFINITE] == 0
+    # the vanishing columns shrink geometrically (by about 5x per sweep in the
+    # blocked kernel's block order: about 12 sweeps in FP32 and 24 in FP64
+    # for these shapes, matching a CPU emulation of that order; 8 to 11 in
+    # the register kernel); the limit is 40
+    limit = 16 if dt == np.float32 else 30
+    assert info[lfa()._lib.LFA_INFO_NONCONVERGED] == 0 and info[lfa()._lib.LFA_INFO_MAX_SWEEPS] <= limit, info
+    A = oracle.symbols(W.astype(np.float64), n, m)
+    S_ref = oracle.svd_symbols(A, compute_uv=False)
+    assert oracle.sigma_error(S, S_ref) <= sigma_gate(tdt)
+    assert np.all(S[..., z:] == 0)
+    if vec:
+        check_vectors(A, S, to_np(U[0]), to_np(V[0]), tdt, "rank-deficient")

@@ -138,6 +138,19 @@ def paper_scale(n: int, seed: int = 6):
     return L, W
 
 
+def resnet18_downsampling(seed: int = 7):
+    """The stride-2 layers where ResNet-18 on 32x32 inputs first halves its
+    grid: the 3x3 convolution 64 -> 128 and the 1x1 shortcut 64 -> 128, both
+    on the 32x32 input grid, float32 He-normal.  Returns a list of
+    (name, layer, stride, W)."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for name, k in (("3x3", 3), ("1x1_shortcut", 1)):
+        L = Layer(128, 64, k, k, 32, 32)
+        out.append((name, L, 2, gaussian(rng, (128, 64, k, k), np.sqrt(2.0 / (64 * k * k)), np.float32)))
+    return out
+
+
 def random_layer(c_out, c_in, kh, kw, n, m=None, seed=0, dtype=np.float32):
     """Generic N(0, 1/(kh*kw*c_in)) layer for parity tests."""
     m = n if m is None else m
