@@ -730,7 +730,8 @@ __device__ __forceinline__ bool block_rotations(const BlockLds<R>& bl, int par, 
         const double ddj = double(dj), ddk = double(dk);
         double al = s0 * ddj * ddj, be = s1 * ddk * ddk;
         quad<R> q;
-        rot = rotation_scaled<R>(al, be, s2 * ddj * ddk, s3 * ddj * ddk, tol, floor, dj, dk, q);
+        // a sweep of small rotations only ends the symbol's sweeps
+        rot = rotation_scaled<R>(al, be, s2 * ddj * ddk, s3 * ddj * ddk, tol, floor, dj, dk, q) > 1;
         dsc[cj] = dj;
         dsc[ck] = dk;
         bl.wprm[wave * B + lane] = q;
@@ -1482,7 +1483,9 @@ __device__ bool wave_group(const SvdArgs<R>& a, char* lds_raw, int base, int tid
                     R dj = dcur[sym * NC + cj], dk = dcur[sym * NC + ck];
                     const double gs = double(dj) * double(dk);   // true gamma = d_j d_k gamma
                     quad<R> q;
-                    rotated |= rotation_scaled<R>(al, be, double(s0) * gs, double(s1) * gs, tol, 0.0, dj, dk, q);
+                    // only rotations larger than kappa keep the symbol
+                    // sweeping (see rotation_scaled)
+                    rotated |= rotation_scaled<R>(al, be, double(s0) * gs, double(s1) * gs, tol, 0.0, dj, dk, q) > 1;
                     // the LP lanes of a pair hold identical sums, parameters,
                     // norms and scales: all of them store (same value, same
                     // address)

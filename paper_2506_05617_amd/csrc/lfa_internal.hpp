@@ -153,12 +153,19 @@ __device__ __forceinline__ quad<R> rotation_tracked(double& al, double& be, R gr
 // tracked squared norms (as rotation_tracked) and the scales, or leaves
 // everything unchanged and returns the identity (zeros) below the threshold
 // or for a numerically zero column (min(al, be) <= floor).
+//
+// Result: 0 without a rotation, 1 for a rotation with |t| <= kappa, 2 for a
+// larger one, kappa = sqrt(tol)/4.  A sweep whose rotations all have
+// |t| <= kappa leaves the columns orthogonal to the threshold (each small
+// rotation changes the other inner products of its columns by O(kappa) times
+// those, which are themselves at most O(kappa)), so the rotation-free sweep
+// that would confirm it can be skipped.
 template <typename R>
-__device__ __forceinline__ bool rotation_scaled(double& al, double& be, double gr, double gi, double tol,
-                                                double floor, R& dj, R& dk, quad<R>& q) {
+__device__ __forceinline__ int rotation_scaled(double& al, double& be, double gr, double gi, double tol,
+                                               double floor, R& dj, R& dk, quad<R>& q) {
     q = {R(0), R(0), R(0), R(0)};
     const double g2 = gr * gr + gi * gi;
-    if (!(g2 > tol * tol * (al * be)) || !(fmin(al, be) > floor)) return false;
+    if (!(g2 > tol * tol * (al * be)) || !(fmin(al, be) > floor)) return 0;
     double rg, t, c, rjk, rkj;
     if constexpr (sizeof(R) == 4) {
         // The tangent t only selects the rotation and may be approximate.
@@ -196,7 +203,7 @@ __device__ __forceinline__ bool rotation_scaled(double& al, double& be, double g
     q = {R(tr * rjk), R(ti * rjk), R(tr * rkj), R(-ti * rkj)};
     dj = R(c * double(dj));
     dk = R(c * double(dk));
-    return true;
+    return 16.0 * t * t > tol ? 2 : 1;
 }
 
 // g_j' = g_j - tau1 g_k, g_k' = g_k + tau2 g_j (see rotation_scaled).
