@@ -122,24 +122,88 @@ __global__ void __launch_bounds__(kDftThreads) dft_axis_lds_kernel(const void* i
     }
 }
 
-// One work-group (64 threads) per frequency k, images in chunks of BC:
+// Power-of-two L: the same transform as a radix-2 Stockham FFT in LDS (the
+// self-sorting form: every stage reads one buffer and writes the other, and
+// the result is in natural order).  Stage with sub-transform length n and
+// stride s = L / n, butterfly i = p s + q (p < n/2, q < s):
+//   Y[q + s (2p)]     = X[q + s p] + X[q + s (p + n/2)]
+//   Y[q + s (2p + 1)] = (X[q + s p] - X[q + s (p + n/2)]) w^(p s),  w = e^{sign 2 pi i / L}
+// LPB = max(1, 512 / L) lines per work-group, L/2 butterflies per line and
+// stage shared by the 256 threads.
+template <typename R, bool REAL_IN, bool REAL_OUT>
+__global__ void __launch_bounds__(kDftThreads) fft_axis_lds_kernel(const void* in_v, void* out_v, long long lines,
+                                                                   int L, int logL, int lpb, AxisMap mp,
+                                                                   const double* tw, int sign, R scale) {
+    extern __shared__ __align__(16) char lds[];
+    cplx<R>* w = reinterpret_cast<cplx<R>*>(lds);      // [L] e^{sign 2 pi i j / L}
+    cplx<R>* buf0 = w + L;                             // [lpb][L]
+    cplx<R>* buf1 = buf0 + lpb * L;                    // [lpb][L]
+    const int tid = threadIdx.x;
+    const long long line0 = (long long)blockIdx.x * lpb;
+    for (int j = tid; j < L; j += kDftThreads) w[j] = {R(tw[2 * j]), R(sign) * R(tw[2 * j + 1])};
+    for (int e = tid; e < lpb * L; e += kDftThreads) {
+        const int li = e >> logL, t = e & (L - 1);
+        const long long line = line0 + li;
+        cplx<R> v = {R(0), R(0)};
+        if (line < lines) {
+            const long long i2 = line % mp.N2, i01 = line / mp.N2;
+            const long long i1 = i01 % mp.N1, i0 = i01 / mp.N1;
+            const long long off = i0 * mp.is0 + i1 * mp.is1 + i2 * mp.is2 + (long long)t * mp.ist;
+            if constexpr (REAL_IN) v.x = static_cast<const R*>(in_v)[off];
+            else v = static_cast<const cplx<R>*>(in_v)[off];
+        }
+        buf0[e] = v;
+    }
+    __syncthreads();
+    const int half_l = L >> 1;
+    for (int st = 0; st < logL; ++st) {
+        const int ls = st, s = 1 << ls, n = L >> ls, hn = n >> 1;   // stride, sub-transform length
+        for (int e = tid; e < lpb * half_l; e += kDftThreads) {
+            const int li = e >> (logL - 1), i = e & (half_l - 1);
+            const int p = i >> ls, q = i & (s - 1);
+            // stage st reads buffer st % 2 and writes the other
+            const cplx<R>* x = ((st & 1) ? buf1 : buf0) + li * L;
+            cplx<R>* y = ((st & 1) ? buf0 : buf1) + li * L;
+            const cplx<R> a = x[q + s * p], b = x[q + s * (p + hn)];
+            const cplx<R> wp = w[p * s];
+            const R dr = a.x - b.x, di = a.y - b.y;
+            y[q + s * (2 * p)] = {a.x + b.x, a.y + b.y};
+            y[q + s * (2 * p + 1)] = {dr * wp.x - di * wp.y, dr * wp.y + di * wp.x};
+        }
+        __syncthreads();
+    }
+    const cplx<R>* X = (logL & 1) ? buf1 : buf0;
+    for (int e = tid; e < lpb * L; e += kDftThreads) {
+        const int li = e >> logL, f = e & (L - 1);
+        const long long line = line0 + li;
+        if (line >= lines) continue;
+        const long long i2 = line % mp.N2, i01 = line / mp.N2;
+        const long long i1 = i01 % mp.N1, i0 = i01 / mp.N1;
+        const long long off = i0 * mp.os0 + i1 * mp.os1 + i2 * mp.os2 + (long long)f * mp.ost;
+        const cplx<R> v = X[e];
+        if constexpr (REAL_OUT) static_cast<R*>(out_v)[off] = v.x * scale;
+        else static_cast<cplx<R>*>(out_v)[off] = {v.x * scale, v.y * scale};
+    }
+}
+
+// One work-group (four waves) per frequency k, images in chunks of BC:
 //   z[b][j] = fac_j * sum_c conj(Rt[k][c][j]) xh[b][k][c]   (j < r, c < cx)
 //   yh[b][k][o] = sum_j Lt[k][o][j] z[b][j]                  (o < cy)
-// with fac_j = f(sigma_j(k)).  The chunk's x_hat vectors and z sit in LDS;
-// Rt[k] is read once per chunk with consecutive j across the threads, and
-// Lt[k] passes through a padded LDS tile of 64 rows x 32 columns (coalesced
-// loads, row reads one per thread), so U and V of a frequency are read once
-// per chunk of images.
-constexpr int kApplyThreads = 64;
+// with fac_j = f(sigma_j(k)).  The chunk's x_hat vectors and z sit in LDS.
+// Both products run over blocks of 64 outputs (one per lane); each wave sums
+// a contiguous quarter of the contraction index, so a lane keeps a quarter
+// of its loads in flight at once (Rt: lanes read consecutive j of one row c;
+// Lt: a lane reads a contiguous piece of its row o), and the four partial
+// sums meet in LDS.  U and V of a frequency are read once per chunk.
+constexpr int kApplyThreads = 256;
+constexpr int kApplyWaves = kApplyThreads / 64;
 constexpr size_t kApplyMaxLds = 160 * 1024 - 1024;   // gfx950 LDS per work-group
 constexpr int kApplyBC = 8;        // images per chunk
-constexpr int kApplyTO = 64;       // rows of an Lt tile (one per thread)
-constexpr int kApplyTJ = 32;       // columns of an Lt tile
 
 template <typename R>
 size_t apply_lds_bytes(int cx, int r) {
     return sizeof(R) * (size_t)((r + 1) & ~1) + sizeof(cplx<R>) * (size_t)kApplyBC * (cx + r) +
-           sizeof(cplx<R>) * (size_t)kApplyTO * (kApplyTJ + 1);
+           sizeof(cplx<R>) * (size_t)kApplyWaves * kApplyBC * 64;
 }
 
 template <typename R>
@@ -149,13 +213,12 @@ __global__ void __launch_bounds__(kApplyThreads) spectral_apply_kernel(
     extern __shared__ __align__(16) char lds[];
     const int k = blockIdx.x;
     if (k >= nfreq) return;
-    const int tid = threadIdx.x;
-    constexpr int NT = kApplyThreads, BC = kApplyBC, TO = kApplyTO, TJ = kApplyTJ;
-    static_assert(TO == NT, "one tile row per thread");
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    constexpr int NT = kApplyThreads, NW = kApplyWaves, BC = kApplyBC;
     R* fac = reinterpret_cast<R*>(lds);                                  // [r]
     cplx<R>* xs = reinterpret_cast<cplx<R>*>(fac + ((r + 1) & ~1));      // [BC][cx]
     cplx<R>* zs = xs + BC * cx;                                          // [BC][r]
-    cplx<R>* lt = zs + BC * r;                                           // [TO][TJ + 1]
+    cplx<R>* part = zs + BC * r;                                         // [NW][BC][64]
     for (int j = tid; j < r; j += NT) {
         const R s = sigma[(size_t)k * r + j];
         R f = s;                                                         // identity
@@ -166,6 +229,11 @@ __global__ void __launch_bounds__(kApplyThreads) spectral_apply_kernel(
     }
     const cplx<R>* Rk = Rt + (size_t)k * cx * r;
     const cplx<R>* Lk = Lt + (size_t)k * cy * r;
+    // this wave's quarter of the contraction over c (first product) and
+    // over j (second product)
+    const int cq = (cx + NW - 1) / NW, c_lo = wave * cq, c_hi = min(cx, c_lo + cq);
+    const int jq = (r + NW - 1) / NW, j_lo = wave * jq, j_hi = min(r, j_lo + jq);
+    constexpr int PF = 8;              // loads issued together
     for (int b0 = 0; b0 < batch; b0 += BC) {
         const int nb = batch - b0 < BC ? batch - b0 : BC;
         __syncthreads();
@@ -174,60 +242,98 @@ __global__ void __launch_bounds__(kApplyThreads) spectral_apply_kernel(
             xs[b * cx + c] = xh[((size_t)(b0 + b) * nfreq + k) * cx + c];
         }
         __syncthreads();
-        // z = fac * R^H x for the chunk
-        for (int j = tid; j < r; j += NT) {
-            R zr[BC], zi[BC];
+        // z = fac * R^H x, 64 columns j at a time
+        for (int j0 = 0; j0 < r; j0 += 64) {
+            const int j = j0 + lane;
+            R ar[BC], ai[BC];
 #pragma unroll
-            for (int b = 0; b < BC; ++b) zr[b] = zi[b] = R(0);
-#pragma unroll 8
-            for (int c = 0; c < cx; ++c) {
-                const cplx<R> a = Rk[(size_t)c * r + j];
-#pragma unroll
-                for (int b = 0; b < BC; ++b) {
-                    if (b < nb) {
-                        const cplx<R> v = xs[b * cx + c];
-                        zr[b] = fma(a.x, v.x, fma(a.y, v.y, zr[b]));
-                        zi[b] = fma(a.x, v.y, fma(-a.y, v.x, zi[b]));
-                    }
-                }
-            }
-#pragma unroll
-            for (int b = 0; b < BC; ++b)
-                if (b < nb) zs[b * r + j] = {zr[b] * fac[j], zi[b] * fac[j]};
-        }
-        // y = L z, tile by tile of L (TO rows x TJ columns)
-        for (int o0 = 0; o0 < cy; o0 += TO) {
-            const int o = o0 + tid;
-            R yr[BC], yi[BC];
-#pragma unroll
-            for (int b = 0; b < BC; ++b) yr[b] = yi[b] = R(0);
-            for (int j0 = 0; j0 < r; j0 += TJ) {
-                __syncthreads();
-#pragma unroll 8
-                for (int it = 0; it < TO * TJ / NT; ++it) {
-                    const int e = it * NT + tid, rr = e / TJ, cc = e - (e / TJ) * TJ;
-                    const int oo = o0 + rr, jj = j0 + cc;
-                    lt[rr * (TJ + 1) + cc] = (oo < cy && jj < r) ? Lk[(size_t)oo * r + jj] : cplx<R>{R(0), R(0)};
-                }
-                __syncthreads();
-                const int jn = r - j0 < TJ ? r - j0 : TJ;
-                for (int jj = 0; jj < jn; ++jj) {
-                    const cplx<R> a = lt[tid * (TJ + 1) + jj];
+            for (int b = 0; b < BC; ++b) ar[b] = ai[b] = R(0);
+            if (j < r) {
+                // whole batches of PF loads, then the rest one at a time
+                auto acc_z = [&](const cplx<R>& a, int c) __attribute__((always_inline)) {
 #pragma unroll
                     for (int b = 0; b < BC; ++b) {
                         if (b < nb) {
-                            const cplx<R> z = zs[b * r + j0 + jj];
+                            const cplx<R> v = xs[b * cx + c];
+                            ar[b] = fma(a.x, v.x, fma(a.y, v.y, ar[b]));
+                            ai[b] = fma(a.x, v.y, fma(-a.y, v.x, ai[b]));
+                        }
+                    }
+                };
+                int c0 = c_lo;
+                for (; c0 + PF <= c_hi; c0 += PF) {
+                    cplx<R> a[PF];
+#pragma unroll
+                    for (int u = 0; u < PF; ++u) a[u] = Rk[(size_t)(c0 + u) * r + j];
+#pragma unroll
+                    for (int u = 0; u < PF; ++u) acc_z(a[u], c0 + u);
+                }
+                for (; c0 < c_hi; ++c0) acc_z(Rk[(size_t)c0 * r + j], c0);
+            }
+#pragma unroll
+            for (int b = 0; b < BC; ++b) part[(wave * BC + b) * 64 + lane] = {ar[b], ai[b]};
+            __syncthreads();
+            for (int e = tid; e < nb * 64; e += NT) {
+                const int b = e >> 6, l = e & 63;
+                if (j0 + l < r) {
+                    R sr = 0, si = 0;
+#pragma unroll
+                    for (int w = 0; w < NW; ++w) {
+                        const cplx<R> q = part[(w * BC + b) * 64 + l];
+                        sr += q.x;
+                        si += q.y;
+                    }
+                    const R f = fac[j0 + l];
+                    zs[b * r + j0 + l] = {sr * f, si * f};
+                }
+            }
+            __syncthreads();
+        }
+        // y = L z, 64 rows o at a time
+        for (int o0 = 0; o0 < cy; o0 += 64) {
+            const int o = o0 + lane;
+            R yr[BC], yi[BC];
+#pragma unroll
+            for (int b = 0; b < BC; ++b) yr[b] = yi[b] = R(0);
+            if (o < cy) {
+                const cplx<R>* Lo = Lk + (size_t)o * r;
+                auto acc_y = [&](const cplx<R>& a, int i) __attribute__((always_inline)) {
+#pragma unroll
+                    for (int b = 0; b < BC; ++b) {
+                        if (b < nb) {
+                            const cplx<R> z = zs[b * r + i];
                             yr[b] = fma(a.x, z.x, fma(-a.y, z.y, yr[b]));
                             yi[b] = fma(a.x, z.y, fma(a.y, z.x, yi[b]));
                         }
                     }
+                };
+                int i0 = j_lo;
+                for (; i0 + PF <= j_hi; i0 += PF) {
+                    cplx<R> a[PF];
+#pragma unroll
+                    for (int u = 0; u < PF; ++u) a[u] = Lo[i0 + u];
+#pragma unroll
+                    for (int u = 0; u < PF; ++u) acc_y(a[u], i0 + u);
+                }
+                for (; i0 < j_hi; ++i0) acc_y(Lo[i0], i0);
+            }
+#pragma unroll
+            for (int b = 0; b < BC; ++b) part[(wave * BC + b) * 64 + lane] = {yr[b], yi[b]};
+            __syncthreads();
+            for (int e = tid; e < nb * 64; e += NT) {
+                const int b = e >> 6, l = e & 63;
+                if (o0 + l < cy) {
+                    R sr = 0, si = 0;
+#pragma unroll
+                    for (int w = 0; w < NW; ++w) {
+                        const cplx<R> q = part[(w * BC + b) * 64 + l];
+                        sr += q.x;
+                        si += q.y;
+                    }
+                    yh[((size_t)(b0 + b) * nfreq + k) * cy + o0 + l] = {sr, si};
                 }
             }
-            if (o < cy) {
-#pragma unroll
-                for (int b = 0; b < BC; ++b)
-                    if (b < nb) yh[((size_t)(b0 + b) * nfreq + k) * cy + o] = {yr[b], yi[b]};
-            }
+            __syncthreads();
         }
     }
 }
@@ -237,6 +343,21 @@ hipError_t launch_axis(const void* in, void* out, long long lines, int L, const 
                        int sign, R scale, hipStream_t st) {
     const long long total = lines * L;
     if (total <= 0) return hipSuccess;
+    if (L >= 2 && (L & (L - 1)) == 0 && L <= kDftLdsMaxL) {
+        const int logL = __builtin_ctz((unsigned)L);
+        const int lpb = L >= 2 * kDftThreads ? 1 : 2 * kDftThreads / L;
+        const long long blocks = (lines + lpb - 1) / lpb;
+        if (blocks > 0x7fffffffLL) return hipErrorInvalidValue;
+        const size_t lds = sizeof(cplx<R>) * (size_t)L * (1 + 2 * lpb);
+        if (lds > 65536) {
+            hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(fft_axis_lds_kernel<R, RI, RO>),
+                                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+            if (e != hipSuccess) return e;
+        }
+        hipLaunchKernelGGL((fft_axis_lds_kernel<R, RI, RO>), dim3((unsigned)blocks), dim3(kDftThreads), lds, st, in,
+                           out, lines, L, logL, lpb, mp, tw, sign, scale);
+        return hipGetLastError();
+    }
     if (L <= kDftLdsMaxL) {
         const int lpb = L >= kDftThreads ? 1 : kDftThreads / L;
         const long long blocks = (lines + lpb - 1) / lpb;

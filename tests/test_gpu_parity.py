@@ -480,6 +480,15 @@ APPLY_GPU_CASES = [
     (12, 8, 6, 4, 2, np.float64),
 ]
 
+# Larger power-of-two axes (the in-LDS FFT with several lines, or one
+# 512- or 1024-point line, per work-group); their spectra have no gap for a
+# cut-off level, so only the operator itself is applied.
+APPLY_FFT_CASES = [
+    (8, 8, 64, 32, 2, np.float32),
+    (4, 4, 512, 4, 1, np.float32),
+    (6, 4, 1024, 4, 1, np.float64),
+]
+
 
 def _gap_level(S, frac):
     """A level near frac * sigma_max in a gap of the spectrum, at least
@@ -492,8 +501,9 @@ def _gap_level(S, frac):
     return 0.5 * (s[i] + s[i + 1])
 
 
-@pytest.mark.parametrize("case", APPLY_GPU_CASES)
-@pytest.mark.parametrize("kind", ["identity", "clip", "truncate", "pinv"])
+@pytest.mark.parametrize("case,kind", [(c, k) for c in APPLY_GPU_CASES
+                                        for k in ("identity", "clip", "truncate", "pinv")]
+                         + [(c, "identity") for c in APPLY_FFT_CASES])
 def test_apply_matches_oracle(case, kind):
     """lfa_apply (transforms, per-frequency spectral map, inverse transforms)
     on the GPU's own SVD, against the oracle's spectral function of the same
@@ -731,3 +741,29 @@ def test_rank_deficient_symbols_converge(case):
     assert np.all(S[..., z:] == 0)
     if vec:
         check_vectors(A, S, to_np(U[0]), to_np(V[0]), tdt, "rank-deficient")
+
+
+def test_crystal_apply_is_the_strided_convolution():
+    """The spectral apply (identity) of a stride-2 layer's crystal form, on
+    the input rearranged into the crystal's channels (torch's
+    pixel_unshuffle: point d of a cell is channel i*4 + d1*2 + d2), is the
+    strided convolution itself: the oracle's dense strided operator applied
+    to the same images."""
+    c_out, c_in, k, n, s, B = 16, 6, 3, 16, 2, 2
+    banner("crystal apply = strided conv")
+    rng = np.random.default_rng(63)
+    W = (rng.standard_normal((c_out, c_in, k, k)) / np.sqrt(c_in * k * k)).astype(np.float32)
+    spec = lfa().LayerSpec(c_out, c_in, k, k, n, n)
+    c = lfa().crystal_layer(spec, s)
+    plan = lfa().Plan([c], torch.float32, True, True)
+    Wc = lfa().crystal_weights(_w(W), spec, s)
+    S, U, V, _ = plan.svd([Wc])
+    x = rng.standard_normal((B, c_in, n, n)).astype(np.float32)
+    xc = torch.nn.functional.pixel_unshuffle(_w(x), s).contiguous()
+    y = plan.apply(0, S[0], U[0], V[0], xc, "identity")
+    torch.cuda.synchronize()
+    D = oracle.strided_operator(W.astype(np.float64), n, n, s)
+    xv = np.transpose(x.astype(np.float64), (0, 2, 3, 1)).reshape(B, -1)       # (z1 n + z2) c_in + i
+    ref = np.transpose((xv @ D.T).reshape(B, n // s, n // s, c_out), (0, 3, 1, 2))
+    err = np.max(np.abs(to_np(y) - ref)) / np.max(np.abs(ref))
+    assert err <= 5e-5, err
