@@ -357,6 +357,19 @@ __device__ void finish(const SvdArgs<R>& a, const Shared<R>& s, int out_idx, int
     const bool want_left = d.transposed ? (a.V != nullptr) : (a.U != nullptr);
     const bool want_right = d.transposed ? (a.U != nullptr) : (a.V != nullptr);
 
+    if (want_right) {
+        cplx<R>* out = (d.transposed ? a.U : a.V) + (size_t)out_idx * N * r;
+        cplx<R>* mir = mirror >= 0 ? (d.transposed ? a.U : a.V) + (size_t)mirror * N * r : nullptr;
+        for (int e = tid; e < N * r; e += nt) {
+            const int i = e / r, c = e - (e / r) * r;
+            const cplx<R> v = Q[(size_t)s.perm[c] * ldv + i];
+            out[e] = v;
+            if (mir) mir[e] = {v.x, -v.y};
+        }
+    }
+    // the accumulator has been written out: its memory may serve the
+    // completion below
+    __syncthreads();
     if (want_left) {
         // normalise columns in place: u_j = g_j / sigma_j (zero columns stay 0)
         for (int e = tid; e < N * M; e += nt) {
@@ -374,9 +387,94 @@ __device__ void finish(const SvdArgs<R>& a, const Shared<R>& s, int out_idx, int
         // vector qualifies; some residual has norm >= 1/sqrt(M)).
         int nz = 0;
         while (nz < N && s.sig[s.perm[N - 1 - nz]] == R(0)) ++nz;
+        const int ra = N - nz;   // accepted columns, in rank order perm[0 .. ra)
+        // Many zero columns (a rank-deficient symbol): the completion is the
+        // trailing columns of Q = H_0 ... H_{ra-1}, the Householder
+        // reflectors of the accepted columns (QR), kept in the
+        // accumulator's memory: nz ra M work instead of the nz N M of
+        // Gram-Schmidt, and two barriers per reflector instead of several
+        // per zero column.
+        const bool householder =
+            nz >= 2 && ra >= 1 && want_right && Q != nullptr && (size_t)ra * M <= (size_t)N * ldv;
+        if (householder) {
+            cplx<R>* Vr = Q;   // [ra][M]
+            for (int e = tid; e < ra * M; e += nt) {
+                const int k = e / M, i = e - (e / M) * M;
+                Vr[e] = G[(size_t)s.perm[k] * ldg + i];
+            }
+            __syncthreads();
+            for (int k = 0; k < ra; ++k) {
+                cplx<R>* v = Vr + (size_t)k * M;
+                R part = 0;
+                for (int i = k + tid; i < M; i += nt) part = fma(v[i].x, v[i].x, fma(v[i].y, v[i].y, part));
+                const R nx = sqrt(block_sum<R>(part, s.red));
+                const cplx<R> al = v[k];
+                const R aa = sqrt(al.x * al.x + al.y * al.y);
+                __syncthreads();
+                if (tid == 0) {
+                    // v_k = alpha + e^{i arg alpha} ||x||, beta = 2 / (v^H v) = 1 / (||x|| (||x|| + |alpha|))
+                    const R pr = aa > R(0) ? al.x / aa : R(1), pi = aa > R(0) ? al.y / aa : R(0);
+                    v[k] = {al.x + pr * nx, al.y + pi * nx};
+                    s.coef[k] = {nx > R(0) ? R(1) / (nx * (nx + aa)) : R(0), R(0)};
+                }
+                __syncthreads();
+                const R beta = s.coef[k].x;
+                // H_k applied to the later accepted columns (rows >= k)
+                for (int j = k + 1 + group; j < ra; j += ngroups) {
+                    const cplx<R>* c = Vr + (size_t)j * M;
+                    cplx<R> w = {R(0), R(0)};
+                    for (int i = k + lane; i < M; i += L) {
+                        w.x = fma(v[i].x, c[i].x, fma(v[i].y, c[i].y, w.x));
+                        w.y = fma(v[i].x, c[i].y, fma(-v[i].y, c[i].x, w.y));
+                    }
+                    w.x = group_sum<R, L>(w.x);
+                    w.y = group_sum<R, L>(w.y);
+                    if (lane == 0) s.coef[j] = w;
+                }
+                __syncthreads();
+                for (int e = tid; e < (ra - k - 1) * M; e += nt) {
+                    const int j = k + 1 + e / M, i = e - (e / M) * M;
+                    if (i < k) continue;
+                    const cplx<R> w = s.coef[j], vi = v[i];
+                    const R fr = beta * (w.x * vi.x - w.y * vi.y), fi = beta * (w.x * vi.y + w.y * vi.x);
+                    Vr[(size_t)j * M + i] = {Vr[(size_t)j * M + i].x - fr, Vr[(size_t)j * M + i].y - fi};
+                }
+                __syncthreads();
+            }
+            // zero column z: H_0 ... H_{ra-1} e_{ra+z}
+            for (int e = tid; e < nz * M; e += nt) {
+                const int z = e / M, i = e - (e / M) * M;
+                G[(size_t)s.perm[ra + z] * ldg + i] = {R(i == ra + z ? 1 : 0), R(0)};
+            }
+            __syncthreads();
+            for (int k = ra - 1; k >= 0; --k) {
+                const cplx<R>* v = Vr + (size_t)k * M;
+                const R beta = s.coef[k].x;
+                for (int z = group; z < nz; z += ngroups) {
+                    const cplx<R>* x = G + (size_t)s.perm[ra + z] * ldg;
+                    cplx<R> w = {R(0), R(0)};
+                    for (int i = k + lane; i < M; i += L) {
+                        w.x = fma(v[i].x, x[i].x, fma(v[i].y, x[i].y, w.x));
+                        w.y = fma(v[i].x, x[i].y, fma(-v[i].y, x[i].x, w.y));
+                    }
+                    w.x = group_sum<R, L>(w.x);
+                    w.y = group_sum<R, L>(w.y);
+                    if (lane == 0) s.coef[ra + z] = w;
+                }
+                __syncthreads();
+                for (int e = tid; e < nz * M; e += nt) {
+                    const int z = e / M, i = e - (e / M) * M;
+                    if (i < k) continue;
+                    const cplx<R> w = s.coef[ra + z], vi = v[i];
+                    cplx<R>* x = G + (size_t)s.perm[ra + z] * ldg;
+                    x[i] = {x[i].x - beta * (w.x * vi.x - w.y * vi.y), x[i].y - beta * (w.x * vi.y + w.y * vi.x)};
+                }
+                __syncthreads();
+            }
+        }
         int cand = 0;
         R thresh = R(0.5);
-        for (int zc = N - nz; zc < N; ++zc) {
+        for (int zc = householder ? N : N - nz; zc < N; ++zc) {
             const int jz = s.perm[zc];
             bool done = false;
             for (int tries = 0; !done && tries < 4 * M; ++tries) {
@@ -442,16 +540,6 @@ __device__ void finish(const SvdArgs<R>& a, const Shared<R>& s, int out_idx, int
         for (int e = tid; e < M * r; e += nt) {
             const int i = e / r, c = e - (e / r) * r;
             const cplx<R> v = G[(size_t)s.perm[c] * ldg + i];
-            out[e] = v;
-            if (mir) mir[e] = {v.x, -v.y};
-        }
-    }
-    if (want_right) {
-        cplx<R>* out = (d.transposed ? a.U : a.V) + (size_t)out_idx * N * r;
-        cplx<R>* mir = mirror >= 0 ? (d.transposed ? a.U : a.V) + (size_t)mirror * N * r : nullptr;
-        for (int e = tid; e < N * r; e += nt) {
-            const int i = e / r, c = e - (e / r) * r;
-            const cplx<R> v = Q[(size_t)s.perm[c] * ldv + i];
             out[e] = v;
             if (mir) mir[e] = {v.x, -v.y};
         }
