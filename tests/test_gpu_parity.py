@@ -767,3 +767,104 @@ def test_crystal_apply_is_the_strided_convolution():
     ref = np.transpose((xv @ D.T).reshape(B, n // s, n // s, c_out), (0, 3, 1, 2))
     err = np.max(np.abs(to_np(y) - ref)) / np.max(np.abs(ref))
     assert err <= 5e-5, err
+
+
+# -------------------------------------------- the other workloads, full size --
+
+def _sample(n, m, count, seed):
+    rng = np.random.default_rng(seed)
+    fr = np.stack([rng.integers(0, n, count), rng.integers(0, m, count)], axis=1)
+    fr[0] = (0, 0)
+    fr[1] = (n - 1, m - 1)
+    return fr
+
+
+@pytest.mark.parametrize("vectors", [False, True])
+def test_rectangular_512x256_full_size_sampled(vectors):
+    """256 -> 512 channels, 3x3, 32x32 grid (1024 symbols of 512 x 256), in
+    the benchmark's launch configuration: 12 sampled symbols against the
+    oracle (sigma; with vectors also residual, orthonormality and
+    projectors), Parseval over the whole grid."""
+    banner(f"512x256 full size, vectors={vectors}")
+    L, W = workloads.rectangular_256_512()
+    out, info = lfa().svd(_w(W), L.n, L.m, compute_uv=vectors, return_info=True)
+    torch.cuda.synchronize()
+    S = out[0] if vectors else out
+    assert info[0] == 0 and info[3] == 0, info
+    fr = _sample(L.n, L.m, 12, 5)
+    A = oracle.symbols(W.astype(np.float64), L.n, L.m, fr)
+    S_ref, U_ref, V_ref = oracle.svd_symbols(A, compute_uv=True)
+    Sg = to_np(S)[fr[:, 0], fr[:, 1]]
+    assert oracle.sigma_error(Sg, S_ref) <= 1e-5
+    if vectors:
+        Ug, Vg = to_np(out[1])[fr[:, 0], fr[:, 1]], to_np(out[2])[fr[:, 0], fr[:, 1]]
+        check_vectors(A, Sg, Ug, Vg, torch.float32, "512x256")
+        check_projectors(S_ref, U_ref, V_ref, Ug, Vg, torch.float32, "512x256")
+    ss = torch.sum(S.double() ** 2).item()
+    assert abs(ss / (L.n * L.m * np.sum(W.astype(np.float64) ** 2)) - 1) <= 1e-5
+
+
+def test_rank_one_512x256_full_size_sampled():
+    """The rank-deficient instance at full size (rank-one taps: rank 9 per
+    symbol), with vectors: sampled sigma against the oracle, the 247
+    vanishing values exactly 0, U and V orthonormal (completed columns
+    included), Parseval over the whole grid."""
+    banner("rank-one 512x256 full size")
+    L, W = workloads.rank_one_taps()
+    (S, U, V), info = lfa().svd(_w(W), L.n, L.m, compute_uv=True, return_info=True)
+    torch.cuda.synchronize()
+    assert info[0] == 0 and info[3] == 0, info
+    fr = _sample(L.n, L.m, 8, 6)
+    A = oracle.symbols(W.astype(np.float64), L.n, L.m, fr)
+    S_ref = oracle.svd_symbols(A, compute_uv=False)
+    Sg = to_np(S)[fr[:, 0], fr[:, 1]]
+    assert oracle.sigma_error(Sg, S_ref) <= 1e-5
+    assert np.all(to_np(S)[..., 9:] == 0)
+    check_vectors(A, Sg, to_np(U)[fr[:, 0], fr[:, 1]], to_np(V)[fr[:, 0], fr[:, 1]], torch.float32, "rank-one")
+    ss = torch.sum(S.double() ** 2).item()
+    assert abs(ss / (L.n * L.m * np.sum(W.astype(np.float64) ** 2)) - 1) <= 1e-5
+
+
+def test_resnet18_stack_full_size():
+    """The twelve ResNet-18 layers at their real grids, as the benchmark's
+    batched step runs them: one persistent sigma-only launch, top-8 per
+    layer, gradient of the top-8 sum.  Per layer: sampled sigma against the
+    oracle, the top-8 values equal to the oracle's singular values at the
+    chosen (p, q, j), and dW against the oracle's gradient for those picks."""
+    banner("ResNet-18 stack full size")
+    layers, Ws = workloads.resnet18_stack()
+    specs = [lfa().LayerSpec(l.c_out, l.c_in, l.kh, l.kw, l.n, l.m) for l in layers]
+    plan = lfa().Plan(specs)
+    Wt = [_w(W) for W in Ws]
+    S, _, _, info = plan.svd(Wt, persistent=True)
+    vals, idx = plan.topk(S, 8)
+    g = torch.ones(len(layers), 8, device=DEV)
+    dW = plan.sigma_grad(Wt, idx, g, persistent=True)
+    torch.cuda.synchronize()
+    assert int(to_np(info)[:, 0].sum()) == 0
+    vals, idx = to_np(vals), to_np(idx)
+    for li, l in enumerate(layers):
+        W64 = Ws[li].astype(np.float64)
+        fr = _sample(l.n, l.m, 6, 20 + li)
+        assert oracle.sigma_error(to_np(S[li])[fr[:, 0], fr[:, 1]], oracle.lfa_svd(W64, l.n, l.m, freqs=fr)) <= 1e-5
+        p, q, j = idx[li].T
+        s_at = oracle.lfa_svd(W64, l.n, l.m, freqs=np.stack([p, q], axis=1))[np.arange(8), j]
+        assert np.max(np.abs(vals[li] - s_at)) <= 1e-5 * s_at.max(), li
+        ref = oracle.sigma_grad(W64, l.n, l.m, idx[li], np.ones(8))
+        assert np.linalg.norm(to_np(dW[li]) - ref) / np.linalg.norm(ref) <= 1e-3, li
+
+
+@pytest.mark.parametrize("asm", [None, "bf16x2", "bf16x3"])
+def test_large_grid_7x7_full_size_sampled(asm):
+    """64 -> 64 channels, 7x7 kernel with five taps scaled by 1e3, 224x224
+    grid (50176 symbols), sigma only, in each precision mode of the
+    benchmark: 24 sampled symbols against the oracle within 1e-5 (the
+    measured errors are 9e-7 FP32, 2e-6 bf16x2, 9e-7 bf16x3)."""
+    banner(f"7x7 224x224 full size, asm={asm}")
+    L, W, _ = workloads.large_grid_7x7()
+    S, info = lfa().svd(_w(W), L.n, L.m, asm=asm, return_info=True)
+    torch.cuda.synchronize()
+    assert info[0] == 0 and info[3] == 0, info
+    fr = _sample(L.n, L.m, 24, 7)
+    S_ref = oracle.lfa_svd(W.astype(np.float64), L.n, L.m, freqs=fr)
+    assert oracle.sigma_error(to_np(S)[fr[:, 0], fr[:, 1]], S_ref) <= 1e-5
