@@ -197,6 +197,30 @@ def bench_assembly(dev, steps, asm):
     return dict(ms=ms, gbs=bytes_moved / (ms * 1e-3) / 1e9, bytes=bytes_moved, A=A, L=L, W=W)
 
 
+def bench_split(dev, steps, L, W, vectors):
+    """Assembly and SVD timed apart, as the paper's Table III splits its
+    runtime into the transformation and the SVD: lfa_symbols (materialised
+    symbols), lfa_svd_symbols on them, and the fused lfa_svd that never
+    writes the symbols."""
+    Wt = torch.from_numpy(W).to(dev)
+    plan = lfa.Plan([lfa.LayerSpec(L.c_out, L.c_in, L.kh, L.kw, L.n, L.m)], want_u=vectors, want_v=vectors)
+    A = plan.symbols([Wt])[0]
+    torch.cuda.synchronize()
+    w_arr, k0 = lfa._lib.ptr_array([Wt.data_ptr()])
+    a_arr, k1 = lfa._lib.ptr_array([A.data_ptr()])
+
+    def asm():
+        lfa._lib.check(plan.lib.lfa_symbols(plan.handle, w_arr, a_arr, lfa.lfa._stream_ptr()), "lfa_symbols")
+
+    _, ev_asm = event_times(asm, steps, 2)
+    _, ev_svd = event_times(lambda: plan.svd_symbols([A]), steps, 2)
+    S, U, V = plan._alloc_outputs(dev, vectors, vectors)
+    _, ev_fused = event_times(lambda: plan.svd([Wt], out=(S, U, V)), steps, 2)
+    t_asm, t_svd, t_fused = (float(np.mean(e)) for e in (ev_asm, ev_svd, ev_fused))
+    return dict(asm_ms=t_asm, svd_ms=t_svd, asm_share=t_asm / (t_asm + t_svd), fused_ms=t_fused,
+                vectors=vectors)
+
+
 def bench_apply(head, dev, kind, batch=8, steps=10):
     """A spectral function of the headline layer's operator applied to
     `batch` images through its SVD (lfa_apply: forward transforms, the
@@ -328,8 +352,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--quick", action="store_true", help="headline workload only")
     ap.add_argument("--only", default=None,
-                    help="run one extra workload after the headline: apply, fp64, rect, strided, stack, "
-                         "large, assembly, paper")
+                    help="run one extra workload after the headline: apply, fp64, rect, strided, split, "
+                         "stack, large, assembly, paper")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the LFA SVD shards over frequencies, but this build "
@@ -412,6 +436,15 @@ def main():
                 ms=r["ms"], sigma_per_s=r["sigma_per_s"], sweeps=r["info"][1:3],
                 crystal_layer=[c.c_out, c.c_in, c.kh, c.kw, c.n, c.m])
         note("strided layers done")
+    if sel("split"):
+        # transformation vs SVD (the paper's Table III), and the fused path
+        Lp, Wp = workloads.paper_scale(1024)
+        sp = bench_split(dev, reps, Lp, Wp, False)
+        # Table III, LFA at n = 1024: transformation 1.28 s, SVD 31.74 s (Xeon Gold 6242, NumPy)
+        sp.update(paper_transform_s=1.28, paper_svd_s=31.74, paper_transform_share=1.28 / (1.28 + 31.74))
+        wl["split_paper_scale_c16_n1024"] = sp
+        wl["split_64x64_uv"] = bench_split(dev, reps, L, W, True)
+        note("assembly / SVD split done")
     if sel("stack"):
         st = bench_stack(dev, reps)
         extra["stack"] = st

@@ -167,7 +167,9 @@ int lfa_svd_persistent(const lfa_plan* plan, const void* const* W, void* const* 
                        size_t ws_bytes, void* stream);
 
 /* SVD of symbols the caller already holds (e.g. from lfa_symbols), same
- * outputs as lfa_svd.  A: per-layer [n][m][c_out][c_in] complex (device). */
+ * outputs as lfa_svd.  A: per-layer [n][m][c_out][c_in] complex (device).
+ * Every symbol is decomposed: caller symbols need not come in conjugate
+ * pairs (lfa_svd decomposes one symbol per pair of frequencies k, -k). */
 int lfa_svd_symbols(const lfa_plan* plan, const void* const* A, void* const* sigma,
                     void* const* U, void* const* V, int32_t* info, void* ws,
                     size_t ws_bytes, void* stream);
