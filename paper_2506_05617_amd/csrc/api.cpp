@@ -460,6 +460,7 @@ int run_svd_layer(const lfa_plan* p, const LayerDesc& d, const void* W, const vo
     a.theta_list = theta_list;
     a.theta_stride = theta_stride;
     a.theta_count = theta_count;
+    a.theta_dedup = theta_list != nullptr && theta_stride == 3;   // top-k picks
     a.max_sweeps = kMaxSweeps;
     a.tol = jacobi_tol(p->tol, d.M);
     const bool acc = (d.transposed ? U : V) != nullptr;
@@ -839,6 +840,7 @@ int sigma_grad_persistent_impl(const lfa_plan* p, const void* const* W, const in
             a.theta_list = idx + (size_t)i * k * 3;
             a.theta_stride = 3;
             a.theta_count = k;
+            a.theta_dedup = 1;
             a.slot_bytes = (long long)slot_bytes(d, true, eb);
             a.gws = slot[i];
         }

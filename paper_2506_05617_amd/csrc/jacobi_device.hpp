@@ -558,6 +558,8 @@ __device__ void finish(const SvdArgs<R>& a, const Shared<R>& s, int out_idx, int
 // Work item `item` (see target_of).
 template <typename R, int L>
 __device__ void svd_one(const SvdArgs<R>& a, char* lds, int item, char* gslot) {
+    bool cj;
+    if (a.theta_dedup && pick_rep(a.theta_list, item, a.d.n, a.d.m, cj) != item) return;   // decomposed already
     const Target tg = target_of(a, item);
     const int theta = tg.theta;
     const bool acc = (a.d.transposed ? a.U : a.V) != nullptr;
@@ -1129,6 +1131,10 @@ template <typename R, int RPT, bool ACC>
 __device__ void block_one(const SvdArgs<R>& a, char* lds, int item, char* gslot, Team& team) {
     // ACC must match the arguments: the right singular vectors (left when
     // transposed) are wanted exactly when the accumulator is kept
+    bool cj;
+    // a pick whose symbol an earlier pick has: every member of the team
+    // skips it alike
+    if (a.theta_dedup && pick_rep(a.theta_list, item, a.d.n, a.d.m, cj) != item) return;
     const Target tg = target_of(a, item);
     const Shared<R> s = carve<R>(lds, a.d, ACC, gslot);
     const BlockLds<R> bl = carve_block<R>(lds, s.small_end);

@@ -245,6 +245,28 @@ __host__ __device__ inline int canonical_theta(int n, int m, int item) {
     return (n / 2) * m + (r - full * m);
 }
 
+// The first of one layer's (p, q, j) picks idx[0 .. s] whose symbol is that
+// of pick s, or its conjugate (real weights: A_{-k} = conj(A_k), so the
+// singular vectors of -k are the conjugates of those of k); `conj` tells
+// which.  Picks of the same symbol need one decomposition.
+__device__ inline int pick_rep(const int32_t* idx, int s, int n, int m, bool& conj) {
+    const int p = idx[3 * s], q = idx[3 * s + 1];
+    const int mp = p > 0 ? n - p : 0, mq = q > 0 ? m - q : 0;
+    for (int t = 0; t < s; ++t) {
+        const int pt = idx[3 * t], qt = idx[3 * t + 1];
+        if (pt == p && qt == q) {
+            conj = false;
+            return t;
+        }
+        if (pt == mp && qt == mq) {
+            conj = true;
+            return t;
+        }
+    }
+    conj = false;
+    return s;
+}
+
 template <typename A>
 __device__ inline Target target_of(const A& a, int item) {
     Target t;
@@ -303,6 +325,9 @@ struct SvdArgs {
     const int32_t* theta_list;   // optional: symbol indices to process
     int theta_stride;            // element stride in theta_list (3 for (p,q,j) triples)
     int theta_count;             // number of symbols to process
+    int theta_dedup;             // theta_list holds one layer's (p, q, j) picks: a pick whose
+                                 // symbol an earlier pick has (itself or its conjugate) is
+                                 // skipped by the blocked and lane-group kernels (see pick_rep)
     int max_sweeps;
     double tol;
     int32_t* wctr;               // register kernel: group counter (cleared) of a grid of

@@ -144,12 +144,15 @@ __global__ void __launch_bounds__(256) adjoint_kernel(AdjointArgs<R> a) {
                                idx[3 * s + 1] < m && idx[3 * s + 2] >= 0 && idx[3 * s + 2] < r;
             if (valid) {   // entries outside the grid contribute nothing
                 const int p = idx[3 * s], q = idx[3 * s + 1], j = idx[3 * s + 2];
-                const long long sym = a.compact ? s : ((long long)p * m + q);
+                // compact slots: the pick that decomposed this symbol (the
+                // conjugate symbol's vectors are the conjugates)
+                bool cj = false;
+                const long long sym = a.compact ? pick_rep(idx, s, n, m, cj) : ((long long)p * m + q);
                 const cplx<R> uu = a.U[layer][(size_t)sym * c_out * r + (size_t)o * r + j];
                 const cplx<R> vv = a.V[layer][(size_t)sym * c_in * r + (size_t)i * r + j];
-                // z = u * conj(v)
+                // z = u * conj(v), conjugated with the vectors
                 zr[u] = uu.x * vv.x + uu.y * vv.y;
-                zi[u] = uu.y * vv.x - uu.x * vv.y;
+                zi[u] = cj ? uu.x * vv.y - uu.y * vv.x : uu.y * vv.x - uu.x * vv.y;
                 gs[u] = g[s];
             }
         }
