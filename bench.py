@@ -43,7 +43,7 @@ import paper_2506_05617_amd as lfa  # noqa: E402
 import workloads  # noqa: E402
 
 METRIC = "singular values/s (with vectors) and σ-grad layers/s vs plain at σ rel err ≤1e-5"
-PEAK_FP32_VECTOR_TFLOPS = 157.3     # MI355X, packed FP32 (this build issues unpacked FP32: half)
+PEAK_FP32_VECTOR_TFLOPS = 157.3     # MI355X, packed FP32 (the kernels are compiled without packed FP32: half that)
 PEAK_HBM_GBS = 8000.0
 
 # HBM bytes per launch of the headline kernel from the PMC passes recorded in
@@ -356,7 +356,7 @@ def main():
                          "stack, large, assembly, paper")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU: the LFA SVD shards over frequencies, but this build "
+        print("bench.py measures one GPU: the LFA SVD shards over frequencies, but this benchmark "
               "runs and reports a single MI355X only (use --gpus 1).", file=sys.stderr)
         sys.exit(2)
     dev = torch.device("cuda:0")

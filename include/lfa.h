@@ -12,9 +12,11 @@
  *     A_k = sum_{y in N} M_y * exp(+2 pi i <k, y>),
  *
  * and the SVD of the whole operator is the union over k of the SVDs
- * A_k = U_k S_k V_k^*.  This library computes the symbols (step a1) and
- * their SVD (steps a2/a3) on the GPU, plus top-k selection and the adjoint
- * that maps d(sum of selected sigma) back to the weights.
+ * A_k = U_k S_k V_k^*.  This library computes the symbols (Algorithm 1,
+ * symbol step) and their SVD (Algorithm 1, SVD step) on the GPU, plus top-k
+ * selection and the adjoint that maps d(sum of selected sigma) back to the
+ * weights, spectral functions of the operator through the SVD, and the
+ * crystal form of strided layers.
  *
  * Conventions (all entry points)
  * ------------------------------
@@ -132,7 +134,7 @@ int lfa_plan_workspace_bytes(const lfa_plan* plan, size_t* bytes);
 int lfa_plan_num_layers(const lfa_plan* plan, int32_t* num_layers);
 int lfa_plan_layer(const lfa_plan* plan, int32_t i, lfa_layer* layer);
 
-/* ---- step a1: symbol assembly ----------------------------------------- */
+/* ---- symbol assembly (Algorithm 1, symbol step) ----------------------- */
 
 /* A[layer][p][q][:, :] = sum_y W[layer][:, :, y] exp(+2 pi i <k, y>)
  * (Sec. III "Convolution Theorem"; Algorithm 1 symbol step), for every
@@ -143,7 +145,7 @@ int lfa_plan_layer(const lfa_plan* plan, int32_t i, lfa_layer* layer);
  * (FP32 or FP64 per dtype).  No workspace is used. */
 int lfa_symbols(const lfa_plan* plan, const void* const* W, void* const* A, void* stream);
 
-/* ---- steps a1-a3: SVD of every symbol ------------------------------- */
+/* ---- SVD of every symbol (Algorithm 1, symbol and SVD steps) --------- */
 
 /* For every layer and frequency, the SVD of the symbol (Sec. III
  * "Convolution Theorem"; Algorithm 1 SVD step) by one-sided Jacobi,
@@ -174,7 +176,7 @@ int lfa_svd_symbols(const lfa_plan* plan, const void* const* A, void* const* sig
                     void* const* U, void* const* V, int32_t* info, void* ws,
                     size_t ws_bytes, void* stream);
 
-/* ---- step a4: top-k per layer --------------------------------------- */
+/* ---- top-k per layer ------------------------------------------------- */
 
 /* The k largest singular values of each layer over all (p, q, j), ordered by
  * value descending, ties by flat index (p, q, j) ascending.
@@ -186,7 +188,7 @@ int lfa_svd_symbols(const lfa_plan* plan, const void* const* A, void* const* sig
 int lfa_topk(const lfa_plan* plan, const void* const* sigma, int32_t k, void* vals,
              int32_t* idx, void* stream);
 
-/* ---- step a5: adjoint -------------------------------------------------- */
+/* ---- adjoint: gradient of a sum of singular values -------------------- */
 
 /* dW[layer][o][i][a][b] = sum_s g[layer][s] *
  *     Re( exp(-2 pi i <k_s, y_ab>) * U_s[o] * conj(V_s[i]) )
