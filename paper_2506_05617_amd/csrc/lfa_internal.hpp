@@ -51,49 +51,6 @@ struct alignas(4 * sizeof(R)) quad {
     R a, b, c, d;
 };
 
-template <typename R>
-__device__ __forceinline__ void rot_apply(cplx<R>& x, cplx<R>& y, R c, R sr, R si) {
-    // x' = c x - sn y ;  y' = c y + conj(sn) x,  sn = sr + i si
-    const cplx<R> xv = x, yv = y;
-    x.x = fma(c, xv.x, -fma(sr, yv.x, -si * yv.y));
-    x.y = fma(c, xv.y, -fma(sr, yv.y, si * yv.x));
-    y.x = fma(c, yv.x, fma(sr, xv.x, si * xv.y));
-    y.y = fma(c, yv.y, fma(sr, xv.y, -si * xv.x));
-}
-
-// Rotation of one column pair from alpha = |g_j|^2, beta = |g_k|^2 and
-// gamma = g_j^H g_k: (c, Re(sn), Im(sn), flag) with sn = s conj(gamma)/|gamma|,
-// or the identity (1, 0, 0, 0) when |gamma| <= tol sqrt(alpha beta).  The
-// threshold test and the angle are evaluated in double precision; the
-// difference beta - alpha of two working-precision sums is exact there.  In
-// the FP32 path the reciprocals and square roots use the hardware
-// approximations (about 2^-23 relative, the rounding c and s receive anyway
-// when they are stored in FP32); the FP64 path keeps correctly rounded ones.
-template <typename R>
-__device__ __forceinline__ quad<R> rotation(R al, R be, R gr, R gi, double tol) {
-    const double g2 = double(gr) * double(gr) + double(gi) * double(gi);
-    quad<R> q = {R(1), R(0), R(0), R(0)};
-    if (!(g2 > tol * tol * (double(al) * double(be)))) return q;
-    if constexpr (sizeof(R) == 4) {
-        const double rg = __builtin_amdgcn_rsq(g2);                  // 1/|gamma|
-        const double z = 0.5 * (double(be) - double(al)) * rg;       // zeta
-        const double az = fabs(z);
-        const double w = fma(az, az, 1.0);
-        const double t = copysign(__builtin_amdgcn_rcp(az + w * __builtin_amdgcn_rsq(w)), z);
-        const double c = __builtin_amdgcn_rsq(fma(t, t, 1.0));
-        const double sn = c * t * rg;
-        q = {R(c), R(sn * double(gr)), R(-sn * double(gi)), R(1)};
-    } else {
-        const double gg = sqrt(g2);
-        const double z = (double(be) - double(al)) / (2.0 * gg);
-        const double t = copysign(1.0, z) / (fabs(z) + sqrt(1.0 + z * z));
-        const double c = 1.0 / sqrt(1.0 + t * t);
-        const double sn = c * t / gg;
-        q = {R(c), R(sn * double(gr)), R(-sn * double(gi)), R(1)};
-    }
-    return q;
-}
-
 // Numerically zero columns.  A symbol of rank below its column count keeps,
 // in the columns that Jacobi drives to zero, rounding noise that every
 // rotation with a nonzero column renews; its direction stays arbitrary, so
@@ -107,52 +64,19 @@ __host__ __device__ constexpr double negligible_sq() {
     return sizeof(R) == 4 ? 0x1p-46 : 0x1p-104;
 }
 
-// As rotation(), from squared column norms al = |g_j|^2 and be = |g_k|^2 that
-// the caller tracks instead of recomputing: the rotation maps them to
-// al - t |gamma| and be + t |gamma| (t = tan of the rotation angle), which
-// are returned through al and be (both clamped at 0: tracked norms drift by
-// rounding, and a negative one would pass the threshold test with gamma = 0;
-// unchanged without a rotation).  No rotation either when a column is
-// numerically zero: min(al, be) <= floor (negligible_sq() ||G||_F^2).
-template <typename R>
-__device__ __forceinline__ quad<R> rotation_tracked(double& al, double& be, R gr, R gi, double tol,
-                                                    double floor) {
-    const double g2 = double(gr) * double(gr) + double(gi) * double(gi);
-    quad<R> q = {R(1), R(0), R(0), R(0)};
-    if (!(g2 > tol * tol * (al * be)) || !(fmin(al, be) > floor)) return q;
-    double rg, t, c;
-    if constexpr (sizeof(R) == 4) {
-        rg = __builtin_amdgcn_rsq(g2);                                // 1/|gamma|
-        const double z = 0.5 * (be - al) * rg;                        // zeta
-        const double az = fabs(z);
-        const double w = fma(az, az, 1.0);
-        t = copysign(__builtin_amdgcn_rcp(az + w * __builtin_amdgcn_rsq(w)), z);
-        c = __builtin_amdgcn_rsq(fma(t, t, 1.0));
-    } else {
-        const double gg = sqrt(g2);
-        rg = 1.0 / gg;
-        const double z = (be - al) / (2.0 * gg);
-        t = copysign(1.0, z) / (fabs(z) + sqrt(1.0 + z * z));
-        c = 1.0 / sqrt(1.0 + t * t);
-    }
-    const double sn = c * t * rg;
-    const double tg = t * g2 * rg;                                    // t |gamma|
-    al = fmax(al - tg, 0.0);
-    be = fmax(be + tg, 0.0);
-    q = {R(c), R(sn * double(gr)), R(-sn * double(gi)), R(1)};
-    return q;
-}
-
 // Scaled ("fast") form of the rotation for columns stored as g_j = G_j / d_j
 // with per-column scale factors d_j.  gr, gi is the true gamma (of G).  The
 // true rotation G_j' = c G_j - sn G_k, G_k' = c G_k + conj(sn) G_j becomes,
 // with the scales multiplied by c, g_j' = g_j - tau1 g_k and
 // g_k' = g_k + tau2 g_j (tau = sn / c, tau1 = tau d_k/d_j,
 // tau2 = conj(tau) d_j/d_k): two complex multiply-adds per row instead of
-// four real-by-complex products.  Returns (tau1, tau2) in q, updates the
-// tracked squared norms (as rotation_tracked) and the scales, or leaves
-// everything unchanged and returns the identity (zeros) below the threshold
-// or for a numerically zero column (min(al, be) <= floor).
+// four real-by-complex products.  Returns (tau1, tau2) in q and updates the
+// scales and the squared norms al, be that the caller tracks instead of
+// recomputing: the rotation maps them to al - t |gamma| and be + t |gamma|
+// (t the tangent of the angle), both clamped at 0 (tracked norms drift by
+// rounding, and a negative one would pass the threshold with gamma = 0).
+// Leaves everything unchanged and returns the identity (zeros) below the
+// threshold or for a numerically zero column (min(al, be) <= floor).
 //
 // Result: 0 without a rotation, 1 for a rotation with |t| <= kappa, 2 for a
 // larger one, kappa = sqrt(tol)/4.  A sweep whose rotations all have
