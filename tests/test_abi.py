@@ -154,3 +154,44 @@ def test_crystal_layer_shapes_and_errors():
         == _lib.LFA_ERR_INVALID_ARG
     assert lib.lfa_crystal_weights(ctypes.byref(_lib.LfaLayer(4, 4, 3, 3, 8, 8)), 2, 0, ctypes.c_void_p(8),
                                    ctypes.c_void_p(8), 7, None) == _lib.LFA_ERR_INVALID_ARG
+
+
+@needs_lib
+def test_apply_and_lift_reject_bad_arguments_before_touching_the_gpu():
+    """lfa_apply, lfa_apply_workspace_bytes and lfa_lift validate on the host:
+    layer, kind, level, counts and pointers; empty calls succeed without a
+    device."""
+    plan = lfa.Plan([lfa.LayerSpec(8, 4, 3, 3, 6, 4)], want_u=True, want_v=True)
+    lib, h = plan.lib, plan.handle
+    nb = ctypes.c_size_t()
+    assert lib.lfa_apply_workspace_bytes(h, 0, 3, ctypes.byref(nb)) == 0
+    assert nb.value >= 2 * 3 * 6 * 4 * 8 * 2 * 4                  # two complex buffers, max(c) = 8
+    assert lib.lfa_apply_workspace_bytes(h, 1, 3, ctypes.byref(nb)) == _lib.LFA_ERR_INVALID_ARG
+    assert lib.lfa_apply_workspace_bytes(h, 0, -1, ctypes.byref(nb)) == _lib.LFA_ERR_INVALID_ARG
+    p = ctypes.c_void_p(8)
+
+    def apply(layer=0, kind=0, param=0.0, batch=1, ptr=p, ws_bytes=1 << 30):
+        return lib.lfa_apply(h, layer, ptr, ptr, ptr, kind, param, ptr, ptr, batch, ptr,
+                             ctypes.c_size_t(ws_bytes), None)
+
+    assert apply(layer=2) == _lib.LFA_ERR_INVALID_ARG
+    assert apply(kind=4) == _lib.LFA_ERR_INVALID_ARG
+    assert apply(kind=-1) == _lib.LFA_ERR_INVALID_ARG
+    assert apply(param=-1.0) == _lib.LFA_ERR_INVALID_ARG
+    assert apply(param=float("nan")) == _lib.LFA_ERR_INVALID_ARG
+    assert apply(batch=-2) == _lib.LFA_ERR_INVALID_ARG
+    assert apply(batch=0) == 0
+    assert apply(ptr=ctypes.c_void_p(None)) == _lib.LFA_ERR_INVALID_ARG
+    assert apply(ws_bytes=16) == _lib.LFA_ERR_WORKSPACE
+    assert _lib.LFA_SPECTRAL_TRUNCATE == 3
+
+    def lift(layer=0, U=p, V=p, idx=p, count=1, uh=p, vh=p):
+        return lib.lfa_lift(h, layer, U, V, idx, count, uh, vh, None)
+
+    assert lift(layer=1) == _lib.LFA_ERR_INVALID_ARG
+    assert lift(count=-1) == _lib.LFA_ERR_INVALID_ARG
+    assert lift(U=None) == _lib.LFA_ERR_INVALID_ARG                 # u_hat without U
+    assert lift(V=None) == _lib.LFA_ERR_INVALID_ARG
+    assert lift(idx=None) == _lib.LFA_ERR_INVALID_ARG
+    assert lift(count=0) == 0
+    assert lift(uh=None, vh=None) == 0                              # nothing to write
