@@ -909,9 +909,11 @@ __device__ void block_sweeps(const LayerDesc& d, const Shared<R>& s, const Block
     // steps unrolled together in the intra passes (B - 1 steps) and the
     // cross passes (B steps); with the accumulator, larger blocks of steps
     // spill registers (measured: 3 and 4 made the 512 x 256 layer with
-    // vectors 1.7x slower, 1 and 2 made it 3 % faster); FP64 keeps one step
+    // vectors 1.7x slower, 1 and 2 made it 3 % faster); without it, 5 and 8
+    // measured 2 % faster than 3 and 4 (15 and 4: no gain); FP64 keeps one
+    // step
     constexpr bool F64 = sizeof(R) == 8;
-    constexpr int KI = (ACC || F64) ? 1 : 3, KC = F64 ? 1 : (ACC ? 2 : 4);
+    constexpr int KI = (ACC || F64) ? 1 : 5, KC = F64 ? 1 : (ACC ? 2 : 8);
     static_assert((B - 1) % KI == 0 && B % KC == 0, "unrolled steps must divide a pass");
     const int tid = threadIdx.x, nt = blockDim.x;
     const int lane = tid & 63, wave = tid >> 6;
