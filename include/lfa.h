@@ -292,7 +292,8 @@ int lfa_apply(const lfa_plan* plan, int32_t layer, const void* sigma, const void
  * pick out of range (p not in [0, n), q not in [0, m) or j not in [0, r))
  * gives zero vectors.  Stream-ordered; count == 0 does nothing.
  * Errors: LFA_ERR_INVALID_ARG (layer, count < 0, idx NULL, an output without
- * its input), LFA_ERR_HIP. */
+ * its input), LFA_ERR_UNSUPPORTED (count * max(c_out, c_in) beyond 2^31 - 1),
+ * LFA_ERR_HIP. */
 int lfa_lift(const lfa_plan* plan, int32_t layer, const void* U, const void* V, const int32_t* idx,
              int32_t count, void* u_hat, void* v_hat, void* stream);
 

@@ -1145,6 +1145,9 @@ int lfa_lift(const lfa_plan* plan, int32_t layer, const void* U, const void* V, 
     if ((u_hat && !U) || (v_hat && !V)) return LFA_ERR_INVALID_ARG;
     if (count == 0 || (!u_hat && !v_hat)) return LFA_OK;
     if (!idx) return LFA_ERR_INVALID_ARG;
+    // one work-group per (pick, channel) row
+    const lfa_layer& l0 = plan->layers[layer];
+    if ((long long)count * std::max(l0.c_out, l0.c_in) > 0x7fffffffLL) return LFA_ERR_UNSUPPORTED;
     lfa_plan* p = const_cast<lfa_plan*>(plan);
     LFA_TRY(ensure_device(p));
     const lfa_layer& l = p->layers[layer];
