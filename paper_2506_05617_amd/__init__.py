@@ -10,6 +10,7 @@ from .lfa import (  # noqa: F401
     SigmaTopK,
     crystal_layer,
     crystal_weights,
+    sigma_sum,
     sigma_topk,
     svd,
     symbols,

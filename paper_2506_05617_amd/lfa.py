@@ -415,3 +415,15 @@ class SigmaTopK(torch.autograd.Function):
 def sigma_topk(plan: Plan, Ws, k: int):
     """Differentiable per-layer top-k singular values: returns (vals [L, k], idx [L, k, 3])."""
     return SigmaTopK.apply(plan, k, *Ws)
+
+
+def sigma_sum(Ws, grids, k: int = 8):
+    """The sum over layers of each layer's k largest singular values, as a
+    differentiable scalar (a spectral-norm style penalty): ``Ws`` are the
+    layers' weights, ``grids`` their (n, m) grids (or n for square grids).
+    The plan for these shapes is built on first use and cached."""
+    grids = [(g, g) if isinstance(g, int) else tuple(g) for g in grids]
+    specs = tuple(_spec(W, n, m) for W, (n, m) in zip(Ws, grids))
+    plan = _plan_for(specs, Ws[0].dtype, False, False)
+    vals, _ = SigmaTopK.apply(plan, k, *Ws)
+    return vals.sum()

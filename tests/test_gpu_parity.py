@@ -868,3 +868,24 @@ def test_large_grid_7x7_full_size_sampled(asm):
     fr = _sample(L.n, L.m, 24, 7)
     S_ref = oracle.lfa_svd(W.astype(np.float64), L.n, L.m, freqs=fr)
     assert oracle.sigma_error(to_np(S)[fr[:, 0], fr[:, 1]], S_ref) <= 1e-5
+
+
+def test_sigma_sum_convenience_matches_topk_and_gradient():
+    """sigma_sum (cached plan, scalar penalty) equals the sum of sigma_topk's
+    values, and its gradient equals the oracle's gradient of the same sum."""
+    banner("sigma_sum")
+    layers, Ws = _small_stack(seed=17)
+    layers, Ws = layers[:3], Ws[:3]
+    Wt = [_w(W).requires_grad_(True) for W in Ws]
+    total = lfa().sigma_sum(Wt, [(l.n, l.m) for l in layers], k=8)
+    total.backward()
+    torch.cuda.synchronize()
+    ref_total = 0.0
+    for li, l in enumerate(layers):
+        s = oracle.lfa_svd(Ws[li].astype(np.float64), l.n, l.m)
+        vals, picks = oracle.topk(s, 8)
+        ref_total += float(vals.sum())
+        ref = oracle.sigma_grad(Ws[li].astype(np.float64), l.n, l.m, picks, np.ones(8))
+        err = np.linalg.norm(to_np(Wt[li].grad) - ref) / np.linalg.norm(ref)
+        assert err <= 1e-3, (li, err)
+    assert abs(float(total) - ref_total) <= 1e-5 * ref_total
