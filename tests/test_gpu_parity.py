@@ -888,4 +888,4 @@ def test_sigma_sum_convenience_matches_topk_and_gradient():
         ref = oracle.sigma_grad(Ws[li].astype(np.float64), l.n, l.m, picks, np.ones(8))
         err = np.linalg.norm(to_np(Wt[li].grad) - ref) / np.linalg.norm(ref)
         assert err <= 1e-3, (li, err)
-    assert abs(float(total) - ref_total) <= 1e-5 * ref_total
+    assert abs(float(total.detach()) - ref_total) <= 1e-5 * ref_total
