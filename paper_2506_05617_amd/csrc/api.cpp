@@ -212,17 +212,18 @@ int wave_queue_reserved(const LayerDesc& d, bool acc, int eb) {
 // Sweeps per turn of a group in the work-queue launch (0: no work queue).
 // A turn costs the save and restore of the group's rows and an L2 write-back
 // and invalidation; measured on the 64 x 64 layer on the 64 x 64 grid (2050
-// groups, 1024 or 2048 resident), 5 sweeps per turn was best or within noise
-// of best for sigma only and with vectors (1 sweep per turn was slower than
-// no work queue).
+// groups, 1024 or 2048 resident; 8 to 10 sweeps per symbol): with vectors 6
+// sweeps per turn was best (1 % ahead of 5), sigma only 4 or 5 (6: 4 %
+// slower); 1 sweep per turn was slower than no work queue.
 constexpr int kQueueSweepsPerTurn = 5;
+constexpr int kQueueSweepsPerTurnVectors = 6;
 int wave_queue_seg(const LayerDesc& d, int groups, int force) {
     if (d.kind != 1 || d.wave_qcap <= 0 || groups > d.wave_qgroups || force == 0) return 0;
     if (force > 0) return force;
     if (groups <= d.wave_qcap) return 0;
     const long long rounds = ((long long)groups + d.wave_qcap - 1) / d.wave_qcap;
     if (rounds > kQueueMaxRounds) return 0;
-    return kQueueSweepsPerTurn;
+    return d.threads > 64 ? kQueueSweepsPerTurnVectors : kQueueSweepsPerTurn;   // a Q wave: vectors
 }
 
 size_t slot_bytes(const LayerDesc& d, bool acc, int eb) {
