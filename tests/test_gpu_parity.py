@@ -478,6 +478,7 @@ APPLY_GPU_CASES = [
     (40, 24, 7, 5, 2, np.float32),      # odd grid
     (64, 64, 8, 8, 2, np.float32),
     (12, 8, 6, 4, 2, np.float64),
+    (12, 8, 8, 8, 2, np.float64),       # in-LDS FFT on both axes, FP64
 ]
 
 # Larger power-of-two axes (the in-LDS FFT with several lines, or one
@@ -487,6 +488,7 @@ APPLY_FFT_CASES = [
     (8, 8, 64, 32, 2, np.float32),
     (4, 4, 512, 4, 1, np.float32),
     (6, 4, 1024, 4, 1, np.float64),
+    (4, 4, 1024, 8, 1, np.float32),
 ]
 
 
