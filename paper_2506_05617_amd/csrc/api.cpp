@@ -525,9 +525,27 @@ int run_svd_layer(const lfa_plan* p, const LayerDesc& d, const void* W, const vo
         }
         int32_t* counters = reinterpret_cast<int32_t*>(region);
         a.gws = region + kCounterBytes;
-        if constexpr (sizeof(R) == 4) e = launch_block_svd_f32(a, teams, W, counters, st);
-        else e = launch_block_svd_f64(a, teams, W, counters, st);
-        HIP_TRY(e);
+        // More symbols than resident work-groups: the whole rounds run one
+        // work-group per symbol, and a short last round (at most half the
+        // device) runs afterwards in teams instead of leaving the other CUs
+        // idle for a whole symbol time.
+        int split = count;
+        int W2 = 1, teams2 = 0;
+        const int rem = resident > 0 ? count % resident : 0;
+        if (W == 1 && cap >= 2 && count > resident && rem > 0 && 2 * rem <= cap) {
+            W2 = std::max(1, std::min(NBP / 2, cap / rem));
+            if (W2 > 1) {
+                split = count - rem;
+                teams2 = rem;
+                teams = std::min(split, kGlobalGrid);
+            }
+        }
+        auto launch = [&](int tm, int w, int i0, int i1) {
+            if constexpr (sizeof(R) == 4) return launch_block_svd_f32(a, tm, w, i0, i1, counters, st);
+            else return launch_block_svd_f64(a, tm, w, i0, i1, counters, st);
+        };
+        HIP_TRY(launch(teams, W, 0, split));
+        if (teams2 > 0) HIP_TRY(launch(teams2, W2, split, count));
         return LFA_OK;
     }
     const size_t lds = lds_bytes_for(d, acc, sizeof(R));

@@ -9,11 +9,12 @@ namespace lfa {
 namespace {
 using namespace dev;
 
-// Grid = teams x W work-groups, all resident at once (the host sizes the
-// grid from the occupancy of this kernel).  Team t owns slot t and works on
-// items t, t + teams, ...
+// Grid = teams x W work-groups, all resident at once when W > 1 (the host
+// sizes the grid from the occupancy of this kernel).  Team t owns slot t and
+// works on items item0 + t, item0 + t + teams, ... below item_end.
 template <typename R, bool ACC>
-__global__ void __launch_bounds__(512) block_kernel(SvdArgs<R> a, int W, int32_t* counters) {
+__global__ void __launch_bounds__(512) block_kernel(SvdArgs<R> a, int W, int item0, int item_end,
+                                                    int32_t* counters) {
     extern __shared__ __align__(16) char lds[];
     const int teams = gridDim.x / W;
     const int tix = blockIdx.x / W;
@@ -25,8 +26,8 @@ __global__ void __launch_bounds__(512) block_kernel(SvdArgs<R> a, int W, int32_t
     team.err = counters + 4 * teams;
     team.target = 0;
     char* gslot = a.gws + (size_t)tix * a.slot_bytes;
-    const int count = item_count(a);
-    for (int item = tix; item < count; item += teams) block_one<R, 1, ACC>(a, lds, item, gslot, team);
+    const int count = min(item_count(a), item_end);
+    for (int item = item0 + tix; item < count; item += teams) block_one<R, 1, ACC>(a, lds, item, gslot, team);
 }
 
 template <typename R, int L>
@@ -104,21 +105,24 @@ size_t block_lds_bytes(const LayerDesc& d, bool accumulate, int elem_bytes) {
 }
 
 template <typename R, bool ACC>
-hipError_t launch_block_t(const SvdArgs<R>& a, int teams, int W, int32_t* counters, hipStream_t st) {
+hipError_t launch_block_t(const SvdArgs<R>& a, int teams, int W, int item0, int item_end, int32_t* counters,
+                          hipStream_t st) {
     const size_t lds = block_lds_bytes(a.d, ACC, sizeof(R));
     hipError_t e = allow_lds(block_kernel<R, ACC>, lds);
     if (e != hipSuccess) return e;
     e = launch_fill_i32(counters, 0, 4LL * teams + 4, st);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((block_kernel<R, ACC>), dim3(teams * W), dim3(a.d.threads), lds, st, a, W, counters);
+    hipLaunchKernelGGL((block_kernel<R, ACC>), dim3(teams * W), dim3(a.d.threads), lds, st, a, W, item0,
+                       item_end, counters);
     return hipGetLastError();
 }
 
 template <typename R>
-hipError_t launch_block(const SvdArgs<R>& a, int teams, int W, int32_t* counters, hipStream_t st) {
+hipError_t launch_block(const SvdArgs<R>& a, int teams, int W, int item0, int item_end, int32_t* counters,
+                        hipStream_t st) {
     const bool acc = (a.d.transposed ? a.U : a.V) != nullptr;
-    return acc ? launch_block_t<R, true>(a, teams, W, counters, st)
-               : launch_block_t<R, false>(a, teams, W, counters, st);
+    return acc ? launch_block_t<R, true>(a, teams, W, item0, item_end, counters, st)
+               : launch_block_t<R, false>(a, teams, W, item0, item_end, counters, st);
 }
 
 template <typename R, bool ACC>
@@ -135,13 +139,13 @@ int block_resident_t(const LayerDesc& d) {
     return per_cu * cus;
 }
 
-hipError_t launch_block_svd_f32(const SvdArgs<float>& a, int teams, int W, int32_t* counters,
-                                hipStream_t s) {
-    return launch_block<float>(a, teams, W, counters, s);
+hipError_t launch_block_svd_f32(const SvdArgs<float>& a, int teams, int W, int item0, int item_end,
+                                int32_t* counters, hipStream_t s) {
+    return launch_block<float>(a, teams, W, item0, item_end, counters, s);
 }
-hipError_t launch_block_svd_f64(const SvdArgs<double>& a, int teams, int W, int32_t* counters,
-                                hipStream_t s) {
-    return launch_block<double>(a, teams, W, counters, s);
+hipError_t launch_block_svd_f64(const SvdArgs<double>& a, int teams, int W, int item0, int item_end,
+                                int32_t* counters, hipStream_t s) {
+    return launch_block<double>(a, teams, W, item0, item_end, counters, s);
 }
 int block_resident(const LayerDesc& d, bool acc, int elem_bytes) {
     if (elem_bytes == 8) return acc ? block_resident_t<double, true>(d) : block_resident_t<double, false>(d);

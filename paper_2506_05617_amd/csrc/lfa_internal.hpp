@@ -324,12 +324,13 @@ size_t lds_bytes_for(const LayerDesc& d, bool accumulate, int elem_bytes);
 
 size_t wave_lds_bytes_for(int nc, int ml, int elem_bytes);
 size_t block_lds_bytes(const LayerDesc& d, bool accumulate, int elem_bytes);
-// Blocked kernel: `teams` teams of W work-groups (all resident at once);
-// counters: 4*teams + 4 int32 of device memory, cleared by the launcher.
-hipError_t launch_block_svd_f32(const SvdArgs<float>& a, int teams, int W, int32_t* counters,
-                                hipStream_t s);
-hipError_t launch_block_svd_f64(const SvdArgs<double>& a, int teams, int W, int32_t* counters,
-                                hipStream_t s);
+// Blocked kernel: `teams` teams of W work-groups (all resident at once when
+// W > 1) over the items [item0, item_end) of the layer; counters: 4*teams + 4
+// int32 of device memory, cleared by the launcher.
+hipError_t launch_block_svd_f32(const SvdArgs<float>& a, int teams, int W, int item0, int item_end,
+                                int32_t* counters, hipStream_t s);
+hipError_t launch_block_svd_f64(const SvdArgs<double>& a, int teams, int W, int item0, int item_end,
+                                int32_t* counters, hipStream_t s);
 // Work-groups of the blocked kernel that fit on the device at once (0 on error).
 int block_resident(const LayerDesc& d, bool accumulate, int elem_bytes);
 
