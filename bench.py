@@ -11,8 +11,9 @@ Also reported (``workloads``):
   * 256 -> 512 channels on a 32x32 grid (1024 symbols of 512x256), sigma-only
     and with U, V, plus the instance with rank-one taps;
   * the 12-layer ResNet-18-shaped stack: sigma-gradient throughput in layers/s
-    (forward sigma of every layer, top-8 per layer, dL/dW), batched (one
-    persistent launch + HIP graph) and plain (one launch per layer and stage);
+    (forward sigma of every layer, top-8 per layer, dL/dW), batched (a HIP
+    graph of one persistent SVD launch keeping U and V, top-8 and one adjoint
+    launch) and plain (one launch per layer and stage);
   * 64 -> 64 channels, 7x7 kernel, 224x224 grid (50176 symbols), sigma-only,
     with FP32 fused assembly and with split-BF16 matrix-core assembly
     (3 and 6 products), and the assembly kernel alone against HBM bandwidth.
@@ -50,7 +51,7 @@ PEAK_HBM_GBS = 8000.0
 # profiles/wave_queue_kernel_single_layer_64x64_uv.md (FETCH_SIZE x 2.00 +
 # WRITE_SIZE x 1.00, calibrated with a copy of known size), valid only for the
 # kernel source they were taken on.
-HEAD_TRAFFIC = {"bytes": 155.48e6 + 429.58e6, "source_hash": "dec940fe89232046",
+HEAD_TRAFFIC = {"bytes": 155.48e6 + 429.58e6, "source_hash": "ba4ace95f43f6388",
                 "files": ("jacobi_device.hpp", "jacobi_wave.hip", "lfa_internal.hpp", "api.cpp")}
 
 
@@ -155,18 +156,27 @@ def bench_stack(dev, steps):
         vals, idx = plan.topk(S, k)
         res["plain"] = (vals, idx, plan.sigma_grad(Wt, idx, ones))
 
-    graph = lfa.GraphStep(plan, Wt, k)
+    # batched: one HIP graph of [persistent SVD keeping every symbol's U, V
+    # -> top-k -> one adjoint launch]; the sigma-only graph (forward sigma,
+    # then the vectors of the picked symbols recomputed) is timed beside it
+    plan_uv = lfa.Plan(specs, torch.float32, want_u=True, want_v=True)
+    graph = lfa.GraphStep(plan_uv, Wt, k)
+    graph_s = lfa.GraphStep(plan, Wt, k)
 
-    def batched():
-        graph.replay()
-        torch.cuda.current_stream().wait_stream(graph.stream)
+    def replay(g):
+        g.replay()
+        torch.cuda.current_stream().wait_stream(g.stream)
 
     wall_p, _ = event_times(plain, steps, 1)
-    wall_b, _ = event_times(batched, steps, 1)
+    wall_b, _ = event_times(lambda: replay(graph), steps, 1)
+    wall_s, _ = event_times(lambda: replay(graph_s), steps, 1)
+    torch.cuda.synchronize()
+    batched_out = (graph.vals.clone(), graph.idx.clone(), [d.clone() for d in graph.dW])
     nl = len(specs)
-    return dict(layers=layers, Ws=Ws, graph=graph, plain_out=res["plain"],
+    return dict(layers=layers, Ws=Ws, graph=graph, plain_out=res["plain"], batched_out=batched_out,
                 plain_layers_per_s=nl * steps / wall_p, batched_layers_per_s=nl * steps / wall_b,
-                plain_ms=wall_p * 1e3 / steps, batched_ms=wall_b * 1e3 / steps)
+                plain_ms=wall_p * 1e3 / steps, batched_ms=wall_b * 1e3 / steps,
+                batched_sigma_only_ms=wall_s * 1e3 / steps)
 
 
 def bench_assembly(dev, steps, asm):
@@ -305,6 +315,13 @@ def cpu_leg(head, extra):
                     ov, _ = oracle.topk(sref, 8)
                     errors[f"stack_top8_layer{li}"] = float(np.max(np.abs(vals[li].cpu().numpy() - ov)) / ov[0])
                 errors["stack_grad_rel_frobenius"] = gerr
+                bvals, bidx, bdW = st["batched_out"]
+                bidx_np = bidx.cpu().numpy()
+                gerr = 0.0
+                for li, l in enumerate(st["layers"]):
+                    ref = oracle.sigma_grad(st["Ws"][li].astype(np.float64), l.n, l.m, bidx_np[li])
+                    gerr = max(gerr, float(np.linalg.norm(bdW[li].cpu().numpy() - ref) / np.linalg.norm(ref)))
+                errors["stack_batched_grad_rel_frobenius"] = gerr
             elif name.startswith("rank_one"):
                 got, ref = sampled(name, res)
                 errors[name + "_zero_sigma_max_rel"] = float(np.max(got[..., 9:] / got[..., :1]))
@@ -452,6 +469,8 @@ def main():
             "layers": 12, "loss": "sum of top-8 sigma per layer",
             "plain_layers_per_s": st["plain_layers_per_s"], "batched_layers_per_s": st["batched_layers_per_s"],
             "plain_ms": st["plain_ms"], "batched_ms": st["batched_ms"],
+            "batched": "HIP graph: persistent SVD with U, V of every symbol, top-8, one adjoint launch",
+            "batched_sigma_only_graph_ms": st["batched_sigma_only_ms"],
             "speedup_batched_vs_plain": st["batched_layers_per_s"] / st["plain_layers_per_s"]}
         note("ResNet-18 stack done")
     if sel("large"):

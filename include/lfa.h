@@ -230,6 +230,21 @@ int lfa_sigma_grad_persistent(const lfa_plan* plan, const void* const* W, const 
 int lfa_graph_create(lfa_plan* plan, const void* const* W, void* const* sigma, int32_t k,
                      void* vals, int32_t* idx, const void* grad, void* const* dW,
                      int32_t* info, void* ws, size_t ws_bytes, void* stream, lfa_graph** out);
+/* The same step with the forward pass keeping every symbol's singular
+ * vectors: [lfa_svd_persistent with U and V -> lfa_topk -> lfa_adjoint].
+ * The gradient then needs no second SVD of the selected symbols (the
+ * derivative of a simple singular value, Re(u^H dA v), takes only its own
+ * singular vectors).  That is faster when the largest symbols dominate (for
+ * instance the twelve 3x3 layers of ResNet-18 on 32x32 inputs), at the price
+ * of U and V storage for every symbol.
+ *   plan : must have both LFA_WANT_U and LFA_WANT_V (else UNSUPPORTED)
+ *   U, V : per-layer device outputs as for lfa_svd, required (INVALID_ARG
+ *          if NULL); they hold the last replay's singular vectors
+ * Other arguments, ownership and errors as lfa_graph_create. */
+int lfa_graph_create_uv(lfa_plan* plan, const void* const* W, void* const* sigma, void* const* U,
+                        void* const* V, int32_t k, void* vals, int32_t* idx, const void* grad,
+                        void* const* dW, int32_t* info, void* ws, size_t ws_bytes, void* stream,
+                        lfa_graph** out);
 int lfa_graph_launch(lfa_graph* graph, void* stream);
 int lfa_graph_destroy(lfa_graph* graph);
 

@@ -67,6 +67,7 @@ SIGNATURES = {
     "lfa_sigma_grad": (I32, [P, PP, P, P, I32, PP, P, SZ, P]),
     "lfa_sigma_grad_persistent": (I32, [P, PP, P, P, I32, PP, P, SZ, P]),
     "lfa_graph_create": (I32, [P, PP, PP, I32, P, P, P, PP, P, P, SZ, P, ctypes.POINTER(P)]),
+    "lfa_graph_create_uv": (I32, [P, PP, PP, PP, PP, I32, P, P, P, PP, P, P, SZ, P, ctypes.POINTER(P)]),
     "lfa_graph_launch": (I32, [P, P]),
     "lfa_graph_destroy": (I32, [P]),
     "lfa_autotune": (I32, [P, PP, PP, PP, PP, P, SZ, P]),

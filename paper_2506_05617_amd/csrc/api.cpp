@@ -1317,20 +1317,31 @@ int lfa_sigma_grad_persistent(const lfa_plan* plan, const void* const* W, const 
     return sigma_grad_persistent_impl<float>(p, W, idx, grad, k, dW, ws, st);
 }
 
-int lfa_graph_create(lfa_plan* plan, const void* const* W, void* const* sigma, int32_t k,
-                     void* vals, int32_t* idx, const void* grad, void* const* dW, int32_t* info,
-                     void* ws, size_t ws_bytes, void* stream, lfa_graph** out) {
+namespace {
+
+// Both graph forms: with U and V (null for the sigma-only form), the forward
+// pass keeps every symbol's singular vectors and the gradient is one adjoint
+// launch; without, the gradient recomputes the vectors of the picks.
+int graph_create(lfa_plan* plan, const void* const* W, void* const* sigma, void* const* U, void* const* V,
+                 int32_t k, void* vals, int32_t* idx, const void* grad, void* const* dW, int32_t* info,
+                 void* ws, size_t ws_bytes, void* stream, lfa_graph** out) {
     if (!out) return LFA_ERR_INVALID_ARG;
     *out = nullptr;
     if (!plan || !vals || !idx || !grad) return LFA_ERR_INVALID_ARG;
-    if (plan->flags & (LFA_WANT_U | LFA_WANT_V)) return LFA_ERR_UNSUPPORTED;
+    const bool uv = U != nullptr || V != nullptr;
+    const uint32_t want = plan->flags & (LFA_WANT_U | LFA_WANT_V);
+    if (want != (uv ? (LFA_WANT_U | LFA_WANT_V) : 0u)) return LFA_ERR_UNSUPPORTED;
     LFA_TRY(check_ptrs(plan, W, true));
     LFA_TRY(check_ptrs(plan, sigma, true));
     LFA_TRY(check_ptrs(plan, dW, true));
+    if (uv) {
+        LFA_TRY(check_ptrs(plan, U, true));
+        LFA_TRY(check_ptrs(plan, V, true));
+    }
     LFA_TRY(check_k(plan, k));
     LFA_TRY(check_ws(plan, ws, ws_bytes));
     LFA_TRY(ensure_device(plan));
-    LFA_TRY(ensure_grad_schedule(plan, k));   // uploads: not allowed while capturing
+    if (!uv) LFA_TRY(ensure_grad_schedule(plan, k));   // uploads: not allowed while capturing
     hipStream_t st = static_cast<hipStream_t>(stream);
     if (st == nullptr) return LFA_ERR_INVALID_ARG;   // cannot capture the legacy default stream
     lfa_graph* g = new (std::nothrow) lfa_graph();
@@ -1340,9 +1351,11 @@ int lfa_graph_create(lfa_plan* plan, const void* const* W, void* const* sigma, i
         delete g;
         return hip_fail(e);
     }
-    int s = lfa_svd_persistent(plan, W, sigma, nullptr, nullptr, info, ws, ws_bytes, stream);
+    int s = lfa_svd_persistent(plan, W, sigma, U, V, info, ws, ws_bytes, stream);
     if (s == LFA_OK) s = lfa_topk(plan, sigma, k, vals, idx, stream);
-    if (s == LFA_OK) s = lfa_sigma_grad_persistent(plan, W, idx, grad, k, dW, ws, ws_bytes, stream);
+    if (s == LFA_OK)
+        s = uv ? lfa_adjoint(plan, U, V, idx, grad, k, dW, stream)
+               : lfa_sigma_grad_persistent(plan, W, idx, grad, k, dW, ws, ws_bytes, stream);
     e = hipStreamEndCapture(st, &g->graph);
     if (s != LFA_OK || e != hipSuccess) {
         if (g->graph) (void)hipGraphDestroy(g->graph);
@@ -1357,6 +1370,26 @@ int lfa_graph_create(lfa_plan* plan, const void* const* W, void* const* sigma, i
     }
     *out = g;
     return LFA_OK;
+}
+
+}  // namespace
+
+int lfa_graph_create(lfa_plan* plan, const void* const* W, void* const* sigma, int32_t k,
+                     void* vals, int32_t* idx, const void* grad, void* const* dW, int32_t* info,
+                     void* ws, size_t ws_bytes, void* stream, lfa_graph** out) {
+    return graph_create(plan, W, sigma, nullptr, nullptr, k, vals, idx, grad, dW, info, ws, ws_bytes, stream,
+                        out);
+}
+
+int lfa_graph_create_uv(lfa_plan* plan, const void* const* W, void* const* sigma, void* const* U,
+                        void* const* V, int32_t k, void* vals, int32_t* idx, const void* grad,
+                        void* const* dW, int32_t* info, void* ws, size_t ws_bytes, void* stream,
+                        lfa_graph** out) {
+    if (!U || !V) {
+        if (out) *out = nullptr;
+        return LFA_ERR_INVALID_ARG;
+    }
+    return graph_create(plan, W, sigma, U, V, k, vals, idx, grad, dW, info, ws, ws_bytes, stream, out);
 }
 
 int lfa_graph_launch(lfa_graph* graph, void* stream) {

@@ -278,18 +278,24 @@ class Plan:
 
 
 class GraphStep:
-    """HIP graph of [persistent sigma-only SVD -> top-k -> sigma gradient] for
-    fixed buffers.  Copy new weights into ``self.W`` and call ``replay()``."""
+    """HIP graph of [persistent SVD -> top-k -> sigma gradient] for fixed
+    buffers.  Copy new weights into ``self.W`` and call ``replay()``.
+
+    With a sigma-only plan the gradient recomputes the singular vectors of the
+    picked symbols (lfa_graph_create).  With a plan that wants U and V the
+    forward pass keeps them for every symbol (``self.U``, ``self.V``) and the
+    gradient is one adjoint launch (lfa_graph_create_uv)."""
 
     def __init__(self, plan: Plan, Ws, k, grad=None, stream=None):
-        if plan.want_u or plan.want_v:
-            raise ValueError("graph step needs a sigma-only plan")
+        if plan.want_u != plan.want_v:
+            raise ValueError("graph step needs a sigma-only plan or one that wants both U and V")
         self.plan = plan
         dev = plan._check_weights(Ws)
         self.W = Ws
         self.k = k
         self.stream = stream if stream is not None else torch.cuda.Stream(device=dev)
-        self.S, _, _ = plan._alloc_outputs(dev, False, False)
+        uv = plan.want_u and plan.want_v
+        self.S, self.U, self.V = plan._alloc_outputs(dev, uv, uv)
         L = len(plan.layers)
         self.vals = torch.empty(L, k, dtype=plan.dtype, device=dev)
         self.idx = torch.empty(L, k, 3, dtype=torch.int32, device=dev)
@@ -305,12 +311,18 @@ class GraphStep:
         self._keep += [k0, k1, k2, ws]
         h = ctypes.c_void_p()
         torch.cuda.synchronize(dev)
-        check(plan.lib.lfa_graph_create(
-            plan.handle, w_arr, s_arr, k, ctypes.c_void_p(self.vals.data_ptr()),
-            ctypes.c_void_p(self.idx.data_ptr()), ctypes.c_void_p(self.grad.data_ptr()), d_arr,
-            ctypes.c_void_p(self.info.data_ptr()), ctypes.c_void_p(ws.data_ptr()),
-            ctypes.c_size_t(ws.numel()), ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h)),
-            "lfa_graph_create")
+        tail = (k, ctypes.c_void_p(self.vals.data_ptr()), ctypes.c_void_p(self.idx.data_ptr()),
+                ctypes.c_void_p(self.grad.data_ptr()), d_arr, ctypes.c_void_p(self.info.data_ptr()),
+                ctypes.c_void_p(ws.data_ptr()), ctypes.c_size_t(ws.numel()),
+                ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h))
+        if uv:
+            u_arr, k3 = ptr_array([x.data_ptr() for x in self.U])
+            v_arr, k4 = ptr_array([x.data_ptr() for x in self.V])
+            self._keep += [k3, k4]
+            check(plan.lib.lfa_graph_create_uv(plan.handle, w_arr, s_arr, u_arr, v_arr, *tail),
+                  "lfa_graph_create_uv")
+        else:
+            check(plan.lib.lfa_graph_create(plan.handle, w_arr, s_arr, *tail), "lfa_graph_create")
         self.handle = h
 
     def replay(self):

@@ -26,7 +26,7 @@ def declared_functions():
 def test_header_declares_the_documented_entry_points():
     names = declared_functions()
     for must in ["lfa_plan_create", "lfa_symbols", "lfa_svd", "lfa_svd_persistent", "lfa_topk",
-                 "lfa_adjoint", "lfa_sigma_grad", "lfa_graph_create", "lfa_autotune",
+                 "lfa_adjoint", "lfa_sigma_grad", "lfa_graph_create", "lfa_graph_create_uv", "lfa_autotune",
                  "lfa_status_string"]:
         assert must in names
     assert set(names) == set(_lib.SIGNATURES), "binding and header disagree"
@@ -104,6 +104,18 @@ def test_compute_calls_reject_bad_arguments_before_touching_the_gpu():
     # k out of range
     assert lib.lfa_topk(plan.handle, one, 0, ctypes.c_void_p(1), ctypes.c_void_p(1), None) == -1
     assert lib.lfa_topk(plan.handle, one, 65, ctypes.c_void_p(1), ctypes.c_void_p(1), None) == -1
+    # graph forms: the vectors form needs U and V and a plan that wants both,
+    # the sigma-only form a plan that wants neither
+    h = ctypes.c_void_p()
+    c1 = ctypes.c_void_p(1)
+    uv = lfa.Plan([lfa.LayerSpec(8, 8, 3, 3, 8, 8)], want_u=True, want_v=True)
+    assert lib.lfa_graph_create_uv(plan.handle, one, one, one, one, 8, c1, c1, c1, one, None, c1,
+                                   1 << 30, c1, ctypes.byref(h)) == -2
+    assert lib.lfa_graph_create_uv(uv.handle, one, one, None, one, 8, c1, c1, c1, one, None, c1,
+                                   1 << 30, c1, ctypes.byref(h)) == -1
+    assert lib.lfa_graph_create(uv.handle, one, one, 8, c1, c1, c1, one, None, c1, 1 << 30, c1,
+                                ctypes.byref(h)) == -2
+    assert h.value is None
 
 
 @needs_lib

@@ -469,6 +469,35 @@ def test_graph_replay_matches_eager():
             assert float(torch.linalg.norm(a - b)) <= 1e-3 * float(torch.linalg.norm(b))
 
 
+def test_graph_with_vectors_replay_matches_eager():
+    """The graph that keeps every symbol's U and V (lfa_graph_create_uv):
+    three replays with new weights in between, each against the eager
+    sigma-only path (sigma, top-8 values, and dW from the recomputed
+    vectors of the picks)."""
+    banner("graph replay with vectors")
+    layers, Ws = _small_stack(seed=23)
+    specs = [lfa().LayerSpec(l.c_out, l.c_in, l.kh, l.kw, l.n, l.m) for l in layers]
+    plan = lfa().Plan(specs)
+    plan_uv = lfa().Plan(specs, want_u=True, want_v=True)
+    Wt = [_w(W) for W in Ws]
+    step = lfa().GraphStep(plan_uv, Wt, 8)
+    rng = np.random.default_rng(6)
+    for rep in range(3):
+        for W in Wt:
+            W.copy_(torch.from_numpy(rng.standard_normal(tuple(W.shape)).astype(np.float32) * 0.1))
+        st = step.replay()
+        st.synchronize()
+        S, _, _, _ = plan.svd(Wt, persistent=False)
+        vals, idx = plan.topk(S, 8)
+        dW = plan.sigma_grad(Wt, idx, torch.ones(len(specs), 8, device=DEV))
+        torch.cuda.synchronize()
+        for a, b in zip(step.S, S):
+            np.testing.assert_allclose(to_np(a), to_np(b), rtol=1e-5, atol=1e-6 * float(b.max()))
+        np.testing.assert_allclose(to_np(step.vals), to_np(vals), rtol=1e-5)
+        for a, b in zip(step.dW, dW):
+            assert float(torch.linalg.norm(a - b)) <= 1e-3 * float(torch.linalg.norm(b)), rep
+
+
 # ------------------------------------------------- spectral functions --
 
 APPLY_GPU_CASES = [
@@ -854,6 +883,38 @@ def test_resnet18_stack_full_size():
         assert np.max(np.abs(vals[li] - s_at)) <= 1e-5 * s_at.max(), li
         ref = oracle.sigma_grad(W64, l.n, l.m, idx[li], np.ones(8))
         assert np.linalg.norm(to_np(dW[li]) - ref) / np.linalg.norm(ref) <= 1e-3, li
+
+
+def test_resnet18_stack_full_size_vectors_graph():
+    """The benchmark's batched step as it runs: one HIP graph of the
+    persistent SVD keeping every symbol's U and V, top-8 per layer and one
+    adjoint launch, replayed twice with eager work in between.  Each replay:
+    top-8 values equal to the oracle's singular values at the chosen
+    (p, q, j), and dW against the oracle's gradient for those picks."""
+    banner("ResNet-18 stack full size, graph with vectors")
+    layers, Ws = workloads.resnet18_stack()
+    specs = [lfa().LayerSpec(l.c_out, l.c_in, l.kh, l.kw, l.n, l.m) for l in layers]
+    plan = lfa().Plan(specs, want_u=True, want_v=True)
+    Wt = [_w(W) for W in Ws]
+    step = lfa().GraphStep(plan, Wt, 8)
+    refs = {}
+    for rep in range(2):
+        step.replay().synchronize()
+        assert int(to_np(step.info)[:, 0].sum()) == 0
+        vals, idx = to_np(step.vals), to_np(step.idx)
+        for li, l in enumerate(layers):
+            W64 = Ws[li].astype(np.float64)
+            p, q, j = idx[li].T
+            s_at = oracle.lfa_svd(W64, l.n, l.m, freqs=np.stack([p, q], axis=1))[np.arange(8), j]
+            assert np.max(np.abs(vals[li] - s_at)) <= 1e-5 * s_at.max(), (rep, li)
+            key = (li, idx[li].tobytes())
+            if key not in refs:
+                refs[key] = oracle.sigma_grad(W64, l.n, l.m, idx[li], np.ones(8))
+            ref = refs[key]
+            assert np.linalg.norm(to_np(step.dW[li]) - ref) / np.linalg.norm(ref) <= 1e-3, (rep, li)
+        # eager work between the replays
+        plan.topk(step.S, 8)
+        torch.cuda.synchronize()
 
 
 @pytest.mark.parametrize("asm", [None, "bf16x2", "bf16x3"])
