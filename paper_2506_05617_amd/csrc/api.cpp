@@ -522,6 +522,11 @@ int run_svd_layer(const lfa_plan* p, const LayerDesc& d, const void* W, const vo
         if (cap >= 2 && 2 * count <= cap) {
             W = std::max(1, std::min(NBP / 2, cap / count));
             teams = W > 1 ? std::min(count, cap / W) : teams;
+        } else if (count < cap && 2 * count <= resident && NBP >= 4) {
+            // between half a device and a device of symbols: pairs, a few
+            // CUs holding two work-groups, instead of half the CUs idle
+            W = 2;
+            teams = count;
         }
         int32_t* counters = reinterpret_cast<int32_t*>(region);
         a.gws = region + kCounterBytes;
