@@ -36,9 +36,14 @@
  *    dtype LFA_F64: double / complex double throughout.
  *  - Every array argument that is "per layer" is a host array of num_layers
  *    device pointers.  All device buffers are allocated and owned by the
- *    caller; the library never allocates device memory inside a compute call.
- *    lfa_plan_create allocates small constant tables (twiddles, work lists)
- *    that lfa_plan_destroy frees.
+ *    caller.  The plan owns small constant tables (twiddles, work lists),
+ *    uploaded to a device by lfa_plan_create when a gfx950 device is
+ *    current, else by lfa_plan_prepare or on the plan's first compute call
+ *    (and, for lfa_sigma_grad_persistent, on the first call with a new k);
+ *    lfa_plan_destroy frees them.  Apart from those first-use uploads, which
+ *    a prepared plan never makes (under stream capture a compute call
+ *    returns LFA_ERR_NOT_PREPARED rather than upload), compute calls
+ *    allocate no device memory.
  *  - `stream` is a hipStream_t passed as void* (NULL = default stream).  All
  *    compute calls are asynchronous on that stream; the return value covers
  *    only the checks made at enqueue time.
@@ -91,7 +96,18 @@ enum lfa_status {
     LFA_ERR_UNSUPPORTED = -2, /* dtype/flag combination or size not supported  */
     LFA_ERR_WORKSPACE = -3,   /* workspace missing or smaller than required    */
     LFA_ERR_HIP = -4,         /* a HIP runtime call or kernel launch failed    */
-    LFA_ERR_NO_DEVICE = -5    /* no usable gfx950 device                       */
+    LFA_ERR_NO_DEVICE = -5,   /* no usable gfx950 device                       */
+    LFA_ERR_NOT_PREPARED = -6,/* the call would have to upload device tables
+                                 (first use on a device, or a new k for the
+                                 persistent gradient) while its stream is
+                                 capturing a graph: call lfa_plan_prepare first */
+    /* Warnings (> 0, a bit set) returned by lfa_info_status once the
+     * results are on the host: the outputs are written either way. */
+    LFA_WARN_NOT_CONVERGED = 1, /* some symbol hit the plan's sweep cap        */
+    LFA_WARN_NONFINITE = 2,     /* some singular value is NaN or infinite
+                                   (non-finite weights)                        */
+    LFA_WARN_TEAM_TIMEOUT = 4   /* a work-group team's barrier gave up waiting
+                                   (that layer's results are not valid)        */
 };
 
 /* Per-layer convergence record written by the SVD entry points into the
@@ -101,17 +117,27 @@ enum lfa_info_word {
     LFA_INFO_NONCONVERGED = 0, /* symbols that hit the sweep cap               */
     LFA_INFO_MAX_SWEEPS = 1,   /* largest number of sweeps used by a symbol    */
     LFA_INFO_SUM_SWEEPS = 2,   /* total sweeps over the layer's symbols        */
-    LFA_INFO_NONFINITE = 3,    /* symbols with a non-finite entry              */
+    LFA_INFO_NONFINITE = 3,    /* bit 1: a singular value of the layer is not
+                                  finite; bit 2: a team barrier timed out      */
     LFA_INFO_WORDS = 4
 };
+
+/* Warnings of a finished call, from a host copy of its `info` record
+ * ([num_layers][LFA_INFO_WORDS]): LFA_OK, or the OR of the LFA_WARN_* bits
+ * that apply to any layer.  This is how a non-converged or non-finite
+ * result is reported: the compute calls themselves are asynchronous, so
+ * their return value cannot.  Errors: LFA_ERR_INVALID_ARG (NULL, num_layers
+ * < 1).  Host only. */
+int lfa_info_status(const int32_t* info, int32_t num_layers);
 
 /* ---- plans -------------------------------------------------------------- */
 
 /* Validate the layers and build a plan: size class and launch shape of each
  * layer, the work list of the persistent batched launch, and device twiddle
  * tables exp(2 pi i j / n) computed on the host in double precision (the grid
- * of Algorithm 1's Init step).  Device tables are uploaded to the current
- * device on first use, so this call itself needs no GPU.
+ * of Algorithm 1's Init step).  The device tables are uploaded to the
+ * current device when it is a gfx950 device, else on first use (see
+ * lfa_plan_prepare), so this call itself needs no GPU.
  *   out        : receives the plan (set to NULL on error)
  *   layers     : host array of num_layers descriptors (copied)
  *   num_layers : >= 1
@@ -122,6 +148,26 @@ enum lfa_info_word {
  * does not fit the dtype. */
 int lfa_plan_create(lfa_plan** out, const lfa_layer* layers, int32_t num_layers,
                     int32_t dtype, uint32_t flags);
+
+/* Upload the plan's device tables (twiddles, persistent work list) to the
+ * current device and, for k > 0, build and upload the work list of
+ * lfa_sigma_grad_persistent for that k.  lfa_plan_create already does the
+ * first when a gfx950 device is current; compute calls do both on first
+ * use.  Needed before capturing calls of a plan into a graph on a device
+ * where the plan has not run yet (or with a new k): under stream capture the
+ * compute calls allocate nothing and return LFA_ERR_NOT_PREPARED instead.
+ * Synchronous; allocates small device tables freed by lfa_plan_destroy.
+ * Errors: LFA_ERR_INVALID_ARG (NULL, k < 0, k invalid as for lfa_topk, or a
+ * device other than the one the plan was prepared on), LFA_ERR_NO_DEVICE,
+ * LFA_ERR_HIP. */
+int lfa_plan_prepare(lfa_plan* plan, int32_t k);
+
+/* Lower the plan's cap on Jacobi sweeps per symbol (1 .. 40; the default is
+ * 40).  A symbol that reaches the cap stops there, its results are written
+ * from the last sweep, and it is counted in LFA_INFO_NONCONVERGED (see
+ * lfa_info_status).  Call it before compute calls on the plan, not
+ * concurrently with them.  Errors: LFA_ERR_INVALID_ARG. */
+int lfa_plan_set_max_sweeps(lfa_plan* plan, int32_t max_sweeps);
 
 /* Free the plan and its device tables.  NULL is accepted. */
 int lfa_plan_destroy(lfa_plan* plan);
@@ -214,8 +260,9 @@ int lfa_sigma_grad(const lfa_plan* plan, const void* const* W, const int32_t* id
 /* Same result as lfa_sigma_grad in two launches for all layers: one
  * persistent launch computes the singular vectors of the k selected symbols
  * of every layer (work-group teams share the large symbols), then one adjoint
- * launch.  The work list for a given k is built and uploaded on the first
- * call with that k (synchronously). */
+ * launch.  The work list for a given k is built and uploaded by
+ * lfa_plan_prepare(plan, k), or on the first call with that k
+ * (synchronously; LFA_ERR_NOT_PREPARED under stream capture). */
 int lfa_sigma_grad_persistent(const lfa_plan* plan, const void* const* W, const int32_t* idx,
                               const void* grad, int32_t k, void* const* dW, void* ws,
                               size_t ws_bytes, void* stream);

@@ -247,8 +247,9 @@ def fourier_basis(n: int, m: int, p: int, q: int, c: int) -> np.ndarray:
     """Orthonormal Fourier modes of one frequency on the crystal torus with c
     collocated channels (Sec. III "Convolution Theorem"): column ``i`` is
     ``e^{2 pi i <k, x>} e_i / sqrt(n m)``.  Shape ``(n*m*c, c)``."""
+    k = frequency_grid(n, m)[p, q]
     x1, x2 = np.meshgrid(np.arange(n), np.arange(m), indexing="ij")
-    wave = np.exp(2j * np.pi * (p * x1 / n + q * x2 / m)).ravel() / np.sqrt(n * m)
+    wave = np.exp(2j * np.pi * (k[0] * x1 + k[1] * x2)).ravel() / np.sqrt(n * m)
     F = np.zeros((n * m * c, c), dtype=np.complex128)
     for i in range(c):
         F[i::c, i] = wave

@@ -33,6 +33,11 @@ LFA_ERR_UNSUPPORTED = -2
 LFA_ERR_WORKSPACE = -3
 LFA_ERR_HIP = -4
 LFA_ERR_NO_DEVICE = -5
+LFA_ERR_NOT_PREPARED = -6
+
+LFA_WARN_NOT_CONVERGED = 1
+LFA_WARN_NONFINITE = 2
+LFA_WARN_TEAM_TIMEOUT = 4
 
 LFA_INFO_NONCONVERGED = 0
 LFA_INFO_MAX_SWEEPS = 1
@@ -55,6 +60,9 @@ SZ = ctypes.c_size_t
 SIGNATURES = {
     "lfa_plan_create": (I32, [ctypes.POINTER(P), ctypes.POINTER(LfaLayer), I32, I32, ctypes.c_uint32]),
     "lfa_plan_destroy": (I32, [P]),
+    "lfa_plan_prepare": (I32, [P, I32]),
+    "lfa_plan_set_max_sweeps": (I32, [P, I32]),
+    "lfa_info_status": (I32, [I32P, I32]),
     "lfa_plan_workspace_bytes": (I32, [P, ctypes.POINTER(SZ)]),
     "lfa_plan_num_layers": (I32, [P, I32P]),
     "lfa_plan_layer": (I32, [P, I32, ctypes.POINTER(LfaLayer)]),

@@ -82,6 +82,7 @@ struct lfa_plan {
     std::vector<WorkItem> items;          // persistent work list, LPT order per chunk
     std::vector<int> chunk_first;         // first item of each chunk of layers (+ end)
     double tol = 0;
+    int max_sweeps = kMaxSweeps;          // sweep cap (lfa_plan_set_max_sweeps)
     int wq_force = -1;                    // work queue: -1 automatic, 0 off, k > 0 forced
     std::mutex mu;
     int device = -1;
@@ -397,8 +398,17 @@ void build_schedule(lfa_plan* p) {
     p->chunk_first.push_back((int)p->items.size());
 }
 
-// Upload device tables on first use from the current device.
-int ensure_device(lfa_plan* p) {
+// A stream that is capturing a graph: uploads (hipMalloc, synchronous
+// copies) are not allowed there.
+bool capturing(hipStream_t st) {
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    return hipStreamIsCapturing(st, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone;
+}
+
+// Upload device tables on the plan's first use on the current device (or
+// in lfa_plan_create / lfa_plan_prepare).  A compute call whose stream is
+// capturing gets LFA_ERR_NOT_PREPARED instead of an upload.
+int ensure_device(lfa_plan* p, hipStream_t st = nullptr, bool check_capture = false) {
     std::lock_guard<std::mutex> lock(p->mu);
     int dev = -1;
     int count = 0;
@@ -409,6 +419,7 @@ int ensure_device(lfa_plan* p) {
     }
     HIP_TRY(hipGetDevice(&dev));
     if (p->device >= 0) return p->device == dev ? LFA_OK : LFA_ERR_INVALID_ARG;
+    if (check_capture && capturing(st)) return LFA_ERR_NOT_PREPARED;
     hipDeviceProp_t prop;
     HIP_TRY(hipGetDeviceProperties(&prop, dev));
     if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0) return LFA_ERR_NO_DEVICE;
@@ -462,7 +473,7 @@ int run_svd_layer(const lfa_plan* p, const LayerDesc& d, const void* W, const vo
     a.theta_stride = theta_stride;
     a.theta_count = theta_count;
     a.theta_dedup = theta_list != nullptr && theta_stride == 3;   // top-k picks
-    a.max_sweeps = kMaxSweeps;
+    a.max_sweeps = p->max_sweeps;
     a.tol = jacobi_tol(p->tol, d.M);
     const bool acc = (d.transposed ? U : V) != nullptr;
     const int count = item_count(a);
@@ -569,7 +580,7 @@ int check_ws(const lfa_plan* p, void* ws, size_t ws_bytes) {
 template <typename R>
 int svd_impl(const lfa_plan* p, const void* const* W, const void* const* A, void* const* sigma,
              void* const* U, void* const* V, int32_t* info, void* ws, size_t ws_bytes,
-             hipStream_t st) {
+             hipStream_t st, bool queue_ok = true) {
     const bool wu = p->flags & LFA_WANT_U, wv = p->flags & LFA_WANT_V;
     char* region = static_cast<char*>(ws) + kAlign;
     if (info) HIP_TRY(launch_fill_i32(info, 0, (long long)p->layers.size() * LFA_INFO_WORDS, st));
@@ -595,7 +606,7 @@ int svd_impl(const lfa_plan* p, const void* const* W, const void* const* A, void
         LFA_TRY(run_svd_layer<R>(p, d, Wi, Ai, sigma[i], wu ? U[i] : nullptr,
                                  wv ? V[i] : nullptr,
                                  info ? info + i * LFA_INFO_WORDS : nullptr, slots, nullptr, 0, 0,
-                                 st, canon));
+                                 st, canon, queue_ok));
     }
     return LFA_OK;
 }
@@ -635,7 +646,7 @@ int persistent_impl(const lfa_plan* p, const void* const* W, void* const* sigma,
             a.V = wv ? static_cast<cplx<R>*>(V[i]) : nullptr;
             a.info = info ? info + i * LFA_INFO_WORDS : nullptr;
             a.tw = p->tw_dev;
-            a.max_sweeps = kMaxSweeps;
+            a.max_sweeps = p->max_sweeps;
             a.tol = jacobi_tol(p->tol, d.M);
             a.canon = 1;
             if (d.kind == 2) {
@@ -766,9 +777,18 @@ int topk_impl(const lfa_plan* p, const void* const* sigma, int k, void* vals, in
 
 // Work list of the persistent SVD of the k selected symbols of every layer
 // (with vectors, blocked kernel), same cost model as build_schedule.
-int ensure_grad_schedule(lfa_plan* p, int k) {
+// The schedule for k, built and uploaded on first use.  `out` points into
+// the plan's map, whose nodes never move or change once inserted; the lookup
+// itself runs under the plan's lock.
+int ensure_grad_schedule(lfa_plan* p, int k, hipStream_t st, bool check_capture,
+                         const lfa_plan::GradSched** out) {
     std::lock_guard<std::mutex> lock(p->mu);
-    if (p->grad_sched.count(k)) return LFA_OK;
+    auto it = p->grad_sched.find(k);
+    if (it != p->grad_sched.end()) {
+        if (out) *out = &it->second;
+        return LFA_OK;
+    }
+    if (check_capture && capturing(st)) return LFA_ERR_NOT_PREPARED;
     lfa_plan::GradSched gs;
     const int eb = elem_bytes(p->dtype);
     const int nl = (int)p->layers.size();
@@ -814,16 +834,17 @@ int ensure_grad_schedule(lfa_plan* p, int k) {
     if (!items.empty())
         HIP_TRY(hipMemcpy(gs.items_dev, items.data(), items.size() * sizeof(WorkItem),
                           hipMemcpyHostToDevice));
-    p->grad_sched[k] = gs;
+    auto ins = p->grad_sched.emplace(k, gs).first;
+    if (out) *out = &ins->second;
     return LFA_OK;
 }
 
 // Sigma gradient in two launches: one persistent SVD-with-vectors of the
 // selected symbols of all layers (compact outputs), then one adjoint launch.
 template <typename R>
-int sigma_grad_persistent_impl(const lfa_plan* p, const void* const* W, const int32_t* idx,
-                               const void* grad, int k, void* const* dW, void* ws, hipStream_t st) {
-    const lfa_plan::GradSched& gs = p->grad_sched.at(k);
+int sigma_grad_persistent_impl(const lfa_plan* p, const lfa_plan::GradSched& gs, const void* const* W,
+                               const int32_t* idx, const void* grad, int k, void* const* dW, void* ws,
+                               hipStream_t st) {
     const int nl = (int)p->layers.size();
     const int eb = sizeof(R);
     int32_t* counter = static_cast<int32_t*>(ws);
@@ -859,7 +880,7 @@ int sigma_grad_persistent_impl(const lfa_plan* p, const void* const* W, const in
             a.U = static_cast<cplx<R>*>(Uc[i]);
             a.V = static_cast<cplx<R>*>(Vc[i]);
             a.tw = p->tw_dev;
-            a.max_sweeps = kMaxSweeps;
+            a.max_sweeps = p->max_sweeps;
             a.tol = jacobi_tol(p->tol, d.M);
             a.theta_list = idx + (size_t)i * k * 3;
             a.theta_stride = 3;
@@ -922,6 +943,10 @@ const char* lfa_status_string(int status) {
         case LFA_ERR_WORKSPACE: return "workspace missing or too small";
         case LFA_ERR_HIP: return "HIP runtime error (see lfa_last_hip_error)";
         case LFA_ERR_NO_DEVICE: return "no usable gfx950 device";
+        case LFA_ERR_NOT_PREPARED: return "plan not prepared on this device (needed under stream capture)";
+        case LFA_WARN_NOT_CONVERGED: return "warning: some symbols hit the sweep cap";
+        case LFA_WARN_NONFINITE: return "warning: non-finite singular values";
+        case LFA_WARN_TEAM_TIMEOUT: return "warning: a work-group team barrier timed out";
         default: return "unknown status";
     }
 }
@@ -1013,6 +1038,13 @@ int lfa_plan_create(lfa_plan** out, const lfa_layer* layers, int32_t num_layers,
             p->pers_slot_off.push_back(0);
         }
     }
+    // device tables on the current device now, when there is a gfx950 one
+    // (otherwise on first use, or in lfa_plan_prepare)
+    {
+        int count = 0;
+        if (hipGetDeviceCount(&count) == hipSuccess && count > 0) (void)ensure_device(p);
+        else (void)hipGetLastError();
+    }
     *out = p;
     return LFA_OK;
 }
@@ -1025,6 +1057,35 @@ int lfa_plan_destroy(lfa_plan* plan) {
         if (kv.second.items_dev) (void)hipFree(kv.second.items_dev);
     delete plan;
     return LFA_OK;
+}
+
+int lfa_plan_prepare(lfa_plan* plan, int32_t k) {
+    if (!plan || k < 0) return LFA_ERR_INVALID_ARG;
+    LFA_TRY(ensure_device(plan));
+    if (k > 0) {
+        LFA_TRY(check_k(plan, k));
+        LFA_TRY(ensure_grad_schedule(plan, k, nullptr, false, nullptr));
+    }
+    return LFA_OK;
+}
+
+int lfa_plan_set_max_sweeps(lfa_plan* plan, int32_t max_sweeps) {
+    if (!plan || max_sweeps < 1 || max_sweeps > kMaxSweeps) return LFA_ERR_INVALID_ARG;
+    std::lock_guard<std::mutex> lock(plan->mu);
+    plan->max_sweeps = max_sweeps;
+    return LFA_OK;
+}
+
+int lfa_info_status(const int32_t* info, int32_t num_layers) {
+    if (!info || num_layers < 1) return LFA_ERR_INVALID_ARG;
+    int w = 0;
+    for (int i = 0; i < num_layers; ++i) {
+        const int32_t* r = info + (size_t)i * LFA_INFO_WORDS;
+        if (r[LFA_INFO_NONCONVERGED] > 0) w |= LFA_WARN_NOT_CONVERGED;
+        if (r[LFA_INFO_NONFINITE] & 1) w |= LFA_WARN_NONFINITE;
+        if (r[LFA_INFO_NONFINITE] & 2) w |= LFA_WARN_TEAM_TIMEOUT;
+    }
+    return w;
 }
 
 int lfa_plan_workspace_bytes(const lfa_plan* plan, size_t* bytes) {
@@ -1088,7 +1149,7 @@ int lfa_apply(const lfa_plan* plan, int32_t layer, const void* sigma, const void
     LFA_TRY(lfa_apply_workspace_bytes(plan, layer, batch, &need));
     if (!ws || ws_bytes < need) return LFA_ERR_WORKSPACE;
     lfa_plan* p = const_cast<lfa_plan*>(plan);
-    LFA_TRY(ensure_device(p));
+    LFA_TRY(ensure_device(p, static_cast<hipStream_t>(stream), true));
     const lfa_layer& l = p->layers[layer];
     const bool pinv = kind == LFA_SPECTRAL_PINV;
     if (!apply_supported(pinv ? l.c_out : l.c_in, std::min(l.c_out, l.c_in), elem_bytes(p->dtype)))
@@ -1173,7 +1234,7 @@ int lfa_lift(const lfa_plan* plan, int32_t layer, const void* U, const void* V, 
     const lfa_layer& l0 = plan->layers[layer];
     if ((long long)count * std::max(l0.c_out, l0.c_in) > 0x7fffffffLL) return LFA_ERR_UNSUPPORTED;
     lfa_plan* p = const_cast<lfa_plan*>(plan);
-    LFA_TRY(ensure_device(p));
+    LFA_TRY(ensure_device(p, static_cast<hipStream_t>(stream), true));
     const lfa_layer& l = p->layers[layer];
     LiftArgs a{};
     a.count = count;
@@ -1200,8 +1261,8 @@ int lfa_symbols(const lfa_plan* plan, const void* const* W, void* const* A, void
     LFA_TRY(check_ptrs(plan, W, true));
     LFA_TRY(check_ptrs(plan, A, true));
     lfa_plan* p = const_cast<lfa_plan*>(plan);
-    LFA_TRY(ensure_device(p));
     hipStream_t st = static_cast<hipStream_t>(stream);
+    LFA_TRY(ensure_device(p, st, true));
     for (size_t i = 0; i < p->layers.size(); ++i) {
         const LayerDesc& d = p->desc[i];
         hipError_t e;
@@ -1231,8 +1292,8 @@ static int svd_common(const lfa_plan* plan, const void* const* W, const void* co
     if (persistent && asm_materialized(plan->flags)) return LFA_ERR_UNSUPPORTED;
     LFA_TRY(check_ws(plan, ws, ws_bytes));
     lfa_plan* p = const_cast<lfa_plan*>(plan);
-    LFA_TRY(ensure_device(p));
     hipStream_t st = static_cast<hipStream_t>(stream);
+    LFA_TRY(ensure_device(p, st, true));
     if (persistent) {
         if (p->dtype == LFA_F64) return persistent_impl<double>(p, W, sigma, U, V, info, ws, st);
         return persistent_impl<float>(p, W, sigma, U, V, info, ws, st);
@@ -1267,8 +1328,8 @@ int lfa_topk(const lfa_plan* plan, const void* const* sigma, int32_t k, void* va
     LFA_TRY(check_ptrs(plan, sigma, true));
     LFA_TRY(check_k(plan, k));
     lfa_plan* p = const_cast<lfa_plan*>(plan);
-    LFA_TRY(ensure_device(p));
     hipStream_t st = static_cast<hipStream_t>(stream);
+    LFA_TRY(ensure_device(p, st, true));
     if (p->dtype == LFA_F64) return topk_impl<double>(p, sigma, k, vals, idx, st);
     return topk_impl<float>(p, sigma, k, vals, idx, st);
 }
@@ -1281,8 +1342,8 @@ int lfa_adjoint(const lfa_plan* plan, const void* const* U, const void* const* V
     LFA_TRY(check_ptrs(plan, dW, true));
     LFA_TRY(check_k(plan, k));
     lfa_plan* p = const_cast<lfa_plan*>(plan);
-    LFA_TRY(ensure_device(p));
     hipStream_t st = static_cast<hipStream_t>(stream);
+    LFA_TRY(ensure_device(p, st, true));
     const int nl = (int)p->layers.size();
     for (int l0 = 0; l0 < nl; l0 += kMaxLaunchLayers) {
         const int l1 = std::min(nl, l0 + kMaxLaunchLayers);
@@ -1300,8 +1361,8 @@ int lfa_sigma_grad(const lfa_plan* plan, const void* const* W, const int32_t* id
     LFA_TRY(check_k(plan, k));
     LFA_TRY(check_ws(plan, ws, ws_bytes));
     lfa_plan* p = const_cast<lfa_plan*>(plan);
-    LFA_TRY(ensure_device(p));
     hipStream_t st = static_cast<hipStream_t>(stream);
+    LFA_TRY(ensure_device(p, st, true));
     if (p->dtype == LFA_F64) return sigma_grad_impl<double>(p, W, idx, grad, k, dW, ws, st);
     return sigma_grad_impl<float>(p, W, idx, grad, k, dW, ws, st);
 }
@@ -1315,11 +1376,12 @@ int lfa_sigma_grad_persistent(const lfa_plan* plan, const void* const* W, const 
     LFA_TRY(check_k(plan, k));
     LFA_TRY(check_ws(plan, ws, ws_bytes));
     lfa_plan* p = const_cast<lfa_plan*>(plan);
-    LFA_TRY(ensure_device(p));
-    LFA_TRY(ensure_grad_schedule(p, k));
     hipStream_t st = static_cast<hipStream_t>(stream);
-    if (p->dtype == LFA_F64) return sigma_grad_persistent_impl<double>(p, W, idx, grad, k, dW, ws, st);
-    return sigma_grad_persistent_impl<float>(p, W, idx, grad, k, dW, ws, st);
+    LFA_TRY(ensure_device(p, st, true));
+    const lfa_plan::GradSched* gs = nullptr;
+    LFA_TRY(ensure_grad_schedule(p, k, st, true, &gs));
+    if (p->dtype == LFA_F64) return sigma_grad_persistent_impl<double>(p, *gs, W, idx, grad, k, dW, ws, st);
+    return sigma_grad_persistent_impl<float>(p, *gs, W, idx, grad, k, dW, ws, st);
 }
 
 namespace {
@@ -1345,9 +1407,10 @@ int graph_create(lfa_plan* plan, const void* const* W, void* const* sigma, void*
     }
     LFA_TRY(check_k(plan, k));
     LFA_TRY(check_ws(plan, ws, ws_bytes));
-    LFA_TRY(ensure_device(plan));
-    if (!uv) LFA_TRY(ensure_grad_schedule(plan, k));   // uploads: not allowed while capturing
     hipStream_t st = static_cast<hipStream_t>(stream);
+    // uploads are not allowed while capturing: do them now
+    LFA_TRY(ensure_device(plan, st, true));
+    if (!uv) LFA_TRY(ensure_grad_schedule(plan, k, st, true, nullptr));
     if (st == nullptr) return LFA_ERR_INVALID_ARG;   // cannot capture the legacy default stream
     lfa_graph* g = new (std::nothrow) lfa_graph();
     if (!g) return LFA_ERR_INVALID_ARG;

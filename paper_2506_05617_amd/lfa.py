@@ -87,6 +87,24 @@ class Plan:
             self.lib.lfa_plan_destroy(h)
             self.handle = None
 
+    def prepare(self, k=0):
+        """Upload the plan's device tables to the current device (and the
+        persistent gradient's work list for k > 0) ahead of graph capture
+        (lfa_plan_prepare)."""
+        check(self.lib.lfa_plan_prepare(self.handle, int(k)), "lfa_plan_prepare")
+
+    def set_max_sweeps(self, max_sweeps):
+        """Cap on Jacobi sweeps per symbol (1 .. 40) for later calls."""
+        check(self.lib.lfa_plan_set_max_sweeps(self.handle, int(max_sweeps)), "lfa_plan_set_max_sweeps")
+
+    def info_status(self, info):
+        """Warnings of a finished call from its info record [L, 4]: 0, or the
+        OR of LFA_WARN_NOT_CONVERGED / _NONFINITE / _TEAM_TIMEOUT
+        (lfa_info_status)."""
+        host = info.detach().to("cpu", torch.int32).contiguous()
+        return check(self.lib.lfa_info_status(ctypes.cast(host.data_ptr(), _lib.I32P), host.shape[0]),
+                     "lfa_info_status")
+
     def workspace(self, device):
         if self._ws is None or self._ws.device != device:
             self._ws = torch.empty(max(self.ws_bytes, 256), dtype=torch.uint8, device=device)
@@ -303,7 +321,10 @@ class GraphStep:
                      else grad.to(plan.dtype).contiguous())
         self.dW = [torch.empty_like(W) for W in Ws]
         self.info = torch.zeros(L, _lib.LFA_INFO_WORDS, dtype=torch.int32, device=dev)
-        ws = plan.workspace(dev)
+        # a workspace of its own: replays run on self.stream and must not
+        # share counters and slots with eager calls on the plan
+        ws = torch.empty(max(plan.ws_bytes, 256), dtype=torch.uint8, device=dev)
+        self._done = torch.cuda.Event()
         self._keep = []
         w_arr, k0 = ptr_array([x.data_ptr() for x in Ws])
         s_arr, k1 = ptr_array([x.data_ptr() for x in self.S])
@@ -326,9 +347,15 @@ class GraphStep:
         self.handle = h
 
     def replay(self):
-        torch.cuda.current_stream().synchronize()
+        """Launch the graph on self.stream after the work queued so far on the
+        current stream (new weights, reads of the last replay's outputs), and
+        make the current stream wait for it.  Returns self.stream."""
+        cur = torch.cuda.current_stream()
+        self.stream.wait_stream(cur)
         check(self.plan.lib.lfa_graph_launch(self.handle, ctypes.c_void_p(self.stream.cuda_stream)),
               "lfa_graph_launch")
+        self._done.record(self.stream)
+        cur.wait_event(self._done)
         return self.stream
 
     def __del__(self):

@@ -87,3 +87,50 @@ def check_projectors(S_ref, U_ref, V_ref, U, V, dtype, tag=""):
         worst = max(worst, err / bound)
         assert err <= bound, f"{tag} projector {lead}, j={j}: {err:.3e} > {bound:.3e}"
     return worst
+
+
+def pick_gaps(S_sym, picks, grad=None):
+    """Relative gap of each picked singular value: the distance from
+    sigma_j(k) to the other singular values of the same symbol, over
+    sigma_max(k), leaving out values picked in that symbol with the same
+    weight (the gradient of a sum over a whole cluster of one symbol is
+    well-posed; only a cut through a cluster makes the picked terms
+    ill-conditioned).  ``S_sym [k, r]`` are the oracle's values of each
+    pick's symbol, ``picks [k, 3]`` the (p, q, j), ``grad [k]`` the weights."""
+    picks = np.asarray(picks)
+    g = np.ones(len(picks)) if grad is None else np.asarray(grad, dtype=np.float64)
+    gaps = np.empty(len(picks))
+    for s, (p, q, j) in enumerate(picks):
+        same = {int(picks[t, 2]) for t in range(len(picks))
+                if picks[t, 0] == p and picks[t, 1] == q and g[t] == g[s]}
+        sv = S_sym[s]
+        d = [abs(sv[j] - sv[jj]) for jj in range(len(sv)) if jj not in same]
+        gaps[s] = (min(d) if d else np.inf) / max(sv[0], np.finfo(np.float64).tiny)
+    return gaps
+
+
+GRAD_GATE = 1e-3          # dL/dW agreement with the oracle (relative)
+GRAD_GAP_MIN = 1e-3       # picks separated by at least this relative gap
+
+
+def grad_errors(dW, ref, S_sym, picks, grad=None, tag=""):
+    """Gradient of a sum of picked singular values against the oracle's.
+
+    The gate is elementwise: max |dW - ref| / max |ref| <= 1e-3, for picks
+    whose singular values are separated from the rest of their symbol by a
+    relative gap of at least 1e-3 (their singular vectors, and so each term
+    of the gradient, are then determined to about u / gap).  When a pick sits
+    in a tighter cluster, its singular vectors are ill-conditioned and only
+    the Frobenius-relative error is gated (at the same 1e-3).  Returns
+    (elementwise, frobenius, min gap)."""
+    dW = np.asarray(dW, dtype=np.float64)
+    ref = np.asarray(ref, dtype=np.float64)
+    elem = float(np.max(np.abs(dW - ref)) / np.max(np.abs(ref)))
+    frob = float(np.linalg.norm(dW - ref) / np.linalg.norm(ref))
+    gap = float(np.min(pick_gaps(S_sym, picks, grad)))
+    if gap >= GRAD_GAP_MIN:
+        assert elem <= GRAD_GATE, f"{tag} gradient elementwise {elem:.3e} (gap {gap:.2e})"
+    else:
+        assert frob <= GRAD_GATE, f"{tag} gradient Frobenius {frob:.3e} (gap {gap:.2e} below 1e-3)"
+    print(f"[grad] {tag} elementwise {elem:.2e} frobenius {frob:.2e} min gap {gap:.2e}", flush=True)
+    return elem, frob, gap

@@ -207,3 +207,45 @@ def test_apply_and_lift_reject_bad_arguments_before_touching_the_gpu():
     assert lift(idx=None) == _lib.LFA_ERR_INVALID_ARG
     assert lift(count=0) == 0
     assert lift(uh=None, vh=None) == 0                              # nothing to write
+
+
+def test_work_queue_loop_runs_the_hand_over_on_every_trip():
+    """Static check of the built work-queue kernels (tests/queue_loop.py):
+    in every wave_queue_kernel instance, each loop around the read of the
+    next group's code also contains thread 0's queue pop.  A loop structure
+    in which the other threads loop around the group code without passing
+    the hand-over (a thread-0 region at the bottom of the loop with a
+    per-lane exit test) hung the GPU; the check flags all 24 instances of
+    that structure and passes the current kernels."""
+    import queue_loop
+
+    obj = os.path.join(ROOT, "_build", "jacobi_wave.hip.o")
+    if not queue_loop.tools_available() or not os.path.exists(obj):
+        pytest.skip("needs the ROCm LLVM tools and the built _build/jacobi_wave.hip.o")
+    res = queue_loop.check_object(obj)
+    assert len(res) == 24, sorted(res)
+    bad = {k: msg for k, (ok, msg) in res.items() if not ok}
+    assert not bad, bad
+
+
+@needs_lib
+def test_info_status_and_sweep_cap_validation():
+    """lfa_info_status turns a host copy of the info record into warning
+    bits; lfa_plan_set_max_sweeps accepts 1 .. 40 only (no GPU needed)."""
+    lib = _lib.load()
+    info = (ctypes.c_int32 * 8)(0, 3, 10, 0, 0, 5, 40, 0)
+    assert lib.lfa_info_status(info, 1) == 0
+    assert lib.lfa_info_status(info, 2) == 0
+    info[4] = 2                                      # layer 1: two symbols hit the cap
+    assert lib.lfa_info_status(info, 2) == _lib.LFA_WARN_NOT_CONVERGED
+    info[7] = 1 | 2                                  # non-finite and a team time-out
+    assert lib.lfa_info_status(info, 2) == (_lib.LFA_WARN_NOT_CONVERGED | _lib.LFA_WARN_NONFINITE
+                                            | _lib.LFA_WARN_TEAM_TIMEOUT)
+    assert lib.lfa_info_status(None, 1) == _lib.LFA_ERR_INVALID_ARG
+    assert lib.lfa_info_status(info, 0) == _lib.LFA_ERR_INVALID_ARG
+    plan = lfa.Plan([lfa.LayerSpec(8, 8, 3, 3, 6, 6)])
+    for bad in (0, -1, 41):
+        assert lib.lfa_plan_set_max_sweeps(plan.handle, bad) == _lib.LFA_ERR_INVALID_ARG
+    for good in (1, 7, 40):
+        assert lib.lfa_plan_set_max_sweeps(plan.handle, good) == _lib.LFA_OK
+    assert lib.lfa_plan_prepare(plan.handle, -1) == _lib.LFA_ERR_INVALID_ARG

@@ -113,6 +113,26 @@ def test_dirichlet_operator_matches_torch_zero_padding():
 
 # --- Convolution theorem / symbol sign -------------------------------------
 
+@pytest.mark.parametrize("n,m", [(5, 6), (4, 4), (1, 3), (7, 2)])
+def test_frequency_grid_is_the_dft_dual_grid(n, m):
+    """oracle.frequency_grid (Algorithm 1, Init; the dual torus of Sec. III):
+    the characters e^{-2 pi i <k, x>} over its frequencies are exactly the
+    rows of numpy's 2-D DFT of the unit impulses on the n x m torus, in the
+    same (p, q) order, and they are n m distinct, mutually orthogonal modes."""
+    k = oracle.frequency_grid(n, m)
+    assert k.shape == (n, m, 2)
+    x1, x2 = np.meshgrid(np.arange(n), np.arange(m), indexing="ij")
+    chars = np.exp(-2j * np.pi * (k[..., 0, None, None] * x1 + k[..., 1, None, None] * x2))
+    impulses = np.eye(n * m).reshape(n * m, n, m)                 # impulse at (x1, x2)
+    dft = np.fft.fft2(impulses, axes=(-2, -1))                    # [x][p][q]
+    expect = np.transpose(dft.reshape(n, m, n, m), (2, 3, 0, 1))  # [p][q][x1][x2]
+    np.testing.assert_allclose(chars, expect, atol=1e-12)
+    E = chars.reshape(n * m, n * m)
+    np.testing.assert_allclose(E @ E.conj().T, n * m * np.eye(n * m), atol=1e-11)
+    # every frequency lies in [0, 1)^2 (one representative per class)
+    assert np.all(k >= 0) and np.all(k < 1)
+
+
 def test_fourier_mode_is_invariant_subspace():
     """(A*f_k)(x) = A_k f_k(x) for f_k = e^{2 pi i <k,x>} v (Sec. III
     "Convolution Theorem"): apply the torch-built operator to a Fourier mode
@@ -574,3 +594,26 @@ def test_crystal_symbols_stride_one_and_parseval():
         S = np.linalg.svd(oracle.crystal_symbols(W, n, m, s), compute_uv=False)
         total = (n // s) * (m // s) * np.sum(W ** 2)
         assert abs(np.sum(S ** 2) - total) <= 1e-12 * total
+
+
+def test_boundary_study_c16_gap_shrinks_with_the_grid():
+    """The paper's boundary-condition study at its channel count (c = 16,
+    3x3; Sec. III "Boundary Conditions", Sec. IV): the sorted periodic (LFA)
+    and zero-padded spectra of the same seeded layers differ by a gap that
+    shrinks with the grid -- about halving from n = 4 to n = 8, as the
+    share of grid points next to the boundary halves -- and the largest
+    singular values approach each other (oracle.boundary_study)."""
+    from oracle import boundary_study as bs
+
+    r = bs.study(sizes=(4, 8), seeds=(41, 42))
+    assert r[8]["max"] < r[4]["max"] and r[8]["mean"] < r[4]["mean"]
+    assert 0.35 <= r[8]["mean"] / r[4]["mean"] <= 0.65, r
+    assert abs(1 - r[8]["top_ratio"]) < abs(1 - r[4]["top_ratio"]), r
+    # zero padding is the periodic convolution on the (n+2)-torus restricted
+    # to an n x n block (3x3 taps reach one cell past the block, which holds
+    # zeros): an isometric compression, so its largest singular value is at
+    # most that torus's largest symbol singular value
+    for n in (4, 8):
+        W = bs.layer(n, 41)
+        sd = np.linalg.svd(oracle.dirichlet_operator(W, n, n), compute_uv=False)
+        assert sd[0] <= oracle.lfa_svd(W, n + 2, n + 2).max() * (1 + 1e-12)
