@@ -207,6 +207,27 @@ int lfa_symbols(const lfa_plan* plan, const void* const* W, void* const* A, void
 int lfa_svd(const lfa_plan* plan, const void* const* W, void* const* sigma, void* const* U,
             void* const* V, int32_t* info, void* ws, size_t ws_bytes, void* stream);
 
+/* lfa_svd for callers that cannot allocate device memory (code under graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * computation and outputs, with no workspace argument.  Its scratch is a
+ * static device array of the library, 64 MiB on each device that runs it,
+ * held from the library's first use on that device until the process ends;
+ * nothing is allocated or freed by the call (the plan must already be
+ * prepared on the current device: lfa_plan_create does that when a gfx950
+ * device is current, else call lfa_plan_prepare).  It runs the plan's own
+ * launch when that fits the scratch, else the same kernels without the
+ * register kernel's work queue (bitwise the same results).  All calls on one
+ * device share that device's scratch, which keeps the last call's contents
+ * (the kernels clear what must start at zero): calls that overlap in time on
+ * one device race and give wrong results -- serialise them (one stream, or
+ * events).
+ * Errors: as lfa_svd, plus LFA_ERR_WORKSPACE when the plan's layers need
+ * more than the 64 MiB scratch even without the work queue (e.g. large
+ * symbols, whose blocked kernel keeps every symbol in a global slot), and
+ * LFA_ERR_NOT_PREPARED when the plan's tables are not on the current device. */
+int lfa_svd_noalloc(const lfa_plan* plan, const void* const* W, void* const* sigma, void* const* U,
+                    void* const* V, int32_t* info, void* stream);
+
 /* Same results as lfa_svd for all layers of the plan in ONE persistent
  * launch: work-groups take (layer, frequency) items from a device work list,
  * largest symbols first.  Fused FP32/FP64 assembly only (no MFMA/BF16 flag). */

@@ -571,6 +571,23 @@ int run_svd_layer(const lfa_plan* p, const LayerDesc& d, const void* W, const vo
     return LFA_OK;
 }
 
+// Workspace bytes lfa_svd itself uses on the plan's device (desc as
+// adjusted at upload), with or without the register kernel's work queue.
+size_t svd_need(const lfa_plan& p, bool queue) {
+    const int eb = elem_bytes(p.dtype);
+    const bool wu = p.flags & LFA_WANT_U, wv = p.flags & LFA_WANT_V;
+    size_t need = 0;
+    for (size_t i = 0; i < p.layers.size(); ++i) {
+        const LayerDesc& d = p.desc[i];
+        const bool acc = accumulates(d, wu, wv);
+        const size_t sym = asm_materialized(p.flags) ? symbols_bytes(p.layers[i], eb) : 0;
+        size_t s = sym + (size_t)svd_grid(d, d.num_symbols) * slot_bytes(d, acc, eb);
+        if (queue && d.wave_qgroups > 0) s = std::max(s, sym + wave_queue_bytes(d, acc, eb, d.wave_qgroups));
+        need = std::max(need, s);
+    }
+    return kAlign + kCounterBytes + align_up(need);
+}
+
 int check_ws(const lfa_plan* p, void* ws, size_t ws_bytes) {
     const size_t need = workspace_bytes(*p);
     if (need > kAlign && (ws == nullptr || ws_bytes < need)) return LFA_ERR_WORKSPACE;
@@ -1306,6 +1323,33 @@ int lfa_svd(const lfa_plan* plan, const void* const* W, void* const* sigma, void
             void* const* V, int32_t* info, void* ws, size_t ws_bytes, void* stream) {
     if (!W) return LFA_ERR_INVALID_ARG;
     return svd_common(plan, W, nullptr, sigma, U, V, info, ws, ws_bytes, stream, false);
+}
+
+int lfa_svd_noalloc(const lfa_plan* plan, const void* const* W, void* const* sigma, void* const* U,
+                    void* const* V, int32_t* info, void* stream) {
+    if (!plan || !W) return LFA_ERR_INVALID_ARG;
+    LFA_TRY(check_ptrs(plan, W, true));
+    LFA_TRY(check_ptrs(plan, sigma, true));
+    LFA_TRY(check_ptrs(plan, U, (plan->flags & LFA_WANT_U) != 0));
+    LFA_TRY(check_ptrs(plan, V, (plan->flags & LFA_WANT_V) != 0));
+    lfa_plan* p = const_cast<lfa_plan*>(plan);
+    int dev = -1;
+    HIP_TRY(hipGetDevice(&dev));
+    {
+        // the device tables must be there already: no upload here
+        std::lock_guard<std::mutex> lock(p->mu);
+        if (p->device != dev) return LFA_ERR_NOT_PREPARED;
+    }
+    void* scr = nullptr;
+    size_t cap = 0;
+    HIP_TRY(lfa::noalloc_scratch(dev, &scr, &cap));
+    // the plan's own launch when it fits; else without the work queue (the
+    // same results, bit for bit); else the layer set is too large
+    const bool queue = svd_need(*p, true) <= cap;
+    if (!queue && svd_need(*p, false) > cap) return LFA_ERR_WORKSPACE;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    if (p->dtype == LFA_F64) return svd_impl<double>(p, W, nullptr, sigma, U, V, info, scr, cap, st, queue);
+    return svd_impl<float>(p, W, nullptr, sigma, U, V, info, scr, cap, st, queue);
 }
 
 int lfa_svd_persistent(const lfa_plan* plan, const void* const* W, void* const* sigma,

@@ -360,6 +360,10 @@ hipError_t launch_symbols_mfma(const LayerDesc& d, const float* W, cplx<float>* 
 
 hipError_t launch_fill_i32(int32_t* p, int32_t value, long long count, hipStream_t s);
 
+// Static device scratch of lfa_svd_noalloc (noalloc.hip): 64 MiB per device.
+constexpr size_t kNoAllocScratchBytes = size_t(64) << 20;
+hipError_t noalloc_scratch(int device, void** ptr, size_t* bytes);
+
 template <typename R>
 struct TopkArgs {
     const R* sigma[kMaxLaunchLayers];

@@ -180,6 +180,23 @@ class Plan:
         fn = self.lib.lfa_svd_persistent if persistent else self.lib.lfa_svd
         return self._svd_call(fn, "lfa_svd_persistent" if persistent else "lfa_svd", Ws, dev, info, out)
 
+    def svd_noalloc(self, Ws, info=None, out=None):
+        """As svd(), through lfa_svd_noalloc: no workspace, the library's static
+        device scratch instead (outputs are still the caller's: allocated
+        here with torch unless `out` is given).  Returns (S, U, V, info)."""
+        dev = self._check_weights(Ws)
+        S, U, V = out if out is not None else self._alloc_outputs(dev, self.want_u, self.want_v)
+        if info is None:
+            info = torch.zeros(len(self.layers), _lib.LFA_INFO_WORDS, dtype=torch.int32, device=dev)
+        w_arr, _k0 = ptr_array([x.data_ptr() for x in Ws])
+        s_arr, _k1 = ptr_array([x.data_ptr() for x in S])
+        u_arr, _k2 = ptr_array([x.data_ptr() if x is not None else 0 for x in U])
+        v_arr, _k3 = ptr_array([x.data_ptr() if x is not None else 0 for x in V])
+        check(self.lib.lfa_svd_noalloc(self.handle, w_arr, s_arr, u_arr if self.want_u else None,
+                                       v_arr if self.want_v else None, ctypes.c_void_p(info.data_ptr()),
+                                       _stream_ptr()), "lfa_svd_noalloc")
+        return S, U, V, info
+
     def svd_symbols(self, As, info=None):
         cdt = _complex_of(self.dtype)
         for A, l in zip(As, self.layers):
