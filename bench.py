@@ -134,48 +134,69 @@ def run_layer(L, W, dev, vectors, steps, warmup, asm=None, dtype=torch.float32):
     wall, ev = event_times(step, steps, warmup)
     inf = info.cpu().numpy()[0]
     ms = wall * 1e3 / steps
+    qr = plan.preconditioned(0)
+    # QR preconditioning: the sweeps run on the N x N factors
+    Lj = workloads.Layer(L.r, L.r, 1, 1, L.n, L.m) if qr else L
     return dict(layer=L, W=W, S=S[0], U=U[0], V=V[0], ms=ms, kernel_ms=float(np.mean(ev)),
                 info=[int(x) for x in inf], sigma_per_s=L.num_sigma / (ms * 1e-3),
-                flops=jacobi_flops(L, int(inf[2]), vectors), plan=plan)
+                flops=jacobi_flops(Lj, int(inf[2]), vectors), plan=plan, qr=qr)
 
 
 def bench_stack(dev, steps):
+    """The ResNet-18 stack's sigma-gradient step: forward sigma of every
+    symbol of every layer, top-8 per layer, dL/dW of the top-8 sum.
+
+    Batched: one HIP graph of [persistent SVD keeping U of every symbol (the
+    side the working matrix converges to: no rotation accumulator) -> top-8
+    -> one-sided adjoint (V of each pick recomputed from W)].  Plain: the same
+    algorithm eagerly, one SVD launch per layer (lfa_svd), then lfa_topk and
+    lfa_adjoint_onesided.  Also timed: the graph keeping U and V of every
+    symbol, the sigma-only graph (vectors of the picks recomputed by a second
+    SVD), and the eager sigma-only path with per-layer recomputation."""
     layers, Ws = workloads.resnet18_stack()
     specs = [lfa.LayerSpec(l.c_out, l.c_in, l.kh, l.kw, l.n, l.m) for l in layers]
     plan = lfa.Plan(specs, torch.float32)
+    plan_u = lfa.Plan(specs, torch.float32, want_u=True)
     Wt = [torch.from_numpy(w).to(dev) for w in Ws]
     k = 8
     ones = torch.ones(len(specs), k, device=dev)
     S, _, _ = plan._alloc_outputs(dev, False, False)
+    Su, Uu, _ = plan_u._alloc_outputs(dev, True, False)
+    dWu = [torch.empty_like(W) for W in Wt]
     info = torch.zeros(len(specs), 4, dtype=torch.int32, device=dev)
     none = [None] * len(S)
     res = {}
 
     def plain():
+        plan_u.svd(Wt, persistent=False, info=info, out=(Su, Uu, none))
+        vals, idx = plan_u.topk(Su, k)
+        res["plain"] = (vals, idx, plan_u.adjoint_onesided(Wt, Su, Uu, idx, ones, out=dWu))
+
+    def plain_recompute():
         plan.svd(Wt, persistent=False, info=info, out=(S, none, none))
         vals, idx = plan.topk(S, k)
-        res["plain"] = (vals, idx, plan.sigma_grad(Wt, idx, ones))
+        plan.sigma_grad(Wt, idx, ones)
 
-    # batched: one HIP graph of [persistent SVD keeping every symbol's U, V
-    # -> top-k -> one adjoint launch]; the sigma-only graph (forward sigma,
-    # then the vectors of the picked symbols recomputed) is timed beside it
-    plan_uv = lfa.Plan(specs, torch.float32, want_u=True, want_v=True)
-    graph = lfa.GraphStep(plan_uv, Wt, k)
+    graph = lfa.GraphStep(plan_u, Wt, k)
+    graph_uv = lfa.GraphStep(lfa.Plan(specs, torch.float32, want_u=True, want_v=True), Wt, k)
     graph_s = lfa.GraphStep(plan, Wt, k)
 
     def replay(g):
         g.replay()
-        torch.cuda.current_stream().wait_stream(g.stream)
 
     wall_p, _ = event_times(plain, steps, 1)
+    wall_r, _ = event_times(plain_recompute, steps, 1)
     wall_b, _ = event_times(lambda: replay(graph), steps, 1)
+    wall_uv, _ = event_times(lambda: replay(graph_uv), steps, 1)
     wall_s, _ = event_times(lambda: replay(graph_s), steps, 1)
     torch.cuda.synchronize()
     batched_out = (graph.vals.clone(), graph.idx.clone(), [d.clone() for d in graph.dW])
     nl = len(specs)
-    return dict(layers=layers, Ws=Ws, graph=graph, plain_out=res["plain"], batched_out=batched_out, S=S,
+    return dict(layers=layers, Ws=Ws, graph=graph, plain_out=res["plain"], batched_out=batched_out, S=Su,
                 plain_layers_per_s=nl * steps / wall_p, batched_layers_per_s=nl * steps / wall_b,
                 plain_ms=wall_p * 1e3 / steps, batched_ms=wall_b * 1e3 / steps,
+                plain_sigma_only_recompute_ms=wall_r * 1e3 / steps,
+                batched_uv_graph_ms=wall_uv * 1e3 / steps,
                 batched_sigma_only_ms=wall_s * 1e3 / steps)
 
 
@@ -477,6 +498,7 @@ def main():
             key = "rectangular_512x256" + ("_uv" if vec else "")
             extra[key] = r
             wl[key] = dict(ms=r["ms"], sigma_per_s=r["sigma_per_s"], sweeps=r["info"][1:3], vectors=vec,
+                           qr_preconditioned=r["qr"],
                            tflops=r["flops"] / (r["kernel_ms"] * 1e-3) / 1e12)
         L3r, W3r = workloads.rank_one_taps()
         r = run_layer(L3r, W3r, dev, True, reps, 1)
@@ -510,8 +532,11 @@ def main():
             "layers": 12, "loss": "sum of top-8 sigma per layer",
             "plain_layers_per_s": st["plain_layers_per_s"], "batched_layers_per_s": st["batched_layers_per_s"],
             "plain_ms": st["plain_ms"], "batched_ms": st["batched_ms"],
-            "batched": "HIP graph: persistent SVD with U, V of every symbol, top-8, one adjoint launch",
+            "batched": "HIP graph: persistent SVD keeping U of every symbol, top-8, one-sided adjoint",
+            "plain": "eager: lfa_svd per layer keeping U, lfa_topk, lfa_adjoint_onesided",
+            "batched_uv_graph_ms": st["batched_uv_graph_ms"],
             "batched_sigma_only_graph_ms": st["batched_sigma_only_ms"],
+            "plain_sigma_only_recompute_ms": st["plain_sigma_only_recompute_ms"],
             "speedup_batched_vs_plain": st["batched_layers_per_s"] / st["plain_layers_per_s"]}
         note("ResNet-18 stack done")
     if sel("large"):

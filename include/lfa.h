@@ -270,6 +270,28 @@ int lfa_adjoint(const lfa_plan* plan, const void* const* U, const void* const* V
                 const int32_t* idx, const void* grad, int32_t k, void* const* dW,
                 void* stream);
 
+/* As lfa_adjoint, from one side of the singular vectors: the side the
+ * one-sided Jacobi working matrix converges to, which an SVD call writes
+ * without a rotation accumulator -- U (c_out x r) of a layer with
+ * c_out >= c_in, V (c_in x r) of one with c_out < c_in.  For each pick
+ * (p, q, j) the other vector follows from the weights,
+ *     v = A_k^H u / sigma_j(k)   or   u = A_k v / sigma_j(k)
+ * (the SVD relations A v = sigma u, A^H u = sigma v; Sec. III "Convolution
+ * Theorem" for A_k), with A_k assembled from W in the kernel; a pick with
+ * sigma <= 0 adds nothing.  Accurate for the large singular values a top-k
+ * picks (the relative error of the recomputed vector is about
+ * u sigma_max / sigma_j).  Two launches: the other vectors (one work-group
+ * per pick), then the adjoint.
+ *   W     : per-layer weights (device)
+ *   sigma : per-layer [n][m][r] singular values from the same SVD
+ *   X     : per-layer kept side, [n][m][c_out][r] (U) or [n][m][c_in][r] (V)
+ *   idx, grad, k, dW : as lfa_adjoint
+ *   ws    : workspace of lfa_plan_workspace_bytes (per-pick vectors)
+ * Errors: as lfa_adjoint, plus LFA_ERR_WORKSPACE. */
+int lfa_adjoint_onesided(const lfa_plan* plan, const void* const* W, const void* const* sigma,
+                         const void* const* X, const int32_t* idx, const void* grad, int32_t k,
+                         void* const* dW, void* ws, size_t ws_bytes, void* stream);
+
 /* As lfa_adjoint, but recomputes the singular vectors of only the selected
  * symbols (at most k per layer) from W into the workspace, so the forward
  * pass can be sigma-only.  Two launches (SVD of the selected symbols, then
@@ -313,6 +335,18 @@ int lfa_graph_create_uv(lfa_plan* plan, const void* const* W, void* const* sigma
                         void* const* V, int32_t k, void* vals, int32_t* idx, const void* grad,
                         void* const* dW, int32_t* info, void* ws, size_t ws_bytes, void* stream,
                         lfa_graph** out);
+/* The step with a one-sided forward pass: [lfa_svd_persistent keeping only
+ * the side of every layer that needs no rotation accumulator -> lfa_topk ->
+ * lfa_adjoint_onesided].  The forward pass costs about what a sigma-only one
+ * does, and the gradient needs no second SVD.
+ *   plan : every layer tall (c_out >= c_in) with exactly LFA_WANT_U, or every
+ *          layer wide with exactly LFA_WANT_V (else UNSUPPORTED)
+ *   X    : per-layer device outputs for that side (U or V as lfa_svd writes
+ *          them), required; they hold the last replay's vectors
+ * Other arguments, ownership and errors as lfa_graph_create. */
+int lfa_graph_create_onesided(lfa_plan* plan, const void* const* W, void* const* sigma, void* const* X,
+                              int32_t k, void* vals, int32_t* idx, const void* grad, void* const* dW,
+                              int32_t* info, void* ws, size_t ws_bytes, void* stream, lfa_graph** out);
 int lfa_graph_launch(lfa_graph* graph, void* stream);
 int lfa_graph_destroy(lfa_graph* graph);
 
@@ -426,6 +460,15 @@ int lfa_autotune(lfa_plan* plan, const void* const* W, void* const* sigma, void*
  * work-group, symbols per work-group and storage (0 = LDS, 1 = global). */
 int lfa_plan_launch_shape(const lfa_plan* plan, int32_t layer, int32_t* lanes_per_pair,
                           int32_t* threads, int32_t* symbols_per_group, int32_t* storage);
+
+/* Whether lfa_svd runs layer `layer` through QR preconditioning (*qr = 1):
+ * the N x N Cholesky factors R of the symbols' Gram matrices, formed in FP64
+ * from the Gram convolution's taps, then the one-sided Jacobi SVD of R,
+ * whose N rows replace the symbol's M (the singular values of R and of the
+ * symbol agree to about sqrt(N u64) sigma_max).  Chosen at plan creation for
+ * FP32 sigma-only plans with working matrices of M > 64 rows and M >= 1.25 N
+ * (the environment variable LFA_NO_QR, read then, turns it off).  Host only. */
+int lfa_plan_preconditioned(const lfa_plan* plan, int32_t layer, int32_t* qr);
 
 /* Work-queue launch of a layer's register kernel (symbols of at most 64
  * rows) on the current device.  When the groups of symbols fill the resident

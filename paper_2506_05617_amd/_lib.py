@@ -77,6 +77,8 @@ SIGNATURES = {
     "lfa_sigma_grad_persistent": (I32, [P, PP, P, P, I32, PP, P, SZ, P]),
     "lfa_graph_create": (I32, [P, PP, PP, I32, P, P, P, PP, P, P, SZ, P, ctypes.POINTER(P)]),
     "lfa_graph_create_uv": (I32, [P, PP, PP, PP, PP, I32, P, P, P, PP, P, P, SZ, P, ctypes.POINTER(P)]),
+    "lfa_graph_create_onesided": (I32, [P, PP, PP, PP, I32, P, P, P, PP, P, P, SZ, P, ctypes.POINTER(P)]),
+    "lfa_adjoint_onesided": (I32, [P, PP, PP, PP, P, P, I32, PP, P, SZ, P]),
     "lfa_graph_launch": (I32, [P, P]),
     "lfa_graph_destroy": (I32, [P]),
     "lfa_autotune": (I32, [P, PP, PP, PP, PP, P, SZ, P]),
@@ -87,6 +89,7 @@ SIGNATURES = {
     "lfa_crystal_layer": (I32, [ctypes.POINTER(LfaLayer), I32, ctypes.POINTER(LfaLayer)]),
     "lfa_crystal_weights": (I32, [ctypes.POINTER(LfaLayer), I32, I32, P, P, I32, P]),
     "lfa_plan_queue_info": (I32, [P, I32, I32P, I32P]),
+    "lfa_plan_preconditioned": (I32, [P, I32, I32P]),
     "lfa_status_string": (ctypes.c_char_p, [I32]),
     "lfa_last_hip_error": (I32, []),
     "lfa_version": (I32, []),

@@ -94,6 +94,7 @@ struct lfa_plan {
     size_t pers_slots_total = 0;
     int pers_teams = 0;                   // team instances (one per blocked-layer symbol)
     int pers_wave_slots = 4;
+    bool pers_acc = false;                // some layer keeps the rotation accumulator
     std::vector<size_t> pers_lds;         // per chunk
     std::vector<int> pers_grid;           // per chunk
     // persistent SVD-with-vectors of the selected symbols, per k
@@ -106,6 +107,11 @@ struct lfa_plan {
     };
     std::map<int, GradSched> grad_sched;
     std::vector<LayerDesc> desc_gsel;     // blocked-kernel shape with vectors, 256 threads
+    // QR preconditioning of tall symbols (lfa_svd, sigma only): per layer
+    // whether it is used, and the launch shape of the SVD of the N x N
+    // factors R
+    std::vector<int> qr;
+    std::vector<LayerDesc> desc_r;
 };
 
 struct lfa_graph {
@@ -260,6 +266,43 @@ size_t sel_bytes(const lfa_layer& l, int eb) {
     return align_up((size_t)kMaxTopk * (r * eb + (size_t)(l.c_out + l.c_in) * r * 2 * eb));
 }
 
+// QR preconditioning (qr.hip) pays where the working matrix is clearly
+// taller than wide and the blocked kernel would run it (M > 64): the
+// sweeps then touch N rows instead of M.  FP32 plans only: the factor is
+// accurate to about sqrt(N u64) sigma_max, far inside the FP32 tolerance
+// but not the FP64 one.  Sigma only (the left singular vectors would need
+// G V S^-1 after the SVD of R).
+bool qr_applies(const lfa_layer& l, int dtype, uint32_t flags) {
+    const int M = std::max(l.c_out, l.c_in), N = std::min(l.c_out, l.c_in);
+    if (dtype != LFA_F32 || (flags & (LFA_WANT_U | LFA_WANT_V))) return false;
+    if (flags & (LFA_ASM_MFMA | LFA_ASM_BF16X2 | LFA_ASM_BF16X3)) return false;
+    if (std::getenv("LFA_NO_QR")) return false;
+    return M > 64 && 4 * M >= 5 * N;
+}
+
+size_t qr_taps_bytes(const lfa_layer& l) {
+    const size_t N = std::min(l.c_out, l.c_in);
+    return align_up((size_t)(2 * l.kh - 1) * (2 * l.kw - 1) * N * N * sizeof(double));
+}
+size_t qr_rsym_bytes(const lfa_layer& l, int eb) {
+    const size_t N = std::min(l.c_out, l.c_in);
+    return align_up((size_t)l.n * l.m * N * N * 2 * eb);
+}
+size_t qr_hslot_bytes(const lfa_layer& l) {
+    const size_t N = std::min(l.c_out, l.c_in);
+    return align_up((size_t)canonical_count(l.n, l.m) * N * N * 2 * sizeof(double));
+}
+
+// Per-pick vectors of the one-sided adjoint: [k][c_out] and [k][c_in]
+// complex per layer, layer after layer.
+size_t pick_vector_bytes(const lfa_plan& p, int k) {
+    const size_t cb = 2 * (size_t)elem_bytes(p.dtype);
+    size_t b = 0;
+    for (const lfa_layer& l : p.layers)
+        b += align_up((size_t)k * l.c_out * cb) + align_up((size_t)k * l.c_in * cb);
+    return b;
+}
+
 // Workspace layout (offsets from ws):
 //   [0, 256)                   persistent dequeue counter
 //   [256, 256 + big)           per-entry-point region (regions of different
@@ -282,6 +325,17 @@ size_t workspace_bytes(const lfa_plan& p) {
         // register kernel: work-queue control, entries, meta and saved state
         if (d.wave_qgroups > 0) s = std::max(s, sym + wave_queue_bytes(d, acc, eb, d.wave_qgroups));
         need = std::max(need, s);
+        if (p.qr[i]) {
+            // R symbols, Gram taps, then the Cholesky slots or the SVD's own
+            // region (counters and slots, or the work queue) of the R layer
+            const LayerDesc& dr = p.desc_r[i];
+            LayerDesc drg = dr;
+            drg.storage = (lds_bytes_for(dr, false, eb) > kLdsSafe) ? kGlobal : dr.storage;
+            size_t svd_r = kCounterBytes + (size_t)svd_grid(drg, dr.num_symbols) * slot_bytes(drg, false, eb);
+            if (dr.wave_qgroups > 0) svd_r = std::max(svd_r, wave_queue_bytes(dr, false, eb, dr.wave_qgroups));
+            need = std::max(need, qr_rsym_bytes(p.layers[i], eb) + qr_taps_bytes(p.layers[i]) +
+                                      std::max(svd_r, qr_hslot_bytes(p.layers[i])));
+        }
         // lfa_sigma_grad: compact outputs of <= kMaxTopk symbols + slots
         const LayerDesc& ds = p.desc_sel[i];
         LayerDesc dsg = ds;
@@ -289,6 +343,8 @@ size_t workspace_bytes(const lfa_plan& p) {
         need = std::max(need, sel_bytes(p.layers[i], eb) +
                                   (size_t)kMaxTopk * slot_bytes(dsg, true, eb));
     }
+    // one-sided adjoint: both vectors of every pick of every layer
+    need = std::max(need, pick_vector_bytes(p, kMaxTopk));
     // persistent: team counters, then the slots of the blocked layers
     need = std::max(need, pers_counter_bytes(p) + p.pers_slots_total);
     // persistent sigma gradient: counters, compact outputs of every layer, slots
@@ -339,7 +395,7 @@ void build_schedule(lfa_plan* p) {
     for (int l0 = 0; l0 < nl; l0 += kMaxLaunchLayers) {
         const int l1 = std::min(nl, l0 + kMaxLaunchLayers);
         p->chunk_first.push_back((int)p->items.size());
-        const bool acc_any = wu || wv;
+        const bool acc_any = p->pers_acc;
         const size_t lds = persistent_lds_bytes(p->desc_pers.data() + l0, l1 - l0, acc_any, eb,
                                                 p->pers_wave_slots);
         int grid = persistent_resident(lds, eb, acc_any);
@@ -441,6 +497,15 @@ int ensure_device(lfa_plan* p, hipStream_t st = nullptr, bool check_capture = fa
         }
         if (lds_bytes_for(p->desc[i], accumulates(p->desc[i], wu, wv), eb) > lds_dev)
             p->desc[i].storage = kGlobal;
+        {
+            LayerDesc& dr = p->desc_r[i];
+            if (dr.kind == 1) {
+                dr.wave_cap = wave_blocks_per_cu(dr.wave_nc, dr.wave_ml, eb, dr.threads, false) * p->num_cus;
+                if (dr.wave_qgroups > 0)
+                    dr.wave_qcap = wave_queue_blocks_per_cu(dr.wave_nc, dr.wave_ml, eb, dr.threads, false) * p->num_cus;
+            }
+            if (lds_bytes_for(dr, false, eb) > lds_dev) dr.storage = kGlobal;
+        }
         if (lds_bytes_for(p->desc_sel[i], true, eb) > lds_dev) p->desc_sel[i].storage = kGlobal;
         if (lds_bytes_for(p->desc_pers[i], accumulates(p->desc_pers[i], wu, wv), eb) > lds_dev)
             p->desc_pers[i].storage = kGlobal;
@@ -583,6 +648,13 @@ size_t svd_need(const lfa_plan& p, bool queue) {
         const size_t sym = asm_materialized(p.flags) ? symbols_bytes(p.layers[i], eb) : 0;
         size_t s = sym + (size_t)svd_grid(d, d.num_symbols) * slot_bytes(d, acc, eb);
         if (queue && d.wave_qgroups > 0) s = std::max(s, sym + wave_queue_bytes(d, acc, eb, d.wave_qgroups));
+        if (p.qr[i]) {
+            const LayerDesc& dr = p.desc_r[i];
+            size_t svd_r = kCounterBytes + (size_t)svd_grid(dr, dr.num_symbols) * slot_bytes(dr, false, eb);
+            if (queue && dr.wave_qgroups > 0) svd_r = std::max(svd_r, wave_queue_bytes(dr, false, eb, dr.wave_qgroups));
+            s = qr_rsym_bytes(p.layers[i], eb) + qr_taps_bytes(p.layers[i]) +
+                std::max(svd_r, qr_hslot_bytes(p.layers[i]));
+        }
         need = std::max(need, s);
     }
     return kAlign + kCounterBytes + align_up(need);
@@ -616,6 +688,40 @@ int svd_impl(const lfa_plan* p, const void* const* W, const void* const* A, void
             } else {
                 Wi = W[i];
             }
+        }
+        if (!A && p->qr[i]) {
+            // QR preconditioning: the Cholesky factors R of the Gram
+            // matrices, then the SVD of the N x N factors (one per conjugate
+            // pair; the mirror's factor is the conjugate)
+            const lfa_layer& l = p->layers[i];
+            char* rsym = region;
+            double* taps = reinterpret_cast<double*>(rsym + qr_rsym_bytes(l, sizeof(R)));
+            char* rest = reinterpret_cast<char*>(taps) + qr_taps_bytes(l);
+            GramArgs<R> g{};
+            g.W = static_cast<const R*>(W[i]);
+            g.c_out = l.c_out;
+            g.c_in = l.c_in;
+            g.kh = l.kh;
+            g.kw = l.kw;
+            g.n = l.n;
+            g.m = l.m;
+            g.M = d.M;
+            g.N = d.N;
+            g.transposed = d.transposed;
+            g.tw_n = d.tw_n;
+            g.tw_m = d.tw_m;
+            g.tw = p->tw_dev;
+            g.C = taps;
+            g.hslots = rest;
+            g.Rsym = reinterpret_cast<cplx<R>*>(rsym);
+            hipError_t e;
+            if constexpr (sizeof(R) == 4) e = launch_gram_qr_f32(g, d.num_canon, st);
+            else e = launch_gram_qr_f64(g, d.num_canon, st);
+            HIP_TRY(e);
+            LFA_TRY(run_svd_layer<R>(p, p->desc_r[i], nullptr, rsym, sigma[i], nullptr, nullptr,
+                                     info ? info + i * LFA_INFO_WORDS : nullptr, rest, nullptr, 0, 0, st,
+                                     true, queue_ok));
+            continue;
         }
         // weights are real: decompose one symbol per conjugate pair.  Symbols
         // handed in by the caller carry no such guarantee.
@@ -654,7 +760,7 @@ int persistent_impl(const lfa_plan* p, const void* const* W, void* const* sigma,
         pa.threads = kPersistentThreads;
         for (int i = l0; i < l1; ++i) {
             const LayerDesc& d = p->desc_pers[i];
-            const bool acc = wu || wv;      // as the plan sized the slots
+            const bool acc = p->pers_acc;   // as the plan sized the slots
             SvdArgs<R>& a = pa.layer[i - l0];
             a.d = d;
             a.W = static_cast<const R*>(W[i]);
@@ -692,8 +798,8 @@ int persistent_impl(const lfa_plan* p, const void* const* W, void* const* sigma,
         HIP_TRY(launch_fill_i32(team_counters, 0, 4LL * p->pers_teams + 4, st));
         const int grid = std::min(p->pers_grid[chunk], count);
         hipError_t e;
-        if constexpr (sizeof(R) == 4) e = launch_persistent_f32(pa, grid, p->pers_lds[chunk], wu || wv, st);
-        else e = launch_persistent_f64(pa, grid, p->pers_lds[chunk], wu || wv, st);
+        if constexpr (sizeof(R) == 4) e = launch_persistent_f32(pa, grid, p->pers_lds[chunk], p->pers_acc, st);
+        else e = launch_persistent_f64(pa, grid, p->pers_lds[chunk], p->pers_acc, st);
         HIP_TRY(e);
     }
     return LFA_OK;
@@ -932,6 +1038,62 @@ int sigma_grad_persistent_impl(const lfa_plan* p, const lfa_plan::GradSched& gs,
     return LFA_OK;
 }
 
+// Gradient from one side of the picks' singular vectors: the side the
+// forward pass kept (U of tall layers, V of wide ones), the other side
+// recomputed from W for each pick, then the adjoint on per-pick vectors.
+template <typename R>
+int adjoint_onesided_impl(const lfa_plan* p, const void* const* W, const void* const* sigma,
+                          const void* const* X, const int32_t* idx, const void* grad, int k,
+                          void* const* dW, void* ws, hipStream_t st) {
+    const int nl = (int)p->layers.size();
+    const size_t cb = 2 * sizeof(R);
+    char* cur = static_cast<char*>(ws) + kAlign;
+    std::vector<void*> Uc(nl), Vc(nl);
+    for (int i = 0; i < nl; ++i) {
+        const lfa_layer& l = p->layers[i];
+        Uc[i] = cur;
+        cur += align_up((size_t)k * l.c_out * cb);
+        Vc[i] = cur;
+        cur += align_up((size_t)k * l.c_in * cb);
+    }
+    for (int l0 = 0; l0 < nl; l0 += kMaxLaunchLayers) {
+        const int l1 = std::min(nl, l0 + kMaxLaunchLayers);
+        OtherSideArgs<R> o{};
+        o.num_layers = l1 - l0;
+        o.k = k;
+        o.idx = idx + (size_t)l0 * k * 3;
+        o.tw = p->tw_dev;
+        for (int i = l0; i < l1; ++i) {
+            const lfa_layer& l = p->layers[i];
+            const int j = i - l0;
+            o.W[j] = static_cast<const R*>(W[i]);
+            o.sigma[j] = static_cast<const R*>(sigma[i]);
+            o.X[j] = static_cast<const cplx<R>*>(X[i]);
+            o.Uc[j] = static_cast<cplx<R>*>(Uc[i]);
+            o.Vc[j] = static_cast<cplx<R>*>(Vc[i]);
+            o.c_out[j] = l.c_out;
+            o.c_in[j] = l.c_in;
+            o.kh[j] = l.kh;
+            o.kw[j] = l.kw;
+            o.n[j] = l.n;
+            o.m[j] = l.m;
+            o.tw_n[j] = p->tw_n[i];
+            o.tw_m[j] = p->tw_m[i];
+        }
+        hipError_t e;
+        if constexpr (sizeof(R) == 4) e = launch_other_side_f32(o, st);
+        else e = launch_other_side_f64(o, st);
+        HIP_TRY(e);
+        std::vector<const void*> Uv(Uc.begin() + l0, Uc.begin() + l1), Vv(Vc.begin() + l0, Vc.begin() + l1);
+        LFA_TRY(adjoint_launch<R>(p, l0, l1, Uv.data(), Vv.data(), idx, grad, k, dW, 2, st));
+    }
+    return LFA_OK;
+}
+
+// The side of a layer's singular vectors that its working matrix converges
+// to (no accumulator): U when c_out >= c_in, V otherwise.
+bool keeps_u(const lfa_layer& l) { return l.c_out >= l.c_in; }
+
 int check_k(const lfa_plan* p, int k) {
     if (k < 1 || k > kMaxTopk) return LFA_ERR_INVALID_ARG;
     for (const lfa_layer& l : p->layers) {
@@ -1013,6 +1175,10 @@ int lfa_plan_create(lfa_plan** out, const lfa_layer* layers, int32_t num_layers,
         }
     }
     const bool wu = flags & LFA_WANT_U, wv = flags & LFA_WANT_V;
+    // the persistent launch keeps the accumulator when some layer needs it
+    // (V of a tall layer, U of a wide one); the side its working matrix
+    // converges to comes without one
+    for (const lfa_layer& l : p->layers) p->pers_acc |= (l.c_out < l.c_in) ? wu : wv;
     for (const lfa_layer& l : p->layers) {
         // one symbol per conjugate pair (canonical_theta enumerates them)
         const int ncanon = lfa::canonical_count(l.n, l.m);
@@ -1026,9 +1192,9 @@ int lfa_plan_create(lfa_plan** out, const lfa_layer* layers, int32_t num_layers,
         // without vectors, the blocked kernel (256 threads) otherwise
         // one accumulator setting for the whole persistent launch (its kernel
         // is compiled with or without the accumulator)
-        const bool pacc = wu || wv;
+        const bool pacc = p->pers_acc;
         LayerDesc dp = make_desc(l, off[l.n], off[l.m], pacc, eb, kLdsCap);
-        if (dp.kind != 1 || pacc) {
+        if (dp.kind != 1 || wu || wv) {
             dp = make_desc(l, off[l.n], off[l.m], pacc, eb, kLdsCap);
             dp.kind = 2;
             dp.threads = kPersistentThreads;
@@ -1044,6 +1210,16 @@ int lfa_plan_create(lfa_plan** out, const lfa_layer* layers, int32_t num_layers,
         }
         p->desc.back().num_canon = ncanon;
         p->desc.back().wave_qgroups = wave_queue_reserved(p->desc.back(), accumulates(p->desc.back(), wu, wv), eb);
+        {
+            const int N = std::min(l.c_out, l.c_in);
+            const bool q = qr_applies(l, dtype, flags);
+            p->qr.push_back(q ? 1 : 0);
+            lfa_layer lr{N, N, 1, 1, l.n, l.m};
+            LayerDesc dr = make_desc(lr, off[l.n], off[l.m], false, eb, kLdsCap);
+            dr.num_canon = ncanon;
+            dr.wave_qgroups = q ? wave_queue_reserved(dr, false, eb) : 0;
+            p->desc_r.push_back(dr);
+        }
         p->desc_sel.back().num_canon = ncanon;
         dp.num_canon = ncanon;
         p->desc_pers.push_back(dp);
@@ -1131,6 +1307,12 @@ int lfa_plan_launch_shape(const lfa_plan* plan, int32_t layer, int32_t* lanes_pe
     if (threads) *threads = d.threads;
     if (symbols_per_group) *symbols_per_group = wave_symbols_per_group(d);
     if (storage) *storage = d.storage;
+    return LFA_OK;
+}
+
+int lfa_plan_preconditioned(const lfa_plan* plan, int32_t layer, int32_t* qr) {
+    if (!plan || !qr || layer < 0 || layer >= (int32_t)plan->layers.size()) return LFA_ERR_INVALID_ARG;
+    *qr = plan->qr[layer];
     return LFA_OK;
 }
 
@@ -1397,6 +1579,23 @@ int lfa_adjoint(const lfa_plan* plan, const void* const* U, const void* const* V
     return LFA_OK;
 }
 
+int lfa_adjoint_onesided(const lfa_plan* plan, const void* const* W, const void* const* sigma,
+                         const void* const* X, const int32_t* idx, const void* grad, int32_t k,
+                         void* const* dW, void* ws, size_t ws_bytes, void* stream) {
+    if (!plan || !idx || !grad) return LFA_ERR_INVALID_ARG;
+    LFA_TRY(check_ptrs(plan, W, true));
+    LFA_TRY(check_ptrs(plan, sigma, true));
+    LFA_TRY(check_ptrs(plan, X, true));
+    LFA_TRY(check_ptrs(plan, dW, true));
+    LFA_TRY(check_k(plan, k));
+    LFA_TRY(check_ws(plan, ws, ws_bytes));
+    lfa_plan* p = const_cast<lfa_plan*>(plan);
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    LFA_TRY(ensure_device(p, st, true));
+    if (p->dtype == LFA_F64) return adjoint_onesided_impl<double>(p, W, sigma, X, idx, grad, k, dW, ws, st);
+    return adjoint_onesided_impl<float>(p, W, sigma, X, idx, grad, k, dW, ws, st);
+}
+
 int lfa_sigma_grad(const lfa_plan* plan, const void* const* W, const int32_t* idx, const void* grad,
                    int32_t k, void* const* dW, void* ws, size_t ws_bytes, void* stream) {
     if (!plan || !idx || !grad) return LFA_ERR_INVALID_ARG;
@@ -1433,15 +1632,27 @@ namespace {
 // Both graph forms: with U and V (null for the sigma-only form), the forward
 // pass keeps every symbol's singular vectors and the gradient is one adjoint
 // launch; without, the gradient recomputes the vectors of the picks.
+// Graph forms: sigma only (U, V, X null), with U and V of every symbol, or
+// one-sided (X: the kept side of every layer, U for tall layers, V for wide
+// ones; the plan wants exactly that side).
 int graph_create(lfa_plan* plan, const void* const* W, void* const* sigma, void* const* U, void* const* V,
                  int32_t k, void* vals, int32_t* idx, const void* grad, void* const* dW, int32_t* info,
-                 void* ws, size_t ws_bytes, void* stream, lfa_graph** out) {
+                 void* ws, size_t ws_bytes, void* stream, lfa_graph** out, void* const* X = nullptr) {
     if (!out) return LFA_ERR_INVALID_ARG;
     *out = nullptr;
     if (!plan || !vals || !idx || !grad) return LFA_ERR_INVALID_ARG;
     const bool uv = U != nullptr || V != nullptr;
     const uint32_t want = plan->flags & (LFA_WANT_U | LFA_WANT_V);
-    if (want != (uv ? (LFA_WANT_U | LFA_WANT_V) : 0u)) return LFA_ERR_UNSUPPORTED;
+    bool ku = false;
+    if (X) {
+        ku = keeps_u(plan->layers[0]);
+        for (const lfa_layer& l : plan->layers)
+            if (keeps_u(l) != ku) return LFA_ERR_UNSUPPORTED;
+        if (want != (ku ? LFA_WANT_U : LFA_WANT_V)) return LFA_ERR_UNSUPPORTED;
+        LFA_TRY(check_ptrs(plan, X, true));
+    } else if (want != (uv ? (LFA_WANT_U | LFA_WANT_V) : 0u)) {
+        return LFA_ERR_UNSUPPORTED;
+    }
     LFA_TRY(check_ptrs(plan, W, true));
     LFA_TRY(check_ptrs(plan, sigma, true));
     LFA_TRY(check_ptrs(plan, dW, true));
@@ -1454,7 +1665,7 @@ int graph_create(lfa_plan* plan, const void* const* W, void* const* sigma, void*
     hipStream_t st = static_cast<hipStream_t>(stream);
     // uploads are not allowed while capturing: do them now
     LFA_TRY(ensure_device(plan, st, true));
-    if (!uv) LFA_TRY(ensure_grad_schedule(plan, k, st, true, nullptr));
+    if (!uv && !X) LFA_TRY(ensure_grad_schedule(plan, k, st, true, nullptr));
     if (st == nullptr) return LFA_ERR_INVALID_ARG;   // cannot capture the legacy default stream
     lfa_graph* g = new (std::nothrow) lfa_graph();
     if (!g) return LFA_ERR_INVALID_ARG;
@@ -1463,11 +1674,16 @@ int graph_create(lfa_plan* plan, const void* const* W, void* const* sigma, void*
         delete g;
         return hip_fail(e);
     }
-    int s = lfa_svd_persistent(plan, W, sigma, U, V, info, ws, ws_bytes, stream);
+    int s = X ? lfa_svd_persistent(plan, W, sigma, ku ? X : nullptr, ku ? nullptr : X, info, ws, ws_bytes, stream)
+              : lfa_svd_persistent(plan, W, sigma, U, V, info, ws, ws_bytes, stream);
     if (s == LFA_OK) s = lfa_topk(plan, sigma, k, vals, idx, stream);
-    if (s == LFA_OK)
-        s = uv ? lfa_adjoint(plan, U, V, idx, grad, k, dW, stream)
-               : lfa_sigma_grad_persistent(plan, W, idx, grad, k, dW, ws, ws_bytes, stream);
+    if (s == LFA_OK) {
+        if (X)
+            s = lfa_adjoint_onesided(plan, W, sigma, X, idx, grad, k, dW, ws, ws_bytes, stream);
+        else
+            s = uv ? lfa_adjoint(plan, U, V, idx, grad, k, dW, stream)
+                   : lfa_sigma_grad_persistent(plan, W, idx, grad, k, dW, ws, ws_bytes, stream);
+    }
     e = hipStreamEndCapture(st, &g->graph);
     if (s != LFA_OK || e != hipSuccess) {
         if (g->graph) (void)hipGraphDestroy(g->graph);
@@ -1502,6 +1718,17 @@ int lfa_graph_create_uv(lfa_plan* plan, const void* const* W, void* const* sigma
         return LFA_ERR_INVALID_ARG;
     }
     return graph_create(plan, W, sigma, U, V, k, vals, idx, grad, dW, info, ws, ws_bytes, stream, out);
+}
+
+int lfa_graph_create_onesided(lfa_plan* plan, const void* const* W, void* const* sigma, void* const* X,
+                              int32_t k, void* vals, int32_t* idx, const void* grad, void* const* dW,
+                              int32_t* info, void* ws, size_t ws_bytes, void* stream, lfa_graph** out) {
+    if (!X) {
+        if (out) *out = nullptr;
+        return LFA_ERR_INVALID_ARG;
+    }
+    return graph_create(plan, W, sigma, nullptr, nullptr, k, vals, idx, grad, dW, info, ws, ws_bytes, stream,
+                        out, X);
 }
 
 int lfa_graph_launch(lfa_graph* graph, void* stream) {

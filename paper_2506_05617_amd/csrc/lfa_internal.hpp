@@ -387,13 +387,57 @@ struct AdjointArgs {
     int blocks_before[kMaxLaunchLayers + 1];
     int num_layers;
     int k;
-    int compact;                    // 1: U/V hold only the k selected symbols
+    int compact;                    // 0: full U/V; 1: U/V hold only the k selected
+                                    // symbols; 2: U/V hold one vector per pick
+                                    // ([k][c_out] and [k][c_in], column j of the pick)
     const int32_t* idx;             // [num_layers][k][3]
     const R* grad;                  // [num_layers][k]
     const double* tw;
 };
 hipError_t launch_adjoint_f32(const AdjointArgs<float>& a, hipStream_t s);
 hipError_t launch_adjoint_f64(const AdjointArgs<double>& a, hipStream_t s);
+
+// QR preconditioning of tall symbols (qr.hip): the FP64 taps C_delta of the
+// Gram convolution, then per decomposed frequency H_k and its Cholesky
+// factor R (R^H R = H_k), written as the N x N symbols the SVD then takes.
+template <typename R>
+struct GramArgs {
+    const R* W;                 // [c_out][c_in][kh*kw]
+    int c_out, c_in, kh, kw, n, m;
+    int M, N;                   // working matrix rows and columns (M > N)
+    int transposed;             // G = A^H (c_out < c_in)
+    int tw_n, tw_m;
+    const double* tw;
+    double* C;                  // [(2kh-1)(2kw-1)][N][N]
+    void* hslots;               // [items][N][N] complex double
+    cplx<R>* Rsym;              // [n*m][N][N]; canonical frequencies written
+};
+size_t gram_cholesky_lds_bytes(int N, int kh, int kw);
+hipError_t launch_gram_qr_f32(const GramArgs<float>& g, int items, hipStream_t s);
+hipError_t launch_gram_qr_f64(const GramArgs<double>& g, int items, hipStream_t s);
+
+// The singular vector a one-sided forward pass did not keep, for each pick
+// (p, q, j) of each layer: with the kept side x (U when c_out >= c_in, else
+// V), v = A_k^H u / sigma or u = A_k v / sigma, A_k assembled from W.
+// Writes both vectors of every pick to the compact per-pick arrays of the
+// adjoint (compact mode 2).
+template <typename R>
+struct OtherSideArgs {
+    const R* W[kMaxLaunchLayers];
+    const R* sigma[kMaxLaunchLayers];      // [n][m][r]
+    const cplx<R>* X[kMaxLaunchLayers];    // kept side, [n][m][c_kept][r]
+    cplx<R>* Uc[kMaxLaunchLayers];         // [k][c_out]
+    cplx<R>* Vc[kMaxLaunchLayers];         // [k][c_in]
+    int c_out[kMaxLaunchLayers], c_in[kMaxLaunchLayers], kh[kMaxLaunchLayers],
+        kw[kMaxLaunchLayers], n[kMaxLaunchLayers], m[kMaxLaunchLayers];
+    int tw_n[kMaxLaunchLayers], tw_m[kMaxLaunchLayers];
+    int num_layers;
+    int k;
+    const int32_t* idx;                    // [num_layers][k][3]
+    const double* tw;
+};
+hipError_t launch_other_side_f32(const OtherSideArgs<float>& a, hipStream_t s);
+hipError_t launch_other_side_f64(const OtherSideArgs<double>& a, hipStream_t s);
 
 // Persistent launch over a work list covering several layers.
 template <typename R>

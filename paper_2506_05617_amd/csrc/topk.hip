@@ -145,11 +145,18 @@ __global__ void __launch_bounds__(256) adjoint_kernel(AdjointArgs<R> a) {
             if (valid) {   // entries outside the grid contribute nothing
                 const int p = idx[3 * s], q = idx[3 * s + 1], j = idx[3 * s + 2];
                 // compact slots: the pick that decomposed this symbol (the
-                // conjugate symbol's vectors are the conjugates)
+                // conjugate symbol's vectors are the conjugates); per-pick
+                // vectors: the pick's own column
                 bool cj = false;
-                const long long sym = a.compact ? pick_rep(idx, s, n, m, cj) : ((long long)p * m + q);
-                const cplx<R> uu = a.U[layer][(size_t)sym * c_out * r + (size_t)o * r + j];
-                const cplx<R> vv = a.V[layer][(size_t)sym * c_in * r + (size_t)i * r + j];
+                cplx<R> uu, vv;
+                if (a.compact == 2) {
+                    uu = a.U[layer][(size_t)s * c_out + o];
+                    vv = a.V[layer][(size_t)s * c_in + i];
+                } else {
+                    const long long sym = a.compact ? pick_rep(idx, s, n, m, cj) : ((long long)p * m + q);
+                    uu = a.U[layer][(size_t)sym * c_out * r + (size_t)o * r + j];
+                    vv = a.V[layer][(size_t)sym * c_in * r + (size_t)i * r + j];
+                }
                 // z = u * conj(v), conjugated with the vectors
                 zr[u] = uu.x * vv.x + uu.y * vv.y;
                 zi[u] = cj ? uu.x * vv.y - uu.y * vv.x : uu.y * vv.x - uu.x * vv.y;
@@ -170,7 +177,98 @@ __global__ void __launch_bounds__(256) adjoint_kernel(AdjointArgs<R> a) {
     }
 }
 
+// One work-group per (layer, pick): the kept vector x (column j of the
+// kept side at the pick's frequency) and the conjugated or plain phases of
+// the taps go to LDS; each thread forms entries of the other vector,
+//   v[i] = (1/sigma) sum_o sum_t W[o,i,t] e^{-2 pi i <k, y_t>} u[o]    (kept U)
+//   u[o] = (1/sigma) sum_i sum_t W[o,i,t] e^{+2 pi i <k, y_t>} v[i]    (kept V),
+// over the kept side's channels in a fixed order.  A pick with sigma not
+// positive (or outside the grid) gets zero vectors: it adds nothing to dW.
+template <typename R>
+__global__ void __launch_bounds__(256) other_side_kernel(OtherSideArgs<R> a) {
+    extern __shared__ __align__(16) char lds_raw[];
+    const int layer = blockIdx.x / a.k, s = blockIdx.x - (blockIdx.x / a.k) * a.k;
+    const int c_out = a.c_out[layer], c_in = a.c_in[layer], kh = a.kh[layer], kw = a.kw[layer];
+    const int n = a.n[layer], m = a.m[layer];
+    const int T = kh * kw, r = c_out < c_in ? c_out : c_in;
+    const bool keep_u = c_out >= c_in;               // the working matrix's side
+    const int ck = keep_u ? c_out : c_in, co = keep_u ? c_in : c_out;
+    cplx<R>* ph = reinterpret_cast<cplx<R>*>(lds_raw);                  // [T]
+    cplx<R>* x = ph + T;                                                  // [ck]
+    const int32_t* pk = a.idx + ((size_t)layer * a.k + s) * 3;
+    const int p = pk[0], q = pk[1], j = pk[2];
+    cplx<R>* kept_out = (keep_u ? a.Uc[layer] : a.Vc[layer]) + (size_t)s * ck;
+    cplx<R>* other_out = (keep_u ? a.Vc[layer] : a.Uc[layer]) + (size_t)s * co;
+    const bool valid = p >= 0 && p < n && q >= 0 && q < m && j >= 0 && j < r;
+    const R sg = valid ? a.sigma[layer][((size_t)p * m + q) * r + j] : R(0);
+    if (!(sg > R(0)) || !(sg < INFINITY)) {
+        for (int e = threadIdx.x; e < ck; e += blockDim.x) kept_out[e] = {R(0), R(0)};
+        for (int e = threadIdx.x; e < co; e += blockDim.x) other_out[e] = {R(0), R(0)};
+        return;
+    }
+    for (int t = threadIdx.x; t < T; t += blockDim.x) {
+        const int aa = t / kw, bb = t - (t / kw) * kw;
+        const int y1 = aa - (kh - 1) / 2, y2 = bb - (kw - 1) / 2;
+        int i1 = (p * y1) % n;
+        if (i1 < 0) i1 += n;
+        int i2 = (q * y2) % m;
+        if (i2 < 0) i2 += m;
+        const double ar = a.tw[2 * (a.tw_n[layer] + i1)], ai = a.tw[2 * (a.tw_n[layer] + i1) + 1];
+        const double br = a.tw[2 * (a.tw_m[layer] + i2)], bi = a.tw[2 * (a.tw_m[layer] + i2) + 1];
+        // exp(+2 pi i <k, y>) for the kept V side, its conjugate for kept U
+        const double im = ar * bi + ai * br;
+        ph[t] = {R(ar * br - ai * bi), R(keep_u ? -im : im)};
+    }
+    const cplx<R>* xs = a.X[layer] + ((size_t)p * m + q) * ck * r;
+    for (int e = threadIdx.x; e < ck; e += blockDim.x) {
+        x[e] = xs[(size_t)e * r + j];
+        kept_out[e] = x[e];
+    }
+    __syncthreads();
+    const R inv = R(1) / sg;
+    const R* W = a.W[layer];
+    for (int e = threadIdx.x; e < co; e += blockDim.x) {
+        R zr = R(0), zi = R(0);
+        for (int c = 0; c < ck; ++c) {
+            // weight (o, i) = (c, e) for kept U, (e, c) for kept V
+            const R* w = W + (keep_u ? ((size_t)c * c_in + e) : ((size_t)e * c_in + c)) * T;
+            R ar = R(0), ai = R(0);                  // sum_t w_t phase_t
+            for (int t = 0; t < T; ++t) {
+                ar = fma(w[t], ph[t].x, ar);
+                ai = fma(w[t], ph[t].y, ai);
+            }
+            const cplx<R> xv = x[c];
+            zr = fma(ar, xv.x, fma(-ai, xv.y, zr));
+            zi = fma(ar, xv.y, fma(ai, xv.x, zi));
+        }
+        other_out[e] = {zr * inv, zi * inv};
+    }
+}
+
 }  // namespace
+
+hipError_t launch_other_side_f32(const OtherSideArgs<float>& a, hipStream_t s) {
+    int maxT = 0, maxC = 0;
+    for (int l = 0; l < a.num_layers; ++l) {
+        maxT = a.kh[l] * a.kw[l] > maxT ? a.kh[l] * a.kw[l] : maxT;
+        const int ck = a.c_out[l] >= a.c_in[l] ? a.c_out[l] : a.c_in[l];
+        maxC = ck > maxC ? ck : maxC;
+    }
+    const size_t lds = sizeof(cplx<float>) * (size_t)(maxT + maxC);
+    hipLaunchKernelGGL(other_side_kernel<float>, dim3(a.num_layers * a.k), dim3(256), lds, s, a);
+    return hipGetLastError();
+}
+hipError_t launch_other_side_f64(const OtherSideArgs<double>& a, hipStream_t s) {
+    int maxT = 0, maxC = 0;
+    for (int l = 0; l < a.num_layers; ++l) {
+        maxT = a.kh[l] * a.kw[l] > maxT ? a.kh[l] * a.kw[l] : maxT;
+        const int ck = a.c_out[l] >= a.c_in[l] ? a.c_out[l] : a.c_in[l];
+        maxC = ck > maxC ? ck : maxC;
+    }
+    const size_t lds = sizeof(cplx<double>) * (size_t)(maxT + maxC);
+    hipLaunchKernelGGL(other_side_kernel<double>, dim3(a.num_layers * a.k), dim3(256), lds, s, a);
+    return hipGetLastError();
+}
 
 hipError_t launch_topk_f32(const TopkArgs<float>& a, hipStream_t s) {
     hipLaunchKernelGGL(topk_kernel<float>, dim3(a.num_layers), dim3(kTopkThreads), 0, s, a);

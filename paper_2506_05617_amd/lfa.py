@@ -118,6 +118,12 @@ class Plan:
               "lfa_plan_queue_info")
         return tuple(v.value for v in vals)
 
+    def preconditioned(self, layer):
+        """True when svd() runs the layer through QR preconditioning."""
+        v = ctypes.c_int32()
+        check(self.lib.lfa_plan_preconditioned(self.handle, layer, ctypes.byref(v)), "lfa_plan_preconditioned")
+        return bool(v.value)
+
     def launch_shape(self, layer):
         vals = [ctypes.c_int32() for _ in range(4)]
         check(self.lib.lfa_plan_launch_shape(self.handle, layer, *[ctypes.byref(v) for v in vals]),
@@ -282,6 +288,27 @@ class Plan:
               "lfa_adjoint")
         return dW
 
+    def adjoint_onesided(self, Ws, S, X, idx, grad, out=None):
+        """dW of sum_s g_s sigma_s from the kept side X of each layer's SVD
+        (U for c_out >= c_in, V otherwise; as svd() writes it) and the
+        weights, which give the other side of each pick (lfa_adjoint_onesided)."""
+        dev = self._check_weights(Ws)
+        k = idx.shape[1]
+        dW = out if out is not None else [
+            torch.empty(l.c_out, l.c_in, l.kh, l.kw, dtype=self.dtype, device=dev) for l in self.layers]
+        ws = self.workspace(dev)
+        w_arr, _k0 = ptr_array([x.data_ptr() for x in Ws])
+        s_arr, _k1 = ptr_array([x.data_ptr() for x in S])
+        x_arr, _k2 = ptr_array([x.data_ptr() for x in X])
+        d_arr, _k3 = ptr_array([x.data_ptr() for x in dW])
+        idx = idx.contiguous()
+        grad = grad.to(self.dtype).contiguous()
+        check(self.lib.lfa_adjoint_onesided(self.handle, w_arr, s_arr, x_arr, ctypes.c_void_p(idx.data_ptr()),
+                                            ctypes.c_void_p(grad.data_ptr()), k, d_arr,
+                                            ctypes.c_void_p(ws.data_ptr()), ctypes.c_size_t(ws.numel()),
+                                            _stream_ptr()), "lfa_adjoint_onesided")
+        return dW
+
     def sigma_grad(self, Ws, idx, grad, out=None, persistent=False):
         dev = self._check_weights(Ws)
         k = idx.shape[1]
@@ -319,18 +346,21 @@ class GraphStep:
     With a sigma-only plan the gradient recomputes the singular vectors of the
     picked symbols (lfa_graph_create).  With a plan that wants U and V the
     forward pass keeps them for every symbol (``self.U``, ``self.V``) and the
-    gradient is one adjoint launch (lfa_graph_create_uv)."""
+    gradient is one adjoint launch (lfa_graph_create_uv).  With a plan that
+    wants only U (every layer c_out >= c_in) or only V (every layer
+    c_out < c_in) the forward pass keeps that side, which needs no rotation
+    accumulator, and the gradient recomputes the other side of each pick
+    from the weights (lfa_graph_create_onesided)."""
 
     def __init__(self, plan: Plan, Ws, k, grad=None, stream=None):
-        if plan.want_u != plan.want_v:
-            raise ValueError("graph step needs a sigma-only plan or one that wants both U and V")
         self.plan = plan
         dev = plan._check_weights(Ws)
         self.W = Ws
         self.k = k
         self.stream = stream if stream is not None else torch.cuda.Stream(device=dev)
         uv = plan.want_u and plan.want_v
-        self.S, self.U, self.V = plan._alloc_outputs(dev, uv, uv)
+        one = plan.want_u != plan.want_v
+        self.S, self.U, self.V = plan._alloc_outputs(dev, plan.want_u, plan.want_v)
         L = len(plan.layers)
         self.vals = torch.empty(L, k, dtype=plan.dtype, device=dev)
         self.idx = torch.empty(L, k, 3, dtype=torch.int32, device=dev)
@@ -359,6 +389,12 @@ class GraphStep:
             self._keep += [k3, k4]
             check(plan.lib.lfa_graph_create_uv(plan.handle, w_arr, s_arr, u_arr, v_arr, *tail),
                   "lfa_graph_create_uv")
+        elif one:
+            self.X = self.U if plan.want_u else self.V
+            x_arr, k3 = ptr_array([x.data_ptr() for x in self.X])
+            self._keep += [k3]
+            check(plan.lib.lfa_graph_create_onesided(plan.handle, w_arr, s_arr, x_arr, *tail),
+                  "lfa_graph_create_onesided")
         else:
             check(plan.lib.lfa_graph_create(plan.handle, w_arr, s_arr, *tail), "lfa_graph_create")
         self.handle = h

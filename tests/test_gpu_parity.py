@@ -512,6 +512,68 @@ def test_graph_with_vectors_replay_matches_eager():
             _grad_check(W64, l, to_np(idx)[li], np.ones(8), dW[li], f"uv replay {rep} layer {li} eager")
 
 
+@pytest.mark.parametrize("wide", [False, True])
+@pytest.mark.parametrize("persistent", [False, True])
+def test_onesided_adjoint_matches_oracle(wide, persistent):
+    """Forward pass keeping only the accumulator-free side (U of tall layers,
+    V of wide ones), top-8, and lfa_adjoint_onesided (the other side of
+    each pick recomputed from W): dW against the oracle's gradient for the
+    same picks (elementwise for separated picks) and against the full
+    adjoint of a plan keeping both sides."""
+    banner(f"one-sided adjoint wide={wide} persistent={persistent}")
+    shapes = ((3, 16, 8), (16, 64, 6), (64, 96, 4), (96, 160, 3))
+    if wide:
+        shapes = tuple((co, ci, n) for ci, co, n in shapes)
+    layers, Ws = workloads.resnet18_stack(seed=27, shapes=shapes)
+    specs = [lfa().LayerSpec(l.c_out, l.c_in, l.kh, l.kw, l.n, l.m) for l in layers]
+    plan = lfa().Plan(specs, want_u=not wide, want_v=wide)
+    Wt = [_w(W) for W in Ws]
+    S, U, V, info = plan.svd(Wt, persistent=persistent)
+    X = V if wide else U
+    vals, idx = plan.topk(S, 8)
+    g = torch.linspace(0.5, 1.5, 8, device=DEV).repeat(len(layers), 1)
+    dW = plan.adjoint_onesided(Wt, S, X, idx, g)
+    plan_uv = lfa().Plan(specs, want_u=True, want_v=True)
+    _, U2, V2, _ = plan_uv.svd(Wt)
+    dW2 = plan_uv.adjoint(U2, V2, idx, g)
+    torch.cuda.synchronize()
+    assert plan.info_status(info) == 0
+    idx_np, g_np = to_np(idx), to_np(g).astype(np.float64)
+    for li, l in enumerate(layers):
+        W64 = Ws[li].astype(np.float64)
+        ref = oracle.sigma_grad(W64, l.n, l.m, idx_np[li], g_np[li])
+        _grad_check(W64, l, idx_np[li], g_np[li], dW[li], f"one-sided layer {li}", ref)
+        _grad_check(W64, l, idx_np[li], g_np[li], dW2[li], f"two-sided layer {li}", ref)
+
+
+def test_onesided_graph_replay_matches_oracle():
+    """lfa_graph_create_onesided: three replays with new weights and eager
+    work in between; each replay's top-8 values against the oracle's
+    spectrum and its dW against the oracle's gradient for its picks."""
+    banner("one-sided graph replay")
+    layers, Ws = _small_stack(seed=29)
+    specs = [lfa().LayerSpec(l.c_out, l.c_in, l.kh, l.kw, l.n, l.m) for l in layers]
+    plan = lfa().Plan(specs, want_u=True)
+    Wt = [_w(W) for W in Ws]
+    step = lfa().GraphStep(plan, Wt, 8)
+    rng = np.random.default_rng(30)
+    for rep in range(3):
+        news = [(rng.standard_normal(W.shape) * 0.1).astype(np.float32) for W in Ws]
+        for W, x in zip(Wt, news):
+            W.copy_(torch.from_numpy(x))
+        step.replay().synchronize()
+        assert plan.info_status(step.info) == 0
+        v, ix = to_np(step.vals), to_np(step.idx)
+        for li, l in enumerate(layers):
+            W64 = news[li].astype(np.float64)
+            s_ref = oracle.lfa_svd(W64, l.n, l.m)
+            ov, _ = oracle.topk(s_ref, 8)
+            np.testing.assert_allclose(v[li], ov, rtol=0, atol=1e-5 * ov[0])
+            _grad_check(W64, l, ix[li], np.ones(8), step.dW[li], f"one-sided replay {rep} layer {li}")
+        plan.topk(step.S, 8)
+        torch.cuda.synchronize()
+
+
 # ------------------------------------------------- spectral functions --
 
 APPLY_GPU_CASES = [
@@ -734,6 +796,55 @@ def test_crystal_sigma_grad_matches_finite_differences():
         fd = (loss(W + h * D) - loss(W - h * D)) / (2 * h)
         an = float(np.sum(dW * D))
         assert abs(an - fd) <= 1e-6 * max(1.0, abs(fd)), (an, fd)
+
+
+QR_CASES = [
+    # c_out, c_in, kh, n, m: FP32 sigma-only layers the plan runs through QR
+    # preconditioning (working matrix M x N with M > 64 and 4 M >= 5 N)
+    (160, 96, 3, 4, 5),       # blocked kernel on the 96 x 96 factors
+    (96, 160, 3, 5, 4),       # wide: G = A^H, factors of A A^H
+    (128, 64, 3, 6, 6),       # 64 x 64 factors: the register kernel
+    (512, 256, 3, 4, 4),      # the rectangular layer's shape on a small grid
+    (200, 24, 1, 3, 7),       # 1x1 kernel, odd grid
+]
+
+
+@pytest.mark.parametrize("case", QR_CASES)
+def test_qr_preconditioned_sigma_matches_oracle(case, monkeypatch):
+    """Sigma of tall FP32 layers through the Gram-taps Cholesky factors
+    (QR preconditioning) against the oracle over the whole grid, and against
+    the same plan without preconditioning (LFA_NO_QR, read at plan
+    creation); Parseval over the whole grid."""
+    c_out, c_in, kh, n, m = case
+    banner(f"qr {case}")
+    L, W = workloads.random_layer(c_out, c_in, kh, kh, n, m, seed=51)
+    spec = lfa().LayerSpec(c_out, c_in, kh, kh, n, m)
+    S, info = (lambda r: (r[0][0], r[3]))(lfa().Plan([spec]).svd([_w(W)]))
+    monkeypatch.setenv("LFA_NO_QR", "1")
+    S2 = lfa().Plan([spec]).svd([_w(W)])[0][0]
+    torch.cuda.synchronize()
+    assert lfa().Plan([spec]).info_status(info) == 0
+    S_ref = oracle.lfa_svd(W.astype(np.float64), n, m)
+    e1 = oracle.sigma_error(to_np(S), S_ref)
+    e2 = oracle.sigma_error(to_np(S2), S_ref)
+    print(f"[qr] {case}: error with QR {e1:.2e}, without {e2:.2e}", flush=True)
+    assert e1 <= 1e-5 and e2 <= 1e-5
+    ss = torch.sum(S.double() ** 2).item()
+    assert abs(ss / (n * m * np.sum(W.astype(np.float64) ** 2)) - 1) <= 1e-5
+
+
+def test_qr_preconditioned_rank_deficient_zeros():
+    """Rank-one taps (rank <= 9 per symbol) through QR preconditioning: the
+    numerically singular pivots give zero rows of R, and the singular values
+    beyond the rank come out exactly 0; the others match the oracle."""
+    banner("qr rank-one")
+    L, W = workloads.rank_one_taps(c_out=192, c_in=96, n=4)
+    spec = lfa().LayerSpec(L.c_out, L.c_in, L.kh, L.kw, L.n, L.m)
+    S = lfa().Plan([spec]).svd([_w(W)])[0][0]
+    torch.cuda.synchronize()
+    S_ref = oracle.lfa_svd(W.astype(np.float64), L.n, L.m)
+    assert oracle.sigma_error(to_np(S), S_ref) <= 1e-5
+    assert np.all(to_np(S)[..., 9:] == 0)
 
 
 # ------------------------------------------------- rank-deficient symbols --
@@ -969,6 +1080,42 @@ def test_resnet18_stack_full_size_vectors_graph():
             _grad_check(W64, l, idx[li], np.ones(8), step.dW[li], f"uv graph replay {rep} layer {li}",
                         refs[key])
         # eager work between the replays
+        plan.topk(step.S, 8)
+        torch.cuda.synchronize()
+
+
+def test_resnet18_stack_full_size_onesided_graph():
+    """The benchmark's batched step: one HIP graph of the persistent SVD
+    keeping U of every symbol (no rotation accumulator), top-8 and the
+    one-sided adjoint, replayed twice with eager work in between: top-8
+    values against the oracle's singular values at the picks, dW against
+    the oracle's gradient elementwise, every symbol's sigma within the gate
+    on sampled frequencies of each layer."""
+    banner("ResNet-18 stack full size, one-sided graph")
+    layers, Ws = workloads.resnet18_stack()
+    specs = [lfa().LayerSpec(l.c_out, l.c_in, l.kh, l.kw, l.n, l.m) for l in layers]
+    plan = lfa().Plan(specs, want_u=True)
+    Wt = [_w(W) for W in Ws]
+    step = lfa().GraphStep(plan, Wt, 8)
+    refs = {}
+    for rep in range(2):
+        step.replay().synchronize()
+        assert plan.info_status(step.info) == 0
+        vals, idx = to_np(step.vals), to_np(step.idx)
+        for li, l in enumerate(layers):
+            W64 = Ws[li].astype(np.float64)
+            p, q, j = idx[li].T
+            s_at = oracle.lfa_svd(W64, l.n, l.m, freqs=np.stack([p, q], axis=1))[np.arange(8), j]
+            assert np.max(np.abs(vals[li] - s_at)) <= 1e-5 * s_at.max(), (rep, li)
+            key = (li, idx[li].tobytes())
+            if key not in refs:
+                refs[key] = oracle.sigma_grad(W64, l.n, l.m, idx[li], np.ones(8))
+            _grad_check(W64, l, idx[li], np.ones(8), step.dW[li], f"one-sided graph {rep} layer {li}",
+                        refs[key])
+            if rep == 0:
+                fr = _sample(l.n, l.m, 4, 40 + li)
+                S_ref = oracle.lfa_svd(W64, l.n, l.m, freqs=fr)
+                assert oracle.sigma_error(to_np(step.S[li])[fr[:, 0], fr[:, 1]], S_ref) <= 1e-5
         plan.topk(step.S, 8)
         torch.cuda.synchronize()
 
