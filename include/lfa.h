@@ -465,9 +465,14 @@ int lfa_plan_launch_shape(const lfa_plan* plan, int32_t layer, int32_t* lanes_pe
  * the N x N Cholesky factors R of the symbols' Gram matrices, formed in FP64
  * from the Gram convolution's taps, then the one-sided Jacobi SVD of R,
  * whose N rows replace the symbol's M (the singular values of R and of the
- * symbol agree to about sqrt(N u64) sigma_max).  Chosen at plan creation for
- * FP32 sigma-only plans with working matrices of M > 64 rows and M >= 1.25 N
- * (the environment variable LFA_NO_QR, read then, turns it off).  Host only. */
+ * symbol agree to about sqrt(N u64) sigma_max); with singular vectors the
+ * SVD of R keeps V and U follows from G V.  Chosen at plan creation for
+ * FP32 plans (any flags but the matrix-core assembly ones) whose working
+ * matrices have M > 64 rows and M >= 1.25 N, when the factors are small
+ * enough for the register kernel (N <= 64) or the layer has at least 256
+ * symbols to decompose (one per conjugate pair); lfa_autotune may change
+ * it.  The environment variable LFA_QR, read at plan creation, turns it off
+ * ("0") or on for every layer of such a shape ("1").  Host only. */
 int lfa_plan_preconditioned(const lfa_plan* plan, int32_t layer, int32_t* qr);
 
 /* Work-queue launch of a layer's register kernel (symbols of at most 64

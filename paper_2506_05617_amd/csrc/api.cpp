@@ -270,14 +270,30 @@ size_t sel_bytes(const lfa_layer& l, int eb) {
 // taller than wide and the blocked kernel would run it (M > 64): the
 // sweeps then touch N rows instead of M.  FP32 plans only: the factor is
 // accurate to about sqrt(N u64) sigma_max, far inside the FP32 tolerance
-// but not the FP64 one.  Sigma only (the left singular vectors would need
-// G V S^-1 after the SVD of R).
+// but not the FP64 one.  With singular vectors the SVD of R keeps its
+// right vectors and the left ones come from G V (qr_left_kernel).
+// Measured on MI355X (sigma only / U / U and V): the 512 x 256 layer on the
+// 32 x 32 grid (514 decomposed symbols) 112 -> 60 / 112 -> 92 / 152 -> 92 ms
+// with the factors; 128 x 64 on 16 x 16 (factors run by the register
+// kernel) 1.50 -> 1.15 / 1.55 -> 1.25 / 2.21 -> 1.25 ms; but with a few
+// symbols of blocked-kernel factors (256 x 128 on 8 x 8, 36 symbols;
+// 512 x 256 on 4 x 4, 10 symbols) the direct kernel's teams were as fast
+// or faster (3.0 vs 3.4, 8.5 vs 8.3 sigma only; 3.1 vs 4.5, 8.7 vs 10.9
+// with U).  So by default: factors whose SVD the register kernel runs
+// (N <= 64), or at least a device's worth of symbols (one per CU of
+// MI355X); lfa_autotune times both where it matters.
+constexpr int kQrMinSymbols = 256;
 bool qr_applies(const lfa_layer& l, int dtype, uint32_t flags) {
     const int M = std::max(l.c_out, l.c_in), N = std::min(l.c_out, l.c_in);
-    if (dtype != LFA_F32 || (flags & (LFA_WANT_U | LFA_WANT_V))) return false;
+    if (dtype != LFA_F32) return false;
     if (flags & (LFA_ASM_MFMA | LFA_ASM_BF16X2 | LFA_ASM_BF16X3)) return false;
-    if (std::getenv("LFA_NO_QR")) return false;
-    return M > 64 && 4 * M >= 5 * N;
+    if (!(M > 64 && 4 * M >= 5 * N)) return false;
+    // LFA_QR: "0" off, "1" on for every such layer (tests, tuning)
+    if (const char* env = std::getenv("LFA_QR")) {
+        if (std::strcmp(env, "0") == 0) return false;
+        if (std::strcmp(env, "1") == 0) return true;
+    }
+    return N <= 64 || canonical_count(l.n, l.m) >= kQrMinSymbols;
 }
 
 size_t qr_taps_bytes(const lfa_layer& l) {
@@ -291,6 +307,27 @@ size_t qr_rsym_bytes(const lfa_layer& l, int eb) {
 size_t qr_hslot_bytes(const lfa_layer& l) {
     const size_t N = std::min(l.c_out, l.c_in);
     return align_up((size_t)canonical_count(l.n, l.m) * N * N * 2 * sizeof(double));
+}
+// Slots of the vectors' finish: Y (ldg x N) and V_R (ldv x N) per item.
+size_t qr_vec_slot_bytes(const LayerDesc& d, int eb) {
+    return align_up((size_t)2 * eb * ((size_t)d.ldg * d.N + (size_t)d.ldv * d.N));
+}
+// The preconditioned path's region: R symbols (overwritten by the right
+// singular vectors of R when vectors are wanted), then the Gram taps and
+// the Cholesky slots or the R SVD's own region; the vectors' slots follow
+// the R symbols once the taps and those are done.
+size_t qr_region_bytes(const lfa_plan& p, int i, bool queue) {
+    const int eb = elem_bytes(p.dtype);
+    const bool vec = (p.flags & (LFA_WANT_U | LFA_WANT_V)) != 0;
+    const lfa_layer& l = p.layers[i];
+    const LayerDesc& dr = p.desc_r[i];
+    LayerDesc drg = dr;
+    drg.storage = (lds_bytes_for(dr, vec, eb) > kLdsSafe) ? kGlobal : dr.storage;
+    size_t svd_r = kCounterBytes + (size_t)svd_grid(drg, dr.num_symbols) * slot_bytes(drg, vec, eb);
+    if (queue && dr.wave_qgroups > 0) svd_r = std::max(svd_r, wave_queue_bytes(dr, vec, eb, dr.wave_qgroups));
+    size_t after = qr_taps_bytes(l) + std::max(svd_r, qr_hslot_bytes(l));
+    if (vec) after = std::max(after, (size_t)p.desc[i].num_canon * qr_vec_slot_bytes(p.desc[i], eb));
+    return qr_rsym_bytes(l, eb) + after;
 }
 
 // Per-pick vectors of the one-sided adjoint: [k][c_out] and [k][c_in]
@@ -325,17 +362,7 @@ size_t workspace_bytes(const lfa_plan& p) {
         // register kernel: work-queue control, entries, meta and saved state
         if (d.wave_qgroups > 0) s = std::max(s, sym + wave_queue_bytes(d, acc, eb, d.wave_qgroups));
         need = std::max(need, s);
-        if (p.qr[i]) {
-            // R symbols, Gram taps, then the Cholesky slots or the SVD's own
-            // region (counters and slots, or the work queue) of the R layer
-            const LayerDesc& dr = p.desc_r[i];
-            LayerDesc drg = dr;
-            drg.storage = (lds_bytes_for(dr, false, eb) > kLdsSafe) ? kGlobal : dr.storage;
-            size_t svd_r = kCounterBytes + (size_t)svd_grid(drg, dr.num_symbols) * slot_bytes(drg, false, eb);
-            if (dr.wave_qgroups > 0) svd_r = std::max(svd_r, wave_queue_bytes(dr, false, eb, dr.wave_qgroups));
-            need = std::max(need, qr_rsym_bytes(p.layers[i], eb) + qr_taps_bytes(p.layers[i]) +
-                                      std::max(svd_r, qr_hslot_bytes(p.layers[i])));
-        }
+        if (p.qr[i]) need = std::max(need, qr_region_bytes(p, (int)i, true));
         // lfa_sigma_grad: compact outputs of <= kMaxTopk symbols + slots
         const LayerDesc& ds = p.desc_sel[i];
         LayerDesc dsg = ds;
@@ -390,13 +417,14 @@ void build_schedule(lfa_plan* p) {
     size_t wmax = 0;
     for (int i = 0; i < nl; ++i)
         if (p->desc_pers[i].kind == 1)
-            wmax = std::max(wmax, lfa::wave_lds_bytes_for(p->desc_pers[i].wave_nc, p->desc_pers[i].wave_ml, eb));
+            wmax = std::max(wmax, lfa::wave_bundle_lds_for(p->desc_pers[i].wave_nc, p->desc_pers[i].wave_ml, eb,
+                                                           wu || wv));
     p->pers_wave_slots = wmax ? (int)std::max<size_t>(1, std::min<size_t>(4, kLdsCap / wmax)) : 4;
     for (int l0 = 0; l0 < nl; l0 += kMaxLaunchLayers) {
         const int l1 = std::min(nl, l0 + kMaxLaunchLayers);
         p->chunk_first.push_back((int)p->items.size());
         const bool acc_any = p->pers_acc;
-        const size_t lds = persistent_lds_bytes(p->desc_pers.data() + l0, l1 - l0, acc_any, eb,
+        const size_t lds = persistent_lds_bytes(p->desc_pers.data() + l0, l1 - l0, acc_any, wu || wv, eb,
                                                 p->pers_wave_slots);
         int grid = persistent_resident(lds, eb, acc_any);
         if (grid <= 0) grid = std::max(1, p->num_cus);
@@ -499,12 +527,13 @@ int ensure_device(lfa_plan* p, hipStream_t st = nullptr, bool check_capture = fa
             p->desc[i].storage = kGlobal;
         {
             LayerDesc& dr = p->desc_r[i];
+            const bool vec = wu || wv;
             if (dr.kind == 1) {
-                dr.wave_cap = wave_blocks_per_cu(dr.wave_nc, dr.wave_ml, eb, dr.threads, false) * p->num_cus;
+                dr.wave_cap = wave_blocks_per_cu(dr.wave_nc, dr.wave_ml, eb, dr.threads, vec) * p->num_cus;
                 if (dr.wave_qgroups > 0)
-                    dr.wave_qcap = wave_queue_blocks_per_cu(dr.wave_nc, dr.wave_ml, eb, dr.threads, false) * p->num_cus;
+                    dr.wave_qcap = wave_queue_blocks_per_cu(dr.wave_nc, dr.wave_ml, eb, dr.threads, vec) * p->num_cus;
             }
-            if (lds_bytes_for(dr, false, eb) > lds_dev) dr.storage = kGlobal;
+            if (lds_bytes_for(dr, vec, eb) > lds_dev) dr.storage = kGlobal;
         }
         if (lds_bytes_for(p->desc_sel[i], true, eb) > lds_dev) p->desc_sel[i].storage = kGlobal;
         if (lds_bytes_for(p->desc_pers[i], accumulates(p->desc_pers[i], wu, wv), eb) > lds_dev)
@@ -648,13 +677,7 @@ size_t svd_need(const lfa_plan& p, bool queue) {
         const size_t sym = asm_materialized(p.flags) ? symbols_bytes(p.layers[i], eb) : 0;
         size_t s = sym + (size_t)svd_grid(d, d.num_symbols) * slot_bytes(d, acc, eb);
         if (queue && d.wave_qgroups > 0) s = std::max(s, sym + wave_queue_bytes(d, acc, eb, d.wave_qgroups));
-        if (p.qr[i]) {
-            const LayerDesc& dr = p.desc_r[i];
-            size_t svd_r = kCounterBytes + (size_t)svd_grid(dr, dr.num_symbols) * slot_bytes(dr, false, eb);
-            if (queue && dr.wave_qgroups > 0) svd_r = std::max(svd_r, wave_queue_bytes(dr, false, eb, dr.wave_qgroups));
-            s = qr_rsym_bytes(p.layers[i], eb) + qr_taps_bytes(p.layers[i]) +
-                std::max(svd_r, qr_hslot_bytes(p.layers[i]));
-        }
+        if (p.qr[i]) s = qr_region_bytes(p, (int)i, queue);
         need = std::max(need, s);
     }
     return kAlign + kCounterBytes + align_up(need);
@@ -718,9 +741,49 @@ int svd_impl(const lfa_plan* p, const void* const* W, const void* const* A, void
             if constexpr (sizeof(R) == 4) e = launch_gram_qr_f32(g, d.num_canon, st);
             else e = launch_gram_qr_f64(g, d.num_canon, st);
             HIP_TRY(e);
-            LFA_TRY(run_svd_layer<R>(p, p->desc_r[i], nullptr, rsym, sigma[i], nullptr, nullptr,
+            const bool vec = wu || wv;
+            // with vectors the SVD of R writes its right singular vectors over
+            // the factors (each work-group reads its own canonical factor
+            // before it writes that frequency and its mirror)
+            LFA_TRY(run_svd_layer<R>(p, p->desc_r[i], nullptr, rsym, sigma[i], nullptr,
+                                     vec ? reinterpret_cast<cplx<R>*>(rsym) : nullptr,
                                      info ? info + i * LFA_INFO_WORDS : nullptr, rest, nullptr, 0, 0, st,
                                      true, queue_ok));
+            if (vec) {
+                QrVecArgs<R> q{};
+                q.W = static_cast<const R*>(W[i]);
+                q.c_out = l.c_out;
+                q.c_in = l.c_in;
+                q.kh = l.kh;
+                q.kw = l.kw;
+                q.n = l.n;
+                q.m = l.m;
+                q.M = d.M;
+                q.N = d.N;
+                q.transposed = d.transposed;
+                q.tw_n = d.tw_n;
+                q.tw_m = d.tw_m;
+                q.tw = p->tw_dev;
+                q.VR = reinterpret_cast<const cplx<R>*>(rsym);
+                q.sigma = static_cast<const R*>(sigma[i]);
+                q.slots = rsym + qr_rsym_bytes(l, sizeof(R));
+                q.slot_bytes = (long long)qr_vec_slot_bytes(d, sizeof(R));
+                q.ldg = d.ldg;
+                q.ldv = d.ldv;
+                SvdArgs<R> a{};
+                a.d = d;
+                a.d.storage = kGlobal;
+                a.canon = 1;
+                a.sigma = static_cast<R*>(sigma[i]);
+                a.U = wu ? static_cast<cplx<R>*>(U[i]) : nullptr;
+                a.V = wv ? static_cast<cplx<R>*>(V[i]) : nullptr;
+                a.tw = p->tw_dev;
+                a.gws = q.slots;
+                a.slot_bytes = q.slot_bytes;
+                if constexpr (sizeof(R) == 4) e = launch_qr_vectors_f32(q, a, d.num_canon, st);
+                else e = launch_qr_vectors_f64(q, a, d.num_canon, st);
+                HIP_TRY(e);
+            }
             continue;
         }
         // weights are real: decompose one symbol per conjugate pair.  Symbols
@@ -791,8 +854,8 @@ int persistent_impl(const lfa_plan* p, const void* const* W, void* const* sigma,
         size_t wl = 0;
         for (int i = l0; i < l1; ++i)
             if (p->desc_pers[i].kind == 1)
-                wl = std::max(wl, wave_lds_bytes_for(p->desc_pers[i].wave_nc, p->desc_pers[i].wave_ml,
-                                                     (int)sizeof(R)));
+                wl = std::max(wl, wave_bundle_lds_for(p->desc_pers[i].wave_nc, p->desc_pers[i].wave_ml,
+                                                     (int)sizeof(R), wu || wv));
         pa.wave_lds = (int)wl;
         HIP_TRY(launch_fill_i32(counter, 0, 1, st));
         HIP_TRY(launch_fill_i32(team_counters, 0, 4LL * p->pers_teams + 4, st));
@@ -919,7 +982,7 @@ int ensure_grad_schedule(lfa_plan* p, int k, hipStream_t st, bool check_capture,
     for (int l0 = 0; l0 < nl; l0 += kMaxLaunchLayers) {
         const int l1 = std::min(nl, l0 + kMaxLaunchLayers);
         gs.chunk_first.push_back((int)items.size());
-        const size_t lds = persistent_lds_bytes(p->desc_gsel.data() + l0, l1 - l0, true, eb, 1);
+        const size_t lds = persistent_lds_bytes(p->desc_gsel.data() + l0, l1 - l0, true, false, eb, 1);
         int grid = persistent_resident(lds, eb, true);
         if (grid <= 0) grid = std::max(1, p->num_cus);
         gs.lds.push_back(lds);
@@ -1194,7 +1257,7 @@ int lfa_plan_create(lfa_plan** out, const lfa_layer* layers, int32_t num_layers,
         // is compiled with or without the accumulator)
         const bool pacc = p->pers_acc;
         LayerDesc dp = make_desc(l, off[l.n], off[l.m], pacc, eb, kLdsCap);
-        if (dp.kind != 1 || wu || wv) {
+        if (dp.kind != 1 || pacc) {
             dp = make_desc(l, off[l.n], off[l.m], pacc, eb, kLdsCap);
             dp.kind = 2;
             dp.threads = kPersistentThreads;
@@ -1215,9 +1278,10 @@ int lfa_plan_create(lfa_plan** out, const lfa_layer* layers, int32_t num_layers,
             const bool q = qr_applies(l, dtype, flags);
             p->qr.push_back(q ? 1 : 0);
             lfa_layer lr{N, N, 1, 1, l.n, l.m};
-            LayerDesc dr = make_desc(lr, off[l.n], off[l.m], false, eb, kLdsCap);
+            const bool vec = wu || wv;       // the SVD of R keeps V_R
+            LayerDesc dr = make_desc(lr, off[l.n], off[l.m], vec, eb, kLdsCap);
             dr.num_canon = ncanon;
-            dr.wave_qgroups = q ? wave_queue_reserved(dr, false, eb) : 0;
+            dr.wave_qgroups = q ? wave_queue_reserved(dr, vec, eb) : 0;
             p->desc_r.push_back(dr);
         }
         p->desc_sel.back().num_canon = ncanon;

@@ -280,6 +280,20 @@ size_t wave_lds_bytes_for(int nc, int ml, int elem_bytes) {
     return 0;
 }
 
+size_t wave_bundle_lds_for(int nc, int ml, int elem_bytes, bool vectors) {
+    const size_t raw = wave_lds_bytes_for(nc, ml, elem_bytes);
+    if (!vectors) return raw;
+    size_t stage = 0;
+#define LFA_CASE(n_, m_)                                                                             \
+    if (nc == n_ && ml == m_)                                                                        \
+        stage = elem_bytes == 8 ? wave_stage_bytes<double, n_, m_>() : wave_stage_bytes<float, n_, m_>();
+    LFA_CASE(4, 16) LFA_CASE(8, 16) LFA_CASE(16, 16)
+    LFA_CASE(4, 32) LFA_CASE(8, 32) LFA_CASE(16, 32) LFA_CASE(32, 32)
+    LFA_CASE(4, 64) LFA_CASE(8, 64) LFA_CASE(16, 64) LFA_CASE(32, 64) LFA_CASE(64, 64)
+#undef LFA_CASE
+    return (((raw + 63) & ~size_t(63)) + stage + 63) & ~size_t(63);
+}
+
 int wave_blocks_per_cu(int nc, int ml, int elem_bytes, int threads, bool vectors) {
 #define LFA_CASE(n_, m_)                                                                \
     if (nc == n_ && ml == m_)                                                           \

@@ -323,6 +323,9 @@ hipError_t launch_crystal_weights(const CrystalArgs& a, int elem_bytes, const vo
 size_t lds_bytes_for(const LayerDesc& d, bool accumulate, int elem_bytes);
 
 size_t wave_lds_bytes_for(int nc, int ml, int elem_bytes);
+// LDS of one wave running a bundle in the persistent launch: the register
+// kernel's arrays, plus its output staging when it writes singular vectors.
+size_t wave_bundle_lds_for(int nc, int ml, int elem_bytes, bool vectors);
 size_t block_lds_bytes(const LayerDesc& d, bool accumulate, int elem_bytes);
 // Blocked kernel: `teams` teams of W work-groups (all resident at once when
 // W > 1) over the items [item0, item_end) of the layer; counters: 4*teams + 4
@@ -413,6 +416,25 @@ struct GramArgs {
     cplx<R>* Rsym;              // [n*m][N][N]; canonical frequencies written
 };
 size_t gram_cholesky_lds_bytes(int N, int kh, int kw);
+
+// Singular vectors of a preconditioned layer (qr.hip): Y = G_k V_R into
+// per-item slots (Y column-major with leading dimension ldg, then V_R with
+// ldv), then the blocked kernels' finish writing sigma, U, V.
+template <typename R>
+struct QrVecArgs {
+    const R* W;
+    int c_out, c_in, kh, kw, n, m;
+    int M, N, transposed;
+    int tw_n, tw_m;
+    const double* tw;
+    const cplx<R>* VR;          // [n*m][N][N] right singular vectors of R
+    const R* sigma;             // [n*m][N] singular values of R (same column order)
+    char* slots;                // [items] slots of slot_bytes
+    long long slot_bytes;
+    int ldg, ldv;
+};
+hipError_t launch_qr_vectors_f32(const QrVecArgs<float>& q, const SvdArgs<float>& a, int items, hipStream_t s);
+hipError_t launch_qr_vectors_f64(const QrVecArgs<double>& q, const SvdArgs<double>& a, int items, hipStream_t s);
 hipError_t launch_gram_qr_f32(const GramArgs<float>& g, int items, hipStream_t s);
 hipError_t launch_gram_qr_f64(const GramArgs<double>& g, int items, hipStream_t s);
 
@@ -458,7 +480,7 @@ constexpr int kPersistentThreads = 256;
 // LDS bytes of the persistent launch for the layers of `descs` (kind 1 bundles
 // with `wave_slots` waves, kind 2 blocked items with 256 threads), and the
 // number of work-groups of the launch that fit on the device at once.
-size_t persistent_lds_bytes(const LayerDesc* descs, int n, bool accumulate, int elem_bytes,
+size_t persistent_lds_bytes(const LayerDesc* descs, int n, bool accumulate, bool bundle_vectors, int elem_bytes,
                             int wave_slots);
 int persistent_resident(size_t lds, int elem_bytes, bool accumulate);
 hipError_t launch_persistent_f32(const PersistentArgs<float>& a, int grid, size_t lds, bool accumulate,

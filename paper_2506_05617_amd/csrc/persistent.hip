@@ -1,8 +1,10 @@
 // Persistent launch of the SVD of every layer of a plan: 256-thread
 // work-groups, about one per CU, take items from a device work list ordered
 // longest first (the host builds it; see WorkItem).  Small symbols (at most
-// 64 rows, no vectors) run as "bundles": each wave of the work-group runs the
-// register kernel on its own symbols with wave-local synchronisation.  Larger
+// 64 rows, no rotation accumulator) run as "bundles": each wave of the
+// work-group runs the register kernel on its own symbols with wave-local
+// synchronisation (writing the side of the vectors its working matrix gives,
+// if wanted, through its own staging LDS).  Larger
 // symbols run the blocked kernel, one row (or two) per thread, by teams of
 // W work-groups whose members are consecutive in the list; a team waits only
 // for members that were taken before it, and every work-group of the grid is
@@ -106,13 +108,14 @@ int resident_p(size_t lds) {
 
 }  // namespace
 
-size_t persistent_lds_bytes(const LayerDesc* descs, int n, bool accumulate, int elem_bytes,
+size_t persistent_lds_bytes(const LayerDesc* descs, int n, bool accumulate, bool bundle_vectors, int elem_bytes,
                             int wave_slots) {
     size_t lds = 0;
     for (int i = 0; i < n; ++i) {
         const LayerDesc& d = descs[i];
         if (d.kind == 1) {
-            lds = std::max(lds, (size_t)wave_slots * wave_lds_bytes_for(d.wave_nc, d.wave_ml, elem_bytes));
+            lds = std::max(lds, (size_t)wave_slots *
+                                    wave_bundle_lds_for(d.wave_nc, d.wave_ml, elem_bytes, bundle_vectors));
         } else {
             LayerDesc db = d;
             db.threads = kPersistentThreads;

@@ -24,12 +24,23 @@
 // sigma(R)^2 = sigma(G)^2 + O(N u64 sigma_max^2), so the singular values of
 // R in FP32 match those of G to about sqrt(N u64) sigma_max (3e-7 at N = 256),
 // well inside the FP32 tolerance.
+//
+// Singular vectors: the SVD of R keeps its right singular vectors V (those
+// of G), and the left ones follow as the columns of Y = G V, normalised
+// (Y = U S), which are orthogonal to about u sigma_max / sigma_j (columns
+// whose singular value the SVD of R found negligible are set to zero and
+// completed); qr_left_kernel forms Y with G assembled from the weights, and
+// the blocked kernels' finish then takes Y and V as its working matrix and
+// accumulator: column norms (sigma, with the negligible-column rule), sort,
+// normalisation, completion of the columns of zero singular values, and
+// the writes of sigma, U and V (mirror frequencies by conjugation).
 #include <hip/hip_runtime.h>
 
-#include "lfa_internal.hpp"
+#include "jacobi_device.hpp"
 
 namespace lfa {
 namespace {
+using namespace dev;
 
 constexpr int kGramTile = 32;     // output tile of C_delta (c, c')
 constexpr int kGramRows = 16;     // rows r per staged chunk
@@ -197,6 +208,126 @@ __global__ void __launch_bounds__(256) gram_cholesky_kernel(GramArgs<R> g) {
     }
 }
 
+constexpr int kQrRows = 64;      // rows of Y per work-group
+constexpr int kQrChunk = 16;     // columns c of G (rows of V) per staged chunk
+
+// Y = G_k V_R for the work-group (item, row tile, column tile): rows
+// r0 .. r0+63 and columns j0 .. j0+16 NW-1 of Y (M x N), with G_k assembled
+// from W (the symbol, or its conjugate transpose for a wide layer) in
+// chunks of 16 columns, staged in LDS beside the matching rows of V_R (the
+// right singular vectors of the factor R, [theta][c][j]).  Thread (rg, cg)
+// accumulates rows r0 + 4 rg + u (u < 4) and columns j0 + cg + 16 w (w < NW).
+// Y goes column-major into the item's slot, as the working matrix of the
+// finish; the (row tile 0, column tile 0) work-group also copies V_R into
+// the slot's accumulator part.
+template <typename R, int NW>
+__global__ void __launch_bounds__(256) qr_left_kernel(QrVecArgs<R> q) {
+    extern __shared__ __align__(16) char lds_raw[];
+    constexpr int JW = 16 * NW;
+    const int rtiles = (q.M + kQrRows - 1) / kQrRows, ctiles = (q.N + JW - 1) / JW;
+    const int item = blockIdx.x / (rtiles * ctiles);
+    const int rest = blockIdx.x - item * rtiles * ctiles;
+    const int r0 = (rest / ctiles) * kQrRows, j0 = (rest - (rest / ctiles) * ctiles) * JW;
+    const int theta = canonical_theta(q.n, q.m, item);
+    const int p = theta / q.m, qq = theta - (theta / q.m) * q.m;
+    const int N = q.N, T = q.kh * q.kw;
+    cplx<R>* ph = reinterpret_cast<cplx<R>*>(lds_raw);            // [T]
+    cplx<R>* gt = ph + T;                                           // [kQrRows][kQrChunk]
+    cplx<R>* vt = gt + kQrRows * kQrChunk;                          // [kQrChunk][JW]
+    const cplx<R>* VR = q.VR + (size_t)theta * N * N;
+    cplx<R>* slot = reinterpret_cast<cplx<R>*>(q.slots + (size_t)item * q.slot_bytes);
+    cplx<R>* Y = slot;                                              // [N][ldg]
+    cplx<R>* Qs = slot + (size_t)q.ldg * N;                        // [N][ldv]
+    for (int t = threadIdx.x; t < T; t += blockDim.x) {
+        const int aa = t / q.kw, bb = t - (t / q.kw) * q.kw;
+        const int y1 = aa - (q.kh - 1) / 2, y2 = bb - (q.kw - 1) / 2;
+        int i1 = (p * y1) % q.n;
+        if (i1 < 0) i1 += q.n;
+        int i2 = (qq * y2) % q.m;
+        if (i2 < 0) i2 += q.m;
+        const double ar = q.tw[2 * (q.tw_n + i1)], ai = q.tw[2 * (q.tw_n + i1) + 1];
+        const double br = q.tw[2 * (q.tw_m + i2)], bi = q.tw[2 * (q.tw_m + i2) + 1];
+        const double im = ar * bi + ai * br;
+        ph[t] = {R(ar * br - ai * bi), R(q.transposed ? -im : im)};
+    }
+    if (rest == 0)
+        for (int e = threadIdx.x; e < N * N; e += blockDim.x) {
+            const int c = e / N, j = e - (e / N) * N;
+            Qs[(size_t)j * q.ldv + c] = VR[e];
+        }
+    const int rg = threadIdx.x >> 4, cg = threadIdx.x & 15;
+    R yr[4][NW], yi[4][NW];
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int w = 0; w < NW; ++w) yr[u][w] = yi[u][w] = R(0);
+    for (int c0 = 0; c0 < N; c0 += kQrChunk) {
+        __syncthreads();
+        // G_k[r][c] = sum_t Wg[r][c][t] e^{2 pi i s <k, y_t>}
+        for (int x = threadIdx.x; x < kQrRows * kQrChunk; x += blockDim.x) {
+            const int rr = x / kQrChunk, cc = x - (x / kQrChunk) * kQrChunk;
+            const int r = r0 + rr, c = c0 + cc;
+            cplx<R> v = {R(0), R(0)};
+            if (r < q.M && c < N) {
+                const R* w = q.W + (q.transposed ? ((size_t)c * q.c_in + r) : ((size_t)r * q.c_in + c)) * T;
+                for (int t = 0; t < T; ++t) {
+                    v.x = fma(w[t], ph[t].x, v.x);
+                    v.y = fma(w[t], ph[t].y, v.y);
+                }
+            }
+            gt[x] = v;
+        }
+        for (int x = threadIdx.x; x < kQrChunk * JW; x += blockDim.x) {
+            const int cc = x / JW, j = j0 + (x - (x / JW) * JW);
+            vt[x] = (c0 + cc < N && j < N) ? VR[(size_t)(c0 + cc) * N + j] : cplx<R>{R(0), R(0)};
+        }
+        __syncthreads();
+#pragma unroll 2
+        for (int cc = 0; cc < kQrChunk; ++cc) {
+            cplx<R> g[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) g[u] = gt[(4 * rg + u) * kQrChunk + cc];
+#pragma unroll
+            for (int w = 0; w < NW; ++w) {
+                const cplx<R> v = vt[cc * JW + cg + 16 * w];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    yr[u][w] = fma(g[u].x, v.x, fma(-g[u].y, v.y, yr[u][w]));
+                    yi[u][w] = fma(g[u].x, v.y, fma(g[u].y, v.x, yi[u][w]));
+                }
+            }
+        }
+    }
+    // columns of singular values the SVD of R set to zero (numerically
+    // negligible) stay exactly zero: the finish then completes them
+    // orthonormally instead of normalising the rounding noise of G V
+    const R* sr = q.sigma + (size_t)theta * N;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        const int r = r0 + 4 * rg + u;
+        if (r >= q.M) continue;
+#pragma unroll
+        for (int w = 0; w < NW; ++w) {
+            const int j = j0 + cg + 16 * w;
+            if (j < N) {
+                const bool keep = sr[j] != R(0);
+                Y[(size_t)j * q.ldg + r] = {keep ? yr[u][w] : R(0), keep ? yi[u][w] : R(0)};
+            }
+        }
+    }
+}
+
+// The blocked kernels' finish on Y and V_R (one work-group per decomposed
+// frequency): sigma, U and V of the symbol into the layer's outputs.
+template <typename R>
+__global__ void __launch_bounds__(256) qr_finish_kernel(SvdArgs<R> a) {
+    extern __shared__ __align__(16) char lds_raw[];
+    const int item = blockIdx.x;
+    const Target tg = target_of(a, item);
+    const Shared<R> s = carve<R>(lds_raw, a.d, true, a.gws + (size_t)item * a.slot_bytes);
+    finish<R, 64>(a, s, tg.out, tg.mirror, 0, true);
+}
+
 }  // namespace
 
 size_t gram_cholesky_lds_bytes(int N, int kh, int kw) {
@@ -219,6 +350,45 @@ hipError_t launch_gram_qr(const GramArgs<R>& g, int items, hipStream_t s) {
     }
     hipLaunchKernelGGL(gram_cholesky_kernel<R>, dim3(items), dim3(256), lds, s, g);
     return hipGetLastError();
+}
+
+template <typename R, int NW>
+hipError_t launch_qr_left_nw(const QrVecArgs<R>& q, int items, hipStream_t s) {
+    constexpr int JW = 16 * NW;
+    const int rtiles = (q.M + kQrRows - 1) / kQrRows, ctiles = (q.N + JW - 1) / JW;
+    const size_t lds = sizeof(cplx<R>) * ((size_t)q.kh * q.kw + kQrRows * kQrChunk + (size_t)kQrChunk * JW);
+    hipLaunchKernelGGL((qr_left_kernel<R, NW>), dim3(items * rtiles * ctiles), dim3(256), lds, s, q);
+    return hipGetLastError();
+}
+
+template <typename R>
+hipError_t launch_qr_vectors(const QrVecArgs<R>& q, const SvdArgs<R>& a, int items, hipStream_t s) {
+    if (items <= 0) return hipSuccess;
+    hipError_t e;
+    if (q.N <= 16) e = launch_qr_left_nw<R, 1>(q, items, s);
+    else if (q.N <= 32) e = launch_qr_left_nw<R, 2>(q, items, s);
+    else if (q.N <= 64) e = launch_qr_left_nw<R, 4>(q, items, s);
+    else if (q.N <= 128) e = launch_qr_left_nw<R, 8>(q, items, s);
+    else e = launch_qr_left_nw<R, 16>(q, items, s);
+    if (e != hipSuccess) return e;
+    // the finish's small arrays (carve): phases, reduction scratch, sigma,
+    // sort permutations, completion coefficients and work vector, flags
+    const size_t lds = sizeof(cplx<R>) * kMaxTaps + sizeof(R) * 64 + (sizeof(R) + 2 * sizeof(int)) * ((q.N + 3) & ~3) +
+                       16 + sizeof(cplx<R>) * ((size_t)q.N + q.M) + sizeof(int) * 4 + 16;
+    if (lds > 65536) {
+        e = hipFuncSetAttribute(reinterpret_cast<const void*>(qr_finish_kernel<R>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(qr_finish_kernel<R>, dim3(items), dim3(256), lds, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_qr_vectors_f32(const QrVecArgs<float>& q, const SvdArgs<float>& a, int items, hipStream_t s) {
+    return launch_qr_vectors<float>(q, a, items, s);
+}
+hipError_t launch_qr_vectors_f64(const QrVecArgs<double>& q, const SvdArgs<double>& a, int items, hipStream_t s) {
+    return launch_qr_vectors<double>(q, a, items, s);
 }
 
 hipError_t launch_gram_qr_f32(const GramArgs<float>& g, int items, hipStream_t s) {

@@ -810,18 +810,50 @@ QR_CASES = [
 
 
 @pytest.mark.parametrize("case", QR_CASES)
+def test_qr_preconditioned_vectors_match_oracle(case, monkeypatch):
+    """Sigma, U and V of tall FP32 layers through QR preconditioning (the
+    SVD of the factors keeps V, the left vectors come from G V): sigma over
+    the whole grid, residual and orthonormality on sampled symbols, and the
+    gauge-free projectors u_j v_j^H of separated singular values against the
+    oracle's."""
+    c_out, c_in, kh, n, m = case
+    banner(f"qr vectors {case}")
+    L, W = workloads.random_layer(c_out, c_in, kh, kh, n, m, seed=52)
+    spec = lfa().LayerSpec(c_out, c_in, kh, kh, n, m)
+    monkeypatch.setenv("LFA_QR", "1")
+    plan = lfa().Plan([spec], want_u=True, want_v=True)
+    assert plan.preconditioned(0)
+    S, U, V, info = plan.svd([_w(W)])
+    torch.cuda.synchronize()
+    assert plan.info_status(info) == 0
+    S_ref = oracle.lfa_svd(W.astype(np.float64), n, m)
+    assert oracle.sigma_error(to_np(S[0]), S_ref) <= 1e-5
+    fr = _sample(n, m, 6, 53)
+    A = oracle.symbols(W.astype(np.float64), n, m, fr)
+    Sg, Ug, Vg = (to_np(x)[fr[:, 0], fr[:, 1]] for x in (S[0], U[0], V[0]))
+    check_vectors(A, Sg, Ug, Vg, torch.float32, f"qr {case}")
+    s_r, u_r, v_r = oracle.svd_symbols(A)
+    check_projectors(s_r, u_r, v_r, Ug, Vg, torch.float32, f"qr {case}")
+
+
+@pytest.mark.parametrize("case", QR_CASES)
 def test_qr_preconditioned_sigma_matches_oracle(case, monkeypatch):
     """Sigma of tall FP32 layers through the Gram-taps Cholesky factors
     (QR preconditioning) against the oracle over the whole grid, and against
-    the same plan without preconditioning (LFA_NO_QR, read at plan
+    the same plan without preconditioning (LFA_QR=0, read at plan
     creation); Parseval over the whole grid."""
     c_out, c_in, kh, n, m = case
     banner(f"qr {case}")
     L, W = workloads.random_layer(c_out, c_in, kh, kh, n, m, seed=51)
     spec = lfa().LayerSpec(c_out, c_in, kh, kh, n, m)
-    S, info = (lambda r: (r[0][0], r[3]))(lfa().Plan([spec]).svd([_w(W)]))
-    monkeypatch.setenv("LFA_NO_QR", "1")
-    S2 = lfa().Plan([spec]).svd([_w(W)])[0][0]
+    monkeypatch.setenv("LFA_QR", "1")
+    plan = lfa().Plan([spec])
+    assert plan.preconditioned(0)
+    S, info = (lambda r: (r[0][0], r[3]))(plan.svd([_w(W)]))
+    monkeypatch.setenv("LFA_QR", "0")
+    plan2 = lfa().Plan([spec])
+    assert not plan2.preconditioned(0)
+    S2 = plan2.svd([_w(W)])[0][0]
     torch.cuda.synchronize()
     assert lfa().Plan([spec]).info_status(info) == 0
     S_ref = oracle.lfa_svd(W.astype(np.float64), n, m)
@@ -833,14 +865,17 @@ def test_qr_preconditioned_sigma_matches_oracle(case, monkeypatch):
     assert abs(ss / (n * m * np.sum(W.astype(np.float64) ** 2)) - 1) <= 1e-5
 
 
-def test_qr_preconditioned_rank_deficient_zeros():
+def test_qr_preconditioned_rank_deficient_zeros(monkeypatch):
     """Rank-one taps (rank <= 9 per symbol) through QR preconditioning: the
     numerically singular pivots give zero rows of R, and the singular values
     beyond the rank come out exactly 0; the others match the oracle."""
     banner("qr rank-one")
     L, W = workloads.rank_one_taps(c_out=192, c_in=96, n=4)
     spec = lfa().LayerSpec(L.c_out, L.c_in, L.kh, L.kw, L.n, L.m)
-    S = lfa().Plan([spec]).svd([_w(W)])[0][0]
+    monkeypatch.setenv("LFA_QR", "1")
+    plan = lfa().Plan([spec])
+    assert plan.preconditioned(0)
+    S = plan.svd([_w(W)])[0][0]
     torch.cuda.synchronize()
     S_ref = oracle.lfa_svd(W.astype(np.float64), L.n, L.m)
     assert oracle.sigma_error(to_np(S), S_ref) <= 1e-5
