@@ -450,11 +450,50 @@ int lfa_crystal_weights(const lfa_layer* layer, int32_t stride, int32_t dtype, c
 
 /* ---- tuning and diagnostics ------------------------------------------- */
 
-/* Time the candidate launch shapes of every layer on `stream` (running the
- * SVD on W into sigma/U/V, which are overwritten) and store the fastest in
- * the plan.  Optional: plans carry a default shape chosen by a cost model. */
+/* What lfa_autotune tunes (OR of these). */
+enum lfa_tune_what {
+    LFA_TUNE_LAYERS = 1u,      /* per layer, for lfa_svd: QR factors or not, matrix-
+                                  core assembly for kernels of 25 taps or more, the
+                                  register kernel's work-queue turns, the blocked
+                                  kernel's work-groups per symbol                 */
+    LFA_TUNE_PERSISTENT = 2u   /* the cost model behind the persistent launch's work
+                                  list (lfa_svd_persistent, the graphs): relative
+                                  cost of register-kernel bundles, team overhead */
+};
+
+/* Choose the plan's launch parameters by timing candidates on the caller's
+ * weights (convergence, and so time, depends on the data), one knob at a
+ * time from the plan's defaults (a cost model), keeping a candidate only if
+ * it is faster, and store the choices in the plan.  Layers of one shape are
+ * tuned once.  Results are identical up to rounding whatever is chosen.
+ *   W, sigma, U, V : as for lfa_svd; sigma/U/V are overwritten
+ *   cache_path     : JSON file of earlier choices, keyed by GPU architecture,
+ *                    dtype, flags and layer shape (and the whole layer list for
+ *                    the persistent cost model), or NULL for no cache.  Found
+ *                    entries are applied without timing; new ones are added
+ *                    and the file rewritten (through a temporary file).
+ *   what           : OR of lfa_tune_what
+ * Synchronous; allocates (and frees) its own device workspace, and uploads a
+ * new persistent work list.  Not concurrently with other calls on the plan,
+ * and not while `stream` captures a graph.  Afterwards
+ * lfa_plan_workspace_bytes may report a different size: query it again.
+ * Errors: LFA_ERR_INVALID_ARG (NULL plan or outputs, unknown `what` bits, a
+ * capturing stream, an unwritable cache file), LFA_ERR_NO_DEVICE,
+ * LFA_ERR_HIP. */
 int lfa_autotune(lfa_plan* plan, const void* const* W, void* const* sigma, void* const* U,
-                 void* const* V, void* ws, size_t ws_bytes, void* stream);
+                 void* const* V, const char* cache_path, uint32_t what, void* stream);
+
+/* The current choices for a layer (autotuned or default): QR factors (0/1),
+ * work-queue sweeps per turn (-1 automatic, 0 off), work-groups per symbol
+ * of the blocked kernel (0 automatic), materialised matrix-core assembly
+ * (-1 as the plan's flags, 0 fused, 1 on).  Any output may be NULL. */
+int lfa_plan_tuning(const lfa_plan* plan, int32_t layer, int32_t* qr, int32_t* queue_seg,
+                    int32_t* team_w, int32_t* asm_mat);
+
+/* The persistent work list's cost model: seconds per unit (N^2 M) of a
+ * register-kernel wave and of a 256-thread blocked work-group, and the
+ * per-member overhead factor of a team of work-groups. */
+int lfa_plan_cost_model(const lfa_plan* plan, double* wave_s, double* block_s, double* team_ovh);
 
 /* Launch shape chosen for a layer: lanes per column pair, threads per
  * work-group, symbols per work-group and storage (0 = LDS, 1 = global). */

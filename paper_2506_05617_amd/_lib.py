@@ -27,6 +27,9 @@ LFA_SPECTRAL_TRUNCATE = 3
 LFA_CRYSTAL_FORWARD = 0
 LFA_CRYSTAL_ADJOINT = 1
 
+LFA_TUNE_LAYERS = 1
+LFA_TUNE_PERSISTENT = 2
+
 LFA_OK = 0
 LFA_ERR_INVALID_ARG = -1
 LFA_ERR_UNSUPPORTED = -2
@@ -81,7 +84,10 @@ SIGNATURES = {
     "lfa_adjoint_onesided": (I32, [P, PP, PP, PP, P, P, I32, PP, P, SZ, P]),
     "lfa_graph_launch": (I32, [P, P]),
     "lfa_graph_destroy": (I32, [P]),
-    "lfa_autotune": (I32, [P, PP, PP, PP, PP, P, SZ, P]),
+    "lfa_autotune": (I32, [P, PP, PP, PP, PP, ctypes.c_char_p, ctypes.c_uint32, P]),
+    "lfa_plan_tuning": (I32, [P, I32, I32P, I32P, I32P, I32P]),
+    "lfa_plan_cost_model": (I32, [P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
+                                  ctypes.POINTER(ctypes.c_double)]),
     "lfa_plan_launch_shape": (I32, [P, I32, I32P, I32P, I32P, I32P]),
     "lfa_apply_workspace_bytes": (I32, [P, I32, I32, ctypes.POINTER(SZ)]),
     "lfa_apply": (I32, [P, I32, P, P, P, I32, ctypes.c_double, P, P, I32, P, SZ, P]),

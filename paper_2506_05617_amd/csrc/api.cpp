@@ -70,6 +70,14 @@ double jacobi_tol(double unit_roundoff, int M) {
 
 }  // namespace
 
+// Per-layer choices of lfa_autotune for lfa_svd (defaults: the cost
+// model's automatic choices).
+struct LayerTune {
+    int queue_seg = -1;    // register kernel's work queue: -1 automatic, 0 off, k sweeps per turn
+    int team_w = 0;        // blocked kernel: work-groups per symbol, 0 automatic
+    int asm_mat = -1;      // -1 the plan's flags, 0 fused assembly, 1 materialised FP32 matrix-core assembly
+};
+
 struct lfa_plan {
     int dtype = LFA_F32;
     uint32_t flags = 0;
@@ -88,6 +96,7 @@ struct lfa_plan {
     int device = -1;
     double* tw_dev = nullptr;
     WorkItem* items_dev = nullptr;
+    std::vector<WorkItem*> old_items;     // earlier uploads (see upload_items)
     int num_cus = 0;
     // persistent launch: slots of the blocked layers, team counters, schedule
     std::vector<size_t> pers_slot_off;    // byte offset of each layer's slots (blocked layers)
@@ -95,6 +104,11 @@ struct lfa_plan {
     int pers_teams = 0;                   // team instances (one per blocked-layer symbol)
     int pers_wave_slots = 4;
     bool pers_acc = false;                // some layer keeps the rotation accumulator
+    // cost model of the persistent work list (lfa_autotune may change it):
+    // seconds per unit N^2 M of a register-kernel wave and of a 256-thread
+    // blocked work-group, and the per-member overhead of a team
+    double cost_wave = 7.5e-9, cost_block = 2.5e-9, team_ovh = 0.08;
+    std::vector<LayerTune> tune;
     std::vector<size_t> pers_lds;         // per chunk
     std::vector<int> pers_grid;           // per chunk
     // persistent SVD-with-vectors of the selected symbols, per k
@@ -257,6 +271,13 @@ int asm_mode(uint32_t flags) {
     return 0;
 }
 
+// Materialised (matrix-core) assembly for layer i: the autotuner's choice,
+// else the plan's flags.
+bool layer_materialized(const lfa_plan& p, size_t i) {
+    const int t = p.tune[i].asm_mat;
+    return t >= 0 ? t == 1 : asm_materialized(p.flags);
+}
+
 size_t pers_counter_bytes(const lfa_plan& p) {
     return align_up(sizeof(int32_t) * (4 * (size_t)p.pers_teams + 4));
 }
@@ -283,11 +304,15 @@ size_t sel_bytes(const lfa_layer& l, int eb) {
 // (N <= 64), or at least a device's worth of symbols (one per CU of
 // MI355X); lfa_autotune times both where it matters.
 constexpr int kQrMinSymbols = 256;
-bool qr_applies(const lfa_layer& l, int dtype, uint32_t flags) {
+bool qr_eligible(const lfa_layer& l, int dtype, uint32_t flags) {
     const int M = std::max(l.c_out, l.c_in), N = std::min(l.c_out, l.c_in);
     if (dtype != LFA_F32) return false;
     if (flags & (LFA_ASM_MFMA | LFA_ASM_BF16X2 | LFA_ASM_BF16X3)) return false;
-    if (!(M > 64 && 4 * M >= 5 * N)) return false;
+    return M > 64 && 4 * M >= 5 * N;
+}
+bool qr_applies(const lfa_layer& l, int dtype, uint32_t flags) {
+    const int N = std::min(l.c_out, l.c_in);
+    if (!qr_eligible(l, dtype, flags)) return false;
     // LFA_QR: "0" off, "1" on for every such layer (tests, tuning)
     if (const char* env = std::getenv("LFA_QR")) {
         if (std::strcmp(env, "0") == 0) return false;
@@ -340,6 +365,24 @@ size_t pick_vector_bytes(const lfa_plan& p, int k) {
     return b;
 }
 
+// Region bytes of lfa_svd for layer i with the given choices (QR factors,
+// materialised assembly, the register kernel's work queue); lds_fallback
+// also reserves global slots for a layer whose LDS need exceeds the
+// always-available 64 KiB (a device with less LDS than the plan assumed).
+size_t svd_layer_need(const lfa_plan& p, size_t i, bool qr, bool mat, bool queue, bool lds_fallback) {
+    const int eb = elem_bytes(p.dtype);
+    const bool wu = p.flags & LFA_WANT_U, wv = p.flags & LFA_WANT_V;
+    const LayerDesc& d = p.desc[i];
+    const bool acc = accumulates(d, wu, wv);
+    LayerDesc dg = d;
+    if (lds_fallback) dg.storage = (lds_bytes_for(d, acc, eb) > kLdsSafe) ? kGlobal : d.storage;
+    const size_t sym = mat ? symbols_bytes(p.layers[i], eb) : 0;
+    size_t s = sym + (size_t)svd_grid(dg, d.num_symbols) * slot_bytes(dg, acc, eb);
+    if (queue && d.wave_qgroups > 0) s = std::max(s, sym + wave_queue_bytes(d, acc, eb, d.wave_qgroups));
+    if (qr && !mat) s = std::max(s, qr_region_bytes(p, (int)i, queue));
+    return s;
+}
+
 // Workspace layout (offsets from ws):
 //   [0, 256)                   persistent dequeue counter
 //   [256, 256 + big)           per-entry-point region (regions of different
@@ -348,21 +391,14 @@ size_t workspace_bytes(const lfa_plan& p) {
     const int eb = elem_bytes(p.dtype);
     const bool wu = p.flags & LFA_WANT_U, wv = p.flags & LFA_WANT_V;
     size_t need = 0;
+    (void)wu;
+    (void)wv;
     for (size_t i = 0; i < p.layers.size(); ++i) {
-        const LayerDesc& d = p.desc[i];
-        const bool acc = accumulates(d, wu, wv);
-        // lfa_svd / lfa_svd_symbols: symbols (materialised assembly) + slots.
-        // A layer whose LDS need exceeds the always-available 64 KiB may fall
-        // back to global slots on a device with less LDS: reserve for that too.
-        LayerDesc dg = d;
-        dg.storage = (lds_bytes_for(d, acc, eb) > kLdsSafe) ? kGlobal : d.storage;
-        size_t s = (size_t)svd_grid(dg, d.num_symbols) * slot_bytes(dg, acc, eb);
-        const size_t sym = asm_materialized(p.flags) ? symbols_bytes(p.layers[i], eb) : 0;
-        s += sym;
-        // register kernel: work-queue control, entries, meta and saved state
-        if (d.wave_qgroups > 0) s = std::max(s, sym + wave_queue_bytes(d, acc, eb, d.wave_qgroups));
-        need = std::max(need, s);
-        if (p.qr[i]) need = std::max(need, qr_region_bytes(p, (int)i, true));
+        // lfa_svd / lfa_svd_symbols: symbols (materialised assembly) + slots,
+        // the work queue, or the QR factors' region.  A layer whose LDS need
+        // exceeds the always-available 64 KiB may fall back to global slots
+        // on a device with less LDS: reserve for that too.
+        need = std::max(need, svd_layer_need(p, i, p.qr[i] != 0, layer_materialized(p, i), true, true));
         // lfa_sigma_grad: compact outputs of <= kMaxTopk symbols + slots
         const LayerDesc& ds = p.desc_sel[i];
         LayerDesc dsg = ds;
@@ -442,10 +478,10 @@ void build_schedule(lfa_plan* p) {
             const double u = double(d.N) * d.N * d.M * (accumulates(d, wu, wv) ? 1.5 : 1.0);
             if (d.kind == 1) {
                 const int spw = 64 / d.wave_ml, per = spw * p->pers_wave_slots;
-                const double dur = 7.5e-9 * u * spw;
+                const double dur = p->cost_wave * u * spw;
                 for (int it = 0; it < d.num_canon; it += per) total += dur;
             } else {
-                sym_cost[i - l0] = 2.5e-9 * u;
+                sym_cost[i - l0] = p->cost_block * u;
                 total += sym_cost[i - l0] * d.num_canon;
             }
         }
@@ -457,14 +493,14 @@ void build_schedule(lfa_plan* p) {
                 const int spw = 64 / d.wave_ml, per = spw * p->pers_wave_slots;
                 const double u = double(d.N) * d.N * d.M;
                 for (int it = 0; it < d.num_canon; it += per)
-                    units.push_back({7.5e-9 * u * spw, i - l0, 0, it, 1});
+                    units.push_back({p->cost_wave * u * spw, i - l0, 0, it, 1});
             } else {
                 const int NB = (d.N + kBlockCols - 1) / kBlockCols, NBP = NB + (NB & 1);
                 const double c = sym_cost[i - l0];
                 int W = 1;
-                while (W < NBP / 2 && W < grid && c * (1 + 0.08 * W) / W > avg) ++W;
+                while (W < NBP / 2 && W < grid && c * (1 + p->team_ovh * W) / W > avg) ++W;
                 for (int it = 0; it < d.num_canon; ++it)
-                    units.push_back({c * (1 + 0.08 * W) / W, i - l0, 1, it, W});
+                    units.push_back({c * (1 + p->team_ovh * W) / W, i - l0, 1, it, W});
             }
         }
         std::stable_sort(units.begin(), units.end(),
@@ -480,6 +516,21 @@ void build_schedule(lfa_plan* p) {
         }
     }
     p->chunk_first.push_back((int)p->items.size());
+}
+
+// The persistent work list to the device.  An earlier list stays allocated
+// until the plan is destroyed: graphs captured before it was replaced (by
+// lfa_autotune) still point at it.
+int upload_items(lfa_plan* p) {
+    if (p->items_dev) {
+        p->old_items.push_back(p->items_dev);
+        p->items_dev = nullptr;
+    }
+    HIP_TRY(hipMalloc(&p->items_dev, std::max<size_t>(1, p->items.size()) * sizeof(WorkItem)));
+    if (!p->items.empty())
+        HIP_TRY(hipMemcpy(p->items_dev, p->items.data(), p->items.size() * sizeof(WorkItem),
+                          hipMemcpyHostToDevice));
+    return LFA_OK;
 }
 
 // A stream that is capturing a graph: uploads (hipMalloc, synchronous
@@ -540,10 +591,7 @@ int ensure_device(lfa_plan* p, hipStream_t st = nullptr, bool check_capture = fa
             p->desc_pers[i].storage = kGlobal;
     }
     build_schedule(p);
-    HIP_TRY(hipMalloc(&p->items_dev, std::max<size_t>(1, p->items.size()) * sizeof(WorkItem)));
-    if (!p->items.empty())
-        HIP_TRY(hipMemcpy(p->items_dev, p->items.data(), p->items.size() * sizeof(WorkItem),
-                          hipMemcpyHostToDevice));
+    LFA_TRY(upload_items(p));
     p->device = dev;
     return LFA_OK;
 }
@@ -552,7 +600,8 @@ template <typename R>
 int run_svd_layer(const lfa_plan* p, const LayerDesc& d, const void* W, const void* A,
                   void* sigma, void* U, void* V, int32_t* info, char* region,
                   const int32_t* theta_list, int theta_stride, int theta_count,
-                  hipStream_t st, bool canon = false, bool queue_ok = true) {
+                  hipStream_t st, bool canon = false, bool queue_ok = true,
+                  const LayerTune* tn = nullptr) {
     SvdArgs<R> a{};
     a.d = d;
     a.canon = theta_list ? 0 : (canon ? 1 : 0);
@@ -576,7 +625,8 @@ int run_svd_layer(const lfa_plan* p, const LayerDesc& d, const void* W, const vo
     if (d.kind == 1) {
         if (acc != (d.threads > 64)) return LFA_ERR_INVALID_ARG;   // shape made for other outputs
         const int groups = wave_groups(d, count);
-        const int seg = queue_ok ? wave_queue_seg(d, groups, p->wq_force) : 0;
+        const int force = (tn && tn->queue_seg >= 0) ? tn->queue_seg : p->wq_force;
+        const int seg = queue_ok ? wave_queue_seg(d, groups, force) : 0;
         if (seg > 0) {
             // work queue in the region: control words and entries, meta, state
             const long long ents = wave_queue_entries(groups, seg);
@@ -624,7 +674,13 @@ int run_svd_layer(const lfa_plan* p, const LayerDesc& d, const void* W, const vo
         const int NB = (d.N + kBlockCols - 1) / kBlockCols, NBP = NB + (NB & 1);
         int W = 1, teams = std::min(count, kGlobalGrid);
         const int cap = std::min(resident, p->num_cus);
-        if (cap >= 2 && 2 * count <= cap) {
+        const bool forced = tn && tn->team_w > 0;
+        if (forced) {
+            // the autotuner's width: teams of W only as many as can be
+            // resident at once (every member of a team must be)
+            W = std::max(1, std::min({tn->team_w, NBP / 2, resident}));
+            teams = W > 1 ? std::max(1, std::min(count, resident / W)) : teams;
+        } else if (cap >= 2 && 2 * count <= cap) {
             W = std::max(1, std::min(NBP / 2, cap / count));
             teams = W > 1 ? std::min(count, cap / W) : teams;
         } else if (count < cap && 2 * count <= resident && NBP >= 4) {
@@ -642,7 +698,7 @@ int run_svd_layer(const lfa_plan* p, const LayerDesc& d, const void* W, const vo
         int split = count;
         int W2 = 1, teams2 = 0;
         const int rem = resident > 0 ? count % resident : 0;
-        if (W == 1 && cap >= 2 && count > resident && rem > 0 && 2 * rem <= cap) {
+        if (!forced && W == 1 && cap >= 2 && count > resident && rem > 0 && 2 * rem <= cap) {
             W2 = std::max(1, std::min(NBP / 2, cap / rem));
             if (W2 > 1) {
                 split = count - rem;
@@ -668,18 +724,9 @@ int run_svd_layer(const lfa_plan* p, const LayerDesc& d, const void* W, const vo
 // Workspace bytes lfa_svd itself uses on the plan's device (desc as
 // adjusted at upload), with or without the register kernel's work queue.
 size_t svd_need(const lfa_plan& p, bool queue) {
-    const int eb = elem_bytes(p.dtype);
-    const bool wu = p.flags & LFA_WANT_U, wv = p.flags & LFA_WANT_V;
     size_t need = 0;
-    for (size_t i = 0; i < p.layers.size(); ++i) {
-        const LayerDesc& d = p.desc[i];
-        const bool acc = accumulates(d, wu, wv);
-        const size_t sym = asm_materialized(p.flags) ? symbols_bytes(p.layers[i], eb) : 0;
-        size_t s = sym + (size_t)svd_grid(d, d.num_symbols) * slot_bytes(d, acc, eb);
-        if (queue && d.wave_qgroups > 0) s = std::max(s, sym + wave_queue_bytes(d, acc, eb, d.wave_qgroups));
-        if (p.qr[i]) s = qr_region_bytes(p, (int)i, queue);
-        need = std::max(need, s);
-    }
+    for (size_t i = 0; i < p.layers.size(); ++i)
+        need = std::max(need, svd_layer_need(p, i, p.qr[i] != 0, layer_materialized(p, i), queue, false));
     return kAlign + kCounterBytes + align_up(need);
 }
 
@@ -689,30 +736,31 @@ int check_ws(const lfa_plan* p, void* ws, size_t ws_bytes) {
     return LFA_OK;
 }
 
+// One layer of lfa_svd (the caller clears the info words).  `region` is the
+// workspace after its first kAlign bytes.
 template <typename R>
-int svd_impl(const lfa_plan* p, const void* const* W, const void* const* A, void* const* sigma,
-             void* const* U, void* const* V, int32_t* info, void* ws, size_t ws_bytes,
-             hipStream_t st, bool queue_ok = true) {
+int svd_layer(const lfa_plan* p, size_t i, const void* const* W, const void* const* A, void* const* sigma,
+              void* const* U, void* const* V, int32_t* info, char* region, hipStream_t st, bool queue_ok) {
     const bool wu = p->flags & LFA_WANT_U, wv = p->flags & LFA_WANT_V;
-    char* region = static_cast<char*>(ws) + kAlign;
-    if (info) HIP_TRY(launch_fill_i32(info, 0, (long long)p->layers.size() * LFA_INFO_WORDS, st));
-    for (size_t i = 0; i < p->layers.size(); ++i) {
+    const LayerTune* tn = &p->tune[i];
+    {
         const LayerDesc& d = p->desc[i];
         const void* Wi = nullptr;
         const void* Ai = A ? A[i] : nullptr;
         char* slots = region;
+        const bool mat = layer_materialized(*p, i);
         if (!A) {
-            if (asm_materialized(p->flags)) {
+            if (mat) {
                 cplx<float>* sym = reinterpret_cast<cplx<float>*>(region);
                 HIP_TRY(launch_symbols_mfma(d, static_cast<const float*>(W[i]), sym, p->tw_dev,
-                                            asm_mode(p->flags), st));
+                                            asm_materialized(p->flags) ? asm_mode(p->flags) : 0, st));
                 Ai = sym;
                 slots = region + symbols_bytes(p->layers[i], sizeof(R));
             } else {
                 Wi = W[i];
             }
         }
-        if (!A && p->qr[i]) {
+        if (!A && !mat && p->qr[i]) {
             // QR preconditioning: the Cholesky factors R of the Gram
             // matrices, then the SVD of the N x N factors (one per conjugate
             // pair; the mirror's factor is the conjugate)
@@ -748,7 +796,7 @@ int svd_impl(const lfa_plan* p, const void* const* W, const void* const* A, void
             LFA_TRY(run_svd_layer<R>(p, p->desc_r[i], nullptr, rsym, sigma[i], nullptr,
                                      vec ? reinterpret_cast<cplx<R>*>(rsym) : nullptr,
                                      info ? info + i * LFA_INFO_WORDS : nullptr, rest, nullptr, 0, 0, st,
-                                     true, queue_ok));
+                                     true, queue_ok, tn));
             if (vec) {
                 QrVecArgs<R> q{};
                 q.W = static_cast<const R*>(W[i]);
@@ -784,7 +832,7 @@ int svd_impl(const lfa_plan* p, const void* const* W, const void* const* A, void
                 else e = launch_qr_vectors_f64(q, a, d.num_canon, st);
                 HIP_TRY(e);
             }
-            continue;
+            return LFA_OK;
         }
         // weights are real: decompose one symbol per conjugate pair.  Symbols
         // handed in by the caller carry no such guarantee.
@@ -792,8 +840,20 @@ int svd_impl(const lfa_plan* p, const void* const* W, const void* const* A, void
         LFA_TRY(run_svd_layer<R>(p, d, Wi, Ai, sigma[i], wu ? U[i] : nullptr,
                                  wv ? V[i] : nullptr,
                                  info ? info + i * LFA_INFO_WORDS : nullptr, slots, nullptr, 0, 0,
-                                 st, canon, queue_ok));
+                                 st, canon, queue_ok, tn));
     }
+    return LFA_OK;
+}
+
+template <typename R>
+int svd_impl(const lfa_plan* p, const void* const* W, const void* const* A, void* const* sigma,
+             void* const* U, void* const* V, int32_t* info, void* ws, size_t ws_bytes,
+             hipStream_t st, bool queue_ok = true) {
+    (void)ws_bytes;
+    char* region = static_cast<char*>(ws) + kAlign;
+    if (info) HIP_TRY(launch_fill_i32(info, 0, (long long)p->layers.size() * LFA_INFO_WORDS, st));
+    for (size_t i = 0; i < p->layers.size(); ++i)
+        LFA_TRY(svd_layer<R>(p, i, W, A, sigma, U, V, info, region, st, queue_ok));
     return LFA_OK;
 }
 
@@ -990,7 +1050,7 @@ int ensure_grad_schedule(lfa_plan* p, int k, hipStream_t st, bool check_capture,
         double total = 0;
         for (int i = l0; i < l1; ++i) {
             const LayerDesc& d = p->desc_gsel[i];
-            total += 2.5e-9 * 1.5 * double(d.N) * d.N * d.M * k;
+            total += p->cost_block * 1.5 * double(d.N) * d.N * d.M * k;
         }
         const double avg = total / grid;
         struct Unit {
@@ -1001,10 +1061,10 @@ int ensure_grad_schedule(lfa_plan* p, int k, hipStream_t st, bool check_capture,
         for (int i = l0; i < l1; ++i) {
             const LayerDesc& d = p->desc_gsel[i];
             const int NB = (d.N + kBlockCols - 1) / kBlockCols, NBP = NB + (NB & 1);
-            const double c = 2.5e-9 * 1.5 * double(d.N) * d.N * d.M;
+            const double c = p->cost_block * 1.5 * double(d.N) * d.N * d.M;
             int W = 1;
-            while (W < NBP / 2 && W < grid && c * (1 + 0.08 * W) / W > avg) ++W;
-            for (int s = 0; s < k; ++s) units.push_back({c * (1 + 0.08 * W) / W, i - l0, s, W});
+            while (W < NBP / 2 && W < grid && c * (1 + p->team_ovh * W) / W > avg) ++W;
+            for (int s = 0; s < k; ++s) units.push_back({c * (1 + p->team_ovh * W) / W, i - l0, s, W});
         }
         std::stable_sort(units.begin(), units.end(),
                          [](const Unit& x, const Unit& y) { return x.dur > y.dur; });
@@ -1169,6 +1229,358 @@ int check_k(const lfa_plan* p, int k) {
 }  // namespace
 
 // ---------------------------------------------------------------------------
+// Autotuner: choices timed on the caller's data, kept in a JSON cache
+// ---------------------------------------------------------------------------
+namespace {
+
+// The cache: {"lfa_autotune": 1, "entries": {key: {field: number, ...}, ...}}.
+using CacheEntries = std::map<std::string, std::map<std::string, double>>;
+
+struct JsonIn {
+    const std::string& t;
+    size_t i = 0;
+    explicit JsonIn(const std::string& text) : t(text) {}
+    void ws() {
+        while (i < t.size() && (t[i] == ' ' || t[i] == '\n' || t[i] == '\r' || t[i] == '\t')) ++i;
+    }
+    bool eat(char c) {
+        ws();
+        if (i < t.size() && t[i] == c) {
+            ++i;
+            return true;
+        }
+        return false;
+    }
+    bool str(std::string& out) {
+        ws();
+        if (i >= t.size() || t[i] != '"') return false;
+        ++i;
+        out.clear();
+        while (i < t.size() && t[i] != '"') {
+            if (t[i] == '\\' && i + 1 < t.size()) ++i;     // keys here carry no escapes but '\\' and '"'
+            out.push_back(t[i++]);
+        }
+        return i < t.size() && t[i++] == '"';
+    }
+    bool num(double& v) {
+        ws();
+        const char* b = t.c_str() + i;
+        char* e = nullptr;
+        v = std::strtod(b, &e);
+        if (e == b) return false;
+        i += (size_t)(e - b);
+        return true;
+    }
+    bool skip() {          // any value
+        ws();
+        if (i >= t.size()) return false;
+        std::string tmp;
+        double d;
+        if (t[i] == '"') return str(tmp);
+        if (t[i] == '{' || t[i] == '[') {
+            const char close = t[i] == '{' ? '}' : ']';
+            const bool obj = t[i] == '{';
+            ++i;
+            if (eat(close)) return true;
+            do {
+                if (obj && !(str(tmp) && eat(':'))) return false;
+                if (!skip()) return false;
+            } while (eat(','));
+            return eat(close);
+        }
+        for (const char* lit : {"true", "false", "null"})
+            if (t.compare(i, std::strlen(lit), lit) == 0) {
+                i += std::strlen(lit);
+                return true;
+            }
+        return num(d);
+    }
+};
+
+// Entries of a cache file; an absent or unreadable file gives none.
+CacheEntries read_cache(const char* path) {
+    CacheEntries out;
+    if (!path || !*path) return out;
+    FILE* f = std::fopen(path, "rb");
+    if (!f) return out;
+    std::string text;
+    char buf[4096];
+    size_t n;
+    while ((n = std::fread(buf, 1, sizeof buf, f)) > 0) text.append(buf, n);
+    std::fclose(f);
+    JsonIn in(text);
+    std::string key;
+    if (!in.eat('{')) return CacheEntries{};
+    if (in.eat('}')) return out;
+    do {
+        if (!(in.str(key) && in.eat(':'))) return CacheEntries{};
+        if (key != "entries") {
+            if (!in.skip()) return CacheEntries{};
+            continue;
+        }
+        if (!in.eat('{')) return CacheEntries{};
+        if (in.eat('}')) continue;
+        do {
+            std::string ek, fk;
+            if (!(in.str(ek) && in.eat(':') && in.eat('{'))) return CacheEntries{};
+            std::map<std::string, double> fields;
+            if (!in.eat('}')) {
+                do {
+                    double v;
+                    if (!(in.str(fk) && in.eat(':') && in.num(v))) return CacheEntries{};
+                    fields[fk] = v;
+                } while (in.eat(','));
+                if (!in.eat('}')) return CacheEntries{};
+            }
+            out[ek] = fields;
+        } while (in.eat(','));
+        if (!in.eat('}')) return CacheEntries{};
+    } while (in.eat(','));
+    return out;
+}
+
+int write_cache(const char* path, const CacheEntries& entries) {
+    if (!path || !*path) return LFA_OK;
+    const std::string tmp = std::string(path) + ".tmp";
+    FILE* f = std::fopen(tmp.c_str(), "wb");
+    if (!f) return LFA_ERR_INVALID_ARG;
+    std::fprintf(f, "{\n \"lfa_autotune\": 1,\n \"entries\": {");
+    bool first = true;
+    for (const auto& kv : entries) {
+        std::fprintf(f, "%s\n  \"%s\": {", first ? "" : ",", kv.first.c_str());
+        bool ff = true;
+        for (const auto& fv : kv.second) {
+            std::fprintf(f, "%s\"%s\": %.9g", ff ? "" : ", ", fv.first.c_str(), fv.second);
+            ff = false;
+        }
+        std::fprintf(f, "}");
+        first = false;
+    }
+    std::fprintf(f, "\n }\n}\n");
+    const bool ok = std::fclose(f) == 0;
+    if (!ok || std::rename(tmp.c_str(), path) != 0) {
+        std::remove(tmp.c_str());
+        return LFA_ERR_INVALID_ARG;
+    }
+    return LFA_OK;
+}
+
+std::string arch_name(int dev) {
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return "unknown";
+    std::string a = prop.gcnArchName;
+    const size_t c = a.find(':');
+    return c == std::string::npos ? a : a.substr(0, c);
+}
+
+std::string plan_prefix(const lfa_plan* p, int dev) {
+    char buf[96];
+    std::snprintf(buf, sizeof buf, "%s/%s/flags%u", arch_name(dev).c_str(), p->dtype == LFA_F64 ? "f64" : "f32",
+                  (unsigned)p->flags);
+    return buf;
+}
+
+std::string layer_key(const lfa_layer& l) {
+    char buf[96];
+    std::snprintf(buf, sizeof buf, "%dx%dx%dx%d@%dx%d", l.c_out, l.c_in, l.kh, l.kw, l.n, l.m);
+    return buf;
+}
+
+// Minimum over `reps` of the event time of fn() on st, after one warm-up.
+template <typename F>
+int time_min(F&& fn, hipStream_t st, int reps, float& best_ms) {
+    hipEvent_t e0, e1;
+    HIP_TRY(hipEventCreate(&e0));
+    HIP_TRY(hipEventCreate(&e1));
+    int status = fn();
+    best_ms = 1e30f;
+    for (int r = 0; r < reps && status == LFA_OK; ++r) {
+        if (hipEventRecord(e0, st) != hipSuccess) status = LFA_ERR_HIP;
+        if (status == LFA_OK) status = fn();
+        if (status == LFA_OK && (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess))
+            status = LFA_ERR_HIP;
+        float ms = 0;
+        if (status == LFA_OK && hipEventElapsedTime(&ms, e0, e1) == hipSuccess) best_ms = std::min(best_ms, ms);
+    }
+    if (status == LFA_OK && hipStreamSynchronize(st) != hipSuccess) status = LFA_ERR_HIP;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return status;
+}
+
+template <typename R>
+int autotune_impl(lfa_plan* p, const void* const* W, void* const* sigma, void* const* U, void* const* V,
+                  const char* cache_path, uint32_t what, hipStream_t st) {
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    CacheEntries cache = read_cache(cache_path);
+    const std::string prefix = plan_prefix(p, dev);
+    const int eb = elem_bytes(p->dtype);
+    const bool wu = p->flags & LFA_WANT_U, wv = p->flags & LFA_WANT_V;
+    const int nl = (int)p->layers.size();
+    // a workspace of its own, large enough for every candidate
+    size_t need = workspace_bytes(*p);
+    for (int i = 0; i < nl; ++i) {
+        const lfa_layer& l = p->layers[i];
+        const bool qe = qr_eligible(l, p->dtype, p->flags);
+        const bool me = p->dtype == LFA_F32 && l.kh * l.kw >= 25;
+        need = std::max(need, kAlign + kCounterBytes +
+                                  align_up(std::max({svd_layer_need(*p, i, qe, false, true, true),
+                                                     svd_layer_need(*p, i, false, me, true, true)})));
+    }
+    char* ws = nullptr;
+    HIP_TRY(hipMalloc(&ws, need));
+    char* region = ws + kAlign;
+    int status = LFA_OK;
+    std::lock_guard<std::mutex> lock(p->mu);
+    bool changed = false;
+
+    if (what & LFA_TUNE_LAYERS) {
+        std::map<std::string, int> done;     // shape key -> first layer tuned with it
+        for (int i = 0; i < nl && status == LFA_OK; ++i) {
+            const lfa_layer& l = p->layers[i];
+            const std::string key = prefix + "/layer/" + layer_key(l);
+            auto apply = [&](int qr, const LayerTune& t) {
+                p->qr[i] = qr;
+                p->tune[i] = t;
+            };
+            auto dn = done.find(key);
+            if (dn != done.end()) {
+                apply(p->qr[dn->second], p->tune[dn->second]);
+                continue;
+            }
+            done[key] = i;
+            auto hit = cache.find(key);
+            if (hit != cache.end()) {
+                auto& f = hit->second;
+                LayerTune t;
+                t.queue_seg = f.count("queue_seg") ? (int)f["queue_seg"] : -1;
+                t.team_w = f.count("team_w") ? (int)f["team_w"] : 0;
+                t.asm_mat = f.count("asm") ? (int)f["asm"] : -1;
+                const int qr = f.count("qr") && qr_eligible(l, p->dtype, p->flags) ? (int)f["qr"] : p->qr[i];
+                if (t.asm_mat == 1 && !(p->dtype == LFA_F32)) t.asm_mat = -1;
+                apply(t.asm_mat == 1 ? 0 : qr, t);
+                continue;
+            }
+            auto run = [&]() -> int {
+                return svd_layer<R>(p, (size_t)i, W, nullptr, sigma, U, V, nullptr, region, st, true);
+            };
+            float best = 0;
+            status = time_min(run, st, 2, best);
+            int best_qr = p->qr[i];
+            LayerTune bt = p->tune[i];
+            auto trial = [&](int qr, const LayerTune& t) {
+                if (status != LFA_OK) return;
+                const int oq = p->qr[i];
+                const LayerTune ot = p->tune[i];
+                apply(qr, t);
+                float ms = 0;
+                status = time_min(run, st, 2, ms);
+                if (status == LFA_OK && ms < best) {
+                    best = ms;
+                    best_qr = qr;
+                    bt = t;
+                } else {
+                    apply(oq, ot);
+                }
+            };
+            // QR factors or not, then matrix-core assembly for many taps
+            if (qr_eligible(l, p->dtype, p->flags)) trial(1 - p->qr[i], p->tune[i]);
+            if (p->dtype == LFA_F32 && l.kh * l.kw >= 25 && !asm_materialized(p->flags) && best_qr == 0) {
+                LayerTune t = bt;
+                t.asm_mat = 1;
+                trial(0, t);
+            }
+            apply(best_qr, bt);
+            // the launch of the path in use: work-queue turns of the register
+            // kernel, or team widths of the blocked kernel
+            const LayerDesc& d = (p->qr[i] && p->tune[i].asm_mat != 1) ? p->desc_r[i] : p->desc[i];
+            if (d.kind == 1 && d.wave_qgroups > 0) {
+                for (int seg : {0, 3, 4, 5, 6, 8}) {
+                    LayerTune t = bt;
+                    t.queue_seg = seg;
+                    trial(best_qr, t);
+                }
+            } else if (d.kind == 2) {
+                const int NB = (d.N + kBlockCols - 1) / kBlockCols, NBP = NB + (NB & 1);
+                for (int w : {1, 2, 4, 8, 16}) {
+                    if (w > NBP / 2) break;
+                    LayerTune t = bt;
+                    t.team_w = w;
+                    trial(best_qr, t);
+                }
+            }
+            apply(best_qr, bt);
+            auto& f = cache[key];
+            f["qr"] = best_qr;
+            f["queue_seg"] = bt.queue_seg;
+            f["team_w"] = bt.team_w;
+            f["asm"] = bt.asm_mat;
+            f["ms"] = best;
+            changed = true;
+        }
+    }
+
+    if (status == LFA_OK && (what & LFA_TUNE_PERSISTENT) && !asm_materialized(p->flags)) {
+        std::string key = prefix + "/persistent";
+        for (const lfa_layer& l : p->layers) key += "/" + layer_key(l);
+        auto hit = cache.find(key);
+        if (hit != cache.end() && hit->second.count("wave_s") && hit->second.count("team_ovh")) {
+            p->cost_wave = hit->second["wave_s"];
+            p->team_ovh = hit->second["team_ovh"];
+            build_schedule(p);
+            status = upload_items(p);
+        } else {
+            auto run = [&]() -> int {
+                if (p->dtype == LFA_F64) return persistent_impl<double>(p, W, sigma, U, V, nullptr, ws, st);
+                return persistent_impl<float>(p, W, sigma, U, V, nullptr, ws, st);
+            };
+            const double w0 = p->cost_wave, o0 = p->team_ovh;
+            double bw = w0, bo = o0;
+            float best = 0;
+            status = time_min(run, st, 2, best);
+            for (double fw : {0.5, 1.0, 2.0}) {
+                for (double ov : {0.02, 0.08, 0.25}) {
+                    if (status != LFA_OK) break;
+                    if (fw == 1.0 && ov == o0) continue;
+                    p->cost_wave = w0 * fw;
+                    p->team_ovh = ov;
+                    build_schedule(p);
+                    status = upload_items(p);
+                    float ms = 0;
+                    if (status == LFA_OK) status = time_min(run, st, 2, ms);
+                    if (status == LFA_OK && ms < best) {
+                        best = ms;
+                        bw = p->cost_wave;
+                        bo = ov;
+                    }
+                }
+            }
+            p->cost_wave = bw;
+            p->team_ovh = bo;
+            build_schedule(p);
+            if (status == LFA_OK) status = upload_items(p);
+            if (status == LFA_OK) {
+                auto& f = cache[key];
+                f["wave_s"] = bw;
+                f["block_s"] = p->cost_block;
+                f["team_ovh"] = bo;
+                f["ms"] = best;
+                changed = true;
+            }
+        }
+    }
+    (void)hipFree(ws);
+    if (status == LFA_OK && changed) status = write_cache(cache_path, cache);
+    (void)eb;
+    (void)wu;
+    (void)wv;
+    return status;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
 // extern "C"
 // ---------------------------------------------------------------------------
 extern "C" {
@@ -1211,6 +1623,7 @@ int lfa_plan_create(lfa_plan** out, const lfa_layer* layers, int32_t num_layers,
     p->dtype = dtype;
     p->flags = flags;
     p->layers.assign(layers, layers + num_layers);
+    p->tune.assign(num_layers, LayerTune{});
     const int eb = elem_bytes(dtype);
     // unit roundoff of the working precision (see jacobi_tol)
     p->tol = dtype == LFA_F64 ? std::ldexp(1.0, -53) : std::ldexp(1.0, -24);
@@ -1281,7 +1694,7 @@ int lfa_plan_create(lfa_plan** out, const lfa_layer* layers, int32_t num_layers,
             const bool vec = wu || wv;       // the SVD of R keeps V_R
             LayerDesc dr = make_desc(lr, off[l.n], off[l.m], vec, eb, kLdsCap);
             dr.num_canon = ncanon;
-            dr.wave_qgroups = q ? wave_queue_reserved(dr, vec, eb) : 0;
+            dr.wave_qgroups = qr_eligible(l, dtype, flags) ? wave_queue_reserved(dr, vec, eb) : 0;
             p->desc_r.push_back(dr);
         }
         p->desc_sel.back().num_canon = ncanon;
@@ -1310,6 +1723,7 @@ int lfa_plan_destroy(lfa_plan* plan) {
     if (!plan) return LFA_OK;
     if (plan->tw_dev) (void)hipFree(plan->tw_dev);
     if (plan->items_dev) (void)hipFree(plan->items_dev);
+    for (WorkItem* w : plan->old_items) (void)hipFree(w);
     for (auto& kv : plan->grad_sched)
         if (kv.second.items_dev) (void)hipFree(kv.second.items_dev);
     delete plan;
@@ -1810,77 +2224,36 @@ int lfa_graph_destroy(lfa_graph* graph) {
 }
 
 int lfa_autotune(lfa_plan* plan, const void* const* W, void* const* sigma, void* const* U,
-                 void* const* V, void* ws, size_t ws_bytes, void* stream) {
-    if (!plan) return LFA_ERR_INVALID_ARG;
+                 void* const* V, const char* cache_path, uint32_t what, void* stream) {
+    if (!plan || (what & ~uint32_t(LFA_TUNE_LAYERS | LFA_TUNE_PERSISTENT))) return LFA_ERR_INVALID_ARG;
     LFA_TRY(check_ptrs(plan, W, true));
     LFA_TRY(check_ptrs(plan, sigma, true));
     LFA_TRY(check_ptrs(plan, U, (plan->flags & LFA_WANT_U) != 0));
     LFA_TRY(check_ptrs(plan, V, (plan->flags & LFA_WANT_V) != 0));
-    LFA_TRY(check_ws(plan, ws, ws_bytes));
-    LFA_TRY(ensure_device(plan));
     hipStream_t st = static_cast<hipStream_t>(stream);
-    const bool wu = plan->flags & LFA_WANT_U, wv = plan->flags & LFA_WANT_V;
-    const int eb = elem_bytes(plan->dtype);
-    hipEvent_t e0, e1;
-    HIP_TRY(hipEventCreate(&e0));
-    HIP_TRY(hipEventCreate(&e1));
-    int status = LFA_OK;
-    for (size_t i = 0; i < plan->layers.size() && status == LFA_OK; ++i) {
-        const LayerDesc base = plan->desc[i];
-        const bool acc = accumulates(base, wu, wv);
-        std::vector<LayerDesc> cands;
-        cands.push_back(make_desc(plan->layers[i], base.tw_n, base.tw_m, acc, eb, kLdsCap));
-        for (int L = 1; L <= 64; L <<= 1) {
-            if (L * kRowsPerLane < base.M) continue;
-            if (L > 4 * base.L) continue;
-            for (int th = 64; th <= 1024; th <<= 1) {
-                if (th < L) continue;
-                if (th > 2 * pow2ceil(((base.N + 1) / 2) * L) && th > 64) continue;
-                cands.push_back(make_desc(plan->layers[i], base.tw_n, base.tw_m, acc, eb,
-                                          base.storage == kGlobal ? 0 : kLdsCap, th, L, false));
-            }
-        }
-        float best = 1e30f;
-        LayerDesc best_d = base;
-        char* region = static_cast<char*>(ws) + kAlign;
-        for (LayerDesc d : cands) {
-            d.num_canon = base.num_canon;
-            // resident work-groups (and the work queue) of the plan's own
-            // register-kernel shape
-            const bool same = d.kind == 1 && base.kind == 1 && d.wave_nc == base.wave_nc &&
-                              d.wave_ml == base.wave_ml && d.threads == base.threads;
-            d.wave_cap = same ? base.wave_cap : 0;
-            d.wave_qcap = same ? base.wave_qcap : 0;
-            d.wave_qgroups = same ? base.wave_qgroups : 0;
-            float ms = 0;
-            for (int rep = 0; rep < 2 && status == LFA_OK; ++rep) {
-                if (hipEventRecord(e0, st) != hipSuccess) { status = LFA_ERR_HIP; break; }
-                if (plan->dtype == LFA_F64)
-                    status = run_svd_layer<double>(plan, d, W[i], nullptr, sigma[i],
-                                                   wu ? U[i] : nullptr, wv ? V[i] : nullptr,
-                                                   nullptr, region, nullptr, 0, 0, st, true);
-                else
-                    status = run_svd_layer<float>(plan, d, W[i], nullptr, sigma[i],
-                                                  wu ? U[i] : nullptr, wv ? V[i] : nullptr,
-                                                  nullptr, region, nullptr, 0, 0, st, true);
-                if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
-                    status = LFA_ERR_HIP;
-                    break;
-                }
-                (void)hipEventElapsedTime(&ms, e0, e1);
-            }
-            if (status != LFA_OK) break;
-            if (ms < best) {
-                best = ms;
-                best_d = d;
-            }
-        }
-        best_d.num_canon = base.num_canon;
-        plan->desc[i] = best_d;
-    }
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
-    return status;
+    if (capturing(st)) return LFA_ERR_INVALID_ARG;
+    LFA_TRY(ensure_device(plan));
+    if (plan->dtype == LFA_F64) return autotune_impl<double>(plan, W, sigma, U, V, cache_path, what, st);
+    return autotune_impl<float>(plan, W, sigma, U, V, cache_path, what, st);
+}
+
+int lfa_plan_tuning(const lfa_plan* plan, int32_t layer, int32_t* qr, int32_t* queue_seg, int32_t* team_w,
+                    int32_t* asm_mat) {
+    if (!plan || layer < 0 || layer >= (int32_t)plan->layers.size()) return LFA_ERR_INVALID_ARG;
+    const LayerTune& t = plan->tune[layer];
+    if (qr) *qr = plan->qr[layer];
+    if (queue_seg) *queue_seg = t.queue_seg;
+    if (team_w) *team_w = t.team_w;
+    if (asm_mat) *asm_mat = t.asm_mat;
+    return LFA_OK;
+}
+
+int lfa_plan_cost_model(const lfa_plan* plan, double* wave_s, double* block_s, double* team_ovh) {
+    if (!plan) return LFA_ERR_INVALID_ARG;
+    if (wave_s) *wave_s = plan->cost_wave;
+    if (block_s) *block_s = plan->cost_block;
+    if (team_ovh) *team_ovh = plan->team_ovh;
+    return LFA_OK;
 }
 
 }  // extern "C"

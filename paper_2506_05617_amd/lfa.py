@@ -326,17 +326,38 @@ class Plan:
                  _stream_ptr()), "lfa_sigma_grad_persistent" if persistent else "lfa_sigma_grad")
         return dW
 
-    def autotune(self, Ws):
+    def autotune(self, Ws, cache_path=None, layers=True, persistent=True):
+        """Time and choose the plan's launch parameters on these weights
+        (lfa_autotune), with an optional JSON cache file.  The workspace size
+        may change: the plan's cached workspace is dropped."""
         dev = self._check_weights(Ws)
         S, U, V = self._alloc_outputs(dev, self.want_u, self.want_v)
-        ws = self.workspace(dev)
         w_arr, _k0 = ptr_array([x.data_ptr() for x in Ws])
         s_arr, _k1 = ptr_array([x.data_ptr() for x in S])
         u_arr, _k2 = ptr_array([x.data_ptr() if x is not None else 0 for x in U])
         v_arr, _k3 = ptr_array([x.data_ptr() if x is not None else 0 for x in V])
-        check(self.lib.lfa_autotune(self.handle, w_arr, s_arr, u_arr, v_arr,
-                                    ctypes.c_void_p(ws.data_ptr()), ctypes.c_size_t(ws.numel()),
+        what = (_lib.LFA_TUNE_LAYERS if layers else 0) | (_lib.LFA_TUNE_PERSISTENT if persistent else 0)
+        torch.cuda.current_stream().synchronize()
+        check(self.lib.lfa_autotune(self.handle, w_arr, s_arr, u_arr if self.want_u else None,
+                                    v_arr if self.want_v else None,
+                                    None if cache_path is None else str(cache_path).encode(), what,
                                     _stream_ptr()), "lfa_autotune")
+        nb = ctypes.c_size_t()
+        check(self.lib.lfa_plan_workspace_bytes(self.handle, ctypes.byref(nb)), "lfa_plan_workspace_bytes")
+        self.ws_bytes = nb.value
+        self._ws = None
+
+    def tuning(self, layer):
+        """(qr, queue_seg, team_w, asm_mat) chosen for a layer."""
+        vals = [ctypes.c_int32() for _ in range(4)]
+        check(self.lib.lfa_plan_tuning(self.handle, layer, *[ctypes.byref(v) for v in vals]), "lfa_plan_tuning")
+        return tuple(v.value for v in vals)
+
+    def cost_model(self):
+        """(seconds per unit of a register-kernel wave, of a blocked work-group, team overhead)."""
+        vals = [ctypes.c_double() for _ in range(3)]
+        check(self.lib.lfa_plan_cost_model(self.handle, *[ctypes.byref(v) for v in vals]), "lfa_plan_cost_model")
+        return tuple(v.value for v in vals)
 
 
 class GraphStep:

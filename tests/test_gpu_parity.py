@@ -1155,6 +1155,61 @@ def test_resnet18_stack_full_size_onesided_graph():
         torch.cuda.synchronize()
 
 
+def test_autotuned_resnet18_stack_matches_oracle(tmp_path):
+    """lfa_autotune on the full ResNet-18 stack (per-layer choices for the
+    per-layer SVD, and the persistent launch's cost model) with a JSON
+    cache; the tuned plan's one-sided graph step then matches the oracle
+    (top-8 values at the picks, dW elementwise, sampled sigma of every
+    layer).  A second plan tuned from the same cache gets the same choices
+    without timing; the cache is valid JSON with an entry per layer shape and
+    one for the persistent launch."""
+    import json
+
+    banner("autotuned ResNet-18 stack")
+    layers, Ws = workloads.resnet18_stack()
+    specs = [lfa().LayerSpec(l.c_out, l.c_in, l.kh, l.kw, l.n, l.m) for l in layers]
+    Wt = [_w(W) for W in Ws]
+    cache = tmp_path / "tune.json"
+    plan = lfa().Plan(specs, want_u=True)
+    plan.autotune(Wt, cache)
+    doc = json.loads(cache.read_text())
+    keys = list(doc["entries"])
+    assert sum("/layer/" in k for k in keys) == len(set(specs)), keys
+    assert sum("/persistent/" in k for k in keys) == 1, keys
+    choices = [plan.tuning(i) for i in range(len(specs))]
+    print(f"[tune] {choices} cost model {plan.cost_model()}", flush=True)
+    plan2 = lfa().Plan(specs, want_u=True)
+    import time
+    t0 = time.perf_counter()
+    plan2.autotune(Wt, cache)
+    assert time.perf_counter() - t0 < 2.0
+    assert [plan2.tuning(i) for i in range(len(specs))] == choices
+    assert plan2.cost_model() == plan.cost_model()
+    step = lfa().GraphStep(plan, Wt, 8)
+    for rep in range(2):
+        step.replay().synchronize()
+        assert plan.info_status(step.info) == 0
+        vals, idx = to_np(step.vals), to_np(step.idx)
+        for li, l in enumerate(layers):
+            W64 = Ws[li].astype(np.float64)
+            p, q, j = idx[li].T
+            s_at = oracle.lfa_svd(W64, l.n, l.m, freqs=np.stack([p, q], axis=1))[np.arange(8), j]
+            assert np.max(np.abs(vals[li] - s_at)) <= 1e-5 * s_at.max(), (rep, li)
+            _grad_check(W64, l, idx[li], np.ones(8), step.dW[li], f"tuned graph {rep} layer {li}")
+            if rep == 0:
+                fr = _sample(l.n, l.m, 4, 60 + li)
+                S_ref = oracle.lfa_svd(W64, l.n, l.m, freqs=fr)
+                assert oracle.sigma_error(to_np(step.S[li])[fr[:, 0], fr[:, 1]], S_ref) <= 1e-5
+    # the per-layer path of the tuned plan as well
+    S, U, _, info = plan.svd(Wt)
+    torch.cuda.synchronize()
+    assert plan.info_status(info) == 0
+    for li, l in enumerate(layers):
+        fr = _sample(l.n, l.m, 4, 80 + li)
+        S_ref = oracle.lfa_svd(Ws[li].astype(np.float64), l.n, l.m, freqs=fr)
+        assert oracle.sigma_error(to_np(S[li])[fr[:, 0], fr[:, 1]], S_ref) <= 1e-5
+
+
 @pytest.mark.parametrize("asm", [None, "bf16x2", "bf16x3"])
 def test_large_grid_7x7_full_size_sampled(asm):
     """64 -> 64 channels, 7x7 kernel with five taps scaled by 1e3, 224x224
