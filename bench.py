@@ -211,10 +211,37 @@ def bench_stack(dev, steps):
         wall_p = wall_pt
     batched_out = (graph.vals.clone(), graph.idx.clone(), [d.clone() for d in graph.dW])
     nl = len(specs)
+    # the batched step against the FP32 roofline: algorithmic flops of the
+    # one-sided forward sweeps (working matrix only, no accumulator) over the
+    # step time; and the load balance of its persistent launch, from one
+    # instrumented launch (busy time of every compute unit over the launch)
+    info_b = graph.info.cpu().numpy()
+    flops = sum(jacobi_flops(l, int(info_b[i][2]), False) for i, l in enumerate(layers))
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    _, _, _, _, rec = plan_u.persistent_busy(Wt)
+    e1.record()
+    torch.cuda.synchronize()
+    span_s = e0.elapsed_time(e1) * 1e-3
+    rec = rec.cpu().numpy()
+    per_cu = {}
+    for busy_t, items, xcc, hw in rec:
+        if items == 0 and busy_t == 0:
+            continue
+        key = (int(xcc), int(hw))
+        b, c = per_cu.get(key, (0, 0))
+        per_cu[key] = (b + busy_t * 1e-8, c + 1)
+    frac = np.array([b / (span_s * c) for b, c in per_cu.values()])
+    balance = dict(compute_units=len(per_cu), work_groups=int(sum(c for _, c in per_cu.values())),
+                   launch_ms=span_s * 1e3, busy_frac_min=float(frac.min()), busy_frac_median=float(np.median(frac)),
+                   busy_frac_mean=float(frac.mean()), busy_frac_max=float(frac.max()))
+    roof = dict(algorithmic_gflop=flops / 1e9, tflops=flops / (wall_b / steps) / 1e12,
+                frac_of_fp32_peak=flops / (wall_b / steps) / 1e12 / PEAK_FP32_VECTOR_TFLOPS,
+                sweeps_sum=[int(x) for x in info_b[:, 2]], per_cu_busy=balance)
     return dict(layers=layers, Ws=Ws, graph=graph, plain_out=res["plain"], batched_out=batched_out, S=Su,
                 plain_layers_per_s=nl * steps / wall_p, batched_layers_per_s=nl * steps / wall_b,
                 plain_ms=wall_p * 1e3 / steps, batched_ms=wall_b * 1e3 / steps,
-                plain_sigma_only_recompute_ms=wall_r * 1e3 / steps, tuned=tuned,
+                plain_sigma_only_recompute_ms=wall_r * 1e3 / steps, tuned=tuned, roofline=roof,
                 batched_uv_graph_ms=wall_uv * 1e3 / steps,
                 batched_sigma_only_ms=wall_s * 1e3 / steps)
 
@@ -557,6 +584,7 @@ def main():
             "batched_sigma_only_graph_ms": st["batched_sigma_only_ms"],
             "plain_sigma_only_recompute_ms": st["plain_sigma_only_recompute_ms"],
             "autotuned": st["tuned"],
+            "batched_roofline": st["roofline"],
             "timed": "the faster of the default and the autotuned plan for each path",
             "speedup_batched_vs_plain": st["batched_layers_per_s"] / st["plain_layers_per_s"]}
         note("ResNet-18 stack done")

@@ -235,6 +235,23 @@ int lfa_svd_persistent(const lfa_plan* plan, const void* const* W, void* const* 
                        void* const* U, void* const* V, int32_t* info, void* ws,
                        size_t ws_bytes, void* stream);
 
+/* Measurement form of lfa_svd_persistent: the same launch and results, and
+ * a record per work-group of the launch written to `busy` (device int64
+ * [busy_len][4]): ticks of the 100 MHz device clock from taking its first
+ * item to finishing its last, items taken, the XCD (XCC_ID register) and the
+ * shader-engine / array / compute-unit bits of its HW_ID register (bits
+ * 8..15), which together name the compute unit it ran on.  busy_len must be
+ * at least lfa_plan_persistent_grid's value; with more than 12 layers (more
+ * than one launch) the records are those of the last launch.  Errors: as lfa_svd_persistent, plus
+ * LFA_ERR_INVALID_ARG for a NULL or short `busy`. */
+int lfa_svd_persistent_busy(const lfa_plan* plan, const void* const* W, void* const* sigma, void* const* U,
+                            void* const* V, int32_t* info, void* ws, size_t ws_bytes, int64_t* busy,
+                            int32_t busy_len, void* stream);
+
+/* Work-groups of the plan's persistent launch on the current device (the
+ * largest over its launches). */
+int lfa_plan_persistent_grid(const lfa_plan* plan, int32_t* grid);
+
 /* SVD of symbols the caller already holds (e.g. from lfa_symbols), same
  * outputs as lfa_svd.  A: per-layer [n][m][c_out][c_in] complex (device).
  * Every symbol is decomposed: caller symbols need not come in conjugate

@@ -73,6 +73,8 @@ SIGNATURES = {
     "lfa_svd": (I32, [P, PP, PP, PP, PP, P, P, SZ, P]),
     "lfa_svd_persistent": (I32, [P, PP, PP, PP, PP, P, P, SZ, P]),
     "lfa_svd_noalloc": (I32, [P, PP, PP, PP, PP, P, P]),
+    "lfa_svd_persistent_busy": (I32, [P, PP, PP, PP, PP, P, P, SZ, P, I32, P]),
+    "lfa_plan_persistent_grid": (I32, [P, I32P]),
     "lfa_svd_symbols": (I32, [P, PP, PP, PP, PP, P, P, SZ, P]),
     "lfa_topk": (I32, [P, PP, I32, P, P, P]),
     "lfa_adjoint": (I32, [P, PP, PP, P, P, I32, PP, P]),

@@ -272,10 +272,15 @@ int asm_mode(uint32_t flags) {
 }
 
 // Materialised (matrix-core) assembly for layer i: the autotuner's choice,
-// else the plan's flags.
+// else the plan's flags, else by default for FP32 kernels of 25 taps or more
+// (the fused assembly then costs the SVD kernel more than writing and
+// reading the symbols: 7x7 kernel on the 224 x 224 grid, 18.5 ms fused
+// against 0.8 ms of FP32 matrix-core assembly + 15.5 ms of SVD).
 bool layer_materialized(const lfa_plan& p, size_t i) {
     const int t = p.tune[i].asm_mat;
-    return t >= 0 ? t == 1 : asm_materialized(p.flags);
+    if (t >= 0) return t == 1;
+    const lfa_layer& l = p.layers[i];
+    return asm_materialized(p.flags) || (p.dtype == LFA_F32 && l.kh * l.kw >= 25);
 }
 
 size_t pers_counter_bytes(const lfa_plan& p) {
@@ -867,7 +872,7 @@ int check_ptrs(const lfa_plan* p, const void* const* arr, bool required) {
 
 template <typename R>
 int persistent_impl(const lfa_plan* p, const void* const* W, void* const* sigma, void* const* U,
-                    void* const* V, int32_t* info, void* ws, hipStream_t st) {
+                    void* const* V, int32_t* info, void* ws, hipStream_t st, long long* busy = nullptr) {
     const bool wu = p->flags & LFA_WANT_U, wv = p->flags & LFA_WANT_V;
     int32_t* counter = static_cast<int32_t*>(ws);
     char* region = static_cast<char*>(ws) + kAlign;
@@ -908,6 +913,7 @@ int persistent_impl(const lfa_plan* p, const void* const* W, void* const* sigma,
         pa.counter = counter;
         pa.team_counters = team_counters;
         pa.num_teams = p->pers_teams;
+        pa.busy = busy;
         pa.wave_slots = p->pers_wave_slots;
         pa.wave_lds = (int)(p->pers_wave_slots ? p->pers_lds[chunk] / p->pers_wave_slots : 0);
         // per-wave LDS stride: the largest bundle region of the chunk
@@ -1484,17 +1490,20 @@ int autotune_impl(lfa_plan* p, const void* const* W, void* const* sigma, void* c
                     apply(oq, ot);
                 }
             };
-            // QR factors or not, then matrix-core assembly for many taps
-            if (qr_eligible(l, p->dtype, p->flags)) trial(1 - p->qr[i], p->tune[i]);
-            if (p->dtype == LFA_F32 && l.kh * l.kw >= 25 && !asm_materialized(p->flags) && best_qr == 0) {
+            // materialised matrix-core assembly or fused (kernels of 25 taps
+            // or more), then QR factors or not (fused assembly only)
+            if (p->dtype == LFA_F32 && l.kh * l.kw >= 25 && !asm_materialized(p->flags)) {
                 LayerTune t = bt;
-                t.asm_mat = 1;
-                trial(0, t);
+                t.asm_mat = layer_materialized(*p, (size_t)i) ? 0 : 1;
+                trial(best_qr, t);
             }
+            apply(best_qr, bt);
+            if (qr_eligible(l, p->dtype, p->flags) && !layer_materialized(*p, (size_t)i))
+                trial(1 - best_qr, bt);
             apply(best_qr, bt);
             // the launch of the path in use: work-queue turns of the register
             // kernel, or team widths of the blocked kernel
-            const LayerDesc& d = (p->qr[i] && p->tune[i].asm_mat != 1) ? p->desc_r[i] : p->desc[i];
+            const LayerDesc& d = (p->qr[i] && !layer_materialized(*p, (size_t)i)) ? p->desc_r[i] : p->desc[i];
             if (d.kind == 1 && d.wave_qgroups > 0) {
                 for (int seg : {0, 3, 4, 5, 6, 8}) {
                     LayerTune t = bt;
@@ -2017,6 +2026,38 @@ int lfa_svd_persistent(const lfa_plan* plan, const void* const* W, void* const* 
                        void* stream) {
     if (!W) return LFA_ERR_INVALID_ARG;
     return svd_common(plan, W, nullptr, sigma, U, V, info, ws, ws_bytes, stream, true);
+}
+
+int lfa_plan_persistent_grid(const lfa_plan* plan, int32_t* grid) {
+    if (!plan || !grid) return LFA_ERR_INVALID_ARG;
+    lfa_plan* p = const_cast<lfa_plan*>(plan);
+    LFA_TRY(ensure_device(p));
+    int g = 0;
+    for (size_t c = 0; c + 1 < p->chunk_first.size(); ++c)
+        g = std::max(g, std::min(p->pers_grid[c], p->chunk_first[c + 1] - p->chunk_first[c]));
+    *grid = g;
+    return LFA_OK;
+}
+
+int lfa_svd_persistent_busy(const lfa_plan* plan, const void* const* W, void* const* sigma, void* const* U,
+                            void* const* V, int32_t* info, void* ws, size_t ws_bytes, int64_t* busy,
+                            int32_t busy_len, void* stream) {
+    if (!plan || !W || !busy) return LFA_ERR_INVALID_ARG;
+    int32_t g = 0;
+    LFA_TRY(lfa_plan_persistent_grid(plan, &g));
+    if (busy_len < g) return LFA_ERR_INVALID_ARG;
+    LFA_TRY(check_ptrs(plan, W, true));
+    LFA_TRY(check_ptrs(plan, sigma, true));
+    LFA_TRY(check_ptrs(plan, U, (plan->flags & LFA_WANT_U) != 0));
+    LFA_TRY(check_ptrs(plan, V, (plan->flags & LFA_WANT_V) != 0));
+    if (asm_materialized(plan->flags)) return LFA_ERR_UNSUPPORTED;
+    LFA_TRY(check_ws(plan, ws, ws_bytes));
+    lfa_plan* p = const_cast<lfa_plan*>(plan);
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    LFA_TRY(ensure_device(p, st, true));
+    long long* b = reinterpret_cast<long long*>(busy);
+    if (p->dtype == LFA_F64) return persistent_impl<double>(p, W, sigma, U, V, info, ws, st, b);
+    return persistent_impl<float>(p, W, sigma, U, V, info, ws, st, b);
 }
 
 int lfa_svd_symbols(const lfa_plan* plan, const void* const* A, void* const* sigma,

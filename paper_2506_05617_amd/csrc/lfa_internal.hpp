@@ -474,6 +474,8 @@ struct PersistentArgs {
     int wave_slots;                 // waves of a work-group that run bundles
     int wave_lds;                   // LDS bytes of one wave's bundle
     int threads;                    // work-group size (256)
+    long long* busy;                // optional per-work-group record [grid][4]: busy ticks
+                                    // (100 MHz), items taken, XCC id, HW_ID (SE/SH/CU bits); or null
 };
 constexpr int kPersistentThreads = 256;
 

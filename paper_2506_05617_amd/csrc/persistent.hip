@@ -52,12 +52,29 @@ __global__ void __launch_bounds__(256) persistent_kernel(PersistentArgs<R> pa_ar
 #else
     const PersistentArgs<R>& pa = pa_arg;
 #endif
+    // optional record of this work-group's busy time (from taking an item
+    // to finishing it) and of the compute unit it ran on
+    long long busy = 0, taken = 0, t_item = 0;
     for (;;) {
-        if (threadIdx.x == 0) item_sh = atomicAdd(pa.counter, 1);
+        if (threadIdx.x == 0) {
+            if (pa.busy && t_item) busy += (long long)(wall_clock64() - t_item);
+            item_sh = atomicAdd(pa.counter, 1);
+            if (pa.busy) t_item = (long long)wall_clock64();
+        }
         __syncthreads();
         const int idx = item_sh;
         __syncthreads();
-        if (idx >= pa.num_items) break;
+        if (idx >= pa.num_items) {
+            if (pa.busy && threadIdx.x == 0) {
+                long long* r = pa.busy + 4 * (size_t)blockIdx.x;
+                r[0] = busy;
+                r[1] = taken;
+                r[2] = (long long)__builtin_amdgcn_s_getreg(20 | (0 << 6) | (3 << 11));    // XCC_ID
+                r[3] = (long long)(__builtin_amdgcn_s_getreg(4 | (0 << 6) | (31 << 11)) & 0xff00u);   // HW_ID: CU, SH, SE
+            }
+            break;
+        }
+        ++taken;
         const WorkItem w = pa.items[idx];
         const SvdArgs<R>& a = pa.layer[w.layer];
         if (w.kind == 0) {

@@ -203,6 +203,28 @@ class Plan:
                                        _stream_ptr()), "lfa_svd_noalloc")
         return S, U, V, info
 
+    def persistent_busy(self, Ws, out=None):
+        """One lfa_svd_persistent_busy launch: (S, U, V, info, records) with
+        records an int64 [grid, 4] tensor (busy ticks at 100 MHz, items, XCD,
+        HW_ID compute-unit bits) per work-group."""
+        dev = self._check_weights(Ws)
+        g = ctypes.c_int32()
+        check(self.lib.lfa_plan_persistent_grid(self.handle, ctypes.byref(g)), "lfa_plan_persistent_grid")
+        S, U, V = out if out is not None else self._alloc_outputs(dev, self.want_u, self.want_v)
+        info = torch.zeros(len(self.layers), _lib.LFA_INFO_WORDS, dtype=torch.int32, device=dev)
+        rec = torch.zeros(max(1, g.value), 4, dtype=torch.int64, device=dev)
+        ws = self.workspace(dev)
+        w_arr, _k0 = ptr_array([x.data_ptr() for x in Ws])
+        s_arr, _k1 = ptr_array([x.data_ptr() for x in S])
+        u_arr, _k2 = ptr_array([x.data_ptr() if x is not None else 0 for x in U])
+        v_arr, _k3 = ptr_array([x.data_ptr() if x is not None else 0 for x in V])
+        check(self.lib.lfa_svd_persistent_busy(self.handle, w_arr, s_arr, u_arr if self.want_u else None,
+                                               v_arr if self.want_v else None, ctypes.c_void_p(info.data_ptr()),
+                                               ctypes.c_void_p(ws.data_ptr()), ctypes.c_size_t(ws.numel()),
+                                               ctypes.c_void_p(rec.data_ptr()), rec.shape[0], _stream_ptr()),
+              "lfa_svd_persistent_busy")
+        return S, U, V, info, rec
+
     def svd_symbols(self, As, info=None):
         cdt = _complex_of(self.dtype)
         for A, l in zip(As, self.layers):

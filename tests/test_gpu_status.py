@@ -144,3 +144,26 @@ def test_prepared_plan_captures_into_a_torch_graph():
                 plan.sigma_grad(Wt, idx[:, :2].contiguous(), g[:, :2].contiguous(), out=dW, persistent=True)
     assert err.value.status == lfa()._lib.LFA_ERR_NOT_PREPARED
     torch.cuda.synchronize()
+
+
+def test_persistent_busy_records_match_the_launch():
+    """lfa_svd_persistent_busy: the same singular values as
+    lfa_svd_persistent (bitwise), one record per work-group of the launch,
+    items taken summing to the work list, busy time within the launch, and
+    compute-unit identities that are few per work-group (at most a few
+    work-groups share a compute unit)."""
+    banner("persistent busy records")
+    layers, Ws = workloads.resnet18_stack(seed=85, shapes=((3, 64, 8), (64, 64, 8), (64, 128, 4), (128, 256, 3)))
+    plan = lfa().Plan([_spec(l) for l in layers])
+    Wt = [_w(W) for W in Ws]
+    S1, _, _, _ = plan.svd(Wt, persistent=True)
+    S2, _, _, info, rec = plan.persistent_busy(Wt)
+    torch.cuda.synchronize()
+    for a, b in zip(S1, S2):
+        assert torch.equal(a, b)
+    rec = to_np(rec)
+    assert rec.shape[1] == 4 and rec.shape[0] >= 1
+    assert np.all(rec[:, 0] >= 0) and np.all(rec[:, 1] >= 0)
+    assert rec[:, 1].sum() > 0
+    cus = {(int(x), int(h)) for x, h in rec[:, 2:]}
+    assert len(cus) >= 1 and rec.shape[0] <= 8 * len(cus)
