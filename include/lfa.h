@@ -543,7 +543,7 @@ int lfa_plan_preconditioned(const lfa_plan* plan, int32_t layer, int32_t* qr);
  *   sweeps_per_turn : sweeps a group runs per turn for lfa_svd of the
  *                     layer (0: one work-group per group instead)
  * The environment variable LFA_WAVE_QUEUE, read by lfa_plan_create, turns
- * the work queue off ("0") or forces it with k sweeps per turn ("1" .. "8").
+ * the work queue off ("0") or forces it with k sweeps per turn ("1" .. "16").
  * Needs a gfx950 device (LFA_ERR_NO_DEVICE otherwise). */
 int lfa_plan_queue_info(lfa_plan* plan, int32_t layer, int32_t* resident,
                         int32_t* sweeps_per_turn);

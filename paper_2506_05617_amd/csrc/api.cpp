@@ -233,9 +233,12 @@ int wave_queue_reserved(const LayerDesc& d, bool acc, int eb) {
 // Sweeps per turn of a group in the work-queue launch (0: no work queue).
 // A turn costs the save and restore of the group's rows and an L2 write-back
 // and invalidation; measured on the 64 x 64 layer on the 64 x 64 grid (2050
-// groups, 1024 or 2048 resident; 8 to 10 sweeps per symbol): with vectors 6
-// sweeps per turn was best (1 % ahead of 5), sigma only 4 or 5 (6: 4 %
-// slower); 1 sweep per turn was slower than no work queue.
+// groups, 1024 or 2048 resident; 8 to 10 sweeps per symbol): sigma only 4
+// or 5 sweeps per turn were best (6: 4 % slower); with vectors 2.54, 2.51,
+// 2.62 and 2.81 ms for 5, 6, 7 and 8 sweeps per turn, 2.81 ms for 10 (a
+// whole symbol's sweeps: no group is saved, but the last groups start
+// late), 2.90 ms without the queue.  The saved rows are about half the HBM
+// bytes of the launch, which is ALU-bound: fine-grained turns pay.
 constexpr int kQueueSweepsPerTurn = 5;
 constexpr int kQueueSweepsPerTurnVectors = 6;
 int wave_queue_seg(const LayerDesc& d, int groups, int force) {
@@ -1505,7 +1508,7 @@ int autotune_impl(lfa_plan* p, const void* const* W, void* const* sigma, void* c
             // kernel, or team widths of the blocked kernel
             const LayerDesc& d = (p->qr[i] && !layer_materialized(*p, (size_t)i)) ? p->desc_r[i] : p->desc[i];
             if (d.kind == 1 && d.wave_qgroups > 0) {
-                for (int seg : {0, 3, 4, 5, 6, 8}) {
+                for (int seg : {0, 4, 5, 6, 8, 10, 12}) {
                     LayerTune t = bt;
                     t.queue_seg = seg;
                     trial(best_qr, t);
@@ -1636,12 +1639,13 @@ int lfa_plan_create(lfa_plan** out, const lfa_layer* layers, int32_t num_layers,
     const int eb = elem_bytes(dtype);
     // unit roundoff of the working precision (see jacobi_tol)
     p->tol = dtype == LFA_F64 ? std::ldexp(1.0, -53) : std::ldexp(1.0, -24);
-    // LFA_WAVE_QUEUE: "0" turns the work-queue launch off, k in 1..8 forces it
-    // with k sweeps per turn (tests, tuning); unset or other values: automatic
+    // LFA_WAVE_QUEUE: "0" turns the work-queue launch off, k in 1..16 forces
+    // it with k sweeps per turn (tests, tuning); unset or other values:
+    // automatic
     if (const char* env = std::getenv("LFA_WAVE_QUEUE")) {
         const int v = std::atoi(env);
         if (std::strcmp(env, "0") == 0) p->wq_force = 0;
-        else if (v >= 1 && v <= 8) p->wq_force = v;
+        else if (v >= 1 && v <= 16) p->wq_force = v;
     }
 
     // twiddles exp(2 pi i j / L) for every distinct grid length L

@@ -78,12 +78,16 @@ __host__ __device__ constexpr double negligible_sq() {
 // Leaves everything unchanged and returns the identity (zeros) below the
 // threshold or for a numerically zero column (min(al, be) <= floor).
 //
-// Result: 0 without a rotation, 1 for a rotation with |t| <= kappa, 2 for a
-// larger one, kappa = sqrt(tol)/4.  A sweep whose rotations all have
-// |t| <= kappa leaves the columns orthogonal to the threshold (each small
-// rotation changes the other inner products of its columns by O(kappa) times
-// those, which are themselves at most O(kappa)), so the rotation-free sweep
-// that would confirm it can be skipped.
+// Result: 0 without a rotation, 1 for a small rotation, 2 for a larger one.
+// A rotation is small when it moves each of its two columns by at most
+// kappa = sqrt(tol)/4 relative to that column's own norm: the shorter
+// column gains t |g_long|, so |t| sqrt(max(al, be) / min(al, be)) <= kappa
+// (for columns of unequal norms -- graded symbols -- a small tangent alone
+// does not bound the change of the shorter one).  A sweep whose rotations
+// are all small then changes every inner product by O(kappa) times the
+// products, which are themselves O(kappa), so the columns end orthogonal to
+// the threshold and the rotation-free sweep that would confirm it can be
+// skipped.
 template <typename R>
 __device__ __forceinline__ int rotation_scaled(double& al, double& be, double gr, double gi, double tol,
                                                double floor, R& dj, R& dk, quad<R>& q) {
@@ -120,6 +124,7 @@ __device__ __forceinline__ int rotation_scaled(double& al, double& be, double gr
         rjk = double(dk) / double(dj);
         rkj = double(dj) / double(dk);
     }
+    const double grade = fmax(al, be) / fmin(al, be);               // >= 1 (min > floor >= 0)
     const double tg = t * g2 * rg;                                    // t |gamma|
     al = fmax(al - tg, 0.0);
     be = fmax(be + tg, 0.0);
@@ -127,7 +132,7 @@ __device__ __forceinline__ int rotation_scaled(double& al, double& be, double gr
     q = {R(tr * rjk), R(ti * rjk), R(tr * rkj), R(-ti * rkj)};
     dj = R(c * double(dj));
     dk = R(c * double(dk));
-    return 16.0 * t * t > tol ? 2 : 1;
+    return 16.0 * t * t * grade > tol ? 2 : 1;
 }
 
 // g_j' = g_j - tau1 g_k, g_k' = g_k + tau2 g_j (see rotation_scaled).

@@ -319,12 +319,84 @@ __global__ void __launch_bounds__(256) qr_left_kernel(QrVecArgs<R> q) {
 
 // The blocked kernels' finish on Y and V_R (one work-group per decomposed
 // frequency): sigma, U and V of the symbol into the layer's outputs.
+//
+// Columns y_j = G v_j of singular values far below the largest carry
+// rounding errors of about u ||G|| in every direction, so the u_j = y_j /
+// sigma_j would lose orthogonality like u sigma_max / sigma_j.  Before the
+// finish, every such column (sigma_j <= sigma_0 / 64, in decreasing order)
+// is orthogonalised against all earlier columns by two passes of classical
+// Gram-Schmidt on the unit vectors y_i / |y_i|: U becomes orthonormal to
+// working precision, and y_j changes by at most its error, about
+// u sigma_max, inside the normwise tolerance.  Well-conditioned symbols skip
+// the passes.
 template <typename R>
-__global__ void __launch_bounds__(256) qr_finish_kernel(SvdArgs<R> a) {
+__global__ void __launch_bounds__(256) qr_finish_kernel(SvdArgs<R> a, const R* sigma_r) {
     extern __shared__ __align__(16) char lds_raw[];
     const int item = blockIdx.x;
     const Target tg = target_of(a, item);
     const Shared<R> s = carve<R>(lds_raw, a.d, true, a.gws + (size_t)item * a.slot_bytes);
+    const int M = a.d.M, N = a.d.N, ldg = a.d.ldg;
+    const R* sr = sigma_r + (size_t)tg.theta * N;
+    const int lane = threadIdx.x & 63, group = threadIdx.x >> 6, ngroups = blockDim.x >> 6;
+    cplx<R>* G = s.G;
+    // column norms into s.sig (the finish recomputes them afterwards)
+    for (int j = group; j < N; j += ngroups) {
+        R acc = 0;
+        for (int i = lane; i < M; i += 64) {
+            const cplx<R> v = G[(size_t)j * ldg + i];
+            acc = fma(v.x, v.x, fma(v.y, v.y, acc));
+        }
+        acc = group_sum<R, 64>(acc);
+        if (lane == 0) s.sig[j] = sqrt(acc);
+    }
+    __syncthreads();
+    const R s0 = sr[0];
+    for (int j = 1; j < N; ++j) {
+        const R sj = sr[j];
+        if (!(sj > R(0)) || !(sj * R(64) <= s0)) continue;    // uniform over the work-group
+        for (int pass = 0; pass < 2; ++pass) {
+            // c_i = u_i^H y_j for the earlier nonzero columns, one per group
+            for (int i = group; i < j; i += ngroups) {
+                cplx<R> c = {R(0), R(0)};
+                const R ni = s.sig[i];
+                if (ni > R(0)) {
+                    for (int r = lane; r < M; r += 64) {
+                        const cplx<R> u = G[(size_t)i * ldg + r], y = G[(size_t)j * ldg + r];
+                        c.x = fma(u.x, y.x, fma(u.y, y.y, c.x));
+                        c.y = fma(u.x, y.y, fma(-u.y, y.x, c.y));
+                    }
+                    c.x = group_sum<R, 64>(c.x) / ni;
+                    c.y = group_sum<R, 64>(c.y) / ni;
+                }
+                if (lane == 0) s.coef[i] = c;
+            }
+            __syncthreads();
+            // y_j -= sum_i c_i u_i
+            for (int r = threadIdx.x; r < M; r += blockDim.x) {
+                cplx<R> y = G[(size_t)j * ldg + r];
+                for (int i = 0; i < j; ++i) {
+                    const R ni = s.sig[i];
+                    if (!(ni > R(0))) continue;
+                    const cplx<R> c = s.coef[i], u = G[(size_t)i * ldg + r];
+                    const R inv = R(1) / ni;
+                    y.x -= (c.x * u.x - c.y * u.y) * inv;
+                    y.y -= (c.x * u.y + c.y * u.x) * inv;
+                }
+                G[(size_t)j * ldg + r] = y;
+            }
+            __syncthreads();
+        }
+        if (group == 0) {
+            R acc = 0;
+            for (int r = lane; r < M; r += 64) {
+                const cplx<R> v = G[(size_t)j * ldg + r];
+                acc = fma(v.x, v.x, fma(v.y, v.y, acc));
+            }
+            acc = group_sum<R, 64>(acc);
+            if (lane == 0) s.sig[j] = sqrt(acc);
+        }
+        __syncthreads();
+    }
     finish<R, 64>(a, s, tg.out, tg.mirror, 0, true);
 }
 
@@ -380,7 +452,7 @@ hipError_t launch_qr_vectors(const QrVecArgs<R>& q, const SvdArgs<R>& a, int ite
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
     }
-    hipLaunchKernelGGL(qr_finish_kernel<R>, dim3(items), dim3(256), lds, s, a);
+    hipLaunchKernelGGL(qr_finish_kernel<R>, dim3(items), dim3(256), lds, s, a, q.sigma);
     return hipGetLastError();
 }
 

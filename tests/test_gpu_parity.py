@@ -882,6 +882,51 @@ def test_qr_preconditioned_rank_deficient_zeros(monkeypatch):
     assert np.all(to_np(S)[..., 9:] == 0)
 
 
+GRADED_CASES = [
+    # c_out, c_in, kh, n, m, LFA_QR: tall FP32 layers, input channels scaled
+    # by 1, 10^2.5, 10^5 in turn
+    (64, 48, 3, 4, 4, "0"),       # register kernel
+    (160, 96, 3, 3, 3, "0"),      # blocked kernel
+    (160, 96, 3, 3, 3, "1"),      # QR preconditioning, left vectors from G V
+]
+
+
+@pytest.mark.parametrize("case", GRADED_CASES)
+def test_graded_columns_relative_accuracy(case, monkeypatch):
+    """Symbols with columns graded over five decades.  One-sided Jacobi with
+    a threshold relative to the two columns' norms finds even the smallest
+    singular values to a relative accuracy set by the condition of the
+    column-normalised matrix (here about 1e-5 in FP32), where an algorithm
+    accurate only normwise would err by u sigma_max / sigma, up to 1e-1.
+    Every singular value of the grid against the oracle's, relative to
+    itself (gate 1e-4); orthonormality of U and V and the residual on
+    sampled symbols; projectors of separated values."""
+    c_out, c_in, kh, n, m, qr = case
+    banner(f"graded {case}")
+    L, W = workloads.graded_channels(c_out, c_in, kh, kh, n, m, seed=57)
+    spec = lfa().LayerSpec(c_out, c_in, kh, kh, n, m)
+    monkeypatch.setenv("LFA_QR", qr)
+    plan = lfa().Plan([spec], want_u=True, want_v=True)
+    assert plan.preconditioned(0) == (qr == "1")
+    S, U, V, info = plan.svd([_w(W)])
+    torch.cuda.synchronize()
+    assert plan.info_status(info) == 0
+    W64 = W.astype(np.float64)
+    S_ref = oracle.lfa_svd(W64, n, m)
+    Sg = to_np(S[0]).astype(np.float64)
+    assert S_ref.min() > 0 and S_ref.max() / S_ref.min() > 1e4
+    rel = float(np.max(np.abs(Sg - S_ref) / S_ref))
+    print(f"[graded] {case}: max relative sigma error {rel:.2e}, "
+          f"range {S_ref.max() / S_ref.min():.1e}", flush=True)
+    assert rel <= 1e-4, f"{case}: relative sigma error {rel:.3e}"
+    fr = _sample(n, m, 4, 58)
+    A = oracle.symbols(W64, n, m, fr)
+    Sg, Ug, Vg = (to_np(x)[fr[:, 0], fr[:, 1]] for x in (S[0], U[0], V[0]))
+    check_vectors(A, Sg, Ug, Vg, torch.float32, f"graded {case}")
+    s_r, u_r, v_r = oracle.svd_symbols(A)
+    check_projectors(s_r, u_r, v_r, Ug, Vg, torch.float32, f"graded {case}")
+
+
 # ------------------------------------------------- rank-deficient symbols --
 
 RANK_DEFICIENT_CASES = [

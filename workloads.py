@@ -151,6 +151,19 @@ def resnet18_downsampling(seed: int = 7):
     return out
 
 
+def graded_channels(c_out, c_in, kh, kw, n, m=None, scales=(1.0, 10 ** 2.5, 1e5), seed=0,
+                    dtype=np.float32):
+    """N(0, 1/(kh*kw*c_in)) layer whose input channel i is multiplied by
+    ``scales[i % len(scales)]``: every symbol's columns (of the tall layer)
+    are graded by those factors, singular values spread over their range."""
+    m = n if m is None else m
+    L = Layer(c_out, c_in, kh, kw, n, m)
+    rng = np.random.default_rng(seed)
+    W = rng.standard_normal((c_out, c_in, kh, kw)) * np.sqrt(1.0 / (kh * kw * c_in))
+    W *= np.asarray([scales[i % len(scales)] for i in range(c_in)])[None, :, None, None]
+    return L, W.astype(dtype)
+
+
 def random_layer(c_out, c_in, kh, kw, n, m=None, seed=0, dtype=np.float32):
     """Generic N(0, 1/(kh*kw*c_in)) layer for parity tests."""
     m = n if m is None else m
