@@ -27,7 +27,7 @@ __global__ void __launch_bounds__(512) block_kernel(SvdArgs<R> a, int W, int ite
     team.target = 0;
     char* gslot = a.gws + (size_t)tix * a.slot_bytes;
     const int count = min(item_count(a), item_end);
-    for (int item = item0 + tix; item < count; item += teams) block_one<R, 1, ACC>(a, lds, item, gslot, team);
+    for (int item = item0 + tix; item < count; item += teams) block_one<R, 1, ACC, !ACC && sizeof(R) == 4>(a, lds, item, gslot, team);
 }
 
 template <typename R, int L>
@@ -98,10 +98,10 @@ size_t block_lds_bytes(const LayerDesc& d, bool accumulate, int elem_bytes) {
     dg.kind = 0;
     dg.storage = kGlobal;
     const int nw = d.threads / 64;
-    // BlockLds: wpart, wsum (two buffers), wprm (quads), wdsc, rflag
+    // BlockLds: wpart, wsum (two buffers), wprm (quads), wdsc, wnrm (FP64), rflag
     return lds_bytes_for(dg, accumulate, elem_bytes) +
            (size_t)elem_bytes * (nw * 64 * kBlkPST + 2 * nw * 4 * kBlk + nw * kBlk * 4 + nw * 2 * kBlk) +
-           16 + 64;
+           (size_t)8 * nw * 2 * kBlk + 8 + 16 + 64;
 }
 
 template <typename R, bool ACC>

@@ -743,6 +743,7 @@ struct BlockLds {
     R* wsum;         // [2][waves][4B] per-wave sums of the step, by step parity
     quad<R>* wprm;   // [waves][B] rotation parameters (each wave its own)
     R* wdsc;         // [waves][2B] column scales of the block pair (each wave its own)
+    double* wnrm;    // [waves][2B] squared norms of the block pair's columns (each wave its own)
     int* rflag;      // rotation made in this sweep
 };
 
@@ -760,7 +761,8 @@ __device__ __forceinline__ BlockLds<R> carve_block(char* lds, size_t off) {
     p = reinterpret_cast<R*>(b.wprm + nw * B);
     b.wdsc = p;
     p += nw * 2 * B;
-    b.rflag = reinterpret_cast<int*>(p);
+    b.wnrm = reinterpret_cast<double*>((reinterpret_cast<size_t>(p) + 7) & ~size_t(7));
+    b.rflag = reinterpret_cast<int*>(b.wnrm + nw * 2 * B);
     return b;
 }
 
@@ -800,39 +802,106 @@ __device__ __forceinline__ void block_wave_sums(const BlockLds<R>& bl, F part, i
     bl.wsum[(par * nw + wave) * 4 * B + lane] = s;
 }
 
+// The same for the inner products alone (the steps after the first of a
+// block pair's visit, whose column norms are carried by the rotations):
+// part(p) gives pair p's g_j^H g_k over the thread's rows.  Quad i < B/2
+// holds pairs i and i + B/2, so two groups of four quads are folded; the
+// wave's sums go to wsum[par][wave][4i .. 4i+3].
+template <typename R, typename F>
+__device__ __forceinline__ void block_wave_gammas(const BlockLds<R>& bl, F part, int par) {
+    constexpr int B = kBlk;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    R* wp = bl.wpart + wave * 64 * kBlkPST;
+#pragma unroll
+    for (int gi = 0; gi < 2; ++gi) {
+        R v[16];
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            const int qi = gi + 2 * b;
+            const cplx<R> x = part(qi), y = part(qi + B / 2);
+            v[4 * b + 0] = x.x;
+            v[4 * b + 1] = x.y;
+            v[4 * b + 2] = y.x;
+            v[4 * b + 3] = y.y;
+        }
+        transpose_add<1, 1>(v);
+        *reinterpret_cast<quad<R>*>(wp + lane * kBlkPST + 4 * gi) = quad<R>{v[0], v[1], v[2], v[3]};
+    }
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    // value l = 4 i + c (l < 32) of quad i = gi + 2 b is held by lanes
+    // 16 b .. 16 b + 15 at slot 4 gi + c; lanes l and l + 32 sum eight each
+    const int l = lane & 31, half = lane >> 5;
+    const int qi = l >> 2, gi = qi & 1, b = qi >> 1;
+    R s = 0;
+#pragma unroll
+    for (int h = 0; h < 8; ++h) s += wp[(b * 16 + half * 8 + h) * kBlkPST + 4 * gi + (l & 3)];
+    s = xsum<32>(s);
+    if (half == 0) bl.wsum[(par * nw + wave) * 4 * B + l] = s;
+}
+
 // After the barrier: lanes p < B of every wave sum the per-wave slots of pair
 // p, take its rotation in scaled form (scales of its columns cj, ck in the
 // wave's copy) and publish it to the wave.  Returns true if this lane's pair
-// rotated.
-template <typename R>
+// rotated.  FULL: the slots hold the four sums of block_wave_sums (the first
+// step of a visit, which meets every column of the block pair once and sets
+// the wave's copy of the squared norms); otherwise they hold the inner
+// products of block_wave_gammas and the norms come from that copy, which the
+// rotations update.
+
+template <typename R, bool TRACK>
 __device__ __forceinline__ bool block_rotations(const BlockLds<R>& bl, int par, int cj, int ck, double tol,
-                                                double floor) {
+                                                double floor, bool full) {
     constexpr int B = kBlk;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
     bool rot = false;
     if (lane < B) {
-        double s0 = 0, s1 = 0, s2 = 0, s3 = 0;
-        for (int w = 0; w < nw; ++w) {
-            const quad<R> x = *reinterpret_cast<const quad<R>*>(bl.wsum + (par * nw + w) * 4 * B + 4 * lane);
-            s0 += double(x.a);
-            s1 += double(x.b);
-            s2 += double(x.c);
-            s3 += double(x.d);
-        }
         R* dsc = bl.wdsc + wave * 2 * B;
+        double* nrm = bl.wnrm + wave * 2 * B;
         R dj = dsc[cj], dk = dsc[ck];
         const double ddj = double(dj), ddk = double(dk);
-        double al = s0 * ddj * ddj, be = s1 * ddk * ddk;
+        double al, be, s2 = 0, s3 = 0;
+        if (!TRACK || full) {
+            double s0 = 0, s1 = 0;
+            for (int w = 0; w < nw; ++w) {
+                const quad<R> x =
+                    *reinterpret_cast<const quad<R>*>(bl.wsum + (par * nw + w) * 4 * B + 4 * lane);
+                s0 += double(x.a);
+                s1 += double(x.b);
+                s2 += double(x.c);
+                s3 += double(x.d);
+            }
+            al = s0 * ddj * ddj;
+            be = s1 * ddk * ddk;
+        } else {
+            const int off = 4 * (lane & (B / 2 - 1)) + (lane < B / 2 ? 0 : 2);
+            for (int w = 0; w < nw; ++w) {
+                const R* x = bl.wsum + (par * nw + w) * 4 * B + off;
+                s2 += double(x[0]);
+                s3 += double(x[1]);
+            }
+            al = nrm[cj];
+            be = nrm[ck];
+        }
         quad<R> q;
         // a sweep of small rotations only ends the symbol's sweeps
         rot = rotation_scaled<R>(al, be, s2 * ddj * ddk, s3 * ddj * ddk, tol, floor, dj, dk, q) > 1;
         dsc[cj] = dj;
         dsc[ck] = dk;
+        if constexpr (TRACK) {
+            nrm[cj] = al;
+            nrm[ck] = be;
+        }
         bl.wprm[wave * B + lane] = q;
     }
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
     __builtin_amdgcn_wave_barrier();
     return rot;
+}
+
+template <typename R>
+__device__ __forceinline__ cplx<R> pair_gamma(cplx<R> x, cplx<R> y) {
+    return {fma(x.x, y.x, x.y * y.y), fma(x.x, y.y, -x.y * y.x)};
 }
 
 template <typename R>
@@ -900,8 +969,11 @@ __device__ void team_barrier(Team& t) {
 }
 
 // RPT rows per thread: thread t owns rows t, t + nt, ..., t + (RPT-1) nt.
-// ACC: the accumulator Q is present (singular vectors wanted).
-template <typename R, int RPT, bool ACC>
+// ACC: the accumulator Q is present (singular vectors wanted).  TRACK: only
+// the first step of a block pair's visit forms the column norms; the later
+// ones form the inner products alone and take the norms the rotations carry
+// (FP32 without the accumulator; see block_one).
+template <typename R, int RPT, bool ACC, bool TRACK>
 __device__ void block_sweeps(const LayerDesc& d, const Shared<R>& s, const BlockLds<R>& bl,
                              int max_sweeps, double tol, Team& team, int& sweeps_out,
                              bool& conv_out) {
@@ -914,6 +986,7 @@ __device__ void block_sweeps(const LayerDesc& d, const Shared<R>& s, const Block
     // step
     constexpr bool F64 = sizeof(R) == 8;
     constexpr int KI = (ACC || F64) ? 1 : 5, KC = F64 ? 1 : (ACC ? 2 : 8);
+    static_assert(!TRACK || (!ACC && !F64), "norm tracking: FP32 without the accumulator");
     static_assert((B - 1) % KI == 0 && B % KC == 0, "unrolled steps must divide a pass");
     const int tid = threadIdx.x, nt = blockDim.x;
     const int lane = tid & 63, wave = tid >> 6;
@@ -1006,25 +1079,42 @@ __device__ void block_sweeps(const LayerDesc& d, const Shared<R>& s, const Block
               for_steps([&](auto kc) __attribute__((always_inline)) {
                 constexpr int K = decltype(kc)::value;
                 const int step = step0 + K;
-                // pair p < B/2: positions (p, B-1-p) of block a, else of block b
-                block_wave_sums<R>(bl, [&](int p) {
-                    quad<R> q = {R(0), R(0), R(0), R(0)};
+                // pair p < B/2: positions (p, B-1-p) of block a, else of block b;
+                // the first step meets every column once and sets the norms
+                const bool full = !TRACK || (K == 0 && step0 == 0);
+                if (full) {
+                    block_wave_sums<R>(bl, [&](int p) {
+                        quad<R> q = {R(0), R(0), R(0), R(0)};
 #pragma unroll
-                    for (int r = 0; r < RPT; ++r) {
-                        const quad<R> x =
-                            p < B / 2 ? pair_partials(ga[r][reg_of<B, K>(p)], ga[r][reg_of<B, K>(B - 1 - p)])
-                                      : pair_partials(gb[r][reg_of<B, K>(p - B / 2)],
-                                                      gb[r][reg_of<B, K>(B - 1 - (p - B / 2))]);
-                        q = {q.a + x.a, q.b + x.b, q.c + x.c, q.d + x.d};
-                    }
-                    return q;
-                }, par);
+                        for (int r = 0; r < RPT; ++r) {
+                            const quad<R> x =
+                                p < B / 2 ? pair_partials(ga[r][reg_of<B, K>(p)], ga[r][reg_of<B, K>(B - 1 - p)])
+                                          : pair_partials(gb[r][reg_of<B, K>(p - B / 2)],
+                                                          gb[r][reg_of<B, K>(B - 1 - (p - B / 2))]);
+                            q = {q.a + x.a, q.b + x.b, q.c + x.c, q.d + x.d};
+                        }
+                        return q;
+                    }, par);
+                } else if constexpr (TRACK) {
+                    block_wave_gammas<R>(bl, [&](int p) {
+                        cplx<R> q = {R(0), R(0)};
+#pragma unroll
+                        for (int r = 0; r < RPT; ++r) {
+                            const cplx<R> x =
+                                p < B / 2 ? pair_gamma(ga[r][reg_of<B, K>(p)], ga[r][reg_of<B, K>(B - 1 - p)])
+                                          : pair_gamma(gb[r][reg_of<B, K>(p - B / 2)],
+                                                       gb[r][reg_of<B, K>(B - 1 - (p - B / 2))]);
+                            q = {q.x + x.x, q.y + x.y};
+                        }
+                        return q;
+                    }, par);
+                }
                 __syncthreads();
                 {
                     // columns of pair `lane` (lanes >= B compute nothing)
                     const int pp = lane < B / 2 ? lane : lane - B / 2, off = lane < B / 2 ? 0 : B;
                     const int cj = off + col_at<B>(pp, step), ck = off + col_at<B>(B - 1 - pp, step);
-                    rotated |= block_rotations<R>(bl, par, cj, ck, tol, floor);
+                    rotated |= block_rotations<R, TRACK>(bl, par, cj, ck, tol, floor, full);
                 }
                 par ^= 1;
                 const quad<R>* prm = bl.wprm + wave * B;
@@ -1072,20 +1162,34 @@ __device__ void block_sweeps(const LayerDesc& d, const Shared<R>& s, const Block
                   for_steps([&](auto kc) __attribute__((always_inline)) {
                     constexpr int K = decltype(kc)::value;
                     const int t = t0 + K;
-                    block_wave_sums<R>(bl, [&](int p) {
-                        quad<R> q = {R(0), R(0), R(0), R(0)};
+                    // the first step meets every column once and sets the norms
+                    const bool full = !TRACK || (K == 0 && t0 == 0);
+                    if (full) {
+                        block_wave_sums<R>(bl, [&](int p) {
+                            quad<R> q = {R(0), R(0), R(0), R(0)};
 #pragma unroll
-                        for (int r = 0; r < RPT; ++r) {
-                            const quad<R> x = pair_partials(ga[r][p], gb[r][(p + K) % B]);
-                            q = {q.a + x.a, q.b + x.b, q.c + x.c, q.d + x.d};
-                        }
-                        return q;
-                    }, par);
+                            for (int r = 0; r < RPT; ++r) {
+                                const quad<R> x = pair_partials(ga[r][p], gb[r][(p + K) % B]);
+                                q = {q.a + x.a, q.b + x.b, q.c + x.c, q.d + x.d};
+                            }
+                            return q;
+                        }, par);
+                    } else if constexpr (TRACK) {
+                        block_wave_gammas<R>(bl, [&](int p) {
+                            cplx<R> q = {R(0), R(0)};
+#pragma unroll
+                            for (int r = 0; r < RPT; ++r) {
+                                const cplx<R> x = pair_gamma(ga[r][p], gb[r][(p + K) % B]);
+                                q = {q.x + x.x, q.y + x.y};
+                            }
+                            return q;
+                        }, par);
+                    }
                     __syncthreads();
                     {
                         const int cj = lane < B ? lane : 0;
                         const int ck = B + ((cj + t) & (B - 1));
-                        rotated |= block_rotations<R>(bl, par, cj, ck, tol, floor);
+                        rotated |= block_rotations<R, TRACK>(bl, par, cj, ck, tol, floor, full);
                     }
                     par ^= 1;
                     const quad<R>* prm = bl.wprm + wave * B;
@@ -1133,7 +1237,12 @@ __device__ void block_sweeps(const LayerDesc& d, const Shared<R>& s, const Block
     conv_out = converged;
 }
 
-template <typename R, int RPT, bool ACC>
+// TRACK (block_sweeps): measured per caller.  In the blocked kernel it makes
+// the sigma-only 256 x 256 factors 10 % faster; with the accumulator, or in
+// FP64, the second form of the step in the same unrolled body spilled
+// registers (the 512 x 256 layer with vectors 1.5x slower), and inside the
+// persistent kernel it cost 6 %.
+template <typename R, int RPT, bool ACC, bool TRACK = false>
 __device__ void block_one(const SvdArgs<R>& a, char* lds, int item, char* gslot, Team& team) {
     // ACC must match the arguments: the right singular vectors (left when
     // transposed) are wanted exactly when the accumulator is kept
@@ -1149,7 +1258,7 @@ __device__ void block_one(const SvdArgs<R>& a, char* lds, int item, char* gslot,
     else __syncthreads();
     int sweeps;
     bool converged;
-    block_sweeps<R, RPT, ACC>(a.d, s, bl, a.max_sweeps, a.tol, team, sweeps, converged);
+    block_sweeps<R, RPT, ACC, TRACK>(a.d, s, bl, a.max_sweeps, a.tol, team, sweeps, converged);
     if (team.member == 0) finish<R, 64>(a, s, tg.out, tg.mirror, sweeps, converged);
     // the slot is reused for the team's next symbol: members wait for the finish
     if (team.W > 1) team_barrier(team);
