@@ -124,7 +124,7 @@ __device__ __forceinline__ int rotation_scaled(double& al, double& be, double gr
         rjk = double(dk) / double(dj);
         rkj = double(dj) / double(dk);
     }
-    const double grade = fmax(al, be) / fmin(al, be);               // >= 1 (min > floor >= 0)
+    const double lo = fmin(al, be), hi = fmax(al, be);
     const double tg = t * g2 * rg;                                    // t |gamma|
     al = fmax(al - tg, 0.0);
     be = fmax(be + tg, 0.0);
@@ -132,7 +132,7 @@ __device__ __forceinline__ int rotation_scaled(double& al, double& be, double gr
     q = {R(tr * rjk), R(ti * rjk), R(tr * rkj), R(-ti * rkj)};
     dj = R(c * double(dj));
     dk = R(c * double(dk));
-    return 16.0 * t * t * grade > tol ? 2 : 1;
+    return 16.0 * t * t * hi > tol * lo ? 2 : 1;                   // t^2 hi/lo > tol/16, no division
 }
 
 // g_j' = g_j - tau1 g_k, g_k' = g_k + tau2 g_j (see rotation_scaled).
