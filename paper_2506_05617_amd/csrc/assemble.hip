@@ -45,11 +45,13 @@ __device__ __forceinline__ void phase_d(const double* tw, const LayerDesc& d, in
 // Symbols are written once and not read back by the kernel: streaming
 // (non-temporal) stores keep them from displacing W and the twiddles in the
 // caches and write at a markedly higher rate.
+// One store of the whole complex value: two stores of its halves would each
+// write every other word of the same lines.
 template <typename R>
 __device__ __forceinline__ void store_stream(cplx<R>* dst, R re, R im) {
-    R* p = reinterpret_cast<R*>(dst);
-    __builtin_nontemporal_store(re, p);
-    __builtin_nontemporal_store(im, p + 1);
+    typedef R pair_t __attribute__((ext_vector_type(2)));
+    const pair_t v = {re, im};
+    __builtin_nontemporal_store(v, reinterpret_cast<pair_t*>(dst));
 }
 
 constexpr int kValuThetaTile = 16;
