@@ -355,9 +355,10 @@ size_t qr_region_bytes(const lfa_plan& p, int i, bool queue) {
     const lfa_layer& l = p.layers[i];
     const LayerDesc& dr = p.desc_r[i];
     LayerDesc drg = dr;
-    drg.storage = (lds_bytes_for(dr, vec, eb) > kLdsSafe) ? kGlobal : dr.storage;
-    size_t svd_r = kCounterBytes + (size_t)svd_grid(drg, dr.num_symbols) * slot_bytes(drg, vec, eb);
-    if (queue && dr.wave_qgroups > 0) svd_r = std::max(svd_r, wave_queue_bytes(dr, vec, eb, dr.wave_qgroups));
+    // the SVD of the factors keeps no accumulator (see svd_layer)
+    drg.storage = (lds_bytes_for(dr, false, eb) > kLdsSafe) ? kGlobal : dr.storage;
+    size_t svd_r = kCounterBytes + (size_t)svd_grid(drg, dr.num_symbols) * slot_bytes(drg, false, eb);
+    if (queue && dr.wave_qgroups > 0) svd_r = std::max(svd_r, wave_queue_bytes(dr, false, eb, dr.wave_qgroups));
     size_t after = qr_taps_bytes(l) + std::max(svd_r, qr_hslot_bytes(l));
     if (vec) after = std::max(after, (size_t)p.desc[i].num_canon * qr_vec_slot_bytes(p.desc[i], eb));
     return qr_rsym_bytes(l, eb) + after;
@@ -586,7 +587,7 @@ int ensure_device(lfa_plan* p, hipStream_t st = nullptr, bool check_capture = fa
             p->desc[i].storage = kGlobal;
         {
             LayerDesc& dr = p->desc_r[i];
-            const bool vec = wu || wv;
+            const bool vec = false;          // the SVD of the factors never accumulates
             if (dr.kind == 1) {
                 dr.wave_cap = wave_blocks_per_cu(dr.wave_nc, dr.wave_ml, eb, dr.threads, vec) * p->num_cus;
                 if (dr.wave_qgroups > 0)
@@ -793,16 +794,18 @@ int svd_layer(const lfa_plan* p, size_t i, const void* const* W, const void* con
             g.C = taps;
             g.hslots = rest;
             g.Rsym = reinterpret_cast<cplx<R>*>(rsym);
+            g.conj_transpose = (wu || wv) ? 1 : 0;
             hipError_t e;
             if constexpr (sizeof(R) == 4) e = launch_gram_qr_f32(g, d.num_canon, st);
             else e = launch_gram_qr_f64(g, d.num_canon, st);
             HIP_TRY(e);
             const bool vec = wu || wv;
-            // with vectors the SVD of R writes its right singular vectors over
-            // the factors (each work-group reads its own canonical factor
+            // with vectors the factors are R^H = V_R S U_R^H: its SVD needs no
+            // rotation accumulator and writes its left singular vectors, V_R,
+            // over the factors (each work-group reads its own canonical factor
             // before it writes that frequency and its mirror)
-            LFA_TRY(run_svd_layer<R>(p, p->desc_r[i], nullptr, rsym, sigma[i], nullptr,
-                                     vec ? reinterpret_cast<cplx<R>*>(rsym) : nullptr,
+            LFA_TRY(run_svd_layer<R>(p, p->desc_r[i], nullptr, rsym, sigma[i],
+                                     vec ? reinterpret_cast<cplx<R>*>(rsym) : nullptr, nullptr,
                                      info ? info + i * LFA_INFO_WORDS : nullptr, rest, nullptr, 0, 0, st,
                                      true, queue_ok, tn));
             if (vec) {
@@ -1704,10 +1707,11 @@ int lfa_plan_create(lfa_plan** out, const lfa_layer* layers, int32_t num_layers,
             const bool q = qr_applies(l, dtype, flags);
             p->qr.push_back(q ? 1 : 0);
             lfa_layer lr{N, N, 1, 1, l.n, l.m};
-            const bool vec = wu || wv;       // the SVD of R keeps V_R
-            LayerDesc dr = make_desc(lr, off[l.n], off[l.m], vec, eb, kLdsCap);
+            // the SVD of the factors never accumulates: sigma only, or the
+            // left vectors of R^H (= V_R)
+            LayerDesc dr = make_desc(lr, off[l.n], off[l.m], false, eb, kLdsCap);
             dr.num_canon = ncanon;
-            dr.wave_qgroups = qr_eligible(l, dtype, flags) ? wave_queue_reserved(dr, vec, eb) : 0;
+            dr.wave_qgroups = qr_eligible(l, dtype, flags) ? wave_queue_reserved(dr, false, eb) : 0;
             p->desc_r.push_back(dr);
         }
         p->desc_sel.back().num_canon = ncanon;

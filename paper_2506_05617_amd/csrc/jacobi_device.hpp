@@ -383,8 +383,9 @@ __device__ void finish(const SvdArgs<R>& a, const Shared<R>& s, int out_idx, int
         // Columns with sigma == 0 (they sort last) get an orthonormal
         // completion: unit vectors e_0, e_1, ... orthogonalised by two passes
         // of classical Gram-Schmidt against every accepted column, kept when
-        // the residual norm exceeds a threshold (1/2, lowered if no unit
-        // vector qualifies; some residual has norm >= 1/sqrt(M)).
+        // the residual norm exceeds a threshold (1/2, at most half the root
+        // mean square of the residuals, lowered if no unit vector qualifies;
+        // some residual has norm >= 1/sqrt(M)).
         int nz = 0;
         while (nz < N && s.sig[s.perm[N - 1 - nz]] == R(0)) ++nz;
         const int ra = N - nz;   // accepted columns, in rank order perm[0 .. ra)
@@ -394,17 +395,27 @@ __device__ void finish(const SvdArgs<R>& a, const Shared<R>& s, int out_idx, int
         // accumulator's memory: nz ra M work instead of the nz N M of
         // Gram-Schmidt, and two barriers per reflector instead of several
         // per zero column.
-        const bool householder =
+        // Without that memory (no accumulator) and with at least twice as
+        // many zero columns as accepted ones, the reflectors go to the last
+        // ra zero columns of G instead: the other zero columns are completed
+        // from them, and those last ra ones by Gram-Schmidt below.
+        const bool hh_q =
             nz >= 2 && ra >= 1 && want_right && Q != nullptr && (size_t)ra * M <= (size_t)N * ldv;
+        const bool hh_g = !hh_q && ra >= 1 && nz >= 2 * ra && nz - ra >= 2;
+        const bool householder = hh_q || hh_g;
+        const int nh = hh_q ? nz : nz - ra;        // zero columns completed from the reflectors
+        // reflector k: Q row block k, or zero column perm[N - ra + k] of G
+        auto refl = [&](int k) -> cplx<R>* {
+            return hh_q ? Q + (size_t)k * M : G + (size_t)s.perm[N - ra + k] * ldg;
+        };
         if (householder) {
-            cplx<R>* Vr = Q;   // [ra][M]
             for (int e = tid; e < ra * M; e += nt) {
                 const int k = e / M, i = e - (e / M) * M;
-                Vr[e] = G[(size_t)s.perm[k] * ldg + i];
+                refl(k)[i] = G[(size_t)s.perm[k] * ldg + i];
             }
             __syncthreads();
             for (int k = 0; k < ra; ++k) {
-                cplx<R>* v = Vr + (size_t)k * M;
+                cplx<R>* v = refl(k);
                 R part = 0;
                 for (int i = k + tid; i < M; i += nt) part = fma(v[i].x, v[i].x, fma(v[i].y, v[i].y, part));
                 const R nx = sqrt(block_sum<R>(part, s.red));
@@ -421,7 +432,7 @@ __device__ void finish(const SvdArgs<R>& a, const Shared<R>& s, int out_idx, int
                 const R beta = s.coef[k].x;
                 // H_k applied to the later accepted columns (rows >= k)
                 for (int j = k + 1 + group; j < ra; j += ngroups) {
-                    const cplx<R>* c = Vr + (size_t)j * M;
+                    const cplx<R>* c = refl(j);
                     cplx<R> w = {R(0), R(0)};
                     for (int i = k + lane; i < M; i += L) {
                         w.x = fma(v[i].x, c[i].x, fma(v[i].y, c[i].y, w.x));
@@ -437,20 +448,21 @@ __device__ void finish(const SvdArgs<R>& a, const Shared<R>& s, int out_idx, int
                     if (i < k) continue;
                     const cplx<R> w = s.coef[j], vi = v[i];
                     const R fr = beta * (w.x * vi.x - w.y * vi.y), fi = beta * (w.x * vi.y + w.y * vi.x);
-                    Vr[(size_t)j * M + i] = {Vr[(size_t)j * M + i].x - fr, Vr[(size_t)j * M + i].y - fi};
+                    cplx<R>* cj = refl(j);
+                    cj[i] = {cj[i].x - fr, cj[i].y - fi};
                 }
                 __syncthreads();
             }
             // zero column z: H_0 ... H_{ra-1} e_{ra+z}
-            for (int e = tid; e < nz * M; e += nt) {
+            for (int e = tid; e < nh * M; e += nt) {
                 const int z = e / M, i = e - (e / M) * M;
                 G[(size_t)s.perm[ra + z] * ldg + i] = {R(i == ra + z ? 1 : 0), R(0)};
             }
             __syncthreads();
             for (int k = ra - 1; k >= 0; --k) {
-                const cplx<R>* v = Vr + (size_t)k * M;
+                const cplx<R>* v = refl(k);
                 const R beta = s.coef[k].x;
-                for (int z = group; z < nz; z += ngroups) {
+                for (int z = group; z < nh; z += ngroups) {
                     const cplx<R>* x = G + (size_t)s.perm[ra + z] * ldg;
                     cplx<R> w = {R(0), R(0)};
                     for (int i = k + lane; i < M; i += L) {
@@ -462,7 +474,7 @@ __device__ void finish(const SvdArgs<R>& a, const Shared<R>& s, int out_idx, int
                     if (lane == 0) s.coef[ra + z] = w;
                 }
                 __syncthreads();
-                for (int e = tid; e < nz * M; e += nt) {
+                for (int e = tid; e < nh * M; e += nt) {
                     const int z = e / M, i = e - (e / M) * M;
                     if (i < k) continue;
                     const cplx<R> w = s.coef[ra + z], vi = v[i];
@@ -474,8 +486,12 @@ __device__ void finish(const SvdArgs<R>& a, const Shared<R>& s, int out_idx, int
         }
         int cand = 0;
         R thresh = R(0.5);
-        for (int zc = householder ? N : N - nz; zc < N; ++zc) {
+        for (int zc = hh_q ? N : (hh_g ? N - ra : N - nz); zc < N; ++zc) {
             const int jz = s.perm[zc];
+            // zc columns are accepted: the unit vectors' residuals have mean
+            // square (M - zc) / M, so some residual is at least that large
+            // and half of it is accepted without a scan of every candidate
+            thresh = fmin(thresh, R(0.5) * sqrt(R(M - zc > 1 ? M - zc : 1) / R(M)));
             bool done = false;
             for (int tries = 0; !done && tries < 4 * M; ++tries) {
                 if (cand == M) {
@@ -1242,8 +1258,11 @@ __device__ void block_sweeps(const LayerDesc& d, const Shared<R>& s, const Block
 // FP64, the second form of the step in the same unrolled body spilled
 // registers (the 512 x 256 layer with vectors 1.5x slower), and inside the
 // persistent kernel it cost 6 %.
+// Always inlined: as a called function its arguments (the layer
+// description in particular) are read through memory in the loops instead of
+// from scalar registers, which measured 10 % slower in the persistent kernel.
 template <typename R, int RPT, bool ACC, bool TRACK = false>
-__device__ void block_one(const SvdArgs<R>& a, char* lds, int item, char* gslot, Team& team) {
+__device__ __forceinline__ void block_one(const SvdArgs<R>& a, char* lds, int item, char* gslot, Team& team) {
     // ACC must match the arguments: the right singular vectors (left when
     // transposed) are wanted exactly when the accumulator is kept
     bool cj;

@@ -419,6 +419,7 @@ struct GramArgs {
     double* C;                  // [(2kh-1)(2kw-1)][N][N]
     void* hslots;               // [items][N][N] complex double
     cplx<R>* Rsym;              // [n*m][N][N]; canonical frequencies written
+    int conj_transpose;         // write R^H instead of R
 };
 size_t gram_cholesky_lds_bytes(int N, int kh, int kw);
 
@@ -432,7 +433,7 @@ struct QrVecArgs {
     int M, N, transposed;
     int tw_n, tw_m;
     const double* tw;
-    const cplx<R>* VR;          // [n*m][N][N] right singular vectors of R
+    const cplx<R>* VR;          // [n*m][N][N] right singular vectors of R (left ones of R^H)
     const R* sigma;             // [n*m][N] singular values of R (same column order)
     char* slots;                // [items] slots of slot_bytes
     long long slot_bytes;

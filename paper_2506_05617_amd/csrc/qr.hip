@@ -103,7 +103,8 @@ __global__ void __launch_bounds__(256) gram_taps_kernel(GramArgs<R> g) {
 
 // One work-group per decomposed frequency: H_k into its slot (upper
 // triangle, FP64), then the Cholesky factor R (R^H R = H, upper) into the
-// layer's R symbols [n*m][N][N] (FP32 or FP64, zeros below the diagonal).
+// layer's R symbols [n*m][N][N] (FP32 or FP64, zeros below the diagonal),
+// or its conjugate transpose R^H (lower) when g.conj_transpose is set.
 template <typename R>
 __global__ void __launch_bounds__(256) gram_cholesky_kernel(GramArgs<R> g) {
     extern __shared__ __align__(16) char lds_raw[];
@@ -185,11 +186,12 @@ __global__ void __launch_bounds__(256) gram_cholesky_kernel(GramArgs<R> g) {
             }
             __syncthreads();
         }
-        // rows of R (zeros left of the diagonal)
+        // rows of R (zeros left of the diagonal), or columns of R^H
         for (int x = threadIdx.x; x < b * N; x += blockDim.x) {
             const int r = x / N, c = x - (x / N) * N;
             const cplx<double> v = c >= k0 + r ? P[(size_t)r * N + (c - k0)] : cplx<double>{0, 0};
-            Rk[(size_t)(k0 + r) * N + c] = {R(v.x), R(v.y)};
+            if (g.conj_transpose) Rk[(size_t)c * N + k0 + r] = {R(v.x), R(-v.y)};
+            else Rk[(size_t)(k0 + r) * N + c] = {R(v.x), R(v.y)};
         }
         // trailing update of the upper triangle: H[i][j] -= sum_r conj(P[r][i]) P[r][j]
         const int t0 = k0 + b, tw = N - t0;
@@ -219,7 +221,9 @@ constexpr int kQrChunk = 16;     // columns c of G (rows of V) per staged chunk
 // accumulates rows r0 + 4 rg + u (u < 4) and columns j0 + cg + 16 w (w < NW).
 // Y goes column-major into the item's slot, as the working matrix of the
 // finish; the (row tile 0, column tile 0) work-group also copies V_R into
-// the slot's accumulator part.
+// the slot's accumulator part.  V_R comes from the SVD of R^H, whose left
+// singular vectors (normalised final columns, no rotation accumulator) are
+// the right ones of R.
 template <typename R, int NW>
 __global__ void __launch_bounds__(256) qr_left_kernel(QrVecArgs<R> q) {
     extern __shared__ __align__(16) char lds_raw[];
