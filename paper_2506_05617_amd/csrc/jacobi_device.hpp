@@ -1253,11 +1253,11 @@ __device__ void block_sweeps(const LayerDesc& d, const Shared<R>& s, const Block
     conv_out = converged;
 }
 
-// TRACK (block_sweeps): measured per caller.  In the blocked kernel it makes
-// the sigma-only 256 x 256 factors 10 % faster; with the accumulator, or in
-// FP64, the second form of the step in the same unrolled body spilled
-// registers (the 512 x 256 layer with vectors 1.5x slower), and inside the
-// persistent kernel it cost 6 %.
+// TRACK (block_sweeps): FP32 without the accumulator.  It makes the
+// sigma-only 256 x 256 factors 10 % faster and the persistent launch of the
+// ResNet-18 gradient 7 %; with the accumulator, or in FP64, the second form
+// of the step in the same unrolled body spilled registers (the 512 x 256
+// layer with vectors ran 1.5x slower).
 // Always inlined: as a called function its arguments (the layer
 // description in particular) are read through memory in the loops instead of
 // from scalar registers, which measured 10 % slower in the persistent kernel.

@@ -89,8 +89,9 @@ __global__ void __launch_bounds__(256) persistent_kernel(PersistentArgs<R> pa_ar
             team.err = pa.team_counters + 4 * pa.num_teams;
             team.target = 0;
             char* gslot = a.gws + (size_t)w.item * a.slot_bytes;
-            if (a.d.M > 256) block_one<R, 2, ACC>(a, lds, w.item, gslot, team);
-            else block_one<R, 1, ACC>(a, lds, w.item, gslot, team);
+            constexpr bool TRACK = !ACC && sizeof(R) == 4;
+            if (a.d.M > 256) block_one<R, 2, ACC, TRACK>(a, lds, w.item, gslot, team);
+            else block_one<R, 1, ACC, TRACK>(a, lds, w.item, gslot, team);
         }
     }
 }
