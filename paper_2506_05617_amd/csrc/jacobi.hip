@@ -12,7 +12,9 @@ using namespace dev;
 // Grid = teams x W work-groups, all resident at once when W > 1 (the host
 // sizes the grid from the occupancy of this kernel).  Team t owns slot t and
 // works on items item0 + t, item0 + t + teams, ... below item_end.
-template <typename R, bool ACC>
+// DUAL: the launch has no teams (W = 1), and each cross step of the sweeps
+// takes two block pairs (FP32 without the accumulator).
+template <typename R, bool ACC, bool DUAL = false>
 __global__ void __launch_bounds__(512) block_kernel(SvdArgs<R> a, int W, int item0, int item_end,
                                                     int32_t* counters) {
     extern __shared__ __align__(16) char lds[];
@@ -27,7 +29,7 @@ __global__ void __launch_bounds__(512) block_kernel(SvdArgs<R> a, int W, int ite
     team.target = 0;
     char* gslot = a.gws + (size_t)tix * a.slot_bytes;
     const int count = min(item_count(a), item_end);
-    for (int item = item0 + tix; item < count; item += teams) block_one<R, 1, ACC, !ACC && sizeof(R) == 4>(a, lds, item, gslot, team);
+    for (int item = item0 + tix; item < count; item += teams) block_one<R, 1, ACC, !ACC && sizeof(R) == 4, DUAL>(a, lds, item, gslot, team);
 }
 
 template <typename R, int L>
@@ -100,21 +102,30 @@ size_t block_lds_bytes(const LayerDesc& d, bool accumulate, int elem_bytes) {
     const int nw = d.threads / 64;
     // BlockLds: wpart, wsum (two buffers), wprm (quads), wdsc, wnrm (FP64), rflag
     return lds_bytes_for(dg, accumulate, elem_bytes) +
-           (size_t)elem_bytes * (nw * 64 * kBlkPST + 2 * nw * 4 * kBlk + nw * kBlk * 4 + nw * 2 * kBlk) +
-           (size_t)8 * nw * 2 * kBlk + 8 + 16 + 64;
+           (size_t)elem_bytes * (nw * 64 * kBlkPST + 2 * nw * kWsumW + nw * kPrmW * 4 + nw * kDscW) +
+           (size_t)8 * nw * kDscW + 8 + 16 + 64;
+}
+
+template <typename R, bool ACC, bool DUAL>
+hipError_t launch_block_k(const SvdArgs<R>& a, int teams, int W, int item0, int item_end, int32_t* counters,
+                          hipStream_t st) {
+    const size_t lds = block_lds_bytes(a.d, ACC, sizeof(R));
+    hipError_t e = allow_lds(block_kernel<R, ACC, DUAL>, lds);
+    if (e != hipSuccess) return e;
+    e = launch_fill_i32(counters, 0, 4LL * teams + 4, st);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((block_kernel<R, ACC, DUAL>), dim3(teams * W), dim3(a.d.threads), lds, st, a, W, item0,
+                       item_end, counters);
+    return hipGetLastError();
 }
 
 template <typename R, bool ACC>
 hipError_t launch_block_t(const SvdArgs<R>& a, int teams, int W, int item0, int item_end, int32_t* counters,
                           hipStream_t st) {
-    const size_t lds = block_lds_bytes(a.d, ACC, sizeof(R));
-    hipError_t e = allow_lds(block_kernel<R, ACC>, lds);
-    if (e != hipSuccess) return e;
-    e = launch_fill_i32(counters, 0, 4LL * teams + 4, st);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((block_kernel<R, ACC>), dim3(teams * W), dim3(a.d.threads), lds, st, a, W, item0,
-                       item_end, counters);
-    return hipGetLastError();
+    if constexpr (!ACC && sizeof(R) == 4) {
+        if (W == 1) return launch_block_k<R, ACC, true>(a, teams, W, item0, item_end, counters, st);
+    }
+    return launch_block_k<R, ACC, false>(a, teams, W, item0, item_end, counters, st);
 }
 
 template <typename R>
@@ -133,6 +144,15 @@ int block_resident_t(const LayerDesc& d) {
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, block_kernel<R, ACC>, d.threads, lds) !=
         hipSuccess)
         return 0;
+    if constexpr (!ACC && sizeof(R) == 4) {
+        // the launch without teams runs the dual kernel: the fewer of the two
+        int per_cu2 = 0;
+        if (allow_lds(block_kernel<R, ACC, true>, lds) != hipSuccess ||
+            hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu2, block_kernel<R, ACC, true>, d.threads, lds) !=
+                hipSuccess)
+            return 0;
+        per_cu = std::min(per_cu, per_cu2);
+    }
     if (hipGetDevice(&dev) != hipSuccess ||
         hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
         return 0;

@@ -752,14 +752,18 @@ __device__ __forceinline__ void for_steps(F&& f, std::integer_sequence<int, I...
 // ---------------------------------------------------------------------------
 constexpr int kBlk = 16;                  // columns per block
 constexpr int kBlkPST = kBlk + 4;         // folded partials per lane (4B / 4) + padding
+// Per-wave LDS areas hold up to two block pairs (the dual cross pass):
+constexpr int kWsumW = 8 * kBlk;          // floats of sums per wave and parity
+constexpr int kPrmW = 2 * kBlk;           // rotation parameters per wave
+constexpr int kDscW = 4 * kBlk;           // column scales (and norms) per wave
 
 template <typename R>
 struct BlockLds {
     R* wpart;        // [waves][64][kBlkPST] folded partials of each wave
-    R* wsum;         // [2][waves][4B] per-wave sums of the step, by step parity
-    quad<R>* wprm;   // [waves][B] rotation parameters (each wave its own)
-    R* wdsc;         // [waves][2B] column scales of the block pair (each wave its own)
-    double* wnrm;    // [waves][2B] squared norms of the block pair's columns (each wave its own)
+    R* wsum;         // [2][waves][kWsumW] per-wave sums of the step, by step parity
+    quad<R>* wprm;   // [waves][kPrmW] rotation parameters (each wave its own)
+    R* wdsc;         // [waves][kDscW] column scales of the block pair(s) (each wave its own)
+    double* wnrm;    // [waves][kDscW] squared norms of those columns (each wave its own)
     int* rflag;      // rotation made in this sweep
 };
 
@@ -772,13 +776,13 @@ __device__ __forceinline__ BlockLds<R> carve_block(char* lds, size_t off) {
     b.wpart = p;
     p += nw * 64 * kBlkPST;
     b.wsum = p;
-    p += 2 * nw * 4 * B;
+    p += 2 * nw * kWsumW;
     b.wprm = reinterpret_cast<quad<R>*>(p);
-    p = reinterpret_cast<R*>(b.wprm + nw * B);
+    p = reinterpret_cast<R*>(b.wprm + nw * kPrmW);
     b.wdsc = p;
-    p += nw * 2 * B;
+    p += nw * kDscW;
     b.wnrm = reinterpret_cast<double*>((reinterpret_cast<size_t>(p) + 7) & ~size_t(7));
-    b.rflag = reinterpret_cast<int*>(b.wnrm + nw * 2 * B);
+    b.rflag = reinterpret_cast<int*>(b.wnrm + nw * kDscW);
     return b;
 }
 
@@ -788,7 +792,7 @@ __device__ __forceinline__ BlockLds<R> carve_block(char* lds, size_t off) {
 // stages (lane^32, lane^16): lane l then holds pair gi + 4 (l / 16), summed
 // over four rows; the 16 lanes of each quarter are summed through LDS.
 template <typename R, typename F>
-__device__ __forceinline__ void block_wave_sums(const BlockLds<R>& bl, F part, int par) {
+__device__ __forceinline__ void block_wave_sums(const BlockLds<R>& bl, F part, int par, int off = 0) {
     constexpr int B = kBlk;
     static_assert(B == 16, "the fold below assumes four groups of four pairs");
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
@@ -815,7 +819,7 @@ __device__ __forceinline__ void block_wave_sums(const BlockLds<R>& bl, F part, i
     R s = 0;
 #pragma unroll
     for (int h = 0; h < 16; ++h) s += wp[(blk * 16 + h) * kBlkPST + slot];
-    bl.wsum[(par * nw + wave) * 4 * B + lane] = s;
+    bl.wsum[(par * nw + wave) * kWsumW + off + lane] = s;
 }
 
 // The same for the inner products alone (the steps after the first of a
@@ -853,7 +857,7 @@ __device__ __forceinline__ void block_wave_gammas(const BlockLds<R>& bl, F part,
 #pragma unroll
     for (int h = 0; h < 8; ++h) s += wp[(b * 16 + half * 8 + h) * kBlkPST + 4 * gi + (l & 3)];
     s = xsum<32>(s);
-    if (half == 0) bl.wsum[(par * nw + wave) * 4 * B + l] = s;
+    if (half == 0) bl.wsum[(par * nw + wave) * kWsumW + l] = s;
 }
 
 // After the barrier: lanes p < B of every wave sum the per-wave slots of pair
@@ -872,8 +876,8 @@ __device__ __forceinline__ bool block_rotations(const BlockLds<R>& bl, int par, 
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
     bool rot = false;
     if (lane < B) {
-        R* dsc = bl.wdsc + wave * 2 * B;
-        double* nrm = bl.wnrm + wave * 2 * B;
+        R* dsc = bl.wdsc + wave * kDscW;
+        double* nrm = bl.wnrm + wave * kDscW;
         R dj = dsc[cj], dk = dsc[ck];
         const double ddj = double(dj), ddk = double(dk);
         double al, be, s2 = 0, s3 = 0;
@@ -881,7 +885,7 @@ __device__ __forceinline__ bool block_rotations(const BlockLds<R>& bl, int par, 
             double s0 = 0, s1 = 0;
             for (int w = 0; w < nw; ++w) {
                 const quad<R> x =
-                    *reinterpret_cast<const quad<R>*>(bl.wsum + (par * nw + w) * 4 * B + 4 * lane);
+                    *reinterpret_cast<const quad<R>*>(bl.wsum + (par * nw + w) * kWsumW + 4 * lane);
                 s0 += double(x.a);
                 s1 += double(x.b);
                 s2 += double(x.c);
@@ -892,7 +896,7 @@ __device__ __forceinline__ bool block_rotations(const BlockLds<R>& bl, int par, 
         } else {
             const int off = 4 * (lane & (B / 2 - 1)) + (lane < B / 2 ? 0 : 2);
             for (int w = 0; w < nw; ++w) {
-                const R* x = bl.wsum + (par * nw + w) * 4 * B + off;
+                const R* x = bl.wsum + (par * nw + w) * kWsumW + off;
                 s2 += double(x[0]);
                 s3 += double(x[1]);
             }
@@ -908,7 +912,61 @@ __device__ __forceinline__ bool block_rotations(const BlockLds<R>& bl, int par, 
             nrm[cj] = al;
             nrm[ck] = be;
         }
-        bl.wprm[wave * B + lane] = q;
+        bl.wprm[wave * kPrmW + lane] = q;
+    }
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    return rot;
+}
+
+// The dual cross step: two block pairs (sets 0 and 1) at once, 2B pairs.
+// Lane l < 2B takes pair p = l mod B of set l / B: columns p of block a and
+// (p + t) mod B of block b, at 2B (set) + p and 2B (set) + B + (p + t) mod B
+// of the wave's scales and norms.  FULL: the slots hold two block_wave_sums
+// results (set s at offset 4B s); otherwise one, whose quad p holds the inner
+// products of pair p of set 0 and of set 1.
+template <typename R>
+__device__ __forceinline__ bool block_rotations_dual(const BlockLds<R>& bl, int par, int t, double tol,
+                                                     double floor, bool full) {
+    constexpr int B = kBlk;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    bool rot = false;
+    if (lane < 2 * B) {
+        const int set = lane / B, p = lane & (B - 1);
+        const int cj = 2 * B * set + p, ck = 2 * B * set + B + ((p + t) & (B - 1));
+        R* dsc = bl.wdsc + wave * kDscW;
+        double* nrm = bl.wnrm + wave * kDscW;
+        R dj = dsc[cj], dk = dsc[ck];
+        const double ddj = double(dj), ddk = double(dk);
+        double al, be, s2 = 0, s3 = 0;
+        if (full) {
+            double s0 = 0, s1 = 0;
+            for (int w = 0; w < nw; ++w) {
+                const quad<R> x = *reinterpret_cast<const quad<R>*>(bl.wsum + (par * nw + w) * kWsumW +
+                                                                     4 * B * set + 4 * p);
+                s0 += double(x.a);
+                s1 += double(x.b);
+                s2 += double(x.c);
+                s3 += double(x.d);
+            }
+            al = s0 * ddj * ddj;
+            be = s1 * ddk * ddk;
+        } else {
+            for (int w = 0; w < nw; ++w) {
+                const R* x = bl.wsum + (par * nw + w) * kWsumW + 4 * p + 2 * set;
+                s2 += double(x[0]);
+                s3 += double(x[1]);
+            }
+            al = nrm[cj];
+            be = nrm[ck];
+        }
+        quad<R> q;
+        rot = rotation_scaled<R>(al, be, s2 * ddj * ddk, s3 * ddj * ddk, tol, floor, dj, dk, q) > 1;
+        dsc[cj] = dj;
+        dsc[ck] = dk;
+        nrm[cj] = al;
+        nrm[ck] = be;
+        bl.wprm[wave * kPrmW + lane] = q;
     }
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
     __builtin_amdgcn_wave_barrier();
@@ -989,8 +1047,8 @@ __device__ void team_barrier(Team& t) {
 // the first step of a block pair's visit forms the column norms; the later
 // ones form the inner products alone and take the norms the rotations carry
 // (FP32 without the accumulator; see block_one).
-template <typename R, int RPT, bool ACC, bool TRACK>
-__device__ void block_sweeps(const LayerDesc& d, const Shared<R>& s, const BlockLds<R>& bl,
+template <typename R, int RPT, bool ACC, bool TRACK, bool DUAL = false>
+__device__ __forceinline__ void block_sweeps(const LayerDesc& d, const Shared<R>& s, const BlockLds<R>& bl,
                              int max_sweeps, double tol, Team& team, int& sweeps_out,
                              bool& conv_out) {
     constexpr int B = kBlk;
@@ -1003,6 +1061,7 @@ __device__ void block_sweeps(const LayerDesc& d, const Shared<R>& s, const Block
     constexpr bool F64 = sizeof(R) == 8;
     constexpr int KI = (ACC || F64) ? 1 : 5, KC = F64 ? 1 : (ACC ? 2 : 8);
     static_assert(!TRACK || (!ACC && !F64), "norm tracking: FP32 without the accumulator");
+    static_assert(!DUAL || (TRACK && RPT == 1), "dual cross steps: tracked norms, one row per thread");
     static_assert((B - 1) % KI == 0 && B % KC == 0, "unrolled steps must divide a pass");
     const int tid = threadIdx.x, nt = blockDim.x;
     const int lane = tid & 63, wave = tid >> 6;
@@ -1019,7 +1078,7 @@ __device__ void block_sweeps(const LayerDesc& d, const Shared<R>& s, const Block
         qrow[r] = acc && rows[r] < N;
     }
     cplx<R> ga[RPT][B], gb[RPT][B], va[ACC ? RPT : 1][ACC ? B : 1], vb[ACC ? RPT : 1][ACC ? B : 1];
-    R* dsc = bl.wdsc + wave * 2 * B;
+    R* dsc = bl.wdsc + wave * kDscW;
     int par = 0;                 // step parity (per-wave sums buffer)
     // block pair in: unit scales (this wave's copy)
     auto load2 = [&](int ba, int bb) {
@@ -1133,7 +1192,7 @@ __device__ void block_sweeps(const LayerDesc& d, const Shared<R>& s, const Block
                     rotated |= block_rotations<R, TRACK>(bl, par, cj, ck, tol, floor, full);
                 }
                 par ^= 1;
-                const quad<R>* prm = bl.wprm + wave * B;
+                const quad<R>* prm = bl.wprm + wave * kPrmW;
 #pragma unroll
                 for (int p = 0; p < B / 2; ++p) {
                     const quad<R> ra = prm[p], rb = prm[B / 2 + p];
@@ -1165,6 +1224,91 @@ __device__ void block_sweeps(const LayerDesc& d, const Shared<R>& s, const Block
         }
         if (W > 1) team_barrier(team);
         // ---- cross passes: round-robin over block pairs
+        if constexpr (DUAL) {
+            // Two block pairs of the outer step at once: each step forms the
+            // 2B inner products of both, folds them in one pass, takes one
+            // work-group barrier and evaluates all 2B rotations, so the fixed
+            // cost of a step (folds, barrier, the FP64 rotation parameters)
+            // is shared by twice the work.  A missing second pair is zeros
+            // (no rotation) and is not stored.
+            constexpr int K2 = 8;
+            for (int os = 0; os < NBP - 1; ++os) {
+                for (int bp = member; bp < NBP / 2; bp += 2 * W) {
+                    int ba0, bb0, ba1 = NB, bb1 = NB;
+                    rr_pair(bp, os, NBP, ba0, bb0);
+                    if (bp + W < NBP / 2) rr_pair(bp + W, os, NBP, ba1, bb1);
+                    bool has0 = ba0 < NB && bb0 < NB, has1 = ba1 < NB && bb1 < NB;
+                    if (!has0) {
+                        ba0 = ba1;
+                        bb0 = bb1;
+                        has0 = has1;
+                        has1 = false;
+                    }
+                    if (!has0) continue;
+                    cplx<R> ga2[2][B], gb2[2][B];
+                    if (lane < 2 * kBlk * 2) dsc[lane] = R(1);
+                    load_block(s.G, d.ldg, ba0, N, rows[0], grow[0], ga2[0]);
+                    load_block(s.G, d.ldg, bb0, N, rows[0], grow[0], gb2[0]);
+                    load_block(s.G, d.ldg, ba1, N, rows[0], grow[0] && has1, ga2[1]);
+                    load_block(s.G, d.ldg, bb1, N, rows[0], grow[0] && has1, gb2[1]);
+                    for (int t0 = 0; t0 < B; t0 += K2) {
+                      for_steps([&](auto kc) __attribute__((always_inline)) {
+                        constexpr int K = decltype(kc)::value;
+                        const int t = t0 + K;
+                        const bool full = (K == 0 && t0 == 0);
+                        if (full) {
+#pragma unroll
+                            for (int st = 0; st < 2; ++st)
+                                block_wave_sums<R>(bl, [&](int p) {
+                                    return pair_partials(ga2[st][p], gb2[st][(p + K) % B]);
+                                }, par, 4 * B * st);
+                        } else {
+                            block_wave_sums<R>(bl, [&](int p) {
+                                const cplx<R> x = pair_gamma(ga2[0][p], gb2[0][(p + K) % B]);
+                                const cplx<R> y = pair_gamma(ga2[1][p], gb2[1][(p + K) % B]);
+                                return quad<R>{x.x, x.y, y.x, y.y};
+                            }, par);
+                        }
+                        __syncthreads();
+                        rotated |= block_rotations_dual<R>(bl, par, t, tol, floor, full);
+                        par ^= 1;
+                        const quad<R>* prm = bl.wprm + wave * kPrmW;
+                        // parameters read in groups of 8 pairs, so that the
+                        // compiler does not hold all 2B of them at once
+#pragma unroll
+                        for (int st = 0; st < 2; ++st)
+#pragma unroll
+                            for (int p0 = 0; p0 < B; p0 += 8) {
+#pragma unroll
+                                for (int p = p0; p < p0 + 8; ++p) {
+                                    const quad<R> rr = prm[B * st + p];
+                                    rot_apply_scaled(ga2[st][p], gb2[st][(p + K) % B], rr.a, rr.b, rr.c, rr.d);
+                                }
+                                __builtin_amdgcn_sched_barrier(0);
+                            }
+                      }, std::make_integer_sequence<int, K2>{});
+                      shift_positions_by<B, K2>(gb2[0]);
+                      shift_positions_by<B, K2>(gb2[1]);
+                    }
+                    // fold the scales and store (block b is back in order)
+                    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+                    __builtin_amdgcn_wave_barrier();
+#pragma unroll
+                    for (int st = 0; st < 2; ++st)
+#pragma unroll
+                        for (int k = 0; k < B; ++k) {
+                            const R fa = dsc[2 * B * st + k], fb = dsc[2 * B * st + B + k];
+                            ga2[st][k] = {ga2[st][k].x * fa, ga2[st][k].y * fa};
+                            gb2[st][k] = {gb2[st][k].x * fb, gb2[st][k].y * fb};
+                        }
+                    store_block(s.G, d.ldg, ba0, N, rows[0], grow[0], ga2[0]);
+                    store_block(s.G, d.ldg, bb0, N, rows[0], grow[0], gb2[0]);
+                    store_block(s.G, d.ldg, ba1, N, rows[0], grow[0] && has1, ga2[1]);
+                    store_block(s.G, d.ldg, bb1, N, rows[0], grow[0] && has1, gb2[1]);
+                }
+                if (W > 1 && os < NBP - 2) team_barrier(team);
+            }
+        } else
         for (int os = 0; os < NBP - 1; ++os) {
             for (int bp = member; bp < NBP / 2; bp += W) {
                 int ba, bb;
@@ -1208,7 +1352,7 @@ __device__ void block_sweeps(const LayerDesc& d, const Shared<R>& s, const Block
                         rotated |= block_rotations<R, TRACK>(bl, par, cj, ck, tol, floor, full);
                     }
                     par ^= 1;
-                    const quad<R>* prm = bl.wprm + wave * B;
+                    const quad<R>* prm = bl.wprm + wave * kPrmW;
 #pragma unroll
                     for (int p = 0; p < B; ++p) {
                         const quad<R> rr = prm[p];
@@ -1261,7 +1405,8 @@ __device__ void block_sweeps(const LayerDesc& d, const Shared<R>& s, const Block
 // Always inlined: as a called function its arguments (the layer
 // description in particular) are read through memory in the loops instead of
 // from scalar registers, which measured 10 % slower in the persistent kernel.
-template <typename R, int RPT, bool ACC, bool TRACK = false>
+// DUAL: two block pairs per cross step (launches without teams, W = 1).
+template <typename R, int RPT, bool ACC, bool TRACK = false, bool DUAL = false>
 __device__ __forceinline__ void block_one(const SvdArgs<R>& a, char* lds, int item, char* gslot, Team& team) {
     // ACC must match the arguments: the right singular vectors (left when
     // transposed) are wanted exactly when the accumulator is kept
@@ -1277,7 +1422,7 @@ __device__ __forceinline__ void block_one(const SvdArgs<R>& a, char* lds, int it
     else __syncthreads();
     int sweeps;
     bool converged;
-    block_sweeps<R, RPT, ACC, TRACK>(a.d, s, bl, a.max_sweeps, a.tol, team, sweeps, converged);
+    block_sweeps<R, RPT, ACC, TRACK, DUAL>(a.d, s, bl, a.max_sweeps, a.tol, team, sweeps, converged);
     if (team.member == 0) finish<R, 64>(a, s, tg.out, tg.mirror, sweeps, converged);
     // the slot is reused for the team's next symbol: members wait for the finish
     if (team.W > 1) team_barrier(team);
