@@ -51,7 +51,7 @@ PEAK_HBM_GBS = 8000.0
 # profiles/wave_queue_kernel_single_layer_64x64_uv.md (FETCH_SIZE x 2.00 +
 # WRITE_SIZE x 1.00, calibrated with a copy of known size), valid only for the
 # kernel source they were taken on.
-HEAD_TRAFFIC = {"bytes": 157.12e6 + 429.06e6, "source_hash": "aaf2eaf782a12288",
+HEAD_TRAFFIC = {"bytes": 157.16e6 + 429.06e6, "source_hash": "8c78eb31be5d20f6",
                 "files": ("jacobi_device.hpp", "jacobi_wave.hip", "lfa_internal.hpp", "api.cpp")}
 
 
