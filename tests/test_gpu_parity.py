@@ -927,6 +927,54 @@ def test_graded_columns_relative_accuracy(case, monkeypatch):
     check_projectors(s_r, u_r, v_r, Ug, Vg, torch.float32, f"graded {case}")
 
 
+DUAL_CASES = [
+    # c_out, c_in, kh, n, m, vectors: more than 256 canonical symbols of more
+    # than 64 rows, so the blocked kernel runs without teams and takes two
+    # block pairs per cross step (LFA_QR=0)
+    (160, 96, 1, 24, 24, False),    # 6 column blocks: 3 pairs per outer step, one step with one pair
+    (224, 200, 1, 24, 24, False),   # 13 blocks, the last one partial (8 columns), a padded block
+    (160, 96, 1, 24, 24, True),     # U only: the accumulator-free side, still dual
+]
+
+
+@pytest.mark.parametrize("case", DUAL_CASES)
+def test_blocked_dual_cross_steps(case, monkeypatch):
+    """The blocked kernel's dual cross steps (two block pairs per step) with
+    an odd number of block pairs per outer step and a partial last block:
+    sigma over the whole grid against the oracle; with U, orthonormality of
+    U and, gauge-free, (A^H U)^H (A^H U) = S^2 on sampled symbols."""
+    c_out, c_in, kh, n, m, vectors = case
+    banner(f"dual {case}")
+    L, W = workloads.random_layer(c_out, c_in, kh, kh, n, m, seed=59)
+    spec = lfa().LayerSpec(c_out, c_in, kh, kh, n, m)
+    monkeypatch.setenv("LFA_QR", "0")
+    plan = lfa().Plan([spec], want_u=vectors)
+    assert not plan.preconditioned(0)
+    S, U, V, info = plan.svd([_w(W)])
+    torch.cuda.synchronize()
+    assert plan.info_status(info) == 0
+    W64 = W.astype(np.float64)
+    S_ref = oracle.lfa_svd(W64, n, m)
+    e = oracle.sigma_error(to_np(S[0]), S_ref)
+    print(f"[dual] {case}: sigma error {e:.2e}", flush=True)
+    assert e <= 1e-5
+    if vectors:
+        fr = _sample(n, m, 6, 60)
+        A = oracle.symbols(W64, n, m, fr)
+        Sg = to_np(S[0])[fr[:, 0], fr[:, 1]].astype(np.float64)
+        Ug = to_np(U[0])[fr[:, 0], fr[:, 1]].astype(np.complex128)
+        r = Sg.shape[-1]
+        ou = np.max(np.abs(np.conj(np.swapaxes(Ug, -1, -2)) @ Ug - np.eye(r)))
+        assert ou <= 1e-5, f"U orthonormality {ou:.3e}"
+        X = np.conj(np.swapaxes(A, -1, -2)) @ Ug                       # A^H U = V S
+        Gm = np.conj(np.swapaxes(X, -1, -2)) @ X
+        D = np.zeros_like(Gm)
+        idx = np.arange(r)
+        D[..., idx, idx] = Sg ** 2
+        err = np.max(np.abs(Gm - D)) / np.max(Sg[..., 0]) ** 2
+        assert err <= 1e-5, f"(A^H U)^H (A^H U) - S^2: {err:.3e}"
+
+
 # ------------------------------------------------- rank-deficient symbols --
 
 RANK_DEFICIENT_CASES = [
