@@ -107,7 +107,7 @@ def run_strided(L, stride, W, dev, steps, warmup):
     c = lfa.crystal_layer(spec, stride)
     plan = lfa.Plan([c], torch.float32, want_u=True, want_v=True)
     S, U, V = plan._alloc_outputs(dev, True, True)
-    info = torch.zeros(1, 4, dtype=torch.int32, device=dev)
+    info = torch.zeros(1, lfa._lib.LFA_INFO_WORDS, dtype=torch.int32, device=dev)
 
     def step():
         Wc = lfa.crystal_weights(Wt, spec, stride)
@@ -126,7 +126,7 @@ def run_layer(L, W, dev, vectors, steps, warmup, asm=None, dtype=torch.float32):
     spec = lfa.LayerSpec(L.c_out, L.c_in, L.kh, L.kw, L.n, L.m)
     plan = lfa.Plan([spec], dtype, want_u=vectors, want_v=vectors, asm=asm)
     S, U, V = plan._alloc_outputs(dev, vectors, vectors)
-    info = torch.zeros(1, 4, dtype=torch.int32, device=dev)
+    info = torch.zeros(1, lfa._lib.LFA_INFO_WORDS, dtype=torch.int32, device=dev)
 
     def step():
         plan.svd([Wt], info=info, out=(S, U, V))
@@ -163,7 +163,7 @@ def bench_stack(dev, steps):
     S, _, _ = plan._alloc_outputs(dev, False, False)
     Su, Uu, _ = plan_u._alloc_outputs(dev, True, False)
     dWu = [torch.empty_like(W) for W in Wt]
-    info = torch.zeros(len(specs), 4, dtype=torch.int32, device=dev)
+    info = torch.zeros(len(specs), lfa._lib.LFA_INFO_WORDS, dtype=torch.int32, device=dev)
     none = [None] * len(S)
     res = {}
 
@@ -503,7 +503,10 @@ def main():
         "config": {"workload": "single conv layer 64->64, 3x3, 64x64 periodic grid, "
                                "4096 symbols 64x64, sigma+U+V",
                    "c_in": 64, "c_out": 64, "kernel": 3, "n": 64, "symbols": 4096},
-        "sweeps": {"sum": head["info"][2], "max": head["info"][1], "nonconverged": head["info"][0]},
+        "sweeps": {"sum": head["info"][2], "max": head["info"][1], "nonconverged": head["info"][0],
+                   "histogram": {str(k): c for k, c in enumerate(
+                       head["info"][lfa._lib.LFA_INFO_HIST:lfa._lib.LFA_INFO_HIST + lfa._lib.LFA_INFO_HIST_BINS])
+                                 if c}},
         "roofline": {"bound": "alu", "kernel": "wave_queue_kernel_f32<64,64> (work queue of groups, 6 sweeps per turn; fused assembly + Jacobi + sort/write)",
                      "achieved": achieved, "peak": PEAK_FP32_VECTOR_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP32_VECTOR_TFLOPS,

@@ -112,14 +112,19 @@ enum lfa_status {
 
 /* Per-layer convergence record written by the SVD entry points into the
  * caller's device buffer `info` (int32, LFA_INFO_WORDS per layer).  The
- * library clears it on the stream before use. */
+ * library clears it on the stream before use.  Symbols are those actually
+ * decomposed (one per conjugate pair for real weights); a symbol that hit the
+ * cap is counted in the bin of the cap. */
 enum lfa_info_word {
     LFA_INFO_NONCONVERGED = 0, /* symbols that hit the sweep cap               */
     LFA_INFO_MAX_SWEEPS = 1,   /* largest number of sweeps used by a symbol    */
     LFA_INFO_SUM_SWEEPS = 2,   /* total sweeps over the layer's symbols        */
     LFA_INFO_NONFINITE = 3,    /* bit 1: a singular value of the layer is not
                                   finite; bit 2: a team barrier timed out      */
-    LFA_INFO_WORDS = 4
+    LFA_INFO_HIST = 4,         /* LFA_INFO_HIST + s: symbols that used s sweeps,
+                                  s = 0 .. 40 (the largest sweep cap)          */
+    LFA_INFO_HIST_BINS = 41,
+    LFA_INFO_WORDS = 45
 };
 
 /* Warnings of a finished call, from a host copy of its `info` record

@@ -46,7 +46,9 @@ LFA_INFO_NONCONVERGED = 0
 LFA_INFO_MAX_SWEEPS = 1
 LFA_INFO_SUM_SWEEPS = 2
 LFA_INFO_NONFINITE = 3
-LFA_INFO_WORDS = 4
+LFA_INFO_HIST = 4
+LFA_INFO_HIST_BINS = 41
+LFA_INFO_WORDS = 45
 
 
 class LfaLayer(ctypes.Structure):

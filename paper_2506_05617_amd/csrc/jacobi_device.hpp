@@ -564,6 +564,7 @@ __device__ void finish(const SvdArgs<R>& a, const Shared<R>& s, int out_idx, int
         if (tid == 0) {
             atomicAdd(&a.info[LFA_INFO_SUM_SWEEPS], sweeps);
             atomicMax(&a.info[LFA_INFO_MAX_SWEEPS], sweeps);
+            atomicAdd(&a.info[LFA_INFO_HIST + min(sweeps, LFA_INFO_HIST_BINS - 1)], 1);
             if (!converged) atomicAdd(&a.info[LFA_INFO_NONCONVERGED], 1);
         }
         if (bad) atomicOr(&a.info[LFA_INFO_NONFINITE], 1);
@@ -1969,6 +1970,7 @@ __device__ bool wave_group(const SvdArgs<R>& a, char* lds_raw, int base, int tid
     if (a.info && wave == 0 && row == 0 && active) {
         atomicAdd(&a.info[LFA_INFO_SUM_SWEEPS], conv_at);
         atomicMax(&a.info[LFA_INFO_MAX_SWEEPS], conv_at);
+        atomicAdd(&a.info[LFA_INFO_HIST + min(conv_at, LFA_INFO_HIST_BINS - 1)], 1);
         if (!my_conv) atomicAdd(&a.info[LFA_INFO_NONCONVERGED], 1);
         bool bad = false;
         for (int k = 0; k < N; ++k) bad |= !isfinite(sigs[sym * NC + k]);

@@ -98,7 +98,7 @@ class Plan:
         check(self.lib.lfa_plan_set_max_sweeps(self.handle, int(max_sweeps)), "lfa_plan_set_max_sweeps")
 
     def info_status(self, info):
-        """Warnings of a finished call from its info record [L, 4]: 0, or the
+        """Warnings of a finished call from its info record [L, LFA_INFO_WORDS]: 0, or the
         OR of LFA_WARN_NOT_CONVERGED / _NONFINITE / _TEAM_TIMEOUT
         (lfa_info_status)."""
         host = info.detach().to("cpu", torch.int32).contiguous()
@@ -166,10 +166,21 @@ class Plan:
         check(self.lib.lfa_symbols(self.handle, w, a, _stream_ptr()), "lfa_symbols")
         return A
 
+    def _info(self, info, dev):
+        """The caller's info record, checked (the library writes
+        LFA_INFO_WORDS int32 per layer into it), or a new one."""
+        if info is None:
+            return torch.zeros(len(self.layers), _lib.LFA_INFO_WORDS, dtype=torch.int32, device=dev)
+        if (info.dtype != torch.int32 or tuple(info.shape) != (len(self.layers), _lib.LFA_INFO_WORDS)
+                or not info.is_contiguous() or info.device != dev):
+            raise ValueError(f"info must be a contiguous int32 tensor [{len(self.layers)}, "
+                             f"{_lib.LFA_INFO_WORDS}] on {dev}, got {tuple(info.shape)} {info.dtype} "
+                             f"on {info.device}")
+        return info
+
     def _svd_call(self, fn, name, inputs, dev, info=None, out=None):
         S, U, V = out if out is not None else self._alloc_outputs(dev, self.want_u, self.want_v)
-        if info is None:
-            info = torch.zeros(len(self.layers), _lib.LFA_INFO_WORDS, dtype=torch.int32, device=dev)
+        info = self._info(info, dev)
         ws = self.workspace(dev)
         i_arr, _k0 = ptr_array([x.data_ptr() for x in inputs])
         s_arr, _k1 = ptr_array([x.data_ptr() for x in S])
@@ -192,8 +203,7 @@ class Plan:
         here with torch unless `out` is given).  Returns (S, U, V, info)."""
         dev = self._check_weights(Ws)
         S, U, V = out if out is not None else self._alloc_outputs(dev, self.want_u, self.want_v)
-        if info is None:
-            info = torch.zeros(len(self.layers), _lib.LFA_INFO_WORDS, dtype=torch.int32, device=dev)
+        info = self._info(info, dev)
         w_arr, _k0 = ptr_array([x.data_ptr() for x in Ws])
         s_arr, _k1 = ptr_array([x.data_ptr() for x in S])
         u_arr, _k2 = ptr_array([x.data_ptr() if x is not None else 0 for x in U])

@@ -228,17 +228,34 @@ def test_work_queue_loop_runs_the_hand_over_on_every_trip():
     assert not bad, bad
 
 
+def test_binding_constants_match_header():
+    """Every numeric enum constant of include/lfa.h that the binding also
+    defines (status codes, flags, info words) has the same value there."""
+    import re
+    text = open(HEADER).read()
+    consts = {m.group(1): int(m.group(2)) for m in re.finditer(r"\b(LFA_[A-Z0-9_]+)\s*=\s*(-?\d+)u?\b", text)}
+    checked = 0
+    for name, val in consts.items():
+        if hasattr(_lib, name):
+            assert getattr(_lib, name) == val, (name, getattr(_lib, name), val)
+            checked += 1
+    assert checked >= 20 and _lib.LFA_INFO_WORDS == _lib.LFA_INFO_HIST + _lib.LFA_INFO_HIST_BINS
+
+
 @needs_lib
 def test_info_status_and_sweep_cap_validation():
     """lfa_info_status turns a host copy of the info record into warning
     bits; lfa_plan_set_max_sweeps accepts 1 .. 40 only (no GPU needed)."""
     lib = _lib.load()
-    info = (ctypes.c_int32 * 8)(0, 3, 10, 0, 0, 5, 40, 0)
+    w = _lib.LFA_INFO_WORDS
+    info = (ctypes.c_int32 * (2 * w))()
+    info[1], info[2], info[w + 1], info[w + 2] = 3, 10, 5, 40
+    info[_lib.LFA_INFO_HIST + 3] = 2                 # histogram words carry no warning
     assert lib.lfa_info_status(info, 1) == 0
     assert lib.lfa_info_status(info, 2) == 0
-    info[4] = 2                                      # layer 1: two symbols hit the cap
+    info[w] = 2                                      # layer 1: two symbols hit the cap
     assert lib.lfa_info_status(info, 2) == _lib.LFA_WARN_NOT_CONVERGED
-    info[7] = 1 | 2                                  # non-finite and a team time-out
+    info[w + 3] = 1 | 2                              # non-finite and a team time-out
     assert lib.lfa_info_status(info, 2) == (_lib.LFA_WARN_NOT_CONVERGED | _lib.LFA_WARN_NONFINITE
                                             | _lib.LFA_WARN_TEAM_TIMEOUT)
     assert lib.lfa_info_status(None, 1) == _lib.LFA_ERR_INVALID_ARG

@@ -76,6 +76,8 @@ def test_sweep_cap_reports_nonconverged(case):
     inf = to_np(info)[0]
     canon = n // 2 + 1 + (n // 2 - 1) * n + (n // 2 + 1)      # one symbol per conjugate pair
     assert inf[0] == canon and inf[1] == 2, inf
+    hist = inf[lfa()._lib.LFA_INFO_HIST:]
+    assert hist[2] == canon and hist.sum() == canon, hist      # every symbol in the bin of the cap
     assert plan.info_status(info) & lfa()._lib.LFA_WARN_NOT_CONVERGED
     assert np.all(np.isfinite(to_np(S[0])))
     plan.set_max_sweeps(40)
@@ -103,7 +105,7 @@ def test_prepared_plan_captures_into_a_torch_graph():
     plan.prepare(k)
     Wt = [_w(W) for W in Ws]
     S, _, _ = plan._alloc_outputs(Wt[0].device, False, False)
-    info = torch.zeros(len(layers), 4, dtype=torch.int32, device=DEV)
+    info = torch.zeros(len(layers), lfa()._lib.LFA_INFO_WORDS, dtype=torch.int32, device=DEV)
     g = torch.ones(len(layers), k, device=DEV)
     dW = [torch.empty_like(W) for W in Wt]
     plan.workspace(Wt[0].device)
@@ -167,3 +169,35 @@ def test_persistent_busy_records_match_the_launch():
     assert rec[:, 1].sum() > 0
     cus = {(int(x), int(h)) for x, h in rec[:, 2:]}
     assert len(cus) >= 1 and rec.shape[0] <= 8 * len(cus)
+
+
+HIST_CASES = [
+    # c_out, c_in, n, persistent: register kernel (work queue), lane-group /
+    # blocked kernels, and the persistent launch
+    (64, 64, 64, False),
+    (160, 96, 8, False),
+    (24, 40, 12, False),
+    (160, 96, 8, True),
+]
+
+
+@pytest.mark.parametrize("case", HIST_CASES)
+def test_sweep_histogram_is_consistent(case):
+    """The info record's sweep histogram counts every decomposed symbol once
+    (one per conjugate pair), its weighted sum is the sweep total and its
+    last nonzero bin the sweep maximum."""
+    c_out, c_in, n, persistent = case
+    banner(f"sweep histogram {case}")
+    L, W = workloads.random_layer(c_out, c_in, 3, 3, n, n, seed=74)
+    plan = lfa().Plan([_spec(L)])
+    S, _, _, info = plan.svd([_w(W)], persistent=persistent)
+    torch.cuda.synchronize()
+    inf = to_np(info)[0]
+    lib = lfa()._lib
+    hist = inf[lib.LFA_INFO_HIST:lib.LFA_INFO_HIST + lib.LFA_INFO_HIST_BINS]
+    canon = (n * n + 4) // 2 if n % 2 == 0 else (n * n + 1) // 2
+    assert hist.sum() == canon, (hist, canon)
+    assert int(np.dot(np.arange(len(hist)), hist)) == inf[lib.LFA_INFO_SUM_SWEEPS], (hist, inf)
+    assert np.flatnonzero(hist).max() == inf[lib.LFA_INFO_MAX_SWEEPS], (hist, inf)
+    assert inf[lib.LFA_INFO_NONCONVERGED] == 0
+
