@@ -294,8 +294,19 @@ def bench_split(dev, steps, L, W, vectors):
     S, U, V = plan._alloc_outputs(dev, vectors, vectors)
     _, ev_fused = event_times(lambda: plan.svd([Wt], out=(S, U, V)), steps, 2)
     t_asm, t_svd, t_fused = (float(np.mean(e)) for e in (ev_asm, ev_svd, ev_fused))
+    # the fused kernel's own split: work-group time in each phase (the
+    # register kernel's phase record), apportioning the fused launch
+    ticks = torch.zeros(4, dtype=torch.int64, device=dev)
+    plan.record_phases(ticks)
+    plan.svd([Wt], out=(S, U, V))
+    torch.cuda.synchronize()
+    plan.record_phases(None)
+    tk = ticks.cpu().numpy().astype(np.float64)
+    share = tk / max(tk.sum(), 1.0)
+    phases = dict(zip(("load_asm", "sweeps", "post", "queue_save"), share.tolist()))
     return dict(asm_ms=t_asm, svd_ms=t_svd, asm_share=t_asm / (t_asm + t_svd), fused_ms=t_fused,
-                vectors=vectors)
+                vectors=vectors, fused_phase_share=phases,
+                fused_phase_ms={k: v * t_fused for k, v in phases.items()})
 
 
 def bench_apply(head, dev, kind, batch=8, steps=10):

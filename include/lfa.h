@@ -174,6 +174,21 @@ int lfa_plan_prepare(lfa_plan* plan, int32_t k);
  * concurrently with them.  Errors: LFA_ERR_INVALID_ARG. */
 int lfa_plan_set_max_sweeps(lfa_plan* plan, int32_t max_sweeps);
 
+/* Phase record of the register kernel, for measurement: the split of the
+ * step into its stages that the paper's Table III reports as transformation
+ * and SVD time, here for a kernel that fuses them.  With `ticks` a device
+ * buffer of 4 uint64 (cleared by the caller), every later lfa_svd launch of
+ * the register kernel (symbols of at most 64 rows) adds, for each group of
+ * symbols it runs, the real-time-clock ticks (100 MHz) its work-group spent
+ * in: [0] loading the symbols (assembly from W, or the restore of a saved
+ * turn of the work queue), [1] the sweeps, [2] the finish (norms, sort,
+ * normalisation, completion, writing sigma, U, V), [3] saving a turn.  The
+ * sums are work-group time, not wall time: their shares apportion a
+ * launch's duration.  Other kernels and entry points ignore it; NULL stops
+ * recording.  The buffer must outlive the launches that use it.
+ * Errors: LFA_ERR_INVALID_ARG (NULL plan).  Host only. */
+int lfa_plan_record_phases(lfa_plan* plan, unsigned long long* ticks);
+
 /* Free the plan and its device tables.  NULL is accepted. */
 int lfa_plan_destroy(lfa_plan* plan);
 

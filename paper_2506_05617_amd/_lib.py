@@ -67,6 +67,7 @@ SIGNATURES = {
     "lfa_plan_destroy": (I32, [P]),
     "lfa_plan_prepare": (I32, [P, I32]),
     "lfa_plan_set_max_sweeps": (I32, [P, I32]),
+    "lfa_plan_record_phases": (I32, [P, P]),
     "lfa_info_status": (I32, [I32P, I32]),
     "lfa_plan_workspace_bytes": (I32, [P, ctypes.POINTER(SZ)]),
     "lfa_plan_num_layers": (I32, [P, I32P]),

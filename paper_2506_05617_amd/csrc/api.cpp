@@ -92,6 +92,7 @@ struct lfa_plan {
     double tol = 0;
     int max_sweeps = kMaxSweeps;          // sweep cap (lfa_plan_set_max_sweeps)
     int wq_force = -1;                    // work queue: -1 automatic, 0 off, k > 0 forced
+    unsigned long long* phase_rec = nullptr;   // register kernel phase record (lfa_plan_record_phases)
     std::mutex mu;
     int device = -1;
     double* tw_dev = nullptr;
@@ -627,6 +628,7 @@ int run_svd_layer(const lfa_plan* p, const LayerDesc& d, const void* W, const vo
     a.theta_dedup = theta_list != nullptr && theta_stride == 3;   // top-k picks
     a.max_sweeps = p->max_sweeps;
     a.tol = jacobi_tol(p->tol, d.M);
+    a.phase = d.kind == 1 ? p->phase_rec : nullptr;
     const bool acc = (d.transposed ? U : V) != nullptr;
     const int count = item_count(a);
     if (count <= 0) return LFA_OK;
@@ -1754,6 +1756,13 @@ int lfa_plan_prepare(lfa_plan* plan, int32_t k) {
         LFA_TRY(check_k(plan, k));
         LFA_TRY(ensure_grad_schedule(plan, k, nullptr, false, nullptr));
     }
+    return LFA_OK;
+}
+
+int lfa_plan_record_phases(lfa_plan* plan, unsigned long long* ticks) {
+    if (!plan) return LFA_ERR_INVALID_ARG;
+    std::lock_guard<std::mutex> lock(plan->mu);
+    plan->phase_rec = ticks;
     return LFA_OK;
 }
 

@@ -1688,6 +1688,16 @@ __device__ bool wave_group(const SvdArgs<R>& a, char* lds_raw, int base, int tid
     cplx<R>* ph = reinterpret_cast<cplx<R>*>(part + SPW * ML * PST);   // [SPW][T]
     cplx<R> g[NC];
     const bool fresh = !SEG || seg.first;
+    // optional phase record (thread 0): load, sweeps, finish, save
+    unsigned long long* const phase = a.phase;
+    unsigned long long t_mark = (phase && tid == 0) ? wall_clock64() : 0;
+    auto phase_add = [&](int k) {
+        if (phase && tid == 0) {
+            const unsigned long long t = wall_clock64();
+            atomicAdd(&phase[k], t - t_mark);
+            t_mark = t;
+        }
+    };
     if (!fresh) {
         // saved rows of this wave (written by another work-group, made
         // visible by the queue's release/acquire)
@@ -1756,6 +1766,7 @@ __device__ bool wave_group(const SvdArgs<R>& a, char* lds_raw, int base, int tid
     }
     // the Q wave reads the scales at the first segment start
     wsync(solo);
+    phase_add(0);
     int cur = 0;                // scale buffer of the current segment
 
     // -------------------------------------------------------------- sweeps
@@ -1903,6 +1914,7 @@ __device__ bool wave_group(const SvdArgs<R>& a, char* lds_raw, int base, int tid
         wsync(solo);
         if (all) break;
     }
+    phase_add(1);
     if (SEG && !all && sweeps < a.max_sweeps) {
         // ------------------------------------------------------------ save
         // fold the last segment's scales (as the finish does) and save the
@@ -1922,6 +1934,7 @@ __device__ bool wave_group(const SvdArgs<R>& a, char* lds_raw, int base, int tid
         // group is queued again
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
         wsync(solo);
+        phase_add(3);
         return false;
     }
     if (!my_conv) conv_at = sweeps;
@@ -1967,14 +1980,46 @@ __device__ bool wave_group(const SvdArgs<R>& a, char* lds_raw, int base, int tid
         nzero[tid] = z;
     }
     wsync(solo);
-    if (a.info && wave == 0 && row == 0 && active) {
-        atomicAdd(&a.info[LFA_INFO_SUM_SWEEPS], conv_at);
-        atomicMax(&a.info[LFA_INFO_MAX_SWEEPS], conv_at);
-        atomicAdd(&a.info[LFA_INFO_HIST + min(conv_at, LFA_INFO_HIST_BINS - 1)], 1);
-        if (!my_conv) atomicAdd(&a.info[LFA_INFO_NONCONVERGED], 1);
+    if (a.info && wave == 0) {
+        // the wave's symbols gathered at lane 0: one atomic per word and per
+        // distinct histogram bin (with a million small symbols, per-symbol
+        // atomics on the same few words serialise)
         bool bad = false;
-        for (int k = 0; k < N; ++k) bad |= !isfinite(sigs[sym * NC + k]);
-        if (bad) atomicOr(&a.info[LFA_INFO_NONFINITE], 1);
+        if (row == 0 && active)
+            for (int k = 0; k < N; ++k) bad |= !isfinite(sigs[sym * NC + k]);
+        int vals[SPW];
+        bool act[SPW];
+        int sum = 0, mx = 0, ncv = 0, anybad = 0;
+#pragma unroll
+        for (int s2 = 0; s2 < SPW; ++s2) {
+            vals[s2] = __shfl(conv_at, s2 * ML, 64);
+            act[s2] = __shfl(int(active), s2 * ML, 64) != 0;
+            const int nco = __shfl(int(!my_conv), s2 * ML, 64);
+            const int b = __shfl(int(bad), s2 * ML, 64);
+            if (act[s2]) {
+                sum += vals[s2];
+                mx = max(mx, vals[s2]);
+                ncv += nco;
+                anybad |= b;
+            }
+        }
+        if (lane == 0 && act[0]) {
+            atomicAdd(&a.info[LFA_INFO_SUM_SWEEPS], sum);
+            atomicMax(&a.info[LFA_INFO_MAX_SWEEPS], mx);
+            if (ncv) atomicAdd(&a.info[LFA_INFO_NONCONVERGED], ncv);
+            if (anybad) atomicOr(&a.info[LFA_INFO_NONFINITE], 1);
+#pragma unroll
+            for (int s2 = 0; s2 < SPW; ++s2) {
+                bool first = act[s2];
+                int cnt = 0;
+#pragma unroll
+                for (int s3 = 0; s3 < SPW; ++s3) {
+                    if (s3 < s2 && act[s3] && vals[s3] == vals[s2]) first = false;
+                    if (act[s3] && vals[s3] == vals[s2]) ++cnt;
+                }
+                if (first) atomicAdd(&a.info[LFA_INFO_HIST + min(vals[s2], LFA_INFO_HIST_BINS - 1)], cnt);
+            }
+        }
     }
     cplx<R>* left = d.transposed ? a.V : a.U;
     cplx<R>* right = d.transposed ? a.U : a.V;
@@ -2062,6 +2107,7 @@ __device__ bool wave_group(const SvdArgs<R>& a, char* lds_raw, int base, int tid
     }
     // the LDS of this group is reused by the next one
     wsync(solo);
+    phase_add(2);
     return true;
 }
 

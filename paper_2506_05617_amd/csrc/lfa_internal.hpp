@@ -268,6 +268,8 @@ struct SvdArgs {
     int32_t* wq_meta;            // [groups][kWaveMeta]
     int wq_cap;                  // queue entries
     int wq_seg;                  // sweeps per run of a group
+    unsigned long long* phase;   // register kernel: real-time-clock ticks per phase (load,
+                                 // sweeps, finish, save), summed over the groups, or null
 };
 
 // Work queue of the register kernel: control words head (next entry to

@@ -93,6 +93,18 @@ class Plan:
         (lfa_plan_prepare)."""
         check(self.lib.lfa_plan_prepare(self.handle, int(k)), "lfa_plan_prepare")
 
+    def record_phases(self, ticks):
+        """Phase record of the register kernel (lfa_plan_record_phases):
+        `ticks` a cleared int64 CUDA tensor of 4 (load, sweeps, finish, save;
+        100 MHz ticks summed over the groups) that later svd() calls add to,
+        or None to stop.  The plan keeps a reference until then."""
+        if ticks is not None and (ticks.dtype != torch.int64 or ticks.numel() < 4 or not ticks.is_cuda
+                                  or not ticks.is_contiguous()):
+            raise ValueError("ticks must be a contiguous int64 CUDA tensor of 4")
+        self._phase_ticks = ticks
+        check(self.lib.lfa_plan_record_phases(self.handle, None if ticks is None else
+                                              ctypes.c_void_p(ticks.data_ptr())), "lfa_plan_record_phases")
+
     def set_max_sweeps(self, max_sweeps):
         """Cap on Jacobi sweeps per symbol (1 .. 40) for later calls."""
         check(self.lib.lfa_plan_set_max_sweeps(self.handle, int(max_sweeps)), "lfa_plan_set_max_sweeps")
