@@ -163,29 +163,42 @@ __global__ void __launch_bounds__(256) gram_cholesky_kernel(GramArgs<R> g) {
             P[(size_t)r * N + c] = c >= r ? H[(size_t)(k0 + r) * N + k0 + c] : cplx<double>{0, 0};
         }
         __syncthreads();
+        // One barrier per row: step r updates rows s > r from the unscaled
+        // row r (the factor 1/d2 folded into the update) and scales row r - 1,
+        // which no thread reads in step r; the last row is scaled after the
+        // loop.
+        double inv_prev = 0.0, sq_prev = 0.0;
+        bool zero_prev = false;
+        auto scale_row = [&](int r, double inv, double sq, bool zero) {
+            for (int c = r + threadIdx.x; c < w; c += blockDim.x) {
+                cplx<double>& v = P[(size_t)r * N + c];
+                v = c == r ? cplx<double>{zero ? 0.0 : sq, 0.0} : cplx<double>{v.x * inv, v.y * inv};
+            }
+        };
         for (int r = 0; r < b; ++r) {
             const double d2 = P[(size_t)r * N + r].x;
             const bool zero = !(d2 > floor) && d2 == d2;    // numerically singular pivot (not NaN)
-            const double inv = zero ? 0.0 : 1.0 / sqrt(d2);
-            __syncthreads();
-            for (int c = r + threadIdx.x; c < w; c += blockDim.x) {
-                cplx<double>& v = P[(size_t)r * N + c];
-                v = c == r ? cplx<double>{zero ? 0.0 : sqrt(d2), 0.0} : cplx<double>{v.x * inv, v.y * inv};
-            }
-            __syncthreads();
-            // rows s in (r, b): P[s][c] -= conj(P[r][s]) P[r][c], c >= s
+            const double sq = sqrt(d2);
+            const double inv = zero ? 0.0 : 1.0 / sq, inv2 = inv * inv;
+            // rows s in (r, b): P[s][c] -= conj(P[r][s]) P[r][c] / d2, c >= s
             const int rows = b - r - 1;
             for (int x = threadIdx.x; x < rows * w; x += blockDim.x) {
                 const int s = r + 1 + x / w, c = x - (x / w) * w;
                 if (c < s) continue;
                 const cplx<double> a = P[(size_t)r * N + s], v = P[(size_t)r * N + c];
                 cplx<double>& t = P[(size_t)s * N + c];
-                // conj(a) v
-                t.x -= a.x * v.x + a.y * v.y;
-                t.y -= a.x * v.y - a.y * v.x;
+                // conj(a) v / d2
+                t.x -= (a.x * v.x + a.y * v.y) * inv2;
+                t.y -= (a.x * v.y - a.y * v.x) * inv2;
             }
+            if (r > 0) scale_row(r - 1, inv_prev, sq_prev, zero_prev);
+            inv_prev = inv;
+            sq_prev = sq;
+            zero_prev = zero;
             __syncthreads();
         }
+        scale_row(b - 1, inv_prev, sq_prev, zero_prev);
+        __syncthreads();
         // rows of R (zeros left of the diagonal), or columns of R^H
         for (int x = threadIdx.x; x < b * N; x += blockDim.x) {
             const int r = x / N, c = x - (x / N) * N;

@@ -201,3 +201,30 @@ def test_sweep_histogram_is_consistent(case):
     assert np.flatnonzero(hist).max() == inf[lib.LFA_INFO_MAX_SWEEPS], (hist, inf)
     assert inf[lib.LFA_INFO_NONCONVERGED] == 0
 
+
+
+def test_phase_record():
+    """The register kernel's phase record: with a buffer set, a launch adds
+    positive work-group time to the load, sweep and finish phases (and to
+    the saves of the work queue when it runs), with the sweeps the largest;
+    after record_phases(None) a launch adds nothing; σ is unchanged."""
+    banner("phase record")
+    L, W = workloads.random_layer(64, 64, 3, 3, 64, 64, seed=75)
+    plan = lfa().Plan([_spec(L)], want_u=True, want_v=True)
+    Wt = _w(W)
+    S0 = plan.svd([Wt])[0][0].clone()
+    ticks = torch.zeros(4, dtype=torch.int64, device=DEV)
+    plan.record_phases(ticks)
+    S1 = plan.svd([Wt])[0][0]
+    torch.cuda.synchronize()
+    plan.record_phases(None)
+    tk = ticks.cpu().numpy()
+    assert np.all(tk[:3] > 0), tk
+    assert tk[1] > tk[0] and tk[1] > tk[2], tk
+    if plan.queue_info(0)[0] > 0:
+        assert tk[3] > 0, tk
+    assert torch.equal(S0, S1)
+    before = ticks.clone()
+    plan.svd([Wt])
+    torch.cuda.synchronize()
+    assert torch.equal(ticks, before)
