@@ -483,8 +483,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--quick", action="store_true", help="headline workload only")
     ap.add_argument("--only", default=None,
-                    help="run one extra workload after the headline: apply, fp64, rect, strided, split, "
-                         "stack, large, assembly, paper")
+                    help="run only these extra workloads after the headline (comma-separated): apply, fp64, "
+                         "rect, strided, split, stack, large, assembly, paper")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the LFA SVD shards over frequencies, but this benchmark "
@@ -527,7 +527,8 @@ def main():
                      "kernel_ms": head["kernel_ms"]},
     }
     extra = {}
-    sel = (lambda name: args.only in (None, name)) if not args.quick else (lambda name: False)
+    only = None if args.only is None else set(args.only.split(","))
+    sel = (lambda name: only is None or name in only) if not args.quick else (lambda name: False)
     if not args.quick:
         reps = 3
         wl = {}

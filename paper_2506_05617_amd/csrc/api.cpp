@@ -317,6 +317,8 @@ bool qr_eligible(const lfa_layer& l, int dtype, uint32_t flags) {
     const int M = std::max(l.c_out, l.c_in), N = std::min(l.c_out, l.c_in);
     if (dtype != LFA_F32) return false;
     if (flags & (LFA_ASM_MFMA | LFA_ASM_BF16X2 | LFA_ASM_BF16X3)) return false;
+    // the Cholesky kernel keeps a panel of its factor's rows in LDS
+    if (gram_cholesky_lds_bytes(N, l.kh, l.kw) > kLdsCap) return false;
     return M > 64 && 4 * M >= 5 * N;
 }
 bool qr_applies(const lfa_layer& l, int dtype, uint32_t flags) {
@@ -704,8 +706,10 @@ int run_svd_layer(const lfa_plan* p, const LayerDesc& d, const void* W, const vo
         a.gws = region + kCounterBytes;
         // More symbols than resident work-groups: the whole rounds run one
         // work-group per symbol, and a short last round (at most half the
-        // device) runs afterwards in teams instead of leaving the other CUs
-        // idle for a whole symbol time.
+        // device) runs in teams instead of leaving the other CUs idle for a
+        // whole symbol time.  The teams join the same grid when the slots
+        // allow (they start on the CUs that the earliest finished symbols
+        // free), else they follow as a launch of their own.
         int split = count;
         int W2 = 1, teams2 = 0;
         const int rem = resident > 0 ? count % resident : 0;
@@ -717,12 +721,16 @@ int run_svd_layer(const lfa_plan* p, const LayerDesc& d, const void* W, const vo
                 teams = std::min(split, kGlobalGrid);
             }
         }
-        auto launch = [&](int tm, int w, int i0, int i1) {
-            if constexpr (sizeof(R) == 4) return launch_block_svd_f32(a, tm, w, i0, i1, counters, st);
-            else return launch_block_svd_f64(a, tm, w, i0, i1, counters, st);
+        auto launch = [&](int tm, int w, int i0, int i1, int tm2, int w2, int i2) {
+            if constexpr (sizeof(R) == 4) return launch_block_svd_f32(a, tm, w, i0, i1, tm2, w2, i2, counters, st);
+            else return launch_block_svd_f64(a, tm, w, i0, i1, tm2, w2, i2, counters, st);
         };
-        HIP_TRY(launch(teams, W, 0, split));
-        if (teams2 > 0) HIP_TRY(launch(teams2, W2, split, count));
+        if (teams2 > 0 && teams + teams2 <= svd_grid(d, d.num_symbols)) {
+            HIP_TRY(launch(teams, W, 0, split, teams2, W2, count));
+        } else {
+            HIP_TRY(launch(teams, W, 0, split, 0, 1, split));
+            if (teams2 > 0) HIP_TRY(launch(teams2, W2, split, count, 0, 1, count));
+        }
         return LFA_OK;
     }
     const size_t lds = lds_bytes_for(d, acc, sizeof(R));
@@ -763,8 +771,10 @@ int svd_layer(const lfa_plan* p, size_t i, const void* const* W, const void* con
         if (!A) {
             if (mat) {
                 cplx<float>* sym = reinterpret_cast<cplx<float>*>(region);
+                // only the canonical symbols: the SVD below takes one per
+                // conjugate pair (real weights)
                 HIP_TRY(launch_symbols_mfma(d, static_cast<const float*>(W[i]), sym, p->tw_dev,
-                                            asm_materialized(p->flags) ? asm_mode(p->flags) : 0, st));
+                                            asm_materialized(p->flags) ? asm_mode(p->flags) : 0, st, true));
                 Ai = sym;
                 slots = region + symbols_bytes(p->layers[i], sizeof(R));
             } else {

@@ -122,14 +122,21 @@ __constant__ int kSegB[2][6] = {{0, 1, 0, 0, 0, 0}, {0, 1, 0, 2, 1, 0}};
 
 constexpr int kMfmaETile = 64;   // e columns per block (4 sub-tiles of 16)
 
+// Frequency of output row r of the matrix-core kernels: every frequency in
+// order, or (canon) the canonical frequency of conjugate pair r, when only
+// one symbol per pair is needed (the SVD of real weights).
+__device__ __forceinline__ int row_theta(const LayerDesc& d, int canon, int r) {
+    return canon ? canonical_theta(d.n, d.m, r) : r;
+}
+
 // Block: 4 waves; wave w owns frequencies theta0 + 16w .. +16 and all 64
 // e-columns of the block (4 output tiles of 16x16, re and im).
 __global__ void __launch_bounds__(256) symbols_mfma(LayerDesc d, const float* __restrict__ W,
                                                     cplx<float>* __restrict__ A,
-                                                    const double* __restrict__ tw, int mode) {
+                                                    const double* __restrict__ tw, int mode, int canon) {
     const int T = d.kh * d.kw;
     const int E = d.c_out * d.c_in;
-    const int HW = d.num_symbols;
+    const int HW = canon ? d.num_canon : d.num_symbols;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int theta0 = blockIdx.y * 64 + wave * 16;
     const int e0 = blockIdx.x * kMfmaETile;
@@ -142,6 +149,7 @@ __global__ void __launch_bounds__(256) symbols_mfma(LayerDesc d, const float* __
         acc_im[s] = floatx4{0.f, 0.f, 0.f, 0.f};
     }
     const int theta_a = theta0 + li;   // row of the A operand this lane feeds
+    const int freq_a = theta_a < HW ? row_theta(d, canon, theta_a) : 0;
     if (mode == 0) {
         // FP32: K-step 4; lane feeds A[i = li][k = lk], B[k = lk][j = li].
         for (int k0 = 0; k0 < T; k0 += 4) {
@@ -149,7 +157,7 @@ __global__ void __launch_bounds__(256) symbols_mfma(LayerDesc d, const float* __
             float pr = 0.f, pi = 0.f;
             if (t < T && theta_a < HW) {
                 double re, im;
-                phase_d(tw, d, theta_a, t, re, im);
+                phase_d(tw, d, freq_a, t, re, im);
                 pr = float(re);
                 pi = float(im);
             }
@@ -179,7 +187,7 @@ __global__ void __launch_bounds__(256) symbols_mfma(LayerDesc d, const float* __
                     const int seg = kk / T, t = kk - (kk / T) * T;
                     if (theta_a < HW) {
                         double re, im;
-                        phase_d(tw, d, theta_a, t, re, im);
+                        phase_d(tw, d, freq_a, t, re, im);
                         unsigned short sr[3], si[3];
                         split_bf16(float(re), terms, sr);
                         split_bf16(float(im), terms, si);
@@ -215,7 +223,8 @@ __global__ void __launch_bounds__(256) symbols_mfma(LayerDesc d, const float* __
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
             const int th = theta0 + 4 * lk + v;
-            if (th < HW && e < E) store_stream(A + (size_t)th * E + e, acc_re[s][v], acc_im[s][v]);
+            if (th < HW && e < E)
+                store_stream(A + (size_t)row_theta(d, canon, th) * E + e, acc_re[s][v], acc_im[s][v]);
         }
     }
 }
@@ -246,17 +255,18 @@ struct Mfma2 {
 template <int MODE>
 __global__ void __launch_bounds__(256) symbols_mfma2(LayerDesc d, const float* __restrict__ W,
                                                      cplx<float>* __restrict__ A,
-                                                     const double* __restrict__ tw, int echunk) {
+                                                     const double* __restrict__ tw, int echunk, int canon) {
     using C = Mfma2<MODE>;
     constexpr int ms = MODE == 3 ? 1 : 0;
     extern __shared__ __align__(16) char lds_raw[];
     const int T = d.kh * d.kw;
     const int E = d.c_out * d.c_in;
-    const int HW = d.num_symbols;
+    const int HW = canon ? d.num_canon : d.num_symbols;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int li = lane & 15, lk = lane >> 4;
     const int theta0 = blockIdx.y * 64 + wave * 16;
     const int theta_a = theta0 + li;
+    const int freq_a = theta_a < HW ? row_theta(d, canon, theta_a) : 0;
     const int ks = (T + C::KSTEP - 1) / C::KSTEP;     // K steps actually used
 
     // A-fragments (phases) of this wave's 16 frequencies: lane (li, lk) holds
@@ -270,7 +280,7 @@ __global__ void __launch_bounds__(256) symbols_mfma2(LayerDesc d, const float* _
             float r = 0.f, im = 0.f;
             if (kt < ks && t < T && theta_a < HW) {
                 double re, imd;
-                phase_d(tw, d, theta_a, t, re, imd);
+                phase_d(tw, d, freq_a, t, re, imd);
                 r = float(re);
                 im = float(imd);
             }
@@ -283,7 +293,7 @@ __global__ void __launch_bounds__(256) symbols_mfma2(LayerDesc d, const float* _
                 unsigned short sr[3] = {0, 0, 0}, si[3] = {0, 0, 0};
                 if (kt < ks && t < T && theta_a < HW) {
                     double re, imd;
-                    phase_d(tw, d, theta_a, t, re, imd);
+                    phase_d(tw, d, freq_a, t, re, imd);
                     split_bf16(float(re), C::TERMS, sr);
                     split_bf16(float(imd), C::TERMS, si);
                 }
@@ -369,7 +379,8 @@ __global__ void __launch_bounds__(256) symbols_mfma2(LayerDesc d, const float* _
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
                 const int th = theta0 + 4 * lk + v;
-                if (th < HW && e < E) store_stream(A + (size_t)th * E + e, acc_re[s][v], acc_im[s][v]);
+                if (th < HW && e < E)
+                    store_stream(A + (size_t)row_theta(d, canon, th) * E + e, acc_re[s][v], acc_im[s][v]);
             }
         }
     }
@@ -381,9 +392,10 @@ constexpr size_t mfma2_lds_bytes() {
 }
 
 template <int MODE>
-hipError_t launch_mfma2(const LayerDesc& d, const float* W, cplx<float>* A, const double* tw, hipStream_t s) {
+hipError_t launch_mfma2(const LayerDesc& d, const float* W, cplx<float>* A, const double* tw, int canon,
+                        hipStream_t s) {
     const int E = d.c_out * d.c_in;
-    const int tblocks = (d.num_symbols + 63) / 64;
+    const int tblocks = ((canon ? d.num_canon : d.num_symbols) + 63) / 64;
     // enough blocks for the device: split the e range when there are few
     // frequency tiles (each block still covers >= 64 columns)
     const int etiles = (E + 63) / 64;
@@ -396,7 +408,7 @@ hipError_t launch_mfma2(const LayerDesc& d, const float* W, cplx<float>* A, cons
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
     }
-    hipLaunchKernelGGL(symbols_mfma2<MODE>, grid, dim3(256), lds, s, d, W, A, tw, echunk);
+    hipLaunchKernelGGL(symbols_mfma2<MODE>, grid, dim3(256), lds, s, d, W, A, tw, echunk, canon);
     return hipGetLastError();
 }
 
@@ -419,15 +431,16 @@ hipError_t launch_symbols_valu_f64(const LayerDesc& d, const double* W, cplx<dou
 }
 
 hipError_t launch_symbols_mfma(const LayerDesc& d, const float* W, cplx<float>* A,
-                               const double* tw, int mode, hipStream_t s) {
+                               const double* tw, int mode, hipStream_t s, bool canon_only) {
+    const int canon = canon_only ? 1 : 0;
     if (d.kh * d.kw <= kMfma2MaxTaps) {
-        if (mode == 0) return launch_mfma2<0>(d, W, A, tw, s);
-        if (mode == 2) return launch_mfma2<2>(d, W, A, tw, s);
-        if (mode == 3) return launch_mfma2<3>(d, W, A, tw, s);
+        if (mode == 0) return launch_mfma2<0>(d, W, A, tw, canon, s);
+        if (mode == 2) return launch_mfma2<2>(d, W, A, tw, canon, s);
+        if (mode == 3) return launch_mfma2<3>(d, W, A, tw, canon, s);
     }
     const int E = d.c_out * d.c_in;
-    const dim3 grid((E + kMfmaETile - 1) / kMfmaETile, (d.num_symbols + 63) / 64);
-    hipLaunchKernelGGL(symbols_mfma, grid, dim3(256), 0, s, d, W, A, tw, mode);
+    const dim3 grid((E + kMfmaETile - 1) / kMfmaETile, ((canon ? d.num_canon : d.num_symbols) + 63) / 64);
+    hipLaunchKernelGGL(symbols_mfma, grid, dim3(256), 0, s, d, W, A, tw, mode, canon);
     return hipGetLastError();
 }
 

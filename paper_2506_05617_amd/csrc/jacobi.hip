@@ -9,27 +9,55 @@ namespace lfa {
 namespace {
 using namespace dev;
 
-// Grid = teams x W work-groups, all resident at once when W > 1 (the host
-// sizes the grid from the occupancy of this kernel).  Team t owns slot t and
-// works on items item0 + t, item0 + t + teams, ... below item_end.
-// DUAL: the launch has no teams (W = 1), and each cross step of the sweeps
-// takes two block pairs (FP32 without the accumulator).
+// The first main_wgs work-groups form teams of W (all resident at once when
+// W > 1: the host sizes the grid from the occupancy of this kernel); team t
+// owns slot t and works on items item0 + t, item0 + t + teams, ... below
+// item_split.  The work-groups after them form teams of W2 for the items
+// item_split .. item_end - 1 (the short last round of a launch with more
+// items than resident work-groups): they are dispatched as the first
+// symbols of the main part finish, and each such team starts once all its
+// members are resident.
+// DUAL: the main part has no teams (W = 1), and each cross step of its
+// sweeps takes two block pairs (FP32 without the accumulator).
 template <typename R, bool ACC, bool DUAL = false>
-__global__ void __launch_bounds__(512) block_kernel(SvdArgs<R> a, int W, int item0, int item_end,
-                                                    int32_t* counters) {
+__global__ void __launch_bounds__(512) block_kernel(SvdArgs<R> a, int W, int item0, int item_split,
+                                                    int32_t* counters, int main_wgs, int W2, int item_end) {
     extern __shared__ __align__(16) char lds[];
-    const int teams = gridDim.x / W;
-    const int tix = blockIdx.x / W;
+    constexpr bool TRACK = !ACC && sizeof(R) == 4;
+    const int teams1 = main_wgs / W, teams2 = ((int)gridDim.x - main_wgs) / W2;
+    int tix, member, wk, first, end, stride;
+    if ((int)blockIdx.x < main_wgs) {
+        tix = blockIdx.x / W;
+        member = blockIdx.x - tix * W;
+        wk = W;
+        first = item0 + tix;
+        end = item_split;
+        stride = teams1;
+    } else {
+        const int b2 = blockIdx.x - main_wgs, t2 = b2 / W2;
+        tix = teams1 + t2;
+        member = b2 - t2 * W2;
+        wk = W2;
+        first = item_split + t2;
+        end = item_end;
+        stride = teams2;
+    }
     Team team;
-    team.member = blockIdx.x - tix * W;
-    team.W = W;
+    team.member = member;
+    team.W = wk;
     team.bar = counters + 4 * tix;
     team.rot = counters + 4 * tix + 1;
-    team.err = counters + 4 * teams;
+    team.err = counters + 4 * (teams1 + teams2);
     team.target = 0;
     char* gslot = a.gws + (size_t)tix * a.slot_bytes;
-    const int count = min(item_count(a), item_end);
-    for (int item = item0 + tix; item < count; item += teams) block_one<R, 1, ACC, !ACC && sizeof(R) == 4, DUAL>(a, lds, item, gslot, team);
+    end = min(item_count(a), end);
+    if constexpr (DUAL) {
+        if ((int)blockIdx.x < main_wgs) {
+            for (int item = first; item < end; item += stride) block_one<R, 1, ACC, TRACK, true>(a, lds, item, gslot, team);
+            return;
+        }
+    }
+    for (int item = first; item < end; item += stride) block_one<R, 1, ACC, TRACK, false>(a, lds, item, gslot, team);
 }
 
 template <typename R, int L>
@@ -106,34 +134,37 @@ size_t block_lds_bytes(const LayerDesc& d, bool accumulate, int elem_bytes) {
            (size_t)8 * nw * kDscW + 8 + 16 + 64;
 }
 
+// teams x W work-groups on items item0 .. item_split - 1, then teams2 x W2
+// on item_split .. item_end - 1 in the same grid (teams2 = 0: none).
 template <typename R, bool ACC, bool DUAL>
-hipError_t launch_block_k(const SvdArgs<R>& a, int teams, int W, int item0, int item_end, int32_t* counters,
-                          hipStream_t st) {
+hipError_t launch_block_k(const SvdArgs<R>& a, int teams, int W, int item0, int item_split, int teams2, int W2,
+                          int item_end, int32_t* counters, hipStream_t st) {
     const size_t lds = block_lds_bytes(a.d, ACC, sizeof(R));
     hipError_t e = allow_lds(block_kernel<R, ACC, DUAL>, lds);
     if (e != hipSuccess) return e;
-    e = launch_fill_i32(counters, 0, 4LL * teams + 4, st);
+    e = launch_fill_i32(counters, 0, 4LL * (teams + teams2) + 4, st);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((block_kernel<R, ACC, DUAL>), dim3(teams * W), dim3(a.d.threads), lds, st, a, W, item0,
-                       item_end, counters);
+    hipLaunchKernelGGL((block_kernel<R, ACC, DUAL>), dim3(teams * W + teams2 * W2), dim3(a.d.threads), lds, st, a,
+                       W, item0, item_split, counters, teams * W, std::max(W2, 1), item_end);
     return hipGetLastError();
 }
 
 template <typename R, bool ACC>
-hipError_t launch_block_t(const SvdArgs<R>& a, int teams, int W, int item0, int item_end, int32_t* counters,
-                          hipStream_t st) {
+hipError_t launch_block_t(const SvdArgs<R>& a, int teams, int W, int item0, int item_split, int teams2, int W2,
+                          int item_end, int32_t* counters, hipStream_t st) {
     if constexpr (!ACC && sizeof(R) == 4) {
-        if (W == 1) return launch_block_k<R, ACC, true>(a, teams, W, item0, item_end, counters, st);
+        if (W == 1)
+            return launch_block_k<R, ACC, true>(a, teams, W, item0, item_split, teams2, W2, item_end, counters, st);
     }
-    return launch_block_k<R, ACC, false>(a, teams, W, item0, item_end, counters, st);
+    return launch_block_k<R, ACC, false>(a, teams, W, item0, item_split, teams2, W2, item_end, counters, st);
 }
 
 template <typename R>
-hipError_t launch_block(const SvdArgs<R>& a, int teams, int W, int item0, int item_end, int32_t* counters,
-                        hipStream_t st) {
+hipError_t launch_block(const SvdArgs<R>& a, int teams, int W, int item0, int item_split, int teams2, int W2,
+                        int item_end, int32_t* counters, hipStream_t st) {
     const bool acc = (a.d.transposed ? a.U : a.V) != nullptr;
-    return acc ? launch_block_t<R, true>(a, teams, W, item0, item_end, counters, st)
-               : launch_block_t<R, false>(a, teams, W, item0, item_end, counters, st);
+    return acc ? launch_block_t<R, true>(a, teams, W, item0, item_split, teams2, W2, item_end, counters, st)
+               : launch_block_t<R, false>(a, teams, W, item0, item_split, teams2, W2, item_end, counters, st);
 }
 
 template <typename R, bool ACC>
@@ -159,13 +190,13 @@ int block_resident_t(const LayerDesc& d) {
     return per_cu * cus;
 }
 
-hipError_t launch_block_svd_f32(const SvdArgs<float>& a, int teams, int W, int item0, int item_end,
-                                int32_t* counters, hipStream_t s) {
-    return launch_block<float>(a, teams, W, item0, item_end, counters, s);
+hipError_t launch_block_svd_f32(const SvdArgs<float>& a, int teams, int W, int item0, int item_split, int teams2,
+                                int W2, int item_end, int32_t* counters, hipStream_t s) {
+    return launch_block<float>(a, teams, W, item0, item_split, teams2, W2, item_end, counters, s);
 }
-hipError_t launch_block_svd_f64(const SvdArgs<double>& a, int teams, int W, int item0, int item_end,
-                                int32_t* counters, hipStream_t s) {
-    return launch_block<double>(a, teams, W, item0, item_end, counters, s);
+hipError_t launch_block_svd_f64(const SvdArgs<double>& a, int teams, int W, int item0, int item_split, int teams2,
+                                int W2, int item_end, int32_t* counters, hipStream_t s) {
+    return launch_block<double>(a, teams, W, item0, item_split, teams2, W2, item_end, counters, s);
 }
 int block_resident(const LayerDesc& d, bool acc, int elem_bytes) {
     if (elem_bytes == 8) return acc ? block_resident_t<double, true>(d) : block_resident_t<double, false>(d);

@@ -335,12 +335,14 @@ size_t wave_lds_bytes_for(int nc, int ml, int elem_bytes);
 size_t wave_bundle_lds_for(int nc, int ml, int elem_bytes, bool vectors);
 size_t block_lds_bytes(const LayerDesc& d, bool accumulate, int elem_bytes);
 // Blocked kernel: `teams` teams of W work-groups (all resident at once when
-// W > 1) over the items [item0, item_end) of the layer; counters: 4*teams + 4
-// int32 of device memory, cleared by the launcher.
-hipError_t launch_block_svd_f32(const SvdArgs<float>& a, int teams, int W, int item0, int item_end,
-                                int32_t* counters, hipStream_t s);
-hipError_t launch_block_svd_f64(const SvdArgs<double>& a, int teams, int W, int item0, int item_end,
-                                int32_t* counters, hipStream_t s);
+// W > 1) over the items [item0, item_split) of the layer, and in the same
+// grid, after them, teams2 teams of W2 over [item_split, item_end) (the
+// short last round; teams2 = 0: none); one global slot per team; counters:
+// 4*(teams + teams2) + 4 int32 of device memory, cleared by the launcher.
+hipError_t launch_block_svd_f32(const SvdArgs<float>& a, int teams, int W, int item0, int item_split, int teams2,
+                                int W2, int item_end, int32_t* counters, hipStream_t s);
+hipError_t launch_block_svd_f64(const SvdArgs<double>& a, int teams, int W, int item0, int item_split, int teams2,
+                                int W2, int item_end, int32_t* counters, hipStream_t s);
 // Work-groups of the blocked kernel that fit on the device at once (0 on error).
 int block_resident(const LayerDesc& d, bool accumulate, int elem_bytes);
 
@@ -364,9 +366,11 @@ hipError_t launch_symbols_valu_f32(const LayerDesc& d, const float* W, cplx<floa
                                    const double* tw, hipStream_t s);
 hipError_t launch_symbols_valu_f64(const LayerDesc& d, const double* W, cplx<double>* A,
                                    const double* tw, hipStream_t s);
-// mode: 0 = FP32 MFMA, 2 = split-BF16 x2 (3 products), 3 = split-BF16 x3 (6 products)
+// mode: 0 = FP32 MFMA, 2 = split-BF16 x2 (3 products), 3 = split-BF16 x3 (6 products);
+// canon_only: only the canonical symbol of each conjugate pair is written
+// (at its own place in A), for the SVD of real weights
 hipError_t launch_symbols_mfma(const LayerDesc& d, const float* W, cplx<float>* A,
-                               const double* tw, int mode, hipStream_t s);
+                               const double* tw, int mode, hipStream_t s, bool canon_only = false);
 
 hipError_t launch_fill_i32(int32_t* p, int32_t value, long long count, hipStream_t s);
 

@@ -44,7 +44,7 @@ using namespace dev;
 
 constexpr int kGramTile = 32;     // output tile of C_delta (c, c')
 constexpr int kGramRows = 16;     // rows r per staged chunk
-constexpr int kPanel = 16;        // rows of R per Cholesky panel
+constexpr int kPanelMax = 16;     // rows of R per Cholesky panel, at most
 
 // C_delta for delta = blockIdx.z, tiles (blockIdx.x, blockIdx.y) of (c, c').
 // 256 threads: thread (tx, ty) in 32 x 8 computes c = c0 + tx, c' = c0' + ty + 8 e.
@@ -105,16 +105,26 @@ __global__ void __launch_bounds__(256) gram_taps_kernel(GramArgs<R> g) {
 // triangle, FP64), then the Cholesky factor R (R^H R = H, upper) into the
 // layer's R symbols [n*m][N][N] (FP32 or FP64, zeros below the diagonal),
 // or its conjugate transpose R^H (lower) when g.conj_transpose is set.
-template <typename R>
+// Right-looking in panels of PANEL rows: the panel's rows are staged in LDS
+// (row stride N + 1, so that column reads of the panel spread over the
+// banks), factored there with one barrier per row, written out as rows of R
+// (or columns of R^H), and the trailing triangle of H in the slot takes the
+// rank-PANEL update, each thread on 4 x 4 tiles of a folded triangle (rows
+// I and nT - 1 - I of the tile triangle share one row of nT + 1 tiles), so
+// that every thread has 16 loads of H in flight and reuses each panel value
+// four times.  Taller panels pass over the trailing triangle fewer times;
+// shorter ones take less LDS, so that more work-groups share a CU.
+template <typename R, int PANEL>
 __global__ void __launch_bounds__(256) gram_cholesky_kernel(GramArgs<R> g) {
     extern __shared__ __align__(16) char lds_raw[];
     const int item = blockIdx.x;
     const int theta = canonical_theta(g.n, g.m, item);
     const int p = theta / g.m, q = theta - (theta / g.m) * g.m;
     const int N = g.N, KD1 = 2 * g.kh - 1, KD2 = 2 * g.kw - 1, ND = KD1 * KD2;
+    const int ldp = N + 1;                                             // LDS row stride of the panel
     cplx<double>* ph = reinterpret_cast<cplx<double>*>(lds_raw);     // [ND]
-    cplx<double>* P = ph + ND;                                         // [kPanel][N]
-    double* red = reinterpret_cast<double*>(P + (size_t)kPanel * N);  // [256]
+    cplx<double>* P = ph + ND;                                         // [PANEL][ldp]
+    double* red = reinterpret_cast<double*>(P + (size_t)PANEL * ldp); // [256]
     cplx<double>* H = reinterpret_cast<cplx<double>*>(g.hslots) + (size_t)item * N * N;
     cplx<R>* Rk = g.Rsym + (size_t)theta * N * N;
     for (int x = threadIdx.x; x < ND; x += blockDim.x) {
@@ -155,41 +165,43 @@ __global__ void __launch_bounds__(256) gram_cholesky_kernel(GramArgs<R> g) {
     }
     const double floor = 4.0 * N * 0x1p-52 * red[0];
     __syncthreads();
-    for (int k0 = 0; k0 < N; k0 += kPanel) {
-        const int b = min(kPanel, N - k0), w = N - k0;
+    for (int k0 = 0; k0 < N; k0 += PANEL) {
+        const int b = min(PANEL, N - k0), w = N - k0;
         // panel rows k0 .. k0+b-1, columns k0 .. N-1 (upper part)
-        for (int x = threadIdx.x; x < b * w; x += blockDim.x) {
-            const int r = x / w, c = x - (x / w) * w;
-            P[(size_t)r * N + c] = c >= r ? H[(size_t)(k0 + r) * N + k0 + c] : cplx<double>{0, 0};
+        for (int r = 0; r < b; ++r) {
+#pragma unroll 4
+            for (int c = threadIdx.x; c < w; c += blockDim.x)
+                P[(size_t)r * ldp + c] = c >= r ? H[(size_t)(k0 + r) * N + k0 + c] : cplx<double>{0, 0};
         }
         __syncthreads();
         // One barrier per row: step r updates rows s > r from the unscaled
         // row r (the factor 1/d2 folded into the update) and scales row r - 1,
         // which no thread reads in step r; the last row is scaled after the
-        // loop.
+        // loop.  Thread c owns column c of the panel.
         double inv_prev = 0.0, sq_prev = 0.0;
         bool zero_prev = false;
         auto scale_row = [&](int r, double inv, double sq, bool zero) {
             for (int c = r + threadIdx.x; c < w; c += blockDim.x) {
-                cplx<double>& v = P[(size_t)r * N + c];
+                cplx<double>& v = P[(size_t)r * ldp + c];
                 v = c == r ? cplx<double>{zero ? 0.0 : sq, 0.0} : cplx<double>{v.x * inv, v.y * inv};
             }
         };
         for (int r = 0; r < b; ++r) {
-            const double d2 = P[(size_t)r * N + r].x;
+            const double d2 = P[(size_t)r * ldp + r].x;
             const bool zero = !(d2 > floor) && d2 == d2;    // numerically singular pivot (not NaN)
             const double sq = sqrt(d2);
             const double inv = zero ? 0.0 : 1.0 / sq, inv2 = inv * inv;
             // rows s in (r, b): P[s][c] -= conj(P[r][s]) P[r][c] / d2, c >= s
-            const int rows = b - r - 1;
-            for (int x = threadIdx.x; x < rows * w; x += blockDim.x) {
-                const int s = r + 1 + x / w, c = x - (x / w) * w;
-                if (c < s) continue;
-                const cplx<double> a = P[(size_t)r * N + s], v = P[(size_t)r * N + c];
-                cplx<double>& t = P[(size_t)s * N + c];
-                // conj(a) v / d2
-                t.x -= (a.x * v.x + a.y * v.y) * inv2;
-                t.y -= (a.x * v.y - a.y * v.x) * inv2;
+            for (int c = r + 1 + threadIdx.x; c < w; c += blockDim.x) {
+                const cplx<double> v = P[(size_t)r * ldp + c];
+                const int se = min(c, b - 1);
+                for (int s = r + 1; s <= se; ++s) {
+                    const cplx<double> a = P[(size_t)r * ldp + s];
+                    cplx<double>& t = P[(size_t)s * ldp + c];
+                    // conj(a) v / d2
+                    t.x -= (a.x * v.x + a.y * v.y) * inv2;
+                    t.y -= (a.x * v.y - a.y * v.x) * inv2;
+                }
             }
             if (r > 0) scale_row(r - 1, inv_prev, sq_prev, zero_prev);
             inv_prev = inv;
@@ -199,25 +211,71 @@ __global__ void __launch_bounds__(256) gram_cholesky_kernel(GramArgs<R> g) {
         }
         scale_row(b - 1, inv_prev, sq_prev, zero_prev);
         __syncthreads();
-        // rows of R (zeros left of the diagonal), or columns of R^H
-        for (int x = threadIdx.x; x < b * N; x += blockDim.x) {
-            const int r = x / N, c = x - (x / N) * N;
-            const cplx<double> v = c >= k0 + r ? P[(size_t)r * N + (c - k0)] : cplx<double>{0, 0};
-            if (g.conj_transpose) Rk[(size_t)c * N + k0 + r] = {R(v.x), R(-v.y)};
-            else Rk[(size_t)(k0 + r) * N + c] = {R(v.x), R(v.y)};
-        }
-        // trailing update of the upper triangle: H[i][j] -= sum_r conj(P[r][i]) P[r][j]
-        const int t0 = k0 + b, tw = N - t0;
-        for (long long x = threadIdx.x; x < (long long)tw * tw; x += blockDim.x) {
-            const int i = (int)(x / tw), j = (int)(x - (x / tw) * tw);
-            if (j < i) continue;
-            cplx<double> h = H[(size_t)(t0 + i) * N + t0 + j];
-            for (int r = 0; r < b; ++r) {
-                const cplx<double> a = P[(size_t)r * N + b + i], v = P[(size_t)r * N + b + j];
-                h.x -= a.x * v.x + a.y * v.y;
-                h.y -= a.x * v.y - a.y * v.x;
+        // rows of R (zeros left of the diagonal), or columns of R^H: thread
+        // (c, r) with r fastest, so that each column's b entries of R^H go
+        // out as one contiguous run
+        if (g.conj_transpose) {
+            for (int x = threadIdx.x; x < PANEL * N; x += blockDim.x) {
+                const int c = x / PANEL, r = x - (x / PANEL) * PANEL;
+                if (r >= b) continue;
+                const cplx<double> v = c >= k0 + r ? P[(size_t)r * ldp + (c - k0)] : cplx<double>{0, 0};
+                Rk[(size_t)c * N + k0 + r] = {R(v.x), R(-v.y)};
             }
-            H[(size_t)(t0 + i) * N + t0 + j] = h;
+        } else {
+            for (int r = 0; r < b; ++r) {
+                for (int c = threadIdx.x; c < N; c += blockDim.x) {
+                    const cplx<double> v = c >= k0 + r ? P[(size_t)r * ldp + (c - k0)] : cplx<double>{0, 0};
+                    Rk[(size_t)(k0 + r) * N + c] = {R(v.x), R(v.y)};
+                }
+            }
+        }
+        // trailing update of the upper triangle:
+        // H[t0 + i][t0 + j] -= sum_r conj(P[r][b + i]) P[r][b + j], i <= j < tw
+        const int t0 = k0 + b, tw = N - t0;
+        const int nT = (tw + 3) >> 2, fold = (nT + 1) >> 1;
+        for (int x = threadIdx.x; x < fold * (nT + 1); x += blockDim.x) {
+            const int f = x / (nT + 1), c = x - f * (nT + 1);
+            int I, J;
+            if (c < nT - f) {
+                I = f;
+                J = f + c;
+            } else {
+                I = nT - 1 - f;
+                J = I + (c - (nT - f));
+                if (I == f) continue;      // odd nT: the middle row of tiles is covered once
+            }
+            const int i0 = 4 * I, j0 = 4 * J;
+            cplx<double> h[4][4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int i = i0 + u, j = j0 + v;
+                    h[u][v] = (i < tw && j < tw && j >= i) ? H[(size_t)(t0 + i) * N + t0 + j]
+                                                          : cplx<double>{0, 0};
+                }
+            for (int r = 0; r < b; ++r) {
+                cplx<double> a[4], e[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    a[u] = P[(size_t)r * ldp + b + min(i0 + u, tw - 1)];
+                    e[u] = P[(size_t)r * ldp + b + min(j0 + u, tw - 1)];
+                }
+#pragma unroll
+                for (int u = 0; u < 4; ++u)
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) {
+                        h[u][v].x -= a[u].x * e[v].x + a[u].y * e[v].y;
+                        h[u][v].y -= a[u].x * e[v].y - a[u].y * e[v].x;
+                    }
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int i = i0 + u, j = j0 + v;
+                    if (i < tw && j < tw && j >= i) H[(size_t)(t0 + i) * N + t0 + j] = h[u][v];
+                }
         }
         __syncthreads();
     }
@@ -419,10 +477,43 @@ __global__ void __launch_bounds__(256) qr_finish_kernel(SvdArgs<R> a, const R* s
 
 }  // namespace
 
-size_t gram_cholesky_lds_bytes(int N, int kh, int kw) {
-    return sizeof(cplx<double>) * ((size_t)(2 * kh - 1) * (2 * kw - 1) + (size_t)kPanel * N) +
+namespace {
+size_t cholesky_lds_bytes(int N, int kh, int kw, int panel) {
+    return sizeof(cplx<double>) * ((size_t)(2 * kh - 1) * (2 * kw - 1) + (size_t)panel * (N + 1)) +
            sizeof(double) * 256;
 }
+
+template <typename R, int PANEL>
+hipError_t launch_cholesky_p(const GramArgs<R>& g, int items, hipStream_t s) {
+    const size_t lds = cholesky_lds_bytes(g.N, g.kh, g.kw, PANEL);
+    if (lds > 65536) {
+        const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(gram_cholesky_kernel<R, PANEL>),
+                                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL((gram_cholesky_kernel<R, PANEL>), dim3(items), dim3(256), lds, s, g);
+    return hipGetLastError();
+}
+
+// Work-groups of the Cholesky kernel with PANEL rows per panel that fit on
+// the device at once (0 on error).
+template <typename R, int PANEL>
+int cholesky_resident(const GramArgs<R>& g) {
+    const size_t lds = cholesky_lds_bytes(g.N, g.kh, g.kw, PANEL);
+    if (lds > 65536 && hipFuncSetAttribute(reinterpret_cast<const void*>(gram_cholesky_kernel<R, PANEL>),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
+        return 0;
+    int per_cu = 0, dev = 0, cus = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, gram_cholesky_kernel<R, PANEL>, 256, lds) !=
+            hipSuccess ||
+        hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+        return 0;
+    return per_cu * cus;
+}
+}  // namespace
+
+size_t gram_cholesky_lds_bytes(int N, int kh, int kw) { return cholesky_lds_bytes(N, kh, kw, kPanelMax); }
 
 template <typename R>
 hipError_t launch_gram_qr(const GramArgs<R>& g, int items, hipStream_t s) {
@@ -431,14 +522,11 @@ hipError_t launch_gram_qr(const GramArgs<R>& g, int items, hipStream_t s) {
     hipLaunchKernelGGL(gram_taps_kernel<R>, dim3(nt, nt, ND), dim3(256), 0, s, g);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || items <= 0) return e;
-    const size_t lds = gram_cholesky_lds_bytes(g.N, g.kh, g.kw);
-    if (lds > 65536) {
-        e = hipFuncSetAttribute(reinterpret_cast<const void*>(gram_cholesky_kernel<R>),
-                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        if (e != hipSuccess) return e;
-    }
-    hipLaunchKernelGGL(gram_cholesky_kernel<R>, dim3(items), dim3(256), lds, s, g);
-    return hipGetLastError();
+    // the tallest panel whose work-groups all fit on the device in one
+    // round (a second round of a few work-groups costs a whole factorisation)
+    if (items <= cholesky_resident<R, kPanelMax>(g)) return launch_cholesky_p<R, kPanelMax>(g, items, s);
+    if (items <= cholesky_resident<R, 12>(g)) return launch_cholesky_p<R, 12>(g, items, s);
+    return launch_cholesky_p<R, kPanelMax>(g, items, s);
 }
 
 template <typename R, int NW>

@@ -128,6 +128,39 @@ def test_svd_matches_oracle(case):
         check_projectors(S_ref, U_ref, V_ref, to_np(U), to_np(V), tdt, str(case))
 
 
+# (c_out, c_in, kh, kw, n, m, asm, vectors)
+MAT_CASES = [
+    (8, 6, 5, 5, 7, 10, None, True),        # 25 taps: matrix-core assembly by default; odd n
+    (6, 8, 5, 5, 10, 7, None, False),       # odd m, c_out < c_in
+    (5, 3, 3, 3, 4, 6, "mfma", True),
+    (12, 12, 9, 9, 9, 10, "bf16x3", False),  # 81 taps: the kernel without held phases
+    (16, 16, 3, 3, 9, 9, "bf16x2", True),
+]
+
+
+@pytest.mark.parametrize("case", MAT_CASES)
+def test_materialised_assembly_svd_matches_oracle(case):
+    """The SVD with the symbols assembled on matrix cores first (only the
+    canonical symbol of each conjugate pair is formed): sigma over the whole
+    grid against the oracle, and with vectors the residuals of every symbol,
+    mirrors included."""
+    c_out, c_in, kh, kw, n, m, asm, vectors = case
+    banner(f"materialised svd {case}")
+    _, W = workloads.random_layer(c_out, c_in, kh, kw, n, m, seed=12, dtype=np.float32)
+    out, info = lfa().svd(_w(W), n, m, asm=asm, compute_uv=vectors, return_info=True)
+    torch.cuda.synchronize()
+    S = out[0] if vectors else out
+    info = to_np(info)
+    assert info[0] == 0 and info[3] == 0, f"info {info}"
+    A = oracle.symbols(W.astype(np.float64), n, m)
+    S_ref = oracle.svd_symbols(A, compute_uv=False)
+    gate = 3e-5 if asm == "bf16x2" else sigma_gate(torch.float32)
+    e = oracle.sigma_error(to_np(S), S_ref)
+    assert e <= gate, f"sigma error {e:.3e}"
+    if vectors and asm != "bf16x2":
+        check_vectors(A, to_np(S), to_np(out[1]), to_np(out[2]), torch.float32, str(case))
+
+
 def test_brute_force_size_against_dense_operator():
     """4->4 channels on the 8x8 grid: sigma of the GPU path == sigma of the
     dense 256x256 operator (LAPACK on the CPU)."""
@@ -1066,16 +1099,19 @@ def _sample(n, m, count, seed):
 @pytest.mark.parametrize("vectors", [False, True])
 def test_rectangular_512x256_full_size_sampled(vectors):
     """256 -> 512 channels, 3x3, 32x32 grid (1024 symbols of 512 x 256), in
-    the benchmark's launch configuration: 12 sampled symbols against the
-    oracle (sigma; with vectors also residual, orthonormality and
-    projectors), Parseval over the whole grid."""
+    the benchmark's launch configuration: 12 sampled symbols and the last
+    canonical ones against the oracle (sigma; with vectors also residual,
+    orthonormality and projectors), Parseval over the whole grid."""
     banner(f"512x256 full size, vectors={vectors}")
     L, W = workloads.rectangular_256_512()
     out, info = lfa().svd(_w(W), L.n, L.m, compute_uv=vectors, return_info=True)
     torch.cuda.synchronize()
     S = out[0] if vectors else out
     assert info[0] == 0 and info[3] == 0, info
-    fr = _sample(L.n, L.m, 12, 5)
+    # plus the last canonical frequencies (row n/2 of the grid, up to m/2),
+    # which the teams of the short last round decompose, and a mirror
+    fr = np.concatenate([_sample(L.n, L.m, 12, 5),
+                         [[L.n // 2, L.m // 2 - 1], [L.n // 2, L.m // 2], [L.n // 2, L.m // 2 + 1]]])
     A = oracle.symbols(W.astype(np.float64), L.n, L.m, fr)
     S_ref, U_ref, V_ref = oracle.svd_symbols(A, compute_uv=True)
     Sg = to_np(S)[fr[:, 0], fr[:, 1]]
