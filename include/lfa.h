@@ -86,8 +86,16 @@ enum lfa_flags {
                              fusing the assembly into the SVD kernel           */
     LFA_ASM_BF16X2 = 8u,  /* as LFA_ASM_MFMA, split-BF16 with 3 products
                              (hi*hi + hi*lo + lo*hi), FP32 accumulation          */
-    LFA_ASM_BF16X3 = 16u  /* as LFA_ASM_MFMA, split-BF16 with 6 products
+    LFA_ASM_BF16X3 = 16u, /* as LFA_ASM_MFMA, split-BF16 with 6 products
                              (three-term split), FP32 accumulation               */
+    LFA_PHASE_NORMALIZE = 32u  /* fix the phase of every singular pair: a pair
+                             (u_j, v_j) is determined only up to a common factor
+                             e^{i phi}; the SVD calls that write U or V multiply
+                             both by the factor that makes the entry of largest
+                             modulus of v_j real and positive (the lowest row
+                             on ties), or of u_j when the plan writes U alone.
+                             Post-processing of Algorithm 1's SVD step; needs
+                             LFA_WANT_U or LFA_WANT_V (else INVALID_ARG)        */
 };
 
 enum lfa_status {
@@ -223,7 +231,8 @@ int lfa_symbols(const lfa_plan* plan, const void* const* W, void* const* A, void
  *   info  : device int32 [num_layers][LFA_INFO_WORDS] or NULL
  *   ws    : device workspace of ws_bytes >= lfa_plan_workspace_bytes
  * The plain path: one launch per layer (plus one assembly launch per layer
- * when the plan asks for MFMA/BF16 assembly). */
+ * when the plan asks for MFMA/BF16 assembly, and one phase launch per layer
+ * with LFA_PHASE_NORMALIZE). */
 int lfa_svd(const lfa_plan* plan, const void* const* W, void* const* sigma, void* const* U,
             void* const* V, int32_t* info, void* ws, size_t ws_bytes, void* stream);
 

@@ -17,6 +17,9 @@ complex128, with NumPy/LAPACK as the only library primitives:
   (Sec. III, "Convolution Theorem"; Algorithm 1, symbol step).
 * ``svd_symbols``      -- per-frequency SVD A_k = U_k S_k V_k^* (Sec. III,
   "Convolution Theorem"; Algorithm 1, SVD step) via ``numpy.linalg.svd``.
+* ``phase_normalize``  -- the common phase of each singular pair fixed so that
+  the largest-modulus entry of v_j is real and positive (post-processing of
+  the SVD step; a convention, the paper leaves the phase open).
 * ``unrolled_operator``-- the dense matrix of (A*f)(x) = sum_y M_y f(x+y) on the
   periodic torus (Sec. I matrix view; Sec. III "Convolutional Mappings").
 * ``lift``             -- global singular vectors F_k U_k, F_k V_k (Sec. III,
@@ -49,6 +52,7 @@ from .lfa64 import (  # noqa: F401
     phase_factors,
     symbols,
     svd_symbols,
+    phase_normalize,
     lfa_svd,
     unrolled_operator,
     dirichlet_operator,

@@ -118,6 +118,33 @@ def svd_symbols(A: np.ndarray, compute_uv: bool = True):
     return s, U, V
 
 
+def phase_normalize(U, V):
+    """Fix the free phase of every singular pair (post-processing of
+    Algorithm 1's SVD step; the paper leaves the phase open).  A pair
+    ``(u_j, v_j)`` of ``A = U diag(s) V^H`` may be multiplied by any common
+    ``e^{i phi}``; this picks the one that makes the entry of largest modulus
+    of ``v_j`` real and positive, the lowest row on ties (of ``u_j`` when
+    ``V`` is None).  ``U [..., c_out, r]`` and ``V [..., c_in, r]`` (either may
+    be None); returns the normalised copies."""
+    key = V if V is not None else U
+    key = np.asarray(key, dtype=np.complex128)
+    rows = key.shape[-2]
+    out = []
+    flat_key = key.reshape(-1, rows, key.shape[-1])
+    phases = np.ones((flat_key.shape[0], key.shape[-1]), dtype=np.complex128)
+    for b in range(flat_key.shape[0]):
+        for j in range(key.shape[-1]):
+            col = flat_key[b, :, j]
+            mod2 = col.real ** 2 + col.imag ** 2
+            i = int(np.argmax(mod2))          # first index of the maximum
+            if mod2[i] > 0:
+                phases[b, j] = np.conj(col[i]) / np.abs(col[i])
+    phases = phases.reshape(key.shape[:-2] + (1, key.shape[-1]))
+    for X in (U, V):
+        out.append(None if X is None else np.asarray(X, dtype=np.complex128) * phases)
+    return out[0], out[1]
+
+
 def lfa_svd(W, n: int, m: int | None = None, compute_uv: bool = False, freqs=None):
     """Algorithm 1 end to end: symbols at every frequency, then their SVD."""
     A = symbols(W, n, m, freqs)

@@ -19,6 +19,7 @@ LFA_WANT_V = 2
 LFA_ASM_MFMA = 4
 LFA_ASM_BF16X2 = 8
 LFA_ASM_BF16X3 = 16
+LFA_PHASE_NORMALIZE = 32
 
 LFA_SPECTRAL_IDENTITY = 0
 LFA_SPECTRAL_CLIP = 1

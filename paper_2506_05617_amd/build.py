@@ -21,7 +21,7 @@ LIB_NAME = "liblfa.so"
 LIB_PATH = os.path.join(PKG, LIB_NAME)
 
 HIP_SOURCES = ["jacobi.hip", "jacobi_wave.hip", "persistent.hip", "assemble.hip", "topk.hip", "apply.hip",
-               "crystal.hip", "noalloc.hip", "qr.hip"]
+               "crystal.hip", "noalloc.hip", "qr.hip", "phase.hip"]
 HOST_SOURCES = ["api.cpp"]
 
 # Packed FP32 instructions are disabled for all device code.

@@ -868,6 +868,25 @@ int svd_layer(const lfa_plan* p, size_t i, const void* const* W, const void* con
     return LFA_OK;
 }
 
+// LFA_PHASE_NORMALIZE: the phase pass over every layer's written vectors
+// (every frequency, mirrors included).
+template <typename R>
+int phase_pass(const lfa_plan* p, void* const* U, void* const* V, hipStream_t st) {
+    if (!(p->flags & LFA_PHASE_NORMALIZE)) return LFA_OK;
+    const bool wu = p->flags & LFA_WANT_U, wv = p->flags & LFA_WANT_V;
+    for (size_t i = 0; i < p->layers.size(); ++i) {
+        const lfa_layer& l = p->layers[i];
+        const int r = std::min(l.c_out, l.c_in);
+        cplx<R>* u = wu ? static_cast<cplx<R>*>(U[i]) : nullptr;
+        cplx<R>* v = wv ? static_cast<cplx<R>*>(V[i]) : nullptr;
+        hipError_t e;
+        if constexpr (sizeof(R) == 4) e = launch_phase_normalize_f32(u, v, l.n * l.m, l.c_out, l.c_in, r, st);
+        else e = launch_phase_normalize_f64(u, v, l.n * l.m, l.c_out, l.c_in, r, st);
+        HIP_TRY(e);
+    }
+    return LFA_OK;
+}
+
 template <typename R>
 int svd_impl(const lfa_plan* p, const void* const* W, const void* const* A, void* const* sigma,
              void* const* U, void* const* V, int32_t* info, void* ws, size_t ws_bytes,
@@ -877,7 +896,7 @@ int svd_impl(const lfa_plan* p, const void* const* W, const void* const* A, void
     if (info) HIP_TRY(launch_fill_i32(info, 0, (long long)p->layers.size() * LFA_INFO_WORDS, st));
     for (size_t i = 0; i < p->layers.size(); ++i)
         LFA_TRY(svd_layer<R>(p, i, W, A, sigma, U, V, info, region, st, queue_ok));
-    return LFA_OK;
+    return phase_pass<R>(p, U, V, st);
 }
 
 int check_ptrs(const lfa_plan* p, const void* const* arr, bool required) {
@@ -949,7 +968,7 @@ int persistent_impl(const lfa_plan* p, const void* const* W, void* const* sigma,
         else e = launch_persistent_f64(pa, grid, p->pers_lds[chunk], p->pers_acc, st);
         HIP_TRY(e);
     }
-    return LFA_OK;
+    return phase_pass<R>(p, U, V, st);
 }
 
 }  // namespace
@@ -1638,8 +1657,10 @@ int lfa_plan_create(lfa_plan** out, const lfa_layer* layers, int32_t num_layers,
     *out = nullptr;
     if (!layers || num_layers < 1 || num_layers > kMaxLayers) return LFA_ERR_INVALID_ARG;
     if (dtype != LFA_F32 && dtype != LFA_F64) return LFA_ERR_INVALID_ARG;
-    const uint32_t known = LFA_WANT_U | LFA_WANT_V | LFA_ASM_MFMA | LFA_ASM_BF16X2 | LFA_ASM_BF16X3;
+    const uint32_t known =
+        LFA_WANT_U | LFA_WANT_V | LFA_ASM_MFMA | LFA_ASM_BF16X2 | LFA_ASM_BF16X3 | LFA_PHASE_NORMALIZE;
     if (flags & ~known) return LFA_ERR_INVALID_ARG;
+    if ((flags & LFA_PHASE_NORMALIZE) && !(flags & (LFA_WANT_U | LFA_WANT_V))) return LFA_ERR_INVALID_ARG;
     const uint32_t asm_flags = flags & (LFA_ASM_MFMA | LFA_ASM_BF16X2 | LFA_ASM_BF16X3);
     if (asm_flags & (asm_flags - 1)) return LFA_ERR_INVALID_ARG;   // more than one
     if (asm_flags && dtype != LFA_F32) return LFA_ERR_UNSUPPORTED;

@@ -362,6 +362,14 @@ int wave_queue_blocks_per_cu(int nc, int ml, int elem_bytes, int threads, bool v
 hipError_t launch_svd_f32(const SvdArgs<float>& a, int grid, size_t lds, hipStream_t s);
 hipError_t launch_svd_f64(const SvdArgs<double>& a, int grid, size_t lds, hipStream_t s);
 
+// LFA_PHASE_NORMALIZE on one layer's outputs: syms symbols of U
+// [syms][rows_u][r] and V [syms][rows_v][r] (either may be null; the phase
+// comes from V when it is there).
+hipError_t launch_phase_normalize_f32(cplx<float>* U, cplx<float>* V, int syms, int rows_u, int rows_v, int r,
+                                      hipStream_t s);
+hipError_t launch_phase_normalize_f64(cplx<double>* U, cplx<double>* V, int syms, int rows_u, int rows_v, int r,
+                                      hipStream_t s);
+
 hipError_t launch_symbols_valu_f32(const LayerDesc& d, const float* W, cplx<float>* A,
                                    const double* tw, hipStream_t s);
 hipError_t launch_symbols_valu_f64(const LayerDesc& d, const double* W, cplx<double>* A,

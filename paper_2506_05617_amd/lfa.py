@@ -64,12 +64,14 @@ class Plan:
     """
 
     def __init__(self, layers: Sequence[LayerSpec], dtype=torch.float32, want_u=False,
-                 want_v=False, asm=None):
+                 want_v=False, asm=None, phase_normalize=False):
         self.lib = _lib.load()
         self.layers = [LayerSpec(*l) if not isinstance(l, LayerSpec) else l for l in layers]
         self.dtype = dtype
         self.want_u, self.want_v, self.asm = want_u, want_v, asm
         flags = (_lib.LFA_WANT_U if want_u else 0) | (_lib.LFA_WANT_V if want_v else 0) | _asm_flag(asm)
+        if phase_normalize:
+            flags |= _lib.LFA_PHASE_NORMALIZE
         arr = (_lib.LfaLayer * len(self.layers))(
             *[_lib.LfaLayer(l.c_out, l.c_in, l.kh, l.kw, l.n, l.m) for l in self.layers])
         h = ctypes.c_void_p()
@@ -490,11 +492,11 @@ class GraphStep:
 _PLANS = {}
 
 
-def _plan_for(specs, dtype, want_u, want_v, asm=None):
-    key = (tuple(specs), dtype, want_u, want_v, asm)
+def _plan_for(specs, dtype, want_u, want_v, asm=None, phase_normalize=False):
+    key = (tuple(specs), dtype, want_u, want_v, asm, phase_normalize)
     p = _PLANS.get(key)
     if p is None:
-        p = Plan(specs, dtype, want_u, want_v, asm)
+        p = Plan(specs, dtype, want_u, want_v, asm, phase_normalize)
         _PLANS[key] = p
     return p
 
@@ -509,9 +511,11 @@ def symbols(W, n, m=None, asm=None):
     return _plan_for([_spec(W, n, m)], W.dtype, False, False, asm).symbols([W])[0]
 
 
-def svd(W, n, m=None, compute_uv=False, asm=None, return_info=False):
-    """Singular values [n, m, r] (and U, V if compute_uv) of one layer."""
-    p = _plan_for([_spec(W, n, m)], W.dtype, compute_uv, compute_uv, asm)
+def svd(W, n, m=None, compute_uv=False, asm=None, return_info=False, phase_normalize=False):
+    """Singular values [n, m, r] (and U, V if compute_uv) of one layer; with
+    phase_normalize (and compute_uv) every pair (u_j, v_j) is multiplied by
+    the phase that makes the largest-modulus entry of v_j real positive."""
+    p = _plan_for([_spec(W, n, m)], W.dtype, compute_uv, compute_uv, asm, phase_normalize and compute_uv)
     S, U, V, info = p.svd([W])
     out = (S[0], U[0], V[0]) if compute_uv else S[0]
     return (out, info[0]) if return_info else out

@@ -71,6 +71,9 @@ def _create(layers, dtype=0, flags=0):
     ((16, 16, 3, 3, 32, 32), 0, 1 << 10, -1),     # unknown flag
     ((16, 16, 3, 3, 32, 32), 0, 8 | 16, -1),      # two assembly modes
     ((16, 16, 3, 3, 32, 32), 1, 8, -2),           # BF16 assembly needs FP32
+    ((16, 16, 3, 3, 32, 32), 0, 32, -1),          # phase normalisation without vectors
+    ((16, 16, 3, 3, 32, 32), 0, 32 | 2, 0),       # ... with V
+    ((16, 16, 3, 3, 32, 32), 1, 32 | 1, 0),       # ... with U alone
     ((1024, 16, 3, 3, 8, 8), 0, 0, -2),           # more rows than one work-group holds
     ((16, 16, 13, 13, 16, 16), 0, 0, -2),         # more than 128 taps
 ])

@@ -161,6 +161,87 @@ def test_materialised_assembly_svd_matches_oracle(case):
         check_vectors(A, to_np(S), to_np(out[1]), to_np(out[2]), torch.float32, str(case))
 
 
+# (c_out, c_in, kh, kw, n, m, dtype)
+PHASE_CASES = [
+    (16, 12, 3, 3, 5, 6, np.float64),      # register kernel, FP64
+    (24, 40, 3, 3, 4, 5, np.float32),      # wide layer: G = A^H
+    (64, 64, 3, 3, 6, 5, np.float32),      # the headline's symbols (work queue)
+    (160, 96, 3, 3, 3, 4, np.float32),     # blocked kernel
+    (256, 128, 3, 3, 4, 4, np.float32),    # QR preconditioning (tall)
+]
+
+
+@pytest.mark.parametrize("case", PHASE_CASES)
+def test_phase_normalize_matches_oracle(case, monkeypatch):
+    """LFA_PHASE_NORMALIZE: sigma bitwise that of the plan without the flag,
+    each (u_j, v_j) that plan's pair times one common phase, the
+    largest-modulus entry of every v_j real and positive, and, for simple
+    singular values whose v_j has a clear largest entry, U and V elementwise
+    equal to the oracle's SVD after the oracle's phase_normalize."""
+    c_out, c_in, kh, kw, n, m, dt = case
+    if c_out >= 256:
+        monkeypatch.setenv("LFA_QR", "1")
+    banner(f"phase normalize {case}")
+    _, W = workloads.random_layer(c_out, c_in, kh, kw, n, m, seed=13, dtype=dt)
+    tdt = torch.float32 if dt == np.float32 else torch.float64
+    S0, U0, V0 = lfa().svd(_w(W), n, m, compute_uv=True)
+    (S, U, V), info = lfa().svd(_w(W), n, m, compute_uv=True, phase_normalize=True, return_info=True)
+    torch.cuda.synchronize()
+    assert to_np(info)[0] == 0
+    assert torch.equal(S, S0)
+    S, U, V, U0, V0 = to_np(S), to_np(U), to_np(V), to_np(U0), to_np(V0)
+    # one common phase per pair: v_j = v0_j z_j and u_j = u0_j z_j, |z_j| = 1
+    z = np.sum(np.conj(V0) * V, axis=-2)                      # [n, m, r]
+    np.testing.assert_allclose(np.abs(z), 1, atol=1e-5 if dt == np.float32 else 1e-12)
+    np.testing.assert_allclose(V, V0 * z[..., None, :], atol=1e-6 if dt == np.float32 else 1e-13)
+    np.testing.assert_allclose(U, U0 * z[..., None, :], atol=1e-6 if dt == np.float32 else 1e-13)
+    # an entry of modulus max |v_j| is exactly real and positive
+    mod = np.abs(V)
+    top = mod.max(axis=-2, keepdims=True)
+    realpos = (V.imag == 0) & (V.real > 0) & (mod >= top * (1 - 1e-6))
+    assert np.all(realpos.any(axis=-2))
+    # the oracle's normalised SVD, where the pair and its phase are unique
+    A = oracle.symbols(W.astype(np.float64), n, m)
+    S_ref, U_ref, V_ref = oracle.svd_symbols(A)
+    U_ref, V_ref = oracle.phase_normalize(U_ref, V_ref)
+    eps = 1e-6 if dt == np.float32 else 1e-13
+    smax = S_ref[..., :1]
+    d = np.abs(np.diff(S_ref, axis=-1))
+    gap = np.full(S_ref.shape, np.inf)
+    gap[..., :-1] = np.minimum(gap[..., :-1], d)
+    gap[..., 1:] = np.minimum(gap[..., 1:], d)
+    rel_gap = gap / smax
+    mref = np.sort(np.abs(V_ref), axis=-2)
+    sep = (mref[..., -1, :] - mref[..., -2, :]) / mref[..., -1, :]
+    ok = (rel_gap > 1e-3) & (sep > 1e-3) & (S_ref > 1e-3 * smax)
+    assert ok.sum() > 0
+    bound = eps * (10 + 1 / rel_gap) * (1 + 1 / sep)
+    ev = np.max(np.abs(V - V_ref), axis=-2)
+    eu = np.max(np.abs(U - U_ref), axis=-2)
+    assert np.all(ev[ok] <= bound[ok]), f"V: worst {np.max(ev[ok] / bound[ok]):.3e} of the bound"
+    assert np.all(eu[ok] <= bound[ok]), f"U: worst {np.max(eu[ok] / bound[ok]):.3e} of the bound"
+
+
+def test_phase_normalize_u_alone():
+    """LFA_PHASE_NORMALIZE with U alone: the rule applies to u_j, and the
+    pairs are those of the plan without the flag times one phase each."""
+    banner("phase normalize, U alone")
+    _, W = workloads.random_layer(32, 24, 3, 3, 4, 6, seed=14, dtype=np.float32)
+    spec = lfa().LayerSpec(32, 24, 3, 3, 4, 6)
+    S0, U0, _, _ = lfa().Plan([spec], torch.float32, True, False).svd([_w(W)])
+    S1, U1, V1, _ = lfa().Plan([spec], torch.float32, True, False, phase_normalize=True).svd([_w(W)])
+    torch.cuda.synchronize()
+    assert V1[0] is None
+    assert torch.equal(S0[0], S1[0])
+    U0, U1 = to_np(U0[0]), to_np(U1[0])
+    z = np.sum(np.conj(U0) * U1, axis=-2)
+    np.testing.assert_allclose(np.abs(z), 1, atol=1e-5)
+    np.testing.assert_allclose(U1, U0 * z[..., None, :], atol=1e-6)
+    mod = np.abs(U1)
+    realpos = (U1.imag == 0) & (U1.real > 0) & (mod >= mod.max(axis=-2, keepdims=True) * (1 - 1e-6))
+    assert np.all(realpos.any(axis=-2))
+
+
 def test_brute_force_size_against_dense_operator():
     """4->4 channels on the 8x8 grid: sigma of the GPU path == sigma of the
     dense 256x256 operator (LAPACK on the CPU)."""

@@ -617,3 +617,53 @@ def test_boundary_study_c16_gap_shrinks_with_the_grid():
         W = bs.layer(n, 41)
         sd = np.linalg.svd(oracle.dirichlet_operator(W, n, n), compute_uv=False)
         assert sd[0] <= oracle.lfa_svd(W, n + 2, n + 2).max() * (1 + 1e-12)
+
+
+# --- Phase normalisation of the singular pairs ----------------------------
+
+def test_phase_normalize_hand_examples():
+    """oracle.phase_normalize on pairs whose answer is written out by hand:
+    the entry of largest modulus of v becomes real positive, u takes the
+    same factor, the lowest row wins an exact tie, and with V absent the
+    rule applies to u."""
+    s = 1 / np.sqrt(2)
+    # already normalised: the largest entry (0.8, row 1) is real positive
+    U, V = oracle.phase_normalize(np.array([[1j]]), np.array([[0.6j], [0.8]]))
+    np.testing.assert_allclose(V, [[0.6j], [0.8]], atol=1e-15)
+    np.testing.assert_allclose(U, [[1j]], atol=1e-15)
+    # largest entry 0.8i (row 0): the factor is -i
+    U, V = oracle.phase_normalize(np.array([[1.0]]), np.array([[0.8j], [0.6]]))
+    np.testing.assert_allclose(V, [[0.8], [-0.6j]], atol=1e-15)
+    np.testing.assert_allclose(U, [[-1j]], atol=1e-15)
+    # exact tie |i/sqrt2| = |1/sqrt2|: row 0 decides, factor -i
+    _, V = oracle.phase_normalize(None, np.array([[1j * s], [s]]))
+    np.testing.assert_allclose(V, [[s], [-1j * s]], atol=1e-15)
+    # U alone: the largest entry -2 (row 0) becomes 2
+    U, V = oracle.phase_normalize(np.array([[-2.0], [1.0]]), None)
+    assert V is None
+    np.testing.assert_allclose(U, [[2.0], [-1.0]], atol=1e-15)
+    # two columns normalised independently
+    _, V = oracle.phase_normalize(None, np.array([[1j, 0.1], [0.1, -3.0]]))
+    np.testing.assert_allclose(V, [[1, 0.1 * -1], [-0.1j, 3.0]], atol=1e-15)
+
+
+def test_phase_normalize_removes_the_gauge():
+    """Any SVD of a matrix with simple singular values differs from another
+    by one phase per pair (U D, V D with D diagonal unitary).  After
+    oracle.phase_normalize two such SVDs are the same, the factorisation
+    A = U diag(s) V^H still holds, every largest entry of v_j is real
+    positive, and a second normalisation changes nothing."""
+    rng = np.random.default_rng(3)
+    A = rng.standard_normal((4, 7, 5)) + 1j * rng.standard_normal((4, 7, 5))
+    s, U, V = oracle.svd_symbols(A)
+    D = np.exp(2j * np.pi * rng.random((4, 1, 5)))
+    U1, V1 = oracle.phase_normalize(U, V)
+    U2, V2 = oracle.phase_normalize(U * D, V * D)
+    np.testing.assert_allclose(U1, U2, atol=1e-12)
+    np.testing.assert_allclose(V1, V2, atol=1e-12)
+    np.testing.assert_allclose((U1 * s[:, None, :]) @ np.conj(np.swapaxes(V1, -1, -2)), A, atol=1e-12)
+    top = np.take_along_axis(V1, np.argmax(np.abs(V1), axis=1)[:, None, :], axis=1)
+    assert np.all(top.real > 0) and np.all(np.abs(top.imag) <= 1e-15 * top.real)
+    U3, V3 = oracle.phase_normalize(U1, V1)
+    np.testing.assert_allclose(U3, U1, atol=1e-15)
+    np.testing.assert_allclose(V3, V1, atol=1e-15)
