@@ -230,14 +230,18 @@ __global__ void __launch_bounds__(256) symbols_mfma(LayerDesc d, const float* __
 }
 
 // ---------------------------------------------- MFMA, phases held --------
-// For up to kMfma2MaxTaps taps.  A block of 4 waves owns 64 frequencies (16
-// per wave) and loops over column tiles of 64 e: the phases of its
-// frequencies are evaluated once, as ready MFMA A-fragments in registers
-// (one set per bfloat16 split term in the split modes), and each 64 x T tile
-// of W is staged once in LDS (as its split terms) and shared by the four
-// waves.  The split modes run one accumulation pass over K = taps per product
-// (A term, W term) of kSegA / kSegB into the same accumulators.
+// For up to kMfma2MaxTaps taps.  A block of 4 waves owns 64 kMfma2Freq
+// frequencies (16 kMfma2Freq per wave, as kMfma2Freq sub-tiles of 16) and
+// loops over column tiles of 64 e: the phases of its frequencies are
+// evaluated once, as ready MFMA A-fragments in registers (one set per
+// bfloat16 split term in the split modes), and each 64 x T tile of W is
+// staged once in LDS (as its split terms) and shared by the four waves; each
+// B fragment read from LDS feeds the MFMAs of every sub-tile.  The next
+// tile's W values are loaded into registers while the matrix cores work on
+// the current one.  The split modes run one accumulation pass over K = taps
+// per product (A term, W term) of kSegA / kSegB into the same accumulators.
 constexpr int kMfma2MaxTaps = 64;
+constexpr int kMfma2Freq = 2;      // 16-frequency sub-tiles per wave (FP32)
 
 // Products of split terms, (A term, W term), in the order of kSegA / kSegB.
 constexpr int kProdA[2][6] = {{0, 0, 1, 0, 0, 0}, {0, 0, 1, 0, 1, 2}};
@@ -250,9 +254,10 @@ struct Mfma2 {
     static constexpr int KSTEP = MODE == 0 ? 4 : 16;
     static constexpr int KS = kMfma2MaxTaps / KSTEP;                         // max K steps
     static constexpr int ROW = MODE == 0 ? kMfma2MaxTaps + 1 : kMfma2MaxTaps + 4;   // LDS row, padded
+    static constexpr int PER = (64 * ROW + 255) / 256;                       // W values per thread per tile
 };
 
-template <int MODE>
+template <int MODE, int FT>
 __global__ void __launch_bounds__(256) symbols_mfma2(LayerDesc d, const float* __restrict__ W,
                                                      cplx<float>* __restrict__ A,
                                                      const double* __restrict__ tw, int echunk, int canon) {
@@ -264,74 +269,96 @@ __global__ void __launch_bounds__(256) symbols_mfma2(LayerDesc d, const float* _
     const int HW = canon ? d.num_canon : d.num_symbols;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int li = lane & 15, lk = lane >> 4;
-    const int theta0 = blockIdx.y * 64 + wave * 16;
-    const int theta_a = theta0 + li;
-    const int freq_a = theta_a < HW ? row_theta(d, canon, theta_a) : 0;
+    const int theta0 = blockIdx.y * 64 * FT + wave * 16 * FT;
     const int ks = (T + C::KSTEP - 1) / C::KSTEP;     // K steps actually used
 
-    // A-fragments (phases) of this wave's 16 frequencies: lane (li, lk) holds
-    // row theta0 + li at taps 4 kt + lk (FP32) or 16 kt + 4 lk + v (bf16)
-    float pr[MODE == 0 ? C::KS : 1], pi[MODE == 0 ? C::KS : 1];
-    bf16x4 ar[C::TERMS][MODE == 0 ? 1 : C::KS], ai[C::TERMS][MODE == 0 ? 1 : C::KS];
+    // A-fragments (phases) of this wave's frequencies: in sub-tile f, lane
+    // (li, lk) holds row theta0 + 16 f + li at taps 4 kt + lk (FP32) or
+    // 16 kt + 4 lk + v (bf16)
+    float pr[FT][MODE == 0 ? C::KS : 1], pi[FT][MODE == 0 ? C::KS : 1];
+    bf16x4 ar[FT][C::TERMS][MODE == 0 ? 1 : C::KS], ai[FT][C::TERMS][MODE == 0 ? 1 : C::KS];
 #pragma unroll
-    for (int kt = 0; kt < C::KS; ++kt) {
-        if constexpr (MODE == 0) {
-            const int t = 4 * kt + lk;
-            float r = 0.f, im = 0.f;
-            if (kt < ks && t < T && theta_a < HW) {
-                double re, imd;
-                phase_d(tw, d, freq_a, t, re, imd);
-                r = float(re);
-                im = float(imd);
-            }
-            pr[kt] = r;
-            pi[kt] = im;
-        } else {
+    for (int f = 0; f < FT; ++f) {
+        const int theta_a = theta0 + 16 * f + li;
+        const int freq_a = theta_a < HW ? row_theta(d, canon, theta_a) : 0;
 #pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const int t = 16 * kt + 4 * lk + v;
-                unsigned short sr[3] = {0, 0, 0}, si[3] = {0, 0, 0};
+        for (int kt = 0; kt < C::KS; ++kt) {
+            if constexpr (MODE == 0) {
+                const int t = 4 * kt + lk;
+                float r = 0.f, im = 0.f;
                 if (kt < ks && t < T && theta_a < HW) {
                     double re, imd;
                     phase_d(tw, d, freq_a, t, re, imd);
-                    split_bf16(float(re), C::TERMS, sr);
-                    split_bf16(float(imd), C::TERMS, si);
+                    r = float(re);
+                    im = float(imd);
                 }
+                pr[f][kt] = r;
+                pi[f][kt] = im;
+            } else {
 #pragma unroll
-                for (int u = 0; u < C::TERMS; ++u) {
-                    ar[u][kt][v] = (short)sr[u];
-                    ai[u][kt][v] = (short)si[u];
+                for (int v = 0; v < 4; ++v) {
+                    const int t = 16 * kt + 4 * lk + v;
+                    unsigned short sr[3] = {0, 0, 0}, si[3] = {0, 0, 0};
+                    if (kt < ks && t < T && theta_a < HW) {
+                        double re, imd;
+                        phase_d(tw, d, freq_a, t, re, imd);
+                        split_bf16(float(re), C::TERMS, sr);
+                        split_bf16(float(imd), C::TERMS, si);
+                    }
+#pragma unroll
+                    for (int u = 0; u < C::TERMS; ++u) {
+                        ar[f][u][kt][v] = (short)sr[u];
+                        ai[f][u][kt][v] = (short)si[u];
+                    }
                 }
             }
         }
     }
 
+    // W tile rows e0 .. e0+63 of T taps each (contiguous in W), zero beyond
+    // T: fetched into registers, then put into LDS (split modes: one plane
+    // per split term)
     const int e_begin = blockIdx.x * echunk, e_end = min(E, e_begin + echunk);
-    for (int e0 = e_begin; e0 < e_end; e0 += 64) {
-        // stage the W tile: rows e0 .. e0+63 of T taps each (contiguous in W),
-        // zero beyond T; split modes: one plane per split term
-        __syncthreads();
-        for (int x = threadIdx.x; x < 64 * C::ROW; x += blockDim.x) {
+    float wreg[C::PER];
+    auto fetch = [&](int e0) {
+#pragma unroll
+        for (int u = 0; u < C::PER; ++u) {
+            const int x = threadIdx.x + 256 * u;
             const int r = x / C::ROW, t = x - r * C::ROW;
             const int e = e0 + r;
-            const float w = (t < T && e < E) ? W[(size_t)e * T + t] : 0.f;
+            wreg[u] = (x < 64 * C::ROW && t < T && e < E) ? W[(size_t)e * T + t] : 0.f;
+        }
+    };
+    auto put = [&]() {
+#pragma unroll
+        for (int u = 0; u < C::PER; ++u) {
+            const int x = threadIdx.x + 256 * u;
+            if (x >= 64 * C::ROW) continue;
             if constexpr (MODE == 0) {
-                reinterpret_cast<float*>(lds_raw)[x] = w;
+                reinterpret_cast<float*>(lds_raw)[x] = wreg[u];
             } else {
                 unsigned short sw[3] = {0, 0, 0};
-                split_bf16(w, C::TERMS, sw);
+                split_bf16(wreg[u], C::TERMS, sw);
 #pragma unroll
-                for (int u = 0; u < C::TERMS; ++u)
-                    reinterpret_cast<unsigned short*>(lds_raw)[u * 64 * C::ROW + x] = sw[u];
+                for (int q = 0; q < C::TERMS; ++q)
+                    reinterpret_cast<unsigned short*>(lds_raw)[q * 64 * C::ROW + x] = sw[q];
             }
         }
+    };
+    if (e_begin < e_end) fetch(e_begin);
+    for (int e0 = e_begin; e0 < e_end; e0 += 64) {
+        __syncthreads();          // the previous tile's readers are done
+        put();
         __syncthreads();
-        floatx4 acc_re[4], acc_im[4];
+        if (e0 + 64 < e_end) fetch(e0 + 64);       // in flight during the MFMAs
+        floatx4 acc_re[FT][4], acc_im[FT][4];
 #pragma unroll
-        for (int s = 0; s < 4; ++s) {
-            acc_re[s] = floatx4{0.f, 0.f, 0.f, 0.f};
-            acc_im[s] = floatx4{0.f, 0.f, 0.f, 0.f};
-        }
+        for (int f = 0; f < FT; ++f)
+#pragma unroll
+            for (int s = 0; s < 4; ++s) {
+                acc_re[f][s] = floatx4{0.f, 0.f, 0.f, 0.f};
+                acc_im[f][s] = floatx4{0.f, 0.f, 0.f, 0.f};
+            }
         if constexpr (MODE == 0) {
             const float* wl = reinterpret_cast<const float*>(lds_raw);
 #pragma unroll
@@ -340,8 +367,11 @@ __global__ void __launch_bounds__(256) symbols_mfma2(LayerDesc d, const float* _
 #pragma unroll
                     for (int s = 0; s < 4; ++s) {
                         const float b = wl[(s * 16 + li) * C::ROW + 4 * kt + lk];
-                        acc_re[s] = __builtin_amdgcn_mfma_f32_16x16x4f32(pr[kt], b, acc_re[s], 0, 0, 0);
-                        acc_im[s] = __builtin_amdgcn_mfma_f32_16x16x4f32(pi[kt], b, acc_im[s], 0, 0, 0);
+#pragma unroll
+                        for (int f = 0; f < FT; ++f) {
+                            acc_re[f][s] = __builtin_amdgcn_mfma_f32_16x16x4f32(pr[f][kt], b, acc_re[f][s], 0, 0, 0);
+                            acc_im[f][s] = __builtin_amdgcn_mfma_f32_16x16x4f32(pi[f][kt], b, acc_im[f][s], 0, 0, 0);
+                        }
                     }
                 }
             }
@@ -353,20 +383,23 @@ __global__ void __launch_bounds__(256) symbols_mfma2(LayerDesc d, const float* _
 #pragma unroll
                 for (int kt = 0; kt < C::KS; ++kt) {
                     if (kt < ks) {
-                        // split terms are selected with compile-time indices
-                        bf16x4 fa_r = ar[0][kt], fa_i = ai[0][kt];
-#pragma unroll
-                        for (int u = 1; u < C::TERMS; ++u)
-                            if (ta == u) {
-                                fa_r = ar[u][kt];
-                                fa_i = ai[u][kt];
-                            }
 #pragma unroll
                         for (int s = 0; s < 4; ++s) {
                             const bf16x4 b = *reinterpret_cast<const bf16x4*>(
                                 wl + tb * 64 * C::ROW + (s * 16 + li) * C::ROW + 16 * kt + 4 * lk);
-                            acc_re[s] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(fa_r, b, acc_re[s], 0, 0, 0);
-                            acc_im[s] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(fa_i, b, acc_im[s], 0, 0, 0);
+#pragma unroll
+                            for (int f = 0; f < FT; ++f) {
+                                // split terms are selected with compile-time indices
+                                bf16x4 fa_r = ar[f][0][kt], fa_i = ai[f][0][kt];
+#pragma unroll
+                                for (int u = 1; u < C::TERMS; ++u)
+                                    if (ta == u) {
+                                        fa_r = ar[f][u][kt];
+                                        fa_i = ai[f][u][kt];
+                                    }
+                                acc_re[f][s] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(fa_r, b, acc_re[f][s], 0, 0, 0);
+                                acc_im[f][s] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(fa_i, b, acc_im[f][s], 0, 0, 0);
+                            }
                         }
                     }
                 }
@@ -374,16 +407,137 @@ __global__ void __launch_bounds__(256) symbols_mfma2(LayerDesc d, const float* _
         }
         // D[i][j]: j = lane & 15 (e), i = 4*(lane >> 4) + v (frequency)
 #pragma unroll
+        for (int f = 0; f < FT; ++f)
+#pragma unroll
+            for (int s = 0; s < 4; ++s) {
+                const int e = e0 + s * 16 + li;
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int th = theta0 + 16 * f + 4 * lk + v;
+                    if (th < HW && e < E)
+                        store_stream(A + (size_t)row_theta(d, canon, th) * E + e, acc_re[f][s][v], acc_im[f][s][v]);
+                }
+            }
+    }
+}
+
+// ---------------------------------------------- MFMA, separable phases ----
+// FP32 matrix cores for kernels of at most kSepMaxRows rows.  The phase of
+// tap (a, b) at frequency (p, q) factors as e^{2 pi i p y1/n} e^{2 pi i q y2/m}
+// (y1, y2 the tap's offsets), so
+//     A_{p,q}[e] = sum_a e^{2 pi i p y1(a)/n} B_q[a][e],
+//     B_q[a][e]  = sum_b W[e][a][b] e^{2 pi i q y2(b)/m}.
+// A block takes one q and 64 columns e: it forms B_q for them (kh x 64
+// complex, into LDS, then into registers as MFMA B fragments), and its waves
+// run the contraction over a (K = kh rounded up to 4) for 16 frequencies p
+// at a time, as four real products per K step (Re Re and -Im Im into the
+// real part, Re Im and Im Re into the imaginary part): kh terms per output
+// instead of the kh kw of the direct contraction.
+constexpr int kSepMaxRows = 16;
+
+// (p, q) is the canonical frequency of its conjugate pair: the set that
+// canonical_theta enumerates (row 0 and, for even n, row n/2 up to q = m/2;
+// the rows 1 .. (n+1)/2 - 1 whole).
+__device__ __forceinline__ bool is_canonical(const LayerDesc& d, int p, int q) {
+    const int full = (d.n + 1) / 2 - 1;
+    if (p >= 1 && p <= full) return true;
+    if (p == 0 || (!(d.n & 1) && p == d.n / 2)) return 2 * q <= d.m;
+    return false;
+}
+
+__global__ void __launch_bounds__(256) symbols_sep(LayerDesc d, const float* __restrict__ W,
+                                                   cplx<float>* __restrict__ A, const double* __restrict__ tw,
+                                                   int canon) {
+    __shared__ float bre[kSepMaxRows][65], bim[kSepMaxRows][65];   // B_q[a][e - e0]
+    __shared__ float bq[2][kMaxTaps];                               // e^{2 pi i q y2(b)/m}
+    const int T = d.kh * d.kw, E = d.c_out * d.c_in;
+    const int e0 = blockIdx.x * 64, q = blockIdx.y;
+    const int KA = (d.kh + 3) & ~3;
+    for (int b = threadIdx.x; b < d.kw; b += blockDim.x) {
+        int i2 = (q * (b - (d.kw - 1) / 2)) % d.m;
+        if (i2 < 0) i2 += d.m;
+        bq[0][b] = float(tw[2 * (d.tw_m + i2)]);
+        bq[1][b] = float(tw[2 * (d.tw_m + i2) + 1]);
+    }
+    __syncthreads();
+    {
+        const int el = threadIdx.x & 63, e = e0 + el;
+        for (int a = threadIdx.x >> 6; a < KA; a += 4) {
+            float sr = 0.f, si = 0.f;
+            if (a < d.kh && e < E) {
+                const float* w = W + (size_t)e * T + a * d.kw;
+                for (int b = 0; b < d.kw; ++b) {
+                    sr = fmaf(w[b], bq[0][b], sr);
+                    si = fmaf(w[b], bq[1][b], si);
+                }
+            }
+            bre[a][el] = sr;
+            bim[a][el] = si;
+        }
+    }
+    __syncthreads();
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int li = lane & 15, lk = lane >> 4;
+    constexpr int KT = kSepMaxRows / 4;
+    const int ksteps = KA / 4;
+    // B fragments: lane (li, lk) holds B[k = 4 kt + lk][j = 16 s + li]
+    float fr[KT][4], fi[KT][4];
+#pragma unroll
+    for (int kt = 0; kt < KT; ++kt)
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+            fr[kt][s] = kt < ksteps ? bre[4 * kt + lk][16 * s + li] : 0.f;
+            fi[kt][s] = kt < ksteps ? bim[4 * kt + lk][16 * s + li] : 0.f;
+        }
+    const int p_end = canon ? d.n / 2 + 1 : d.n;
+    const int y1off = (d.kh - 1) / 2;
+    for (int p0 = wave * 16; p0 < p_end; p0 += 64) {
+        floatx4 yr[4], yi[4];
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+            yr[s] = floatx4{0.f, 0.f, 0.f, 0.f};
+            yi[s] = floatx4{0.f, 0.f, 0.f, 0.f};
+        }
+        const int p = p0 + li;      // row of the A operand this lane feeds
+#pragma unroll
+        for (int kt = 0; kt < KT; ++kt) {
+            if (kt < ksteps) {
+                const int a = 4 * kt + lk;
+                float ar = 0.f, ai = 0.f;
+                if (a < d.kh && p < d.n) {
+                    int i1 = (p * (a - y1off)) % d.n;
+                    if (i1 < 0) i1 += d.n;
+                    ar = float(tw[2 * (d.tw_n + i1)]);
+                    ai = float(tw[2 * (d.tw_n + i1) + 1]);
+                }
+#pragma unroll
+                for (int s = 0; s < 4; ++s) {
+                    yr[s] = __builtin_amdgcn_mfma_f32_16x16x4f32(ar, fr[kt][s], yr[s], 0, 0, 0);
+                    yr[s] = __builtin_amdgcn_mfma_f32_16x16x4f32(-ai, fi[kt][s], yr[s], 0, 0, 0);
+                    yi[s] = __builtin_amdgcn_mfma_f32_16x16x4f32(ar, fi[kt][s], yi[s], 0, 0, 0);
+                    yi[s] = __builtin_amdgcn_mfma_f32_16x16x4f32(ai, fr[kt][s], yi[s], 0, 0, 0);
+                }
+            }
+        }
+        // D[i][j]: j = lane & 15 (e), i = 4*(lane >> 4) + v (p)
+#pragma unroll
         for (int s = 0; s < 4; ++s) {
             const int e = e0 + s * 16 + li;
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
-                const int th = theta0 + 4 * lk + v;
-                if (th < HW && e < E)
-                    store_stream(A + (size_t)row_theta(d, canon, th) * E + e, acc_re[s][v], acc_im[s][v]);
+                const int pp = p0 + 4 * lk + v;
+                if (pp < d.n && e < E && (!canon || is_canonical(d, pp, q)))
+                    store_stream(A + ((size_t)pp * d.m + q) * E + e, yr[s][v], yi[s][v]);
             }
         }
     }
+}
+
+hipError_t launch_sep(const LayerDesc& d, const float* W, cplx<float>* A, const double* tw, int canon,
+                      hipStream_t s) {
+    const int E = d.c_out * d.c_in;
+    hipLaunchKernelGGL(symbols_sep, dim3((E + 63) / 64, d.m), dim3(256), 0, s, d, W, A, tw, canon);
+    return hipGetLastError();
 }
 
 template <int MODE>
@@ -391,11 +545,11 @@ constexpr size_t mfma2_lds_bytes() {
     return 64 * (size_t)Mfma2<MODE>::ROW * (MODE == 0 ? sizeof(float) : Mfma2<MODE>::TERMS * sizeof(unsigned short));
 }
 
-template <int MODE>
-hipError_t launch_mfma2(const LayerDesc& d, const float* W, cplx<float>* A, const double* tw, int canon,
-                        hipStream_t s) {
+template <int MODE, int FT>
+hipError_t launch_mfma2_ft(const LayerDesc& d, const float* W, cplx<float>* A, const double* tw, int canon,
+                           hipStream_t s) {
     const int E = d.c_out * d.c_in;
-    const int tblocks = ((canon ? d.num_canon : d.num_symbols) + 63) / 64;
+    const int tblocks = ((canon ? d.num_canon : d.num_symbols) + 64 * FT - 1) / (64 * FT);
     // enough blocks for the device: split the e range when there are few
     // frequency tiles (each block still covers >= 64 columns)
     const int etiles = (E + 63) / 64;
@@ -404,12 +558,21 @@ hipError_t launch_mfma2(const LayerDesc& d, const float* W, cplx<float>* A, cons
     const dim3 grid((E + echunk - 1) / echunk, tblocks);
     const size_t lds = mfma2_lds_bytes<MODE>();
     if (lds > 65536) {
-        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(symbols_mfma2<MODE>),
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(symbols_mfma2<MODE, FT>),
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
     }
-    hipLaunchKernelGGL(symbols_mfma2<MODE>, grid, dim3(256), lds, s, d, W, A, tw, echunk, canon);
+    hipLaunchKernelGGL((symbols_mfma2<MODE, FT>), grid, dim3(256), lds, s, d, W, A, tw, echunk, canon);
     return hipGetLastError();
+}
+
+// Two sub-tiles per wave for FP32 (0.64 -> 0.54 ms on the 7x7 224 x 224
+// grid); one for the split modes, whose phase fragments for two sub-tiles
+// leave one wave per SIMD (split-BF16 x3: 0.69 ms with one, 0.76 with two).
+template <int MODE>
+hipError_t launch_mfma2(const LayerDesc& d, const float* W, cplx<float>* A, const double* tw, int canon,
+                        hipStream_t s) {
+    return launch_mfma2_ft<MODE, MODE == 0 ? kMfma2Freq : 1>(d, W, A, tw, canon, s);
 }
 
 }  // namespace
@@ -433,6 +596,7 @@ hipError_t launch_symbols_valu_f64(const LayerDesc& d, const double* W, cplx<dou
 hipError_t launch_symbols_mfma(const LayerDesc& d, const float* W, cplx<float>* A,
                                const double* tw, int mode, hipStream_t s, bool canon_only) {
     const int canon = canon_only ? 1 : 0;
+    if (mode == 0 && d.kh <= kSepMaxRows) return launch_sep(d, W, A, tw, canon, s);
     if (d.kh * d.kw <= kMfma2MaxTaps) {
         if (mode == 0) return launch_mfma2<0>(d, W, A, tw, canon, s);
         if (mode == 2) return launch_mfma2<2>(d, W, A, tw, canon, s);

@@ -69,7 +69,10 @@ def test_symbols_match_oracle(case):
 
 
 @pytest.mark.parametrize("asm,gate", [("mfma", 1e-6), ("bf16x3", 1e-6), ("bf16x2", 3e-5)])
-@pytest.mark.parametrize("shape", [(64, 64, 3, 3, 9, 7), (64, 64, 7, 7, 10, 10), (5, 3, 3, 3, 4, 6)])
+@pytest.mark.parametrize("shape", [(64, 64, 3, 3, 9, 7), (64, 64, 7, 7, 10, 10), (5, 3, 3, 3, 4, 6),
+                                   (2, 2, 2, 4, 5, 6),       # even kernel extents
+                                   (4, 3, 1, 9, 3, 10),      # one kernel row
+                                   (3, 2, 17, 3, 18, 4)])    # 17 rows: the direct contraction
 def test_symbols_matrix_cores(asm, gate, shape):
     c_out, c_in, kh, kw, n, m = shape
     banner(f"symbols {asm} {shape}")
