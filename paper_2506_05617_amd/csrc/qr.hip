@@ -283,6 +283,7 @@ __global__ void __launch_bounds__(256) gram_cholesky_kernel(GramArgs<R> g) {
 
 constexpr int kQrRows = 64;      // rows of Y per work-group
 constexpr int kQrChunk = 16;     // columns c of G (rows of V) per staged chunk
+constexpr int kQrTaps = 16;      // taps held in registers by the matrix-core left-vector kernel
 
 // Y = G_k V_R for the work-group (item, row tile, column tile): rows
 // r0 .. r0+63 and columns j0 .. j0+16 NW-1 of Y (M x N), with G_k assembled
@@ -388,6 +389,150 @@ __global__ void __launch_bounds__(256) qr_left_kernel(QrVecArgs<R> q) {
                 const bool keep = sr[j] != R(0);
                 Y[(size_t)j * q.ldg + r] = {keep ? yr[u][w] : R(0), keep ? yi[u][w] : R(0)};
             }
+        }
+    }
+}
+
+// The same product on FP32 matrix cores.  Work-group (item, row tile of 64,
+// column tile of 16 NJ): G_k assembled from W in chunks of 16 columns c into
+// LDS (real and imaginary planes), the matching 16 rows of V_R beside them;
+// wave w forms rows r0 + 16 w .. r0 + 16 w + 15 against the tile's columns
+// as NJ tiles of 16 x 16, each complex product as four real MFMA products
+// per K step of 4 (Re Re and -Im Im into the real part, Re Im and Im Re into
+// the imaginary part).
+typedef float qr_floatx4 __attribute__((ext_vector_type(4)));
+
+template <int NJ>
+__global__ void __launch_bounds__(256) qr_left_mfma(QrVecArgs<float> q) {
+    constexpr int JW = 16 * NJ;
+    __shared__ float gre[kQrRows][kQrChunk + 1], gim[kQrRows][kQrChunk + 1];   // G chunk [r][c]
+    __shared__ float vre[kQrChunk][JW + 1], vim[kQrChunk][JW + 1];             // V_R chunk [c][j]
+    __shared__ cplx<float> ph[kMaxTaps];
+    const int rtiles = (q.M + kQrRows - 1) / kQrRows, ctiles = (q.N + JW - 1) / JW;
+    const int item = blockIdx.x / (rtiles * ctiles);
+    const int rest = blockIdx.x - item * rtiles * ctiles;
+    const int r0 = (rest / ctiles) * kQrRows, j0 = (rest - (rest / ctiles) * ctiles) * JW;
+    const int theta = canonical_theta(q.n, q.m, item);
+    const int p = theta / q.m, qq = theta - (theta / q.m) * q.m;
+    const int N = q.N, T = q.kh * q.kw;
+    const cplx<float>* VR = q.VR + (size_t)theta * N * N;
+    cplx<float>* slot = reinterpret_cast<cplx<float>*>(q.slots + (size_t)item * q.slot_bytes);
+    cplx<float>* Y = slot;                                          // [N][ldg]
+    cplx<float>* Qs = slot + (size_t)q.ldg * N;                    // [N][ldv]
+    for (int t = threadIdx.x; t < T; t += blockDim.x) {
+        const int aa = t / q.kw, bb = t - (t / q.kw) * q.kw;
+        const int y1 = aa - (q.kh - 1) / 2, y2 = bb - (q.kw - 1) / 2;
+        int i1 = (p * y1) % q.n;
+        if (i1 < 0) i1 += q.n;
+        int i2 = (qq * y2) % q.m;
+        if (i2 < 0) i2 += q.m;
+        const double ar = q.tw[2 * (q.tw_n + i1)], ai = q.tw[2 * (q.tw_n + i1) + 1];
+        const double br = q.tw[2 * (q.tw_m + i2)], bi = q.tw[2 * (q.tw_m + i2) + 1];
+        const double im = ar * bi + ai * br;
+        ph[t] = {float(ar * br - ai * bi), float(q.transposed ? -im : im)};
+    }
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int li = lane & 15, lk = lane >> 4;
+    qr_floatx4 yr[NJ], yi[NJ];
+#pragma unroll
+    for (int s = 0; s < NJ; ++s) {
+        yr[s] = qr_floatx4{0.f, 0.f, 0.f, 0.f};
+        yi[s] = qr_floatx4{0.f, 0.f, 0.f, 0.f};
+    }
+    for (int c0 = 0; c0 < N; c0 += kQrChunk) {
+        __syncthreads();
+        // G_k[r][c] = sum_t Wg[r][c][t] e^{2 pi i s <k, y_t>}: each thread's
+        // 4 entries, their taps loaded all at once (up to kQrTaps in
+        // registers) before the sums
+        constexpr int PER = kQrRows * kQrChunk / 256;
+        if (T <= kQrTaps) {
+            float wv[PER][kQrTaps];
+#pragma unroll
+            for (int u = 0; u < PER; ++u) {
+                const int x = threadIdx.x + 256 * u;
+                const int rr = x / kQrChunk, cc = x - (x / kQrChunk) * kQrChunk;
+                const int r = r0 + rr, c = c0 + cc;
+                const bool ok = r < q.M && c < N;
+                const float* w = q.W + (q.transposed ? ((size_t)c * q.c_in + r) : ((size_t)r * q.c_in + c)) * T;
+#pragma unroll
+                for (int t = 0; t < kQrTaps; ++t) wv[u][t] = (ok && t < T) ? w[t] : 0.f;
+            }
+#pragma unroll
+            for (int u = 0; u < PER; ++u) {
+                const int x = threadIdx.x + 256 * u;
+                const int rr = x / kQrChunk, cc = x - (x / kQrChunk) * kQrChunk;
+                float vr = 0.f, vi = 0.f;
+#pragma unroll
+                for (int t = 0; t < kQrTaps; ++t) {
+                    if (t < T) {
+                        vr = fmaf(wv[u][t], ph[t].x, vr);
+                        vi = fmaf(wv[u][t], ph[t].y, vi);
+                    }
+                }
+                gre[rr][cc] = vr;
+                gim[rr][cc] = vi;
+            }
+        } else {
+            for (int x = threadIdx.x; x < kQrRows * kQrChunk; x += blockDim.x) {
+                const int rr = x / kQrChunk, cc = x - (x / kQrChunk) * kQrChunk;
+                const int r = r0 + rr, c = c0 + cc;
+                float vr = 0.f, vi = 0.f;
+                if (r < q.M && c < N) {
+                    const float* w = q.W + (q.transposed ? ((size_t)c * q.c_in + r) : ((size_t)r * q.c_in + c)) * T;
+                    for (int t = 0; t < T; ++t) {
+                        vr = fmaf(w[t], ph[t].x, vr);
+                        vi = fmaf(w[t], ph[t].y, vi);
+                    }
+                }
+                gre[rr][cc] = vr;
+                gim[rr][cc] = vi;
+            }
+        }
+        // (256 threads: fixed trip counts, so that the loads are unrolled
+        // and four at a time in flight; full unrolling leaves one wave per SIMD)
+#pragma unroll 4
+        for (int x = threadIdx.x; x < kQrChunk * JW; x += 256) {
+            const int cc = x / JW, jj = x - (x / JW) * JW, j = j0 + jj;
+            const cplx<float> v = (c0 + cc < N && j < N) ? VR[(size_t)(c0 + cc) * N + j] : cplx<float>{0.f, 0.f};
+            vre[cc][jj] = v.x;
+            vim[cc][jj] = v.y;
+        }
+        __syncthreads();
+        // the row-tile-0 work-groups also copy V_R into the slot's
+        // accumulator part (Qs[j][c] = V_R[c][j]): from the staged chunk,
+        // 16 consecutive c of one column j per 16 lanes
+        if (r0 == 0)
+#pragma unroll
+            for (int x = threadIdx.x; x < kQrChunk * JW; x += 256) {
+                const int jj = x / kQrChunk, cc = x - (x / kQrChunk) * kQrChunk;
+                if (c0 + cc < N && j0 + jj < N)
+                    Qs[(size_t)(j0 + jj) * q.ldv + c0 + cc] = {vre[cc][jj], vim[cc][jj]};
+            }
+#pragma unroll
+        for (int kt = 0; kt < kQrChunk / 4; ++kt) {
+            const float ar = gre[16 * wave + li][4 * kt + lk], ai = gim[16 * wave + li][4 * kt + lk];
+#pragma unroll
+            for (int s = 0; s < NJ; ++s) {
+                const float br = vre[4 * kt + lk][16 * s + li], bi = vim[4 * kt + lk][16 * s + li];
+                yr[s] = __builtin_amdgcn_mfma_f32_16x16x4f32(ar, br, yr[s], 0, 0, 0);
+                yr[s] = __builtin_amdgcn_mfma_f32_16x16x4f32(-ai, bi, yr[s], 0, 0, 0);
+                yi[s] = __builtin_amdgcn_mfma_f32_16x16x4f32(ar, bi, yi[s], 0, 0, 0);
+                yi[s] = __builtin_amdgcn_mfma_f32_16x16x4f32(ai, br, yi[s], 0, 0, 0);
+            }
+        }
+    }
+    // columns of singular values the SVD of R set to zero stay exactly zero
+    // (see qr_left_kernel); D[i][j]: j = lane & 15 (column), i = 4*(lane >> 4) + v (row)
+    const float* sr = q.sigma + (size_t)theta * N;
+#pragma unroll
+    for (int s = 0; s < NJ; ++s) {
+        const int j = j0 + 16 * s + li;
+        if (j >= N) continue;
+        const bool keep = sr[j] != 0.f;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int r = r0 + 16 * wave + 4 * lk + v;
+            if (r < q.M) Y[(size_t)j * q.ldg + r] = {keep ? yr[s][v] : 0.f, keep ? yi[s][v] : 0.f};
         }
     }
 }
@@ -538,11 +683,26 @@ hipError_t launch_qr_left_nw(const QrVecArgs<R>& q, int items, hipStream_t s) {
     return hipGetLastError();
 }
 
+template <int NJ>
+hipError_t launch_qr_left_mfma_nj(const QrVecArgs<float>& q, int items, hipStream_t s) {
+    constexpr int JW = 16 * NJ;
+    const int rtiles = (q.M + kQrRows - 1) / kQrRows, ctiles = (q.N + JW - 1) / JW;
+    hipLaunchKernelGGL((qr_left_mfma<NJ>), dim3(items * rtiles * ctiles), dim3(256), 0, s, q);
+    return hipGetLastError();
+}
+
 template <typename R>
 hipError_t launch_qr_vectors(const QrVecArgs<R>& q, const SvdArgs<R>& a, int items, hipStream_t s) {
     if (items <= 0) return hipSuccess;
     hipError_t e;
-    if (q.N <= 16) e = launch_qr_left_nw<R, 1>(q, items, s);
+    if constexpr (sizeof(R) == 4) {
+        // FP32: matrix cores, column tiles of up to 128 (256 would hold 256
+        // accumulator registers per lane: one wave per SIMD)
+        if (q.N <= 16) e = launch_qr_left_mfma_nj<1>(q, items, s);
+        else if (q.N <= 32) e = launch_qr_left_mfma_nj<2>(q, items, s);
+        else if (q.N <= 64) e = launch_qr_left_mfma_nj<4>(q, items, s);
+        else e = launch_qr_left_mfma_nj<8>(q, items, s);
+    } else if (q.N <= 16) e = launch_qr_left_nw<R, 1>(q, items, s);
     else if (q.N <= 32) e = launch_qr_left_nw<R, 2>(q, items, s);
     else if (q.N <= 64) e = launch_qr_left_nw<R, 4>(q, items, s);
     else if (q.N <= 128) e = launch_qr_left_nw<R, 8>(q, items, s);

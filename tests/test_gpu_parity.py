@@ -923,6 +923,8 @@ QR_CASES = [
     (128, 64, 3, 6, 6),       # 64 x 64 factors: the register kernel
     (512, 256, 3, 4, 4),      # the rectangular layer's shape on a small grid
     (200, 24, 1, 3, 7),       # 1x1 kernel, odd grid
+    (100, 72, 4, 5, 6),       # 16 taps: rows of W not staged in LDS
+    (144, 80, 5, 6, 5),       # 25 taps
 ]
 
 
