@@ -146,6 +146,8 @@ __global__ void __launch_bounds__(256) gram_cholesky_kernel(GramArgs<R> g) {
         const int c = (int)(x / N), e = (int)(x - (x / N) * N);
         if (e < c) continue;
         double hr = 0, hi = 0;
+        // unrolled: eight taps' loads in flight at a time
+#pragma unroll 8
         for (int d = 0; d < ND; ++d) {
             const double v = g.C[((size_t)d * N + c) * N + e];
             hr = fma(v, ph[d].x, hr);
