@@ -310,9 +310,10 @@ __device__ void finish(const SvdArgs<R>& a, const Shared<R>& s, int out_idx, int
     cplx<R>* G = s.G;
     cplx<R>* Q = s.Q;
 
-    // column norms
+    // column norms (unrolled: several loads in flight)
     for (int j = group; j < N; j += ngroups) {
         R acc = 0;
+#pragma unroll 8
         for (int i = lane; i < M; i += L) {
             const cplx<R> v = G[(size_t)j * ldg + i];
             acc = fma(v.x, v.x, fma(v.y, v.y, acc));
@@ -360,11 +361,25 @@ __device__ void finish(const SvdArgs<R>& a, const Shared<R>& s, int out_idx, int
     if (want_right) {
         cplx<R>* out = (d.transposed ? a.U : a.V) + (size_t)out_idx * N * r;
         cplx<R>* mir = mirror >= 0 ? (d.transposed ? a.U : a.V) + (size_t)mirror * N * r : nullptr;
-        for (int e = tid; e < N * r; e += nt) {
-            const int i = e / r, c = e - (e / r) * r;
-            const cplx<R> v = Q[(size_t)s.perm[c] * ldv + i];
-            out[e] = v;
-            if (mir) mir[e] = {v.x, -v.y};
+        // four entries per thread loaded before any is stored
+        for (int e0 = tid; e0 < N * r; e0 += 4 * nt) {
+            cplx<R> v[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int e = e0 + u * nt;
+                if (e < N * r) {
+                    const int i = e / r, c = e - (e / r) * r;
+                    v[u] = Q[(size_t)s.perm[c] * ldv + i];
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int e = e0 + u * nt;
+                if (e < N * r) {
+                    out[e] = v[u];
+                    if (mir) mir[e] = {v[u].x, -v[u].y};
+                }
+            }
         }
     }
     // the accumulator has been written out: its memory may serve the
@@ -372,12 +387,26 @@ __device__ void finish(const SvdArgs<R>& a, const Shared<R>& s, int out_idx, int
     __syncthreads();
     if (want_left) {
         // normalise columns in place: u_j = g_j / sigma_j (zero columns stay 0)
-        for (int e = tid; e < N * M; e += nt) {
-            const int j = e / M, i = e - (e / M) * M;
-            const R sj = s.sig[j];
-            const cplx<R> v = G[(size_t)j * ldg + i];
-            const R inv = sj > R(0) ? R(1) / sj : R(0);
-            G[(size_t)j * ldg + i] = {v.x * inv, v.y * inv};
+        for (int e0 = tid; e0 < N * M; e0 += 4 * nt) {
+            cplx<R> v[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int e = e0 + u * nt;
+                if (e < N * M) {
+                    const int j = e / M, i = e - (e / M) * M;
+                    v[u] = G[(size_t)j * ldg + i];
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int e = e0 + u * nt;
+                if (e < N * M) {
+                    const int j = e / M, i = e - (e / M) * M;
+                    const R sj = s.sig[j];
+                    const R inv = sj > R(0) ? R(1) / sj : R(0);
+                    G[(size_t)j * ldg + i] = {v[u].x * inv, v[u].y * inv};
+                }
+            }
         }
         __syncthreads();
         // Columns with sigma == 0 (they sort last) get an orthonormal
@@ -465,6 +494,7 @@ __device__ void finish(const SvdArgs<R>& a, const Shared<R>& s, int out_idx, int
                 for (int z = group; z < nh; z += ngroups) {
                     const cplx<R>* x = G + (size_t)s.perm[ra + z] * ldg;
                     cplx<R> w = {R(0), R(0)};
+#pragma unroll 8
                     for (int i = k + lane; i < M; i += L) {
                         w.x = fma(v[i].x, x[i].x, fma(v[i].y, x[i].y, w.x));
                         w.y = fma(v[i].x, x[i].y, fma(-v[i].y, x[i].x, w.y));
@@ -474,12 +504,29 @@ __device__ void finish(const SvdArgs<R>& a, const Shared<R>& s, int out_idx, int
                     if (lane == 0) s.coef[ra + z] = w;
                 }
                 __syncthreads();
-                for (int e = tid; e < nh * M; e += nt) {
-                    const int z = e / M, i = e - (e / M) * M;
-                    if (i < k) continue;
-                    const cplx<R> w = s.coef[ra + z], vi = v[i];
-                    cplx<R>* x = G + (size_t)s.perm[ra + z] * ldg;
-                    x[i] = {x[i].x - beta * (w.x * vi.x - w.y * vi.y), x[i].y - beta * (w.x * vi.y + w.y * vi.x)};
+                // four entries per thread loaded before any is stored
+                for (int e0 = tid; e0 < nh * M; e0 += 4 * nt) {
+                    cplx<R> xv[4], vv[4];
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        const int e = e0 + u * nt;
+                        const int z = e / M, i = e - (e / M) * M;
+                        if (e < nh * M && i >= k) {
+                            xv[u] = G[(size_t)s.perm[ra + z] * ldg + i];
+                            vv[u] = v[i];
+                        }
+                    }
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        const int e = e0 + u * nt;
+                        const int z = e / M, i = e - (e / M) * M;
+                        if (e < nh * M && i >= k) {
+                            const cplx<R> w = s.coef[ra + z];
+                            G[(size_t)s.perm[ra + z] * ldg + i] = {
+                                xv[u].x - beta * (w.x * vv[u].x - w.y * vv[u].y),
+                                xv[u].y - beta * (w.x * vv[u].y + w.y * vv[u].x)};
+                        }
+                    }
                 }
                 __syncthreads();
             }
@@ -553,11 +600,24 @@ __device__ void finish(const SvdArgs<R>& a, const Shared<R>& s, int out_idx, int
         // write: out[theta][i][c] = G[perm[c]][i]
         cplx<R>* out = (d.transposed ? a.V : a.U) + (size_t)out_idx * M * r;
         cplx<R>* mir = mirror >= 0 ? (d.transposed ? a.V : a.U) + (size_t)mirror * M * r : nullptr;
-        for (int e = tid; e < M * r; e += nt) {
-            const int i = e / r, c = e - (e / r) * r;
-            const cplx<R> v = G[(size_t)s.perm[c] * ldg + i];
-            out[e] = v;
-            if (mir) mir[e] = {v.x, -v.y};
+        for (int e0 = tid; e0 < M * r; e0 += 4 * nt) {
+            cplx<R> v[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int e = e0 + u * nt;
+                if (e < M * r) {
+                    const int i = e / r, c = e - (e / r) * r;
+                    v[u] = G[(size_t)s.perm[c] * ldg + i];
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int e = e0 + u * nt;
+                if (e < M * r) {
+                    out[e] = v[u];
+                    if (mir) mir[e] = {v[u].x, -v[u].y};
+                }
+            }
         }
     }
     if (a.info) {

@@ -564,6 +564,7 @@ __global__ void __launch_bounds__(256) qr_finish_kernel(SvdArgs<R> a, const R* s
     // column norms into s.sig (the finish recomputes them afterwards)
     for (int j = group; j < N; j += ngroups) {
         R acc = 0;
+#pragma unroll 8
         for (int i = lane; i < M; i += 64) {
             const cplx<R> v = G[(size_t)j * ldg + i];
             acc = fma(v.x, v.x, fma(v.y, v.y, acc));
@@ -582,6 +583,7 @@ __global__ void __launch_bounds__(256) qr_finish_kernel(SvdArgs<R> a, const R* s
                 cplx<R> c = {R(0), R(0)};
                 const R ni = s.sig[i];
                 if (ni > R(0)) {
+#pragma unroll 8
                     for (int r = lane; r < M; r += 64) {
                         const cplx<R> u = G[(size_t)i * ldg + r], y = G[(size_t)j * ldg + r];
                         c.x = fma(u.x, y.x, fma(u.y, y.y, c.x));
