@@ -177,6 +177,9 @@ __global__ void __launch_bounds__(256) adjoint_kernel(AdjointArgs<R> a) {
     }
 }
 
+constexpr int kOtherTaps = 16;   // taps of the unrolled form of other_side_kernel
+constexpr int kOtherSlice = 64;  // entries of the other vector per work-group (one wave)
+
 // One work-group per (layer, pick): the kept vector x (column j of the
 // kept side at the pick's frequency) and the conjugated or plain phases of
 // the taps go to LDS; each thread forms entries of the other vector,
@@ -184,15 +187,21 @@ __global__ void __launch_bounds__(256) adjoint_kernel(AdjointArgs<R> a) {
 //   u[o] = (1/sigma) sum_i sum_t W[o,i,t] e^{+2 pi i <k, y_t>} v[i]    (kept V),
 // over the kept side's channels in a fixed order.  A pick with sigma not
 // positive (or outside the grid) gets zero vectors: it adds nothing to dW.
+// Each (layer, pick) is split over `parts` work-groups, each forming a slice
+// of kOtherSlice entries of the other vector (the first also writes the
+// kept vector).
 template <typename R>
-__global__ void __launch_bounds__(256) other_side_kernel(OtherSideArgs<R> a) {
+__global__ void __launch_bounds__(256) other_side_kernel(OtherSideArgs<R> a, int parts) {
     extern __shared__ __align__(16) char lds_raw[];
-    const int layer = blockIdx.x / a.k, s = blockIdx.x - (blockIdx.x / a.k) * a.k;
+    const int b = blockIdx.x / parts, part = blockIdx.x - (blockIdx.x / parts) * parts;
+    const int layer = b / a.k, s = b - (b / a.k) * a.k;
     const int c_out = a.c_out[layer], c_in = a.c_in[layer], kh = a.kh[layer], kw = a.kw[layer];
     const int n = a.n[layer], m = a.m[layer];
     const int T = kh * kw, r = c_out < c_in ? c_out : c_in;
     const bool keep_u = c_out >= c_in;               // the working matrix's side
     const int ck = keep_u ? c_out : c_in, co = keep_u ? c_in : c_out;
+    const int e_lo = part * kOtherSlice, e_hi = min(co, e_lo + kOtherSlice);
+    if (e_lo >= co) return;                       // never the first part
     cplx<R>* ph = reinterpret_cast<cplx<R>*>(lds_raw);                  // [T]
     cplx<R>* x = ph + T;                                                  // [ck]
     const int32_t* pk = a.idx + ((size_t)layer * a.k + s) * 3;
@@ -202,8 +211,9 @@ __global__ void __launch_bounds__(256) other_side_kernel(OtherSideArgs<R> a) {
     const bool valid = p >= 0 && p < n && q >= 0 && q < m && j >= 0 && j < r;
     const R sg = valid ? a.sigma[layer][((size_t)p * m + q) * r + j] : R(0);
     if (!(sg > R(0)) || !(sg < INFINITY)) {
-        for (int e = threadIdx.x; e < ck; e += blockDim.x) kept_out[e] = {R(0), R(0)};
-        for (int e = threadIdx.x; e < co; e += blockDim.x) other_out[e] = {R(0), R(0)};
+        if (part == 0)
+            for (int e = threadIdx.x; e < ck; e += blockDim.x) kept_out[e] = {R(0), R(0)};
+        for (int e = e_lo + threadIdx.x; e < e_hi; e += blockDim.x) other_out[e] = {R(0), R(0)};
         return;
     }
     for (int t = threadIdx.x; t < T; t += blockDim.x) {
@@ -222,24 +232,48 @@ __global__ void __launch_bounds__(256) other_side_kernel(OtherSideArgs<R> a) {
     const cplx<R>* xs = a.X[layer] + ((size_t)p * m + q) * ck * r;
     for (int e = threadIdx.x; e < ck; e += blockDim.x) {
         x[e] = xs[(size_t)e * r + j];
-        kept_out[e] = x[e];
+        if (part == 0) kept_out[e] = x[e];
     }
     __syncthreads();
     const R inv = R(1) / sg;
     const R* W = a.W[layer];
-    for (int e = threadIdx.x; e < co; e += blockDim.x) {
+    for (int e = e_lo + threadIdx.x; e < e_hi; e += blockDim.x) {
         R zr = R(0), zi = R(0);
-        for (int c = 0; c < ck; ++c) {
-            // weight (o, i) = (c, e) for kept U, (e, c) for kept V
-            const R* w = W + (keep_u ? ((size_t)c * c_in + e) : ((size_t)e * c_in + c)) * T;
-            R ar = R(0), ai = R(0);                  // sum_t w_t phase_t
-            for (int t = 0; t < T; ++t) {
-                ar = fma(w[t], ph[t].x, ar);
-                ai = fma(w[t], ph[t].y, ai);
+        if (T <= kOtherTaps) {
+            // the same sums with the tap loop unrolled and the channel loop
+            // by four, so that the weight loads are in flight together
+#pragma unroll 4
+            for (int c = 0; c < ck; ++c) {
+                const R* w = W + (keep_u ? ((size_t)c * c_in + e) : ((size_t)e * c_in + c)) * T;
+                R ar = R(0), ai = R(0);
+#pragma unroll
+                for (int t = 0; t < kOtherTaps; ++t) {
+                    // loads without a branch (taps past T read tap 0 and
+                    // add an exact zero), so that none waits on another
+                    const int tt = t < T ? t : 0;
+                    const R wt = w[tt];
+                    const cplx<R> pt = ph[tt];
+                    const R m = t < T ? wt : R(0);
+                    ar = fma(m, pt.x, ar);
+                    ai = fma(m, pt.y, ai);
+                }
+                const cplx<R> xv = x[c];
+                zr = fma(ar, xv.x, fma(-ai, xv.y, zr));
+                zi = fma(ar, xv.y, fma(ai, xv.x, zi));
             }
-            const cplx<R> xv = x[c];
-            zr = fma(ar, xv.x, fma(-ai, xv.y, zr));
-            zi = fma(ar, xv.y, fma(ai, xv.x, zi));
+        } else {
+            for (int c = 0; c < ck; ++c) {
+                // weight (o, i) = (c, e) for kept U, (e, c) for kept V
+                const R* w = W + (keep_u ? ((size_t)c * c_in + e) : ((size_t)e * c_in + c)) * T;
+                R ar = R(0), ai = R(0);                  // sum_t w_t phase_t
+                for (int t = 0; t < T; ++t) {
+                    ar = fma(w[t], ph[t].x, ar);
+                    ai = fma(w[t], ph[t].y, ai);
+                }
+                const cplx<R> xv = x[c];
+                zr = fma(ar, xv.x, fma(-ai, xv.y, zr));
+                zi = fma(ar, xv.y, fma(ai, xv.x, zi));
+            }
         }
         other_out[e] = {zr * inv, zi * inv};
     }
@@ -255,7 +289,11 @@ hipError_t launch_other_side_f32(const OtherSideArgs<float>& a, hipStream_t s) {
         maxC = ck > maxC ? ck : maxC;
     }
     const size_t lds = sizeof(cplx<float>) * (size_t)(maxT + maxC);
-    hipLaunchKernelGGL(other_side_kernel<float>, dim3(a.num_layers * a.k), dim3(256), lds, s, a);
+    int maxO = 1;
+    for (int l = 0; l < a.num_layers; ++l) maxO = std::max(maxO, std::min(a.c_out[l], a.c_in[l]));
+    const int parts = (maxO + kOtherSlice - 1) / kOtherSlice;
+    hipLaunchKernelGGL(other_side_kernel<float>, dim3(a.num_layers * a.k * parts), dim3(kOtherSlice), lds, s, a,
+                       parts);
     return hipGetLastError();
 }
 hipError_t launch_other_side_f64(const OtherSideArgs<double>& a, hipStream_t s) {
@@ -266,7 +304,11 @@ hipError_t launch_other_side_f64(const OtherSideArgs<double>& a, hipStream_t s) 
         maxC = ck > maxC ? ck : maxC;
     }
     const size_t lds = sizeof(cplx<double>) * (size_t)(maxT + maxC);
-    hipLaunchKernelGGL(other_side_kernel<double>, dim3(a.num_layers * a.k), dim3(256), lds, s, a);
+    int maxO = 1;
+    for (int l = 0; l < a.num_layers; ++l) maxO = std::max(maxO, std::min(a.c_out[l], a.c_in[l]));
+    const int parts = (maxO + kOtherSlice - 1) / kOtherSlice;
+    hipLaunchKernelGGL(other_side_kernel<double>, dim3(a.num_layers * a.k * parts), dim3(kOtherSlice), lds, s, a,
+                       parts);
     return hipGetLastError();
 }
 
