@@ -144,6 +144,8 @@ __device__ R block_sum(R v, R* red) {
 // ---------------------------------------------------------------------------
 // Load the symbol of frequency theta into G (and Q = I).
 // ---------------------------------------------------------------------------
+constexpr int kLoadTaps = 16;    // taps of the unrolled assembly in load_symbol
+
 template <typename R>
 __device__ void load_symbol(const SvdArgs<R>& a, const Shared<R>& s, int theta) {
     const LayerDesc& d = a.d;
@@ -158,26 +160,69 @@ __device__ void load_symbol(const SvdArgs<R>& a, const Shared<R>& s, int theta) 
             s.ph[t] = {R(re), R(im)};
         }
         __syncthreads();
-        for (int e = tid; e < E; e += nt) {
-            const R* w = a.W + (size_t)e * T;
-            R re = 0, im = 0;
-            for (int t = 0; t < T; ++t) {
-                const R wt = w[t];
-                const cplx<R> ph = s.ph[t];
-                re = fma(wt, ph.x, re);
-                im = fma(wt, ph.y, im);
+        if (T <= kLoadTaps) {
+            // two entries per thread at a time, their taps loaded without a
+            // branch (taps past T read tap 0 and add an exact zero), so that
+            // the loads are in flight together; the sums are the same
+            for (int e0 = tid; e0 < E; e0 += 2 * nt) {
+                R wv[2][kLoadTaps];
+#pragma unroll
+                for (int u = 0; u < 2; ++u) {
+                    const int e = e0 + u * nt;
+                    const R* w = a.W + (size_t)(e < E ? e : 0) * T;
+#pragma unroll
+                    for (int t = 0; t < kLoadTaps; ++t) wv[u][t] = w[t < T ? t : 0];
+                }
+#pragma unroll
+                for (int u = 0; u < 2; ++u) {
+                    const int e = e0 + u * nt;
+                    if (e >= E) continue;
+                    R re = 0, im = 0;
+#pragma unroll
+                    for (int t = 0; t < kLoadTaps; ++t) {
+                        const R wt = t < T ? wv[u][t] : R(0);
+                        const cplx<R> ph = s.ph[t < T ? t : 0];
+                        re = fma(wt, ph.x, re);
+                        im = fma(wt, ph.y, im);
+                    }
+                    const int o = e / d.c_in, i = e - (e / d.c_in) * d.c_in;
+                    if (!d.transposed) s.G[(size_t)i * d.ldg + o] = {re, im};
+                    else               s.G[(size_t)o * d.ldg + i] = {re, -im};
+                }
             }
-            const int o = e / d.c_in, i = e - (e / d.c_in) * d.c_in;
-            if (!d.transposed) s.G[(size_t)i * d.ldg + o] = {re, im};
-            else               s.G[(size_t)o * d.ldg + i] = {re, -im};
+        } else {
+            for (int e = tid; e < E; e += nt) {
+                const R* w = a.W + (size_t)e * T;
+                R re = 0, im = 0;
+                for (int t = 0; t < T; ++t) {
+                    const R wt = w[t];
+                    const cplx<R> ph = s.ph[t];
+                    re = fma(wt, ph.x, re);
+                    im = fma(wt, ph.y, im);
+                }
+                const int o = e / d.c_in, i = e - (e / d.c_in) * d.c_in;
+                if (!d.transposed) s.G[(size_t)i * d.ldg + o] = {re, im};
+                else               s.G[(size_t)o * d.ldg + i] = {re, -im};
+            }
         }
     } else {
+        // four entries per thread loaded before any is stored
         const cplx<R>* A = a.A + (size_t)theta * E;
-        for (int e = tid; e < E; e += nt) {
-            const cplx<R> v = A[e];
-            const int o = e / d.c_in, i = e - (e / d.c_in) * d.c_in;
-            if (!d.transposed) s.G[(size_t)i * d.ldg + o] = v;
-            else               s.G[(size_t)o * d.ldg + i] = {v.x, -v.y};
+        for (int e0 = tid; e0 < E; e0 += 4 * nt) {
+            cplx<R> v[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int e = e0 + u * nt;
+                if (e < E) v[u] = A[e];
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int e = e0 + u * nt;
+                if (e >= E) continue;
+                const int o = e / d.c_in, i = e - (e / d.c_in) * d.c_in;
+                if (!d.transposed) s.G[(size_t)i * d.ldg + o] = v[u];
+                else               s.G[(size_t)o * d.ldg + i] = {v[u].x, -v[u].y};
+            }
         }
     }
     if (s.Q) {
