@@ -146,7 +146,10 @@ __device__ R block_sum(R v, R* red) {
 // ---------------------------------------------------------------------------
 constexpr int kLoadTaps = 16;    // taps of the unrolled assembly in load_symbol
 
-template <typename R>
+// BATCH: the assembly with its weight loads in flight together (taken by
+// the kernels without an accumulator; with one, its registers spilled into
+// the sweeps).
+template <typename R, bool BATCH = true>
 __device__ void load_symbol(const SvdArgs<R>& a, const Shared<R>& s, int theta) {
     const LayerDesc& d = a.d;
     const int tid = threadIdx.x, nt = blockDim.x;
@@ -160,7 +163,7 @@ __device__ void load_symbol(const SvdArgs<R>& a, const Shared<R>& s, int theta) 
             s.ph[t] = {R(re), R(im)};
         }
         __syncthreads();
-        if (T <= kLoadTaps) {
+        if (BATCH && T <= kLoadTaps) {
             // two entries per thread at a time, their taps loaded without a
             // branch (taps past T read tap 0 and add an exact zero), so that
             // the loads are in flight together; the sums are the same
@@ -1523,7 +1526,7 @@ __device__ __forceinline__ void block_one(const SvdArgs<R>& a, char* lds, int it
     const Target tg = target_of(a, item);
     const Shared<R> s = carve<R>(lds, a.d, ACC, gslot);
     const BlockLds<R> bl = carve_block<R>(lds, s.small_end);
-    if (team.member == 0) load_symbol<R>(a, s, tg.theta);
+    if (team.member == 0) load_symbol<R, !ACC>(a, s, tg.theta);
     if (team.W > 1) team_barrier(team);
     else __syncthreads();
     int sweeps;
