@@ -533,6 +533,125 @@ __global__ void __launch_bounds__(256) symbols_sep(LayerDesc d, const float* __r
     }
 }
 
+// The separable form in the split-BF16 modes (MODE 2: two terms, three
+// products; MODE 3: three terms, six products).  B_q is formed in FP32 as
+// above, then each value of the B fragments and of the phase fragments is
+// split into bfloat16 terms; the kept products of terms accumulate in FP32
+// on v_mfma_f32_16x16x16bf16_1k, the kernel rows (at most 16) in one K step.
+template <int MODE>
+__global__ void __launch_bounds__(256) symbols_sep_bf(LayerDesc d, const float* __restrict__ W,
+                                                      cplx<float>* __restrict__ A,
+                                                      const double* __restrict__ tw, int canon) {
+    constexpr int TERMS = MODE == 2 ? 2 : 3, NPROD = MODE == 2 ? 3 : 6, ms = MODE == 3 ? 1 : 0;
+    __shared__ float bre[kSepMaxRows][65], bim[kSepMaxRows][65];   // B_q[a][e - e0]
+    __shared__ float bq[2][kMaxTaps];
+    const int T = d.kh * d.kw, E = d.c_out * d.c_in;
+    const int e0 = blockIdx.x * 64, q = blockIdx.y;
+    for (int b = threadIdx.x; b < d.kw; b += blockDim.x) {
+        int i2 = (q * (b - (d.kw - 1) / 2)) % d.m;
+        if (i2 < 0) i2 += d.m;
+        bq[0][b] = float(tw[2 * (d.tw_m + i2)]);
+        bq[1][b] = float(tw[2 * (d.tw_m + i2) + 1]);
+    }
+    __syncthreads();
+    {
+        const int el = threadIdx.x & 63, e = e0 + el;
+        for (int a = threadIdx.x >> 6; a < kSepMaxRows; a += 4) {
+            float sr = 0.f, si = 0.f;
+            if (a < d.kh && e < E) {
+                const float* w = W + (size_t)e * T + a * d.kw;
+                for (int b = 0; b < d.kw; ++b) {
+                    sr = fmaf(w[b], bq[0][b], sr);
+                    si = fmaf(w[b], bq[1][b], si);
+                }
+            }
+            bre[a][el] = sr;
+            bim[a][el] = si;
+        }
+    }
+    __syncthreads();
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int li = lane & 15, lk = lane >> 4;
+    // B fragments: lane (li, lk) holds B[k = 4 lk + v][j = 16 s + li], v < 4,
+    // as split terms
+    bf16x4 fr[4][TERMS], fi[4][TERMS];
+#pragma unroll
+    for (int s = 0; s < 4; ++s)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            unsigned short hr[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
+            split_bf16(bre[4 * lk + v][16 * s + li], TERMS, hr);
+            split_bf16(bim[4 * lk + v][16 * s + li], TERMS, hi);
+#pragma unroll
+            for (int u = 0; u < TERMS; ++u) {
+                fr[s][u][v] = (short)hr[u];
+                fi[s][u][v] = (short)hi[u];
+            }
+        }
+    const int p_end = canon ? d.n / 2 + 1 : d.n;
+    const int y1off = (d.kh - 1) / 2;
+    for (int p0 = wave * 16; p0 < p_end; p0 += 64) {
+        floatx4 yr[4], yi[4];
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+            yr[s] = floatx4{0.f, 0.f, 0.f, 0.f};
+            yi[s] = floatx4{0.f, 0.f, 0.f, 0.f};
+        }
+        // A fragments: row p = p0 + li, k = a = 4 lk + v; -Im kept beside Im
+        const int p = p0 + li;
+        bf16x4 ar[TERMS], ai[TERMS], an[TERMS];
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int a = 4 * lk + v;
+            float re = 0.f, im = 0.f;
+            if (a < d.kh && p < d.n) {
+                int i1 = (p * (a - y1off)) % d.n;
+                if (i1 < 0) i1 += d.n;
+                re = float(tw[2 * (d.tw_n + i1)]);
+                im = float(tw[2 * (d.tw_n + i1) + 1]);
+            }
+            unsigned short hr[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
+            split_bf16(re, TERMS, hr);
+            split_bf16(im, TERMS, hi);
+#pragma unroll
+            for (int u = 0; u < TERMS; ++u) {
+                ar[u][v] = (short)hr[u];
+                ai[u][v] = (short)hi[u];
+                an[u][v] = (short)(hi[u] ^ 0x8000u);     // -Im: the sign bit flipped
+            }
+        }
+#pragma unroll
+        for (int pp = 0; pp < NPROD; ++pp) {
+            const int ta = kProdA[ms][pp], tb = kProdB[ms][pp];
+#pragma unroll
+            for (int s = 0; s < 4; ++s) {
+                yr[s] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ar[ta], fr[s][tb], yr[s], 0, 0, 0);
+                yr[s] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(an[ta], fi[s][tb], yr[s], 0, 0, 0);
+                yi[s] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ar[ta], fi[s][tb], yi[s], 0, 0, 0);
+                yi[s] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ai[ta], fr[s][tb], yi[s], 0, 0, 0);
+            }
+        }
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+            const int e = e0 + s * 16 + li;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int pp = p0 + 4 * lk + v;
+                if (pp < d.n && e < E && (!canon || is_canonical(d, pp, q)))
+                    store_stream(A + ((size_t)pp * d.m + q) * E + e, yr[s][v], yi[s][v]);
+            }
+        }
+    }
+}
+
+template <int MODE>
+hipError_t launch_sep_bf(const LayerDesc& d, const float* W, cplx<float>* A, const double* tw, int canon,
+                         hipStream_t s) {
+    const int E = d.c_out * d.c_in;
+    hipLaunchKernelGGL(symbols_sep_bf<MODE>, dim3((E + 63) / 64, d.m), dim3(256), 0, s, d, W, A, tw, canon);
+    return hipGetLastError();
+}
+
 hipError_t launch_sep(const LayerDesc& d, const float* W, cplx<float>* A, const double* tw, int canon,
                       hipStream_t s) {
     const int E = d.c_out * d.c_in;
@@ -596,7 +715,11 @@ hipError_t launch_symbols_valu_f64(const LayerDesc& d, const double* W, cplx<dou
 hipError_t launch_symbols_mfma(const LayerDesc& d, const float* W, cplx<float>* A,
                                const double* tw, int mode, hipStream_t s, bool canon_only) {
     const int canon = canon_only ? 1 : 0;
-    if (mode == 0 && d.kh <= kSepMaxRows) return launch_sep(d, W, A, tw, canon, s);
+    if (d.kh <= kSepMaxRows) {
+        if (mode == 0) return launch_sep(d, W, A, tw, canon, s);
+        if (mode == 2) return launch_sep_bf<2>(d, W, A, tw, canon, s);
+        if (mode == 3) return launch_sep_bf<3>(d, W, A, tw, canon, s);
+    }
     if (d.kh * d.kw <= kMfma2MaxTaps) {
         if (mode == 0) return launch_mfma2<0>(d, W, A, tw, canon, s);
         if (mode == 2) return launch_mfma2<2>(d, W, A, tw, canon, s);
