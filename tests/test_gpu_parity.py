@@ -1210,6 +1210,34 @@ def test_rectangular_512x256_full_size_sampled(vectors):
     assert abs(ss / (L.n * L.m * np.sum(W.astype(np.float64) ** 2)) - 1) <= 1e-5
 
 
+def test_blocked_last_round_teams_with_vectors(monkeypatch):
+    """The short last round of the blocked kernel with the rotation
+    accumulator (vectors, QR preconditioning off): 514 canonical symbols of
+    256 x 192, two more than a round of resident work-groups (one or two per
+    CU), so the last two run in teams at the end of the same grid.  Sampled
+    symbols, the last canonical ones among them, against the oracle (sigma,
+    residual, orthonormality); Parseval over the whole grid."""
+    monkeypatch.setenv("LFA_QR", "0")
+    banner("blocked last-round teams with vectors, 256x192 on 32x32")
+    n = m = 32
+    _, W = workloads.random_layer(256, 192, 3, 3, n, m, seed=21, dtype=np.float32)
+    plan = lfa().Plan([lfa().LayerSpec(256, 192, 3, 3, n, m)], torch.float32, True, True)
+    assert not plan.preconditioned(0)
+    S, U, V, info = plan.svd([_w(W)])
+    torch.cuda.synchronize()
+    info = to_np(info)[0]
+    assert info[0] == 0 and info[3] == 0, info
+    fr = np.concatenate([_sample(n, m, 6, 8), [[n // 2, m // 2 - 1], [n // 2, m // 2], [n // 2, m // 2 + 1]]])
+    A = oracle.symbols(W.astype(np.float64), n, m, fr)
+    S_ref = oracle.svd_symbols(A, compute_uv=False)
+    Sg = to_np(S[0])[fr[:, 0], fr[:, 1]]
+    assert oracle.sigma_error(Sg, S_ref) <= 1e-5
+    check_vectors(A, Sg, to_np(U[0])[fr[:, 0], fr[:, 1]], to_np(V[0])[fr[:, 0], fr[:, 1]], torch.float32,
+                  "last-round teams")
+    ss = torch.sum(S[0].double() ** 2).item()
+    assert abs(ss / (n * m * np.sum(W.astype(np.float64) ** 2)) - 1) <= 1e-5
+
+
 def test_rank_one_512x256_full_size_sampled():
     """The rank-deficient instance at full size (rank-one taps: rank 9 per
     symbol), with vectors: sampled sigma against the oracle, the 247
