@@ -348,7 +348,10 @@ __device__ int jacobi(const LayerDesc& d, const Shared<R>& s, int max_sweeps, do
 // ---------------------------------------------------------------------------
 // Norms, sort, normalisation, completion of zero columns, outputs.
 // ---------------------------------------------------------------------------
-template <typename R, int L>
+// WIDE: the completion of zero columns forms four columns' inner products at
+// once (their loads and reductions overlap).  The persistent kernel takes the
+// one-column loops, which hold fewer registers beside its other paths.
+template <typename R, int L, bool WIDE = true>
 __device__ void finish(const SvdArgs<R>& a, const Shared<R>& s, int out_idx, int mirror,
                        int sweeps, bool converged) {
     const LayerDesc& d = a.d;
@@ -539,17 +542,53 @@ __device__ void finish(const SvdArgs<R>& a, const Shared<R>& s, int out_idx, int
             for (int k = ra - 1; k >= 0; --k) {
                 const cplx<R>* v = refl(k);
                 const R beta = s.coef[k].x;
-                for (int z = group; z < nh; z += ngroups) {
-                    const cplx<R>* x = G + (size_t)s.perm[ra + z] * ldg;
-                    cplx<R> w = {R(0), R(0)};
+                if constexpr (!WIDE) {
+                    for (int z = group; z < nh; z += ngroups) {
+                        const cplx<R>* x = G + (size_t)s.perm[ra + z] * ldg;
+                        cplx<R> w = {R(0), R(0)};
 #pragma unroll 8
-                    for (int i = k + lane; i < M; i += L) {
-                        w.x = fma(v[i].x, x[i].x, fma(v[i].y, x[i].y, w.x));
-                        w.y = fma(v[i].x, x[i].y, fma(-v[i].y, x[i].x, w.y));
+                        for (int i = k + lane; i < M; i += L) {
+                            w.x = fma(v[i].x, x[i].x, fma(v[i].y, x[i].y, w.x));
+                            w.y = fma(v[i].x, x[i].y, fma(-v[i].y, x[i].x, w.y));
+                        }
+                        w.x = group_sum<R, L>(w.x);
+                        w.y = group_sum<R, L>(w.y);
+                        if (lane == 0) s.coef[ra + z] = w;
                     }
-                    w.x = group_sum<R, L>(w.x);
-                    w.y = group_sum<R, L>(w.y);
-                    if (lane == 0) s.coef[ra + z] = w;
+                } else {
+                    // four columns per group at once, so that their loads and
+                    // reductions overlap (each column's sum in the same order)
+                    for (int z0 = 4 * group; z0 < nh; z0 += 4 * ngroups) {
+                        const cplx<R>* x[4];
+#pragma unroll
+                        for (int c = 0; c < 4; ++c)
+                            x[c] = G + (size_t)s.perm[ra + (z0 + c < nh ? z0 + c : nh - 1)] * ldg;
+                        cplx<R> w[4];
+#pragma unroll
+                        for (int c = 0; c < 4; ++c) w[c] = {R(0), R(0)};
+#pragma unroll 2
+                        for (int i = k + lane; i < M; i += L) {
+                            const cplx<R> vi = v[i];
+                            cplx<R> xi[4];
+#pragma unroll
+                            for (int c = 0; c < 4; ++c) xi[c] = x[c][i];
+#pragma unroll
+                            for (int c = 0; c < 4; ++c) {
+                                w[c].x = fma(vi.x, xi[c].x, fma(vi.y, xi[c].y, w[c].x));
+                                w[c].y = fma(vi.x, xi[c].y, fma(-vi.y, xi[c].x, w[c].y));
+                            }
+                        }
+#pragma unroll
+                        for (int c = 0; c < 4; ++c) {
+                            w[c].x = group_sum<R, L>(w[c].x);
+                            w[c].y = group_sum<R, L>(w[c].y);
+                        }
+                        if (lane == 0) {
+#pragma unroll
+                            for (int c = 0; c < 4; ++c)
+                                if (z0 + c < nh) s.coef[ra + z0 + c] = w[c];
+                        }
+                    }
                 }
                 __syncthreads();
                 // four entries per thread loaded before any is stored
@@ -596,26 +635,81 @@ __device__ void finish(const SvdArgs<R>& a, const Shared<R>& s, int out_idx, int
                 for (int i = tid; i < M; i += nt) G[(size_t)jz * ldg + i] = {R(i == cand), R(0)};
                 __syncthreads();
                 for (int pass = 0; pass < 2; ++pass) {
-                    for (int col = group; col < N; col += ngroups) {
-                        // accepted: nonzero columns and zero columns completed earlier
-                        const bool use = col != jz && (s.sig[col] > R(0) || s.inv[col] < zc);
-                        cplx<R> acc = {0, 0};
-                        if (use) {
+                    if constexpr (!WIDE) {
+                        for (int col = group; col < N; col += ngroups) {
+                            // accepted: nonzero columns and zero columns completed earlier
+                            const bool use = col != jz && (s.sig[col] > R(0) || s.inv[col] < zc);
+                            cplx<R> acc = {0, 0};
+                            if (use) {
+                                for (int i = lane; i < M; i += L) {
+                                    const cplx<R> u = G[(size_t)col * ldg + i];
+                                    const cplx<R> x = G[(size_t)jz * ldg + i];
+                                    acc.x = fma(u.x, x.x, fma(u.y, x.y, acc.x));
+                                    acc.y = fma(u.x, x.y, fma(-u.y, x.x, acc.y));
+                                }
+                            }
+                            acc.x = group_sum<R, L>(acc.x);
+                            acc.y = group_sum<R, L>(acc.y);
+                            if (lane == 0) s.coef[col] = acc;
+                        }
+                    } else {
+                        // four columns per group at once (each column's sum in
+                        // the same order)
+                        for (int c0 = 4 * group; c0 < N; c0 += 4 * ngroups) {
+                            int col[4];
+                            bool use[4];
+#pragma unroll
+                            for (int c = 0; c < 4; ++c) {
+                                const int cc = c0 + c;
+                                // accepted: nonzero columns and zero columns completed earlier
+                                use[c] = cc < N && cc != jz && (s.sig[cc] > R(0) || s.inv[cc] < zc);
+                                col[c] = cc < N ? cc : N - 1;
+                            }
+                            cplx<R> acc[4];
+#pragma unroll
+                            for (int c = 0; c < 4; ++c) acc[c] = {R(0), R(0)};
+#pragma unroll 2
                             for (int i = lane; i < M; i += L) {
-                                const cplx<R> u = G[(size_t)col * ldg + i];
                                 const cplx<R> x = G[(size_t)jz * ldg + i];
-                                acc.x = fma(u.x, x.x, fma(u.y, x.y, acc.x));
-                                acc.y = fma(u.x, x.y, fma(-u.y, x.x, acc.y));
+                                cplx<R> u[4];
+#pragma unroll
+                                for (int c = 0; c < 4; ++c) u[c] = G[(size_t)col[c] * ldg + i];
+#pragma unroll
+                                for (int c = 0; c < 4; ++c) {
+                                    acc[c].x = fma(u[c].x, x.x, fma(u[c].y, x.y, acc[c].x));
+                                    acc[c].y = fma(u[c].x, x.y, fma(-u[c].y, x.x, acc[c].y));
+                                }
+                            }
+#pragma unroll
+                            for (int c = 0; c < 4; ++c) {
+                                acc[c].x = group_sum<R, L>(acc[c].x);
+                                acc[c].y = group_sum<R, L>(acc[c].y);
+                            }
+                            if (lane == 0) {
+#pragma unroll
+                                for (int c = 0; c < 4; ++c)
+                                    if (c0 + c < N) s.coef[c0 + c] = use[c] ? acc[c] : cplx<R>{R(0), R(0)};
                             }
                         }
-                        acc.x = group_sum<R, L>(acc.x);
-                        acc.y = group_sum<R, L>(acc.y);
-                        if (lane == 0) s.coef[col] = acc;
                     }
                     __syncthreads();
                     for (int i = tid; i < M; i += nt) {
                         cplx<R> x = G[(size_t)jz * ldg + i];
-                        for (int col = 0; col < N; ++col) {
+                        // eight columns' entries loaded before they are used
+                        // (the same updates in the same order)
+                        int col = 0;
+                        for (; WIDE && col + 8 <= N; col += 8) {
+                            cplx<R> u[8];
+#pragma unroll
+                            for (int c = 0; c < 8; ++c) u[c] = G[(size_t)(col + c) * ldg + i];
+#pragma unroll
+                            for (int c = 0; c < 8; ++c) {
+                                const cplx<R> cf = s.coef[col + c];
+                                x.x -= cf.x * u[c].x - cf.y * u[c].y;
+                                x.y -= cf.x * u[c].y + cf.y * u[c].x;
+                            }
+                        }
+                        for (; col < N; ++col) {
                             const cplx<R> cf = s.coef[col];
                             const cplx<R> u = G[(size_t)col * ldg + i];
                             x.x -= cf.x * u.x - cf.y * u.y;
@@ -1515,7 +1609,7 @@ __device__ __forceinline__ void block_sweeps(const LayerDesc& d, const Shared<R>
 // description in particular) are read through memory in the loops instead of
 // from scalar registers, which measured 10 % slower in the persistent kernel.
 // DUAL: two block pairs per cross step (launches without teams, W = 1).
-template <typename R, int RPT, bool ACC, bool TRACK = false, bool DUAL = false>
+template <typename R, int RPT, bool ACC, bool TRACK = false, bool DUAL = false, bool WIDE = true>
 __device__ __forceinline__ void block_one(const SvdArgs<R>& a, char* lds, int item, char* gslot, Team& team) {
     // ACC must match the arguments: the right singular vectors (left when
     // transposed) are wanted exactly when the accumulator is kept
@@ -1532,7 +1626,7 @@ __device__ __forceinline__ void block_one(const SvdArgs<R>& a, char* lds, int it
     int sweeps;
     bool converged;
     block_sweeps<R, RPT, ACC, TRACK, DUAL>(a.d, s, bl, a.max_sweeps, a.tol, team, sweeps, converged);
-    if (team.member == 0) finish<R, 64>(a, s, tg.out, tg.mirror, sweeps, converged);
+    if (team.member == 0) finish<R, 64, WIDE>(a, s, tg.out, tg.mirror, sweeps, converged);
     // the slot is reused for the team's next symbol: members wait for the finish
     if (team.W > 1) team_barrier(team);
     if (a.info && threadIdx.x == 0 && team.member == 0 &&

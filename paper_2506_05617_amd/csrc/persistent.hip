@@ -91,13 +91,13 @@ __global__ void __launch_bounds__(256) persistent_kernel(PersistentArgs<R> pa_ar
             char* gslot = a.gws + (size_t)w.item * a.slot_bytes;
             constexpr bool TRACK = !ACC && sizeof(R) == 4;
             if (a.d.M > 256) {
-                block_one<R, 2, ACC, TRACK>(a, lds, w.item, gslot, team);
+                block_one<R, 2, ACC, TRACK, false, false>(a, lds, w.item, gslot, team);
             } else if constexpr (TRACK) {
                 // a work-group of its own: two block pairs per cross step
-                if (w.W == 1) block_one<R, 1, ACC, TRACK, true>(a, lds, w.item, gslot, team);
-                else block_one<R, 1, ACC, TRACK>(a, lds, w.item, gslot, team);
+                if (w.W == 1) block_one<R, 1, ACC, TRACK, true, false>(a, lds, w.item, gslot, team);
+                else block_one<R, 1, ACC, TRACK, false, false>(a, lds, w.item, gslot, team);
             } else {
-                block_one<R, 1, ACC, TRACK>(a, lds, w.item, gslot, team);
+                block_one<R, 1, ACC, TRACK, false, false>(a, lds, w.item, gslot, team);
             }
         }
     }
