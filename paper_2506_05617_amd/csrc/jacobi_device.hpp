@@ -591,34 +591,67 @@ __device__ void finish(const SvdArgs<R>& a, const Shared<R>& s, int out_idx, int
                     }
                 }
                 __syncthreads();
-                // four entries per thread loaded before any is stored
-                for (int e0 = tid; e0 < nh * M; e0 += 4 * nt) {
-                    cplx<R> xv[4], vv[4];
+                if constexpr (!WIDE) {
+                    // four entries per thread loaded before any is stored
+                    for (int e0 = tid; e0 < nh * M; e0 += 4 * nt) {
+                        cplx<R> xv[4], vv[4];
 #pragma unroll
-                    for (int u = 0; u < 4; ++u) {
-                        const int e = e0 + u * nt;
-                        const int z = e / M, i = e - (e / M) * M;
-                        if (e < nh * M && i >= k) {
-                            xv[u] = G[(size_t)s.perm[ra + z] * ldg + i];
-                            vv[u] = v[i];
+                        for (int u = 0; u < 4; ++u) {
+                            const int e = e0 + u * nt;
+                            const int z = e / M, i = e - (e / M) * M;
+                            if (e < nh * M && i >= k) {
+                                xv[u] = G[(size_t)s.perm[ra + z] * ldg + i];
+                                vv[u] = v[i];
+                            }
+                        }
+#pragma unroll
+                        for (int u = 0; u < 4; ++u) {
+                            const int e = e0 + u * nt;
+                            const int z = e / M, i = e - (e / M) * M;
+                            if (e < nh * M && i >= k) {
+                                const cplx<R> w = s.coef[ra + z];
+                                G[(size_t)s.perm[ra + z] * ldg + i] = {
+                                    xv[u].x - beta * (w.x * vv[u].x - w.y * vv[u].y),
+                                    xv[u].y - beta * (w.x * vv[u].y + w.y * vv[u].x)};
+                            }
                         }
                     }
+                } else {
+                    // eight entries per thread loaded, without branches (an
+                    // index past the end is clamped and its value unused),
+                    // before any is stored
+                    const int ne = nh * M;
+                    for (int e0 = tid; e0 < ne; e0 += 8 * nt) {
+                        cplx<R> xv[8], vv[8];
+                        int col[8], row[8];
 #pragma unroll
-                    for (int u = 0; u < 4; ++u) {
-                        const int e = e0 + u * nt;
-                        const int z = e / M, i = e - (e / M) * M;
-                        if (e < nh * M && i >= k) {
-                            const cplx<R> w = s.coef[ra + z];
-                            G[(size_t)s.perm[ra + z] * ldg + i] = {
-                                xv[u].x - beta * (w.x * vv[u].x - w.y * vv[u].y),
-                                xv[u].y - beta * (w.x * vv[u].y + w.y * vv[u].x)};
+                        for (int u = 0; u < 8; ++u) {
+                            const int e = e0 + u * nt < ne ? e0 + u * nt : ne - 1;
+                            const int z = e / M;
+                            row[u] = e - z * M;
+                            col[u] = z;
+                            xv[u] = G[(size_t)s.perm[ra + z] * ldg + row[u]];
+                            vv[u] = v[row[u]];
+                        }
+#pragma unroll
+                        for (int u = 0; u < 8; ++u) {
+                            if (e0 + u * nt < ne && row[u] >= k) {
+                                const cplx<R> w = s.coef[ra + col[u]];
+                                G[(size_t)s.perm[ra + col[u]] * ldg + row[u]] = {
+                                    xv[u].x - beta * (w.x * vv[u].x - w.y * vv[u].y),
+                                    xv[u].y - beta * (w.x * vv[u].y + w.y * vv[u].x)};
+                            }
                         }
                     }
                 }
                 __syncthreads();
             }
         }
-        int cand = 0;
+        // After the reflectors the directions still missing are close to the
+        // unit vectors e_nz, ..., e_{M-1} (the trailing columns of Q are
+        // perturbed unit vectors), so the scan starts there; otherwise at e_0.
+        // The threshold is lowered after every M candidates.
+        int cand = hh_g && nz < M ? nz : 0, scanned = 0;
         R thresh = R(0.5);
         for (int zc = hh_q ? N : (hh_g ? N - ra : N - nz); zc < N; ++zc) {
             const int jz = s.perm[zc];
@@ -628,8 +661,9 @@ __device__ void finish(const SvdArgs<R>& a, const Shared<R>& s, int out_idx, int
             thresh = fmin(thresh, R(0.5) * sqrt(R(M - zc > 1 ? M - zc : 1) / R(M)));
             bool done = false;
             for (int tries = 0; !done && tries < 4 * M; ++tries) {
-                if (cand == M) {
-                    cand = 0;
+                if (cand == M) cand = 0;
+                if (scanned == M) {
+                    scanned = 0;
                     thresh *= R(0.2);
                 }
                 for (int i = tid; i < M; i += nt) G[(size_t)jz * ldg + i] = {R(i == cand), R(0)};
@@ -736,6 +770,7 @@ __device__ void finish(const SvdArgs<R>& a, const Shared<R>& s, int out_idx, int
                     done = true;
                 }
                 ++cand;
+                ++scanned;
                 __syncthreads();
             }
         }
