@@ -53,11 +53,13 @@ __global__ void __launch_bounds__(512) block_kernel(SvdArgs<R> a, int W, int ite
     end = min(item_count(a), end);
     if constexpr (DUAL) {
         if ((int)blockIdx.x < main_wgs) {
-            for (int item = first; item < end; item += stride) block_one<R, 1, ACC, TRACK, true>(a, lds, item, gslot, team);
+            for (int item = first; item < end; item += stride) block_one<R, 1, ACC, TRACK, true, !ACC>(a, lds, item, gslot, team);
             return;
         }
     }
-    for (int item = first; item < end; item += stride) block_one<R, 1, ACC, TRACK, false>(a, lds, item, gslot, team);
+    // the wider zero-column completion of the finish only without the
+    // accumulator: beside it the registers spill into the sweeps
+    for (int item = first; item < end; item += stride) block_one<R, 1, ACC, TRACK, false, !ACC>(a, lds, item, gslot, team);
 }
 
 template <typename R, int L>
