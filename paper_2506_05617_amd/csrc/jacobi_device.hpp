@@ -349,8 +349,9 @@ __device__ int jacobi(const LayerDesc& d, const Shared<R>& s, int max_sweeps, do
 // Norms, sort, normalisation, completion of zero columns, outputs.
 // ---------------------------------------------------------------------------
 // WIDE: the completion of zero columns forms four columns' inner products at
-// once (their loads and reductions overlap).  The persistent kernel takes the
-// one-column loops, which hold fewer registers beside its other paths.
+// once (their loads and reductions overlap).  The persistent kernel and the
+// blocked kernel with the rotation accumulator take the one-column loops:
+// beside their other paths the wider ones spill registers into the sweeps.
 template <typename R, int L, bool WIDE = true>
 __device__ void finish(const SvdArgs<R>& a, const Shared<R>& s, int out_idx, int mirror,
                        int sweeps, bool converged) {
