@@ -51,7 +51,7 @@ PEAK_HBM_GBS = 8000.0
 # profiles/wave_queue_kernel_single_layer_64x64_uv.md (FETCH_SIZE x 2.00 +
 # WRITE_SIZE x 1.00, calibrated with a copy of known size), valid only for the
 # kernel source they were taken on.
-HEAD_TRAFFIC = {"bytes": 154.09e6 + 430.67e6, "source_hash": "108425e757ceebd9",
+HEAD_TRAFFIC = {"bytes": 154.12e6 + 430.67e6, "source_hash": "dbb3f0c77c1e297e",
                 "files": ("jacobi_device.hpp", "jacobi_wave.hip", "lfa_internal.hpp", "api.cpp")}
 
 

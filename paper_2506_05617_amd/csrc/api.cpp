@@ -43,7 +43,6 @@ constexpr size_t kAlign = 256;
 constexpr size_t kLdsCap = 160 * 1024 - 1024;  // gfx950: 160 KiB of LDS per work-group
 constexpr size_t kLdsSafe = 64 * 1024;         // always available without opt-in
 constexpr int kGlobalGrid = 1024;              // blocks of a launch using global slots
-constexpr int kPersistentGrid = 1024;          // upper bound of the persistent grid
 
 constexpr int kMaxTopk = 64;
 constexpr int kBlockCols = 16;                    // column block of the blocked kernel
@@ -673,7 +672,6 @@ int run_svd_layer(const lfa_plan* p, const LayerDesc& d, const void* W, const vo
         HIP_TRY(e);
         return LFA_OK;
     }
-    const int grid = svd_grid(d, count);
     a.slot_bytes = (long long)slot_bytes(d, acc, sizeof(R));
     a.gws = d.storage == kGlobal ? region : nullptr;
     if (d.kind == 2) {
@@ -733,11 +731,8 @@ int run_svd_layer(const lfa_plan* p, const LayerDesc& d, const void* W, const vo
         }
         return LFA_OK;
     }
-    const size_t lds = lds_bytes_for(d, acc, sizeof(R));
-    if constexpr (sizeof(R) == 4) e = launch_svd_f32(a, grid, lds, st);
-    else e = launch_svd_f64(a, grid, lds, st);
-    HIP_TRY(e);
-    return LFA_OK;
+    // every layer description is of the register (M <= 64) or the blocked kind
+    return LFA_ERR_UNSUPPORTED;
 }
 
 // Workspace bytes lfa_svd itself uses on the plan's device (desc as

@@ -1,6 +1,5 @@
-// Kernels and launchers of the lane-group kernel (symbols that fit in LDS,
-// or in a global slot) and of the blocked kernel (more than 64 rows); the
-// device code is in jacobi_device.hpp.
+// Kernel and launchers of the blocked kernel (symbols of more than 64 rows);
+// the device code is in jacobi_device.hpp.
 #include <hip/hip_runtime.h>
 
 #include "jacobi_device.hpp"
@@ -62,43 +61,12 @@ __global__ void __launch_bounds__(512) block_kernel(SvdArgs<R> a, int W, int ite
     for (int item = first; item < end; item += stride) block_one<R, 1, ACC, TRACK, false, !ACC>(a, lds, item, gslot, team);
 }
 
-template <typename R, int L>
-__global__ void __launch_bounds__(1024) svd_kernel(SvdArgs<R> a) {
-    extern __shared__ __align__(16) char lds[];
-    char* gslot = a.gws ? a.gws + (size_t)blockIdx.x * a.slot_bytes : nullptr;
-    // with a symbol list, outputs are compact (entry `item` of the list)
-    const int count = item_count(a);
-    for (int item = blockIdx.x; item < count; item += gridDim.x) svd_one<R, L>(a, lds, item, gslot);
-}
-
 // Dynamic LDS above 64 KiB needs an explicit per-kernel opt-in.
 template <typename K>
 hipError_t allow_lds(K kernel, size_t lds) {
     if (lds <= 65536) return hipSuccess;
     return hipFuncSetAttribute(reinterpret_cast<const void*>(kernel),
                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-}
-
-template <typename R, int L>
-hipError_t launch_svd_L(const SvdArgs<R>& a, int grid, size_t lds, hipStream_t st) {
-    hipError_t e = allow_lds(svd_kernel<R, L>, lds);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((svd_kernel<R, L>), dim3(grid), dim3(a.d.threads), lds, st, a);
-    return hipGetLastError();
-}
-
-template <typename R>
-hipError_t launch_svd(const SvdArgs<R>& a, int grid, size_t lds, hipStream_t st) {
-    switch (a.d.L) {
-        case 1: return launch_svd_L<R, 1>(a, grid, lds, st);
-        case 2: return launch_svd_L<R, 2>(a, grid, lds, st);
-        case 4: return launch_svd_L<R, 4>(a, grid, lds, st);
-        case 8: return launch_svd_L<R, 8>(a, grid, lds, st);
-        case 16: return launch_svd_L<R, 16>(a, grid, lds, st);
-        case 32: return launch_svd_L<R, 32>(a, grid, lds, st);
-        case 64: return launch_svd_L<R, 64>(a, grid, lds, st);
-        default: return hipErrorInvalidValue;
-    }
 }
 
 __global__ void fill_i32_kernel(int32_t* p, int32_t v, long long n) {
@@ -203,13 +171,6 @@ hipError_t launch_block_svd_f64(const SvdArgs<double>& a, int teams, int W, int 
 int block_resident(const LayerDesc& d, bool acc, int elem_bytes) {
     if (elem_bytes == 8) return acc ? block_resident_t<double, true>(d) : block_resident_t<double, false>(d);
     return acc ? block_resident_t<float, true>(d) : block_resident_t<float, false>(d);
-}
-
-hipError_t launch_svd_f32(const SvdArgs<float>& a, int grid, size_t lds, hipStream_t s) {
-    return launch_svd<float>(a, grid, lds, s);
-}
-hipError_t launch_svd_f64(const SvdArgs<double>& a, int grid, size_t lds, hipStream_t s) {
-    return launch_svd<double>(a, grid, lds, s);
 }
 
 hipError_t launch_fill_i32(int32_t* p, int32_t value, long long count, hipStream_t s) {

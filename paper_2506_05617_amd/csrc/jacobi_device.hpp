@@ -11,28 +11,20 @@
 namespace lfa {
 namespace dev {
 
-// ===================== lane-group and blocked kernels ======================
+// ============================ blocked kernel ================================
 //  Batched one-sided Jacobi SVD of convolution symbols on gfx950.
 //
-// One work-group owns one symbol at a time.  It assembles the c_out x c_in
-// symbol A_k = sum_y M_y exp(+2 pi i <k,y>) (Sec. III "Convolution Theorem",
-// Algorithm 1 symbol step) straight into its working matrix G (LDS, or a
-// global slot for symbols larger than LDS), runs complex one-sided (Hestenes)
-// Jacobi sweeps on the columns of G with a parallel round-robin pair order,
-// and writes sigma (sorted), U and V (Algorithm 1 SVD step).
+// One work-group (or a team of them) owns one symbol at a time.  It
+// assembles the c_out x c_in symbol A_k = sum_y M_y exp(+2 pi i <k,y>)
+// (Sec. III "Convolution Theorem", Algorithm 1 symbol step) straight into
+// its working matrix G (a global slot), runs complex one-sided (Hestenes)
+// Jacobi sweeps on the columns of G, and writes sigma (sorted), U and V
+// (Algorithm 1 SVD step).  The load and the finish below are shared with
+// the QR path and the persistent kernel.
 //
 // G is M x N, column-major with leading dimension ldg, M = max(c_out, c_in),
 // N = min(c_out, c_in).  For c_out >= c_in, G = A and the accumulated
 // rotations form V; for c_out < c_in, G = A^H and the roles of U and V swap.
-//
-// A column pair (j, k) is handled by a group of L lanes of one wavefront;
-// lane l owns rows l, l+L, ... of both columns in registers.  The three inner
-// products alpha = |g_j|^2, beta = |g_k|^2, gamma = g_j^H g_k are reduced with
-// xor shuffles inside the lane group, the rotation is computed in double
-// precision by every lane of the group (no broadcast), and applied to the
-// registers, then written back.  The N/2 pairs of one round-robin step are
-// disjoint, so groups never touch the same column within a step; a
-// work-group barrier separates steps.
 
 
 template <typename R>
@@ -45,7 +37,7 @@ __device__ __forceinline__ R shfl_xor(R v, int mask) {
     return __shfl_xor(v, mask, 64);
 }
 
-// Sum over the L lanes of a lane group (L a power of two <= 64).
+// Sum over groups of L consecutive lanes (L a power of two <= 64).
 template <typename R, int L>
 __device__ __forceinline__ R group_sum(R v) {
 #pragma unroll
@@ -235,114 +227,6 @@ __device__ void load_symbol(const SvdArgs<R>& a, const Shared<R>& s, int theta) 
             s.Q[(size_t)j * d.ldv + i] = {R(i == j ? 1 : 0), R(0)};
         }
     }
-}
-
-// ---------------------------------------------------------------------------
-// One-sided Jacobi sweeps.  Returns the number of sweeps used; `converged`
-// tells whether the last sweep made no rotation.
-// ---------------------------------------------------------------------------
-template <typename R, int L>
-__device__ int jacobi(const LayerDesc& d, const Shared<R>& s, int max_sweeps, double tol,
-                      bool& converged) {
-    constexpr int RM = kRowsPerLane;
-    const int tid = threadIdx.x;
-    const int lane = tid & (L - 1), group = tid / L, ngroups = blockDim.x / L;
-    const int M = d.M, N = d.N, ldg = d.ldg, ldv = d.ldv;
-    const int Np = N + (N & 1);
-    const int npairs = Np / 2, nsteps = Np - 1;
-    cplx<R>* __restrict__ G = s.G;
-    cplx<R>* __restrict__ Q = s.Q;
-
-    // numerically zero columns (see negligible_sq): ||G||_F^2 before the sweeps
-    R fro = 0;
-    for (int e = tid; e < N * M; e += blockDim.x) {
-        const int j = e / M, i = e - (e / M) * M;
-        const cplx<R> v = G[(size_t)j * ldg + i];
-        fro = fma(v.x, v.x, fma(v.y, v.y, fro));
-    }
-    const double floor = negligible_sq<R>() * double(block_sum<R>(fro, s.red));
-    if (tid == 0) s.flags[0] = s.flags[1] = s.flags[2] = 0;
-    __syncthreads();
-    converged = (N < 2);
-    int sweep = 0;
-    while (!converged && sweep < max_sweeps) {
-        if (tid == 0) s.flags[(sweep + 1) % 3] = 0;
-        for (int step = 0; step < nsteps; ++step) {
-            for (int pb = 0; pb < npairs; pb += ngroups) {
-                const int pr = pb + group;
-                if (pr >= npairs) continue;
-                int j, k;
-                rr_pair(pr, step, Np, j, k);
-                if (j >= N || k >= N) continue;
-                cplx<R> x[RM], y[RM];
-                R al = 0, be = 0, gr = 0, gi = 0;
-#pragma unroll
-                for (int t = 0; t < RM; ++t) {
-                    const int i = lane + t * L;
-                    if (i < M) {
-                        x[t] = G[(size_t)j * ldg + i];
-                        y[t] = G[(size_t)k * ldg + i];
-                        al = fma(x[t].x, x[t].x, fma(x[t].y, x[t].y, al));
-                        be = fma(y[t].x, y[t].x, fma(y[t].y, y[t].y, be));
-                        gr = fma(x[t].x, y[t].x, fma(x[t].y, y[t].y, gr));
-                        gi = fma(x[t].x, y[t].y, fma(-x[t].y, y[t].x, gi));
-                    }
-                }
-                al = group_sum<R, L>(al);
-                be = group_sum<R, L>(be);
-                gr = group_sum<R, L>(gr);
-                gi = group_sum<R, L>(gi);
-                const double g = sqrt(double(gr) * double(gr) + double(gi) * double(gi));
-                if (!(g > tol * sqrt(double(al) * double(be)))) continue;
-                if (!(fmin(double(al), double(be)) > floor)) continue;
-                // Real 2x2 symmetric Schur step on [[al, g], [g, be]] after the
-                // phase of gamma is moved into column k.
-                const double zeta = (double(be) - double(al)) / (2.0 * g);
-                const double tt = copysign(1.0, zeta) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-                const double cs = 1.0 / sqrt(1.0 + tt * tt);
-                const double sn = cs * tt;
-                // x' = c x - s e^{-i phi} y ;  y' = c y + s e^{+i phi} x
-                const R c = R(cs);
-                const R sr = R(sn * double(gr) / g), si = R(-sn * double(gi) / g);
-#pragma unroll
-                for (int t = 0; t < RM; ++t) {
-                    const int i = lane + t * L;
-                    if (i < M) {
-                        const cplx<R> xv = x[t], yv = y[t];
-                        cplx<R> xn, yn;
-                        xn.x = fma(c, xv.x, -fma(sr, yv.x, -si * yv.y));
-                        xn.y = fma(c, xv.y, -fma(sr, yv.y, si * yv.x));
-                        yn.x = fma(c, yv.x, fma(sr, xv.x, si * xv.y));
-                        yn.y = fma(c, yv.y, fma(sr, xv.y, -si * xv.x));
-                        G[(size_t)j * ldg + i] = xn;
-                        G[(size_t)k * ldg + i] = yn;
-                    }
-                }
-                if (Q) {
-#pragma unroll
-                    for (int t = 0; t < RM; ++t) {
-                        const int i = lane + t * L;
-                        if (i < N) {
-                            const cplx<R> xv = Q[(size_t)j * ldv + i], yv = Q[(size_t)k * ldv + i];
-                            cplx<R> xn, yn;
-                            xn.x = fma(c, xv.x, -fma(sr, yv.x, -si * yv.y));
-                            xn.y = fma(c, xv.y, -fma(sr, yv.y, si * yv.x));
-                            yn.x = fma(c, yv.x, fma(sr, xv.x, si * xv.y));
-                            yn.y = fma(c, yv.y, fma(sr, xv.y, -si * xv.x));
-                            Q[(size_t)j * ldv + i] = xn;
-                            Q[(size_t)k * ldv + i] = yn;
-                        }
-                    }
-                }
-                if (lane == 0) s.flags[sweep % 3] = 1;
-            }
-            __syncthreads();
-        }
-        converged = (s.flags[sweep % 3] == 0);
-        ++sweep;
-    }
-    __syncthreads();
-    return sweep;
 }
 
 // ---------------------------------------------------------------------------
@@ -810,22 +694,6 @@ __device__ void finish(const SvdArgs<R>& a, const Shared<R>& s, int out_idx, int
     __syncthreads();
 }
 
-// Work item `item` (see target_of).
-template <typename R, int L>
-__device__ void svd_one(const SvdArgs<R>& a, char* lds, int item, char* gslot) {
-    bool cj;
-    if (a.theta_dedup && pick_rep(a.theta_list, item, a.d.n, a.d.m, cj) != item) return;   // decomposed already
-    const Target tg = target_of(a, item);
-    const int theta = tg.theta;
-    const bool acc = (a.d.transposed ? a.U : a.V) != nullptr;
-    const Shared<R> s = carve<R>(lds, a.d, acc, gslot);
-    load_symbol<R>(a, s, theta);
-    __syncthreads();
-    bool converged;
-    const int sweeps = jacobi<R, L>(a.d, s, a.max_sweeps, a.tol, converged);
-    finish<R, L>(a, s, tg.out, tg.mirror, sweeps, converged);
-}
-
 // ---- cross-lane exchanges (gfx950 permlane swaps) ------------------------
 // xadd32(a, b): lanes 0-31 receive a(l) + a(l+32), lanes 32-63 b(l-32) + b(l).
 // xadd16(a, b): lanes whose bit 4 is clear receive a(l) + a(l+16), the others
@@ -1008,7 +876,6 @@ struct BlockLds {
 
 template <typename R>
 __device__ __forceinline__ BlockLds<R> carve_block(char* lds, size_t off) {
-    constexpr int B = kBlk;
     const int nw = blockDim.x >> 6;
     BlockLds<R> b;
     R* p = reinterpret_cast<R*>(lds + ((off + 63) & ~size_t(63)));

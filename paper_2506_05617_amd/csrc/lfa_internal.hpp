@@ -32,7 +32,7 @@ struct LayerDesc {
     int ldg, ldv;      // leading dimensions (elements) of G and of the accumulator
     int num_symbols;   // n*m
     int num_canon;     // frequencies with index <= that of their mirror (-k)
-    int kind;          // 0: lane-group kernel (LDS/global), 1: register (wave) kernel,
+    int kind;          // 1: register (wave) kernel (M <= 64),
                        // 2: blocked kernel (rows in threads, column blocks in registers)
     int wave_nc;       // wave kernel: padded column count (power of two)
     int wave_ml;       // wave kernel: lanes per symbol (16, 32 or 64)
@@ -256,7 +256,7 @@ struct SvdArgs {
     int theta_count;             // number of symbols to process
     int theta_dedup;             // theta_list holds one layer's (p, q, j) picks: a pick whose
                                  // symbol an earlier pick has (itself or its conjugate) is
-                                 // skipped by the blocked and lane-group kernels (see pick_rep)
+                                 // skipped by the blocked kernel (see pick_rep)
     int max_sweeps;
     double tol;
     int32_t* wctr;               // register kernel: group counter (cleared) of a grid of
@@ -359,8 +359,6 @@ hipError_t launch_wave_queue_f32(const SvdArgs<float>& a, int grid, hipStream_t 
 hipError_t launch_wave_queue_f64(const SvdArgs<double>& a, int grid, hipStream_t s);
 // The same for the work-queue launch.
 int wave_queue_blocks_per_cu(int nc, int ml, int elem_bytes, int threads, bool vectors);
-hipError_t launch_svd_f32(const SvdArgs<float>& a, int grid, size_t lds, hipStream_t s);
-hipError_t launch_svd_f64(const SvdArgs<double>& a, int grid, size_t lds, hipStream_t s);
 
 // LFA_PHASE_NORMALIZE on one layer's outputs: syms symbols of U
 // [syms][rows_u][r] and V [syms][rows_v][r] (either may be null; the phase

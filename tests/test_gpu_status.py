@@ -172,7 +172,7 @@ def test_persistent_busy_records_match_the_launch():
 
 
 HIST_CASES = [
-    # c_out, c_in, n, persistent: register kernel (work queue), lane-group /
+    # c_out, c_in, n, persistent: register kernel (work queue), register /
     # blocked kernels, and the persistent launch
     (64, 64, 64, False),
     (160, 96, 8, False),
